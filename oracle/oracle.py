@@ -1,0 +1,251 @@
+"""ctypes wrapper of the FP64 CPU oracle (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` import this module.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build_oracle
+
+NSP = 3
+_lib = None
+
+
+class OCfg(C.Structure):
+    _fields_ = [("L", C.c_double), ("N", C.c_int32), ("periodic", C.c_int32), ("V", C.c_double),
+                ("n0", C.c_double), ("Te0", C.c_double), ("Ti0", C.c_double),
+                ("n_load", C.c_int64), ("gamma_emit", C.c_double), ("Tc", C.c_double),
+                ("ng", C.c_double), ("Tne", C.c_double), ("Tni", C.c_double), ("dt", C.c_double),
+                ("sig_el", C.c_double), ("sig_x0", C.c_double), ("lotz_a", C.c_double),
+                ("sig_cx", C.c_double), ("sig_iel", C.c_double), ("channels", C.c_uint32),
+                ("replenish", C.c_int32), ("seed", C.c_uint32), ("diode", C.c_uint32)]
+
+
+class ODerived(C.Structure):
+    _fields_ = [("dz", C.c_double), ("invdz", C.c_double), ("w0", C.c_double),
+                ("qm", C.c_double * 3), ("mass", C.c_double * 3), ("numax", C.c_double * 2),
+                ("lam", C.c_double * 2), ("sig_n", C.c_double * 2)]
+
+
+class OTally(C.Structure):
+    _fields_ = [("abs_count", (C.c_int64 * 2) * 3), ("abs_energy", (C.c_double * 2) * 3),
+                ("n_emit", C.c_int64), ("n_repl", C.c_int64), ("n_iz", C.c_int64),
+                ("cand", C.c_int64 * 2), ("coll", C.c_int64 * 5), ("nullcoll_exceed", C.c_int64)]
+
+
+class ODiag(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("gamma_emit", "gamma_emit_meas", "gamma_ref", "gamma_net",
+                                          "gamma_anode", "backflow_pct", "eta_net", "eta_anode")] + [
+        ("gamma_abs", (C.c_double * 2) * 3), ("q_abs", (C.c_double * 2) * 3)] + [
+        (n, C.c_double) for n in ("wf_eff", "q_emit_theory", "q_ion_cath_recomb", "q_cool1", "q_cool2",
+                                  "q_ion_anode_recomb", "q_anode1", "q_anode2", "phi_vc_eff")]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = build_oracle.LIB
+        if not os.path.exists(path):
+            build_oracle.build()
+        L = C.CDLL(path)
+        P = C.c_void_p
+        d, i64, u32, i32 = C.c_double, C.c_int64, C.c_uint32, C.c_int32
+        L.o_create.restype = P
+        L.o_create.argtypes = [C.POINTER(OCfg)]
+        L.o_destroy.argtypes = [P]
+        for f in ("o_load", "o_step", "o_refield"):
+            getattr(L, f).argtypes = [P]
+            getattr(L, f).restype = C.c_int
+        L.o_count.argtypes = [P, C.c_int]
+        L.o_count.restype = i64
+        L.o_stepno.argtypes = [P]
+        L.o_stepno.restype = i64
+        L.o_next_id.argtypes = [P]
+        L.o_next_id.restype = u32
+        L.o_set_counters.argtypes = [P, i64, u32]
+        L.o_get_particles.argtypes = [P, C.c_int] + [P] * 6
+        L.o_set_particles.argtypes = [P, C.c_int, i64] + [P] * 6
+        L.o_set_particles.restype = C.c_int
+        for f in ("o_get_hist",):
+            getattr(L, f).argtypes = [P, C.c_int, P]
+        L.o_get_phi.argtypes = [P, P]
+        L.o_get_E.argtypes = [P, P]
+        L.o_get_tally.argtypes = [P, C.POINTER(OTally)]
+        L.o_get_derived.argtypes = [P, C.POINTER(ODerived)]
+        L.o_philox4x32_10.argtypes = [P, P, P]
+        L.o_u24.argtypes = [u32]
+        L.o_u24.restype = d
+        L.o_u32.argtypes = [u32]
+        L.o_u32.restype = d
+        L.o_u53.argtypes = [u32, u32]
+        L.o_u53.restype = d
+        L.o_sigma.argtypes = [C.POINTER(OCfg), C.c_int, d]
+        L.o_sigma.restype = d
+        L.o_derive.argtypes = [C.POINTER(OCfg), C.POINTER(ODerived)]
+        L.o_derive.restype = C.c_int
+        L.o_deposit.argtypes = [i64, P, i32, d, P]
+        L.o_solve.argtypes = [i32, d, d, P, P]
+        L.o_solve.restype = C.c_int
+        L.o_efield.argtypes = [i32, d, P, P]
+        L.o_diag.argtypes = [d, d, d, d, P, P, d, C.POINTER(ODiag)]
+        L.o_eta_vc.argtypes = [d, d, d]
+        L.o_eta_vc.restype = d
+        _lib = L
+    return _lib
+
+
+def make_cfg(p: dict) -> OCfg:
+    c = OCfg()
+    for name, _ in OCfg._fields_:
+        setattr(c, name, p[name])
+    return c
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().o_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def derive(p: dict) -> dict:
+    c = make_cfg(p)
+    d = ODerived()
+    if lib().o_derive(C.byref(c), C.byref(d)) != 0:
+        raise ValueError("invalid configuration")
+    return {"dz": d.dz, "invdz": d.invdz, "w0": d.w0, "qm": list(d.qm), "mass": list(d.mass),
+            "numax": list(d.numax), "lam": list(d.lam), "sig_n": list(d.sig_n)}
+
+
+def sigma(p: dict, channel: int, eps_eV: float) -> float:
+    c = make_cfg(p)
+    return lib().o_sigma(C.byref(c), channel, float(eps_eV))
+
+
+def deposit(z, N, invdz):
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    H = np.zeros(N + 1, dtype=np.int64)
+    lib().o_deposit(len(z), _ptr(z), N, invdz, _ptr(H))
+    return H
+
+
+def solve(N, dz, V, rho):
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    phi = np.zeros(N + 1, dtype=np.float64)
+    lib().o_solve(N, dz, V, _ptr(rho), _ptr(phi))
+    return phi
+
+
+def efield(N, dz, phi):
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    E = np.zeros(N + 1, dtype=np.float64)
+    lib().o_efield(N, dz, _ptr(phi), _ptr(E))
+    return E
+
+
+def diag(gamma_emit, Tc, w0, window_s, count, energy, n_emit):
+    cnt = np.ascontiguousarray(count, dtype=np.float64).reshape(3, 2)
+    en = np.ascontiguousarray(energy, dtype=np.float64).reshape(3, 2)
+    out = ODiag()
+    lib().o_diag(gamma_emit, Tc, w0, window_s, _ptr(cnt), _ptr(en), n_emit, C.byref(out))
+    res = {}
+    for name, typ in ODiag._fields_:
+        v = getattr(out, name)
+        res[name] = np.array([[v[s][w] for w in range(2)] for s in range(3)]) if name in (
+            "gamma_abs", "q_abs") else v
+    return res
+
+
+class Sim:
+    """One oracle diode."""
+
+    def __init__(self, p: dict):
+        self.p = dict(p)
+        self._cfg = make_cfg(p)
+        self.h = lib().o_create(C.byref(self._cfg))
+        if not self.h:
+            raise ValueError("oracle: invalid configuration")
+        self.N = p["N"]
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().o_destroy(self.h)
+            self.h = None
+
+    def load(self):
+        if lib().o_load(self.h) != 0:
+            raise RuntimeError("oracle load failed")
+
+    def step(self, n=1):
+        for _ in range(n):
+            if lib().o_step(self.h) != 0:
+                raise RuntimeError("oracle step failed")
+
+    def refield(self):
+        lib().o_refield(self.h)
+
+    @property
+    def stepno(self):
+        return lib().o_stepno(self.h)
+
+    @property
+    def next_id(self):
+        return lib().o_next_id(self.h)
+
+    def set_counters(self, step, next_id):
+        lib().o_set_counters(self.h, int(step), int(next_id))
+
+    def count(self, sp):
+        return lib().o_count(self.h, sp)
+
+    def particles(self, sp):
+        n = self.count(sp)
+        z, vx, vy, vz = (np.zeros(n) for _ in range(4))
+        pid, tc = np.zeros(n, np.uint32), np.zeros(n, np.uint32)
+        lib().o_get_particles(self.h, sp, _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), _ptr(pid), _ptr(tc))
+        return {"z": z, "vx": vx, "vy": vy, "vz": vz, "id": pid, "tc": tc}
+
+    def set_particles(self, sp, d):
+        n = len(d["z"])
+        arrs = [np.ascontiguousarray(d[k], dtype=np.float64) for k in ("z", "vx", "vy", "vz")]
+        arrs += [np.ascontiguousarray(d[k], dtype=np.uint32) for k in ("id", "tc")]
+        if lib().o_set_particles(self.h, sp, n, *[_ptr(a) for a in arrs]) != 0:
+            raise MemoryError
+        self._keep = getattr(self, "_keep", []) + [arrs]
+
+    def hist(self, sp):
+        H = np.zeros(self.N + 1, np.int64)
+        lib().o_get_hist(self.h, sp, _ptr(H))
+        return H
+
+    def phi(self):
+        a = np.zeros(self.N + 1)
+        lib().o_get_phi(self.h, _ptr(a))
+        return a
+
+    def E(self):
+        a = np.zeros(self.N + 1)
+        lib().o_get_E(self.h, _ptr(a))
+        return a
+
+    def tally(self):
+        t = OTally()
+        lib().o_get_tally(self.h, C.byref(t))
+        return {"abs_count": np.array([[t.abs_count[s][w] for w in range(2)] for s in range(3)]),
+                "abs_energy": np.array([[t.abs_energy[s][w] for w in range(2)] for s in range(3)]),
+                "n_emit": t.n_emit, "n_repl": t.n_repl, "n_iz": t.n_iz,
+                "cand": np.array(list(t.cand)), "coll": np.array(list(t.coll)),
+                "nullcoll_exceed": t.nullcoll_exceed}
+
+    def derived(self):
+        d = ODerived()
+        lib().o_get_derived(self.h, C.byref(d))
+        return {"dz": d.dz, "invdz": d.invdz, "w0": d.w0, "numax": list(d.numax), "lam": list(d.lam)}

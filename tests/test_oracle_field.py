@@ -1,0 +1,118 @@
+"""Pins of the oracle's deposit, Poisson solve and field.
+
+Poisson ("Model": potential from the charge density, Dirichlet electrodes
+phi(0) = 0, phi(L) = V; field from its gradient) is checked against closed
+forms (Laplace, uniform charge) and against scipy's banded solver.  The
+fixed-point CIC deposit is checked against exact rational arithmetic,
+its conservation and first-moment invariants, and permutation invariance.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.linalg import solve_banded
+
+EPS0 = 8.8541878128e-12
+
+
+def test_laplace_is_linear(O):
+    N, L, V = 257, 5e-3, 10.0
+    dz = L / N
+    phi = O.solve(N, dz, V, np.zeros(N + 1))
+    exact = V * np.arange(N + 1) / N
+    assert np.max(np.abs(phi - exact)) < 1e-12 * V
+    E = O.efield(N, dz, phi)
+    assert np.allclose(E, -V / L, rtol=1e-10, atol=0)
+
+
+def test_uniform_charge_quadratic(O):
+    # phi = -(rho/2eps0) z (z - L) + V z / L is exact on nodes (second difference
+    # of a quadratic is exact)
+    N, L, V, rho0 = 300, 2e-2, -3.0, 1.7e-4
+    dz = L / N
+    z = np.arange(N + 1) * dz
+    phi = O.solve(N, dz, V, np.full(N + 1, rho0))
+    exact = -(rho0 / (2 * EPS0)) * z * (z - L) + V * z / L
+    assert np.max(np.abs(phi - exact)) < 1e-10 * np.max(np.abs(exact))
+    E = O.efield(N, dz, phi)
+    # interior: central difference of a quadratic is exact: E = rho/eps0 (z - L/2) - V/L
+    Eex = rho0 / EPS0 * (z - L / 2) - V / L
+    assert np.max(np.abs(E[1:-1] - Eex[1:-1])) < 1e-9 * np.max(np.abs(Eex))
+    # walls: one-sided first-order difference
+    assert E[0] == pytest.approx((phi[0] - phi[1]) / dz, rel=1e-14)
+    assert E[-1] == pytest.approx((phi[-2] - phi[-1]) / dz, rel=1e-14)
+
+
+@pytest.mark.parametrize("N", [2, 3, 64, 2048])
+def test_random_charge_vs_banded(O, N):
+    rng = np.random.default_rng(N)
+    L, V = 5e-3, 10.0
+    dz = L / N
+    rho = rng.normal(0, 1e-5, N + 1)
+    phi = O.solve(N, dz, V, rho)
+    n = N - 1
+    ab = np.zeros((3, n))
+    ab[0, 1:] = 1.0
+    ab[1, :] = -2.0
+    ab[2, :-1] = 1.0
+    rhs = -rho[1:N] * dz * dz / EPS0
+    rhs[-1] -= V
+    ref = solve_banded((1, 1), ab, rhs)
+    assert phi[0] == 0.0 and phi[N] == V
+    scale = max(np.max(np.abs(ref)), V)
+    assert np.max(np.abs(phi[1:N] - ref)) < 1e-12 * scale
+
+
+def _exact_deposit(z, N, invdz):
+    """Exact rational evaluation of the fixed-point CIC definition."""
+    H = [0] * (N + 1)
+    for zz in z:
+        s = Fraction(zz) * Fraction(invdz)
+        # the oracle forms s in double precision with one rounding
+        s = Fraction(float(s))
+        j = int(np.floor(float(s)))
+        j = min(max(j, 0), N - 1)
+        f = s - j
+        x = f * 2**32
+        a = round(x)   # Python rounds halves to even
+        H[j] += 2**32 - a
+        H[j + 1] += a
+    return np.array(H, dtype=np.int64)
+
+
+def test_deposit_exact_small(O):
+    rng = np.random.default_rng(3)
+    N, L = 16, 1e-3
+    invdz = N / L
+    z = rng.uniform(0, L, 40)
+    # particles exactly on nodes and at half cells (rounding ties)
+    z = np.concatenate([z, [0.0, L / N * 3, L / N * 7.5, L * (1 - 1e-17)]])
+    H = O.deposit(z, N, invdz)
+    assert np.array_equal(H, _exact_deposit(z, N, invdz))
+
+
+def test_deposit_invariants(O):
+    rng = np.random.default_rng(11)
+    N, L = 512, 5e-3
+    invdz = N / L
+    z = rng.uniform(0, L, 100000)
+    H = O.deposit(z, N, invdz)
+    # each particle deposits exactly 2^32
+    assert H.sum() == len(z) * 2**32
+    assert (H >= 0).all()
+    # CIC preserves the first moment: sum_j j H_j = sum_p 2^32 s_p to rounding
+    first = (np.arange(N + 1, dtype=np.float64) * H.astype(np.float64)).sum() / 2**32
+    assert abs(first - (z * invdz).sum()) < 1e-6 * len(z) + 1e-12 * first
+    # order independence, bit for bit
+    perm = rng.permutation(len(z))
+    assert np.array_equal(O.deposit(z[perm], N, invdz), H)
+    # a particle exactly on node j puts 2^32 on node j
+    one = O.deposit(np.array([7 * L / N]), N, invdz)
+    assert one[7] == 2**32 and one.sum() == 2**32
+
+
+def test_deposit_wall_clamp(O):
+    N, L = 8, 1.0
+    H = O.deposit(np.array([np.nextafter(L, 0)]), N, N / L)
+    # z within an ulp below L lands on the last node
+    assert H[N] + H[N - 1] == 2**32 and H[N] >= H[N - 1]
