@@ -1,0 +1,122 @@
+"""Throughput of the PIC-MCC diode hot path on one MI355X.
+
+A step is one pass of the whole hot path for every diode of the workload:
+cell re-sort (every K steps), gather + push + absorption + null-collision MCC +
+fixed-point deposit, sources (ionisation products, thermionic emission, pair
+replenishment), Poisson solve and field.  Inputs are resident in HBM before
+the timed region; the metric is live particle-steps per second.
+
+Prints one JSON line.  Options: --gpus (must be 1), --steps, --warmup,
+--workload {bench,tiny,large,sweep}, --no-cpu-baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_PARTICLE_STEP = 28      # z r/w 16 B + v_z r/w 8 B + free-flight counter read 4 B
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    from paper_2605_07083_amd import presets
+    if name == "bench":
+        return "2048-cell helium diode, 409.6k macro-particles per species, emission 7.25e19 m^-2 s^-1", [presets.bench()]
+    if name == "tiny":
+        return "256-cell helium diode, 25.6k macro-particles per species, emission 1e19 m^-2 s^-1", [presets.tiny()]
+    if name == "large":
+        return "16384-cell collisional helium diode, 16.4M macro-particles per species", [presets.large()]
+    if name == "sweep":
+        return "32-diode emission sweep 1e19-1.2e20 m^-2 s^-1, 100-600k per species", presets.sweep()
+    raise SystemExit("unknown workload " + name)
+
+
+def cpu_baseline(cfg, seconds=12.0):
+    """The FP64 oracle, single-threaded, on a bounded sample of the same diode."""
+    from oracle import oracle as O
+    s = O.Sim(cfg)
+    s.load()
+    s.step(2)
+    live = sum(s.count(sp) for sp in range(3))
+    t0 = time.perf_counter()
+    steps = 0
+    ps = 0
+    while time.perf_counter() - t0 < seconds:
+        ps += sum(s.count(sp) for sp in range(3))
+        s.step(1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return {"value": ps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d steps of the same diode from its initial load (%d live particles), FP64, one thread"
+                      % (steps, live)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--workload", default="bench")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        raise SystemExit("bench.py measures one GPU only: this build has no multi-GPU path "
+                         "(the design notes describe how it would shard)")
+
+    import torch
+    from paper_2605_07083_amd import pic
+
+    desc, cfgs = workload(args.workload)
+    print("bench: workload %s, %d diode(s), warmup %d, steps %d" % (args.workload, len(cfgs), args.warmup,
+                                                                    args.steps), file=sys.stderr, flush=True)
+    h = pic.Handle(cfgs, device="cuda:0")
+    h.step(args.warmup)
+    h.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = h.step_timed(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    h.sync()
+    live = r["mean_live"]
+    value = live * args.steps / wall
+    kern_s = r["particle_kernel_ms"] * 1e-3
+    achieved = BYTES_PER_PARTICLE_STEP * live / kern_s / 1e9
+    out = {
+        "metric": "particle-steps/s (push+MCC+deposit) on 1 GPU",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 positions / f32 velocities / int64 deposit",
+        "data": "synthetic (seeded Philox load of the stated diode)",
+        "config": {"workload": desc, "n_diodes": len(cfgs), "cells": cfgs[0]["N"],
+                   "particles_per_species": cfgs[0]["n_load"], "live_particles": live,
+                   "sort_period": h_sort_period(cfgs)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_particles", "kernel_ms": r["particle_kernel_ms"],
+                     "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP},
+    }
+    if not args.no_cpu_baseline and len(cfgs) == 1:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfgs[0], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def h_sort_period(cfgs):
+    return cfgs[0].get("sort_period", 0) or 16
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) PIC-MCC thermionic-diode library.
+ *
+ * The library advances the 1D3V electrostatic particle-in-cell / Monte Carlo
+ * collision model of a thermionically emitting helium cathode-anode diode of
+ * Zhang, Zhou and Zhao (electron transpiration cooling): every step gathers
+ * the field, pushes particles (leapfrog), absorbs them at the electrodes,
+ * applies null-collision MCC against a uniform helium background, injects
+ * thermionic electrons and replenished pairs, deposits charge and solves the
+ * 1D Poisson problem ("Model": numerical setup; "Emission and collisions").
+ * Diagnostics follow "Benchmark cases" and "Boundary energy diagnostics",
+ * eqs. 1-10.
+ *
+ * Conventions (all entry points):
+ *  - SI units; temperatures in eV.
+ *  - Species: 0 plasma electrons, 1 emitted electrons, 2 He+ ions.
+ *    Walls: 0 cathode (z = 0, phi = 0), 1 anode (z = L, phi = V).
+ *    Channels: 0 e-He elastic, 1 excitation, 2 ionisation, 3 He+-He charge
+ *    exchange, 4 He+-He elastic.
+ *  - Ownership: the caller owns the device workspace and the HIP stream; the
+ *    library owns only the host-side handle and never frees caller memory.
+ *  - Errors: every call returns 0 or a negative PIC_E* code; no exception
+ *    crosses the ABI.  pic_last_error() gives a message.  Device-side
+ *    conditions (capacity, null-collision bound, queue overflow) are sticky
+ *    bits reported by the next synchronising call.
+ *  - Asynchrony: pic_step only enqueues work on the bound stream.  Calls that
+ *    return host data synchronise that stream first.
+ *  - Device pointers are hipMalloc-compatible (e.g. a torch uint8 CUDA tensor);
+ *    host pointers are ordinary host memory.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_OK 0
+#define PIC_EINVAL (-1)     /* bad argument or configuration */
+#define PIC_ENOSPACE (-2)   /* workspace too small or particle capacity exceeded */
+#define PIC_EHIP (-3)       /* HIP runtime error */
+#define PIC_ENULLCOLL (-4)  /* a candidate's collision frequency exceeded nu_max */
+#define PIC_ENAN (-5)       /* non-finite particle state */
+#define PIC_ERANGE (-6)     /* a queue or histogram bound was exceeded */
+
+#define PIC_MAX_DIODES 256
+
+/* One diode.  Filled by the caller; read by pic_workspace_size / pic_init. */
+typedef struct pic_config {
+    double L;             /* gap length (m) */
+    int32_t N;            /* cells; nodes 0..N; N >= 2 */
+    int32_t flags;        /* reserved, must be 0 */
+    double V;             /* anode potential (V) */
+    double n0;            /* initial plasma density (m^-3) */
+    double Te0, Ti0;      /* initial electron / ion temperature (eV) */
+    int64_t n_load;       /* macro-particles per species (electrons, ions) at load */
+    double gamma_emit;    /* imposed emitted-electron flux (m^-2 s^-1) */
+    double Tc;            /* emission temperature (eV) */
+    double ng;            /* neutral density (m^-3) */
+    double Tne, Tni;      /* neutral target temperature, e / ion collisions (eV) */
+    double dt;            /* time step (s) */
+    double sig_el;        /* e-He elastic cross section (m^2), energy independent */
+    double sig_x0;        /* excitation scale (m^2): sig_x0 ln(x)/x, x = eps/19.82 eV */
+    double lotz_a;        /* ionisation: Lotz a (m^2 eV^2), q = 2, threshold 24.59 eV */
+    double sig_cx;        /* He+-He charge exchange (m^2), energy independent */
+    double sig_iel;       /* He+-He elastic (m^2), energy independent */
+    uint32_t channels;    /* bit c enables channel c */
+    int32_t replenish;    /* 1: re-inject one e-ion pair per ion lost ("Model") */
+    uint32_t seed;        /* Philox key word 1 = seed ^ diode */
+    uint32_t diode;       /* index used in the key */
+    int32_t tally_period; /* D: tallies snapshot every D steps (>= 1) */
+    int32_t sort_period;  /* K: cell re-sort every K steps (0: library default) */
+    double capacity_factor; /* slots per species = factor * n_load (0: 1.6) */
+} pic_config;
+
+/* Cumulative raw tallies of one diode since pic_init. */
+typedef struct pic_tally {
+    int64_t step;                 /* completed steps */
+    int64_t n_live[3];            /* live particles per species */
+    int64_t abs_count[3][2];      /* particles absorbed per species and wall */
+    double abs_energy[3][2];      /* sum over them of 1/2 m |v|^2 (J per macro-particle) */
+    int64_t n_emit, n_repl, n_iz; /* emitted, replenished pairs, ionisation events */
+    int64_t cand[2];              /* null-collision candidates (electrons, ions) */
+    int64_t coll[5];              /* real collisions per channel */
+    uint32_t next_id;             /* next particle id */
+    uint32_t err_bits;            /* sticky device error bits */
+} pic_tally;
+
+/* Boundary diagnostics over a window ("Benchmark cases", eqs. 1-10). */
+typedef struct pic_diag {
+    int64_t step_begin, step_end; /* window [begin, end) in steps */
+    double gamma_emit;            /* imposed Gamma_emit */
+    double gamma_emit_meas;       /* injected macro-electrons * w0 / window */
+    double gamma_ref;             /* emitted electrons returning to the cathode */
+    double gamma_net;             /* Gamma_emit - Gamma_ref */
+    double gamma_anode;           /* emitted electrons collected at the anode */
+    double backflow_pct;          /* 100 Gamma_ref / Gamma_emit */
+    double eta_net, eta_anode;    /* Gamma_net / Gamma_emit, Gamma_anode / Gamma_emit */
+    double gamma_abs[3][2];       /* particle flux per species and wall (m^-2 s^-1) */
+    double q_abs[3][2];           /* kinetic energy flux per species and wall (W m^-2) */
+    double wf_eff;                /* eq. 2 (eV) */
+    double q_emit_theory;         /* eq. 1 */
+    double q_ion_cath_recomb;     /* eq. 3 */
+    double q_cool1, q_cool2;      /* eqs. 4, 5 */
+    double q_ion_anode_recomb;    /* eq. 7 */
+    double q_anode1, q_anode2;    /* eqs. 6, 8 */
+    double phi_vc_eff;            /* eq. 10 (V); NaN if Gamma_net <= 0 */
+    double n_live[3];             /* live particles at the window end */
+} pic_diag;
+
+/* Quantities derived from a configuration on the host (no GPU needed). */
+typedef struct pic_derived {
+    double dz, invdz, w0;         /* cell, 1/cell, macro-weight n0 L / n_load (m^-2) */
+    double numax[2];              /* null-collision bound, electrons / ions (s^-1) */
+    double lam[2];                /* numax * dt */
+    double emit_per_step;         /* Gamma_emit dt / w0 */
+    int64_t capacity[3];          /* particle slots per species */
+} pic_derived;
+
+typedef struct pic_handle pic_handle;
+
+/* Derived parameters of one configuration ("Model": w0 = n0 dz / N_ppc;
+ * null-collision bound per species).  Host only.  PIC_EINVAL on a bad config. */
+int pic_derive(const pic_config *cfg, pic_derived *out);
+
+/* Device workspace bytes for n_diodes diodes (1 <= n_diodes <= PIC_MAX_DIODES). */
+int pic_workspace_size(const pic_config *cfgs, int n_diodes, size_t *bytes);
+
+/* Create a handle over a caller-owned device workspace of at least
+ * pic_workspace_size bytes (256-byte aligned), bound to hip_stream (a
+ * hipStream_t; NULL = default stream).  Enqueues the initial load (uniform
+ * positions, Maxwellian velocities; "Model"), the first deposit and the first
+ * field solve.  Asynchronous. */
+int pic_init(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes,
+             void *hip_stream, pic_handle **out);
+
+/* Advance every diode nsteps steps.  Asynchronous on the bound stream. */
+int pic_step(pic_handle *h, int64_t nsteps);
+
+/* Synchronise the bound stream; return the first sticky device error, if any. */
+int pic_sync(pic_handle *h);
+
+/* Raw cumulative tallies of one diode.  Synchronises. */
+int pic_get_tally(pic_handle *h, int diode, pic_tally *out);
+
+/* Boundary diagnostics of one diode over the last window_steps steps
+ * (a multiple of tally_period and at most tally_period * 1024 steps back), or
+ * since the initial load when window_steps == 0.  Synchronises. */
+int pic_diagnostics(pic_handle *h, int diode, int64_t window_steps, pic_diag *out);
+
+/* Node profiles of one diode (N+1 doubles each, any pointer may be NULL):
+ * phi (V), electron density (both populations) and ion density (m^-3) from
+ * the last deposit, or time averages since pic_avg_reset when time_avg != 0.
+ * Boundary nodes carry half-cell volumes.  Synchronises. */
+int pic_get_fields(pic_handle *h, int diode, double *phi, double *n_e, double *n_i, int time_avg);
+
+/* Start (on != 0) or stop time averaging of phi and densities. */
+int pic_avg_reset(pic_handle *h, int on);
+
+/* Raw per-species fixed-point deposit of the last step (N+1 int64; a particle
+ * deposits 2^32 in total).  Synchronises. */
+int pic_get_hist(pic_handle *h, int diode, int species, int64_t *out);
+
+/* Field at the nodes used by the next push (N+1 doubles).  Synchronises. */
+int pic_get_efield(pic_handle *h, int diode, double *out);
+
+/* Live particles of one species, sorted by id, into host arrays of capacity
+ * cap; *n_out receives the count (PIC_ENOSPACE if cap is too small).  Any
+ * array may be NULL.  tc is the step at which the particle is next a
+ * null-collision candidate.  Synchronises. */
+int pic_get_particles(pic_handle *h, int diode, int species, int64_t cap, int64_t *n_out,
+                      double *z, float *vx, float *vy, float *vz, uint32_t *id, uint32_t *tc);
+
+/* Replace one species of one diode by n host particles (cell order need not be
+ * kept: the next step re-sorts).  Synchronises. */
+int pic_set_particles(pic_handle *h, int diode, int species, int64_t n, const double *z,
+                      const float *vx, const float *vy, const float *vz, const uint32_t *id,
+                      const uint32_t *tc);
+
+/* Set the step counter and next particle id of one diode. */
+int pic_set_counters(pic_handle *h, int diode, int64_t step, uint32_t next_id);
+
+/* Re-deposit the current particles and re-solve the field without stepping. */
+int pic_refield(pic_handle *h);
+
+/* Per-kernel timing: run nsteps steps with HIP events around every launch of
+ * the particle kernel on the bound stream and return their mean duration (ms)
+ * and the mean live-particle count per launch.  Synchronises. */
+int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *mean_live,
+                   double *total_ms);
+
+/* Message of the last failing call on this thread. */
+const char *pic_last_error(void);
+
+/* Release the handle (not the caller's workspace or stream). */
+void pic_destroy(pic_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,745 @@
+// pic_host.hip -- host side of the C ABI declared in include/pic.h.
+//
+// Configuration derivation, workspace layout, launch schedule (load, cell
+// re-sort every K steps, particle kernel, sources+field kernel), and the
+// host-side diagnostics of "Benchmark cases" / "Boundary energy diagnostics"
+// (eqs. 1-10) computed from the device's integer tallies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstddef>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/pic.h"
+#include "pic_internal.h"
+
+using namespace pic;
+
+extern "C" hipError_t picx_launch_load(const Diode *D, const long long *n_load, int nd, long long max_load,
+                                       hipStream_t s);
+extern "C" hipError_t picx_launch_particles(const Diode *D, int nd, int mode, int ppt, int grid, hipStream_t s);
+extern "C" hipError_t picx_launch_sources_field(const Diode *D, int nd, int mode, hipStream_t s);
+extern "C" hipError_t picx_launch_sort(const Diode *D, int nd, int ppt, int grid, hipStream_t s);
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(PIC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+
+// ----------------------------------------------------------------------------
+// Derived quantities ("Model": w0 = n0 dz / N_ppc, dt and grid; MCC bound).
+// ----------------------------------------------------------------------------
+double sigma_ch(const pic_config &c, int ch, double eps)
+{
+    if (!(c.channels & (1u << ch))) return 0.0;
+    switch (ch) {
+    case CH_EEL: return c.sig_el;
+    case CH_EXC: {
+        if (eps <= E_EXC) return 0.0;
+        double x = eps / E_EXC;
+        return c.sig_x0 * std::log(x) / x;
+    }
+    case CH_IZ:
+        if (eps <= E_ION) return 0.0;
+        return c.lotz_a * 2.0 * std::log(eps / E_ION) / (eps * E_ION);
+    case CH_CX: return c.sig_cx;
+    case CH_IEL: return c.sig_iel;
+    }
+    return 0.0;
+}
+
+// Null-collision bound: max of n_g sigma_T(eps(g)) g on a dense grid of relative
+// speeds up to the largest expected one, with a 0.1 % margin.
+double numax_of(const pic_config &c, bool ion, double m, double sig_n)
+{
+    if (!(c.ng > 0.0)) return 0.0;
+    double mu = m * MASS_HE / (m + MASS_HE);
+    double ecap = ion ? std::fabs(c.V) + 40.0 * c.Ti0 : std::fabs(c.V) + 40.0 * c.Te0 + 40.0 * c.Tc;
+    double gcap = std::sqrt(2.0 * Q_E * ecap / m) + 6.0 * sig_n;
+    double best = 0.0;
+    for (int i = 1; i <= 65536; ++i) {
+        double g = gcap * (double)i / 65536.0;
+        double eps = 0.5 * mu * g * g / Q_E;
+        double sig = ion ? sigma_ch(c, CH_CX, eps) + sigma_ch(c, CH_IEL, eps)
+                         : sigma_ch(c, CH_EEL, eps) + sigma_ch(c, CH_EXC, eps) + sigma_ch(c, CH_IZ, eps);
+        double nu = c.ng * sig * g;
+        if (nu > best) best = nu;
+    }
+    return best * 1.001;
+}
+
+int check_cfg(const pic_config &c)
+{
+    if (c.N < 2 || c.N > 32767) return fail(PIC_EINVAL, "N must be in [2, 32767]");
+    if (!(c.L > 0.0) || !(c.dt > 0.0)) return fail(PIC_EINVAL, "L and dt must be positive");
+    if (c.n_load < 1 || c.n_load > (1ll << 29)) return fail(PIC_EINVAL, "n_load must be in [1, 2^29]");
+    if (c.ng < 0.0 || c.gamma_emit < 0.0 || c.Te0 < 0.0 || c.Ti0 < 0.0 || c.Tc < 0.0 || c.Tne < 0.0 ||
+        c.Tni < 0.0 || c.n0 < 0.0)
+        return fail(PIC_EINVAL, "negative density, flux or temperature");
+    if (c.tally_period < 1) return fail(PIC_EINVAL, "tally_period must be >= 1");
+    if (c.flags != 0) return fail(PIC_EINVAL, "flags must be 0");
+    return PIC_OK;
+}
+
+void derive(const pic_config &c, pic_derived &d)
+{
+    d.dz = c.L / (double)c.N;
+    d.invdz = (double)c.N / c.L;
+    d.w0 = c.n0 * c.L / (double)c.n_load;
+    double mi = MASS_HE - MASS_E;
+    double sne = std::sqrt(Q_E * c.Tne / MASS_HE), sni = std::sqrt(Q_E * c.Tni / MASS_HE);
+    d.numax[0] = numax_of(c, false, MASS_E, sne);
+    d.numax[1] = numax_of(c, true, mi, sni);
+    d.lam[0] = d.numax[0] * c.dt;
+    d.lam[1] = d.numax[1] * c.dt;
+    d.emit_per_step = d.w0 > 0.0 ? c.gamma_emit * c.dt / d.w0 : 0.0;
+    double f = c.capacity_factor > 0.0 ? c.capacity_factor : 1.6;
+    int64_t cap = (int64_t)std::ceil(f * (double)c.n_load) + 4096;
+    cap = (cap + 255) / 256 * 256;
+    for (int s = 0; s < NSP; ++s) d.capacity[s] = cap;
+}
+
+// ----------------------------------------------------------------------------
+// Workspace layout: one bump allocation per array, 256-byte aligned.
+// ----------------------------------------------------------------------------
+struct Bump {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = (off + ALIGN - 1) / ALIGN * ALIGN;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+void layout(const pic_config *cfgs, int nd, const std::vector<pic_derived> &der, Bump &bp,
+            std::vector<Diode> &hD, Diode *&dD, long long *&dNload, size_t &zero_end)
+{
+    dD = bp.take<Diode>(nd);
+    dNload = bp.take<long long>(nd);
+    // everything below is cleared at init
+    size_t zero_begin = bp.off;
+    (void)zero_begin;
+    DiodeState *st = bp.take<DiodeState>(nd);
+    DiodeTally *tl = bp.take<DiodeTally>(nd);
+    hD.assign(nd, Diode{});
+    for (int d = 0; d < nd; ++d) {
+        Diode &D = hD[d];
+        const int nn = cfgs[d].N + 1;
+        D.st = st ? st + d : nullptr;
+        D.tally = tl ? tl + d : nullptr;
+        D.ring = bp.take<TallySnap>(RING);
+        D.izq = bp.take<IzEvent>(IZQ_CAP);
+        for (int s = 0; s < NSP; ++s) {
+            D.H[s] = bp.take<unsigned long long>(nn);
+            D.Hlast[s] = bp.take<long long>(nn);
+            D.Hsum[s] = bp.take<long long>(nn);
+            D.cell_cnt[s] = bp.take<int32_t>(nn);
+        }
+        D.phi = bp.take<double>(nn);
+        D.E = bp.take<double>(nn);
+        D.phi_sum = bp.take<double>(nn);
+    }
+    zero_end = bp.off;
+    for (int d = 0; d < nd; ++d) {
+        Diode &D = hD[d];
+        for (int p = 0; p < 2; ++p)
+            for (int s = 0; s < NSP; ++s) {
+                size_t cap = (size_t)der[d].capacity[s];
+                D.buf[p][s].z = bp.take<double>(cap);
+                D.buf[p][s].vz = bp.take<float>(cap);
+                D.buf[p][s].vx = bp.take<float>(cap);
+                D.buf[p][s].vy = bp.take<float>(cap);
+                D.buf[p][s].id = bp.take<uint32_t>(cap);
+                D.buf[p][s].tc = bp.take<uint32_t>(cap);
+            }
+    }
+}
+
+void fill_params(const pic_config &c, const pic_derived &der, Diode &D)
+{
+    D.L = c.L;
+    D.dz = der.dz;
+    D.invdz = der.invdz;
+    D.V = c.V;
+    D.dt = c.dt;
+    D.w0 = der.w0;
+    D.alpha = Q_E * der.w0 * der.dz / (4294967296.0 * EPS0);
+    D.N = c.N;
+    for (int s = 0; s < NSP; ++s) D.cap[s] = (int32_t)der.capacity[s];
+    const double mi = MASS_HE - MASS_E;
+    D.mass[SP_P] = D.mass[SP_E] = MASS_E;
+    D.mass[SP_I] = mi;
+    D.qmdt[SP_P] = D.qmdt[SP_E] = -Q_E / MASS_E * c.dt;
+    D.qmdt[SP_I] = Q_E / mi * c.dt;
+    for (int ion = 0; ion < 2; ++ion) {
+        const double m = ion ? mi : MASS_E;
+        const double mu = m * MASS_HE / (m + MASS_HE);
+        D.numax[ion] = der.numax[ion];
+        D.lam[ion] = der.lam[ion];
+        D.numax_f[ion] = (float)der.numax[ion];
+        D.sig_n[ion] = (float)std::sqrt(Q_E * (ion ? c.Tni : c.Tne) / MASS_HE);
+        D.half_mu_over_e[ion] = (float)(0.5 * mu / Q_E);
+        D.mfrac_m[ion] = (float)(m / (m + MASS_HE));
+        D.mfrac_M[ion] = (float)(MASS_HE / (m + MASS_HE));
+        D.two_e_over_mu[ion] = (float)(2.0 * Q_E / mu);
+    }
+    D.ng = (float)c.ng;
+    D.sig_el = (float)c.sig_el;
+    D.sig_x0 = (float)c.sig_x0;
+    D.lotz_a2 = (float)(2.0 * c.lotz_a / E_ION);
+    D.sig_cx = (float)c.sig_cx;
+    D.sig_iel = (float)c.sig_iel;
+    D.emit_x = der.emit_per_step;
+    D.sig_c = std::sqrt(Q_E * c.Tc / MASS_E);
+    D.sig_e0 = std::sqrt(Q_E * c.Te0 / MASS_E);
+    D.sig_i0 = std::sqrt(Q_E * c.Ti0 / mi);
+    D.kseed = c.seed ^ c.diode;
+    D.channels = c.channels;
+    D.replenish = c.replenish;
+    D.tally_period = c.tally_period;
+}
+
+}  // namespace
+
+struct pic_handle {
+    int nd = 0;
+    std::vector<pic_config> cfg;
+    std::vector<pic_derived> der;
+    char *ws = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    std::vector<Diode> hD;
+    Diode *dD = nullptr;
+    long long *dNload = nullptr;
+    int64_t issued = 0;         // steps enqueued so far (re-sort schedule)
+    bool sort_next = true;      // force a re-sort before the next step
+    int ppt = 4;
+    int grid = 1024;
+    int sort_period = 16;
+    std::vector<std::array<int64_t, NSP>> live_offset;
+};
+
+namespace {
+
+int grid_for(const pic_handle *h)
+{
+    int64_t chunks = 0;
+    for (int d = 0; d < h->nd; ++d)
+        for (int s = 0; s < NSP; ++s) chunks += (h->der[d].capacity[s] + 256 * h->ppt - 1) / (256 * h->ppt);
+    int64_t g = std::min<int64_t>(chunks, 2048);
+    g = std::max<int64_t>(8, (g + 7) / 8 * 8);
+    return (int)g;
+}
+
+int launch_step(pic_handle *h)
+{
+    if (h->sort_next || (h->sort_period > 0 && h->issued % h->sort_period == 0)) {
+        HIP_TRY(picx_launch_sort(h->dD, h->nd, h->ppt, h->grid, h->stream));
+        h->sort_next = false;
+    }
+    HIP_TRY(picx_launch_particles(h->dD, h->nd, 0, h->ppt, h->grid, h->stream));
+    HIP_TRY(picx_launch_sources_field(h->dD, h->nd, 0, h->stream));
+    h->issued++;
+    return PIC_OK;
+}
+
+int refield(pic_handle *h)
+{
+    HIP_TRY(picx_launch_sort(h->dD, h->nd, h->ppt, h->grid, h->stream));
+    HIP_TRY(picx_launch_particles(h->dD, h->nd, 1, h->ppt, h->grid, h->stream));
+    HIP_TRY(picx_launch_sources_field(h->dD, h->nd, 1, h->stream));
+    h->sort_next = false;
+    return PIC_OK;
+}
+
+int read_state(pic_handle *h, int d, DiodeState &st, DiodeTally &t)
+{
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipMemcpy(&st, h->hD[d].st, sizeof(st), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&t, h->hD[d].tally, sizeof(t), hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+void live_counts(const pic_handle *h, int d, const DiodeTally &t, int64_t out[NSP])
+{
+    const int64_t nl = h->cfg[d].n_load;
+    int64_t born[NSP] = {nl + (int64_t)t.n_iz + (int64_t)t.n_repl, (int64_t)t.n_emit,
+                         nl + (int64_t)t.n_iz + (int64_t)t.n_repl};
+    for (int s = 0; s < NSP; ++s)
+        out[s] = born[s] - (int64_t)t.abs_count[s][0] - (int64_t)t.abs_count[s][1] + h->live_offset[d][s];
+}
+
+int err_code(uint32_t bits)
+{
+    if (bits & ERR_CAPACITY) return fail(PIC_ENOSPACE, "particle capacity exceeded on the device");
+    if (bits & ERR_NULLCOLL) return fail(PIC_ENULLCOLL, "collision frequency exceeded the null-collision bound");
+    if (bits & ERR_IZQ) return fail(PIC_ERANGE, "ionisation queue overflow");
+    if (bits & ERR_NAN) return fail(PIC_ENAN, "non-finite particle position");
+    return PIC_OK;
+}
+
+// Boundary diagnostics over a window of tallies ("Benchmark cases": Gamma_net,
+// backflow ratio, efficiencies; "Boundary energy diagnostics": eqs. 1-10).
+void diag_window(const pic_config &c, double w0, double window_s, const DiodeTally &a, const DiodeTally &b,
+                 pic_diag &o)
+{
+    const double inv = w0 / window_s;
+    for (int s = 0; s < NSP; ++s)
+        for (int w = 0; w < 2; ++w) {
+            o.gamma_abs[s][w] = (double)(b.abs_count[s][w] - a.abs_count[s][w]) * inv;
+            o.q_abs[s][w] = (b.abs_energy[s][w] - a.abs_energy[s][w]) * inv;
+        }
+    const double ge = c.gamma_emit;
+    o.gamma_emit = ge;
+    o.gamma_emit_meas = (double)(b.n_emit - a.n_emit) * inv;
+    o.gamma_ref = o.gamma_abs[SP_E][0];
+    o.gamma_anode = o.gamma_abs[SP_E][1];
+    o.gamma_net = ge - o.gamma_ref;
+    o.backflow_pct = ge > 0.0 ? 100.0 * o.gamma_ref / ge : NAN;
+    o.eta_net = ge > 0.0 ? o.gamma_net / ge : NAN;
+    o.eta_anode = ge > 0.0 ? o.gamma_anode / ge : NAN;
+    const double kbe = K_B / Q_E;
+    const double AR = 1.20e6 / (kbe * kbe);          // A m^-2 eV^-2
+    const double Tc = c.Tc;
+    o.wf_eff = (ge > 0.0 && Tc > 0.0) ? -Tc * std::log(Q_E * ge / (AR * Tc * Tc)) : NAN;
+    o.q_emit_theory = ge * Q_E * (o.wf_eff + 2.0 * Tc);
+    o.q_ion_cath_recomb = o.gamma_abs[SP_I][0] * Q_E * E_ION;
+    o.q_cool1 = o.q_emit_theory - o.q_abs[SP_E][0] - o.q_abs[SP_P][0] - o.q_abs[SP_I][0];
+    o.q_cool2 = o.q_cool1 - o.q_ion_cath_recomb;
+    o.q_anode1 = o.q_abs[SP_E][1] + o.q_abs[SP_P][1] + o.q_abs[SP_I][1];
+    o.q_ion_anode_recomb = o.gamma_abs[SP_I][1] * Q_E * E_ION;
+    o.q_anode2 = o.q_anode1 + o.q_ion_anode_recomb;
+    o.phi_vc_eff = (ge > 0.0 && o.gamma_net > 0.0) ? Tc * std::log(o.gamma_net / ge) : NAN;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char *pic_last_error(void) { return g_err.c_str(); }
+
+int pic_derive(const pic_config *cfg, pic_derived *out)
+{
+    if (!cfg || !out) return fail(PIC_EINVAL, "null argument");
+    int rc = check_cfg(*cfg);
+    if (rc) return rc;
+    derive(*cfg, *out);
+    return PIC_OK;
+}
+
+int pic_workspace_size(const pic_config *cfgs, int n_diodes, size_t *bytes)
+{
+    if (!cfgs || !bytes || n_diodes < 1 || n_diodes > PIC_MAX_DIODES) return fail(PIC_EINVAL, "bad arguments");
+    std::vector<pic_derived> der(n_diodes);
+    for (int d = 0; d < n_diodes; ++d) {
+        int rc = check_cfg(cfgs[d]);
+        if (rc) return rc;
+        derive(cfgs[d], der[d]);
+    }
+    Bump bp{nullptr};
+    std::vector<Diode> hD;
+    Diode *dD;
+    long long *dN;
+    size_t zend;
+    layout(cfgs, n_diodes, der, bp, hD, dD, dN, zend);
+    *bytes = (bp.off + ALIGN - 1) / ALIGN * ALIGN;
+    return PIC_OK;
+}
+
+int pic_init(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes, void *hip_stream,
+             pic_handle **out)
+{
+    if (!cfgs || !out || !dev_workspace || n_diodes < 1 || n_diodes > PIC_MAX_DIODES)
+        return fail(PIC_EINVAL, "bad arguments");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % ALIGN) return fail(PIC_EINVAL, "workspace not 256-byte aligned");
+    size_t need;
+    int rc = pic_workspace_size(cfgs, n_diodes, &need);
+    if (rc) return rc;
+    if (bytes < need) return fail(PIC_ENOSPACE, "workspace too small");
+    pic_handle *h = new (std::nothrow) pic_handle;
+    if (!h) return fail(PIC_ENOSPACE, "host allocation failed");
+    h->nd = n_diodes;
+    h->cfg.assign(cfgs, cfgs + n_diodes);
+    h->der.resize(n_diodes);
+    for (int d = 0; d < n_diodes; ++d) derive(cfgs[d], h->der[d]);
+    h->ws = static_cast<char *>(dev_workspace);
+    h->bytes = bytes;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->live_offset.assign(n_diodes, std::array<int64_t, NSP>{0, 0, 0});
+    h->sort_period = cfgs[0].sort_period > 0 ? cfgs[0].sort_period : 16;
+    Bump bp{h->ws};
+    size_t zend;
+    layout(cfgs, n_diodes, h->der, bp, h->hD, h->dD, h->dNload, zend);
+    for (int d = 0; d < n_diodes; ++d) fill_params(cfgs[d], h->der[d], h->hD[d]);
+    h->grid = grid_for(h);
+
+    auto cleanup = [&](int code) { delete h; return code; };
+    size_t zbeg = (reinterpret_cast<char *>(h->hD[0].st) - h->ws);
+    if (hipMemsetAsync(h->ws + zbeg, 0, zend - zbeg, h->stream) != hipSuccess)
+        return cleanup(fail(PIC_EHIP, "hipMemsetAsync failed"));
+    std::vector<DiodeState> st(n_diodes);
+    std::vector<long long> nl(n_diodes);
+    long long maxl = 0;
+    for (int d = 0; d < n_diodes; ++d) {
+        std::memset(&st[d], 0, sizeof(DiodeState));
+        st[d].n[SP_P] = st[d].n[SP_I] = (int32_t)cfgs[d].n_load;
+        st[d].next_id = (uint32_t)(2 * cfgs[d].n_load);
+        nl[d] = cfgs[d].n_load;
+        maxl = std::max(maxl, nl[d]);
+    }
+    if (hipMemcpyAsync(h->dD, h->hD.data(), sizeof(Diode) * n_diodes, hipMemcpyHostToDevice, h->stream) ||
+        hipMemcpyAsync(h->dNload, nl.data(), sizeof(long long) * n_diodes, hipMemcpyHostToDevice, h->stream) ||
+        hipMemcpyAsync(h->hD[0].st, st.data(), sizeof(DiodeState) * n_diodes, hipMemcpyHostToDevice, h->stream))
+        return cleanup(fail(PIC_EHIP, "hipMemcpyAsync failed"));
+    if (picx_launch_load(h->dD, h->dNload, n_diodes, maxl, h->stream) != hipSuccess)
+        return cleanup(fail(PIC_EHIP, "load launch failed"));
+    // the staging vectors die here: wait for the copies
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return cleanup(fail(PIC_EHIP, "sync failed"));
+    rc = refield(h);
+    if (rc) return cleanup(rc);
+    *out = h;
+    return PIC_OK;
+}
+
+int pic_step(pic_handle *h, int64_t nsteps)
+{
+    if (!h || nsteps < 0) return fail(PIC_EINVAL, "bad arguments");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        int rc = launch_step(h);
+        if (rc) return rc;
+    }
+    return PIC_OK;
+}
+
+int pic_sync(pic_handle *h)
+{
+    if (!h) return fail(PIC_EINVAL, "null handle");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int d = 0; d < h->nd; ++d) {
+        uint32_t err = 0;
+        HIP_TRY(hipMemcpy(&err, &h->hD[d].st->err, sizeof(err), hipMemcpyDeviceToHost));
+        if (err) return err_code(err);
+    }
+    return PIC_OK;
+}
+
+int pic_get_tally(pic_handle *h, int diode, pic_tally *out)
+{
+    if (!h || !out || diode < 0 || diode >= h->nd) return fail(PIC_EINVAL, "bad arguments");
+    DiodeState st;
+    DiodeTally t;
+    int rc = read_state(h, diode, st, t);
+    if (rc) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->step = st.step;
+    live_counts(h, diode, t, out->n_live);
+    for (int s = 0; s < NSP; ++s)
+        for (int w = 0; w < 2; ++w) {
+            out->abs_count[s][w] = (int64_t)t.abs_count[s][w];
+            out->abs_energy[s][w] = t.abs_energy[s][w];
+        }
+    out->n_emit = (int64_t)t.n_emit;
+    out->n_repl = (int64_t)t.n_repl;
+    out->n_iz = (int64_t)t.n_iz;
+    for (int k = 0; k < 2; ++k) out->cand[k] = (int64_t)t.cand[k];
+    for (int k = 0; k < NCH; ++k) out->coll[k] = (int64_t)t.coll[k];
+    out->next_id = st.next_id;
+    out->err_bits = st.err;
+    return PIC_OK;
+}
+
+int pic_diagnostics(pic_handle *h, int diode, int64_t window_steps, pic_diag *out)
+{
+    if (!h || !out || diode < 0 || diode >= h->nd || window_steps < 0) return fail(PIC_EINVAL, "bad arguments");
+    const pic_config &c = h->cfg[diode];
+    DiodeState st;
+    DiodeTally now;
+    int rc = read_state(h, diode, st, now);
+    if (rc) return rc;
+    std::memset(out, 0, sizeof(*out));
+    DiodeTally zero;
+    std::memset(&zero, 0, sizeof(zero));
+    const int64_t D = c.tally_period;
+    int64_t e_step = st.step, b_step = 0;
+    DiodeTally tb = zero, te = now;
+    if (window_steps > 0) {
+        if (window_steps % D) return fail(PIC_EINVAL, "window_steps must be a multiple of tally_period");
+        e_step = (int64_t)st.step / D * D;
+        b_step = e_step - window_steps;
+        if (b_step < 0) return fail(PIC_EINVAL, "window reaches before step 0");
+        if (window_steps / D >= RING) return fail(PIC_EINVAL, "window longer than the snapshot ring");
+        auto snap_at = [&](int64_t s, DiodeTally &t) -> int {
+            if (s == 0) { t = zero; return PIC_OK; }
+            TallySnap sn;
+            HIP_TRY(hipMemcpy(&sn, h->hD[diode].ring + (s / D) % RING, sizeof(sn), hipMemcpyDeviceToHost));
+            if ((int64_t)sn.step != s) return fail(PIC_ERANGE, "snapshot no longer in the ring");
+            t = sn.t;
+            return PIC_OK;
+        };
+        if ((rc = snap_at(b_step, tb))) return rc;
+        if ((rc = snap_at(e_step, te))) return rc;
+    }
+    if (e_step <= b_step) return fail(PIC_EINVAL, "empty window");
+    out->step_begin = b_step;
+    out->step_end = e_step;
+    diag_window(c, h->der[diode].w0, (double)(e_step - b_step) * c.dt, tb, te, *out);
+    int64_t live[NSP];
+    live_counts(h, diode, te, live);
+    for (int s = 0; s < NSP; ++s) out->n_live[s] = (double)live[s];
+    return err_code(st.err);
+}
+
+int pic_avg_reset(pic_handle *h, int on)
+{
+    if (!h) return fail(PIC_EINVAL, "null handle");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int d = 0; d < h->nd; ++d) {
+        const Diode &D = h->hD[d];
+        const size_t nn = h->cfg[d].N + 1;
+        for (int s = 0; s < NSP; ++s) HIP_TRY(hipMemsetAsync(D.Hsum[s], 0, nn * sizeof(long long), h->stream));
+        HIP_TRY(hipMemsetAsync(D.phi_sum, 0, nn * sizeof(double), h->stream));
+        int v[2] = {on ? 1 : 0, 0};
+        HIP_TRY(hipMemcpyAsync(&D.st->avg_on, v, sizeof(v), hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    return PIC_OK;
+}
+
+int pic_get_fields(pic_handle *h, int diode, double *phi, double *n_e, double *n_i, int time_avg)
+{
+    if (!h || diode < 0 || diode >= h->nd) return fail(PIC_EINVAL, "bad arguments");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const Diode &D = h->hD[diode];
+    const int nn = h->cfg[diode].N + 1;
+    DiodeState st;
+    HIP_TRY(hipMemcpy(&st, D.st, sizeof(st), hipMemcpyDeviceToHost));
+    const double navg = time_avg ? (double)std::max(st.avg_steps, 1) : 1.0;
+    if (time_avg && st.avg_steps == 0) return fail(PIC_EINVAL, "no time average accumulated");
+    if (phi) {
+        HIP_TRY(hipMemcpy(phi, time_avg ? D.phi_sum : D.phi, nn * sizeof(double), hipMemcpyDeviceToHost));
+        if (time_avg)
+            for (int j = 0; j < nn; ++j) phi[j] /= navg;
+    }
+    std::vector<long long> H[NSP];
+    for (int s = 0; s < NSP; ++s) {
+        H[s].resize(nn);
+        HIP_TRY(hipMemcpy(H[s].data(), time_avg ? D.Hsum[s] : D.Hlast[s], nn * sizeof(long long),
+                          hipMemcpyDeviceToHost));
+    }
+    const double k = h->der[diode].w0 / (4294967296.0 * h->der[diode].dz * navg);
+    for (int j = 0; j < nn; ++j) {
+        const double vol = (j == 0 || j == nn - 1) ? 2.0 : 1.0;
+        if (n_e) n_e[j] = k * vol * ((double)H[SP_P][j] + (double)H[SP_E][j]);
+        if (n_i) n_i[j] = k * vol * (double)H[SP_I][j];
+    }
+    return PIC_OK;
+}
+
+int pic_get_hist(pic_handle *h, int diode, int species, int64_t *out)
+{
+    if (!h || !out || diode < 0 || diode >= h->nd || species < 0 || species >= NSP)
+        return fail(PIC_EINVAL, "bad arguments");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipMemcpy(out, h->hD[diode].Hlast[species], (h->cfg[diode].N + 1) * sizeof(int64_t),
+                      hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+int pic_get_efield(pic_handle *h, int diode, double *out)
+{
+    if (!h || !out || diode < 0 || diode >= h->nd) return fail(PIC_EINVAL, "bad arguments");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipMemcpy(out, h->hD[diode].E, (h->cfg[diode].N + 1) * sizeof(double), hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+int pic_get_particles(pic_handle *h, int diode, int species, int64_t cap, int64_t *n_out, double *z, float *vx,
+                      float *vy, float *vz, uint32_t *id, uint32_t *tc)
+{
+    if (!h || !n_out || diode < 0 || diode >= h->nd || species < 0 || species >= NSP || cap < 0)
+        return fail(PIC_EINVAL, "bad arguments");
+    DiodeState st;
+    DiodeTally t;
+    int rc = read_state(h, diode, st, t);
+    if (rc) return rc;
+    const int n = st.n[species];
+    const SpeciesBuf &b = h->hD[diode].buf[st.parity][species];
+    std::vector<double> hz(n);
+    std::vector<float> hvx(n), hvy(n), hvz(n);
+    std::vector<uint32_t> hid(n), htc(n);
+    if (n > 0) {
+        HIP_TRY(hipMemcpy(hz.data(), b.z, n * sizeof(double), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hvx.data(), b.vx, n * sizeof(float), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hvy.data(), b.vy, n * sizeof(float), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hvz.data(), b.vz, n * sizeof(float), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hid.data(), b.id, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(htc.data(), b.tc, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    }
+    std::vector<int> idx;
+    idx.reserve(n);
+    for (int i = 0; i < n; ++i)
+        if (hz[i] >= 0.0) idx.push_back(i);
+    std::sort(idx.begin(), idx.end(), [&](int a, int c) { return hid[a] < hid[c]; });
+    *n_out = (int64_t)idx.size();
+    if ((int64_t)idx.size() > cap) return fail(PIC_ENOSPACE, "output capacity too small");
+    for (size_t k = 0; k < idx.size(); ++k) {
+        const int i = idx[k];
+        if (z) z[k] = hz[i];
+        if (vx) vx[k] = hvx[i];
+        if (vy) vy[k] = hvy[i];
+        if (vz) vz[k] = hvz[i];
+        if (id) id[k] = hid[i];
+        if (tc) tc[k] = htc[i];
+    }
+    return PIC_OK;
+}
+
+int pic_set_particles(pic_handle *h, int diode, int species, int64_t n, const double *z, const float *vx,
+                      const float *vy, const float *vz, const uint32_t *id, const uint32_t *tc)
+{
+    if (!h || diode < 0 || diode >= h->nd || species < 0 || species >= NSP || n < 0)
+        return fail(PIC_EINVAL, "bad arguments");
+    if (n > 0 && (!z || !vx || !vy || !vz || !id || !tc)) return fail(PIC_EINVAL, "null array");
+    if (n > h->der[diode].capacity[species]) return fail(PIC_ENOSPACE, "more particles than capacity");
+    for (int64_t i = 0; i < n; ++i)
+        if (!(z[i] > 0.0 && z[i] < h->cfg[diode].L)) return fail(PIC_EINVAL, "particle outside (0, L)");
+    DiodeState st;
+    DiodeTally t;
+    int rc = read_state(h, diode, st, t);
+    if (rc) return rc;
+    const SpeciesBuf &b = h->hD[diode].buf[st.parity][species];
+    if (n > 0) {
+        HIP_TRY(hipMemcpy(b.z, z, n * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b.vx, vx, n * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b.vy, vy, n * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b.vz, vz, n * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b.id, id, n * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b.tc, tc, n * sizeof(uint32_t), hipMemcpyHostToDevice));
+    }
+    int32_t nn = (int32_t)n;
+    HIP_TRY(hipMemcpy(&h->hD[diode].st->n[species], &nn, sizeof(nn), hipMemcpyHostToDevice));
+    int64_t live[NSP];
+    live_counts(h, diode, t, live);
+    h->live_offset[diode][species] += n - live[species];
+    h->sort_next = true;
+    return PIC_OK;
+}
+
+int pic_set_counters(pic_handle *h, int diode, int64_t step, uint32_t next_id)
+{
+    if (!h || diode < 0 || diode >= h->nd || step < 0 || step >= 0xFFFFFFFFll) return fail(PIC_EINVAL, "bad arguments");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    uint32_t v[2] = {next_id, (uint32_t)step};
+    static_assert(offsetof(DiodeState, step) == offsetof(DiodeState, next_id) + 4, "layout");
+    HIP_TRY(hipMemcpy(&h->hD[diode].st->next_id, v, sizeof(v), hipMemcpyHostToDevice));
+    return PIC_OK;
+}
+
+int pic_refield(pic_handle *h)
+{
+    if (!h) return fail(PIC_EINVAL, "null handle");
+    return refield(h);
+}
+
+int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *mean_live, double *total_ms)
+{
+    if (!h || nsteps < 1) return fail(PIC_EINVAL, "bad arguments");
+    const int64_t every = std::max<int64_t>(1, nsteps / 512);
+    const int64_t nev = (nsteps + every - 1) / every;
+    std::vector<hipEvent_t> ev(2 * nev);
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    hipEvent_t t0, t1;
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+    int64_t live0[NSP], live1[NSP];
+    {
+        DiodeState st;
+        DiodeTally t;
+        int64_t sum[NSP] = {0, 0, 0};
+        for (int d = 0; d < h->nd; ++d) {
+            int rc = read_state(h, d, st, t);
+            if (rc) return rc;
+            live_counts(h, d, t, live0);
+            for (int s = 0; s < NSP; ++s) sum[s] += live0[s];
+        }
+        std::copy(sum, sum + NSP, live0);
+    }
+    HIP_TRY(hipEventRecord(t0, h->stream));
+    int64_t k_ev = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (h->sort_next || (h->sort_period > 0 && h->issued % h->sort_period == 0)) {
+            HIP_TRY(picx_launch_sort(h->dD, h->nd, h->ppt, h->grid, h->stream));
+            h->sort_next = false;
+        }
+        const bool rec = (k % every) == 0 && k_ev < nev;
+        if (rec) HIP_TRY(hipEventRecord(ev[2 * k_ev], h->stream));
+        HIP_TRY(picx_launch_particles(h->dD, h->nd, 0, h->ppt, h->grid, h->stream));
+        if (rec) { HIP_TRY(hipEventRecord(ev[2 * k_ev + 1], h->stream)); ++k_ev; }
+        HIP_TRY(picx_launch_sources_field(h->dD, h->nd, 0, h->stream));
+        h->issued++;
+    }
+    HIP_TRY(hipEventRecord(t1, h->stream));
+    HIP_TRY(hipEventSynchronize(t1));
+    double acc = 0.0;
+    for (int64_t q = 0; q < k_ev; ++q) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]));
+        acc += ms;
+    }
+    float tot = 0.f;
+    HIP_TRY(hipEventElapsedTime(&tot, t0, t1));
+    {
+        DiodeState st;
+        DiodeTally t;
+        int64_t sum[NSP] = {0, 0, 0};
+        for (int d = 0; d < h->nd; ++d) {
+            int rc = read_state(h, d, st, t);
+            if (rc) return rc;
+            live_counts(h, d, t, live1);
+            for (int s = 0; s < NSP; ++s) sum[s] += live1[s];
+        }
+        std::copy(sum, sum + NSP, live1);
+    }
+    for (auto &e : ev) hipEventDestroy(e);
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    if (particle_kernel_ms) *particle_kernel_ms = acc / (double)k_ev;
+    if (mean_live) {
+        double a = 0, b = 0;
+        for (int s = 0; s < NSP; ++s) { a += live0[s]; b += live1[s]; }
+        *mean_live = 0.5 * (a + b);
+    }
+    if (total_ms) *total_ms = tot;
+    return PIC_OK;
+}
+
+void pic_destroy(pic_handle *h) { delete h; }
+
+}  // extern "C"

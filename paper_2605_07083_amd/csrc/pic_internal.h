@@ -1,0 +1,118 @@
+// pic_internal.h -- device-resident data layout of the gfx950 PIC-MCC library.
+//
+// Every diode of a handle owns, inside the caller's workspace:
+//   * two structure-of-arrays particle buffers per species (ping-pong for the
+//     cell re-sort): z f64, vz f32, vx f32, vy f32, id u32, tc u32;
+//   * three fixed-point deposit histograms (int64, N+1 nodes) plus copies of
+//     the last step's, phi and E (f64, N+1), time-average accumulators;
+//   * sort scratch (one int32 per cell and species), the ionisation queue,
+//     the mutable state block, cumulative tallies and a ring of snapshots.
+// The hot loop streams z (r/w), vz (r/w) and tc (r) only; vx, vy and id are
+// touched for null-collision candidates and absorbed particles.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int NSP = 3;
+constexpr int SP_P = 0, SP_E = 1, SP_I = 2;
+constexpr int NCH = 5;
+constexpr int CH_EEL = 0, CH_EXC = 1, CH_IZ = 2, CH_CX = 3, CH_IEL = 4;
+constexpr uint32_t EV_COLL = 1, EV_LOAD = 2, EV_EMIT = 3, EV_BIRTH = 4;
+constexpr uint32_t LOAD_STEP = 0xFFFFFFFFu;
+constexpr uint32_t NEVER = 0xFFFFFFFFu;
+constexpr int RING = 1024;           // tally snapshots kept per diode
+constexpr int IZQ_CAP = 4096;        // ionisation events per diode per step
+constexpr int MAX_DIODES = 256;
+
+// sticky device error bits
+constexpr uint32_t ERR_CAPACITY = 1u;
+constexpr uint32_t ERR_NULLCOLL = 2u;
+constexpr uint32_t ERR_NAN = 4u;
+constexpr uint32_t ERR_IZQ = 8u;
+
+// physical constants (CODATA 2018)
+constexpr double Q_E = 1.602176634e-19;
+constexpr double K_B = 1.380649e-23;
+constexpr double EPS0 = 8.8541878128e-12;
+constexpr double MASS_E = 9.1093837015e-31;
+constexpr double MASS_HE = 6.6464731e-27;
+constexpr double E_EXC = 19.82;
+constexpr double E_ION = 24.59;
+
+struct SpeciesBuf {
+    double *z;
+    float *vz, *vx, *vy;
+    uint32_t *id, *tc;
+};
+
+// Mutable per-diode state (device).
+struct DiodeState {
+    int32_t n[NSP];        // slots in use in the current buffer (live + holes)
+    int32_t n_new[NSP];    // live count found by the re-sort
+    int32_t parity;        // which buffer is current
+    uint32_t next_id;
+    uint32_t step;
+    int32_t iz_count;      // ionisation events queued this step
+    int32_t ion_lost;      // ions absorbed this step
+    uint32_t err;
+    int32_t avg_on;
+    int32_t avg_steps;
+};
+
+// Cumulative tallies (device); all integers are order independent.
+struct DiodeTally {
+    unsigned long long abs_count[NSP][2];
+    double abs_energy[NSP][2];
+    unsigned long long n_emit, n_repl, n_iz;
+    unsigned long long cand[2];
+    unsigned long long coll[NCH];
+};
+
+struct TallySnap {
+    unsigned long long step;
+    DiodeTally t;
+};
+
+struct IzEvent {
+    double z;
+    uint32_t parent;
+    float ve[3];   // secondary electron
+    float vi[3];   // new ion
+    uint32_t pad;
+};
+
+// Read-only parameters and buffer pointers of one diode (device copy).
+struct Diode {
+    double L, dz, invdz, V, dt, w0;
+    double alpha;          // e w0 dz / (2^32 eps0): node charge -> Poisson rhs
+    int32_t N;
+    int32_t cap[NSP];
+    double qmdt[NSP];      // (q/m) dt
+    double mass[NSP];
+    double numax[2], lam[2];
+    float numax_f[2];
+    float sig_n[2];        // neutral thermal speed per axis (e, ion collisions)
+    float half_mu_over_e[2];
+    float mfrac_m[2];      // m / (m + M)
+    float mfrac_M[2];      // M / (m + M)
+    float two_e_over_mu[2];
+    float ng, sig_el, sig_x0, lotz_a2, sig_cx, sig_iel;
+    double emit_x;         // Gamma dt / w0
+    double sig_c, sig_e0, sig_i0;
+    uint32_t kseed, channels;
+    int32_t replenish, tally_period;
+    SpeciesBuf buf[2][NSP];
+    unsigned long long *H[NSP];
+    long long *Hlast[NSP];
+    long long *Hsum[NSP];
+    double *phi, *E, *phi_sum;
+    int32_t *cell_cnt[NSP];
+    IzEvent *izq;
+    DiodeState *st;
+    DiodeTally *tally;
+    TallySnap *ring;
+};
+
+}  // namespace pic

@@ -1,0 +1,204 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Bit-exact: deposits (as a function of the particle array), ids, free-flight
+counters, absorbed / collision / birth counts.  Floating point: positions and
+velocities within 1e-5 relative (FP32 velocities), phi and E within 1e-10 of
+their maxima.
+"""
+import numpy as np
+import pytest
+
+from gpu_compare import (by_id, compare_particles, compare_tallies, deposit_matches, field_matches,
+                         gpu_state, oracle_from_gpu, restart_step_check)
+from paper_2605_07083_amd import presets
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pic():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2605_07083_amd import pic as P
+    P.lib()
+    return P
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def test_load_matches_oracle(pic, O):
+    cfg = presets.tiny()
+    _say("case: load, tiny diode")
+    h = pic.Handle(cfg)
+    st, t = gpu_state(h)
+    s = O.Sim(cfg)
+    s.load()
+    for sp in (0, 2):
+        g, o = by_id(st[sp]), by_id(s.particles(sp))
+        assert np.array_equal(g["id"], o["id"])
+        assert np.array_equal(g["z"], o["z"])            # same FP64 expression: bit exact
+        assert np.array_equal(g["tc"], o["tc"])
+        for c in ("vx", "vy", "vz"):
+            # FP64 Box-Muller on both sides, rounded once to FP32 on the GPU
+            assert np.max(np.abs(g[c] - o[c].astype(np.float32)) / np.abs(o[c]).max()) < 1e-6
+    assert len(st[1]["id"]) == 0
+    assert deposit_matches(O, cfg, h, st) == []
+    s2 = oracle_from_gpu(O, cfg, st, t)
+    assert field_matches(O, cfg, h, s2) == []
+
+
+@pytest.mark.parametrize("name,over", [
+    ("tiny, emission x100", dict(gamma_emit=1e21)),
+    ("hot electrons: excitation and ionisation", dict(Te0=25.0, gamma_emit=1e21, ng=3.2e22)),
+    ("ions: charge exchange and elastic", dict(Ti0=1.0, ng=3.2e22, gamma_emit=0.0)),
+])
+def test_restart_parity_per_step(pic, O, name, over):
+    cfg = presets.scaled(presets.tiny(), **over)
+    _say("case: restart parity, " + name)
+    h = pic.Handle(cfg)
+    probs = restart_step_check(O, cfg, h, 100)
+    assert probs == [], "\n".join(probs[:20])
+    t = h.tally()
+    assert t["cand"].sum() > 0 and t["coll"].sum() > 0
+    if over.get("Te0", 0) > 20:
+        assert t["coll"][1] > 0 and t["coll"][2] > 0 and t["n_iz"] > 0
+    if over.get("Ti0", 0) >= 1.0:
+        assert t["coll"][3] > 0 and t["coll"][4] > 0
+    if over.get("gamma_emit", 0) > 0:
+        assert t["n_emit"] > 100
+
+
+def test_free_run_100_steps(pic, O):
+    cfg = presets.scaled(presets.tiny(), gamma_emit=1e21)
+    _say("case: free-running 100 steps, tiny")
+    h = pic.Handle(cfg)
+    s = O.Sim(cfg)
+    s.load()
+    t0g, t0o = h.tally(), s.tally()
+    h.step(100)
+    s.step(100)
+    st, t1g = gpu_state(h)
+    probs = []
+    for sp in range(3):
+        probs += compare_particles(cfg, st[sp], s.particles(sp), sp)
+    probs += compare_tallies(t0g, t1g, t0o, s.tally())
+    probs += deposit_matches(O, cfg, h, st)
+    assert probs == [], "\n".join(probs[:20])
+
+
+def test_batched_equals_single(pic, O):
+    base = presets.tiny()
+    cfgs = [presets.scaled(base, diode=d, gamma_emit=g, Tc=T * presets.KB_OVER_E, n_load=nl)
+            for d, (g, T, nl) in enumerate([(1e21, 1800, 20000), (3e21, 2200, 31000), (5e20, 2000, 9000)])]
+    _say("case: batched 3 diodes vs single")
+    hb = pic.Handle(cfgs)
+    hs = [pic.Handle(c) for c in cfgs]
+    hb.step(60)
+    for h in hs:
+        h.step(60)
+    for d, h in enumerate(hs):
+        tb, ts = hb.tally(d), h.tally()
+        for k in ("abs_count", "cand", "coll", "n_live"):
+            assert np.array_equal(tb[k], ts[k]), (d, k)
+        for k in ("n_emit", "n_repl", "n_iz", "next_id"):
+            assert tb[k] == ts[k]
+        for sp in range(3):
+            assert np.array_equal(hb.hist(d, sp), h.hist(0, sp))
+            pb, ps = hb.particles(d, sp), h.particles(0, sp)
+            for k in pb:
+                assert np.array_equal(pb[k], ps[k]), (d, sp, k)
+
+
+def test_bench_scale_parity(pic, O):
+    cfg = presets.bench()
+    _say("case: benchmark diode (2048 cells, 409.6k per species), 40 steps then restart parity")
+    h = pic.Handle(cfg)
+    h.step(40)
+    probs = restart_step_check(O, cfg, h, 2)
+    assert probs == [], "\n".join(probs[:20])
+
+
+def test_large_scale_parity(pic, O):
+    cfg = presets.large()
+    _say("case: large diode (16384 cells, 16.4M per species), 3 steps then one restart step")
+    h = pic.Handle(cfg)
+    h.step(3)
+    probs = restart_step_check(O, cfg, h, 1)
+    assert probs == [], "\n".join(probs[:20])
+
+
+def test_edge_cases(pic, O):
+    _say("case: edge cases")
+    # smallest grid, no emission: the emitted population stays empty
+    cfg = presets.scaled(presets.tiny(), N=2, n_load=500, gamma_emit=0.0)
+    h = pic.Handle(cfg)
+    assert restart_step_check(O, cfg, h, 20) == []
+    assert len(h.particles(0, 1)["id"]) == 0
+    # particles exactly on nodes, in the last ulp below L, and an empty species
+    cfg = presets.scaled(presets.tiny(), n_load=64, gamma_emit=0.0, ng=0.0)
+    h = pic.Handle(cfg)
+    L, N = cfg["L"], cfg["N"]
+    z = np.array([L / N * k for k in range(1, 9)] + [np.nextafter(L, 0), L * 0.5])
+    n = len(z)
+    p = {"z": z, "vx": np.zeros(n, np.float32), "vy": np.zeros(n, np.float32),
+         "vz": np.zeros(n, np.float32), "id": np.arange(n, dtype=np.uint32),
+         "tc": np.full(n, 0xFFFFFFFF, np.uint32)}
+    h.set_particles(0, 0, p)
+    h.set_particles(0, 2, {k: v[:0] for k, v in p.items()})
+    h.set_counters(0, 0, n)
+    h.refield()
+    st, t = gpu_state(h)
+    assert deposit_matches(O, cfg, h, st) == []
+    assert restart_step_check(O, cfg, h, 5) == []
+    # rejected inputs
+    with pytest.raises(pic.PicError) as e:
+        h.set_particles(0, 0, dict(p, z=np.full(n, 2 * L)))
+    assert e.value.code == pic.PIC_EINVAL
+    with pytest.raises(pic.PicError):
+        pic.Handle(presets.scaled(presets.tiny(), N=1))
+
+
+def test_capacity_overflow_reported(pic):
+    _say("case: capacity overflow")
+    cfg = presets.scaled(presets.tiny(), n_load=1000, capacity_factor=0.001, gamma_emit=2e24)
+    h = pic.Handle(cfg)
+    h.step(50)
+    with pytest.raises(pic.PicError) as e:
+        h.sync()
+    assert e.value.code == pic.PIC_ENOSPACE
+
+
+def test_diagnostics_window(pic, O):
+    cfg = presets.scaled(presets.tiny(), gamma_emit=3e21, tally_period=50)
+    _say("case: diagnostics windows")
+    h = pic.Handle(cfg)
+    h.step(300)
+    t = h.tally()
+    w0 = pic.pic_derive(cfg)["w0"]
+    whole = h.diagnostics(0, 0)
+    ref = O.diag(cfg["gamma_emit"], cfg["Tc"], w0, 300 * cfg["dt"], t["abs_count"], t["abs_energy"],
+                 t["n_emit"])
+    for k in ("gamma_ref", "gamma_net", "gamma_anode", "backflow_pct", "eta_net", "eta_anode",
+              "wf_eff", "q_emit_theory", "q_cool1", "q_cool2", "q_anode1", "q_anode2"):
+        assert whole[k] == pytest.approx(ref[k], rel=1e-12, abs=1e-12), k
+    win = h.diagnostics(0, 100)
+    assert (win["step_begin"], win["step_end"]) == (200, 300)
+    assert np.array_equal(win["n_live"], t["n_live"])
+
+
+def test_time_average_fields(pic):
+    cfg = presets.tiny()
+    _say("case: time-averaged fields")
+    h = pic.Handle(cfg)
+    h.step(5)
+    h.avg_reset(True)
+    acc = None
+    for _ in range(8):
+        h.step(1)
+        f = h.fields(0)
+        acc = {k: v.copy() for k, v in f.items()} if acc is None else {k: acc[k] + f[k] for k in f}
+    avg = h.fields(0, time_avg=True)
+    for k in acc:
+        assert np.allclose(avg[k], acc[k] / 8, rtol=1e-12, atol=1e-9 * np.abs(acc[k]).max())
