@@ -192,6 +192,14 @@ int pic_refield(pic_handle *h);
 int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *mean_live,
                    double *total_ms);
 
+/* Launch schedule of the hot loop: particles per thread in the particle and
+ * sort kernels (1, 2, 4 or 8; 0 keeps), persistent grid size (0: default),
+ * re-sort period in steps (0 keeps) and whether full re-sort periods are
+ * replayed from a captured HIP graph (-1 keeps).  Results do not depend on
+ * these choices.  Synchronises. */
+int pic_set_tuning(pic_handle *h, int ppt, int grid, int sort_period, int use_graph);
+int pic_get_tuning(pic_handle *h, int *ppt, int *grid, int *sort_period, int *use_graph);
+
 /* Message of the last failing call on this thread. */
 const char *pic_last_error(void);
 

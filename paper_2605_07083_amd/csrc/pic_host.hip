@@ -24,9 +24,11 @@ using namespace pic;
 
 extern "C" hipError_t picx_launch_load(const Diode *D, const long long *n_load, int nd, long long max_load,
                                        hipStream_t s);
-extern "C" hipError_t picx_launch_particles(const Diode *D, int nd, int mode, int ppt, int grid, hipStream_t s);
-extern "C" hipError_t picx_launch_sources_field(const Diode *D, int nd, int mode, hipStream_t s);
-extern "C" hipError_t picx_launch_sort(const Diode *D, int nd, int ppt, int grid, hipStream_t s);
+extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int nd, int mode, int ppt, int grid,
+                                            int parity, hipStream_t s);
+extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
+                                                hipStream_t s);
+extern "C" hipError_t picx_launch_sort(const Diode *D, DiodeState *S, int nd, int ppt, int grid, hipStream_t s);
 
 namespace {
 
@@ -115,7 +117,7 @@ void derive(const pic_config &c, pic_derived &d)
     d.emit_per_step = d.w0 > 0.0 ? c.gamma_emit * c.dt / d.w0 : 0.0;
     double f = c.capacity_factor > 0.0 ? c.capacity_factor : 1.6;
     int64_t cap = (int64_t)std::ceil(f * (double)c.n_load) + 4096;
-    cap = (cap + 255) / 256 * 256;
+    cap = (cap + 2047) / 2048 * 2048;   // a multiple of the largest particle chunk
     for (int s = 0; s < NSP; ++s) d.capacity[s] = cap;
 }
 
@@ -235,11 +237,23 @@ struct pic_handle {
     std::vector<Diode> hD;
     Diode *dD = nullptr;
     long long *dNload = nullptr;
+    DiodeState *dS = nullptr;   // state array (diode d at dS + d)
+    int max_nodes = 0;
     int64_t issued = 0;         // steps enqueued so far (re-sort schedule)
+    int parity = 0;             // current particle buffer (flips with every re-sort)
     bool sort_next = true;      // force a re-sort before the next step
-    int ppt = 4;
+    int ppt = 2;
     int grid = 1024;
     int sort_period = 16;
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
+    hipGraphExec_t graph[2] = {nullptr, nullptr};   // re-sort + sort_period steps, per start parity
+    ~pic_handle()
+    {
+        for (auto g : graph)
+            if (g) (void)hipGraphExecDestroy(g);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
     std::vector<std::array<int64_t, NSP>> live_offset;
 };
 
@@ -255,23 +269,88 @@ int grid_for(const pic_handle *h)
     return (int)g;
 }
 
+// parity: buffer current before the re-sort; the re-sort flips it
+int enqueue_sort(pic_handle *h, hipStream_t s)
+{
+    HIP_TRY(picx_launch_sort(h->dD, h->dS, h->nd, h->ppt, h->grid, s));
+    return PIC_OK;
+}
+
+int enqueue_body(pic_handle *h, hipStream_t s, int parity)
+{
+    HIP_TRY(picx_launch_particles(h->dD, h->dS, h->nd, 0, h->ppt, h->grid, parity, s));
+    HIP_TRY(picx_launch_sources_field(h->dD, h->dS, h->nd, 0, h->max_nodes, s));
+    return PIC_OK;
+}
+
+bool sort_due(const pic_handle *h)
+{
+    return h->sort_next || (h->sort_period > 0 && h->issued % h->sort_period == 0);
+}
+
 int launch_step(pic_handle *h)
 {
-    if (h->sort_next || (h->sort_period > 0 && h->issued % h->sort_period == 0)) {
-        HIP_TRY(picx_launch_sort(h->dD, h->nd, h->ppt, h->grid, h->stream));
+    if (sort_due(h)) {
+        int rc = enqueue_sort(h, h->stream);
+        if (rc) return rc;
+        h->parity ^= 1;
         h->sort_next = false;
     }
-    HIP_TRY(picx_launch_particles(h->dD, h->nd, 0, h->ppt, h->grid, h->stream));
-    HIP_TRY(picx_launch_sources_field(h->dD, h->nd, 0, h->stream));
+    int rc = enqueue_body(h, h->stream, h->parity);
+    if (rc) return rc;
     h->issued++;
+    return PIC_OK;
+}
+
+// A captured graph of one re-sort and sort_period steps, replayed whenever the
+// schedule reaches a re-sort boundary with at least that many steps to go.
+int ensure_graph(pic_handle *h, int p)
+{
+    if (h->graph[p]) return PIC_OK;
+    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g;
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_sort(h, h->cap_stream);
+    for (int k = 0; rc == PIC_OK && k < h->sort_period; ++k) rc = enqueue_body(h, h->cap_stream, p ^ 1);
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->graph[p], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->graph[p] = nullptr;
+        return fail(PIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    return PIC_OK;
+}
+
+int run_steps(pic_handle *h, int64_t nsteps)
+{
+    int64_t left = nsteps;
+    while (left > 0) {
+        if (h->use_graph && h->sort_period > 1 && !h->sort_next && h->issued % h->sort_period == 0 &&
+            left >= h->sort_period) {
+            int rc = ensure_graph(h, h->parity);
+            if (rc) return rc;
+            HIP_TRY(hipGraphLaunch(h->graph[h->parity], h->stream));
+            h->parity ^= 1;
+            h->issued += h->sort_period;
+            left -= h->sort_period;
+            continue;
+        }
+        int rc = launch_step(h);
+        if (rc) return rc;
+        --left;
+    }
     return PIC_OK;
 }
 
 int refield(pic_handle *h)
 {
-    HIP_TRY(picx_launch_sort(h->dD, h->nd, h->ppt, h->grid, h->stream));
-    HIP_TRY(picx_launch_particles(h->dD, h->nd, 1, h->ppt, h->grid, h->stream));
-    HIP_TRY(picx_launch_sources_field(h->dD, h->nd, 1, h->stream));
+    HIP_TRY(picx_launch_sort(h->dD, h->dS, h->nd, h->ppt, h->grid, h->stream));
+    h->parity ^= 1;
+    HIP_TRY(picx_launch_particles(h->dD, h->dS, h->nd, 1, h->ppt, h->grid, h->parity, h->stream));
+    HIP_TRY(picx_launch_sources_field(h->dD, h->dS, h->nd, 1, h->max_nodes, h->stream));
     h->sort_next = false;
     return PIC_OK;
 }
@@ -397,7 +476,11 @@ int pic_init(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t b
     Bump bp{h->ws};
     size_t zend;
     layout(cfgs, n_diodes, h->der, bp, h->hD, h->dD, h->dNload, zend);
-    for (int d = 0; d < n_diodes; ++d) fill_params(cfgs[d], h->der[d], h->hD[d]);
+    for (int d = 0; d < n_diodes; ++d) {
+        fill_params(cfgs[d], h->der[d], h->hD[d]);
+        h->max_nodes = std::max(h->max_nodes, cfgs[d].N + 1);
+    }
+    h->dS = h->hD[0].st;
     h->grid = grid_for(h);
 
     auto cleanup = [&](int code) { delete h; return code; };
@@ -431,11 +514,7 @@ int pic_init(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t b
 int pic_step(pic_handle *h, int64_t nsteps)
 {
     if (!h || nsteps < 0) return fail(PIC_EINVAL, "bad arguments");
-    for (int64_t k = 0; k < nsteps; ++k) {
-        int rc = launch_step(h);
-        if (rc) return rc;
-    }
-    return PIC_OK;
+    return run_steps(h, nsteps);
 }
 
 int pic_sync(pic_handle *h)
@@ -694,15 +773,17 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
     HIP_TRY(hipEventRecord(t0, h->stream));
     int64_t k_ev = 0;
     for (int64_t k = 0; k < nsteps; ++k) {
-        if (h->sort_next || (h->sort_period > 0 && h->issued % h->sort_period == 0)) {
-            HIP_TRY(picx_launch_sort(h->dD, h->nd, h->ppt, h->grid, h->stream));
+        if (sort_due(h)) {
+            int rc = enqueue_sort(h, h->stream);
+            if (rc) return rc;
+            h->parity ^= 1;
             h->sort_next = false;
         }
         const bool rec = (k % every) == 0 && k_ev < nev;
         if (rec) HIP_TRY(hipEventRecord(ev[2 * k_ev], h->stream));
-        HIP_TRY(picx_launch_particles(h->dD, h->nd, 0, h->ppt, h->grid, h->stream));
+        HIP_TRY(picx_launch_particles(h->dD, h->dS, h->nd, 0, h->ppt, h->grid, h->parity, h->stream));
         if (rec) { HIP_TRY(hipEventRecord(ev[2 * k_ev + 1], h->stream)); ++k_ev; }
-        HIP_TRY(picx_launch_sources_field(h->dD, h->nd, 0, h->stream));
+        HIP_TRY(picx_launch_sources_field(h->dD, h->dS, h->nd, 0, h->max_nodes, h->stream));
         h->issued++;
     }
     HIP_TRY(hipEventRecord(t1, h->stream));
@@ -737,6 +818,34 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
         *mean_live = 0.5 * (a + b);
     }
     if (total_ms) *total_ms = tot;
+    return PIC_OK;
+}
+
+int pic_set_tuning(pic_handle *h, int ppt, int grid, int sort_period, int use_graph)
+{
+    if (!h) return fail(PIC_EINVAL, "null handle");
+    if (ppt != 0 && ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8) return fail(PIC_EINVAL, "ppt must be 1, 2, 4 or 8");
+    if (grid < 0 || grid > 65536 || sort_period < 0) return fail(PIC_EINVAL, "bad grid or sort period");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (ppt) h->ppt = ppt;
+    h->grid = grid ? (grid + 7) / 8 * 8 : grid_for(h);
+    if (sort_period) h->sort_period = sort_period;
+    if (use_graph >= 0) h->use_graph = use_graph != 0;
+    for (auto &g : h->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    return PIC_OK;
+}
+
+int pic_get_tuning(pic_handle *h, int *ppt, int *grid, int *sort_period, int *use_graph)
+{
+    if (!h) return fail(PIC_EINVAL, "null handle");
+    if (ppt) *ppt = h->ppt;
+    if (grid) *grid = h->grid;
+    if (sort_period) *sort_period = h->sort_period;
+    if (use_graph) *use_graph = h->use_graph ? 1 : 0;
     return PIC_OK;
 }
 

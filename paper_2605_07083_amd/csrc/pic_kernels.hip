@@ -20,7 +20,8 @@ namespace pic {
 constexpr int NT = 256;            // threads per particle block
 constexpr int NW = NT / 64;        // wavefronts per particle block
 constexpr int WMAX = 1024;         // LDS window (nodes) of the field tile / histogram
-constexpr int CQ = 512;            // LDS candidate queue per chunk
+constexpr int CQ = 4096;           // LDS queue of rare work (candidates, absorptions); > 2 chunks
+constexpr int DRIFT = 96;          // cells of drift since the last re-sort kept in the LDS window
 constexpr double TWO32 = 4294967296.0;
 
 // ---------------------------------------------------------------------------
@@ -131,6 +132,53 @@ __device__ __forceinline__ void block_minmax(int &mn, int &mx, int *sh)
     __syncthreads();
 }
 
+
+// ---------------------------------------------------------------------------
+// Wave-level run reductions.  Cell-sorted particles put long runs of equal
+// cells in consecutive lanes; combining each run before touching LDS turns a
+// 64-way same-address atomic into one atomic per run.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+// Segmented inclusive sums of (L, A) over runs of equal key in consecutive
+// lanes; 'last' marks the final lane of each run, which then holds the run sums.
+__device__ __forceinline__ void run_sums(int key, unsigned long long &L, unsigned long long &A, bool &last)
+{
+    const int lane = lane_id();
+    const int prev = __shfl_up(key, 1, 64);
+    const int next = __shfl_down(key, 1, 64);
+    int flag = (lane == 0 || prev != key) ? 1 : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long Lo = __shfl_up(L, o, 64), Ao = __shfl_up(A, o, 64);
+        const int fo = __shfl_up(flag, o, 64);
+        if (lane >= o) {
+            if (!flag) { L += Lo; A += Ao; }
+            flag |= fo;
+        }
+    }
+    last = (lane == 63) || (next != key);
+}
+
+// Start lane and length of the run of equal keys that contains this lane.
+__device__ __forceinline__ void run_extent(int key, int &start, int &len)
+{
+    const int lane = lane_id();
+    const int prev = __shfl_up(key, 1, 64);
+    const int next = __shfl_down(key, 1, 64);
+    int s = (lane == 0 || prev != key) ? lane : 0;
+    int e = (lane == 63 || next != key) ? lane : 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(s, o, 64);
+        const int u = __shfl_down(e, o, 64);
+        if (lane >= o) s = max(s, t);
+        if (lane + o < 64) e = min(e, u);
+    }
+    start = s;
+    len = e - s + 1;
+}
+
 // ---------------------------------------------------------------------------
 // Chunk map shared by the persistent particle and sort kernels.
 // ---------------------------------------------------------------------------
@@ -139,8 +187,8 @@ struct ChunkMap {
     int total;
 };
 
-__device__ void build_chunk_map(const Diode *__restrict__ D, int nd, int chunk, bool use_new,
-                                int *seg_end, ChunkMap &cm)
+__device__ void build_chunk_map(const DiodeState *__restrict__ S, int nd, int chunk, bool use_new,
+                                int *seg_end, ChunkMap &cm, int *seg_n = nullptr)
 {
     int nseg = nd * NSP;
     if (threadIdx.x < 64) {
@@ -149,9 +197,10 @@ __device__ void build_chunk_map(const Diode *__restrict__ D, int nd, int chunk, 
             int sidx = b0 + threadIdx.x;
             int c = 0;
             if (sidx < nseg) {
-                const DiodeState *st = D[sidx / NSP].st;
-                int n = use_new ? st->n_new[sidx % NSP] : st->n[sidx % NSP];
+                const DiodeState &st = S[sidx / NSP];
+                int n = use_new ? st.n_new[sidx % NSP] : st.n[sidx % NSP];
                 c = (n + chunk - 1) / chunk;
+                if (seg_n) seg_n[sidx] = n;
             }
             // inclusive wave scan
 #pragma unroll
@@ -206,7 +255,7 @@ struct ChunkCounts {
     int coll[NCH];
 };
 
-__device__ void mcc_one(const Diode &dd, int s, const SpeciesBuf &b, int i, uint32_t step, double zn,
+__device__ __noinline__ void mcc_one(const Diode &dd, int s, const SpeciesBuf &b, int i, uint32_t step, double zn,
                         float vzn, ChunkCounts *cc)
 {
     const int ion = (s == SP_I);
@@ -301,171 +350,257 @@ __device__ void mcc_one(const Diode &dd, int s, const SpeciesBuf &b, int i, uint
 
 // ---------------------------------------------------------------------------
 // Particle kernel.  mode 0: full step; mode 1: deposit only (load / refield).
+//
+// Each block owns a contiguous range of chunks; each thread owns PPT
+// consecutive slots of a chunk, which after the cell re-sort mostly share a
+// cell.  Runs of chunks of one (diode, species) share one LDS window: the
+// field tile of the gather and the fixed-point histogram of the deposit cover
+// the cells of the run's first and last particle plus a drift margin;
+// particles outside it use global memory.  The deposit sums a thread's
+// consecutive same-cell particles in registers and touches LDS only when the
+// cell changes; a wave whose lanes end in one cell combines them first.
+// Inside a run the chunk loop has no barrier and the next chunk's particle
+// data is loaded while the current one is processed.  Rare work (candidates,
+// absorbed particles) is queued in LDS and done in batches.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Rare work item: slot index with the kind in the top two bits
+// (0 candidate, 1 absorbed at the cathode, 2 absorbed at the anode).  Its
+// position and new v_z are re-read from the buffers, stored by the main loop.
+constexpr uint32_t RARE_SHIFT = 30;
+constexpr uint32_t RARE_MASK = (1u << RARE_SHIFT) - 1u;
+
 template <int PPT>
-__global__ __launch_bounds__(NT) void k_particles(const Diode *__restrict__ D, int nd, int mode)
+struct ChunkRegs {
+    double z[PPT];
+    float vz[PPT];
+    uint32_t tc[PPT];
+};
+
+// Slots [t0, t0 + PPT) of one thread; capacities are multiples of the largest
+// chunk, so the whole range is always inside the buffer.
+template <int PPT>
+__device__ __forceinline__ void load_chunk(ChunkRegs<PPT> &C, const SpeciesBuf &b, int t0, int mode)
+{
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) C.z[k] = b.z[t0 + k];
+    if (mode == 0) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            C.vz[k] = b.vz[t0 + k];
+            C.tc[k] = b.tc[t0 + k];
+        }
+    }
+}
+
+__device__ __forceinline__ void rare_absorbed(const Diode &dd, int s, const SpeciesBuf &b, int i, int wall)
+{
+    const double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
+    const double ke = 0.5 * dd.mass[s] * (vx * vx + vy * vy + vz * vz);
+    atomicAdd(&dd.tally->abs_count[s][wall], 1ull);
+    atomicAdd(&dd.tally->abs_energy[s][wall], ke);
+    if (s == SP_I) atomicAdd(&dd.st->ion_lost, 1);
+}
+
+__device__ __forceinline__ void do_rare(const Diode &dd, int s, const SpeciesBuf &b, uint32_t item, uint32_t step,
+                                        ChunkCounts *cc)
+{
+    const int i = (int)(item & RARE_MASK);
+    const uint32_t kind = item >> RARE_SHIFT;
+    if (kind == 0u) mcc_one(dd, s, b, i, step, b.z[i], b.vz[i], cc);
+    else rare_absorbed(dd, s, b, i, (int)kind - 1);
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Add (L, A) to nodes (j, j+1): the LDS window when inside it, else global.
+__device__ __forceinline__ void flush_run(int j, unsigned long long L, unsigned long long A, int w0, int wn,
+                                          unsigned long long *hist, unsigned long long *H)
+{
+    const int jl = j - w0;
+    if (jl >= 0 && jl + 1 < wn) {
+        if (L) atomicAdd(&hist[jl], L);
+        if (A) atomicAdd(&hist[jl + 1], A);
+    } else {
+        if (L) atomicAdd(&H[j], L);
+        if (A) atomicAdd(&H[j + 1], A);
+    }
+}
+
+template <int PPT>
+__global__ __launch_bounds__(NT) void k_particles(const Diode *__restrict__ D, const DiodeState *__restrict__ S,
+                                                  int nd, int mode, int parity)
 {
     constexpr int CHUNK = NT * PPT;
     __shared__ int seg_end[NSP * MAX_DIODES];
-    __shared__ int red[2 * NW];
+    __shared__ int seg_n[NSP * MAX_DIODES];
     __shared__ double etile[WMAX + 2];
     __shared__ unsigned long long hist[WMAX + 2];
-    __shared__ int q_idx[CQ];
-    __shared__ float q_vz[CQ];
-    __shared__ double q_z[CQ];
+    __shared__ uint32_t rq[CQ];
     __shared__ int q_n;
     __shared__ ChunkCounts cc;
 
     ChunkMap cm;
-    build_chunk_map(D, nd, CHUNK, false, seg_end, cm);
-    int first, end, stride;
-    chunk_range(cm.total, first, end, stride);
+    build_chunk_map(S, nd, CHUNK, false, seg_end, cm, seg_n);
     const int tid = threadIdx.x;
+    const int per_block = (cm.total + gridDim.x - 1) / gridDim.x;
+    const int c_begin = blockIdx.x * per_block;
+    const int c_end = min(cm.total, c_begin + per_block);
 
-    for (int c = first; c < end; c += stride) {
+    for (int c = c_begin; c < c_end;) {
         const int seg = find_seg(seg_end, cm.nseg, c);
+        const int run_end = min(c_end, seg_end[seg]);
+        const int segbase = seg ? seg_end[seg - 1] : 0;
         const int d = seg / NSP, s = seg - d * NSP;
-        const int base = (c - (seg ? seg_end[seg - 1] : 0)) * CHUNK;
         const Diode &dd = D[d];
-        DiodeState *st = dd.st;
-        const int n = st->n[s];
-        const int par = st->parity;
-        const uint32_t step = st->step;
-        const SpeciesBuf b = dd.buf[par][s];
+        const SpeciesBuf b = dd.buf[parity][s];
         const int N = dd.N;
         const double invdz = dd.invdz;
+        const int n = seg_n[seg];
+        const int slot0 = (c - segbase) * CHUNK;
 
+        ChunkRegs<PPT> A;
+        load_chunk<PPT>(A, b, slot0 + tid * PPT, mode);
+        const uint32_t step = S[d].step;
+        // window of the run from its first and last particle
+        const int last_slot = min(n, (run_end - segbase) * CHUNK) - 1;
+        int w0, wn;
+        {
+            int ja, jb;
+            double f;
+            cic(b.z[slot0], invdz, N, ja, f);
+            cic(b.z[max(last_slot, slot0)], invdz, N, jb, f);
+            w0 = max(0, min(ja, jb) - DRIFT);
+            wn = min(min(N, max(ja, jb) + 1 + DRIFT) - w0 + 1, WMAX + 1);
+        }
+        for (int t = tid; t < wn; t += NT) {
+            if (mode == 0) etile[t] = dd.E[w0 + t];
+            hist[t] = 0ull;
+        }
         if (tid == 0) {
             q_n = 0;
             cc.cand = 0;
 #pragma unroll
             for (int k = 0; k < NCH; ++k) cc.coll[k] = 0;
         }
+        lds_barrier();
 
-        double z[PPT];
-        bool alive[PPT];
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            int i = base + k * NT + tid;
-            z[k] = -1.0;
-            if (i < n) z[k] = b.z[i];
-            alive[k] = z[k] >= 0.0;
-        }
-
-        if (mode == 0) {
-            float vz[PPT];
-            uint32_t tc[PPT];
-            int jo[PPT];
-            double fo[PPT];
-            int mn = 0x7fffffff, mx = -1;
+        const double qmdt = dd.qmdt[s], dt = dd.dt, L = dd.L;
+        unsigned long long *H = dd.H[s];
+        for (int cc_ = c; cc_ < run_end; ++cc_) {
+            const int t0 = (cc_ - segbase) * CHUNK + tid * PPT;
+            ChunkRegs<PPT> B;
+            if (cc_ + 1 < run_end) load_chunk<PPT>(B, b, t0 + CHUNK, mode);
+            int jcur = -1;
+            unsigned long long accL = 0ull, accA = 0ull;
+            double zw[PPT];
+            float vw[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                int i = base + k * NT + tid;
-                if (alive[k]) {
-                    vz[k] = b.vz[i];
-                    tc[k] = b.tc[i];
-                    cic(z[k], invdz, N, jo[k], fo[k]);
-                    mn = min(mn, jo[k]);
-                    mx = max(mx, jo[k]);
-                }
-            }
-            block_minmax(mn, mx, red);
-            if (mx < 0) {  // no live particle in this chunk
-                __syncthreads();
-                continue;
-            }
-            // field tile: nodes mn .. mx+1 (at most WMAX+1 of them) staged in LDS
-            const int g0 = mn;
-            const int gcount = min(mx + 2 - mn, WMAX + 1);
-            for (int t = tid; t < gcount; t += NT) etile[t] = dd.E[g0 + t];
-            __syncthreads();
-            const double qmdt = dd.qmdt[s], dt = dd.dt, L = dd.L;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                if (!alive[k]) continue;
-                const int i = base + k * NT + tid;
-                double e0, e1;
-                const int jl = jo[k] - g0;
-                if (jl + 1 < gcount) { e0 = etile[jl]; e1 = etile[jl + 1]; }
-                else { e0 = dd.E[jo[k]]; e1 = dd.E[jo[k] + 1]; }
-                double Ep;
-                {
+                const int i = t0 + k;
+                bool alive = i < n && A.z[k] >= 0.0;
+                double z = A.z[k];
+                zw[k] = A.z[k];
+                vw[k] = A.vz[k];
+                if (alive && mode == 0) {
+                    int jo;
+                    double fo;
+                    cic(z, invdz, N, jo, fo);
+                    double e0, e1;
+                    const int jl = jo - w0;
+                    if (jl >= 0 && jl + 1 < wn) { e0 = etile[jl]; e1 = etile[jl + 1]; }
+                    else { e0 = dd.E[jo]; e1 = dd.E[jo + 1]; }
+                    double Ep;
+                    {
 #pragma clang fp contract(off)
-                    Ep = (1.0 - fo[k]) * e0 + fo[k] * e1;
+                        Ep = (1.0 - fo) * e0 + fo * e1;
+                    }
+                    const float vzn = (float)((double)A.vz[k] + qmdt * Ep);
+                    const double zn = z + (double)vzn * dt;
+                    vw[k] = vzn;
+                    if (zn <= 0.0 || zn >= L) {
+                        // absorbing electrodes: tallied with the rare work
+                        zw[k] = -1.0;
+                        alive = false;
+                        const int q = atomicAdd(&q_n, 1);
+                        rq[q] = (uint32_t)i | ((zn <= 0.0 ? 1u : 2u) << RARE_SHIFT);
+                    } else {
+                        if (!(zn == zn)) atomicOr(&dd.st->err, ERR_NAN);
+                        z = zn;
+                        zw[k] = zn;
+                        if (A.tc[k] == step) {
+                            const int q = atomicAdd(&q_n, 1);
+                            rq[q] = (uint32_t)i;
+                        }
+                    }
                 }
-                const float vzn = (float)((double)vz[k] + qmdt * Ep);
-                const double zn = z[k] + (double)vzn * dt;
-                if (zn <= 0.0 || zn >= L) {
-                    // absorbing electrodes
-                    const int wall = zn <= 0.0 ? 0 : 1;
-                    const double vxa = b.vx[i], vya = b.vy[i], vza = vzn;
-                    const double ke = 0.5 * dd.mass[s] * (vxa * vxa + vya * vya + vza * vza);
-                    atomicAdd(&dd.tally->abs_count[s][wall], 1ull);
-                    atomicAdd(&dd.tally->abs_energy[s][wall], ke);
-                    if (s == SP_I) atomicAdd(&st->ion_lost, 1);
-                    b.z[i] = -1.0;
-                    alive[k] = false;
-                    continue;
-                }
-                if (!(zn == zn)) atomicOr(&st->err, ERR_NAN);
-                z[k] = zn;
-                b.z[i] = zn;
-                if (tc[k] == step) {
-                    int q = atomicAdd(&q_n, 1);
-                    if (q < CQ) { q_idx[q] = i; q_vz[q] = vzn; q_z[q] = zn; }
-                    else mcc_one(dd, s, b, i, step, zn, vzn, &cc);
-                } else {
-                    b.vz[i] = vzn;
+                if (alive) {
+                    int j;
+                    double f;
+                    cic(z, invdz, N, j, f);
+                    const unsigned long long a = fixed_right(f);
+                    if (j != jcur) {
+                        if (jcur >= 0) flush_run(jcur, accL, accA, w0, wn, hist, H);
+                        jcur = j;
+                        accL = (1ull << 32) - a;
+                        accA = a;
+                    } else {
+                        accL += (1ull << 32) - a;
+                        accA += a;
+                    }
                 }
             }
-        }
-
-        // ---- deposit: LDS window histogram of the new positions ----
-        int jn[PPT];
-        unsigned long long an[PPT];
-        int mn = 0x7fffffff, mx = -1;
+            if (mode == 0) {
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            if (!alive[k]) continue;
-            double f;
-            cic(z[k], invdz, N, jn[k], f);
-            an[k] = fixed_right(f);
-            mn = min(mn, jn[k]);
-            mx = max(mx, jn[k]);
-        }
-        block_minmax(mn, mx, red);
-        if (mx >= 0) {
-            const int h0 = mn;
-            const int hcount = min(mx + 2 - mn, WMAX + 1);
-            for (int t = tid; t < hcount; t += NT) hist[t] = 0ull;
-            __syncthreads();
-            unsigned long long *H = dd.H[s];
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                if (!alive[k]) continue;
-                const int jl = jn[k] - h0;
-                const unsigned long long left = (1ull << 32) - an[k];
-                if (jl + 1 < hcount) {
-                    if (left) atomicAdd(&hist[jl], left);
-                    if (an[k]) atomicAdd(&hist[jl + 1], an[k]);
-                } else {
-                    atomicAdd(&H[jn[k]], left);
-                    atomicAdd(&H[jn[k] + 1], an[k]);
+                for (int k = 0; k < PPT; ++k) {
+                    b.z[t0 + k] = zw[k];
+                    b.vz[t0 + k] = vw[k];
                 }
             }
-            __syncthreads();
-            for (int t = tid; t < hcount; t += NT) {
-                unsigned long long v = hist[t];
-                if (v) atomicAdd(&H[h0 + t], v);
+            // last run of every lane: combine across the wave when all lanes agree
+            const int j0w = __shfl(jcur, 0, 64);
+            const bool same = __all(jcur == j0w);
+            if (same) {
+                const unsigned long long sL = wave_sum_u64(accL), sA = wave_sum_u64(accA);
+                if (lane_id() == 0 && j0w >= 0) flush_run(j0w, sL, sA, w0, wn, hist, H);
+            } else if (jcur >= 0) {
+                flush_run(jcur, accL, accA, w0, wn, hist, H);
+            }
+            if (cc_ + 1 < run_end) A = B;
+            // rare work in batches, before the queue could overflow with the next chunk
+            if (mode == 0 && cc_ + 1 < run_end) {
+                lds_barrier();
+                const int qn = q_n;
+                if (qn > CQ - CHUNK) {
+                    __syncthreads();
+                    for (int q = tid; q < qn; q += NT) do_rare(dd, s, b, rq[q], step, &cc);
+                    __syncthreads();
+                    if (tid == 0) q_n = 0;
+                    lds_barrier();
+                }
             }
         }
-
-        // ---- null-collision candidates of this chunk, all lanes busy ----
+        // the main loop's stores precede the rare work's (workgroup-scope fence)
+        __syncthreads();
+        for (int t = tid; t < wn; t += NT) {
+            const unsigned long long v = hist[t];
+            if (v) atomicAdd(&H[w0 + t], v);
+        }
         if (mode == 0) {
-            __syncthreads();
-            const int qn = min(q_n, CQ);
-            for (int q = tid; q < qn; q += NT) mcc_one(dd, s, b, q_idx[q], step, q_z[q], q_vz[q], &cc);
-            __syncthreads();
+            const int qn = q_n;
+            for (int q = tid; q < qn; q += NT) do_rare(dd, s, b, rq[q], step, &cc);
+            lds_barrier();
             if (tid == 0) {
                 const int ion = (s == SP_I);
                 if (cc.cand) atomicAdd(&dd.tally->cand[ion], (unsigned long long)cc.cand);
@@ -474,7 +609,8 @@ __global__ __launch_bounds__(NT) void k_particles(const Diode *__restrict__ D, i
                     if (cc.coll[k]) atomicAdd(&dd.tally->coll[k], (unsigned long long)cc.coll[k]);
             }
         }
-        __syncthreads();
+        lds_barrier();
+        c = run_end;
     }
 }
 
@@ -512,14 +648,15 @@ __global__ __launch_bounds__(256) void k_load(const Diode *__restrict__ D, const
 // Cell re-sort: count -> scan -> scatter -> finalize (compacts holes too).
 // ---------------------------------------------------------------------------
 template <int PPT>
-__global__ __launch_bounds__(NT) void k_sort_count(const Diode *__restrict__ D, int nd)
+__global__ __launch_bounds__(NT) void k_sort_count(const Diode *__restrict__ D, const DiodeState *__restrict__ S,
+                                                   int nd)
 {
     constexpr int CHUNK = NT * PPT;
     __shared__ int seg_end[NSP * MAX_DIODES];
     __shared__ int red[2 * NW];
     __shared__ int cnt[WMAX + 2];
     ChunkMap cm;
-    build_chunk_map(D, nd, CHUNK, false, seg_end, cm);
+    build_chunk_map(S, nd, CHUNK, false, seg_end, cm);
     int first, end, stride;
     chunk_range(cm.total, first, end, stride);
     const int tid = threadIdx.x;
@@ -528,8 +665,8 @@ __global__ __launch_bounds__(NT) void k_sort_count(const Diode *__restrict__ D, 
         const int d = seg / NSP, s = seg - d * NSP;
         const int base = (c - (seg ? seg_end[seg - 1] : 0)) * CHUNK;
         const Diode &dd = D[d];
-        const int n = dd.st->n[s];
-        const SpeciesBuf b = dd.buf[dd.st->parity][s];
+        const int n = S[d].n[s];
+        const SpeciesBuf b = dd.buf[S[d].parity][s];
         int j[PPT];
         bool alive[PPT];
         int mn = 0x7fffffff, mx = -1;
@@ -553,10 +690,15 @@ __global__ __launch_bounds__(NT) void k_sort_count(const Diode *__restrict__ D, 
             int *cc = dd.cell_cnt[s];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                if (!alive[k]) continue;
-                int jl = j[k] - mn;
-                if (jl < w) atomicAdd(&cnt[jl], 1);
-                else atomicAdd(&cc[j[k]], 1);
+                int key = -1 - tid;
+                if (alive[k]) {
+                    const int jl = j[k] - mn;
+                    if (jl < w) key = jl;
+                    else atomicAdd(&cc[j[k]], 1);
+                }
+                int start, len;
+                run_extent(key, start, len);
+                if (key >= 0 && lane_id() == start) atomicAdd(&cnt[key], len);
             }
             __syncthreads();
             for (int t = tid; t < w; t += NT)
@@ -596,14 +738,15 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const Diode *__restrict__ D)
 }
 
 template <int PPT>
-__global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D, int nd)
+__global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D, const DiodeState *__restrict__ S,
+                                                     int nd)
 {
     constexpr int CHUNK = NT * PPT;
     __shared__ int seg_end[NSP * MAX_DIODES];
     __shared__ int red[2 * NW];
     __shared__ int cnt[WMAX + 2];
     ChunkMap cm;
-    build_chunk_map(D, nd, CHUNK, false, seg_end, cm);
+    build_chunk_map(S, nd, CHUNK, false, seg_end, cm);
     int first, end, stride;
     chunk_range(cm.total, first, end, stride);
     const int tid = threadIdx.x;
@@ -612,8 +755,8 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
         const int d = seg / NSP, s = seg - d * NSP;
         const int base = (c - (seg ? seg_end[seg - 1] : 0)) * CHUNK;
         const Diode &dd = D[d];
-        const int n = dd.st->n[s];
-        const int par = dd.st->parity;
+        const int n = S[d].n[s];
+        const int par = S[d].parity;
         const SpeciesBuf src = dd.buf[par][s], dst = dd.buf[par ^ 1][s];
         int j[PPT], rank[PPT];
         double z[PPT];
@@ -639,10 +782,18 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
             int *cur = dd.cell_cnt[s];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                if (!alive[k]) continue;
-                int jl = j[k] - mn;
-                if (jl < w) rank[k] = atomicAdd(&cnt[jl], 1);
-                else rank[k] = -1 - atomicAdd(&cur[j[k]], 1);   // outlier: global slot
+                int key = -1 - tid;
+                if (alive[k]) {
+                    const int jl = j[k] - mn;
+                    if (jl < w) key = jl;
+                    else rank[k] = -1 - atomicAdd(&cur[j[k]], 1);   // outlier: global slot
+                }
+                int start, len;
+                run_extent(key, start, len);
+                int b0 = 0;
+                if (key >= 0 && lane_id() == start) b0 = atomicAdd(&cnt[key], len);
+                b0 = __shfl(b0, start, 64);
+                if (key >= 0) rank[k] = b0 + lane_id() - start;
             }
             __syncthreads();
             for (int t = tid; t < w; t += NT) {
@@ -736,33 +887,61 @@ __device__ __forceinline__ double to_double(I128 a)
 constexpr int FT = 1024;
 constexpr int FW = FT / 64;
 
-template <typename T, typename Op>
-__device__ __forceinline__ T block_excl_scan(T v, T *sh, Op op, T zero, T &total)
+// Block-wide exclusive scan of one value per thread (1024 threads): wave
+// scans with cross-lane shuffles, one LDS exchange of the 16 wave totals.
+__device__ __forceinline__ long long block_excl_scan_i64(long long v, long long *sh, long long &total)
 {
-    // Hillis-Steele over the 1024 thread values in LDS
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < FT; o <<= 1) {
-        T t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : zero;
-        __syncthreads();
-        if (threadIdx.x >= (unsigned)o) sh[threadIdx.x] = op(sh[threadIdx.x], t);
-        __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    long long x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        long long y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
-    T incl = sh[threadIdx.x];
-    total = sh[FT - 1];
+    if (lane == 63) sh[w] = x;
     __syncthreads();
-    T excl = threadIdx.x ? sh[threadIdx.x - 1] : zero;
+    long long off = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < FW; ++q) {
+        const long long t = sh[q];
+        if (q < w) off += t;
+        tot += t;
+    }
     __syncthreads();
-    (void)incl;
-    return excl;
+    total = tot;
+    return off + x - v;
 }
 
-struct AddI64 {
-    __device__ long long operator()(long long a, long long b) const { return a + b; }
-};
-struct AddI128 {
-    __device__ I128 operator()(I128 a, I128 b) const { return add(a, b); }
-};
+__device__ __forceinline__ I128 shfl_up_i128(I128 a, int o)
+{
+    I128 r;
+    r.lo = __shfl_up(a.lo, o, 64);
+    r.hi = __shfl_up(a.hi, o, 64);
+    return r;
+}
+
+__device__ __forceinline__ I128 block_excl_scan_i128(I128 v, I128 *sh, I128 &total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    I128 x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        I128 y = shfl_up_i128(x, o);
+        if (lane >= o) x = add(x, y);
+    }
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    I128 off = i128(0), tot = i128(0);
+#pragma unroll
+    for (int q = 0; q < FW; ++q) {
+        const I128 t = sh[q];
+        if (q < w) off = add(off, t);
+        tot = add(tot, t);
+    }
+    __syncthreads();
+    total = tot;
+    return add(off, add(x, neg(v)));
+}
 
 __device__ __forceinline__ void deposit_global(const Diode &dd, int s, double z)
 {
@@ -780,227 +959,231 @@ __device__ void write_particle(const SpeciesBuf &b, int i, double z, float vx, f
     b.z[i] = z; b.vx[i] = vx; b.vy[i] = vy; b.vz[i] = vz; b.id[i] = id; b.tc[i] = tc;
 }
 
-__global__ __launch_bounds__(FT) void k_sources_field(const Diode *__restrict__ D, int mode)
+// Births of one step: ionisation products in increasing parent id, thermionic
+// emission (flux-weighted half-Maxwellian at Tc placed at z = v_z dt), pair
+// replenishment (one e-ion pair per ion lost, shared uniform position,
+// Maxwellian at the initial temperatures).  Newborns deposit directly.
+__device__ void sources(const Diode &dd, DiodeState *st, unsigned long long *keys)
 {
-    const Diode &dd = D[blockIdx.x];
-    DiodeState *st = dd.st;
     const int tid = threadIdx.x;
-    __shared__ unsigned long long keys[IZQ_CAP];
-    __shared__ long long sh64[FT];
-    __shared__ I128 sh128[FT];
-    __shared__ double phl[FT], phr[FT];
     __shared__ int s_ne, s_q, s_R, s_bP, s_bE, s_bI, s_okP, s_okE, s_okI;
     __shared__ uint32_t s_id0, s_step;
-
-    if (mode == 0) {
-        if (tid == 0) {
-            const uint32_t step = st->step;
-            const int q = min(st->iz_count, IZQ_CAP);
-            const int R = dd.replenish ? st->ion_lost : 0;
-            int ne = 0;
-            if (dd.emit_x > 0.0) {
-                const double fl = floor(dd.emit_x);
-                uint4 be = philox(step, EV_EMIT, 0u, 0u, 0xFFFFFFFFu, dd.kseed);
-                ne = (int)fl + (u53(be.x, be.y) < dd.emit_x - fl ? 1 : 0);
-            }
-            s_q = q; s_R = R; s_ne = ne; s_step = step; s_id0 = st->next_id;
-            s_bP = st->n[SP_P]; s_bE = st->n[SP_E]; s_bI = st->n[SP_I];
-            // capacity: births that do not fit are dropped and flagged
-            s_okP = min(q + R, dd.cap[SP_P] - s_bP);
-            s_okE = min(ne, dd.cap[SP_E] - s_bE);
-            s_okI = min(q + R, dd.cap[SP_I] - s_bI);
-            if (s_okP < q + R || s_okE < ne || s_okI < q + R) atomicOr(&st->err, ERR_CAPACITY);
+    if (tid == 0) {
+        const uint32_t step = st->step;
+        const int q = min(st->iz_count, IZQ_CAP);
+        const int R = dd.replenish ? st->ion_lost : 0;
+        int ne = 0;
+        if (dd.emit_x > 0.0) {
+            const double fl = floor(dd.emit_x);
+            uint4 be = philox(step, EV_EMIT, 0u, 0u, 0xFFFFFFFFu, dd.kseed);
+            ne = (int)fl + (u53(be.x, be.y) < dd.emit_x - fl ? 1 : 0);
         }
-        __syncthreads();
-        const int q = s_q, R = s_R, ne = s_ne;
-        const uint32_t step = s_step, id0 = s_id0;
-        const int par = st->parity;
-        const SpeciesBuf bP = dd.buf[par][SP_P], bE = dd.buf[par][SP_E], bI = dd.buf[par][SP_I];
-
-        // ionisation products ordered by parent id (bitonic sort in LDS)
-        if (q > 0) {
-            int np2 = 1;
-            while (np2 < q) np2 <<= 1;
-            for (int t = tid; t < np2; t += FT)
-                keys[t] = t < q ? ((unsigned long long)dd.izq[t].parent << 32) | (unsigned)t : ~0ull;
-            __syncthreads();
-            for (int k = 2; k <= np2; k <<= 1) {
-                for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                    for (int t = tid; t < np2; t += FT) {
-                        int p = t ^ jj;
-                        if (p > t) {
-                            unsigned long long a = keys[t], bb = keys[p];
-                            bool up = (t & k) == 0;
-                            if ((a > bb) == up) { keys[t] = bb; keys[p] = a; }
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            const double lam_e = dd.lam[0], lam_i = dd.lam[1];
-            for (int r = tid; r < q; r += FT) {
-                const IzEvent ev = dd.izq[(int)(keys[r] & 0xFFFFFFFFull)];
-                const uint32_t ide = id0 + 2u * r, idi = ide + 1u;
-                uint4 be = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
-                uint4 bi = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
-                if (r < s_okP) {
-                    write_particle(bP, s_bP + r, ev.z, ev.ve[0], ev.ve[1], ev.ve[2], ide,
-                                   next_candidate(step, lam_e, be.z, be.w));
-                    deposit_global(dd, SP_P, ev.z);
-                }
-                if (r < s_okI) {
-                    write_particle(bI, s_bI + r, ev.z, ev.vi[0], ev.vi[1], ev.vi[2], idi,
-                                   next_candidate(step, lam_i, bi.z, bi.w));
-                    deposit_global(dd, SP_I, ev.z);
-                }
-            }
-        }
-        // thermionic emission: flux-weighted half-Maxwellian at Tc, z = v_z dt
-        for (int i = tid; i < ne; i += FT) {
-            const uint32_t idn = id0 + 2u * q + i;
-            uint4 b0 = philox(step, EV_BIRTH, 0u, 0u, idn, dd.kseed);
-            uint4 b1 = philox(step, EV_BIRTH, 1u, 0u, idn, dd.kseed);
-            double n1, n2;
-            bm32(b0.x, b0.y, n1, n2);
-            const float vz = (float)(dd.sig_c * sqrt(-2.0 * log(u53(b0.z, b0.w))));
-            const float vx = (float)(dd.sig_c * n1), vy = (float)(dd.sig_c * n2);
-            const double z = (double)vz * dd.dt;
-            const uint32_t tc = next_candidate(step, dd.lam[0], b1.z, b1.w);
-            if (i < s_okE) {
-                if (z >= dd.L) {
-                    const double ke = 0.5 * dd.mass[SP_E] *
-                                      ((double)vx * vx + (double)vy * vy + (double)vz * vz);
-                    atomicAdd(&dd.tally->abs_count[SP_E][1], 1ull);
-                    atomicAdd(&dd.tally->abs_energy[SP_E][1], ke);
-                    write_particle(bE, s_bE + i, -1.0, vx, vy, vz, idn, tc);
-                } else {
-                    write_particle(bE, s_bE + i, z, vx, vy, vz, idn, tc);
-                    deposit_global(dd, SP_E, z);
-                }
-            }
-        }
-        // pair replenishment: one e-ion pair per ion lost this step, shared
-        // uniform position, Maxwellian at the initial temperatures
-        for (int r = tid; r < R; r += FT) {
-            const uint32_t ide = id0 + 2u * q + ne + 2u * r, idi = ide + 1u;
-            uint4 e0 = philox(step, EV_BIRTH, 0u, 0u, ide, dd.kseed);
-            uint4 e1 = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
-            uint4 i0 = philox(step, EV_BIRTH, 0u, 0u, idi, dd.kseed);
-            uint4 i1 = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
-            const double z = dd.L * u53(e1.x, e1.y);
-            double a1, a2, a3, a4;
-            bm32(e0.x, e0.y, a1, a2);
-            bm32(e0.z, e0.w, a3, a4);
-            if (q + r < s_okP) {
-                write_particle(bP, s_bP + q + r, z, (float)(dd.sig_e0 * a1), (float)(dd.sig_e0 * a2),
-                               (float)(dd.sig_e0 * a3), ide, next_candidate(step, dd.lam[0], e1.z, e1.w));
-                deposit_global(dd, SP_P, z);
-            }
-            bm32(i0.x, i0.y, a1, a2);
-            bm32(i0.z, i0.w, a3, a4);
-            if (q + r < s_okI) {
-                write_particle(bI, s_bI + q + r, z, (float)(dd.sig_i0 * a1), (float)(dd.sig_i0 * a2),
-                               (float)(dd.sig_i0 * a3), idi, next_candidate(step, dd.lam[1], i1.z, i1.w));
-                deposit_global(dd, SP_I, z);
-            }
-        }
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) {
-            st->n[SP_P] = s_bP + s_okP;
-            st->n[SP_E] = s_bE + s_okE;
-            st->n[SP_I] = s_bI + s_okI;
-            st->next_id = id0 + 2u * q + ne + 2u * R;
-            dd.tally->n_emit += ne;
-            dd.tally->n_repl += R;
-            dd.tally->n_iz += q;
-            st->iz_count = 0;
-            st->ion_lost = 0;
-        }
+        s_q = q; s_R = R; s_ne = ne; s_step = step; s_id0 = st->next_id;
+        s_bP = st->n[SP_P]; s_bE = st->n[SP_E]; s_bI = st->n[SP_I];
+        // births that do not fit are dropped and flagged
+        s_okP = min(q + R, dd.cap[SP_P] - s_bP);
+        s_okE = min(ne, dd.cap[SP_E] - s_bE);
+        s_okI = min(q + R, dd.cap[SP_I] - s_bI);
+        if (s_okP < q + R || s_okE < ne || s_okI < q + R) atomicOr(&st->err, ERR_CAPACITY);
     }
     __syncthreads();
+    const int q = s_q, R = s_R, ne = s_ne;
+    const uint32_t step = s_step, id0 = s_id0;
+    const int par = st->parity;
+    const SpeciesBuf bP = dd.buf[par][SP_P], bE = dd.buf[par][SP_E], bI = dd.buf[par][SP_I];
 
-    // ---- Poisson: phi_{j-1} - 2 phi_j + phi_{j+1} = -alpha R_j, phi_0 = 0, phi_N = V.
-    // With S1_j = sum_{k=1..j} R_k and T_j = sum_{m=1..j-1} S1_m (exact integers),
-    // phi_j = V j / N + alpha (j T_N - N T_j) / N.
+    if (q > 0) {
+        int np2 = 1;
+        while (np2 < q) np2 <<= 1;
+        for (int t = tid; t < np2; t += FT)
+            keys[t] = t < q ? ((unsigned long long)dd.izq[t].parent << 32) | (unsigned)t : ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= np2; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int t = tid; t < np2; t += FT) {
+                    const int p = t ^ jj;
+                    if (p > t) {
+                        const unsigned long long a = keys[t], bb = keys[p];
+                        const bool up = (t & k) == 0;
+                        if ((a > bb) == up) { keys[t] = bb; keys[p] = a; }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int r = tid; r < q; r += FT) {
+            const IzEvent ev = dd.izq[(int)(keys[r] & 0xFFFFFFFFull)];
+            const uint32_t ide = id0 + 2u * r, idi = ide + 1u;
+            const uint4 be = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
+            const uint4 bi = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
+            if (r < s_okP) {
+                write_particle(bP, s_bP + r, ev.z, ev.ve[0], ev.ve[1], ev.ve[2], ide,
+                               next_candidate(step, dd.lam[0], be.z, be.w));
+                deposit_global(dd, SP_P, ev.z);
+            }
+            if (r < s_okI) {
+                write_particle(bI, s_bI + r, ev.z, ev.vi[0], ev.vi[1], ev.vi[2], idi,
+                               next_candidate(step, dd.lam[1], bi.z, bi.w));
+                deposit_global(dd, SP_I, ev.z);
+            }
+        }
+    }
+    for (int i = tid; i < ne; i += FT) {
+        const uint32_t idn = id0 + 2u * q + i;
+        const uint4 b0 = philox(step, EV_BIRTH, 0u, 0u, idn, dd.kseed);
+        const uint4 b1 = philox(step, EV_BIRTH, 1u, 0u, idn, dd.kseed);
+        double n1, n2;
+        bm32(b0.x, b0.y, n1, n2);
+        const float vz = (float)(dd.sig_c * sqrt(-2.0 * log(u53(b0.z, b0.w))));
+        const float vx = (float)(dd.sig_c * n1), vy = (float)(dd.sig_c * n2);
+        const double z = (double)vz * dd.dt;
+        const uint32_t tc = next_candidate(step, dd.lam[0], b1.z, b1.w);
+        if (i < s_okE) {
+            if (z >= dd.L) {
+                const double ke = 0.5 * dd.mass[SP_E] * ((double)vx * vx + (double)vy * vy + (double)vz * vz);
+                atomicAdd(&dd.tally->abs_count[SP_E][1], 1ull);
+                atomicAdd(&dd.tally->abs_energy[SP_E][1], ke);
+                write_particle(bE, s_bE + i, -1.0, vx, vy, vz, idn, tc);
+            } else {
+                write_particle(bE, s_bE + i, z, vx, vy, vz, idn, tc);
+                deposit_global(dd, SP_E, z);
+            }
+        }
+    }
+    for (int r = tid; r < R; r += FT) {
+        const uint32_t ide = id0 + 2u * q + ne + 2u * r, idi = ide + 1u;
+        const uint4 e0 = philox(step, EV_BIRTH, 0u, 0u, ide, dd.kseed);
+        const uint4 e1 = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
+        const uint4 i0 = philox(step, EV_BIRTH, 0u, 0u, idi, dd.kseed);
+        const uint4 i1 = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
+        const double z = dd.L * u53(e1.x, e1.y);
+        double a1, a2, a3, a4;
+        bm32(e0.x, e0.y, a1, a2);
+        bm32(e0.z, e0.w, a3, a4);
+        if (q + r < s_okP) {
+            write_particle(bP, s_bP + q + r, z, (float)(dd.sig_e0 * a1), (float)(dd.sig_e0 * a2),
+                           (float)(dd.sig_e0 * a3), ide, next_candidate(step, dd.lam[0], e1.z, e1.w));
+            deposit_global(dd, SP_P, z);
+        }
+        bm32(i0.x, i0.y, a1, a2);
+        bm32(i0.z, i0.w, a3, a4);
+        if (q + r < s_okI) {
+            write_particle(bI, s_bI + q + r, z, (float)(dd.sig_i0 * a1), (float)(dd.sig_i0 * a2),
+                           (float)(dd.sig_i0 * a3), idi, next_candidate(step, dd.lam[1], i1.z, i1.w));
+            deposit_global(dd, SP_I, z);
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        st->n[SP_P] = s_bP + s_okP;
+        st->n[SP_E] = s_bE + s_okE;
+        st->n[SP_I] = s_bI + s_okI;
+        st->next_id = id0 + 2u * q + ne + 2u * R;
+        dd.tally->n_emit += ne;
+        dd.tally->n_repl += R;
+        dd.tally->n_iz += q;
+        st->iz_count = 0;
+        st->ion_lost = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sources and field: one workgroup of 1024 threads per diode; each thread owns
+// PER consecutive nodes held in registers.
+// mode 0: births, solve, field, tallies, step + 1; mode 1: solve and field only.
+//
+// Poisson: phi_{j-1} - 2 phi_j + phi_{j+1} = -alpha R_j (j = 1..N-1),
+// phi_0 = 0, phi_N = V, R = H_I - H_P - H_E.  With S1_j = sum_{k=1..j} R_k and
+// T_j = sum_{m=1..j-1} S1_m, both exact integers (64 and 128 bit),
+// phi_j = V j / N + alpha (j T_N - N T_j) / N: the direct solution of the
+// constant-coefficient Dirichlet system, rounded once at the end.
+// ---------------------------------------------------------------------------
+template <int PER>
+__global__ __launch_bounds__(FT) void k_sources_field(const Diode *__restrict__ D, DiodeState *__restrict__ S,
+                                                      int mode)
+{
+    const Diode &dd = D[blockIdx.x];
+    DiodeState *st = S + blockIdx.x;
+    const int tid = threadIdx.x;
+    __shared__ unsigned long long keys[IZQ_CAP];
+    __shared__ long long sh64[FW];
+    __shared__ I128 sh128[FW];
+    __shared__ double phl[FT], phr[FT];
+
+    if (mode == 0) sources(dd, st, keys);
+    __syncthreads();
+
     const int N = dd.N;
     const int nn = N + 1;
-    const int per = (nn + FT - 1) / FT;
-    const int j0 = tid * per;
-    const int j1 = min(nn, j0 + per);      // nodes [j0, j1)
-    constexpr int MAXPER = 32;              // N <= 32767
-    long long Rl[MAXPER];
-    long long s1loc = 0;
-    for (int q = 0; q < per; ++q) {
-        const int j = j0 + q;
-        long long v = 0;
-        if (j < j1 && j >= 1 && j <= N - 1)
-            v = (long long)(dd.H[SP_I][j] - dd.H[SP_P][j] - dd.H[SP_E][j]);
-        Rl[q] = v;
-        s1loc += v;
+    const int j0 = tid * PER;
+    long long S1[PER];
+    long long acc = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int j = j0 + k;
+        long long r = 0;
+        if (j >= 1 && j <= N - 1)
+            r = (long long)(dd.H[SP_I][j] - dd.H[SP_P][j] - dd.H[SP_E][j]);
+        acc += r;
+        S1[k] = acc;                       // local inclusive sums of R
     }
     long long tot64;
-    long long s1off = block_excl_scan<long long>(s1loc, sh64, AddI64(), 0ll, tot64);
-    // S1 at each own node (inclusive), and the local sums of S1 over m < j
+    const long long s1off = block_excl_scan_i64(acc, sh64, tot64);
     I128 tloc = i128(0);
-    {
-        long long run = s1off;
-        for (int q = 0; q < per; ++q) {
-            const int j = j0 + q;
-            if (j >= j1) break;
-            run += Rl[q];
-            Rl[q] = run;                                  // now S1_j
-            if (j >= 1 && j <= N - 1) tloc = add(tloc, i128(run));
-        }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        S1[k] += s1off;                    // S1_j
+        const int j = j0 + k;
+        if (j >= 1 && j <= N - 1) tloc = add(tloc, i128(S1[k]));
     }
     I128 T_N;
-    I128 toff = block_excl_scan<I128>(tloc, sh128, AddI128(), i128(0), T_N);
+    I128 T = block_excl_scan_i128(tloc, sh128, T_N);   // T_{j0}
     const double alpha_n = dd.alpha / (double)N;
-    double phi_loc[MAXPER];
-    {
-        I128 T = toff;                                     // T_{j0} = sum_{m < j0} S1_m
-        for (int q = 0; q < per; ++q) {
-            const int j = j0 + q;
-            if (j >= j1) break;
-            double phi;
-            if (j == 0) phi = 0.0;
-            else if (j == N) phi = dd.V;
-            else {
-                I128 x = add(mul_small(T_N, (unsigned)j), neg(mul_small(T, (unsigned)N)));
-                phi = dd.V * (double)j / (double)N + alpha_n * to_double(x);
-            }
-            phi_loc[q] = phi;
-            if (j >= 1 && j <= N - 1) T = add(T, i128(Rl[q]));
+    double ph[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int j = j0 + k;
+        double v = 0.0;
+        if (j == N) v = dd.V;
+        else if (j >= 1 && j < N) {
+            const I128 x = add(mul_small(T_N, (unsigned)j), neg(mul_small(T, (unsigned)N)));
+            v = dd.V * (double)j / (double)N + alpha_n * to_double(x);
         }
+        ph[k] = v;
+        if (j >= 1 && j <= N - 1) T = add(T, i128(S1[k]));
     }
-    // neighbours across thread boundaries
-    phl[tid] = j0 < j1 ? phi_loc[0] : 0.0;
-    phr[tid] = j0 < j1 ? phi_loc[j1 - j0 - 1] : 0.0;
+    phl[tid] = ph[0];
+    phr[tid] = ph[PER - 1];
     __syncthreads();
     const double inv2dz = 1.0 / (2.0 * dd.dz);
-    for (int q = 0; q < per; ++q) {
-        const int j = j0 + q;
-        if (j >= j1) break;
-        const double ph = phi_loc[q];
-        double pm = q > 0 ? phi_loc[q - 1] : (tid > 0 ? phr[tid - 1] : 0.0);
-        double pp = j + 1 < j1 ? phi_loc[q + 1] : (tid + 1 < FT ? phl[tid + 1] : 0.0);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int j = j0 + k;
+        if (j >= nn) break;
+        const double pm = k > 0 ? ph[k - 1] : (tid > 0 ? phr[tid - 1] : 0.0);
+        const double pp = k + 1 < PER ? ph[k + 1] : (tid + 1 < FT ? phl[tid + 1] : 0.0);
         double E;
-        if (j == 0) E = (ph - pp) / dd.dz;
-        else if (j == N) E = (pm - ph) / dd.dz;
+        if (j == 0) E = (ph[k] - pp) / dd.dz;
+        else if (j == N) E = (pm - ph[k]) / dd.dz;
         else E = (pm - pp) * inv2dz;
-        dd.phi[j] = ph;
+        dd.phi[j] = ph[k];
         dd.E[j] = E;
     }
     // keep the last deposit, clear the accumulators, time averages
     const int avg = st->avg_on;
     for (int j = tid; j < nn; j += FT) {
+#pragma unroll
         for (int s = 0; s < NSP; ++s) {
             const long long h = (long long)dd.H[s][j];
             dd.Hlast[s][j] = h;
             dd.H[s][j] = 0ull;
             if (avg) dd.Hsum[s][j] += h;
         }
-        if (avg) dd.phi_sum[j] += dd.phi[j];
+    }
+    if (avg) {
+        __syncthreads();
+        for (int j = tid; j < nn; j += FT) dd.phi_sum[j] += dd.phi[j];
     }
     __syncthreads();
     if (mode == 0 && tid == 0) {
@@ -1039,23 +1222,32 @@ extern "C" hipError_t picx_launch_load(const Diode *D, const long long *n_load, 
     default: { constexpr int P_ = 8; __VA_ARGS__; } break;          \
     }
 
-extern "C" hipError_t picx_launch_particles(const Diode *D, int nd, int mode, int ppt, int grid, hipStream_t s)
+extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int nd, int mode, int ppt, int grid,
+                                            int parity, hipStream_t s)
 {
-    PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_particles<P_>, dim3(grid), dim3(NT), 0, s, D, nd, mode));
+    PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_particles<P_>, dim3(grid), dim3(NT), 0, s, D, S, nd, mode, parity));
     return hipGetLastError();
 }
 
-extern "C" hipError_t picx_launch_sources_field(const Diode *D, int nd, int mode, hipStream_t s)
+// max_nodes: the largest N + 1 over the diodes (<= 32768)
+extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
+                                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sources_field, dim3(nd), dim3(FT), 0, s, D, mode);
+    const int per = (max_nodes + FT - 1) / FT;
+    if (per <= 1) hipLaunchKernelGGL(k_sources_field<1>, dim3(nd), dim3(FT), 0, s, D, S, mode);
+    else if (per <= 2) hipLaunchKernelGGL(k_sources_field<2>, dim3(nd), dim3(FT), 0, s, D, S, mode);
+    else if (per <= 4) hipLaunchKernelGGL(k_sources_field<4>, dim3(nd), dim3(FT), 0, s, D, S, mode);
+    else if (per <= 8) hipLaunchKernelGGL(k_sources_field<8>, dim3(nd), dim3(FT), 0, s, D, S, mode);
+    else if (per <= 16) hipLaunchKernelGGL(k_sources_field<16>, dim3(nd), dim3(FT), 0, s, D, S, mode);
+    else hipLaunchKernelGGL(k_sources_field<32>, dim3(nd), dim3(FT), 0, s, D, S, mode);
     return hipGetLastError();
 }
 
-extern "C" hipError_t picx_launch_sort(const Diode *D, int nd, int ppt, int grid, hipStream_t s)
+extern "C" hipError_t picx_launch_sort(const Diode *D, DiodeState *S, int nd, int ppt, int grid, hipStream_t s)
 {
-    PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_sort_count<P_>, dim3(grid), dim3(NT), 0, s, D, nd));
+    PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_sort_count<P_>, dim3(grid), dim3(NT), 0, s, D, S, nd));
     hipLaunchKernelGGL(k_sort_scan, dim3(nd * NSP), dim3(1024), 0, s, D);
-    PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_sort_scatter<P_>, dim3(grid), dim3(NT), 0, s, D, nd));
+    PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_sort_scatter<P_>, dim3(grid), dim3(NT), 0, s, D, S, nd));
     hipLaunchKernelGGL(k_sort_finalize, dim3(nd), dim3(256), 0, s, D);
     return hipGetLastError();
 }

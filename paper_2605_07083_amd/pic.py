@@ -59,7 +59,7 @@ class PicDerived(C.Structure):
 SYMBOLS = ["pic_derive", "pic_workspace_size", "pic_init", "pic_step", "pic_sync", "pic_get_tally",
            "pic_diagnostics", "pic_get_fields", "pic_avg_reset", "pic_get_hist", "pic_get_efield",
            "pic_get_particles", "pic_set_particles", "pic_set_counters", "pic_refield",
-           "pic_step_timed", "pic_last_error", "pic_destroy"]
+           "pic_step_timed", "pic_set_tuning", "pic_get_tuning", "pic_last_error", "pic_destroy"]
 
 _lib = None
 
@@ -90,6 +90,8 @@ def lib():
         "pic_set_counters": ([P, i, i64, C.c_uint32], i),
         "pic_refield": ([P], i),
         "pic_step_timed": ([P, i64, C.POINTER(d), C.POINTER(d), C.POINTER(d)], i),
+        "pic_set_tuning": ([P, i, i, i, i], i),
+        "pic_get_tuning": ([P, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i)], i),
         "pic_last_error": ([], C.c_char_p),
         "pic_destroy": ([P], None),
     }
@@ -261,6 +263,14 @@ class Handle:
         arrs = [z] + [np.ascontiguousarray(p[k], np.float32) for k in ("vx", "vy", "vz")]
         arrs += [np.ascontiguousarray(p[k], np.uint32) for k in ("id", "tc")]
         _check(lib().pic_set_particles(self.h, d, sp, len(z), *[_ptr(a) for a in arrs]))
+
+    def set_tuning(self, ppt=0, grid=0, sort_period=0, use_graph=-1):
+        _check(lib().pic_set_tuning(self.h, int(ppt), int(grid), int(sort_period), int(use_graph)))
+
+    def tuning(self):
+        v = [C.c_int() for _ in range(4)]
+        _check(lib().pic_get_tuning(self.h, *[C.byref(x) for x in v]))
+        return dict(zip(("ppt", "grid", "sort_period", "use_graph"), [x.value for x in v]))
 
     def set_counters(self, d, step, next_id):
         _check(lib().pic_set_counters(self.h, d, int(step), int(next_id)))

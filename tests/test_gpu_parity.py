@@ -162,7 +162,7 @@ def test_edge_cases(pic, O):
 
 def test_capacity_overflow_reported(pic):
     _say("case: capacity overflow")
-    cfg = presets.scaled(presets.tiny(), n_load=1000, capacity_factor=0.001, gamma_emit=2e24)
+    cfg = presets.scaled(presets.tiny(), n_load=1000, capacity_factor=0.001, gamma_emit=2e25)
     h = pic.Handle(cfg)
     h.step(50)
     with pytest.raises(pic.PicError) as e:
