@@ -27,8 +27,10 @@ extern "C" hipError_t picx_launch_load(const Diode *D, const long long *n_load, 
 extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int nd, int mode, int ppt, int grid,
                                             int parity, hipStream_t s);
 extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
-                                                hipStream_t s);
-extern "C" hipError_t picx_launch_sort(const Diode *D, DiodeState *S, int nd, int ppt, int grid, hipStream_t s);
+                                                int parity, hipStream_t s);
+extern "C" hipError_t picx_prepare(void);
+extern "C" hipError_t picx_launch_sort(const Diode *D, DiodeState *S, int nd, int ppt, int grid, int parity,
+                                       hipStream_t s);
 
 namespace {
 
@@ -270,16 +272,16 @@ int grid_for(const pic_handle *h)
 }
 
 // parity: buffer current before the re-sort; the re-sort flips it
-int enqueue_sort(pic_handle *h, hipStream_t s)
+int enqueue_sort(pic_handle *h, hipStream_t s, int parity)
 {
-    HIP_TRY(picx_launch_sort(h->dD, h->dS, h->nd, h->ppt, h->grid, s));
+    HIP_TRY(picx_launch_sort(h->dD, h->dS, h->nd, h->ppt, h->grid, parity, s));
     return PIC_OK;
 }
 
 int enqueue_body(pic_handle *h, hipStream_t s, int parity)
 {
     HIP_TRY(picx_launch_particles(h->dD, h->dS, h->nd, 0, h->ppt, h->grid, parity, s));
-    HIP_TRY(picx_launch_sources_field(h->dD, h->dS, h->nd, 0, h->max_nodes, s));
+    HIP_TRY(picx_launch_sources_field(h->dD, h->dS, h->nd, 0, h->max_nodes, parity, s));
     return PIC_OK;
 }
 
@@ -291,7 +293,7 @@ bool sort_due(const pic_handle *h)
 int launch_step(pic_handle *h)
 {
     if (sort_due(h)) {
-        int rc = enqueue_sort(h, h->stream);
+        int rc = enqueue_sort(h, h->stream, h->parity);
         if (rc) return rc;
         h->parity ^= 1;
         h->sort_next = false;
@@ -310,7 +312,7 @@ int ensure_graph(pic_handle *h, int p)
     if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     hipGraph_t g;
     HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_sort(h, h->cap_stream);
+    int rc = enqueue_sort(h, h->cap_stream, p);
     for (int k = 0; rc == PIC_OK && k < h->sort_period; ++k) rc = enqueue_body(h, h->cap_stream, p ^ 1);
     hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
     if (rc) return rc;
@@ -347,10 +349,10 @@ int run_steps(pic_handle *h, int64_t nsteps)
 
 int refield(pic_handle *h)
 {
-    HIP_TRY(picx_launch_sort(h->dD, h->dS, h->nd, h->ppt, h->grid, h->stream));
+    HIP_TRY(picx_launch_sort(h->dD, h->dS, h->nd, h->ppt, h->grid, h->parity, h->stream));
     h->parity ^= 1;
     HIP_TRY(picx_launch_particles(h->dD, h->dS, h->nd, 1, h->ppt, h->grid, h->parity, h->stream));
-    HIP_TRY(picx_launch_sources_field(h->dD, h->dS, h->nd, 1, h->max_nodes, h->stream));
+    HIP_TRY(picx_launch_sources_field(h->dD, h->dS, h->nd, 1, h->max_nodes, h->parity, h->stream));
     h->sort_next = false;
     return PIC_OK;
 }
@@ -484,6 +486,7 @@ int pic_init(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t b
     h->grid = grid_for(h);
 
     auto cleanup = [&](int code) { delete h; return code; };
+    if (picx_prepare() != hipSuccess) return cleanup(fail(PIC_EHIP, "kernel attribute setup failed"));
     size_t zbeg = (reinterpret_cast<char *>(h->hD[0].st) - h->ws);
     if (hipMemsetAsync(h->ws + zbeg, 0, zend - zbeg, h->stream) != hipSuccess)
         return cleanup(fail(PIC_EHIP, "hipMemsetAsync failed"));
@@ -774,7 +777,7 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
     int64_t k_ev = 0;
     for (int64_t k = 0; k < nsteps; ++k) {
         if (sort_due(h)) {
-            int rc = enqueue_sort(h, h->stream);
+            int rc = enqueue_sort(h, h->stream, h->parity);
             if (rc) return rc;
             h->parity ^= 1;
             h->sort_next = false;
@@ -783,7 +786,7 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
         if (rec) HIP_TRY(hipEventRecord(ev[2 * k_ev], h->stream));
         HIP_TRY(picx_launch_particles(h->dD, h->dS, h->nd, 0, h->ppt, h->grid, h->parity, h->stream));
         if (rec) { HIP_TRY(hipEventRecord(ev[2 * k_ev + 1], h->stream)); ++k_ev; }
-        HIP_TRY(picx_launch_sources_field(h->dD, h->dS, h->nd, 0, h->max_nodes, h->stream));
+        HIP_TRY(picx_launch_sources_field(h->dD, h->dS, h->nd, 0, h->max_nodes, h->parity, h->stream));
         h->issued++;
     }
     HIP_TRY(hipEventRecord(t1, h->stream));

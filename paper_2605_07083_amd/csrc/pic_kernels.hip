@@ -255,7 +255,7 @@ struct ChunkCounts {
     int coll[NCH];
 };
 
-__device__ __noinline__ void mcc_one(const Diode &dd, int s, const SpeciesBuf &b, int i, uint32_t step, double zn,
+__device__ __forceinline__ void mcc_one(const Diode &dd, int s, const SpeciesBuf &b, int i, uint32_t step, double zn,
                         float vzn, ChunkCounts *cc)
 {
     const int ion = (s == SP_I);
@@ -470,8 +470,6 @@ __global__ __launch_bounds__(NT) void k_particles(const Diode *__restrict__ D, c
         const int n = seg_n[seg];
         const int slot0 = (c - segbase) * CHUNK;
 
-        ChunkRegs<PPT> A;
-        load_chunk<PPT>(A, b, slot0 + tid * PPT, mode);
         const uint32_t step = S[d].step;
         // window of the run from its first and last particle
         const int last_slot = min(n, (run_end - segbase) * CHUNK) - 1;
@@ -498,10 +496,32 @@ __global__ __launch_bounds__(NT) void k_particles(const Diode *__restrict__ D, c
 
         const double qmdt = dd.qmdt[s], dt = dd.dt, L = dd.L;
         unsigned long long *H = dd.H[s];
-        for (int cc_ = c; cc_ < run_end; ++cc_) {
+        // chunks of the run, then one extra pass that drains the rare-work queue;
+        // the queue is also drained before any chunk that could overflow it
+        for (int cc_ = c;; ++cc_) {
+            const bool done = cc_ == run_end;
+            if (mode == 0) {
+                lds_barrier();
+                const int qn = q_n;
+                if (done || qn > CQ - CHUNK) {
+                    // the main loop's stores precede the rare work's (workgroup-scope fence)
+                    __syncthreads();
+                    for (int q = tid; q < qn; q += NT) {
+                        const uint32_t item = rq[q];
+                        const int i = (int)(item & RARE_MASK);
+                        const uint32_t kind = item >> RARE_SHIFT;
+                        if (kind == 0u) mcc_one(dd, s, b, i, step, b.z[i], b.vz[i], &cc);
+                        else rare_absorbed(dd, s, b, i, (int)kind - 1);
+                    }
+                    __syncthreads();
+                    if (tid == 0) q_n = 0;
+                    lds_barrier();
+                }
+            }
+            if (done) break;
             const int t0 = (cc_ - segbase) * CHUNK + tid * PPT;
-            ChunkRegs<PPT> B;
-            if (cc_ + 1 < run_end) load_chunk<PPT>(B, b, t0 + CHUNK, mode);
+            ChunkRegs<PPT> A;
+            load_chunk<PPT>(A, b, t0, mode);
             int jcur = -1;
             unsigned long long accL = 0ull, accA = 0ull;
             double zw[PPT];
@@ -570,44 +590,24 @@ __global__ __launch_bounds__(NT) void k_particles(const Diode *__restrict__ D, c
             }
             // last run of every lane: combine across the wave when all lanes agree
             const int j0w = __shfl(jcur, 0, 64);
-            const bool same = __all(jcur == j0w);
-            if (same) {
+            if (__all(jcur == j0w)) {
                 const unsigned long long sL = wave_sum_u64(accL), sA = wave_sum_u64(accA);
                 if (lane_id() == 0 && j0w >= 0) flush_run(j0w, sL, sA, w0, wn, hist, H);
             } else if (jcur >= 0) {
                 flush_run(jcur, accL, accA, w0, wn, hist, H);
             }
-            if (cc_ + 1 < run_end) A = B;
-            // rare work in batches, before the queue could overflow with the next chunk
-            if (mode == 0 && cc_ + 1 < run_end) {
-                lds_barrier();
-                const int qn = q_n;
-                if (qn > CQ - CHUNK) {
-                    __syncthreads();
-                    for (int q = tid; q < qn; q += NT) do_rare(dd, s, b, rq[q], step, &cc);
-                    __syncthreads();
-                    if (tid == 0) q_n = 0;
-                    lds_barrier();
-                }
-            }
         }
-        // the main loop's stores precede the rare work's (workgroup-scope fence)
-        __syncthreads();
+        lds_barrier();
         for (int t = tid; t < wn; t += NT) {
             const unsigned long long v = hist[t];
             if (v) atomicAdd(&H[w0 + t], v);
         }
-        if (mode == 0) {
-            const int qn = q_n;
-            for (int q = tid; q < qn; q += NT) do_rare(dd, s, b, rq[q], step, &cc);
-            lds_barrier();
-            if (tid == 0) {
-                const int ion = (s == SP_I);
-                if (cc.cand) atomicAdd(&dd.tally->cand[ion], (unsigned long long)cc.cand);
+        if (mode == 0 && tid == 0) {
+            const int ion = (s == SP_I);
+            if (cc.cand) atomicAdd(&dd.tally->cand[ion], (unsigned long long)cc.cand);
 #pragma unroll
-                for (int k = 0; k < NCH; ++k)
-                    if (cc.coll[k]) atomicAdd(&dd.tally->coll[k], (unsigned long long)cc.coll[k]);
-            }
+            for (int k = 0; k < NCH; ++k)
+                if (cc.coll[k]) atomicAdd(&dd.tally->coll[k], (unsigned long long)cc.coll[k]);
         }
         lds_barrier();
         c = run_end;
@@ -647,64 +647,91 @@ __global__ __launch_bounds__(256) void k_load(const Diode *__restrict__ D, const
 // ---------------------------------------------------------------------------
 // Cell re-sort: count -> scan -> scatter -> finalize (compacts holes too).
 // ---------------------------------------------------------------------------
+// Window of a run of chunks for the re-sort: cells of its first and last
+// particle plus the drift margin (cells, not nodes).
+__device__ __forceinline__ void sort_window(const Diode &dd, const SpeciesBuf &b, int slot0, int last_slot, int &w0,
+                                            int &wn)
+{
+    int ja, jb;
+    double f;
+    cic(b.z[slot0], dd.invdz, dd.N, ja, f);
+    cic(b.z[max(last_slot, slot0)], dd.invdz, dd.N, jb, f);
+    w0 = max(0, min(ja, jb) - DRIFT);
+    wn = min(min(dd.N - 1, max(ja, jb) + DRIFT) - w0 + 1, WMAX + 1);
+}
+
+// Cell counts of the live particles.  Each thread counts runs of equal cells
+// over its PPT consecutive slots and adds them to the block's LDS window.
 template <int PPT>
 __global__ __launch_bounds__(NT) void k_sort_count(const Diode *__restrict__ D, const DiodeState *__restrict__ S,
-                                                   int nd)
+                                                   int nd, int parity)
 {
     constexpr int CHUNK = NT * PPT;
     __shared__ int seg_end[NSP * MAX_DIODES];
-    __shared__ int red[2 * NW];
+    __shared__ int seg_n[NSP * MAX_DIODES];
     __shared__ int cnt[WMAX + 2];
     ChunkMap cm;
-    build_chunk_map(S, nd, CHUNK, false, seg_end, cm);
-    int first, end, stride;
-    chunk_range(cm.total, first, end, stride);
+    build_chunk_map(S, nd, CHUNK, false, seg_end, cm, seg_n);
     const int tid = threadIdx.x;
-    for (int c = first; c < end; c += stride) {
+    const int per_block = (cm.total + gridDim.x - 1) / gridDim.x;
+    const int c_begin = blockIdx.x * per_block;
+    const int c_end = min(cm.total, c_begin + per_block);
+    for (int c = c_begin; c < c_end;) {
         const int seg = find_seg(seg_end, cm.nseg, c);
+        const int run_end = min(c_end, seg_end[seg]);
+        const int segbase = seg ? seg_end[seg - 1] : 0;
         const int d = seg / NSP, s = seg - d * NSP;
-        const int base = (c - (seg ? seg_end[seg - 1] : 0)) * CHUNK;
         const Diode &dd = D[d];
-        const int n = S[d].n[s];
-        const SpeciesBuf b = dd.buf[S[d].parity][s];
-        int j[PPT];
-        bool alive[PPT];
-        int mn = 0x7fffffff, mx = -1;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            int i = base + k * NT + tid;
-            double z = i < n ? b.z[i] : -1.0;
-            alive[k] = z >= 0.0;
-            if (alive[k]) {
-                double f;
-                cic(z, dd.invdz, dd.N, j[k], f);
-                mn = min(mn, j[k]);
-                mx = max(mx, j[k]);
-            }
-        }
-        block_minmax(mn, mx, red);
-        if (mx >= 0) {
-            const int w = min(mx + 1 - mn, WMAX + 1);
-            for (int t = tid; t < w; t += NT) cnt[t] = 0;
-            __syncthreads();
-            int *cc = dd.cell_cnt[s];
+        const SpeciesBuf b = dd.buf[parity][s];
+        const int n = seg_n[seg];
+        const int slot0 = (c - segbase) * CHUNK;
+        int w0, wn;
+        sort_window(dd, b, slot0, min(n, (run_end - segbase) * CHUNK) - 1, w0, wn);
+        for (int t = tid; t < wn; t += NT) cnt[t] = 0;
+        lds_barrier();
+        int *gc = dd.cell_cnt[s];
+        for (int cc_ = c; cc_ < run_end; ++cc_) {
+            const int t0 = (cc_ - segbase) * CHUNK + tid * PPT;
+            int jcur = -1, run = 0;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                int key = -1 - tid;
-                if (alive[k]) {
-                    const int jl = j[k] - mn;
-                    if (jl < w) key = jl;
-                    else atomicAdd(&cc[j[k]], 1);
+                const double z = b.z[t0 + k];
+                if (t0 + k < n && z >= 0.0) {
+                    int j;
+                    double f;
+                    cic(z, dd.invdz, dd.N, j, f);
+                    if (j != jcur) {
+                        if (run) {
+                            const int jl = jcur - w0;
+                            if (jl >= 0 && jl < wn) atomicAdd(&cnt[jl], run);
+                            else atomicAdd(&gc[jcur], run);
+                        }
+                        jcur = j;
+                        run = 1;
+                    } else {
+                        ++run;
+                    }
                 }
-                int start, len;
-                run_extent(key, start, len);
-                if (key >= 0 && lane_id() == start) atomicAdd(&cnt[key], len);
             }
-            __syncthreads();
-            for (int t = tid; t < w; t += NT)
-                if (cnt[t]) atomicAdd(&cc[mn + t], cnt[t]);
+            const int j0w = __shfl(jcur, 0, 64);
+            int tot = run;
+            if (__all(jcur == j0w)) {
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+                if (lane_id() != 0) run = 0;
+                else run = tot;
+            }
+            if (run) {
+                const int jl = jcur - w0;
+                if (jl >= 0 && jl < wn) atomicAdd(&cnt[jl], run);
+                else atomicAdd(&gc[jcur], run);
+            }
         }
-        __syncthreads();
+        lds_barrier();
+        for (int t = tid; t < wn; t += NT)
+            if (cnt[t]) atomicAdd(&gc[w0 + t], cnt[t]);
+        lds_barrier();
+        c = run_end;
     }
 }
 
@@ -737,84 +764,92 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const Diode *__restrict__ D)
     if (threadIdx.x == 1023) dd.st->n_new[s] = part[1023];
 }
 
+// Scatter into the other buffer in cell order (holes dropped).  Ranks within
+// a block come from LDS atomics on runs of equal cells, block bases from one
+// global atomic per (block, cell).
 template <int PPT>
 __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D, const DiodeState *__restrict__ S,
-                                                     int nd)
+                                                     int nd, int parity)
 {
     constexpr int CHUNK = NT * PPT;
     __shared__ int seg_end[NSP * MAX_DIODES];
-    __shared__ int red[2 * NW];
+    __shared__ int seg_n[NSP * MAX_DIODES];
     __shared__ int cnt[WMAX + 2];
     ChunkMap cm;
-    build_chunk_map(S, nd, CHUNK, false, seg_end, cm);
-    int first, end, stride;
-    chunk_range(cm.total, first, end, stride);
+    build_chunk_map(S, nd, CHUNK, false, seg_end, cm, seg_n);
     const int tid = threadIdx.x;
-    for (int c = first; c < end; c += stride) {
+    const int per_block = (cm.total + gridDim.x - 1) / gridDim.x;
+    const int c_begin = blockIdx.x * per_block;
+    const int c_end = min(cm.total, c_begin + per_block);
+    for (int c = c_begin; c < c_end;) {
         const int seg = find_seg(seg_end, cm.nseg, c);
+        const int segbase = seg ? seg_end[seg - 1] : 0;
+        // one chunk per window here: ranks of the whole chunk must fit in registers
+        const int run_end = c + 1;
         const int d = seg / NSP, s = seg - d * NSP;
-        const int base = (c - (seg ? seg_end[seg - 1] : 0)) * CHUNK;
         const Diode &dd = D[d];
-        const int n = S[d].n[s];
-        const int par = S[d].parity;
-        const SpeciesBuf src = dd.buf[par][s], dst = dd.buf[par ^ 1][s];
+        const SpeciesBuf src = dd.buf[parity][s], dst = dd.buf[parity ^ 1][s];
+        const int n = seg_n[seg];
+        const int slot0 = (c - segbase) * CHUNK;
+        int w0, wn;
+        sort_window(dd, src, slot0, min(n, (run_end - segbase) * CHUNK) - 1, w0, wn);
+        for (int t = tid; t < wn; t += NT) cnt[t] = 0;
+        lds_barrier();
+        int *cur = dd.cell_cnt[s];
+        const int t0 = slot0 + tid * PPT;
         int j[PPT], rank[PPT];
         double z[PPT];
-        bool alive[PPT];
-        int mn = 0x7fffffff, mx = -1;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            int i = base + k * NT + tid;
-            z[k] = i < n ? src.z[i] : -1.0;
-            alive[k] = z[k] >= 0.0;
-            if (alive[k]) {
+            z[k] = src.z[t0 + k];
+            j[k] = -1;
+            if (t0 + k < n && z[k] >= 0.0) {
                 double f;
                 cic(z[k], dd.invdz, dd.N, j[k], f);
-                mn = min(mn, j[k]);
-                mx = max(mx, j[k]);
             }
         }
-        block_minmax(mn, mx, red);
-        if (mx >= 0) {
-            const int w = min(mx + 1 - mn, WMAX + 1);
-            for (int t = tid; t < w; t += NT) cnt[t] = 0;
-            __syncthreads();
-            int *cur = dd.cell_cnt[s];
+        // runs of equal cells: one LDS atomic per run gives the run's base rank
+        int base = 0, pos = 0;
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                int key = -1 - tid;
-                if (alive[k]) {
-                    const int jl = j[k] - mn;
-                    if (jl < w) key = jl;
-                    else rank[k] = -1 - atomicAdd(&cur[j[k]], 1);   // outlier: global slot
+        for (int k = 0; k < PPT; ++k) {
+            rank[k] = 0;
+            if (j[k] < 0) continue;
+            const bool head = (k == 0) || (j[k] != j[k > 0 ? k - 1 : 0]);
+            if (head) {
+                int len = 1;
+                bool same = true;
+#pragma unroll
+                for (int m = k + 1; m < PPT; ++m) {
+                    same = same && (j[m] == j[k]);
+                    len += same ? 1 : 0;
                 }
-                int start, len;
-                run_extent(key, start, len);
-                int b0 = 0;
-                if (key >= 0 && lane_id() == start) b0 = atomicAdd(&cnt[key], len);
-                b0 = __shfl(b0, start, 64);
-                if (key >= 0) rank[k] = b0 + lane_id() - start;
+                const int jl = j[k] - w0;
+                if (jl >= 0 && jl < wn) base = atomicAdd(&cnt[jl], len);
+                else base = -1 - atomicAdd(&cur[j[k]], len);       // outlier: global slots
+                pos = 0;
             }
-            __syncthreads();
-            for (int t = tid; t < w; t += NT) {
-                int v = cnt[t];
-                if (v) cnt[t] = atomicAdd(&cur[mn + t], v);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                if (!alive[k]) continue;
-                const int i = base + k * NT + tid;
-                int dest = rank[k] >= 0 ? cnt[j[k] - mn] + rank[k] : -1 - rank[k];
-                dst.z[dest] = z[k];
-                dst.vz[dest] = src.vz[i];
-                dst.vx[dest] = src.vx[i];
-                dst.vy[dest] = src.vy[i];
-                dst.id[dest] = src.id[i];
-                dst.tc[dest] = src.tc[i];
-            }
+            rank[k] = base >= 0 ? base + pos : base - pos;
+            ++pos;
         }
-        __syncthreads();
+        lds_barrier();
+        for (int t = tid; t < wn; t += NT) {
+            const int v = cnt[t];
+            if (v) cnt[t] = atomicAdd(&cur[w0 + t], v);
+        }
+        lds_barrier();
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (j[k] < 0) continue;
+            const int dest = rank[k] >= 0 ? cnt[j[k] - w0] + rank[k] : -1 - rank[k];
+            dst.z[dest] = z[k];
+            dst.vz[dest] = src.vz[t0 + k];
+            dst.vx[dest] = src.vx[t0 + k];
+            dst.vy[dest] = src.vy[t0 + k];
+            dst.id[dest] = src.id[t0 + k];
+            dst.tc[dest] = src.tc[t0 + k];
+        }
+        lds_barrier();
+        c = run_end;
     }
 }
 
@@ -886,6 +921,7 @@ __device__ __forceinline__ double to_double(I128 a)
 // ---------------------------------------------------------------------------
 constexpr int FT = 1024;
 constexpr int FW = FT / 64;
+constexpr size_t LDS_FIELD_BYTES = 148 * 1024;   // node arrays staged in LDS up to 18944 nodes
 
 // Block-wide exclusive scan of one value per thread (1024 threads): wave
 // scans with cross-lane shuffles, one LDS exchange of the 16 wave totals.
@@ -959,17 +995,18 @@ __device__ void write_particle(const SpeciesBuf &b, int i, double z, float vx, f
     b.z[i] = z; b.vx[i] = vx; b.vy[i] = vy; b.vz[i] = vz; b.id[i] = id; b.tc[i] = tc;
 }
 
-// Births of one step: ionisation products in increasing parent id, thermionic
-// emission (flux-weighted half-Maxwellian at Tc placed at z = v_z dt), pair
-// replenishment (one e-ion pair per ion lost, shared uniform position,
-// Maxwellian at the initial temperatures).  Newborns deposit directly.
-__device__ void sources(const Diode &dd, DiodeState *st, unsigned long long *keys)
+// Births of one step, one thread per newborn: ionisation products in
+// increasing parent id, thermionic emission (flux-weighted half-Maxwellian at
+// Tc placed at z = v_z dt), pair replenishment (one e-ion pair per ion lost,
+// shared uniform position, Maxwellian at the initial temperatures).
+// Newborns deposit directly into the global histograms.
+__device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, unsigned long long *keys, uint32_t step,
+                                        int parity)
 {
     const int tid = threadIdx.x;
     __shared__ int s_ne, s_q, s_R, s_bP, s_bE, s_bI, s_okP, s_okE, s_okI;
-    __shared__ uint32_t s_id0, s_step;
+    __shared__ uint32_t s_id0;
     if (tid == 0) {
-        const uint32_t step = st->step;
         const int q = min(st->iz_count, IZQ_CAP);
         const int R = dd.replenish ? st->ion_lost : 0;
         int ne = 0;
@@ -978,7 +1015,7 @@ __device__ void sources(const Diode &dd, DiodeState *st, unsigned long long *key
             uint4 be = philox(step, EV_EMIT, 0u, 0u, 0xFFFFFFFFu, dd.kseed);
             ne = (int)fl + (u53(be.x, be.y) < dd.emit_x - fl ? 1 : 0);
         }
-        s_q = q; s_R = R; s_ne = ne; s_step = step; s_id0 = st->next_id;
+        s_q = q; s_R = R; s_ne = ne; s_id0 = st->next_id;
         s_bP = st->n[SP_P]; s_bE = st->n[SP_E]; s_bI = st->n[SP_I];
         // births that do not fit are dropped and flagged
         s_okP = min(q + R, dd.cap[SP_P] - s_bP);
@@ -988,9 +1025,8 @@ __device__ void sources(const Diode &dd, DiodeState *st, unsigned long long *key
     }
     __syncthreads();
     const int q = s_q, R = s_R, ne = s_ne;
-    const uint32_t step = s_step, id0 = s_id0;
-    const int par = st->parity;
-    const SpeciesBuf bP = dd.buf[par][SP_P], bE = dd.buf[par][SP_E], bI = dd.buf[par][SP_I];
+    const uint32_t id0 = s_id0;
+    const SpeciesBuf bP = dd.buf[parity][SP_P], bE = dd.buf[parity][SP_E], bI = dd.buf[parity][SP_I];
 
     if (q > 0) {
         int np2 = 1;
@@ -1011,7 +1047,11 @@ __device__ void sources(const Diode &dd, DiodeState *st, unsigned long long *key
                 __syncthreads();
             }
         }
-        for (int r = tid; r < q; r += FT) {
+    }
+    const int total = q + ne + R;
+    for (int x = tid; x < total; x += FT) {
+        if (x < q) {
+            const int r = x;
             const IzEvent ev = dd.izq[(int)(keys[r] & 0xFFFFFFFFull)];
             const uint32_t ide = id0 + 2u * r, idi = ide + 1u;
             const uint4 be = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
@@ -1026,55 +1066,53 @@ __device__ void sources(const Diode &dd, DiodeState *st, unsigned long long *key
                                next_candidate(step, dd.lam[1], bi.z, bi.w));
                 deposit_global(dd, SP_I, ev.z);
             }
-        }
-    }
-    for (int i = tid; i < ne; i += FT) {
-        const uint32_t idn = id0 + 2u * q + i;
-        const uint4 b0 = philox(step, EV_BIRTH, 0u, 0u, idn, dd.kseed);
-        const uint4 b1 = philox(step, EV_BIRTH, 1u, 0u, idn, dd.kseed);
-        double n1, n2;
-        bm32(b0.x, b0.y, n1, n2);
-        const float vz = (float)(dd.sig_c * sqrt(-2.0 * log(u53(b0.z, b0.w))));
-        const float vx = (float)(dd.sig_c * n1), vy = (float)(dd.sig_c * n2);
-        const double z = (double)vz * dd.dt;
-        const uint32_t tc = next_candidate(step, dd.lam[0], b1.z, b1.w);
-        if (i < s_okE) {
-            if (z >= dd.L) {
-                const double ke = 0.5 * dd.mass[SP_E] * ((double)vx * vx + (double)vy * vy + (double)vz * vz);
-                atomicAdd(&dd.tally->abs_count[SP_E][1], 1ull);
-                atomicAdd(&dd.tally->abs_energy[SP_E][1], ke);
-                write_particle(bE, s_bE + i, -1.0, vx, vy, vz, idn, tc);
-            } else {
-                write_particle(bE, s_bE + i, z, vx, vy, vz, idn, tc);
-                deposit_global(dd, SP_E, z);
+        } else if (x < q + ne) {
+            const int i = x - q;
+            const uint32_t idn = id0 + 2u * q + i;
+            const uint4 b0 = philox(step, EV_BIRTH, 0u, 0u, idn, dd.kseed);
+            const uint4 b1 = philox(step, EV_BIRTH, 1u, 0u, idn, dd.kseed);
+            double n1, n2;
+            bm32(b0.x, b0.y, n1, n2);
+            const float vz = (float)(dd.sig_c * sqrt(-2.0 * log(u53(b0.z, b0.w))));
+            const float vx = (float)(dd.sig_c * n1), vy = (float)(dd.sig_c * n2);
+            const double z = (double)vz * dd.dt;
+            const uint32_t tc = next_candidate(step, dd.lam[0], b1.z, b1.w);
+            if (i < s_okE) {
+                if (z >= dd.L) {
+                    const double ke = 0.5 * dd.mass[SP_E] * ((double)vx * vx + (double)vy * vy + (double)vz * vz);
+                    atomicAdd(&dd.tally->abs_count[SP_E][1], 1ull);
+                    atomicAdd(&dd.tally->abs_energy[SP_E][1], ke);
+                    write_particle(bE, s_bE + i, -1.0, vx, vy, vz, idn, tc);
+                } else {
+                    write_particle(bE, s_bE + i, z, vx, vy, vz, idn, tc);
+                    deposit_global(dd, SP_E, z);
+                }
+            }
+        } else {
+            const int r = x - q - ne;
+            const uint32_t ide = id0 + 2u * q + ne + 2u * r, idi = ide + 1u;
+            const uint4 e0 = philox(step, EV_BIRTH, 0u, 0u, ide, dd.kseed);
+            const uint4 e1 = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
+            const uint4 i0 = philox(step, EV_BIRTH, 0u, 0u, idi, dd.kseed);
+            const uint4 i1 = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
+            const double z = dd.L * u53(e1.x, e1.y);
+            double a1, a2, a3, a4;
+            bm32(e0.x, e0.y, a1, a2);
+            bm32(e0.z, e0.w, a3, a4);
+            if (q + r < s_okP) {
+                write_particle(bP, s_bP + q + r, z, (float)(dd.sig_e0 * a1), (float)(dd.sig_e0 * a2),
+                               (float)(dd.sig_e0 * a3), ide, next_candidate(step, dd.lam[0], e1.z, e1.w));
+                deposit_global(dd, SP_P, z);
+            }
+            bm32(i0.x, i0.y, a1, a2);
+            bm32(i0.z, i0.w, a3, a4);
+            if (q + r < s_okI) {
+                write_particle(bI, s_bI + q + r, z, (float)(dd.sig_i0 * a1), (float)(dd.sig_i0 * a2),
+                               (float)(dd.sig_i0 * a3), idi, next_candidate(step, dd.lam[1], i1.z, i1.w));
+                deposit_global(dd, SP_I, z);
             }
         }
     }
-    for (int r = tid; r < R; r += FT) {
-        const uint32_t ide = id0 + 2u * q + ne + 2u * r, idi = ide + 1u;
-        const uint4 e0 = philox(step, EV_BIRTH, 0u, 0u, ide, dd.kseed);
-        const uint4 e1 = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
-        const uint4 i0 = philox(step, EV_BIRTH, 0u, 0u, idi, dd.kseed);
-        const uint4 i1 = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
-        const double z = dd.L * u53(e1.x, e1.y);
-        double a1, a2, a3, a4;
-        bm32(e0.x, e0.y, a1, a2);
-        bm32(e0.z, e0.w, a3, a4);
-        if (q + r < s_okP) {
-            write_particle(bP, s_bP + q + r, z, (float)(dd.sig_e0 * a1), (float)(dd.sig_e0 * a2),
-                           (float)(dd.sig_e0 * a3), ide, next_candidate(step, dd.lam[0], e1.z, e1.w));
-            deposit_global(dd, SP_P, z);
-        }
-        bm32(i0.x, i0.y, a1, a2);
-        bm32(i0.z, i0.w, a3, a4);
-        if (q + r < s_okI) {
-            write_particle(bI, s_bI + q + r, z, (float)(dd.sig_i0 * a1), (float)(dd.sig_i0 * a2),
-                           (float)(dd.sig_i0 * a3), idi, next_candidate(step, dd.lam[1], i1.z, i1.w));
-            deposit_global(dd, SP_I, z);
-        }
-    }
-    __threadfence();
-    __syncthreads();
     if (tid == 0) {
         st->n[SP_P] = s_bP + s_okP;
         st->n[SP_E] = s_bE + s_okE;
@@ -1088,9 +1126,31 @@ __device__ void sources(const Diode &dd, DiodeState *st, unsigned long long *key
     }
 }
 
+__device__ __forceinline__ long long wave_incl_scan_i64(long long x)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ I128 wave_incl_scan_i128(I128 x)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const I128 y = shfl_up_i128(x, o);
+        if (lane >= o) x = add(x, y);
+    }
+    return x;
+}
+
 // ---------------------------------------------------------------------------
-// Sources and field: one workgroup of 1024 threads per diode; each thread owns
-// PER consecutive nodes held in registers.
+// Sources and field: one workgroup of 1024 threads per diode.  Nodes are
+// handled in TILES coalesced tiles of 1024 (node j = t * 1024 + thread).
 // mode 0: births, solve, field, tallies, step + 1; mode 1: solve and field only.
 //
 // Poisson: phi_{j-1} - 2 phi_j + phi_{j+1} = -alpha R_j (j = 1..N-1),
@@ -1099,80 +1159,123 @@ __device__ void sources(const Diode &dd, DiodeState *st, unsigned long long *key
 // phi_j = V j / N + alpha (j T_N - N T_j) / N: the direct solution of the
 // constant-coefficient Dirichlet system, rounded once at the end.
 // ---------------------------------------------------------------------------
-template <int PER>
+template <int TILES>
 __global__ __launch_bounds__(FT) void k_sources_field(const Diode *__restrict__ D, DiodeState *__restrict__ S,
-                                                      int mode)
+                                                      int mode, int parity)
 {
     const Diode &dd = D[blockIdx.x];
     DiodeState *st = S + blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
     __shared__ unsigned long long keys[IZQ_CAP];
-    __shared__ long long sh64[FW];
-    __shared__ I128 sh128[FW];
-    __shared__ double phl[FT], phr[FT];
+    __shared__ long long tot64[TILES * FW];
+    __shared__ I128 tot128[TILES * FW];
+    __shared__ I128 s_TN;
+    const uint32_t step = st->step;
 
-    if (mode == 0) sources(dd, st, keys);
+    if (mode == 0) sources(dd, st, keys, step, parity);
     __syncthreads();
 
     const int N = dd.N;
     const int nn = N + 1;
-    const int j0 = tid * PER;
-    long long S1[PER];
-    long long acc = 0;
+    // R at the owned nodes (coalesced), wave-inclusive scans, wave totals to LDS
+    long long S1[TILES];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int j = j0 + k;
+    for (int t = 0; t < TILES; ++t) {
+        const int j = t * FT + tid;
         long long r = 0;
-        if (j >= 1 && j <= N - 1)
-            r = (long long)(dd.H[SP_I][j] - dd.H[SP_P][j] - dd.H[SP_E][j]);
-        acc += r;
-        S1[k] = acc;                       // local inclusive sums of R
+        if (j >= 1 && j <= N - 1) r = (long long)(dd.H[SP_I][j] - dd.H[SP_P][j] - dd.H[SP_E][j]);
+        S1[t] = wave_incl_scan_i64(r);
+        if (lane == 63) tot64[t * FW + w] = S1[t];
     }
-    long long tot64;
-    const long long s1off = block_excl_scan_i64(acc, sh64, tot64);
-    I128 tloc = i128(0);
+    __syncthreads();
+    if (w == 0) {
+        // exclusive scan of the TILES*FW wave totals (in node order), by wave 0
+        constexpr int PERL = (TILES * FW + 63) / 64;
+        long long v[PERL];
+        long long run = 0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        S1[k] += s1off;                    // S1_j
-        const int j = j0 + k;
-        if (j >= 1 && j <= N - 1) tloc = add(tloc, i128(S1[k]));
-    }
-    I128 T_N;
-    I128 T = block_excl_scan_i128(tloc, sh128, T_N);   // T_{j0}
-    const double alpha_n = dd.alpha / (double)N;
-    double ph[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int j = j0 + k;
-        double v = 0.0;
-        if (j == N) v = dd.V;
-        else if (j >= 1 && j < N) {
-            const I128 x = add(mul_small(T_N, (unsigned)j), neg(mul_small(T, (unsigned)N)));
-            v = dd.V * (double)j / (double)N + alpha_n * to_double(x);
+        for (int q = 0; q < PERL; ++q) {
+            const int idx = lane * PERL + q;
+            v[q] = idx < TILES * FW ? tot64[idx] : 0;
+            run += v[q];
         }
-        ph[k] = v;
-        if (j >= 1 && j <= N - 1) T = add(T, i128(S1[k]));
+        const long long incl = wave_incl_scan_i64(run);
+        long long off = incl - run;
+#pragma unroll
+        for (int q = 0; q < PERL; ++q) {
+            const int idx = lane * PERL + q;
+            if (idx < TILES * FW) tot64[idx] = off;
+            off += v[q];
+        }
     }
-    phl[tid] = ph[0];
-    phr[tid] = ph[PER - 1];
+    __syncthreads();
+    // S1_j, and the wave sums of the T increments (S1 at interior nodes)
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) {
+        S1[t] += tot64[t * FW + w];
+        const int j = t * FT + tid;
+        const long long m = (j >= 1 && j <= N - 1) ? S1[t] : 0;
+        I128 x = i128(m);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            I128 y;
+            y.lo = __shfl_xor(x.lo, o, 64);
+            y.hi = __shfl_xor(x.hi, o, 64);
+            x = add(x, y);
+        }
+        if (lane == 0) tot128[t * FW + w] = x;
+    }
+    __syncthreads();
+    if (w == 0) {
+        constexpr int PERL = (TILES * FW + 63) / 64;
+        I128 v[PERL];
+        I128 run = i128(0);
+#pragma unroll
+        for (int q = 0; q < PERL; ++q) {
+            const int idx = lane * PERL + q;
+            v[q] = idx < TILES * FW ? tot128[idx] : i128(0);
+            run = add(run, v[q]);
+        }
+        const I128 incl = wave_incl_scan_i128(run);
+        I128 off = add(incl, neg(run));
+#pragma unroll
+        for (int q = 0; q < PERL; ++q) {
+            const int idx = lane * PERL + q;
+            if (idx < TILES * FW) tot128[idx] = off;
+            off = add(off, v[q]);
+        }
+        if (lane == 63) s_TN = incl;
+    }
+    __syncthreads();
+    const I128 T_N = s_TN;
+    const double alpha_n = dd.alpha / (double)N;
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) {
+        const int j = t * FT + tid;
+        const long long m = (j >= 1 && j <= N - 1) ? S1[t] : 0;
+        const I128 mi = i128(m);
+        const I128 T = add(add(wave_incl_scan_i128(mi), neg(mi)), tot128[t * FW + w]);   // T_j
+        if (j < nn) {
+            double v = 0.0;
+            if (j == N) v = dd.V;
+            else if (j >= 1) {
+                const I128 x = add(mul_small(T_N, (unsigned)j), neg(mul_small(T, (unsigned)N)));
+                v = dd.V * (double)j / (double)N + alpha_n * to_double(x);
+            }
+            dd.phi[j] = v;
+        }
+    }
     __syncthreads();
     const double inv2dz = 1.0 / (2.0 * dd.dz);
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int j = j0 + k;
-        if (j >= nn) break;
-        const double pm = k > 0 ? ph[k - 1] : (tid > 0 ? phr[tid - 1] : 0.0);
-        const double pp = k + 1 < PER ? ph[k + 1] : (tid + 1 < FT ? phl[tid + 1] : 0.0);
-        double E;
-        if (j == 0) E = (ph[k] - pp) / dd.dz;
-        else if (j == N) E = (pm - ph[k]) / dd.dz;
-        else E = (pm - pp) * inv2dz;
-        dd.phi[j] = ph[k];
-        dd.E[j] = E;
-    }
-    // keep the last deposit, clear the accumulators, time averages
     const int avg = st->avg_on;
     for (int j = tid; j < nn; j += FT) {
+        double E;
+        const double pc = dd.phi[j];
+        if (j == 0) E = (pc - dd.phi[1]) / dd.dz;
+        else if (j == N) E = (dd.phi[N - 1] - pc) / dd.dz;
+        else E = (dd.phi[j - 1] - dd.phi[j + 1]) * inv2dz;
+        dd.E[j] = E;
+        // keep the last deposit, clear the accumulators, time averages
 #pragma unroll
         for (int s = 0; s < NSP; ++s) {
             const long long h = (long long)dd.H[s][j];
@@ -1180,14 +1283,137 @@ __global__ __launch_bounds__(FT) void k_sources_field(const Diode *__restrict__ 
             dd.H[s][j] = 0ull;
             if (avg) dd.Hsum[s][j] += h;
         }
-    }
-    if (avg) {
-        __syncthreads();
-        for (int j = tid; j < nn; j += FT) dd.phi_sum[j] += dd.phi[j];
+        if (avg) dd.phi_sum[j] += pc;
     }
     __syncthreads();
     if (mode == 0 && tid == 0) {
-        const uint32_t nstep = st->step + 1u;
+        const uint32_t nstep = step + 1u;
+        st->step = nstep;
+        if (avg) st->avg_steps += 1;
+        if (dd.tally_period > 0 && nstep % (uint32_t)dd.tally_period == 0u) {
+            TallySnap &sn = dd.ring[(nstep / (uint32_t)dd.tally_period) % RING];
+            sn.step = nstep;
+            sn.t = *dd.tally;
+        }
+    }
+}
+
+// Same step with the node arrays staged in LDS (dynamic shared memory of
+// nn * 8 bytes): coalesced loads, then each thread walks PER consecutive nodes
+// serially in registers, with two block scans of the per-thread totals.
+__device__ __forceinline__ long long block_scan_excl_i64(long long v, long long *sh, long long &total)
+{
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const long long incl = wave_incl_scan_i64(v);
+    if (lane == 63) sh[w] = incl;
+    __syncthreads();
+    long long off = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < FW; ++q) {
+        const long long t = sh[q];
+        if (q < w) off += t;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return off + incl - v;
+}
+
+__device__ __forceinline__ I128 block_scan_excl_i128(I128 v, I128 *sh, I128 &total)
+{
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const I128 incl = wave_incl_scan_i128(v);
+    if (lane == 63) sh[w] = incl;
+    __syncthreads();
+    I128 off = i128(0), tot = i128(0);
+#pragma unroll
+    for (int q = 0; q < FW; ++q) {
+        const I128 t = sh[q];
+        if (q < w) off = add(off, t);
+        tot = add(tot, t);
+    }
+    __syncthreads();
+    total = tot;
+    return add(off, add(incl, neg(v)));
+}
+
+__global__ __launch_bounds__(FT) void k_sources_field_lds(const Diode *__restrict__ D, DiodeState *__restrict__ S,
+                                                          int mode, int parity)
+{
+    // births use the array first as their sort keys, the solve then as R_j and phi_j
+    extern __shared__ long long nodes[];
+    const Diode &dd = D[blockIdx.x];
+    DiodeState *st = S + blockIdx.x;
+    const int tid = threadIdx.x;
+    __shared__ long long sh64[FW];
+    __shared__ I128 sh128[FW];
+    const uint32_t step = st->step;
+
+    if (mode == 0) sources(dd, st, reinterpret_cast<unsigned long long *>(nodes), step, parity);
+    __syncthreads();
+
+    const int N = dd.N;
+    const int nn = N + 1;
+    for (int j = tid; j < nn; j += FT) {
+        long long r = 0;
+        if (j >= 1 && j <= N - 1) r = (long long)(dd.H[SP_I][j] - dd.H[SP_P][j] - dd.H[SP_E][j]);
+        nodes[j] = r;
+    }
+    __syncthreads();
+    const int per = (nn + FT - 1) / FT;
+    const int j0 = tid * per, j1 = min(nn, j0 + per);
+    long long loc = 0;
+    for (int j = j0; j < j1; ++j) loc += nodes[j];
+    long long tot;
+    const long long s1off = block_scan_excl_i64(loc, sh64, tot);
+    I128 tl = i128(0);
+    {
+        long long S1 = s1off;
+        for (int j = j0; j < j1; ++j) {
+            S1 += nodes[j];
+            if (j >= 1 && j <= N - 1) tl = add(tl, i128(S1));
+        }
+    }
+    I128 T_N;
+    I128 T = block_scan_excl_i128(tl, sh128, T_N);
+    const double alpha_n = dd.alpha / (double)N;
+    {
+        long long S1 = s1off;
+        for (int j = j0; j < j1; ++j) {
+            S1 += nodes[j];
+            double v = 0.0;
+            if (j == N) v = dd.V;
+            else if (j >= 1) {
+                const I128 x = add(mul_small(T_N, (unsigned)j), neg(mul_small(T, (unsigned)N)));
+                v = dd.V * (double)j / (double)N + alpha_n * to_double(x);
+            }
+            nodes[j] = __double_as_longlong(v);
+            if (j >= 1 && j <= N - 1) T = add(T, i128(S1));
+        }
+    }
+    __syncthreads();
+    const double inv2dz = 1.0 / (2.0 * dd.dz);
+    const int avg = st->avg_on;
+    for (int j = tid; j < nn; j += FT) {
+        const double pc = __longlong_as_double(nodes[j]);
+        double E;
+        if (j == 0) E = (pc - __longlong_as_double(nodes[1])) / dd.dz;
+        else if (j == N) E = (__longlong_as_double(nodes[N - 1]) - pc) / dd.dz;
+        else E = (__longlong_as_double(nodes[j - 1]) - __longlong_as_double(nodes[j + 1])) * inv2dz;
+        dd.phi[j] = pc;
+        dd.E[j] = E;
+#pragma unroll
+        for (int s = 0; s < NSP; ++s) {
+            const long long h = (long long)dd.H[s][j];
+            dd.Hlast[s][j] = h;
+            dd.H[s][j] = 0ull;
+            if (avg) dd.Hsum[s][j] += h;
+        }
+        if (avg) dd.phi_sum[j] += pc;
+    }
+    __syncthreads();
+    if (mode == 0 && tid == 0) {
+        const uint32_t nstep = step + 1u;
         st->step = nstep;
         if (avg) st->avg_steps += 1;
         if (dd.tally_period > 0 && nstep % (uint32_t)dd.tally_period == 0u) {
@@ -1231,23 +1457,41 @@ extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int n
 
 // max_nodes: the largest N + 1 over the diodes (<= 32768)
 extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
-                                                hipStream_t s)
+                                                int parity, hipStream_t s)
 {
-    const int per = (max_nodes + FT - 1) / FT;
-    if (per <= 1) hipLaunchKernelGGL(k_sources_field<1>, dim3(nd), dim3(FT), 0, s, D, S, mode);
-    else if (per <= 2) hipLaunchKernelGGL(k_sources_field<2>, dim3(nd), dim3(FT), 0, s, D, S, mode);
-    else if (per <= 4) hipLaunchKernelGGL(k_sources_field<4>, dim3(nd), dim3(FT), 0, s, D, S, mode);
-    else if (per <= 8) hipLaunchKernelGGL(k_sources_field<8>, dim3(nd), dim3(FT), 0, s, D, S, mode);
-    else if (per <= 16) hipLaunchKernelGGL(k_sources_field<16>, dim3(nd), dim3(FT), 0, s, D, S, mode);
-    else hipLaunchKernelGGL(k_sources_field<32>, dim3(nd), dim3(FT), 0, s, D, S, mode);
+    if ((size_t)max_nodes * 8 <= LDS_FIELD_BYTES) {
+        const size_t bytes = (size_t)max(max_nodes, IZQ_CAP) * 8;
+        hipLaunchKernelGGL(k_sources_field_lds, dim3(nd), dim3(FT), bytes, s, D, S, mode, parity);
+        return hipGetLastError();
+    }
+    const int tiles = (max_nodes + FT - 1) / FT;
+#define LAUNCH_SF(T) hipLaunchKernelGGL(k_sources_field<T>, dim3(nd), dim3(FT), 0, s, D, S, mode, parity)
+    if (tiles <= 1) LAUNCH_SF(1);
+    else if (tiles <= 2) LAUNCH_SF(2);
+    else if (tiles <= 3) LAUNCH_SF(3);
+    else if (tiles <= 4) LAUNCH_SF(4);
+    else if (tiles <= 8) LAUNCH_SF(8);
+    else if (tiles <= 12) LAUNCH_SF(12);
+    else if (tiles <= 17) LAUNCH_SF(17);
+    else if (tiles <= 24) LAUNCH_SF(24);
+    else LAUNCH_SF(32);
+#undef LAUNCH_SF
     return hipGetLastError();
 }
 
-extern "C" hipError_t picx_launch_sort(const Diode *D, DiodeState *S, int nd, int ppt, int grid, hipStream_t s)
+// parity: the buffer current before the re-sort
+extern "C" hipError_t picx_launch_sort(const Diode *D, DiodeState *S, int nd, int ppt, int grid, int parity,
+                                       hipStream_t s)
 {
-    PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_sort_count<P_>, dim3(grid), dim3(NT), 0, s, D, S, nd));
+    PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_sort_count<P_>, dim3(grid), dim3(NT), 0, s, D, S, nd, parity));
     hipLaunchKernelGGL(k_sort_scan, dim3(nd * NSP), dim3(1024), 0, s, D);
-    PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_sort_scatter<P_>, dim3(grid), dim3(NT), 0, s, D, S, nd));
+    PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_sort_scatter<P_>, dim3(grid), dim3(NT), 0, s, D, S, nd, parity));
     hipLaunchKernelGGL(k_sort_finalize, dim3(nd), dim3(256), 0, s, D);
     return hipGetLastError();
+}
+
+extern "C" hipError_t picx_prepare(void)
+{
+    return hipFuncSetAttribute((const void *)k_sources_field_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)LDS_FIELD_BYTES);
 }
