@@ -7,7 +7,10 @@ replenishment), Poisson solve and field.  Inputs are resident in HBM before
 the timed region; the metric is live particle-steps per second.
 
 Prints one JSON line.  Options: --gpus (must be 1), --steps, --warmup,
---workload {bench,tiny,large,sweep}, --no-cpu-baseline.
+--workload {large,bench,tiny,sweep} (default large: the 16384-cell,
+16.4M-per-species diode, the one configuration whose per-step working set
+exceeds the 256 MB last-level cache), --no-cpu-baseline.  --copy-probe BYTES
+runs a plain device copy of that size instead (counter calibration).
 """
 import argparse
 import json
@@ -59,9 +62,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--workload", default="bench")
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="large")
+    ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-steps", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -71,11 +76,24 @@ def main():
     import torch
     from paper_2605_07083_amd import pic
 
+    if args.copy_probe:
+        n = args.copy_probe // 4
+        a = torch.empty(n, dtype=torch.float32, device="cuda:0")
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "launches": 3}), flush=True)
+        return
+
     desc, cfgs = workload(args.workload)
     print("bench: workload %s, %d diode(s), warmup %d, steps %d" % (args.workload, len(cfgs), args.warmup,
                                                                     args.steps), file=sys.stderr, flush=True)
     h = pic.Handle(cfgs, device="cuda:0")
     h.step(args.warmup)
+    tune = h.autotune(trial_steps=args.tune_steps) if args.tune_steps > 0 else h.tuning()
+    print("bench: schedule %s" % tune, file=sys.stderr, flush=True)
     h.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -102,7 +120,7 @@ def main():
         "data": "synthetic (seeded Philox load of the stated diode)",
         "config": {"workload": desc, "n_diodes": len(cfgs), "cells": cfgs[0]["N"],
                    "particles_per_species": cfgs[0]["n_load"], "live_particles": live,
-                   "sort_period": h_sort_period(cfgs)},
+                   "schedule": {k: tune[k] for k in ("ppt", "grid", "sort_period", "use_graph")}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_particles", "kernel_ms": r["particle_kernel_ms"],
@@ -112,10 +130,6 @@ def main():
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfgs[0], args.cpu_seconds)
     print(json.dumps(out), flush=True)
-
-
-def h_sort_period(cfgs):
-    return cfgs[0].get("sort_period", 0) or 16
 
 
 if __name__ == "__main__":

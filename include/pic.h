@@ -120,6 +120,18 @@ typedef struct pic_derived {
     int64_t capacity[3];          /* particle slots per species */
 } pic_derived;
 
+/* Steady-state verdict of one diode (see pic_steady_state). */
+typedef struct pic_steady {
+    int32_t steady;            /* 1 if the criterion was met */
+    int32_t blocks;            /* complete blocks examined */
+    int64_t block_steps;       /* steps per block */
+    int64_t steady_step;       /* end step of the first steady block, -1 if none */
+    double backflow_pct;       /* mean backflow ratio of the blocks after it (NaN if none) */
+    int32_t blocks_averaged;   /* how many blocks entered that mean (<= 4) */
+    int32_t pad;
+    double last_backflow_pct;  /* backflow ratio of the last complete block */
+} pic_steady;
+
 typedef struct pic_handle pic_handle;
 
 /* Derived parameters of one configuration ("Model": w0 = n0 dz / N_ppc;
@@ -199,6 +211,32 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
  * these choices.  Synchronises. */
 int pic_set_tuning(pic_handle *h, int ppt, int grid, int sort_period, int use_graph);
 int pic_get_tuning(pic_handle *h, int *ppt, int *grid, int *sort_period, int *use_graph);
+
+/* Choose the launch schedule by timing candidates on the handle's own
+ * diodes (coordinate descent over particles per thread, re-sort period, grid
+ * size and graph replay; each candidate runs whole re-sort periods of at least
+ * trial_steps real steps, so the diodes advance).  Leaves the best schedule
+ * set and returns it with its time per step.  Synchronises. */
+int pic_autotune(pic_handle *h, int64_t trial_steps, int *ppt, int *grid, int *sort_period, int *use_graph,
+                 double *ms_per_step);
+
+/* Late-time steady state ("Benchmark cases": fluxes are averaged over late
+ * intervals in which they fluctuate around stable means; the paper leaves the
+ * interval choice open).  Tallies are grouped in blocks of block_tallies
+ * snapshots; block b is steady when its backflow ratio differs from those of
+ * blocks b-1 and b-2 by less than tol_pp percentage points and its live
+ * particle count from that of block b-1 by less than the fraction tol_rel.
+ * The steady backflow ratio is the mean over the up to four following blocks.
+ * Uses the snapshot ring, so it sees at most 1024 tally periods.  Synchronises. */
+int pic_steady_state(pic_handle *h, int diode, int block_tallies, double tol_pp, double tol_rel,
+                     pic_steady *out);
+
+/* The same criterion on host series of per-block backflow ratios (percent) and
+ * live counts: *steady_block is the first steady block (-1 if none),
+ * *br_steady the mean of up to four following blocks, *n_mean how many.
+ * Host only. */
+int pic_steady_from_series(const double *br, const double *n_live, int nblocks, double tol_pp, double tol_rel,
+                           int *steady_block, double *br_steady, int *n_mean);
 
 /* Message of the last failing call on this thread. */
 const char *pic_last_error(void);

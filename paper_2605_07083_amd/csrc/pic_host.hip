@@ -852,6 +852,138 @@ int pic_get_tuning(pic_handle *h, int *ppt, int *grid, int *sort_period, int *us
     return PIC_OK;
 }
 
+// Launch-schedule autotuner: coordinate descent over particles per thread,
+// re-sort period, grid size and graph replay, each candidate timed with HIP
+// events over whole re-sort periods of real steps (the diodes advance).
+int pic_autotune(pic_handle *h, int64_t trial_steps, int *ppt, int *grid, int *sort_period, int *use_graph,
+                 double *ms_per_step)
+{
+    if (!h || trial_steps < 1) return fail(PIC_EINVAL, "bad arguments");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto timed = [&](int p, int g, int k, int ug, double &ms) -> int {
+        int rc = pic_set_tuning(h, p, g, k, ug);
+        if (rc) return rc;
+        // align to a re-sort boundary and warm the new schedule for one period
+        int64_t pad = (h->sort_period - h->issued % h->sort_period) % h->sort_period;
+        if ((rc = run_steps(h, pad + h->sort_period))) return rc;
+        const int64_t n = std::max<int64_t>(1, (trial_steps + h->sort_period - 1) / h->sort_period) * h->sort_period;
+        HIP_TRY(hipEventRecord(e0, h->stream));
+        if ((rc = run_steps(h, n))) return rc;
+        HIP_TRY(hipEventRecord(e1, h->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        ms = t / (double)n;
+        return PIC_OK;
+    };
+    int bp = h->ppt, bk = h->sort_period, bu = h->use_graph ? 1 : 0;
+    int bg = h->grid;
+    double best = 1e300, ms;
+    int rc;
+    for (int p : {2, 4, 8}) {
+        if ((rc = timed(p, 0, bk, bu, ms))) return rc;
+        if (ms < best) { best = ms; bp = p; bg = h->grid; }
+    }
+    for (int k : {16, 32, 64}) {
+        if ((rc = timed(bp, 0, k, bu, ms))) return rc;
+        if (ms < best * 0.999 || k == bk) {
+            if (ms < best * 0.999) { best = ms; bk = k; }
+        }
+    }
+    for (int g : {256, 512, 1024, 2048}) {
+        if ((rc = timed(bp, g, bk, bu, ms))) return rc;
+        if (ms < best * 0.999) { best = ms; bg = g; }
+    }
+    for (int u : {0, 1}) {
+        if ((rc = timed(bp, bg, bk, u, ms))) return rc;
+        if (ms < best * 0.999) { best = ms; bu = u; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if ((rc = pic_set_tuning(h, bp, bg, bk, bu))) return rc;
+    if (ppt) *ppt = bp;
+    if (grid) *grid = h->grid;
+    if (sort_period) *sort_period = bk;
+    if (use_graph) *use_graph = bu;
+    if (ms_per_step) *ms_per_step = best;
+    return PIC_OK;
+}
+
+int pic_steady_from_series(const double *br, const double *n_live, int nblocks, double tol_pp, double tol_rel,
+                           int *steady_block, double *br_steady, int *n_mean)
+{
+    if (!br || !n_live || nblocks < 0 || !steady_block || !br_steady || !n_mean || !(tol_pp > 0.0) ||
+        !(tol_rel > 0.0))
+        return fail(PIC_EINVAL, "bad arguments");
+    *steady_block = -1;
+    *br_steady = NAN;
+    *n_mean = 0;
+    for (int b = 2; b < nblocks; ++b) {
+        const bool br_ok = std::fabs(br[b] - br[b - 1]) < tol_pp && std::fabs(br[b] - br[b - 2]) < tol_pp;
+        const bool n_ok = n_live[b] > 0.0 && std::fabs(n_live[b] - n_live[b - 1]) / n_live[b] < tol_rel;
+        if (br_ok && n_ok) {
+            *steady_block = b;
+            double acc = 0.0;
+            int m = 0;
+            for (int q = b + 1; q < nblocks && q <= b + 4; ++q, ++m) acc += br[q];
+            *n_mean = m;
+            *br_steady = m ? acc / m : NAN;
+            return PIC_OK;
+        }
+    }
+    return PIC_OK;
+}
+
+int pic_steady_state(pic_handle *h, int diode, int block_tallies, double tol_pp, double tol_rel, pic_steady *out)
+{
+    if (!h || !out || diode < 0 || diode >= h->nd || block_tallies < 1) return fail(PIC_EINVAL, "bad arguments");
+    const pic_config &c = h->cfg[diode];
+    DiodeState st;
+    DiodeTally now;
+    int rc = read_state(h, diode, st, now);
+    if (rc) return rc;
+    std::vector<TallySnap> ring(RING);
+    HIP_TRY(hipMemcpy(ring.data(), h->hD[diode].ring, sizeof(TallySnap) * RING, hipMemcpyDeviceToHost));
+    const int64_t D = c.tally_period, blk = D * block_tallies;
+    const int64_t last = (int64_t)st.step / blk;     // complete blocks
+    const int64_t first = std::max<int64_t>(0, last - (RING / block_tallies) + 1);
+    auto snap = [&](int64_t stepno, DiodeTally &t) -> bool {
+        if (stepno == 0) { std::memset(&t, 0, sizeof(t)); return true; }
+        const TallySnap &sn = ring[(stepno / D) % RING];
+        if ((int64_t)sn.step != stepno) return false;
+        t = sn.t;
+        return true;
+    };
+    std::vector<double> br, nl;
+    int64_t b0 = -1;
+    for (int64_t b = first; b < last; ++b) {
+        DiodeTally ta, tb;
+        if (!snap(b * blk, ta) || !snap((b + 1) * blk, tb)) { br.clear(); nl.clear(); b0 = -1; continue; }
+        if (b0 < 0) b0 = b;
+        const double win = (double)blk * c.dt;
+        const double g_ref = (double)(tb.abs_count[SP_E][0] - ta.abs_count[SP_E][0]) * h->der[diode].w0 / win;
+        br.push_back(c.gamma_emit > 0.0 ? 100.0 * g_ref / c.gamma_emit : 0.0);
+        int64_t live[NSP];
+        live_counts(h, diode, tb, live);
+        nl.push_back((double)(live[0] + live[1] + live[2]));
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->blocks = (int)br.size();
+    out->block_steps = blk;
+    int sb = -1, nm = 0;
+    double bs = NAN;
+    if ((rc = pic_steady_from_series(br.data(), nl.data(), (int)br.size(), tol_pp, tol_rel, &sb, &bs, &nm)))
+        return rc;
+    out->steady = sb >= 0 ? 1 : 0;
+    out->steady_step = sb >= 0 ? (b0 + sb + 1) * blk : -1;
+    out->backflow_pct = bs;
+    out->blocks_averaged = nm;
+    out->last_backflow_pct = br.empty() ? NAN : br.back();
+    return PIC_OK;
+}
+
 void pic_destroy(pic_handle *h) { delete h; }
 
 }  // extern "C"

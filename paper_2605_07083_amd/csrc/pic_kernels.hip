@@ -438,8 +438,11 @@ __device__ __forceinline__ void flush_run(int j, unsigned long long L, unsigned 
     }
 }
 
+#ifndef PIC_PARTICLE_MIN_WAVES
+#define PIC_PARTICLE_MIN_WAVES 1
+#endif
 template <int PPT>
-__global__ __launch_bounds__(NT) void k_particles(const Diode *__restrict__ D, const DiodeState *__restrict__ S,
+__global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const Diode *__restrict__ D, const DiodeState *__restrict__ S,
                                                   int nd, int mode, int parity)
 {
     constexpr int CHUNK = NT * PPT;

@@ -50,6 +50,12 @@ class PicDiag(C.Structure):
                 + [("n_live", C.c_double * 3)])
 
 
+class PicSteady(C.Structure):
+    _fields_ = [("steady", C.c_int32), ("blocks", C.c_int32), ("block_steps", C.c_int64),
+                ("steady_step", C.c_int64), ("backflow_pct", C.c_double), ("blocks_averaged", C.c_int32),
+                ("pad", C.c_int32), ("last_backflow_pct", C.c_double)]
+
+
 class PicDerived(C.Structure):
     _fields_ = [("dz", C.c_double), ("invdz", C.c_double), ("w0", C.c_double),
                 ("numax", C.c_double * 2), ("lam", C.c_double * 2),
@@ -59,7 +65,8 @@ class PicDerived(C.Structure):
 SYMBOLS = ["pic_derive", "pic_workspace_size", "pic_init", "pic_step", "pic_sync", "pic_get_tally",
            "pic_diagnostics", "pic_get_fields", "pic_avg_reset", "pic_get_hist", "pic_get_efield",
            "pic_get_particles", "pic_set_particles", "pic_set_counters", "pic_refield",
-           "pic_step_timed", "pic_set_tuning", "pic_get_tuning", "pic_last_error", "pic_destroy"]
+           "pic_step_timed", "pic_set_tuning", "pic_get_tuning", "pic_autotune", "pic_steady_state", "pic_steady_from_series", "pic_last_error",
+           "pic_destroy"]
 
 _lib = None
 
@@ -92,6 +99,9 @@ def lib():
         "pic_step_timed": ([P, i64, C.POINTER(d), C.POINTER(d), C.POINTER(d)], i),
         "pic_set_tuning": ([P, i, i, i, i], i),
         "pic_get_tuning": ([P, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i)], i),
+        "pic_autotune": ([P, i64, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(d)], i),
+        "pic_steady_state": ([P, i, i, d, d, C.POINTER(PicSteady)], i),
+        "pic_steady_from_series": ([P, P, i, d, d, C.POINTER(i), C.POINTER(d), C.POINTER(i)], i),
         "pic_last_error": ([], C.c_char_p),
         "pic_destroy": ([P], None),
     }
@@ -154,6 +164,17 @@ def pic_workspace_size(cfgs) -> int:
 
 def _ptr(a):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def steady_from_series(br, n_live, tol_pp=1.0, tol_rel=0.01):
+    """Host-only steady-state criterion on per-block series (see pic.h)."""
+    br = np.ascontiguousarray(br, np.float64)
+    nl = np.ascontiguousarray(n_live, np.float64)
+    b, m = C.c_int(), C.c_int()
+    v = C.c_double()
+    _check(lib().pic_steady_from_series(_ptr(br), _ptr(nl), len(br), tol_pp, tol_rel, C.byref(b), C.byref(v),
+                                        C.byref(m)))
+    return {"steady_block": b.value, "backflow_pct": v.value, "blocks_averaged": m.value}
 
 
 class Handle:
@@ -266,6 +287,19 @@ class Handle:
 
     def set_tuning(self, ppt=0, grid=0, sort_period=0, use_graph=-1):
         _check(lib().pic_set_tuning(self.h, int(ppt), int(grid), int(sort_period), int(use_graph)))
+
+    def autotune(self, trial_steps=64):
+        v = [C.c_int() for _ in range(4)]
+        ms = C.c_double()
+        _check(lib().pic_autotune(self.h, int(trial_steps), *[C.byref(x) for x in v], C.byref(ms)))
+        return dict(zip(("ppt", "grid", "sort_period", "use_graph"), [x.value for x in v]), ms_per_step=ms.value)
+
+    def steady_state(self, d=0, block_tallies=50, tol_pp=1.0, tol_rel=0.01):
+        o = PicSteady()
+        _check(lib().pic_steady_state(self.h, d, int(block_tallies), float(tol_pp), float(tol_rel), C.byref(o)))
+        return {"steady": bool(o.steady), "blocks": o.blocks, "block_steps": o.block_steps,
+                "steady_step": o.steady_step, "backflow_pct": o.backflow_pct,
+                "blocks_averaged": o.blocks_averaged, "last_backflow_pct": o.last_backflow_pct}
 
     def tuning(self):
         v = [C.c_int() for _ in range(4)]
