@@ -66,7 +66,7 @@ def main():
     ap.add_argument("--workload", default="large")
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tune-steps", type=int, default=64)
+    ap.add_argument("--tune-steps", type=int, default=192)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -198,9 +198,11 @@ int pic_set_counters(pic_handle *h, int diode, int64_t step, uint32_t next_id);
 /* Re-deposit the current particles and re-solve the field without stepping. */
 int pic_refield(pic_handle *h);
 
-/* Per-kernel timing: run nsteps steps with HIP events around every launch of
- * the particle kernel on the bound stream and return their mean duration (ms)
- * and the mean live-particle count per launch.  Synchronises. */
+/* Per-kernel timing: run nsteps steps on the current schedule with HIP events
+ * around sampled launches of the particle kernel on the bound stream (with
+ * graph replay: the first particle kernel of every replayed re-sort period)
+ * and return their mean duration (ms), the mean live-particle count and the
+ * total time (ms).  Synchronises. */
 int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *mean_live,
                    double *total_ms);
 

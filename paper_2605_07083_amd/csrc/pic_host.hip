@@ -250,10 +250,22 @@ struct pic_handle {
     bool use_graph = true;
     hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
     hipGraphExec_t graph[2] = {nullptr, nullptr};   // re-sort + sort_period steps, per start parity
+    // the same graphs with event-record nodes around the first particle kernel
+    hipGraphExec_t tgraph[2] = {nullptr, nullptr};
+    hipGraph_t tsrc[2] = {nullptr, nullptr};  // kept alive: its node handles address the exec's nodes
+    std::vector<hipGraphNode_t> tnode[2];   // (start, end) per step of the period
+    int tpos[2] = {-1, -1};                 // step whose pair holds pool events
+    hipEvent_t tev[2] = {nullptr, nullptr}; // placeholders recorded by the other steps
     ~pic_handle()
     {
         for (auto g : graph)
             if (g) (void)hipGraphExecDestroy(g);
+        for (auto g : tgraph)
+            if (g) (void)hipGraphExecDestroy(g);
+        for (auto g : tsrc)
+            if (g) (void)hipGraphDestroy(g);
+        for (auto e : tev)
+            if (e) (void)hipEventDestroy(e);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
     std::vector<std::array<int64_t, NSP>> live_offset;
@@ -323,6 +335,77 @@ int ensure_graph(pic_handle *h, int p)
         h->graph[p] = nullptr;
         return fail(PIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
+    return PIC_OK;
+}
+
+// Timed variant of a re-sort period graph.  The captured period is a chain
+// (re-sort kernels, then particle and field kernel per step); event-record
+// nodes are spliced in around every step's particle kernel.  Before each
+// replay one step's pair is pointed at fresh events (the step rotates from
+// replay to replay, so the sample covers the whole period); the other pairs
+// record placeholders.
+int ensure_timed_graph(pic_handle *h, int p)
+{
+    if (h->tgraph[p]) return PIC_OK;
+    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    for (auto &e : h->tev)
+        if (!e) HIP_TRY(hipEventCreate(&e));
+    const int K = h->sort_period;
+    hipGraph_t g;
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_sort(h, h->cap_stream, p);
+    for (int k = 0; rc == PIC_OK && k < K; ++k) rc = enqueue_body(h, h->cap_stream, p ^ 1);
+    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc) return rc;
+    if (e2 != hipSuccess) return fail(PIC_EHIP, "graph capture of the timed period failed");
+    auto bail = [&](const char *m) { (void)hipGraphDestroy(g); return fail(PIC_EHIP, m); };
+    // walk the chain from its root
+    size_t nn = 0;
+    if (hipGraphGetNodes(g, nullptr, &nn) != hipSuccess) return bail("hipGraphGetNodes failed");
+    std::vector<hipGraphNode_t> nodes(nn), chain;
+    if (hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) return bail("hipGraphGetNodes failed");
+    hipGraphNode_t cur = nullptr;
+    for (auto nd : nodes) {
+        size_t nd_in = 0;
+        if (hipGraphNodeGetDependencies(nd, nullptr, &nd_in) != hipSuccess) return bail("dependency query failed");
+        if (nd_in == 0) {
+            if (cur) return bail("captured period is not a chain");
+            cur = nd;
+        }
+    }
+    while (cur) {
+        chain.push_back(cur);
+        size_t nout = 0;
+        if (hipGraphNodeGetDependentNodes(cur, nullptr, &nout) != hipSuccess || nout > 1)
+            return bail("captured period is not a chain");
+        hipGraphNode_t next = nullptr;
+        if (nout == 1 && hipGraphNodeGetDependentNodes(cur, &next, &nout) != hipSuccess)
+            return bail("dependency query failed");
+        cur = nout ? next : nullptr;
+    }
+    if ((int)chain.size() < 2 * K + 1) return bail("unexpected captured period");
+    const int first = (int)chain.size() - 2 * K;      // particle kernel of step 0
+    std::vector<hipGraphNode_t> marks(2 * K);
+    for (int k = 0; k < K; ++k) {
+        hipGraphNode_t pred = chain[first + 2 * k - 1], part = chain[first + 2 * k];
+        hipGraphNode_t field = chain[first + 2 * k + 1];
+        if (hipGraphRemoveDependencies(g, &pred, &part, 1) != hipSuccess ||
+            hipGraphRemoveDependencies(g, &part, &field, 1) != hipSuccess ||
+            hipGraphAddEventRecordNode(&marks[2 * k], g, &pred, 1, h->tev[0]) != hipSuccess ||
+            hipGraphAddDependencies(g, &marks[2 * k], &part, 1) != hipSuccess ||
+            hipGraphAddEventRecordNode(&marks[2 * k + 1], g, &part, 1, h->tev[1]) != hipSuccess ||
+            hipGraphAddDependencies(g, &marks[2 * k + 1], &field, 1) != hipSuccess)
+            return bail("splicing event nodes failed");
+    }
+    hipError_t e = hipGraphInstantiate(&h->tgraph[p], g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        h->tgraph[p] = nullptr;
+        return fail(PIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    h->tsrc[p] = g;
+    h->tnode[p] = marks;
+    h->tpos[p] = -1;
     return PIC_OK;
 }
 
@@ -754,40 +837,68 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
 {
     if (!h || nsteps < 1) return fail(PIC_EINVAL, "bad arguments");
     const int64_t every = std::max<int64_t>(1, nsteps / 512);
-    const int64_t nev = (nsteps + every - 1) / every;
+    const int64_t nev = nsteps / std::max<int64_t>(1, std::min<int64_t>(every, h->sort_period)) + 2;
     std::vector<hipEvent_t> ev(2 * nev);
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     hipEvent_t t0, t1;
     HIP_TRY(hipEventCreate(&t0));
     HIP_TRY(hipEventCreate(&t1));
-    int64_t live0[NSP], live1[NSP];
-    {
+    auto live_sum = [&](int64_t out[NSP]) -> int {
         DiodeState st;
         DiodeTally t;
-        int64_t sum[NSP] = {0, 0, 0};
+        int64_t sum[NSP] = {0, 0, 0}, l[NSP];
         for (int d = 0; d < h->nd; ++d) {
             int rc = read_state(h, d, st, t);
             if (rc) return rc;
-            live_counts(h, d, t, live0);
-            for (int s = 0; s < NSP; ++s) sum[s] += live0[s];
+            live_counts(h, d, t, l);
+            for (int s = 0; s < NSP; ++s) sum[s] += l[s];
         }
-        std::copy(sum, sum + NSP, live0);
-    }
+        std::copy(sum, sum + NSP, out);
+        return PIC_OK;
+    };
+    int64_t live0[NSP], live1[NSP];
+    int rc = live_sum(live0);
+    if (rc) return rc;
     HIP_TRY(hipEventRecord(t0, h->stream));
-    int64_t k_ev = 0;
-    for (int64_t k = 0; k < nsteps; ++k) {
+    int64_t k_ev = 0, left = nsteps, k = 0;
+    while (left > 0) {
+        if (h->use_graph && h->sort_period > 1 && !h->sort_next && h->issued % h->sort_period == 0 &&
+            left >= h->sort_period && k_ev < nev) {
+            // one re-sort period replayed from its graph, first particle kernel timed
+            const int p = h->parity;
+            if ((rc = ensure_timed_graph(h, p))) return rc;
+            const int pos = (int)(k_ev % h->sort_period);
+            if (h->tpos[p] >= 0) {
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * h->tpos[p]], h->tev[0]));
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * h->tpos[p] + 1], h->tev[1]));
+            }
+            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos], ev[2 * k_ev]));
+            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos + 1], ev[2 * k_ev + 1]));
+            h->tpos[p] = pos;
+            HIP_TRY(hipGraphLaunch(h->tgraph[p], h->stream));
+            ++k_ev;
+            h->parity ^= 1;
+            h->issued += h->sort_period;
+            left -= h->sort_period;
+            k += h->sort_period;
+            continue;
+        }
         if (sort_due(h)) {
-            int rc = enqueue_sort(h, h->stream, h->parity);
-            if (rc) return rc;
+            if ((rc = enqueue_sort(h, h->stream, h->parity))) return rc;
             h->parity ^= 1;
             h->sort_next = false;
         }
-        const bool rec = (k % every) == 0 && k_ev < nev;
+        const bool rec = !h->use_graph && (k % every) == 0 && k_ev < nev;
         if (rec) HIP_TRY(hipEventRecord(ev[2 * k_ev], h->stream));
         HIP_TRY(picx_launch_particles(h->dD, h->dS, h->nd, 0, h->ppt, h->grid, h->parity, h->stream));
-        if (rec) { HIP_TRY(hipEventRecord(ev[2 * k_ev + 1], h->stream)); ++k_ev; }
+        if (rec) {
+            HIP_TRY(hipEventRecord(ev[2 * k_ev + 1], h->stream));
+            ++k_ev;
+        }
         HIP_TRY(picx_launch_sources_field(h->dD, h->dS, h->nd, 0, h->max_nodes, h->parity, h->stream));
         h->issued++;
+        --left;
+        ++k;
     }
     HIP_TRY(hipEventRecord(t1, h->stream));
     HIP_TRY(hipEventSynchronize(t1));
@@ -799,22 +910,11 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
     }
     float tot = 0.f;
     HIP_TRY(hipEventElapsedTime(&tot, t0, t1));
-    {
-        DiodeState st;
-        DiodeTally t;
-        int64_t sum[NSP] = {0, 0, 0};
-        for (int d = 0; d < h->nd; ++d) {
-            int rc = read_state(h, d, st, t);
-            if (rc) return rc;
-            live_counts(h, d, t, live1);
-            for (int s = 0; s < NSP; ++s) sum[s] += live1[s];
-        }
-        std::copy(sum, sum + NSP, live1);
-    }
-    for (auto &e : ev) hipEventDestroy(e);
-    hipEventDestroy(t0);
-    hipEventDestroy(t1);
-    if (particle_kernel_ms) *particle_kernel_ms = acc / (double)k_ev;
+    if ((rc = live_sum(live1))) return rc;
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (particle_kernel_ms) *particle_kernel_ms = k_ev ? acc / (double)k_ev : NAN;
     if (mean_live) {
         double a = 0, b = 0;
         for (int s = 0; s < NSP; ++s) { a += live0[s]; b += live1[s]; }
@@ -837,6 +937,16 @@ int pic_set_tuning(pic_handle *h, int ppt, int grid, int sort_period, int use_gr
     for (auto &g : h->graph)
         if (g) {
             (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    for (auto &g : h->tgraph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    for (auto &g : h->tsrc)
+        if (g) {
+            (void)hipGraphDestroy(g);
             g = nullptr;
         }
     return PIC_OK;

@@ -202,3 +202,26 @@ def test_time_average_fields(pic):
     avg = h.fields(0, time_avg=True)
     for k in acc:
         assert np.allclose(avg[k], acc[k] / 8, rtol=1e-12, atol=1e-9 * np.abs(acc[k]).max())
+
+
+def test_autotune_keeps_parity(pic, O):
+    cfg = presets.scaled(presets.bench(), n_load=204800)
+    _say("case: autotune then restart parity")
+    h = pic.Handle(cfg)
+    h.step(10)
+    t = h.autotune(trial_steps=16)
+    assert t["ppt"] in (2, 4, 8) and t["sort_period"] in (16, 32, 64) and t["ms_per_step"] > 0
+    probs = restart_step_check(O, cfg, h, 3)
+    assert probs == [], "\n".join(probs[:20])
+
+
+def test_steady_state_on_device(pic):
+    cfg = presets.scaled(presets.tiny(), gamma_emit=2e21, tally_period=10)
+    _say("case: steady-state detector on device tallies")
+    h = pic.Handle(cfg)
+    h.step(3000)
+    st = h.steady_state(0, block_tallies=20, tol_pp=5.0, tol_rel=0.05)
+    assert st["blocks"] == 3000 // 200
+    assert st["block_steps"] == 200
+    if st["steady"]:
+        assert st["steady_step"] % 200 == 0 and st["steady_step"] <= 3000
