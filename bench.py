@@ -23,6 +23,23 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_PARTICLE_STEP = 28      # z r/w 16 B + v_z r/w 8 B + free-flight counter read 4 B
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_particles_large_diode_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2605_07083_amd", "csrc", "pic_kernels.hip")
+
+
+def measured_traffic():
+    """Counter-measured HBM bytes per particle-kernel launch of the large diode,
+    if the committed profile was taken with the current kernel source."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(ln.split(": ", 1) for ln in text.splitlines() if ln.startswith(("traffic_bytes", "source_sha")))
+    if fields.get("source_sha256", "").strip() != src:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def workload(name):
@@ -122,7 +139,10 @@ def main():
                    "particles_per_species": cfgs[0]["n_load"], "live_particles": live,
                    "schedule": {k: tune[k] for k in ("ppt", "grid", "sort_period", "use_graph")}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if args.workload == "large" else None,
+                     "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes_per_launch": BYTES_PER_PARTICLE_STEP * live,
                      "kernel": "k_particles", "kernel_ms": r["particle_kernel_ms"],
                      "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP},
     }
