@@ -59,6 +59,8 @@ def lib():
         for f in ("o_load", "o_step", "o_refield"):
             getattr(L, f).argtypes = [P]
             getattr(L, f).restype = C.c_int
+        L.o_load_profiles.argtypes = [P, P, P]
+        L.o_load_profiles.restype = C.c_int
         L.o_count.argtypes = [P, C.c_int]
         L.o_count.restype = i64
         L.o_stepno.argtypes = [P]
@@ -183,6 +185,17 @@ class Sim:
     def load(self):
         if lib().o_load(self.h) != 0:
             raise RuntimeError("oracle load failed")
+
+    def load_profiles(self, ne, ni):
+        """Warm start from cell-centre densities (N values each, m^-3)."""
+        ne = np.ascontiguousarray(ne, dtype=np.float64)
+        ni = np.ascontiguousarray(ni, dtype=np.float64)
+        assert ne.shape == (self.N,) and ni.shape == (self.N,)
+        rc = lib().o_load_profiles(self.h, _ptr(ne), _ptr(ni))
+        if rc == -2:
+            raise ValueError("oracle: negative or non-finite density")
+        if rc != 0:
+            raise RuntimeError("oracle profile load failed")
 
     def step(self, n=1):
         for _ in range(n):

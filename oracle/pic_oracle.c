@@ -36,7 +36,7 @@
 #define TWO32 4294967296.0
 #define PI_D 3.14159265358979323846
 
-enum { EV_COLL = 1, EV_LOAD = 2, EV_EMIT = 3, EV_BIRTH = 4 };
+enum { EV_COLL = 1, EV_LOAD = 2, EV_EMIT = 3, EV_BIRTH = 4, EV_PROFILE = 5 };
 #define LOAD_STEP 0xFFFFFFFFu
 #define NEVER 0xFFFFFFFFu
 
@@ -439,6 +439,54 @@ int o_load(osim *o)
             uint32_t tc = next_candidate(0u, lam, b1[2], b1[3]);
             if (tc != NEVER) tc -= 1u;
             sp_push(&o->sp[s], z, sig * n1, sig * n2, sig * n3, id, tc);
+        }
+    }
+    o->next_id = id;
+    return o_refield(o);
+}
+
+/* Warm start from density profiles (a loaded state whose densities follow
+ * given n_e(z), n_i(z) at the N cell centres instead of the uniform n0).
+ * Cell j of species q (0: electrons, 1: ions) receives floor(x) particles
+ * plus one with probability frac(x), x = n_q[j] dz / w0; the Bernoulli draw
+ * is keyed by the cell: key (j, seed ^ diode), counter (LOAD, PROFILE, q, 0).
+ * Ids run over the electron cells in order, then the ion cells.  Each
+ * particle then draws exactly as in the uniform load, except that its
+ * position is uniform inside its cell: z = (j + U) dz. */
+int o_load_profiles(osim *o, const double *ne, const double *ni)
+{
+    const ocfg *c = &o->c;
+    for (int s = 0; s < ONSP; ++s) o->sp[s].n = 0;
+    memset(&o->t, 0, sizeof(o->t));
+    o->step = 0;
+    uint32_t id = 0;
+    const int load_sp[2] = {OSP_P, OSP_I};
+    for (int q = 0; q < 2; ++q) {
+        const int s = load_sp[q];
+        const double *dens = q == 0 ? ne : ni;
+        const double T = (s == OSP_I) ? c->Ti0 : c->Te0;
+        const double sig = sqrt(Q_E * T / o->d.mass[s]);
+        const double lam = o->d.lam[s == OSP_I ? 1 : 0];
+        for (int32_t j = 0; j < c->N; ++j) {
+            const double x = dens[j] * o->d.dz / o->d.w0;
+            if (!(x >= 0.0) || x > 1073741824.0) return -2;
+            const double fl = floor(x);
+            uint32_t bc[4];
+            draw((uint32_t)j, kseed(o), LOAD_STEP, EV_PROFILE, (uint32_t)q, bc);
+            const int64_t cnt = (int64_t)fl + (o_u53(bc[0], bc[1]) < x - fl ? 1 : 0);
+            if (sp_reserve(&o->sp[s], o->sp[s].n + cnt)) return -1;
+            for (int64_t p = 0; p < cnt; ++p, ++id) {
+                uint32_t b0[4], b1[4];
+                draw(id, kseed(o), LOAD_STEP, EV_LOAD, 0, b0);
+                draw(id, kseed(o), LOAD_STEP, EV_LOAD, 1, b1);
+                double n1, n2, n3, n4;
+                normal_pair32(b0[0], b0[1], &n1, &n2);
+                normal_pair32(b0[2], b0[3], &n3, &n4);
+                const double z = ((double)j + o_u53(b1[0], b1[1])) * o->d.dz;
+                uint32_t tc = next_candidate(0u, lam, b1[2], b1[3]);
+                if (tc != NEVER) tc -= 1u;
+                sp_push(&o->sp[s], z, sig * n1, sig * n2, sig * n3, id, tc);
+            }
         }
     }
     o->next_id = id;

@@ -80,6 +80,9 @@ void o_efield(int32_t N, double dz, const double *phi, double *E);
 osim *o_create(const ocfg *c);
 void o_destroy(osim *o);
 int o_load(osim *o);
+/* Load from cell-centre densities n_e, n_i (N values each, m^-3); -2 on a
+ * negative or non-finite density. */
+int o_load_profiles(osim *o, const double *ne, const double *ni);
 int o_step(osim *o);
 int o_refield(osim *o);
 int64_t o_count(const osim *o, int sp);

@@ -97,5 +97,20 @@ def surrogate_params(n, seed):
                 V=rng.uniform(5.0, 20.0, n), ng=rng.uniform(1e21, 1e22, n))
 
 
-__all__ = ["tiny", "bench", "sweep", "large", "paper", "scaled", "surrogate_params",
+SURROGATE_LAYERS = [(16, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 3)]
+
+
+def surrogate_test_weights(seed, scale=1.0):
+    """Seeded FP32 weights W_l [Cout][Cin][5] ~ N(0, scale^2 / (5 Cin)) and
+    biases ~ N(0, 0.01^2) for the six surrogate layers (test inputs)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    W, b = [], []
+    for cin, cout in SURROGATE_LAYERS:
+        W.append((scale * rng.normal(0.0, math.sqrt(1.0 / (5 * cin)), (cout, cin, 5))).astype(np.float32))
+        b.append(rng.normal(0.0, 0.01, cout).astype(np.float32))
+    return W, b
+
+
+__all__ = ["tiny", "bench", "sweep", "large", "paper", "scaled", "surrogate_params", "surrogate_test_weights", "SURROGATE_LAYERS",
            "KB_OVER_E", "CH_ALL", "CH_EEL", "CH_EXC", "CH_IZ", "CH_CX", "CH_IEL", "math"]
