@@ -149,6 +149,22 @@ int pic_workspace_size(const pic_config *cfgs, int n_diodes, size_t *bytes);
 int pic_init(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes,
              void *hip_stream, pic_handle **out);
 
+/* Warm start: as pic_init, but the particles follow given densities instead
+ * of the uniform n0 (the loaded state of "Model" with n(z) in place of n0).
+ * dev_dens is a device array [n_diodes][2][Nmax] of doubles (m^-3): row 0 the
+ * electron density, row 1 the ion density at the N cell centres of each diode
+ * (Nmax = the largest N; shorter rows are padded and ignored).  Cell c of a
+ * species receives floor(x) particles plus one with probability frac(x),
+ * x = n_c dz / w0 (w0 from the configuration as in pic_init), drawn from
+ * Philox keyed by the cell; positions are uniform in the cell, velocities
+ * Maxwellian at Te0 / Ti0, electrons join the plasma population, ids run over
+ * the electron cells then the ion cells.  The array is read before return
+ * (the call synchronises the stream).  PIC_ENAN for a negative or non-finite
+ * density, PIC_ENOSPACE when a species exceeds its capacity
+ * (capacity_factor x n_load). */
+int pic_init_from_profiles(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes,
+                           void *hip_stream, const double *dev_dens, pic_handle **out);
+
 /* Advance every diode nsteps steps.  Asynchronous on the bound stream. */
 int pic_step(pic_handle *h, int64_t nsteps);
 
@@ -171,6 +187,11 @@ int pic_get_fields(pic_handle *h, int diode, double *phi, double *n_e, double *n
 
 /* Start (on != 0) or stop time averaging of phi and densities. */
 int pic_avg_reset(pic_handle *h, int on);
+
+/* The same for one diode (diode = -1: all): clears its sums and sets its
+ * averaging flag, leaving the other diodes' averages untouched.  Lets each
+ * diode of a batch average over its own late-time window.  Synchronises. */
+int pic_avg_control(pic_handle *h, int diode, int on);
 
 /* Raw per-species fixed-point deposit of the last step (N+1 int64; a particle
  * deposits 2^32 in total).  Synchronises. */

@@ -1,0 +1,100 @@
+/* surrogate.h -- C ABI of the learned warm start (libpic.so).
+ *
+ * A surrogate maps the four quantities the paper varies or fixes per run --
+ * emission flux Gamma ("Benchmark cases", Table 2), cathode temperature T_c,
+ * bias V and neutral density n_g ("Model", "Emission and collisions") -- to
+ * the late-time profiles it reports ("Results": time-averaged potential and
+ * densities) on X cell centres:
+ *     out[b][0][x] = phi / V,  out[b][1][x] = ln(n_e / n0),  out[b][2][x] = ln(n_i / n0).
+ * The profiles seed pic_init_from_profiles so that a run starts near its late
+ * state.  The paper has no surrogate; the network is a reading: six 1D
+ * convolutions (kernel 5, zero padding 2) with channels 16 -> 64 (x5) -> 3
+ * and tanh between layers, on bfloat16 weights and activations with FP32
+ * accumulation (gfx950 matrix cores), trained by mean squared error with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8) on FP32 master weights.
+ *
+ * Input channels: the parameters mapped to [-1, 1] over Gamma in
+ * [1e19, 1.2e20] m^-2 s^-1 (log), T_c in [1800, 2200] K, V in [5, 20] V,
+ * n_g in [1e21, 1e22] m^-3 (log), and 12 functions of the position
+ * u = (x + 1/2) / X: 2u - 1, 1 - 2u, sin / cos of (pi, 2 pi, 4 pi) u,
+ * exp(-64 u), exp(-64 (1 - u)), exp(-16 u), exp(-16 (1 - u)).
+ *
+ * Packed weights (host arrays, FP32): layer by layer, W_l[co][ci][t] (t the
+ * kernel tap, y[x] += W[co][ci][t] a[ci][x + t - 2]) -- SUR_WEIGHTS values --
+ * and the biases b_l[co] -- SUR_BIASES values.
+ *
+ * Ownership: the caller owns the device workspace and the stream; the
+ * library owns the host-side handle.  Errors: every call returns 0 or a
+ * negative PIC_* code (pic.h); sur_last_error() has the message.  Calls on a
+ * handle are asynchronous on its stream unless they say otherwise.
+ */
+#ifndef PAPER_2605_07083_SURROGATE_H
+#define PAPER_2605_07083_SURROGATE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SUR_LAYERS 6
+#define SUR_IN 16
+#define SUR_HIDDEN 64
+#define SUR_OUT 3
+#define SUR_KS 5
+#define SUR_WEIGHTS 88000   /* 64*16*5 + 4*64*64*5 + 3*64*5 */
+#define SUR_BIASES 323      /* 5*64 + 3 */
+
+typedef struct sur_net sur_net;
+
+/* Device workspace for batches of up to max_batch samples of `cells`
+ * positions (cells a positive multiple of 64). */
+int sur_workspace_size(int max_batch, int cells, size_t *bytes);
+
+/* Create a network over a caller-owned workspace (256-byte aligned) bound to
+ * hip_stream.  Weights start N(0, 1/(5 C_in)) from Philox keyed by seed,
+ * biases 0, Adam moments 0. */
+int sur_create(int max_batch, int cells, void *dev_workspace, size_t bytes, void *hip_stream, uint32_t seed,
+               sur_net **out);
+
+/* Replace the master weights (host arrays, packed as above) and reset the Adam
+ * moments and step count.  Synchronises. */
+int sur_set_weights(sur_net *n, const float *w, const float *b);
+
+/* Copy the master weights out (packed).  Synchronises. */
+int sur_get_weights(sur_net *n, float *w, float *b);
+
+/* Gradients of the mean squared error from the last sur_train_step (packed).
+ * Synchronises. */
+int sur_get_grads(sur_net *n, float *w, float *b);
+
+/* Forward pass.  dev_params [batch][4] = (Gamma, T_c K, V, n_g) FP32 on the
+ * device; dev_out [batch][3][cells] FP32 on the device. */
+int sur_forward(sur_net *n, const float *dev_params, int batch, float *dev_out);
+
+/* One training step on a batch: forward, loss = mean over (b, c, x) of
+ * (out - target)^2, backward (input and weight gradients on the matrix
+ * cores; the gradient entering each layer rounded to bfloat16), one Adam
+ * update of every master weight and bias, re-quantisation to bfloat16.
+ * dev_target [batch][3][cells] FP32.  If loss != NULL the call synchronises
+ * and stores the loss of this batch before the update. */
+int sur_train_step(sur_net *n, const float *dev_params, const float *dev_target, int batch, float lr,
+                   double *loss);
+
+/* Forward pass converted to the warm-start loader's input: dev_dens
+ * [batch][2][cells] doubles, n0[b] exp(out[b][1]) and n0[b] exp(out[b][2]);
+ * dev_n0 [batch] doubles on the device. */
+int sur_densities(sur_net *n, const float *dev_params, const double *dev_n0, int batch, double *dev_dens);
+
+/* Message of the last failing surrogate call on this thread. */
+const char *sur_last_error(void);
+
+/* Release the handle (not the caller's workspace or stream). */
+void sur_destroy(sur_net *n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic.so")
-SOURCES = ["pic_kernels.hip", "pic_host.hip"]
+SOURCES = ["pic_kernels.hip", "pic_host.hip", "surrogate_kernels.hip", "surrogate_host.hip"]
 ARCH = os.environ.get("PIC_OFFLOAD_ARCH", "gfx950")
 
 

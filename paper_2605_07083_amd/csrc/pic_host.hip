@@ -29,6 +29,8 @@ extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int n
 extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
                                                 int parity, hipStream_t s);
 extern "C" hipError_t picx_prepare(void);
+extern "C" hipError_t picx_launch_profile_load(const Diode *D, const double *dens, int nd, int max_cells,
+                                               hipStream_t s);
 extern "C" hipError_t picx_launch_sort(const Diode *D, DiodeState *S, int nd, int ppt, int grid, int parity,
                                        hipStream_t s);
 
@@ -537,8 +539,10 @@ int pic_workspace_size(const pic_config *cfgs, int n_diodes, size_t *bytes)
     return PIC_OK;
 }
 
-int pic_init(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes, void *hip_stream,
-             pic_handle **out)
+// dens == nullptr: uniform load; else the warm-start loader over dens
+// [n_diodes][2][max N] (device).
+static int init_impl(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes, void *hip_stream,
+                     const double *dens, pic_handle **out)
 {
     if (!cfgs || !out || !dev_workspace || n_diodes < 1 || n_diodes > PIC_MAX_DIODES)
         return fail(PIC_EINVAL, "bad arguments");
@@ -587,14 +591,52 @@ int pic_init(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t b
         hipMemcpyAsync(h->dNload, nl.data(), sizeof(long long) * n_diodes, hipMemcpyHostToDevice, h->stream) ||
         hipMemcpyAsync(h->hD[0].st, st.data(), sizeof(DiodeState) * n_diodes, hipMemcpyHostToDevice, h->stream))
         return cleanup(fail(PIC_EHIP, "hipMemcpyAsync failed"));
-    if (picx_launch_load(h->dD, h->dNload, n_diodes, maxl, h->stream) != hipSuccess)
-        return cleanup(fail(PIC_EHIP, "load launch failed"));
+    if (!dens) {
+        if (picx_launch_load(h->dD, h->dNload, n_diodes, maxl, h->stream) != hipSuccess)
+            return cleanup(fail(PIC_EHIP, "load launch failed"));
+    } else {
+        int max_cells = 0;
+        for (int d = 0; d < n_diodes; ++d) max_cells = std::max(max_cells, cfgs[d].N);
+        if (picx_launch_profile_load(h->dD, dens, n_diodes, max_cells, h->stream) != hipSuccess)
+            return cleanup(fail(PIC_EHIP, "profile load launch failed"));
+    }
     // the staging vectors die here: wait for the copies
     if (hipStreamSynchronize(h->stream) != hipSuccess) return cleanup(fail(PIC_EHIP, "sync failed"));
+    if (dens) {
+        for (int d = 0; d < n_diodes; ++d) {
+            DiodeState sd;
+            if (hipMemcpy(&sd, h->hD[d].st, sizeof(sd), hipMemcpyDeviceToHost) != hipSuccess)
+                return cleanup(fail(PIC_EHIP, "state read failed"));
+            const uint32_t err = sd.err;
+            // live counts are births minus losses from n_load: offset by what was loaded
+            h->live_offset[d][SP_P] = (int64_t)sd.n[SP_P] - cfgs[d].n_load;
+            h->live_offset[d][SP_I] = (int64_t)sd.n[SP_I] - cfgs[d].n_load;
+            if (err & ERR_NAN)
+                return cleanup(fail(PIC_ENAN, "diode " + std::to_string(d) +
+                                                  ": density profile negative, not finite or above 2^30 per cell"));
+            if (err & ERR_CAPACITY)
+                return cleanup(fail(PIC_ENOSPACE, "diode " + std::to_string(d) +
+                                                      ": profile holds more particles than the capacity "
+                                                      "(raise capacity_factor or n_load)"));
+        }
+    }
     rc = refield(h);
     if (rc) return cleanup(rc);
     *out = h;
     return PIC_OK;
+}
+
+int pic_init(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes, void *hip_stream,
+             pic_handle **out)
+{
+    return init_impl(cfgs, n_diodes, dev_workspace, bytes, hip_stream, nullptr, out);
+}
+
+int pic_init_from_profiles(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes,
+                           void *hip_stream, const double *dev_dens, pic_handle **out)
+{
+    if (!dev_dens) return fail(PIC_EINVAL, "null density profiles");
+    return init_impl(cfgs, n_diodes, dev_workspace, bytes, hip_stream, dev_dens, out);
 }
 
 int pic_step(pic_handle *h, int64_t nsteps)
@@ -681,11 +723,14 @@ int pic_diagnostics(pic_handle *h, int diode, int64_t window_steps, pic_diag *ou
     return err_code(st.err);
 }
 
-int pic_avg_reset(pic_handle *h, int on)
+int pic_avg_reset(pic_handle *h, int on) { return pic_avg_control(h, -1, on); }
+
+int pic_avg_control(pic_handle *h, int diode, int on)
 {
-    if (!h) return fail(PIC_EINVAL, "null handle");
+    if (!h || diode < -1 || diode >= h->nd) return fail(PIC_EINVAL, "bad arguments");
     HIP_TRY(hipStreamSynchronize(h->stream));
     for (int d = 0; d < h->nd; ++d) {
+        if (diode >= 0 && d != diode) continue;
         const Diode &D = h->hD[d];
         const size_t nn = h->cfg[d].N + 1;
         for (int s = 0; s < NSP; ++s) HIP_TRY(hipMemsetAsync(D.Hsum[s], 0, nn * sizeof(long long), h->stream));

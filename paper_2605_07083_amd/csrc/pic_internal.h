@@ -19,7 +19,7 @@ constexpr int NSP = 3;
 constexpr int SP_P = 0, SP_E = 1, SP_I = 2;
 constexpr int NCH = 5;
 constexpr int CH_EEL = 0, CH_EXC = 1, CH_IZ = 2, CH_CX = 3, CH_IEL = 4;
-constexpr uint32_t EV_COLL = 1, EV_LOAD = 2, EV_EMIT = 3, EV_BIRTH = 4;
+constexpr uint32_t EV_COLL = 1, EV_LOAD = 2, EV_EMIT = 3, EV_BIRTH = 4, EV_PROFILE = 5;
 constexpr uint32_t LOAD_STEP = 0xFFFFFFFFu;
 constexpr uint32_t NEVER = 0xFFFFFFFFu;
 constexpr int RING = 1024;           // tally snapshots kept per diode

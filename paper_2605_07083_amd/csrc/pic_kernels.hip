@@ -648,6 +648,123 @@ __global__ __launch_bounds__(256) void k_load(const Diode *__restrict__ D, const
 }
 
 // ---------------------------------------------------------------------------
+// Warm start from cell-centre density profiles.  dens[d][q][c] (q = 0
+// electrons, 1 ions; rows of max_cells doubles).  Cell c of species q holds
+// floor(x) particles plus one with probability frac(x), x = n dz / w0, the
+// Bernoulli draw keyed by the cell.  One block per diode writes the exclusive
+// cell offsets (N + 1 entries) into the re-sort's count array, the live
+// counts and the next id; errors are sticky bits that skip the fill.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_profile_count(const Diode *__restrict__ D, const double *__restrict__ dens,
+                                                        int max_cells)
+{
+    const Diode &dd = D[blockIdx.x];
+    const int N = dd.N, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    __shared__ long long wsum[16];
+    __shared__ long long base_s;
+    __shared__ int bad;
+    if (tid == 0) bad = 0;
+    long long tot[2];
+    for (int q = 0; q < 2; ++q) {
+        const int s = q == 0 ? SP_P : SP_I;
+        const double *n = dens + ((size_t)blockIdx.x * 2 + q) * max_cells;
+        int *off = dd.cell_cnt[s];
+        if (tid == 0) base_s = 0;
+        __syncthreads();
+        for (int c0 = 0; c0 < N; c0 += 1024) {
+            const int c = c0 + tid;
+            long long cnt = 0;
+            if (c < N) {
+                const double x = n[c] * dd.dz / dd.w0;
+                if (!(x >= 0.0) || x > 1073741824.0) {
+                    bad = 1;
+                } else {
+                    const double fl = floor(x);
+                    const uint4 r = philox(LOAD_STEP, EV_PROFILE, (uint32_t)q, 0u, (uint32_t)c, dd.kseed);
+                    cnt = (long long)fl + (u53(r.x, r.y) < x - fl ? 1 : 0);
+                }
+            }
+            long long inc = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const long long t = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += t;
+            }
+            if (lane == 63) wsum[w] = inc;
+            __syncthreads();
+            long long wb = base_s;
+            for (int k = 0; k < w; ++k) wb += wsum[k];
+            const long long excl = wb + inc - cnt;
+            if (c < N) off[c] = (int)min(excl, 0x7FFFFFFFll);
+            __syncthreads();
+            if (tid == 1023) base_s = excl + cnt;
+            __syncthreads();
+        }
+        tot[q] = base_s;
+        if (tid == 0) off[N] = (int)min(base_s, 0x7FFFFFFFll);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        DiodeState *st = dd.st;
+        uint32_t err = 0;
+        if (bad) err |= ERR_NAN;
+        if (tot[0] > dd.cap[SP_P] || tot[1] > dd.cap[SP_I] || tot[0] + tot[1] > 0xFFFF0000ll) err |= ERR_CAPACITY;
+        st->n[SP_E] = 0;
+        if (err) {
+            st->err |= err;
+            st->n[SP_P] = st->n[SP_I] = 0;
+            st->next_id = 0;
+        } else {
+            st->n[SP_P] = (int32_t)tot[0];
+            st->n[SP_I] = (int32_t)tot[1];
+            st->next_id = (uint32_t)(tot[0] + tot[1]);
+        }
+    }
+}
+
+// One wave per (cell, species): the cell's particles, drawn exactly as in the
+// uniform load (keyed by id) except for the position, uniform in the cell.
+__global__ __launch_bounds__(256) void k_profile_fill(const Diode *__restrict__ D)
+{
+    const Diode &dd = D[blockIdx.y];
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int s = blockIdx.z == 0 ? SP_P : SP_I;
+    if (c >= dd.N || dd.st->err) return;
+    const int *off = dd.cell_cnt[s];
+    const int a = off[c], e = off[c + 1];
+    const uint32_t id0 = s == SP_P ? 0u : (uint32_t)dd.cell_cnt[SP_P][dd.N];
+    const double sig = s == SP_P ? dd.sig_e0 : dd.sig_i0;
+    const double lam = dd.lam[s == SP_I];
+    const SpeciesBuf b = dd.buf[0][s];
+    for (int i = a + lane; i < e; i += 64) {
+        const uint32_t id = id0 + (uint32_t)i;
+        const uint4 b0 = philox(LOAD_STEP, EV_LOAD, 0u, 0u, id, dd.kseed);
+        const uint4 b1 = philox(LOAD_STEP, EV_LOAD, 1u, 0u, id, dd.kseed);
+        double n1, n2, n3, n4;
+        bm32(b0.x, b0.y, n1, n2);
+        bm32(b0.z, b0.w, n3, n4);
+        b.z[i] = ((double)c + u53(b1.x, b1.y)) * dd.dz;
+        b.vx[i] = (float)(sig * n1);
+        b.vy[i] = (float)(sig * n2);
+        b.vz[i] = (float)(sig * n3);
+        b.id[i] = id;
+        uint32_t tc = next_candidate(0u, lam, b1.z, b1.w);
+        if (tc != NEVER) tc -= 1u;
+        b.tc[i] = tc;
+    }
+}
+
+// The re-sort expects its count array zeroed.
+__global__ __launch_bounds__(256) void k_profile_clear(const Diode *__restrict__ D)
+{
+    const Diode &dd = D[blockIdx.x];
+    for (int j = threadIdx.x; j <= dd.N; j += 256) {
+        dd.cell_cnt[SP_P][j] = 0;
+        dd.cell_cnt[SP_I][j] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Cell re-sort: count -> scan -> scatter -> finalize (compacts holes too).
 // ---------------------------------------------------------------------------
 // Window of a run of chunks for the re-sort: cells of its first and last
@@ -1440,6 +1557,16 @@ extern "C" hipError_t picx_launch_load(const Diode *D, const long long *n_load, 
     if (max_load <= 0) return hipSuccess;
     dim3 grid((unsigned)((max_load + 255) / 256), nd, 2);
     hipLaunchKernelGGL(k_load, grid, dim3(256), 0, s, D, n_load);
+    return hipGetLastError();
+}
+
+// max_cells: the largest N over the diodes (row length of dens)
+extern "C" hipError_t picx_launch_profile_load(const Diode *D, const double *dens, int nd, int max_cells,
+                                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_profile_count, dim3(nd), dim3(1024), 0, s, D, dens, max_cells);
+    hipLaunchKernelGGL(k_profile_fill, dim3((max_cells + 3) / 4, nd, 2), dim3(256), 0, s, D);
+    hipLaunchKernelGGL(k_profile_clear, dim3(nd), dim3(256), 0, s, D);
     return hipGetLastError();
 }
 

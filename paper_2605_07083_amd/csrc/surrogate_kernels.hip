@@ -1,0 +1,472 @@
+// surrogate_kernels.hip -- BF16-MFMA 1D convolution network of the learned
+// warm start: (emission flux, cathode temperature, bias, neutral density) ->
+// (phi / V, ln(n_e / n0), ln(n_i / n0)) at the X cell centres of a diode.
+//
+// Net: 6 conv1d layers, kernel 5, zero padding 2, channels
+// 16 -> 64 -> 64 -> 64 -> 64 -> 64 -> 3 (stored padded to 16), tanh after
+// layers 1-5.  Input channels: the 4 normalised parameters and 12 functions of
+// the position.  Weights are BF16 (FP32 master copies for Adam), activations
+// enter every layer as BF16, all products accumulate in FP32 on
+// v_mfma_f32_16x16x32_bf16.
+//
+// Layouts (channels last): activations act[b][x][c]; forward weights
+// Wf[co][t*Cin + ci] (K contiguous), transposed weights for the input gradient
+// Wb[ci][t*Cout + co]; both padded with zeros to a multiple of 32 in K.
+//
+// MFMA 16x16x32 (bf16) lane layout: lane l supplies A[l%16][8(l/16)+i] and
+// B[8(l/16)+i][l%16], i = 0..7, and receives D[4(l/16)+i][l%16], i = 0..3.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sur {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int KS = 5;     // kernel size
+constexpr int PAD = 2;
+
+__device__ __forceinline__ bf16x8 zero8()
+{
+    bf16x8 z;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) z[i] = (__bf16)0.0f;
+    return z;
+}
+
+__device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// ---------------------------------------------------------------------------
+// Input features.  params[b] = (Gamma m^-2 s^-1, T_c K, V volts, n_g m^-3) are
+// mapped to [-1, 1] over the training ranges (log scale for the flux and the
+// density); the position features resolve both sheaths and the interior.
+// ---------------------------------------------------------------------------
+__global__ void k_features(const float *__restrict__ params, __bf16 *__restrict__ feat, int X, int B)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= X * B) return;
+    const int b = idx / X, x = idx - b * X;
+    const float g = params[4 * b + 0], T = params[4 * b + 1], V = params[4 * b + 2], ng = params[4 * b + 3];
+    const float u = ((float)x + 0.5f) / (float)X;
+    float f[16];
+    f[0] = 2.0f * (log10f(g / 1e19f) / log10f(12.0f)) - 1.0f;
+    f[1] = (T - 2000.0f) / 200.0f;
+    f[2] = (V - 12.5f) / 7.5f;
+    f[3] = 2.0f * log10f(ng / 1e21f) - 1.0f;
+    f[4] = 2.0f * u - 1.0f;
+    f[5] = 1.0f - 2.0f * u;
+    float s1, c1, s2, c2, s4, c4;
+    sincospif(u, &s1, &c1);
+    sincospif(2.0f * u, &s2, &c2);
+    sincospif(4.0f * u, &s4, &c4);
+    f[6] = s1; f[7] = c1; f[8] = s2; f[9] = c2; f[10] = s4; f[11] = c4;
+    f[12] = __expf(-64.0f * u);
+    f[13] = __expf(-64.0f * (1.0f - u));
+    f[14] = __expf(-16.0f * u);
+    f[15] = __expf(-16.0f * (1.0f - u));
+    __bf16 *o = feat + (size_t)idx * 16;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) o[c] = (__bf16)f[c];
+}
+
+// ---------------------------------------------------------------------------
+// Forward conv: out[b][x][co] = act(bias[co] + sum_{t, ci} W[co][t][ci] in[b][x+t-2][ci]).
+// GEMM M = positions, N = COUT, K = 5*CIN (padded to KP).  A wave computes 16
+// positions x COUT; a block of 4 waves 64 positions.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, bool TANH>
+__global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ in, const __bf16 *__restrict__ Wf,
+                                                  const float *__restrict__ bias, float *__restrict__ yf,
+                                                  __bf16 *__restrict__ yb, int X, int B)
+{
+    constexpr int K = KS * CIN;
+    constexpr int KP = (K + 31) / 32 * 32;
+    constexpr int NT = COUT / 16;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tiles = X / 64;
+    const int b = blockIdx.x / tiles;
+    const int x0 = (blockIdx.x - b * tiles) * 64 + w * 16;
+    if (b >= B) return;
+    const int m = lane & 15, kb = lane >> 4;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const __bf16 *inb = in + (size_t)b * X * CIN;
+#pragma unroll
+    for (int ks = 0; ks < KP / 32; ++ks) {
+        const int kappa = ks * 32 + kb * 8;
+        bf16x8 a = zero8();
+        if (kappa < K) {
+            const int t = kappa / CIN, ci = kappa - t * CIN;
+            const int xs = x0 + m + t - PAD;
+            if (xs >= 0 && xs < X) a = load8(inb + (size_t)xs * CIN + ci);
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const bf16x8 bw = load8(Wf + (size_t)(nt * 16 + m) * KP + kappa);
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[nt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int co = nt * 16 + m;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int x = x0 + kb * 4 + i;
+            float v = acc[nt][i] + bias[co];
+            if (TANH) v = tanhf(v);
+            const size_t o = ((size_t)b * X + x) * COUT + co;
+            yf[o] = v;
+            if (yb) yb[o] = (__bf16)v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Loss: mean over (b, channel < 3, x) of (out - target)^2.  Writes
+// dZ = 2 (out - target) / count as BF16 in the padded 16-channel layout.
+// target[b][c][x], out[b][x][16].
+// ---------------------------------------------------------------------------
+__global__ void k_loss(const float *__restrict__ out, const float *__restrict__ target, __bf16 *__restrict__ dz,
+                       double *__restrict__ loss, int X, int B)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const double inv = 1.0 / (3.0 * (double)X * (double)B);
+    double acc = 0.0;
+    if (idx < X * B) {
+        const int b = idx / X, x = idx - b * X;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            float g = 0.0f;
+            if (c < 3) {
+                const float d = out[(size_t)idx * 16 + c] - target[((size_t)b * 3 + c) * X + x];
+                acc += (double)d * d;
+                g = (float)(2.0 * inv) * d;
+            }
+            dz[(size_t)idx * 16 + c] = (__bf16)g;
+        }
+    }
+    // wave reduction, one atomic per wave
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0 && acc != 0.0) atomicAdd(loss, acc * inv);
+}
+
+// ---------------------------------------------------------------------------
+// Input gradient: dY[b][x][ci] = sum_{t, co} W[co][t][ci] dZ[b][x-t+2][co],
+// then (tanh) dZprev = dY (1 - y^2) stored as BF16.  GEMM M = positions,
+// N = CIN, K = 5*COUT (padded), B from the transposed weights Wb[ci][t*COUT+co].
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_dgrad(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ Wb,
+                                                    const float *__restrict__ yprev, __bf16 *__restrict__ dzprev,
+                                                    int X, int B)
+{
+    constexpr int K = KS * COUT;
+    constexpr int KP = (K + 31) / 32 * 32;
+    constexpr int NT = CIN / 16;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tiles = X / 64;
+    const int b = blockIdx.x / tiles;
+    const int x0 = (blockIdx.x - b * tiles) * 64 + w * 16;
+    if (b >= B) return;
+    const int m = lane & 15, kb = lane >> 4;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const __bf16 *dzb = dz + (size_t)b * X * COUT;
+#pragma unroll
+    for (int ks = 0; ks < KP / 32; ++ks) {
+        const int kappa = ks * 32 + kb * 8;
+        bf16x8 a = zero8();
+        if (kappa < K) {
+            const int t = kappa / COUT, co = kappa - t * COUT;
+            const int xs = x0 + m - t + PAD;
+            if (xs >= 0 && xs < X) a = load8(dzb + (size_t)xs * COUT + co);
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const bf16x8 bw = load8(Wb + (size_t)(nt * 16 + m) * KP + kappa);
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[nt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int ci = nt * 16 + m;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int x = x0 + kb * 4 + i;
+            const size_t o = ((size_t)b * X + x) * CIN + ci;
+            const float y = yprev[o];
+            dzprev[o] = (__bf16)(acc[nt][i] * (1.0f - y * y));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dW[co][t*CIN+ci] += sum_{positions} dZ[p][co] in[p+t-2][ci].
+// GEMM M = COUT, N = 5*CIN (16-wide tiles), K = positions (32 per MFMA).
+// Each wave owns one (co tile, kappa tile) and a slice of positions; the
+// slices are summed with FP32 atomics.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_wgrad(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ in,
+                                                    float *__restrict__ dW, int X, int B, int slice)
+{
+    constexpr int K = KS * CIN;
+    constexpr int KP = (K + 31) / 32 * 32;
+    constexpr int MT = COUT / 16, NTK = KP / 16;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int tile = wave % (MT * NTK), sl = wave / (MT * NTK);
+    const int mt = tile / NTK, nk = tile - mt * NTK;
+    const int P = X * B;
+    const int p_begin = sl * slice, p_end = min(P, p_begin + slice);
+    if (p_begin >= P) return;
+    const int m = lane & 15, kb = lane >> 4;
+    const int co = mt * 16 + m;               // A row
+    const int kappa = nk * 16 + m;            // B column
+    const int t = kappa / CIN, ci = kappa - t * CIN;
+    const bool kv = kappa < K;
+    f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int p0 = p_begin; p0 < p_end; p0 += 32) {
+        bf16x8 a, bb;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int p = p0 + kb * 8 + i;
+            __bf16 av = (__bf16)0.0f, bv = (__bf16)0.0f;
+            if (p < p_end) {
+                av = dz[(size_t)p * COUT + co];
+                if (kv) {
+                    const int b = p / X, x = p - b * X;
+                    const int xs = x + t - PAD;
+                    if (xs >= 0 && xs < X) bv = in[((size_t)b * X + xs) * CIN + ci];
+                }
+            }
+            a[i] = av;
+            bb[i] = bv;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = mt * 16 + kb * 4 + i;     // co
+        const int col = nk * 16 + m;              // kappa
+        if (col < K) atomicAdd(&dW[(size_t)row * KP + col], acc[i]);
+    }
+}
+
+// Bias gradient: db[co] = sum over positions of dZ[p][co].
+template <int COUT>
+__global__ void k_bias_grad(const __bf16 *__restrict__ dz, float *__restrict__ db, int P)
+{
+    const int co = threadIdx.x % COUT;
+    const int lanes = blockDim.x / COUT;
+    float acc = 0.0f;
+    for (int p = blockIdx.x * lanes + threadIdx.x / COUT; p < P; p += gridDim.x * lanes)
+        acc += (float)dz[(size_t)p * COUT + co];
+    atomicAdd(&db[co], acc);
+}
+
+__global__ void k_zero(float *__restrict__ p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Adam on the FP32 master weights of one layer (weights in the padded
+// forward layout [COUTP][KP], only co < cout_real and kappa < 5*CIN live),
+// then the BF16 forward and transposed copies.
+// ---------------------------------------------------------------------------
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ mo, float *__restrict__ ve,
+                       const float *__restrict__ g, int n, float lr, float b1, float b2, float eps, float c1,
+                       float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float m1 = b1 * mo[i] + (1.0f - b1) * gi;
+    const float v1 = b2 * ve[i] + (1.0f - b2) * gi * gi;
+    mo[i] = m1;
+    ve[i] = v1;
+    w[i] -= lr * (m1 / c1) / (sqrtf(v1 / c2) + eps);
+}
+
+// masters [COUTP][KP] (kappa = t*CIN + ci) -> Wf (same layout, bf16) and
+// Wb[ci][t*COUTP + co] (padded to KPB)
+__global__ void k_requant(const float *__restrict__ wm, __bf16 *__restrict__ Wf, __bf16 *__restrict__ Wb, int cin,
+                          int coutp, int cout_real, int kp, int kpb)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= coutp * kp) return;
+    const int co = i / kp, kappa = i - co * kp;
+    const bool live = co < cout_real && kappa < KS * cin;
+    const __bf16 v = (__bf16)(live ? wm[i] : 0.0f);
+    Wf[i] = v;
+    if (kappa < KS * cin) {
+        const int t = kappa / cin, ci = kappa - t * cin;
+        Wb[(size_t)ci * kpb + t * coutp + co] = v;
+    }
+}
+
+// Initial weights: N(0, 1/(5*CIN)) from Philox keyed by (layer, seed).
+__global__ void k_init_weights(float *__restrict__ wm, int cin, int coutp, int cout_real, int kp, uint32_t layer,
+                               uint32_t seed)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= coutp * kp) return;
+    const int co = i / kp, kappa = i - co * kp;
+    float v = 0.0f;
+    if (co < cout_real && kappa < KS * cin) {
+        const uint4 r = philox((uint32_t)i, layer, 7u, 0u, seed, 0x5A11u);
+        const float u1 = ((float)(r.x >> 8) + 0.5f) * (1.0f / 16777216.0f);
+        const float u2 = ((float)(r.y >> 8) + 0.5f) * (1.0f / 16777216.0f);
+        float s, c;
+        sincospif(2.0f * u2, &s, &c);
+        v = sqrtf(-2.0f * logf(u1)) * c * sqrtf(1.0f / (float)(KS * cin));
+    }
+    wm[i] = v;
+}
+
+// Network output -> densities per cell for the warm-start loader:
+// dens[d][0][x] = n0 exp(out[d][x][1]), dens[d][1][x] = n0 exp(out[d][x][2]).
+__global__ void k_to_densities(const float *__restrict__ out, const double *__restrict__ n0, double *__restrict__ dens,
+                               int X, int B)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= X * B) return;
+    const int b = idx / X, x = idx - b * X;
+    dens[((size_t)b * 2 + 0) * X + x] = n0[b] * exp((double)out[(size_t)idx * 16 + 1]);
+    dens[((size_t)b * 2 + 1) * X + x] = n0[b] * exp((double)out[(size_t)idx * 16 + 2]);
+}
+
+// Network output [b][x][16] -> caller layout [b][3][x].
+__global__ void k_unpack(const float *__restrict__ y, float *__restrict__ out, int X, int B)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= X * B) return;
+    const int b = idx / X, x = idx - b * X;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[((size_t)b * 3 + c) * X + x] = y[(size_t)idx * 16 + c];
+}
+
+}  // namespace sur
+
+// ---------------------------------------------------------------------------
+// Launch wrappers
+// ---------------------------------------------------------------------------
+using namespace sur;
+
+extern "C" hipError_t surx_features(const float *params, __bf16 *feat, int X, int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_features, dim3((X * B + 255) / 256), dim3(256), 0, s, params, feat, X, B);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t surx_conv_fwd(int layer, const __bf16 *in, const __bf16 *Wf, const float *bias, float *yf,
+                                    __bf16 *yb, int X, int B, hipStream_t s)
+{
+    dim3 g(X / 64 * B), t(256);
+    if (layer == 0) hipLaunchKernelGGL((k_conv_fwd<16, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, X, B);
+    else if (layer < 5) hipLaunchKernelGGL((k_conv_fwd<64, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, X, B);
+    else hipLaunchKernelGGL((k_conv_fwd<64, 16, false>), g, t, 0, s, in, Wf, bias, yf, yb, X, B);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t surx_loss(const float *out, const float *target, __bf16 *dz, double *loss, int X, int B,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_loss, dim3((X * B + 255) / 256), dim3(256), 0, s, out, target, dz, loss, X, B);
+    return hipGetLastError();
+}
+
+// input gradient of layer `layer` (1..5; layer 0 has none)
+extern "C" hipError_t surx_conv_dgrad(int layer, const __bf16 *dz, const __bf16 *Wb, const float *yprev,
+                                      __bf16 *dzprev, int X, int B, hipStream_t s)
+{
+    dim3 g(X / 64 * B), t(256);
+    if (layer == 5) hipLaunchKernelGGL((k_conv_dgrad<64, 16>), g, t, 0, s, dz, Wb, yprev, dzprev, X, B);
+    else hipLaunchKernelGGL((k_conv_dgrad<64, 64>), g, t, 0, s, dz, Wb, yprev, dzprev, X, B);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t surx_conv_wgrad(int layer, const __bf16 *dz, const __bf16 *in, float *dW, float *db, int X,
+                                      int B, hipStream_t s)
+{
+    const int P = X * B;
+    const int slice = 4096;
+    const int slices = (P + slice - 1) / slice;
+    if (layer == 0) {
+        constexpr int tiles = (64 / 16) * (96 / 16);
+        hipLaunchKernelGGL((k_conv_wgrad<16, 64>), dim3((tiles * slices + 3) / 4), dim3(256), 0, s, dz, in, dW, X, B,
+                           slice);
+        hipLaunchKernelGGL(k_bias_grad<64>, dim3(64), dim3(256), 0, s, dz, db, P);
+    } else if (layer < 5) {
+        constexpr int tiles = (64 / 16) * (320 / 16);
+        hipLaunchKernelGGL((k_conv_wgrad<64, 64>), dim3((tiles * slices + 3) / 4), dim3(256), 0, s, dz, in, dW, X, B,
+                           slice);
+        hipLaunchKernelGGL(k_bias_grad<64>, dim3(64), dim3(256), 0, s, dz, db, P);
+    } else {
+        constexpr int tiles = (16 / 16) * (320 / 16);
+        hipLaunchKernelGGL((k_conv_wgrad<64, 16>), dim3((tiles * slices + 3) / 4), dim3(256), 0, s, dz, in, dW, X, B,
+                           slice);
+        hipLaunchKernelGGL(k_bias_grad<16>, dim3(64), dim3(256), 0, s, dz, db, P);
+    }
+    return hipGetLastError();
+}
+
+extern "C" hipError_t surx_zero(float *p, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t surx_adam(float *w, float *m, float *v, const float *g, int n, float lr, float b1, float b2,
+                                float eps, float c1, float c2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t surx_requant(const float *wm, __bf16 *Wf, __bf16 *Wb, int cin, int coutp, int cout_real, int kp,
+                                   int kpb, hipStream_t s)
+{
+    const int n = coutp * kp;
+    hipLaunchKernelGGL(k_requant, dim3((n + 255) / 256), dim3(256), 0, s, wm, Wf, Wb, cin, coutp, cout_real, kp, kpb);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t surx_init_weights(float *wm, int cin, int coutp, int cout_real, int kp, uint32_t layer,
+                                        uint32_t seed, hipStream_t s)
+{
+    const int n = coutp * kp;
+    hipLaunchKernelGGL(k_init_weights, dim3((n + 255) / 256), dim3(256), 0, s, wm, cin, coutp, cout_real, kp, layer,
+                       seed);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t surx_to_densities(const float *out, const double *n0, double *dens, int X, int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_densities, dim3((X * B + 255) / 256), dim3(256), 0, s, out, n0, dens, X, B);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t surx_unpack(const float *y, float *out, int X, int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_unpack, dim3((X * B + 255) / 256), dim3(256), 0, s, y, out, X, B);
+    return hipGetLastError();
+}

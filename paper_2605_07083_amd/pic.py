@@ -62,8 +62,8 @@ class PicDerived(C.Structure):
                 ("emit_per_step", C.c_double), ("capacity", C.c_int64 * 3)]
 
 
-SYMBOLS = ["pic_derive", "pic_workspace_size", "pic_init", "pic_step", "pic_sync", "pic_get_tally",
-           "pic_diagnostics", "pic_get_fields", "pic_avg_reset", "pic_get_hist", "pic_get_efield",
+SYMBOLS = ["pic_derive", "pic_workspace_size", "pic_init", "pic_init_from_profiles", "pic_step", "pic_sync", "pic_get_tally",
+           "pic_diagnostics", "pic_get_fields", "pic_avg_reset", "pic_avg_control", "pic_get_hist", "pic_get_efield",
            "pic_get_particles", "pic_set_particles", "pic_set_counters", "pic_refield",
            "pic_step_timed", "pic_set_tuning", "pic_get_tuning", "pic_autotune", "pic_steady_state", "pic_steady_from_series", "pic_last_error",
            "pic_destroy"]
@@ -84,12 +84,14 @@ def lib():
         "pic_derive": ([C.POINTER(PicConfig), C.POINTER(PicDerived)], i),
         "pic_workspace_size": ([C.POINTER(PicConfig), i, C.POINTER(C.c_size_t)], i),
         "pic_init": ([C.POINTER(PicConfig), i, P, C.c_size_t, P, C.POINTER(P)], i),
+        "pic_init_from_profiles": ([C.POINTER(PicConfig), i, P, C.c_size_t, P, P, C.POINTER(P)], i),
         "pic_step": ([P, i64], i),
         "pic_sync": ([P], i),
         "pic_get_tally": ([P, i, C.POINTER(PicTally)], i),
         "pic_diagnostics": ([P, i, i64, C.POINTER(PicDiag)], i),
         "pic_get_fields": ([P, i, P, P, P, i], i),
         "pic_avg_reset": ([P, i], i),
+        "pic_avg_control": ([P, i, i], i),
         "pic_get_hist": ([P, i, i, P], i),
         "pic_get_efield": ([P, i, P], i),
         "pic_get_particles": ([P, i, i, i64, C.POINTER(i64), P, P, P, P, P, P], i),
@@ -180,7 +182,9 @@ def steady_from_series(br, n_live, tol_pp=1.0, tol_rel=0.01):
 class Handle:
     """One or more diodes advanced together on one GPU."""
 
-    def __init__(self, cfgs, device="cuda:0", ppt=None, grid=None):
+    def __init__(self, cfgs, device="cuda:0", ppt=None, grid=None, densities=None):
+        """densities: optional device tensor [n_diodes][2][max N] float64 of
+        cell-centre electron and ion densities (m^-3) for the warm start."""
         import torch
         if isinstance(cfgs, dict):
             cfgs = [cfgs]
@@ -195,8 +199,18 @@ class Handle:
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             self.stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
-        _check(lib().pic_init(self._arr, self.nd, C.c_void_p(self.ws.data_ptr()), nbytes,
-                              C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        if densities is None:
+            _check(lib().pic_init(self._arr, self.nd, C.c_void_p(self.ws.data_ptr()), nbytes,
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        else:
+            nmax = max(c["N"] for c in cfgs)
+            if (densities.device != self.device or densities.dtype != torch.float64
+                    or tuple(densities.shape) != (self.nd, 2, nmax) or not densities.is_contiguous()):
+                raise ValueError("densities must be a contiguous float64 [%d, 2, %d] tensor on %s"
+                                 % (self.nd, nmax, self.device))
+            _check(lib().pic_init_from_profiles(self._arr, self.nd, C.c_void_p(self.ws.data_ptr()), nbytes,
+                                                C.c_void_p(self.stream.cuda_stream),
+                                                C.c_void_p(densities.data_ptr()), C.byref(h)))
         self.h = h
 
     def close(self):
@@ -256,6 +270,10 @@ class Handle:
 
     def avg_reset(self, on=True):
         _check(lib().pic_avg_reset(self.h, 1 if on else 0))
+
+    def avg_control(self, d, on=True):
+        """Clear diode d's time averages and switch its averaging on or off."""
+        _check(lib().pic_avg_control(self.h, int(d), 1 if on else 0))
 
     def hist(self, d=0, sp=0):
         H = np.zeros(self.cfgs[d]["N"] + 1, np.int64)

@@ -97,6 +97,26 @@ def surrogate_params(n, seed):
                 V=rng.uniform(5.0, 20.0, n), ng=rng.uniform(1e21, 1e22, n))
 
 
+SURROGATE_TRAIN_SEED = 0x5EED0004
+SURROGATE_HELDOUT_SEED = 0x5EED0104
+
+
+def surrogate_cases(n, seed):
+    """Warm-start dataset diodes: the benchmark geometry (5 mm, 2048 cells,
+    200 particles per cell and species, dt 5 ps) with flux, cathode
+    temperature, bias and neutral density drawn uniformly (surrogate_params).
+    Tallies every 500 steps so that the snapshot ring spans 512k steps."""
+    import numpy as np
+    q = surrogate_params(n, seed)
+    out = []
+    for d in range(n):
+        out.append(_base(N=2048, n_load=409600, gamma_emit=float(q["gamma_emit"][d]),
+                         Tc=float(q["T_K"][d]) * KB_OVER_E, V=float(q["V"][d]), ng=float(q["ng"][d]),
+                         seed=seed & 0xFFFFFFFF, diode=d, tally_period=500, nsteps=400000,
+                         T_K=float(q["T_K"][d])))
+    return out
+
+
 SURROGATE_LAYERS = [(16, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 3)]
 
 
@@ -112,5 +132,5 @@ def surrogate_test_weights(seed, scale=1.0):
     return W, b
 
 
-__all__ = ["tiny", "bench", "sweep", "large", "paper", "scaled", "surrogate_params", "surrogate_test_weights", "SURROGATE_LAYERS",
+__all__ = ["tiny", "bench", "sweep", "large", "paper", "scaled", "surrogate_params", "surrogate_cases", "SURROGATE_TRAIN_SEED", "SURROGATE_HELDOUT_SEED", "surrogate_test_weights", "SURROGATE_LAYERS",
            "KB_OVER_E", "CH_ALL", "CH_EEL", "CH_EXC", "CH_IZ", "CH_CX", "CH_IEL", "math"]

@@ -17,10 +17,10 @@ from paper_2605_07083_amd import pic, presets
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "pic.h")).read()
+def _declared(header="pic.h", prefix="pic"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(%s_[a-z_]+)\s*\(" % prefix, src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -31,6 +31,29 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) <= set(pic.SYMBOLS)
+    from paper_2605_07083_amd import surrogate
+    names = _declared("surrogate.h", "sur")
+    assert len(names) == 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(surrogate.SYMBOLS)
+
+
+def test_surrogate_workspace_and_shapes():
+    from paper_2605_07083_amd import surrogate
+    assert surrogate.N_WEIGHTS == 88000 and surrogate.N_BIASES == 323
+    a = surrogate.workspace_size(1, 2048)
+    b = surrogate.workspace_size(32, 2048)
+    assert b > 20 * (a - 2_000_000) and b < 200 * 2 ** 20
+    for bad in ((0, 2048), (4, 100), (4, 0)):
+        with pytest.raises(pic.PicError) as e:
+            surrogate.workspace_size(*bad)
+        assert e.value.code == pic.PIC_EINVAL
+    W = [np.arange(ci * co * 5, dtype=np.float32).reshape(co, ci, 5) for ci, co in surrogate.LAYERS]
+    B = [np.arange(co, dtype=np.float32) for _, co in surrogate.LAYERS]
+    w, b = surrogate.pack(W, B)
+    W2, B2 = surrogate.unpack(w, b)
+    assert all(np.array_equal(x, y) for x, y in zip(W, W2)) and all(np.array_equal(x, y) for x, y in zip(B, B2))
 
 
 @pytest.mark.parametrize("name", ["tiny", "bench", "large", "paper"])
