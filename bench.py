@@ -7,7 +7,7 @@ replenishment), Poisson solve and field.  Inputs are resident in HBM before
 the timed region; the metric is live particle-steps per second.
 
 Prints one JSON line.  Options: --gpus (must be 1), --steps, --warmup,
---workload {large,bench,tiny,sweep} (default large: the 16384-cell,
+--workload {large,bench,tiny,sweep,surrogate} (default large: the 16384-cell,
 16.4M-per-species diode, the one configuration whose per-step working set
 exceeds the 256 MB last-level cache), --no-cpu-baseline.  --copy-probe BYTES
 runs a plain device copy of that size instead (counter calibration).
@@ -75,6 +75,71 @@ def cpu_baseline(cfg, seconds=12.0):
                       % (steps, live)}
 
 
+# FLOPs of one surrogate training step per position: forward and weight
+# gradients 2 * 88000 each (88000 = multiply-adds of the six layers per
+# position), input gradients of layers 1-5 2 * 82880.
+SUR_FLOP_PER_POSITION = 2 * 88000 + 2 * 88000 + 2 * 82880
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def surrogate_bench(args):
+    """Training throughput of the warm-start surrogate (batch 32 x 2048 cells)."""
+    import numpy as np
+    import torch
+    from paper_2605_07083_amd import presets
+    from paper_2605_07083_amd.surrogate import Surrogate
+    B, X = 32, 2048
+    q = presets.surrogate_params(B, presets.SURROGATE_TRAIN_SEED)
+    P = torch.tensor(np.stack([q["gamma_emit"], q["T_K"], q["V"], q["ng"]], 1), dtype=torch.float32,
+                     device="cuda:0")
+    u = np.linspace(0.5 / X, 1 - 0.5 / X, X)
+    T = torch.tensor(np.stack([np.stack([u * (1 + 0.01 * k), np.log(0.3 + u), np.log(1.3 - u)])
+                               for k in range(B)]), dtype=torch.float32, device="cuda:0")
+    net = Surrogate(B, X, seed=1)
+    for _ in range(args.warmup):
+        net.train_step(P, T, 1e-3, want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.train_step(P, T, 1e-3, want_loss=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        net.forward(P)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t1) / args.steps
+    step_s = wall / args.steps
+    achieved = SUR_FLOP_PER_POSITION * B * X / step_s / 1e12
+    out = {"metric": "surrogate training samples/s", "value": B * args.steps / wall, "unit": "samples/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16 x bf16 -> f32 (f32 master weights)", "data": "synthetic smooth targets",
+           "config": {"workload": "warm-start surrogate, 6 conv1d layers k=5, 64 channels, batch 32 x 2048 cells",
+                      "batch": B, "cells": X, "forward_ms_batch32": fwd * 1e3},
+           "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
+                        "kernel": "sur_train_step (all kernels of one step)",
+                        "flop_per_step": SUR_FLOP_PER_POSITION * B * X}}
+    if not args.no_cpu_baseline:
+        from oracle import surrogate_oracle as SO
+        W, b = presets.surrogate_test_weights(1)
+        Bs = 2
+        f = SO.features(P[:Bs].double().cpu().numpy(), X)
+        tg = T[:Bs].double().cpu().numpy()
+        zeros = lambda L: [np.zeros_like(x, dtype=np.float64) for x in L]
+        t2 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t2 < args.cpu_seconds:
+            SO.train_step(W, b, zeros(W), zeros(W), zeros(b), zeros(b), 1, f, tg, 1e-3)
+            n += 1
+        dt = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": Bs * n / dt, "unit": "samples/s", "cores": torch.get_num_threads(),
+                               "kind": "oracle", "sample": "%d FP64 training steps of %d samples x %d cells "
+                                                          "(torch CPU conv1d + autograd)" % (n, Bs, X)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +167,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n * 4, "launches": 3}), flush=True)
+        return
+
+    if args.workload == "surrogate":
+        surrogate_bench(args)
         return
 
     desc, cfgs = workload(args.workload)

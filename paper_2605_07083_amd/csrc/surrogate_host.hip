@@ -14,13 +14,14 @@
 #include "../../include/surrogate.h"
 
 extern "C" {
-hipError_t surx_features(const float *params, __bf16 *feat, int X, int B, hipStream_t s);
+hipError_t surx_features(const float *params, __bf16 *feat, __bf16 *featT, int X, int B, hipStream_t s);
 hipError_t surx_conv_fwd(int layer, const __bf16 *in, const __bf16 *Wf, const float *bias, float *yf, __bf16 *yb,
-                         int X, int B, hipStream_t s);
-hipError_t surx_loss(const float *out, const float *target, __bf16 *dz, double *loss, int X, int B, hipStream_t s);
-hipError_t surx_conv_dgrad(int layer, const __bf16 *dz, const __bf16 *Wb, const float *yprev, __bf16 *dzprev, int X,
-                           int B, hipStream_t s);
-hipError_t surx_conv_wgrad(int layer, const __bf16 *dz, const __bf16 *in, float *dW, float *db, int X, int B,
+                         __bf16 *ybT, int X, int B, hipStream_t s);
+hipError_t surx_loss(const float *out, const float *target, __bf16 *dz, __bf16 *dzT, double *loss, int X, int B,
+                     hipStream_t s);
+hipError_t surx_conv_dgrad(int layer, const __bf16 *dz, const __bf16 *Wb, const float *yprev, __bf16 *dzprev,
+                           __bf16 *dzprevT, int X, int B, hipStream_t s);
+hipError_t surx_conv_wgrad(int layer, const __bf16 *dzT, const __bf16 *inT, float *dW, float *db, int X, int B,
                            hipStream_t s);
 hipError_t surx_zero(float *p, size_t n, hipStream_t s);
 hipError_t surx_adam(float *w, float *m, float *v, const float *g, int n, float lr, float b1, float b2, float eps,
@@ -87,9 +88,12 @@ struct sur_net {
     size_t param_bytes = 0;       // weights, moments, grads: the first bytes of ws
     Layer L[SUR_LAYERS];
     __bf16 *feat = nullptr;       // [bmax][X][16]
+    __bf16 *featT = nullptr;      // [bmax][16][X] (channels first, for weight gradients)
     float *yf[SUR_LAYERS];        // [bmax][X][coutp]
     __bf16 *yb[SUR_LAYERS - 1];   // bf16 copies of the hidden outputs
+    __bf16 *ybT[SUR_LAYERS - 1];  // channels-first copies [bmax][64][X]
     __bf16 *dz[2];                // [bmax][X][64]
+    __bf16 *dzT[2];               // [bmax][64][X]
     double *loss = nullptr;
     long long t = 0;              // Adam steps taken
 };
@@ -121,10 +125,16 @@ void layout(sur_net &n, Bump &bp)
     n.loss = bp.take<double>(1);
     n.param_bytes = bp.off;
     n.feat = bp.take<__bf16>(P * SUR_IN);
+    n.featT = bp.take<__bf16>(P * SUR_IN);
     for (int l = 0; l < SUR_LAYERS; ++l) n.yf[l] = bp.take<float>(P * COUTP[l]);
-    for (int l = 0; l < SUR_LAYERS - 1; ++l) n.yb[l] = bp.take<__bf16>(P * COUTP[l]);
-    n.dz[0] = bp.take<__bf16>(P * SUR_HIDDEN);
-    n.dz[1] = bp.take<__bf16>(P * SUR_HIDDEN);
+    for (int l = 0; l < SUR_LAYERS - 1; ++l) {
+        n.yb[l] = bp.take<__bf16>(P * COUTP[l]);
+        n.ybT[l] = bp.take<__bf16>(P * COUTP[l]);
+    }
+    for (int k = 0; k < 2; ++k) {
+        n.dz[k] = bp.take<__bf16>(P * SUR_HIDDEN);
+        n.dzT[k] = bp.take<__bf16>(P * SUR_HIDDEN);
+    }
 }
 
 int check_shape(int batch, int cells)
@@ -143,13 +153,15 @@ int requant_all(sur_net *n)
     return PIC_OK;
 }
 
-int forward(sur_net *n, const float *params, int B)
+// train: also write the channels-first copies the weight gradients read
+int forward(sur_net *n, const float *params, int B, bool train)
 {
-    SUR_TRY(surx_features(params, n->feat, n->X, B, n->stream));
+    SUR_TRY(surx_features(params, n->feat, train ? n->featT : nullptr, n->X, B, n->stream));
     for (int l = 0; l < SUR_LAYERS; ++l) {
         const __bf16 *in = l == 0 ? n->feat : n->yb[l - 1];
         __bf16 *yb = l < SUR_LAYERS - 1 ? n->yb[l] : nullptr;
-        SUR_TRY(surx_conv_fwd(l, in, n->L[l].wf, n->L[l].bias, n->yf[l], yb, n->X, B, n->stream));
+        __bf16 *ybT = train && l < SUR_LAYERS - 1 ? n->ybT[l] : nullptr;
+        SUR_TRY(surx_conv_fwd(l, in, n->L[l].wf, n->L[l].bias, n->yf[l], yb, ybT, n->X, B, n->stream));
     }
     return PIC_OK;
 }
@@ -273,7 +285,7 @@ int sur_forward(sur_net *n, const float *dev_params, int batch, float *dev_out)
 {
     if (!n || !dev_params || !dev_out) return fail(PIC_EINVAL, "bad arguments");
     if (batch < 1 || batch > n->bmax) return fail(PIC_EINVAL, "batch exceeds the workspace's max_batch");
-    int rc = forward(n, dev_params, batch);
+    int rc = forward(n, dev_params, batch, false);
     if (rc) return rc;
     SUR_TRY(surx_unpack(n->yf[SUR_LAYERS - 1], dev_out, n->X, batch, n->stream));
     return PIC_OK;
@@ -285,10 +297,10 @@ int sur_train_step(sur_net *n, const float *dev_params, const float *dev_target,
     if (batch < 1 || batch > n->bmax) return fail(PIC_EINVAL, "batch exceeds the workspace's max_batch");
     if (!(lr > 0.0f)) return fail(PIC_EINVAL, "learning rate must be positive");
     const int X = n->X;
-    int rc = forward(n, dev_params, batch);
+    int rc = forward(n, dev_params, batch, true);
     if (rc) return rc;
     SUR_TRY(surx_zero(reinterpret_cast<float *>(n->loss), 2, n->stream));
-    SUR_TRY(surx_loss(n->yf[SUR_LAYERS - 1], dev_target, n->dz[0], n->loss, X, batch, n->stream));
+    SUR_TRY(surx_loss(n->yf[SUR_LAYERS - 1], dev_target, n->dz[0], n->dzT[0], n->loss, X, batch, n->stream));
     for (int l = 0; l < SUR_LAYERS; ++l) {
         const Layer &L = n->L[l];
         SUR_TRY(surx_zero(L.dw, (size_t)L.coutp * L.kp, n->stream));
@@ -297,10 +309,11 @@ int sur_train_step(sur_net *n, const float *dev_params, const float *dev_target,
     int cur = 0;
     for (int l = SUR_LAYERS - 1; l >= 0; --l) {
         const Layer &L = n->L[l];
-        const __bf16 *in = l == 0 ? n->feat : n->yb[l - 1];
-        SUR_TRY(surx_conv_wgrad(l, n->dz[cur], in, L.dw, L.db, X, batch, n->stream));
+        const __bf16 *inT = l == 0 ? n->featT : n->ybT[l - 1];
+        SUR_TRY(surx_conv_wgrad(l, n->dzT[cur], inT, L.dw, L.db, X, batch, n->stream));
         if (l > 0) {
-            SUR_TRY(surx_conv_dgrad(l, n->dz[cur], L.wb, n->yf[l - 1], n->dz[cur ^ 1], X, batch, n->stream));
+            SUR_TRY(surx_conv_dgrad(l, n->dz[cur], L.wb, n->yf[l - 1], n->dz[cur ^ 1], n->dzT[cur ^ 1], X, batch,
+                                    n->stream));
             cur ^= 1;
         }
     }
@@ -325,7 +338,7 @@ int sur_densities(sur_net *n, const float *dev_params, const double *dev_n0, int
 {
     if (!n || !dev_params || !dev_n0 || !dev_dens) return fail(PIC_EINVAL, "bad arguments");
     if (batch < 1 || batch > n->bmax) return fail(PIC_EINVAL, "batch exceeds the workspace's max_batch");
-    int rc = forward(n, dev_params, batch);
+    int rc = forward(n, dev_params, batch, false);
     if (rc) return rc;
     SUR_TRY(surx_to_densities(n->yf[SUR_LAYERS - 1], dev_n0, dev_dens, n->X, batch, n->stream));
     return PIC_OK;

@@ -9,7 +9,9 @@
 // enter every layer as BF16, all products accumulate in FP32 on
 // v_mfma_f32_16x16x32_bf16.
 //
-// Layouts (channels last): activations act[b][x][c]; forward weights
+// Layouts: activations channels last act[b][x][c] for the forward and input
+// gradient GEMMs (K runs over channels), plus channels-first copies
+// actT[b][c][x] for the weight gradient (K runs over positions); forward weights
 // Wf[co][t*Cin + ci] (K contiguous), transposed weights for the input gradient
 // Wb[ci][t*Cout + co]; both padded with zeros to a multiple of 32 in K.
 //
@@ -54,7 +56,8 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
 // mapped to [-1, 1] over the training ranges (log scale for the flux and the
 // density); the position features resolve both sheaths and the interior.
 // ---------------------------------------------------------------------------
-__global__ void k_features(const float *__restrict__ params, __bf16 *__restrict__ feat, int X, int B)
+__global__ void k_features(const float *__restrict__ params, __bf16 *__restrict__ feat, __bf16 *__restrict__ featT,
+                           int X, int B)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= X * B) return;
@@ -80,6 +83,22 @@ __global__ void k_features(const float *__restrict__ params, __bf16 *__restrict_
     __bf16 *o = feat + (size_t)idx * 16;
 #pragma unroll
     for (int c = 0; c < 16; ++c) o[c] = (__bf16)f[c];
+    if (featT) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) featT[((size_t)b * 16 + c) * X + x] = (__bf16)f[c];
+    }
+}
+
+// Four consecutive positions of one channel, stored as one 8-byte word.
+__device__ __forceinline__ void store4T(__bf16 *p, float v0, float v1, float v2, float v3)
+{
+    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+    bf16x4 q;
+    q[0] = (__bf16)v0;
+    q[1] = (__bf16)v1;
+    q[2] = (__bf16)v2;
+    q[3] = (__bf16)v3;
+    *reinterpret_cast<bf16x4 *>(p) = q;
 }
 
 // ---------------------------------------------------------------------------
@@ -90,7 +109,7 @@ __global__ void k_features(const float *__restrict__ params, __bf16 *__restrict_
 template <int CIN, int COUT, bool TANH>
 __global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ in, const __bf16 *__restrict__ Wf,
                                                   const float *__restrict__ bias, float *__restrict__ yf,
-                                                  __bf16 *__restrict__ yb, int X, int B)
+                                                  __bf16 *__restrict__ yb, __bf16 *__restrict__ ybT, int X, int B)
 {
     constexpr int K = KS * CIN;
     constexpr int KP = (K + 31) / 32 * 32;
@@ -123,15 +142,17 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ in,
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         const int co = nt * 16 + m;
+        float v[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int x = x0 + kb * 4 + i;
-            float v = acc[nt][i] + bias[co];
-            if (TANH) v = tanhf(v);
+            v[i] = acc[nt][i] + bias[co];
+            if (TANH) v[i] = tanhf(v[i]);
             const size_t o = ((size_t)b * X + x) * COUT + co;
-            yf[o] = v;
-            if (yb) yb[o] = (__bf16)v;
+            yf[o] = v[i];
+            if (yb) yb[o] = (__bf16)v[i];
         }
+        if (ybT) store4T(ybT + ((size_t)b * COUT + co) * X + x0 + kb * 4, v[0], v[1], v[2], v[3]);
     }
 }
 
@@ -141,7 +162,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ in,
 // target[b][c][x], out[b][x][16].
 // ---------------------------------------------------------------------------
 __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ target, __bf16 *__restrict__ dz,
-                       double *__restrict__ loss, int X, int B)
+                       __bf16 *__restrict__ dzT, double *__restrict__ loss, int X, int B)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const double inv = 1.0 / (3.0 * (double)X * (double)B);
@@ -157,6 +178,7 @@ __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ 
                 g = (float)(2.0 * inv) * d;
             }
             dz[(size_t)idx * 16 + c] = (__bf16)g;
+            dzT[((size_t)b * 16 + c) * X + x] = (__bf16)g;
         }
     }
     // wave reduction, one atomic per wave
@@ -173,7 +195,7 @@ __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ 
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_conv_dgrad(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ Wb,
                                                     const float *__restrict__ yprev, __bf16 *__restrict__ dzprev,
-                                                    int X, int B)
+                                                    __bf16 *__restrict__ dzprevT, int X, int B)
 {
     constexpr int K = KS * COUT;
     constexpr int KP = (K + 31) / 32 * 32;
@@ -206,79 +228,108 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const __bf16 *__restrict__ d
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         const int ci = nt * 16 + m;
+        float v[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int x = x0 + kb * 4 + i;
             const size_t o = ((size_t)b * X + x) * CIN + ci;
             const float y = yprev[o];
-            dzprev[o] = (__bf16)(acc[nt][i] * (1.0f - y * y));
+            v[i] = acc[nt][i] * (1.0f - y * y);
+            dzprev[o] = (__bf16)v[i];
         }
+        store4T(dzprevT + ((size_t)b * CIN + ci) * X + x0 + kb * 4, v[0], v[1], v[2], v[3]);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient: dW[co][t*CIN+ci] += sum_{positions} dZ[p][co] in[p+t-2][ci].
-// GEMM M = COUT, N = 5*CIN (16-wide tiles), K = positions (32 per MFMA).
-// Each wave owns one (co tile, kappa tile) and a slice of positions; the
-// slices are summed with FP32 atomics.
+// Weight and bias gradients: dW[co][t*CIN+ci] += sum_x dZ[b][co][x] in[b][ci][x+t-2],
+// db[co] += sum_x dZ[b][co][x], from the channels-first copies.  GEMM M = COUT,
+// N = 5*CIN (16-wide tiles, one tap t per tile), K = positions, 32 per MFMA.
+// A wave owns one (co tile, kappa tile) over one sample; the samples are
+// summed with FP32 atomics.  Lane (m, kb) reads 8 consecutive positions as
+// one 16-byte load for A; for B the same 8 positions shifted by t - 2, taken
+// from a 12-element window (16 bytes plus one dword on each side, zero
+// outside the sample).  The kappa tiles starting at 0 also sum dZ for db.
 // ---------------------------------------------------------------------------
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int T>
+__device__ __forceinline__ bf16x8 window8(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t w4,
+                                          uint32_t w5)
+{
+    // elements T .. T+7 of the 12-element window w0..w5 (2 per dword, low first)
+    u32x4 r;
+    if constexpr (T == 0) r = (u32x4){w0, w1, w2, w3};
+    else if constexpr (T == 2) r = (u32x4){w1, w2, w3, w4};
+    else if constexpr (T == 4) r = (u32x4){w2, w3, w4, w5};
+    else if constexpr (T == 1)
+        r = (u32x4){(w0 >> 16) | (w1 << 16), (w1 >> 16) | (w2 << 16), (w2 >> 16) | (w3 << 16), (w3 >> 16) | (w4 << 16)};
+    else
+        r = (u32x4){(w1 >> 16) | (w2 << 16), (w2 >> 16) | (w3 << 16), (w3 >> 16) | (w4 << 16), (w4 >> 16) | (w5 << 16)};
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+template <int T>
+__device__ __forceinline__ f32x4 wgrad_tile(const __bf16 *__restrict__ arow, const __bf16 *__restrict__ brow, int X,
+                                            int kb, bool bias_tile, float &bsum)
+{
+    f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const uint32_t *bw = reinterpret_cast<const uint32_t *>(brow);
+    for (int x0 = 0; x0 < X; x0 += 32) {
+        const int xa = x0 + kb * 8;
+        const bf16x8 a = load8(arow + xa);
+        const u32x4 mid = *reinterpret_cast<const u32x4 *>(brow + xa);
+        const uint32_t lo = xa > 0 ? bw[(xa >> 1) - 1] : 0u;
+        const uint32_t hi = xa + 8 < X ? bw[(xa >> 1) + 4] : 0u;
+        const bf16x8 b = window8<T>(lo, mid[0], mid[1], mid[2], mid[3], hi);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        if (bias_tile) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) bsum += (float)a[i];
+        }
+    }
+    return acc;
+}
+
 template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv_wgrad(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ in,
-                                                    float *__restrict__ dW, int X, int B, int slice)
+__global__ __launch_bounds__(256) void k_conv_wgrad(const __bf16 *__restrict__ dzT, const __bf16 *__restrict__ inT,
+                                                    float *__restrict__ dW, float *__restrict__ db, int X, int B)
 {
     constexpr int K = KS * CIN;
     constexpr int KP = (K + 31) / 32 * 32;
-    constexpr int MT = COUT / 16, NTK = KP / 16;
+    constexpr int MT = COUT / 16, NTK = K / 16;    // tiles past K are padding: dW stays 0 there
+    static_assert(CIN % 16 == 0 && K % 16 == 0, "a kappa tile must lie within one tap");
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int tile = wave % (MT * NTK), sl = wave / (MT * NTK);
+    const int tile = wave % (MT * NTK), b = wave / (MT * NTK);
+    if (b >= B) return;
     const int mt = tile / NTK, nk = tile - mt * NTK;
-    const int P = X * B;
-    const int p_begin = sl * slice, p_end = min(P, p_begin + slice);
-    if (p_begin >= P) return;
     const int m = lane & 15, kb = lane >> 4;
-    const int co = mt * 16 + m;               // A row
-    const int kappa = nk * 16 + m;            // B column
-    const int t = kappa / CIN, ci = kappa - t * CIN;
-    const bool kv = kappa < K;
-    f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int p0 = p_begin; p0 < p_end; p0 += 32) {
-        bf16x8 a, bb;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int p = p0 + kb * 8 + i;
-            __bf16 av = (__bf16)0.0f, bv = (__bf16)0.0f;
-            if (p < p_end) {
-                av = dz[(size_t)p * COUT + co];
-                if (kv) {
-                    const int b = p / X, x = p - b * X;
-                    const int xs = x + t - PAD;
-                    if (xs >= 0 && xs < X) bv = in[((size_t)b * X + xs) * CIN + ci];
-                }
-            }
-            a[i] = av;
-            bb[i] = bv;
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc, 0, 0, 0);
+    const int co = mt * 16 + m;
+    const int kappa = nk * 16 + m;
+    const int t = (nk * 16) / CIN, ci = kappa - t * CIN;
+    const __bf16 *arow = dzT + ((size_t)b * COUT + co) * X;
+    const __bf16 *brow = inT + ((size_t)b * CIN + ci) * X;
+    const bool bias_tile = nk == 0;
+    float bsum = 0.0f;
+    f32x4 acc;
+    switch (t) {   // the tap, hence the shift t - 2, is uniform over the wave
+    case 0: acc = wgrad_tile<0>(arow, brow, X, kb, bias_tile, bsum); break;
+    case 1: acc = wgrad_tile<1>(arow, brow, X, kb, bias_tile, bsum); break;
+    case 2: acc = wgrad_tile<2>(arow, brow, X, kb, bias_tile, bsum); break;
+    case 3: acc = wgrad_tile<3>(arow, brow, X, kb, bias_tile, bsum); break;
+    default: acc = wgrad_tile<4>(arow, brow, X, kb, bias_tile, bsum); break;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int row = mt * 16 + kb * 4 + i;     // co
-        const int col = nk * 16 + m;              // kappa
-        if (col < K) atomicAdd(&dW[(size_t)row * KP + col], acc[i]);
+        atomicAdd(&dW[(size_t)row * KP + kappa], acc[i]);
     }
-}
-
-// Bias gradient: db[co] = sum over positions of dZ[p][co].
-template <int COUT>
-__global__ void k_bias_grad(const __bf16 *__restrict__ dz, float *__restrict__ db, int P)
-{
-    const int co = threadIdx.x % COUT;
-    const int lanes = blockDim.x / COUT;
-    float acc = 0.0f;
-    for (int p = blockIdx.x * lanes + threadIdx.x / COUT; p < P; p += gridDim.x * lanes)
-        acc += (float)dz[(size_t)p * COUT + co];
-    atomicAdd(&db[co], acc);
+    if (bias_tile) {
+        bsum += __shfl_xor(bsum, 16, 64);
+        bsum += __shfl_xor(bsum, 32, 64);
+        if (kb == 0) atomicAdd(&db[co], bsum);
+    }
 }
 
 __global__ void k_zero(float *__restrict__ p, size_t n)
@@ -371,61 +422,51 @@ __global__ void k_unpack(const float *__restrict__ y, float *__restrict__ out, i
 // ---------------------------------------------------------------------------
 using namespace sur;
 
-extern "C" hipError_t surx_features(const float *params, __bf16 *feat, int X, int B, hipStream_t s)
+extern "C" hipError_t surx_features(const float *params, __bf16 *feat, __bf16 *featT, int X, int B, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_features, dim3((X * B + 255) / 256), dim3(256), 0, s, params, feat, X, B);
+    hipLaunchKernelGGL(k_features, dim3((X * B + 255) / 256), dim3(256), 0, s, params, feat, featT, X, B);
     return hipGetLastError();
 }
 
+// ybT may be null (inference: no weight gradient follows)
 extern "C" hipError_t surx_conv_fwd(int layer, const __bf16 *in, const __bf16 *Wf, const float *bias, float *yf,
-                                    __bf16 *yb, int X, int B, hipStream_t s)
+                                    __bf16 *yb, __bf16 *ybT, int X, int B, hipStream_t s)
 {
     dim3 g(X / 64 * B), t(256);
-    if (layer == 0) hipLaunchKernelGGL((k_conv_fwd<16, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, X, B);
-    else if (layer < 5) hipLaunchKernelGGL((k_conv_fwd<64, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, X, B);
-    else hipLaunchKernelGGL((k_conv_fwd<64, 16, false>), g, t, 0, s, in, Wf, bias, yf, yb, X, B);
+    if (layer == 0) hipLaunchKernelGGL((k_conv_fwd<16, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
+    else if (layer < 5) hipLaunchKernelGGL((k_conv_fwd<64, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
+    else hipLaunchKernelGGL((k_conv_fwd<64, 16, false>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
     return hipGetLastError();
 }
 
-extern "C" hipError_t surx_loss(const float *out, const float *target, __bf16 *dz, double *loss, int X, int B,
-                                hipStream_t s)
+extern "C" hipError_t surx_loss(const float *out, const float *target, __bf16 *dz, __bf16 *dzT, double *loss, int X,
+                                int B, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_loss, dim3((X * B + 255) / 256), dim3(256), 0, s, out, target, dz, loss, X, B);
+    hipLaunchKernelGGL(k_loss, dim3((X * B + 255) / 256), dim3(256), 0, s, out, target, dz, dzT, loss, X, B);
     return hipGetLastError();
 }
 
 // input gradient of layer `layer` (1..5; layer 0 has none)
 extern "C" hipError_t surx_conv_dgrad(int layer, const __bf16 *dz, const __bf16 *Wb, const float *yprev,
-                                      __bf16 *dzprev, int X, int B, hipStream_t s)
+                                      __bf16 *dzprev, __bf16 *dzprevT, int X, int B, hipStream_t s)
 {
     dim3 g(X / 64 * B), t(256);
-    if (layer == 5) hipLaunchKernelGGL((k_conv_dgrad<64, 16>), g, t, 0, s, dz, Wb, yprev, dzprev, X, B);
-    else hipLaunchKernelGGL((k_conv_dgrad<64, 64>), g, t, 0, s, dz, Wb, yprev, dzprev, X, B);
+    if (layer == 5) hipLaunchKernelGGL((k_conv_dgrad<64, 16>), g, t, 0, s, dz, Wb, yprev, dzprev, dzprevT, X, B);
+    else hipLaunchKernelGGL((k_conv_dgrad<64, 64>), g, t, 0, s, dz, Wb, yprev, dzprev, dzprevT, X, B);
     return hipGetLastError();
 }
 
-extern "C" hipError_t surx_conv_wgrad(int layer, const __bf16 *dz, const __bf16 *in, float *dW, float *db, int X,
+// weight and bias gradients of layer `layer` from the channels-first copies
+extern "C" hipError_t surx_conv_wgrad(int layer, const __bf16 *dzT, const __bf16 *inT, float *dW, float *db, int X,
                                       int B, hipStream_t s)
 {
-    const int P = X * B;
-    const int slice = 4096;
-    const int slices = (P + slice - 1) / slice;
-    if (layer == 0) {
-        constexpr int tiles = (64 / 16) * (96 / 16);
-        hipLaunchKernelGGL((k_conv_wgrad<16, 64>), dim3((tiles * slices + 3) / 4), dim3(256), 0, s, dz, in, dW, X, B,
-                           slice);
-        hipLaunchKernelGGL(k_bias_grad<64>, dim3(64), dim3(256), 0, s, dz, db, P);
-    } else if (layer < 5) {
-        constexpr int tiles = (64 / 16) * (320 / 16);
-        hipLaunchKernelGGL((k_conv_wgrad<64, 64>), dim3((tiles * slices + 3) / 4), dim3(256), 0, s, dz, in, dW, X, B,
-                           slice);
-        hipLaunchKernelGGL(k_bias_grad<64>, dim3(64), dim3(256), 0, s, dz, db, P);
-    } else {
-        constexpr int tiles = (16 / 16) * (320 / 16);
-        hipLaunchKernelGGL((k_conv_wgrad<64, 16>), dim3((tiles * slices + 3) / 4), dim3(256), 0, s, dz, in, dW, X, B,
-                           slice);
-        hipLaunchKernelGGL(k_bias_grad<16>, dim3(64), dim3(256), 0, s, dz, db, P);
-    }
+    auto blocks = [&](int tiles) { return dim3((unsigned)((tiles * B + 3) / 4)); };
+    if (layer == 0)
+        hipLaunchKernelGGL((k_conv_wgrad<16, 64>), blocks(4 * 5), dim3(256), 0, s, dzT, inT, dW, db, X, B);
+    else if (layer < 5)
+        hipLaunchKernelGGL((k_conv_wgrad<64, 64>), blocks(4 * 20), dim3(256), 0, s, dzT, inT, dW, db, X, B);
+    else
+        hipLaunchKernelGGL((k_conv_wgrad<64, 16>), blocks(1 * 20), dim3(256), 0, s, dzT, inT, dW, db, X, B);
     return hipGetLastError();
 }
 
