@@ -168,6 +168,7 @@ void layout(const pic_config *cfgs, int nd, const std::vector<pic_derived> &der,
         D.phi = bp.take<double>(nn);
         D.E = bp.take<double>(nn);
         D.phi_sum = bp.take<double>(nn);
+        D.agg = bp.take<FieldAgg>((nn + 1023) / 1024);
     }
     zero_end = bp.off;
     for (int d = 0; d < nd; ++d) {

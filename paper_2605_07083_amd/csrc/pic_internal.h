@@ -83,6 +83,17 @@ struct IzEvent {
     uint32_t pad;
 };
 
+// Per-tile aggregates of the tiled field solve: A = sum of rho over the tile,
+// B (128-bit, lo/hi) = sum over its interior nodes of the in-tile inclusive
+// prefix of rho, n = its interior node count.
+struct FieldAgg {
+    long long A;
+    unsigned long long B_lo;
+    long long B_hi;
+    int32_t n;
+    int32_t pad;
+};
+
 // Read-only parameters and buffer pointers of one diode (device copy).
 struct Diode {
     double L, dz, invdz, V, dt, w0;
@@ -113,6 +124,7 @@ struct Diode {
     DiodeState *st;
     DiodeTally *tally;
     TallySnap *ring;
+    FieldAgg *agg;         // one per FT-node tile of the field solve
 };
 
 }  // namespace pic

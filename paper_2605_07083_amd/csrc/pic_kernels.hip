@@ -20,7 +20,7 @@ namespace pic {
 constexpr int NT = 256;            // threads per particle block
 constexpr int NW = NT / 64;        // wavefronts per particle block
 constexpr int WMAX = 1024;         // LDS window (nodes) of the field tile / histogram
-constexpr int CQ = 4096;           // LDS queue of rare work (candidates, absorptions); > 2 chunks
+constexpr int QW_SLACK = 128;      // per-wave LDS queue of rare work: 64 PPT + QW_SLACK entries
 constexpr int DRIFT = 96;          // cells of drift since the last re-sort kept in the LDS window
 constexpr double TWO32 = 4294967296.0;
 
@@ -255,7 +255,7 @@ struct ChunkCounts {
     int coll[NCH];
 };
 
-__device__ __forceinline__ void mcc_one(const Diode &dd, int s, const SpeciesBuf &b, int i, uint32_t step, double zn,
+__device__ __forceinline__ float mcc_one(const Diode &dd, int s, const SpeciesBuf &b, int i, uint32_t step, double zn,
                         float vzn, ChunkCounts *cc)
 {
     const int ion = (s == SP_I);
@@ -346,6 +346,7 @@ __device__ __forceinline__ void mcc_one(const Diode &dd, int s, const SpeciesBuf
     }
     b.vz[i] = vz;
     b.tc[i] = tcn;
+    return vz;
 }
 
 // ---------------------------------------------------------------------------
@@ -399,9 +400,10 @@ __device__ __forceinline__ void load_chunk(ChunkRegs<PPT> &C, const SpeciesBuf &
     }
 }
 
-__device__ __forceinline__ void rare_absorbed(const Diode &dd, int s, const SpeciesBuf &b, int i, int wall)
+// vzn: v_z at the crossing (v^{n+1/2})
+__device__ __forceinline__ void rare_absorbed(const Diode &dd, int s, const SpeciesBuf &b, int i, int wall, float vzn)
 {
-    const double vx = b.vx[i], vy = b.vy[i], vz = b.vz[i];
+    const double vx = b.vx[i], vy = b.vy[i], vz = vzn;
     const double ke = 0.5 * dd.mass[s] * (vx * vx + vy * vy + vz * vz);
     atomicAdd(&dd.tally->abs_count[s][wall], 1ull);
     atomicAdd(&dd.tally->abs_energy[s][wall], ke);
@@ -414,7 +416,7 @@ __device__ __forceinline__ void do_rare(const Diode &dd, int s, const SpeciesBuf
     const int i = (int)(item & RARE_MASK);
     const uint32_t kind = item >> RARE_SHIFT;
     if (kind == 0u) mcc_one(dd, s, b, i, step, b.z[i], b.vz[i], cc);
-    else rare_absorbed(dd, s, b, i, (int)kind - 1);
+    else rare_absorbed(dd, s, b, i, (int)kind - 1, b.vz[i]);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
@@ -450,8 +452,11 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
     __shared__ int seg_n[NSP * MAX_DIODES];
     __shared__ double etile[WMAX + 2];
     __shared__ unsigned long long hist[WMAX + 2];
-    __shared__ uint32_t rq[CQ];
-    __shared__ int q_n;
+    constexpr int QW = 64 * PPT + QW_SLACK;
+    __shared__ uint32_t rq_i[NW][QW];   // slot | kind << 30
+    __shared__ float rq_v[NW][QW];      // v_z after the push
+    __shared__ double rq_z[NW][QW];     // z after the push
+    __shared__ int q_n[NW];
     __shared__ ChunkCounts cc;
 
     ChunkMap cm;
@@ -489,8 +494,8 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             if (mode == 0) etile[t] = dd.E[w0 + t];
             hist[t] = 0ull;
         }
+        if (tid < NW) q_n[tid] = 0;
         if (tid == 0) {
-            q_n = 0;
             cc.cand = 0;
 #pragma unroll
             for (int k = 0; k < NCH; ++k) cc.coll[k] = 0;
@@ -499,36 +504,40 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
 
         const double qmdt = dd.qmdt[s], dt = dd.dt, L = dd.L;
         unsigned long long *H = dd.H[s];
-        // chunks of the run, then one extra pass that drains the rare-work queue;
-        // the queue is also drained before any chunk that could overflow it
+        // The chunks of the run have no barrier: each wave streams its share of
+        // every chunk, holding the next chunk's particle registers in flight
+        // while it works on the current one.  Rare work (candidates, absorbed
+        // particles) goes to the wave's LDS queue with the particle's new z and
+        // v_z, and the wave drains it at full lane occupancy when it could
+        // overflow and after the run.  The main loop does not store v_z of a
+        // candidate: the drain writes it after the collision, so no slot is
+        // written by both.
+        const int w = tid >> 6, lane = tid & 63;
+        ChunkRegs<PPT> A, Bn;
+        if (c < run_end) load_chunk<PPT>(A, b, (c - segbase) * CHUNK + tid * PPT, mode);
         for (int cc_ = c;; ++cc_) {
             const bool done = cc_ == run_end;
             if (mode == 0) {
-                lds_barrier();
-                const int qn = q_n;
-                if (done || qn > CQ - CHUNK) {
-                    // the main loop's stores precede the rare work's (workgroup-scope fence)
-                    __syncthreads();
-                    for (int q = tid; q < qn; q += NT) {
-                        const uint32_t item = rq[q];
+                const int qn = q_n[w];
+                if (done || qn > QW - 64 * PPT) {
+                    for (int q = lane; q < qn; q += 64) {
+                        const uint32_t item = rq_i[w][q];
                         const int i = (int)(item & RARE_MASK);
                         const uint32_t kind = item >> RARE_SHIFT;
-                        if (kind == 0u) mcc_one(dd, s, b, i, step, b.z[i], b.vz[i], &cc);
-                        else rare_absorbed(dd, s, b, i, (int)kind - 1);
+                        if (kind == 0u) mcc_one(dd, s, b, i, step, rq_z[w][q], rq_v[w][q], &cc);
+                        else rare_absorbed(dd, s, b, i, (int)kind - 1, rq_v[w][q]);
                     }
-                    __syncthreads();
-                    if (tid == 0) q_n = 0;
-                    lds_barrier();
+                    if (lane == 0) q_n[w] = 0;
                 }
             }
             if (done) break;
             const int t0 = (cc_ - segbase) * CHUNK + tid * PPT;
-            ChunkRegs<PPT> A;
-            load_chunk<PPT>(A, b, t0, mode);
+            if (cc_ + 1 < run_end) load_chunk<PPT>(Bn, b, t0 + CHUNK, mode);
             int jcur = -1;
             unsigned long long accL = 0ull, accA = 0ull;
             double zw[PPT];
             float vw[PPT];
+            bool keepv[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const int i = t0 + k;
@@ -536,6 +545,7 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                 double z = A.z[k];
                 zw[k] = A.z[k];
                 vw[k] = A.vz[k];
+                keepv[k] = true;
                 if (alive && mode == 0) {
                     int jo;
                     double fo;
@@ -552,20 +562,26 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                     const float vzn = (float)((double)A.vz[k] + qmdt * Ep);
                     const double zn = z + (double)vzn * dt;
                     vw[k] = vzn;
+                    uint32_t item = NEVER;
                     if (zn <= 0.0 || zn >= L) {
                         // absorbing electrodes: tallied with the rare work
                         zw[k] = -1.0;
                         alive = false;
-                        const int q = atomicAdd(&q_n, 1);
-                        rq[q] = (uint32_t)i | ((zn <= 0.0 ? 1u : 2u) << RARE_SHIFT);
+                        item = (uint32_t)i | ((zn <= 0.0 ? 1u : 2u) << RARE_SHIFT);
                     } else {
                         if (!(zn == zn)) atomicOr(&dd.st->err, ERR_NAN);
                         z = zn;
                         zw[k] = zn;
                         if (A.tc[k] == step) {
-                            const int q = atomicAdd(&q_n, 1);
-                            rq[q] = (uint32_t)i;
+                            item = (uint32_t)i;
+                            keepv[k] = false;
                         }
+                    }
+                    if (item != NEVER) {
+                        const int q = atomicAdd(&q_n[w], 1);
+                        rq_i[w][q] = item;
+                        rq_v[w][q] = vzn;
+                        rq_z[w][q] = zn;
                     }
                 }
                 if (alive) {
@@ -586,19 +602,20 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             }
             if (mode == 0) {
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    b.z[t0 + k] = zw[k];
-                    b.vz[t0 + k] = vw[k];
-                }
+                for (int k = 0; k < PPT; ++k) b.z[t0 + k] = zw[k];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+                    if (keepv[k]) b.vz[t0 + k] = vw[k];
             }
             // last run of every lane: combine across the wave when all lanes agree
             const int j0w = __shfl(jcur, 0, 64);
             if (__all(jcur == j0w)) {
                 const unsigned long long sL = wave_sum_u64(accL), sA = wave_sum_u64(accA);
-                if (lane_id() == 0 && j0w >= 0) flush_run(j0w, sL, sA, w0, wn, hist, H);
+                if (lane == 0 && j0w >= 0) flush_run(j0w, sL, sA, w0, wn, hist, H);
             } else if (jcur >= 0) {
                 flush_run(jcur, accL, accA, w0, wn, hist, H);
             }
+            A = Bn;
         }
         lds_barrier();
         for (int t = tid; t < wn; t += NT) {
@@ -1043,60 +1060,12 @@ constexpr int FT = 1024;
 constexpr int FW = FT / 64;
 constexpr size_t LDS_FIELD_BYTES = 148 * 1024;   // node arrays staged in LDS up to 18944 nodes
 
-// Block-wide exclusive scan of one value per thread (1024 threads): wave
-// scans with cross-lane shuffles, one LDS exchange of the 16 wave totals.
-__device__ __forceinline__ long long block_excl_scan_i64(long long v, long long *sh, long long &total)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    long long x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        long long y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) sh[w] = x;
-    __syncthreads();
-    long long off = 0, tot = 0;
-#pragma unroll
-    for (int q = 0; q < FW; ++q) {
-        const long long t = sh[q];
-        if (q < w) off += t;
-        tot += t;
-    }
-    __syncthreads();
-    total = tot;
-    return off + x - v;
-}
-
 __device__ __forceinline__ I128 shfl_up_i128(I128 a, int o)
 {
     I128 r;
     r.lo = __shfl_up(a.lo, o, 64);
     r.hi = __shfl_up(a.hi, o, 64);
     return r;
-}
-
-__device__ __forceinline__ I128 block_excl_scan_i128(I128 v, I128 *sh, I128 &total)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    I128 x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        I128 y = shfl_up_i128(x, o);
-        if (lane >= o) x = add(x, y);
-    }
-    if (lane == 63) sh[w] = x;
-    __syncthreads();
-    I128 off = i128(0), tot = i128(0);
-#pragma unroll
-    for (int q = 0; q < FW; ++q) {
-        const I128 t = sh[q];
-        if (q < w) off = add(off, t);
-        tot = add(tot, t);
-    }
-    __syncthreads();
-    total = tot;
-    return add(off, add(x, neg(v)));
 }
 
 __device__ __forceinline__ void deposit_global(const Diode &dd, int s, double z)
@@ -1269,9 +1238,8 @@ __device__ __forceinline__ I128 wave_incl_scan_i128(I128 x)
 }
 
 // ---------------------------------------------------------------------------
-// Sources and field: one workgroup of 1024 threads per diode.  Nodes are
-// handled in TILES coalesced tiles of 1024 (node j = t * 1024 + thread).
-// mode 0: births, solve, field, tallies, step + 1; mode 1: solve and field only.
+// Sources and field.  mode 0: births, solve, field, tallies, step + 1;
+// mode 1: solve and field only.
 //
 // Poisson: phi_{j-1} - 2 phi_j + phi_{j+1} = -alpha R_j (j = 1..N-1),
 // phi_0 = 0, phi_N = V, R = H_I - H_P - H_E.  With S1_j = sum_{k=1..j} R_k and
@@ -1279,145 +1247,6 @@ __device__ __forceinline__ I128 wave_incl_scan_i128(I128 x)
 // phi_j = V j / N + alpha (j T_N - N T_j) / N: the direct solution of the
 // constant-coefficient Dirichlet system, rounded once at the end.
 // ---------------------------------------------------------------------------
-template <int TILES>
-__global__ __launch_bounds__(FT) void k_sources_field(const Diode *__restrict__ D, DiodeState *__restrict__ S,
-                                                      int mode, int parity)
-{
-    const Diode &dd = D[blockIdx.x];
-    DiodeState *st = S + blockIdx.x;
-    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
-    __shared__ unsigned long long keys[IZQ_CAP];
-    __shared__ long long tot64[TILES * FW];
-    __shared__ I128 tot128[TILES * FW];
-    __shared__ I128 s_TN;
-    const uint32_t step = st->step;
-
-    if (mode == 0) sources(dd, st, keys, step, parity);
-    __syncthreads();
-
-    const int N = dd.N;
-    const int nn = N + 1;
-    // R at the owned nodes (coalesced), wave-inclusive scans, wave totals to LDS
-    long long S1[TILES];
-#pragma unroll
-    for (int t = 0; t < TILES; ++t) {
-        const int j = t * FT + tid;
-        long long r = 0;
-        if (j >= 1 && j <= N - 1) r = (long long)(dd.H[SP_I][j] - dd.H[SP_P][j] - dd.H[SP_E][j]);
-        S1[t] = wave_incl_scan_i64(r);
-        if (lane == 63) tot64[t * FW + w] = S1[t];
-    }
-    __syncthreads();
-    if (w == 0) {
-        // exclusive scan of the TILES*FW wave totals (in node order), by wave 0
-        constexpr int PERL = (TILES * FW + 63) / 64;
-        long long v[PERL];
-        long long run = 0;
-#pragma unroll
-        for (int q = 0; q < PERL; ++q) {
-            const int idx = lane * PERL + q;
-            v[q] = idx < TILES * FW ? tot64[idx] : 0;
-            run += v[q];
-        }
-        const long long incl = wave_incl_scan_i64(run);
-        long long off = incl - run;
-#pragma unroll
-        for (int q = 0; q < PERL; ++q) {
-            const int idx = lane * PERL + q;
-            if (idx < TILES * FW) tot64[idx] = off;
-            off += v[q];
-        }
-    }
-    __syncthreads();
-    // S1_j, and the wave sums of the T increments (S1 at interior nodes)
-#pragma unroll
-    for (int t = 0; t < TILES; ++t) {
-        S1[t] += tot64[t * FW + w];
-        const int j = t * FT + tid;
-        const long long m = (j >= 1 && j <= N - 1) ? S1[t] : 0;
-        I128 x = i128(m);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            I128 y;
-            y.lo = __shfl_xor(x.lo, o, 64);
-            y.hi = __shfl_xor(x.hi, o, 64);
-            x = add(x, y);
-        }
-        if (lane == 0) tot128[t * FW + w] = x;
-    }
-    __syncthreads();
-    if (w == 0) {
-        constexpr int PERL = (TILES * FW + 63) / 64;
-        I128 v[PERL];
-        I128 run = i128(0);
-#pragma unroll
-        for (int q = 0; q < PERL; ++q) {
-            const int idx = lane * PERL + q;
-            v[q] = idx < TILES * FW ? tot128[idx] : i128(0);
-            run = add(run, v[q]);
-        }
-        const I128 incl = wave_incl_scan_i128(run);
-        I128 off = add(incl, neg(run));
-#pragma unroll
-        for (int q = 0; q < PERL; ++q) {
-            const int idx = lane * PERL + q;
-            if (idx < TILES * FW) tot128[idx] = off;
-            off = add(off, v[q]);
-        }
-        if (lane == 63) s_TN = incl;
-    }
-    __syncthreads();
-    const I128 T_N = s_TN;
-    const double alpha_n = dd.alpha / (double)N;
-#pragma unroll
-    for (int t = 0; t < TILES; ++t) {
-        const int j = t * FT + tid;
-        const long long m = (j >= 1 && j <= N - 1) ? S1[t] : 0;
-        const I128 mi = i128(m);
-        const I128 T = add(add(wave_incl_scan_i128(mi), neg(mi)), tot128[t * FW + w]);   // T_j
-        if (j < nn) {
-            double v = 0.0;
-            if (j == N) v = dd.V;
-            else if (j >= 1) {
-                const I128 x = add(mul_small(T_N, (unsigned)j), neg(mul_small(T, (unsigned)N)));
-                v = dd.V * (double)j / (double)N + alpha_n * to_double(x);
-            }
-            dd.phi[j] = v;
-        }
-    }
-    __syncthreads();
-    const double inv2dz = 1.0 / (2.0 * dd.dz);
-    const int avg = st->avg_on;
-    for (int j = tid; j < nn; j += FT) {
-        double E;
-        const double pc = dd.phi[j];
-        if (j == 0) E = (pc - dd.phi[1]) / dd.dz;
-        else if (j == N) E = (dd.phi[N - 1] - pc) / dd.dz;
-        else E = (dd.phi[j - 1] - dd.phi[j + 1]) * inv2dz;
-        dd.E[j] = E;
-        // keep the last deposit, clear the accumulators, time averages
-#pragma unroll
-        for (int s = 0; s < NSP; ++s) {
-            const long long h = (long long)dd.H[s][j];
-            dd.Hlast[s][j] = h;
-            dd.H[s][j] = 0ull;
-            if (avg) dd.Hsum[s][j] += h;
-        }
-        if (avg) dd.phi_sum[j] += pc;
-    }
-    __syncthreads();
-    if (mode == 0 && tid == 0) {
-        const uint32_t nstep = step + 1u;
-        st->step = nstep;
-        if (avg) st->avg_steps += 1;
-        if (dd.tally_period > 0 && nstep % (uint32_t)dd.tally_period == 0u) {
-            TallySnap &sn = dd.ring[(nstep / (uint32_t)dd.tally_period) % RING];
-            sn.step = nstep;
-            sn.t = *dd.tally;
-        }
-    }
-}
-
 // Same step with the node arrays staged in LDS (dynamic shared memory of
 // nn * 8 bytes): coalesced loads, then each thread walks PER consecutive nodes
 // serially in registers, with two block scans of the per-thread totals.
@@ -1544,6 +1373,153 @@ __global__ __launch_bounds__(FT) void k_sources_field_lds(const Diode *__restric
     }
 }
 
+// ---------------------------------------------------------------------------
+// Large grids: the same step spread over tiles of FT nodes, so that the node
+// arrays move through many CUs instead of one.
+//   k_births       births of the step (one block per diode).
+//   k_field_agg    per tile: A_t = sum of rho over the tile, B_t = sum over the
+//                  tile's interior nodes of the in-tile inclusive prefix of rho.
+//   k_field_solve  per tile: with P_t = sum_{u<t} A_u (= S1 before the tile),
+//                  Q_t = sum_{u<t} (n_u P_u + B_u) (= T before the tile) and
+//                  T_N from all tiles, the exact S1_j and T_j of its nodes and
+//                  of one halo node on each side, phi_j and E_j as in the
+//                  single-block kernel, and the node bookkeeping.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(FT) void k_births(const Diode *__restrict__ D, DiodeState *__restrict__ S, int parity)
+{
+    extern __shared__ long long nodes[];
+    const Diode &dd = D[blockIdx.x];
+    DiodeState *st = S + blockIdx.x;
+    sources(dd, st, reinterpret_cast<unsigned long long *>(nodes), st->step, parity);
+}
+
+__device__ __forceinline__ long long node_rho(const Diode &dd, int j)
+{
+    if (j < 1 || j > dd.N - 1) return 0;
+    return (long long)(dd.H[SP_I][j] - dd.H[SP_P][j] - dd.H[SP_E][j]);
+}
+
+__global__ __launch_bounds__(FT) void k_field_agg(const Diode *__restrict__ D)
+{
+    const Diode &dd = D[blockIdx.y];
+    const int t = blockIdx.x, nn = dd.N + 1;
+    const int a = t * FT;
+    if (a >= nn) return;
+    __shared__ long long sh64[FW];
+    __shared__ I128 sh128[FW];
+    const int j = a + threadIdx.x;
+    const long long r = j < nn ? node_rho(dd, j) : 0;
+    long long A;
+    const long long excl = block_scan_excl_i64(r, sh64, A);
+    const bool interior = j >= 1 && j <= dd.N - 1;
+    I128 B;
+    block_scan_excl_i128(interior ? i128(excl + r) : i128(0), sh128, B);
+    if (threadIdx.x == 0) {
+        FieldAgg &g = dd.agg[t];
+        g.A = A;
+        g.B_lo = B.lo;
+        g.B_hi = B.hi;
+        g.n = max(0, min(a + FT, dd.N) - max(a, 1));
+    }
+}
+
+__device__ __forceinline__ double phi_node(const Diode &dd, int j, const I128 &T_N, const I128 &Tj)
+{
+    const int N = dd.N;
+    if (j <= 0) return 0.0;
+    if (j >= N) return dd.V;
+    const I128 x = add(mul_small(T_N, (unsigned)j), neg(mul_small(Tj, (unsigned)N)));
+    return dd.V * (double)j / (double)N + (dd.alpha / (double)N) * to_double(x);
+}
+
+__global__ __launch_bounds__(FT) void k_field_solve(const Diode *__restrict__ D, DiodeState *__restrict__ S, int mode,
+                                                    int ntiles)
+{
+    const Diode &dd = D[blockIdx.y];
+    DiodeState *st = S + blockIdx.y;
+    const int t = blockIdx.x, N = dd.N, nn = N + 1;
+    const int a = t * FT;
+    if (a >= nn) return;
+    const int b = min(nn, a + FT);
+    __shared__ long long sh64[FW];
+    __shared__ I128 sh128[FW];
+    __shared__ double ph[FT + 2];
+    __shared__ long long s_P;
+    __shared__ I128 s_Q, s_TN;
+    if (threadIdx.x == 0) {
+        long long P = 0, Pt = 0;
+        I128 Q = i128(0), TN = i128(0);
+        const int nt = min(ntiles, (nn + FT - 1) / FT);
+        for (int u = 0; u < nt; ++u) {
+            const FieldAgg g = dd.agg[u];
+            I128 Bu;
+            Bu.lo = g.B_lo;
+            Bu.hi = g.B_hi;
+            // S1 summed over tile u: its n interior nodes each carry P_u, plus B_u
+            const I128 su = add(mul_small(i128(P), (unsigned)g.n), Bu);
+            if (u < t) Q = add(Q, su);
+            if (u == t) Pt = P;
+            TN = add(TN, su);
+            P += g.A;
+        }
+        s_P = Pt;
+        s_Q = Q;
+        s_TN = TN;
+    }
+    __syncthreads();
+    const long long P = s_P;
+    const I128 Q = s_Q, T_N = s_TN;
+    const int j = a + threadIdx.x;
+    const long long r = j < b ? node_rho(dd, j) : 0;
+    long long Aloc;
+    const long long S1 = P + block_scan_excl_i64(r, sh64, Aloc) + r;      // inclusive S1_j
+    const bool interior = j >= 1 && j <= N - 1 && j < b;
+    I128 Tsum;
+    const I128 Tloc = block_scan_excl_i128(interior ? i128(S1) : i128(0), sh128, Tsum);
+    const I128 Tj = add(Q, Tloc);                                        // sum_{m=1..j-1} S1_m
+    if (j < b) ph[threadIdx.x + 1] = phi_node(dd, j, T_N, Tj);
+    if (threadIdx.x == 0) {
+        // halo below: T_{a-1} = Q - S1_{a-1} if a-1 is interior, S1_{a-1} = P
+        if (a >= 1) {
+            const int jm = a - 1;
+            const I128 Tm = (jm >= 1 && jm <= N - 1) ? add(Q, neg(i128(P))) : Q;
+            ph[0] = phi_node(dd, jm, T_N, Tm);
+        }
+        // halo above: T_b = Q + (sum over the tile's interior nodes of S1)
+        if (b <= N) ph[b - a + 1] = phi_node(dd, b, T_N, add(Q, Tsum));
+    }
+    __syncthreads();
+    if (j < b) {
+        const int k = threadIdx.x + 1;
+        const double pc = ph[k];
+        double E;
+        if (j == 0) E = (pc - ph[k + 1]) / dd.dz;
+        else if (j == N) E = (ph[k - 1] - pc) / dd.dz;
+        else E = (ph[k - 1] - ph[k + 1]) * (1.0 / (2.0 * dd.dz));
+        dd.phi[j] = pc;
+        dd.E[j] = E;
+        const int avg = st->avg_on;
+#pragma unroll
+        for (int sp = 0; sp < NSP; ++sp) {
+            const long long h = (long long)dd.H[sp][j];
+            dd.Hlast[sp][j] = h;
+            dd.H[sp][j] = 0ull;
+            if (avg) dd.Hsum[sp][j] += h;
+        }
+        if (avg) dd.phi_sum[j] += pc;
+    }
+    if (mode == 0 && t == 0 && threadIdx.x == 0) {
+        const uint32_t nstep = st->step + 1u;
+        st->step = nstep;
+        if (st->avg_on) st->avg_steps += 1;
+        if (dd.tally_period > 0 && nstep % (uint32_t)dd.tally_period == 0u) {
+            TallySnap &sn = dd.ring[(nstep / (uint32_t)dd.tally_period) % RING];
+            sn.step = nstep;
+            sn.t = *dd.tally;
+        }
+    }
+}
+
 }  // namespace pic
 
 // ---------------------------------------------------------------------------
@@ -1585,27 +1561,24 @@ extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int n
     return hipGetLastError();
 }
 
-// max_nodes: the largest N + 1 over the diodes (<= 32768)
+// max_nodes: the largest N + 1 over the diodes.  Up to FIELD_TILE_MIN nodes
+// one block per diode does the whole step (fewest launches); above, births,
+// tile aggregates and the tiled solve run as three kernels over many CUs.
+constexpr int FIELD_TILE_MIN = 8192;
+
 extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
                                                 int parity, hipStream_t s)
 {
-    if ((size_t)max_nodes * 8 <= LDS_FIELD_BYTES) {
-        const size_t bytes = (size_t)max(max_nodes, IZQ_CAP) * 8;
+    const size_t keys = (size_t)IZQ_CAP * 8;
+    if (max_nodes <= FIELD_TILE_MIN) {
+        const size_t bytes = std::max((size_t)max_nodes * 8, keys);
         hipLaunchKernelGGL(k_sources_field_lds, dim3(nd), dim3(FT), bytes, s, D, S, mode, parity);
         return hipGetLastError();
     }
     const int tiles = (max_nodes + FT - 1) / FT;
-#define LAUNCH_SF(T) hipLaunchKernelGGL(k_sources_field<T>, dim3(nd), dim3(FT), 0, s, D, S, mode, parity)
-    if (tiles <= 1) LAUNCH_SF(1);
-    else if (tiles <= 2) LAUNCH_SF(2);
-    else if (tiles <= 3) LAUNCH_SF(3);
-    else if (tiles <= 4) LAUNCH_SF(4);
-    else if (tiles <= 8) LAUNCH_SF(8);
-    else if (tiles <= 12) LAUNCH_SF(12);
-    else if (tiles <= 17) LAUNCH_SF(17);
-    else if (tiles <= 24) LAUNCH_SF(24);
-    else LAUNCH_SF(32);
-#undef LAUNCH_SF
+    if (mode == 0) hipLaunchKernelGGL(k_births, dim3(nd), dim3(FT), keys, s, D, S, parity);
+    hipLaunchKernelGGL(k_field_agg, dim3(tiles, nd), dim3(FT), 0, s, D);
+    hipLaunchKernelGGL(k_field_solve, dim3(tiles, nd), dim3(FT), 0, s, D, S, mode, tiles);
     return hipGetLastError();
 }
 

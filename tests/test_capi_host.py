@@ -44,7 +44,10 @@ def test_surrogate_workspace_and_shapes():
     assert surrogate.N_WEIGHTS == 88000 and surrogate.N_BIASES == 323
     a = surrogate.workspace_size(1, 2048)
     b = surrogate.workspace_size(32, 2048)
-    assert b > 20 * (a - 2_000_000) and b < 200 * 2 ** 20
+    # per position: features 2 x 16 bf16, outputs 5 x 64 + 16 FP32, hidden bf16
+    # copies 2 x 5 x 64, two gradient buffers 2 x 2 x 64 bf16 = 3200 bytes
+    per_pos = 2 * 16 * 2 + (5 * 64 + 16) * 4 + 2 * 5 * 64 * 2 + 2 * 2 * 64 * 2
+    assert abs((b - a) - per_pos * 31 * 2048) < 64 * 1024
     for bad in ((0, 2048), (4, 100), (4, 0)):
         with pytest.raises(pic.PicError) as e:
             surrogate.workspace_size(*bad)

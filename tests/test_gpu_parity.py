@@ -225,3 +225,20 @@ def test_steady_state_on_device(pic):
     assert st["block_steps"] == 200
     if st["steady"]:
         assert st["steady_step"] % 200 == 0 and st["steady_step"] <= 3000
+
+
+def test_tiled_field_path_ragged(pic, O):
+    """Grids above 8192 nodes take the multi-block field solve (births, tile
+    aggregates, tiled solve): a ragged 9001-node diode batched with a 257-node
+    one, field and deposit against the oracle, then restart parity."""
+    _say("case: tiled field path, N = 9000 with N = 256 in one batch")
+    big = presets.scaled(presets.tiny(), N=9000, L=5e-3 * 9000 / 256, n_load=180000, gamma_emit=3e21, diode=0)
+    small = presets.scaled(presets.tiny(), gamma_emit=1e21, diode=1)
+    h = pic.Handle([big, small])
+    for d, cfg in enumerate((big, small)):
+        st, t = gpu_state(h, d)
+        assert deposit_matches(O, cfg, h, st, d) == []
+        s = oracle_from_gpu(O, cfg, st, t)
+        assert field_matches(O, cfg, h, s, d) == []
+    assert restart_step_check(O, big, h, 8, d=0) == []
+    assert restart_step_check(O, small, h, 4, d=1) == []
