@@ -183,6 +183,7 @@ void layout(const pic_config *cfgs, int nd, const std::vector<pic_derived> &der,
                 D.buf[p][s].id = bp.take<uint32_t>(cap);
                 D.buf[p][s].tc = bp.take<uint32_t>(cap);
             }
+        for (int s = 0; s < NSP; ++s) D.rare[s] = bp.take<uint32_t>((size_t)der[d].capacity[s]);
     }
 }
 
@@ -281,7 +282,7 @@ int grid_for(const pic_handle *h)
     int64_t chunks = 0;
     for (int d = 0; d < h->nd; ++d)
         for (int s = 0; s < NSP; ++s) chunks += (h->der[d].capacity[s] + 256 * h->ppt - 1) / (256 * h->ppt);
-    int64_t g = std::min<int64_t>(chunks, 2048);
+    int64_t g = std::min<int64_t>(chunks, 4096);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     return (int)g;
 }
@@ -1038,7 +1039,7 @@ int pic_autotune(pic_handle *h, int64_t trial_steps, int *ppt, int *grid, int *s
     int bg = h->grid;
     double best = 1e300, ms;
     int rc;
-    for (int p : {2, 4, 8}) {
+    for (int p : {1, 2, 4}) {
         if ((rc = timed(p, 0, bk, bu, ms))) return rc;
         if (ms < best) { best = ms; bp = p; bg = h->grid; }
     }
@@ -1048,7 +1049,7 @@ int pic_autotune(pic_handle *h, int64_t trial_steps, int *ppt, int *grid, int *s
             if (ms < best * 0.999) { best = ms; bk = k; }
         }
     }
-    for (int g : {256, 512, 1024, 2048}) {
+    for (int g : {512, 1024, 2048, 4096, 8192}) {
         if ((rc = timed(bp, g, bk, bu, ms))) return rc;
         if (ms < best * 0.999) { best = ms; bg = g; }
     }

@@ -8,7 +8,9 @@
 //   * sort scratch (one int32 per cell and species), the ionisation queue,
 //     the mutable state block, cumulative tallies and a ring of snapshots.
 // The hot loop streams z (r/w), vz (r/w) and tc (r) only; vx, vy and id are
-// touched for null-collision candidates and absorbed particles.
+// touched for null-collision candidates and absorbed particles, which the hot
+// loop lists per species (one u32 per slot of capacity) for the sources
+// kernels.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -59,6 +61,8 @@ struct DiodeState {
     uint32_t err;
     int32_t avg_on;
     int32_t avg_steps;
+    int32_t rare_n[NSP];   // rare items (candidates, absorbed) listed this step
+    uint32_t pad;
 };
 
 // Cumulative tallies (device); all integers are order independent.
@@ -81,6 +85,18 @@ struct IzEvent {
     float ve[3];   // secondary electron
     float vi[3];   // new ion
     uint32_t pad;
+};
+
+// Tallies of one block's rare work (collision candidates, absorbed
+// particles), accumulated in LDS and flushed once: candidate and channel
+// counts per electron/ion class, absorbed counts and energies per
+// (species, wall), ions lost.
+struct RareTally {
+    unsigned int cand[2];
+    unsigned int coll[NCH];
+    unsigned int abs_count[NSP][2];
+    int ion_lost;
+    double abs_energy[NSP][2];
 };
 
 // Per-tile aggregates of the tiled field solve: A = sum of rho over the tile,
@@ -125,6 +141,7 @@ struct Diode {
     DiodeTally *tally;
     TallySnap *ring;
     FieldAgg *agg;         // one per FT-node tile of the field solve
+    uint32_t *rare[NSP];   // the step's rare items per species: slot | kind << 30
 };
 
 }  // namespace pic

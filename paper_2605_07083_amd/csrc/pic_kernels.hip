@@ -19,9 +19,11 @@ namespace pic {
 
 constexpr int NT = 256;            // threads per particle block
 constexpr int NW = NT / 64;        // wavefronts per particle block
-constexpr int WMAX = 1024;         // LDS window (nodes) of the field tile / histogram
-constexpr int QW_SLACK = 128;      // per-wave LDS queue of rare work: 64 PPT + QW_SLACK entries
+constexpr int WMAX = 512;          // LDS window (nodes) of the field tile / histogram
+constexpr int QW_SLACK = 1024;     // per-wave LDS queue of rare items: 64 PPT + QW_SLACK entries
 constexpr int DRIFT = 96;          // cells of drift since the last re-sort kept in the LDS window
+constexpr int FT = 1024;           // threads of the sources / field blocks
+constexpr int FW = FT / 64;
 constexpr double TWO32 = 4294967296.0;
 
 // ---------------------------------------------------------------------------
@@ -182,6 +184,11 @@ __device__ __forceinline__ void run_extent(int key, int &start, int &len)
 // ---------------------------------------------------------------------------
 // Chunk map shared by the persistent particle and sort kernels.
 // ---------------------------------------------------------------------------
+// A block-uniform integer (read from LDS or loaded by every lane from one
+// address) made a scalar, so that what is derived from it (diode, species,
+// buffer pointers, parameters) lives in scalar registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 struct ChunkMap {
     int nseg;
     int total;
@@ -214,7 +221,7 @@ __device__ void build_chunk_map(const DiodeState *__restrict__ S, int nd, int ch
     }
     __syncthreads();
     cm.nseg = nseg;
-    cm.total = seg_end[nseg - 1];
+    cm.total = uni(seg_end[nseg - 1]);
 }
 
 // Chunks [first, total) with stride, XCD-grouped when the grid is a multiple of 8:
@@ -250,25 +257,29 @@ __device__ __forceinline__ int find_seg(const int *seg_end, int nseg, int c)
 // a uniform times nu_max picks the first channel whose cumulative frequency
 // exceeds it, otherwise the collision is null.
 // ---------------------------------------------------------------------------
-struct ChunkCounts {
-    int cand;
-    int coll[NCH];
-};
+__device__ __forceinline__ void rare_tally_zero(RareTally *t)
+{
+    // called by thread 0 only, before a barrier
+    *t = RareTally{};
+}
 
 __device__ __forceinline__ float mcc_one(const Diode &dd, int s, const SpeciesBuf &b, int i, uint32_t step, double zn,
-                        float vzn, ChunkCounts *cc)
+                        float vzn, RareTally *cc)
 {
     const int ion = (s == SP_I);
     float vx = b.vx[i], vy = b.vy[i], vz = vzn;
     const uint32_t id = b.id[i];
-    uint4 C0 = philox(step, EV_COLL, 0u, 0u, id, dd.kseed);
-    uint4 C1 = philox(step, EV_COLL, 1u, 0u, id, dd.kseed);
-    uint4 C2 = philox(step, EV_COLL, 2u, 0u, id, dd.kseed);
+    // The three counter blocks are generated one at a time, each consumed
+    // before the next (scheduling barriers keep their rounds from being
+    // interleaved, which would hold all of them live at once).
+    const uint4 C0 = philox(step, EV_COLL, 0u, 0u, id, dd.kseed);
     const float sn = dd.sig_n[ion];
     float a1, a2, a3, a4;
     bm24(C0.x, C0.y, a1, a2);
     bm24(C0.z, C0.w, a3, a4);
     const float vnx = sn * a1, vny = sn * a2, vnz = sn * a3;
+    __builtin_amdgcn_sched_barrier(0);
+    const uint4 C1 = philox(step, EV_COLL, 1u, 0u, id, dd.kseed);
     const float gx = vx - vnx, gy = vy - vny, gz = vz - vnz;
     const float g2 = gx * gx + gy * gy + gz * gz;
     const float gm = sqrtf(g2);
@@ -296,10 +307,12 @@ __device__ __forceinline__ float mcc_one(const Diode &dd, int s, const SpeciesBu
         if (taken < 0 && r < cum) taken = CH_IZ;
     }
     if (cum > dd.numax_f[ion]) atomicOr(&dd.st->err, ERR_NULLCOLL);
+    __builtin_amdgcn_sched_barrier(0);
+    const uint4 C2 = philox(step, EV_COLL, 2u, 0u, id, dd.kseed);
     const uint32_t tcn = next_candidate(step, dd.lam[ion], C2.z, C2.w);
-    atomicAdd(&cc->cand, 1);
+    atomicAdd(&cc->cand[ion], 1u);
     if (taken >= 0) {
-        atomicAdd(&cc->coll[taken], 1);
+        atomicAdd(&cc->coll[taken], 1u);
         const float fm = dd.mfrac_m[ion], fM = dd.mfrac_M[ion];
         const float cx = fm * vx + fM * vnx, cy = fm * vy + fM * vny, cz = fm * vz + fM * vnz;
         if (taken == CH_CX) {
@@ -401,22 +414,71 @@ __device__ __forceinline__ void load_chunk(ChunkRegs<PPT> &C, const SpeciesBuf &
 }
 
 // vzn: v_z at the crossing (v^{n+1/2})
-__device__ __forceinline__ void rare_absorbed(const Diode &dd, int s, const SpeciesBuf &b, int i, int wall, float vzn)
+__device__ __forceinline__ void rare_absorbed(const Diode &dd, int s, const SpeciesBuf &b, int i, int wall, float vzn,
+                                              RareTally *rt)
 {
     const double vx = b.vx[i], vy = b.vy[i], vz = vzn;
     const double ke = 0.5 * dd.mass[s] * (vx * vx + vy * vy + vz * vz);
-    atomicAdd(&dd.tally->abs_count[s][wall], 1ull);
-    atomicAdd(&dd.tally->abs_energy[s][wall], ke);
-    if (s == SP_I) atomicAdd(&dd.st->ion_lost, 1);
+    atomicAdd(&rt->abs_count[s][wall], 1u);
+    atomicAdd(&rt->abs_energy[s][wall], ke);
+    if (s == SP_I) atomicAdd(&rt->ion_lost, 1);
 }
 
-__device__ __forceinline__ void do_rare(const Diode &dd, int s, const SpeciesBuf &b, uint32_t item, uint32_t step,
-                                        ChunkCounts *cc)
+
+// The step's rare items of one diode (all species): collisions of candidates,
+// tallies of absorbed particles, into the block's LDS tally.  Items
+// [first, n) with stride `stride` of each list.
+__device__ __forceinline__ void process_rare(const Diode &dd, const DiodeState *st, int parity, uint32_t step,
+                                             int first, int stride, RareTally *rt)
 {
-    const int i = (int)(item & RARE_MASK);
-    const uint32_t kind = item >> RARE_SHIFT;
-    if (kind == 0u) mcc_one(dd, s, b, i, step, b.z[i], b.vz[i], cc);
-    else rare_absorbed(dd, s, b, i, (int)kind - 1, b.vz[i]);
+#pragma unroll 1
+    for (int s = 0; s < NSP; ++s) {
+        const int n = st->rare_n[s];
+        const SpeciesBuf b = dd.buf[parity][s];
+        for (int k = first; k < n; k += stride) {
+            const uint32_t item = dd.rare[s][k];
+            const int i = (int)(item & RARE_MASK);
+            const uint32_t kind = item >> RARE_SHIFT;
+            if (kind == 0u) mcc_one(dd, s, b, i, step, b.z[i], b.vz[i], rt);
+            else rare_absorbed(dd, s, b, i, (int)kind - 1, b.vz[i], rt);
+        }
+    }
+}
+
+// Add a block-run tally to the diode's tallies with device atomics (the
+// particle kernel's runs end at different times, so these rarely contend).
+__device__ __forceinline__ void flush_tally(const Diode &dd, const RareTally &t)
+{
+    for (int ion = 0; ion < 2; ++ion)
+        if (t.cand[ion]) atomicAdd(&dd.tally->cand[ion], (unsigned long long)t.cand[ion]);
+#pragma unroll
+    for (int k = 0; k < NCH; ++k)
+        if (t.coll[k]) atomicAdd(&dd.tally->coll[k], (unsigned long long)t.coll[k]);
+#pragma unroll
+    for (int sp = 0; sp < NSP; ++sp)
+        for (int w = 0; w < 2; ++w)
+            if (t.abs_count[sp][w]) {
+                atomicAdd(&dd.tally->abs_count[sp][w], (unsigned long long)t.abs_count[sp][w]);
+                atomicAdd(&dd.tally->abs_energy[sp][w], t.abs_energy[sp][w]);
+            }
+    if (t.ion_lost) atomicAdd(&dd.st->ion_lost, t.ion_lost);
+}
+
+// Add a block tally to the diode's cumulative tallies and ion-loss count.
+__device__ __forceinline__ void apply_tally(const Diode &dd, DiodeState *st, const RareTally &t)
+{
+    for (int ion = 0; ion < 2; ++ion)
+        if (t.cand[ion]) dd.tally->cand[ion] += t.cand[ion];
+#pragma unroll
+    for (int k = 0; k < NCH; ++k)
+        if (t.coll[k]) dd.tally->coll[k] += t.coll[k];
+#pragma unroll
+    for (int sp = 0; sp < NSP; ++sp)
+        for (int w = 0; w < 2; ++w) {
+            dd.tally->abs_count[sp][w] += t.abs_count[sp][w];
+            dd.tally->abs_energy[sp][w] += t.abs_energy[sp][w];
+        }
+    if (t.ion_lost) atomicAdd(&st->ion_lost, t.ion_lost);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
@@ -448,17 +510,16 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                                                   int nd, int mode, int parity)
 {
     constexpr int CHUNK = NT * PPT;
-    __shared__ int seg_end[NSP * MAX_DIODES];
-    __shared__ int seg_n[NSP * MAX_DIODES];
+    extern __shared__ int seg_dyn[];    // seg_end, seg_n: NSP * nd each
+    int *seg_end = seg_dyn, *seg_n = seg_dyn + NSP * nd;
     __shared__ double etile[WMAX + 2];
     __shared__ unsigned long long hist[WMAX + 2];
     constexpr int QW = 64 * PPT + QW_SLACK;
     __shared__ uint32_t rq_i[NW][QW];   // slot | kind << 30
-    __shared__ float rq_v[NW][QW];      // v_z after the push
-    __shared__ double rq_z[NW][QW];     // z after the push
     __shared__ int q_n[NW];
-    __shared__ ChunkCounts cc;
+    __shared__ RareTally rt;
 
+    if (threadIdx.x == 0) rare_tally_zero(&rt);
     ChunkMap cm;
     build_chunk_map(S, nd, CHUNK, false, seg_end, cm, seg_n);
     const int tid = threadIdx.x;
@@ -467,18 +528,18 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
     const int c_end = min(cm.total, c_begin + per_block);
 
     for (int c = c_begin; c < c_end;) {
-        const int seg = find_seg(seg_end, cm.nseg, c);
-        const int run_end = min(c_end, seg_end[seg]);
-        const int segbase = seg ? seg_end[seg - 1] : 0;
+        const int seg = uni(find_seg(seg_end, cm.nseg, c));
+        const int run_end = uni(min(c_end, seg_end[seg]));
+        const int segbase = uni(seg ? seg_end[seg - 1] : 0);
         const int d = seg / NSP, s = seg - d * NSP;
         const Diode &dd = D[d];
         const SpeciesBuf b = dd.buf[parity][s];
         const int N = dd.N;
         const double invdz = dd.invdz;
-        const int n = seg_n[seg];
+        const int n = uni(seg_n[seg]);
         const int slot0 = (c - segbase) * CHUNK;
 
-        const uint32_t step = S[d].step;
+        const uint32_t step = (uint32_t)uni((int)S[d].step);
         // window of the run from its first and last particle
         const int last_slot = min(n, (run_end - segbase) * CHUNK) - 1;
         int w0, wn;
@@ -487,57 +548,46 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             double f;
             cic(b.z[slot0], invdz, N, ja, f);
             cic(b.z[max(last_slot, slot0)], invdz, N, jb, f);
-            w0 = max(0, min(ja, jb) - DRIFT);
-            wn = min(min(N, max(ja, jb) + 1 + DRIFT) - w0 + 1, WMAX + 1);
+            w0 = uni(max(0, min(ja, jb) - DRIFT));
+            wn = uni(min(min(N, max(ja, jb) + 1 + DRIFT) - w0 + 1, WMAX + 1));
         }
         for (int t = tid; t < wn; t += NT) {
             if (mode == 0) etile[t] = dd.E[w0 + t];
             hist[t] = 0ull;
         }
         if (tid < NW) q_n[tid] = 0;
-        if (tid == 0) {
-            cc.cand = 0;
-#pragma unroll
-            for (int k = 0; k < NCH; ++k) cc.coll[k] = 0;
-        }
         lds_barrier();
 
         const double qmdt = dd.qmdt[s], dt = dd.dt, L = dd.L;
         unsigned long long *H = dd.H[s];
         // The chunks of the run have no barrier: each wave streams its share of
         // every chunk, holding the next chunk's particle registers in flight
-        // while it works on the current one.  Rare work (candidates, absorbed
-        // particles) goes to the wave's LDS queue with the particle's new z and
-        // v_z, and the wave drains it at full lane occupancy when it could
-        // overflow and after the run.  The main loop does not store v_z of a
-        // candidate: the drain writes it after the collision, so no slot is
-        // written by both.
+        // while it works on the current one.  Rare items (collision candidates,
+        // absorbed particles) go to the wave's LDS queue and are done by the
+        // whole block after the run.  A wave whose queue could overflow moves
+        // its items to the species' list in global memory instead, which the
+        // sources kernels work through.
         const int w = tid >> 6, lane = tid & 63;
+        uint32_t *rare = dd.rare[s];
         ChunkRegs<PPT> A, Bn;
         if (c < run_end) load_chunk<PPT>(A, b, (c - segbase) * CHUNK + tid * PPT, mode);
-        for (int cc_ = c;; ++cc_) {
-            const bool done = cc_ == run_end;
+        for (int cc_ = c; cc_ < run_end; ++cc_) {
             if (mode == 0) {
                 const int qn = q_n[w];
-                if (done || qn > QW - 64 * PPT) {
-                    for (int q = lane; q < qn; q += 64) {
-                        const uint32_t item = rq_i[w][q];
-                        const int i = (int)(item & RARE_MASK);
-                        const uint32_t kind = item >> RARE_SHIFT;
-                        if (kind == 0u) mcc_one(dd, s, b, i, step, rq_z[w][q], rq_v[w][q], &cc);
-                        else rare_absorbed(dd, s, b, i, (int)kind - 1, rq_v[w][q]);
-                    }
+                if (qn > QW - 64 * PPT) {
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(&dd.st->rare_n[s], qn);
+                    base = __shfl(base, 0, 64);
+                    for (int q = lane; q < qn; q += 64) rare[base + q] = rq_i[w][q];
                     if (lane == 0) q_n[w] = 0;
                 }
             }
-            if (done) break;
             const int t0 = (cc_ - segbase) * CHUNK + tid * PPT;
             if (cc_ + 1 < run_end) load_chunk<PPT>(Bn, b, t0 + CHUNK, mode);
             int jcur = -1;
             unsigned long long accL = 0ull, accA = 0ull;
             double zw[PPT];
             float vw[PPT];
-            bool keepv[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const int i = t0 + k;
@@ -545,7 +595,6 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                 double z = A.z[k];
                 zw[k] = A.z[k];
                 vw[k] = A.vz[k];
-                keepv[k] = true;
                 if (alive && mode == 0) {
                     int jo;
                     double fo;
@@ -572,16 +621,11 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                         if (!(zn == zn)) atomicOr(&dd.st->err, ERR_NAN);
                         z = zn;
                         zw[k] = zn;
-                        if (A.tc[k] == step) {
-                            item = (uint32_t)i;
-                            keepv[k] = false;
-                        }
+                        if (A.tc[k] == step) item = (uint32_t)i;
                     }
                     if (item != NEVER) {
                         const int q = atomicAdd(&q_n[w], 1);
                         rq_i[w][q] = item;
-                        rq_v[w][q] = vzn;
-                        rq_z[w][q] = zn;
                     }
                 }
                 if (alive) {
@@ -602,10 +646,10 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             }
             if (mode == 0) {
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) b.z[t0 + k] = zw[k];
-#pragma unroll
-                for (int k = 0; k < PPT; ++k)
-                    if (keepv[k]) b.vz[t0 + k] = vw[k];
+                for (int k = 0; k < PPT; ++k) {
+                    b.z[t0 + k] = zw[k];
+                    b.vz[t0 + k] = vw[k];
+                }
             }
             // last run of every lane: combine across the wave when all lanes agree
             const int j0w = __shfl(jcur, 0, 64);
@@ -617,17 +661,32 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             }
             A = Bn;
         }
-        lds_barrier();
+        // the main loop's z, v_z stores precede the rare work's reads (workgroup scope)
+        __syncthreads();
         for (int t = tid; t < wn; t += NT) {
             const unsigned long long v = hist[t];
             if (v) atomicAdd(&H[w0 + t], v);
         }
-        if (mode == 0 && tid == 0) {
-            const int ion = (s == SP_I);
-            if (cc.cand) atomicAdd(&dd.tally->cand[ion], (unsigned long long)cc.cand);
+        if (mode == 0) {
+            // the run's rare items with the whole block, while their lines are
+            // still in cache: collisions of candidates, tallies of absorbed
+            int tot = 0;
 #pragma unroll
-            for (int k = 0; k < NCH; ++k)
-                if (cc.coll[k]) atomicAdd(&dd.tally->coll[k], (unsigned long long)cc.coll[k]);
+            for (int q = 0; q < NW; ++q) tot += q_n[q];
+            for (int q = tid; q < tot; q += NT) {
+                int wq = 0, k = q;
+                while (k >= q_n[wq]) { k -= q_n[wq]; ++wq; }
+                const uint32_t item = rq_i[wq][k];
+                const int i = (int)(item & RARE_MASK);
+                const uint32_t kind = item >> RARE_SHIFT;
+                if (kind == 0u) mcc_one(dd, s, b, i, step, b.z[i], b.vz[i], &rt);
+                else rare_absorbed(dd, s, b, i, (int)kind - 1, b.vz[i], &rt);
+            }
+            lds_barrier();
+            if (tid == 0) {
+                flush_tally(dd, rt);
+                rare_tally_zero(&rt);
+            }
         }
         lds_barrier();
         c = run_end;
@@ -1056,8 +1115,6 @@ __device__ __forceinline__ double to_double(I128 a)
 // Sources and field: one workgroup of 1024 threads per diode.
 // mode 0: births, solve, field, tallies, step + 1; mode 1: solve and field only.
 // ---------------------------------------------------------------------------
-constexpr int FT = 1024;
-constexpr int FW = FT / 64;
 constexpr size_t LDS_FIELD_BYTES = 148 * 1024;   // node arrays staged in LDS up to 18944 nodes
 
 __device__ __forceinline__ I128 shfl_up_i128(I128 a, int o)
@@ -1096,8 +1153,9 @@ __device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, unsigne
     __shared__ int s_ne, s_q, s_R, s_bP, s_bE, s_bI, s_okP, s_okE, s_okI;
     __shared__ uint32_t s_id0;
     if (tid == 0) {
-        const int q = min(st->iz_count, IZQ_CAP);
-        const int R = dd.replenish ? st->ion_lost : 0;
+        // counters bumped with atomics at L2 in this kernel too: read them there
+        const int q = min(__hip_atomic_load(&st->iz_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), IZQ_CAP);
+        const int R = dd.replenish ? __hip_atomic_load(&st->ion_lost, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
         int ne = 0;
         if (dd.emit_x > 0.0) {
             const double fl = floor(dd.emit_x);
@@ -1212,7 +1270,25 @@ __device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, unsigne
         dd.tally->n_iz += q;
         st->iz_count = 0;
         st->ion_lost = 0;
+#pragma unroll
+        for (int sp = 0; sp < NSP; ++sp) st->rare_n[sp] = 0;
     }
+}
+
+// The sources part of a step for one diode, by one block of FT threads: the
+// rare items the particle kernel could not hold in LDS (normally none), then
+// the births.  keys: IZQ_CAP u64 of LDS scratch.
+__device__ __forceinline__ void step_sources(const Diode &dd, DiodeState *st, unsigned long long *keys,
+                                             uint32_t step, int parity, RareTally *rt)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) rare_tally_zero(rt);
+    __syncthreads();
+    process_rare(dd, st, parity, step, tid, FT, rt);
+    __syncthreads();
+    if (tid == 0) apply_tally(dd, st, *rt);
+    __syncthreads();
+    sources(dd, st, keys, step, parity);
 }
 
 __device__ __forceinline__ long long wave_incl_scan_i64(long long x)
@@ -1286,19 +1362,20 @@ __device__ __forceinline__ I128 block_scan_excl_i128(I128 v, I128 *sh, I128 &tot
     return add(off, add(incl, neg(v)));
 }
 
-__global__ __launch_bounds__(FT) void k_sources_field_lds(const Diode *__restrict__ D, DiodeState *__restrict__ S,
+__global__ __launch_bounds__(FT) void k_sources_field_lds(const Diode *__restrict__ D, DiodeState *S,
                                                           int mode, int parity)
 {
     // births use the array first as their sort keys, the solve then as R_j and phi_j
     extern __shared__ long long nodes[];
     const Diode &dd = D[blockIdx.x];
-    DiodeState *st = S + blockIdx.x;
+    DiodeState *st = dd.st;   // the pointer the rare-item code also writes through
     const int tid = threadIdx.x;
     __shared__ long long sh64[FW];
     __shared__ I128 sh128[FW];
+    __shared__ RareTally rt;
     const uint32_t step = st->step;
 
-    if (mode == 0) sources(dd, st, reinterpret_cast<unsigned long long *>(nodes), step, parity);
+    if (mode == 0) step_sources(dd, st, reinterpret_cast<unsigned long long *>(nodes), step, parity, &rt);
     __syncthreads();
 
     const int N = dd.N;
@@ -1376,7 +1453,7 @@ __global__ __launch_bounds__(FT) void k_sources_field_lds(const Diode *__restric
 // ---------------------------------------------------------------------------
 // Large grids: the same step spread over tiles of FT nodes, so that the node
 // arrays move through many CUs instead of one.
-//   k_births       births of the step (one block per diode).
+//   k_births       overflow rare items and births (one block per diode).
 //   k_field_agg    per tile: A_t = sum of rho over the tile, B_t = sum over the
 //                  tile's interior nodes of the in-tile inclusive prefix of rho.
 //   k_field_solve  per tile: with P_t = sum_{u<t} A_u (= S1 before the tile),
@@ -1385,12 +1462,13 @@ __global__ __launch_bounds__(FT) void k_sources_field_lds(const Diode *__restric
 //                  of one halo node on each side, phi_j and E_j as in the
 //                  single-block kernel, and the node bookkeeping.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FT) void k_births(const Diode *__restrict__ D, DiodeState *__restrict__ S, int parity)
+__global__ __launch_bounds__(FT) void k_births(const Diode *__restrict__ D, int parity)
 {
     extern __shared__ long long nodes[];
+    __shared__ RareTally rt;
     const Diode &dd = D[blockIdx.x];
-    DiodeState *st = S + blockIdx.x;
-    sources(dd, st, reinterpret_cast<unsigned long long *>(nodes), st->step, parity);
+    DiodeState *st = dd.st;
+    step_sources(dd, st, reinterpret_cast<unsigned long long *>(nodes), st->step, parity, &rt);
 }
 
 __device__ __forceinline__ long long node_rho(const Diode &dd, int j)
@@ -1432,11 +1510,11 @@ __device__ __forceinline__ double phi_node(const Diode &dd, int j, const I128 &T
     return dd.V * (double)j / (double)N + (dd.alpha / (double)N) * to_double(x);
 }
 
-__global__ __launch_bounds__(FT) void k_field_solve(const Diode *__restrict__ D, DiodeState *__restrict__ S, int mode,
+__global__ __launch_bounds__(FT) void k_field_solve(const Diode *__restrict__ D, DiodeState *S, int mode,
                                                     int ntiles)
 {
     const Diode &dd = D[blockIdx.y];
-    DiodeState *st = S + blockIdx.y;
+    DiodeState *st = dd.st;   // the pointer the rare-item code also writes through
     const int t = blockIdx.x, N = dd.N, nn = N + 1;
     const int a = t * FT;
     if (a >= nn) return;
@@ -1557,7 +1635,8 @@ extern "C" hipError_t picx_launch_profile_load(const Diode *D, const double *den
 extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int nd, int mode, int ppt, int grid,
                                             int parity, hipStream_t s)
 {
-    PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_particles<P_>, dim3(grid), dim3(NT), 0, s, D, S, nd, mode, parity));
+    const size_t seg_bytes = sizeof(int) * 2 * NSP * nd;
+    PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_particles<P_>, dim3(grid), dim3(NT), seg_bytes, s, D, S, nd, mode, parity));
     return hipGetLastError();
 }
 
@@ -1576,7 +1655,7 @@ extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, i
         return hipGetLastError();
     }
     const int tiles = (max_nodes + FT - 1) / FT;
-    if (mode == 0) hipLaunchKernelGGL(k_births, dim3(nd), dim3(FT), keys, s, D, S, parity);
+    if (mode == 0) hipLaunchKernelGGL(k_births, dim3(nd), dim3(FT), keys, s, D, parity);
     hipLaunchKernelGGL(k_field_agg, dim3(tiles, nd), dim3(FT), 0, s, D);
     hipLaunchKernelGGL(k_field_solve, dim3(tiles, nd), dim3(FT), 0, s, D, S, mode, tiles);
     return hipGetLastError();
