@@ -178,10 +178,8 @@ void layout(const pic_config *cfgs, int nd, const std::vector<pic_derived> &der,
                 size_t cap = (size_t)der[d].capacity[s];
                 D.buf[p][s].z = bp.take<double>(cap);
                 D.buf[p][s].vz = bp.take<float>(cap);
-                D.buf[p][s].vx = bp.take<float>(cap);
-                D.buf[p][s].vy = bp.take<float>(cap);
-                D.buf[p][s].id = bp.take<uint32_t>(cap);
                 D.buf[p][s].tc = bp.take<uint32_t>(cap);
+                D.buf[p][s].cold = bp.take<ColdRec>(cap);
             }
         for (int s = 0; s < NSP; ++s) D.rare[s] = bp.take<uint32_t>((size_t)der[d].capacity[s]);
     }
@@ -804,30 +802,29 @@ int pic_get_particles(pic_handle *h, int diode, int species, int64_t cap, int64_
     const int n = st.n[species];
     const SpeciesBuf &b = h->hD[diode].buf[st.parity][species];
     std::vector<double> hz(n);
-    std::vector<float> hvx(n), hvy(n), hvz(n);
-    std::vector<uint32_t> hid(n), htc(n);
+    std::vector<float> hvz(n);
+    std::vector<uint32_t> htc(n);
+    std::vector<ColdRec> hcold(n);
     if (n > 0) {
         HIP_TRY(hipMemcpy(hz.data(), b.z, n * sizeof(double), hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(hvx.data(), b.vx, n * sizeof(float), hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(hvy.data(), b.vy, n * sizeof(float), hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(hvz.data(), b.vz, n * sizeof(float), hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(hid.data(), b.id, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(htc.data(), b.tc, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hcold.data(), b.cold, n * sizeof(ColdRec), hipMemcpyDeviceToHost));
     }
     std::vector<int> idx;
     idx.reserve(n);
     for (int i = 0; i < n; ++i)
         if (hz[i] >= 0.0) idx.push_back(i);
-    std::sort(idx.begin(), idx.end(), [&](int a, int c) { return hid[a] < hid[c]; });
+    std::sort(idx.begin(), idx.end(), [&](int a, int c) { return hcold[a].id < hcold[c].id; });
     *n_out = (int64_t)idx.size();
     if ((int64_t)idx.size() > cap) return fail(PIC_ENOSPACE, "output capacity too small");
     for (size_t k = 0; k < idx.size(); ++k) {
         const int i = idx[k];
         if (z) z[k] = hz[i];
-        if (vx) vx[k] = hvx[i];
-        if (vy) vy[k] = hvy[i];
+        if (vx) vx[k] = hcold[i].vx;
+        if (vy) vy[k] = hcold[i].vy;
         if (vz) vz[k] = hvz[i];
-        if (id) id[k] = hid[i];
+        if (id) id[k] = hcold[i].id;
         if (tc) tc[k] = htc[i];
     }
     return PIC_OK;
@@ -848,12 +845,12 @@ int pic_set_particles(pic_handle *h, int diode, int species, int64_t n, const do
     if (rc) return rc;
     const SpeciesBuf &b = h->hD[diode].buf[st.parity][species];
     if (n > 0) {
+        std::vector<ColdRec> hcold(n);
+        for (int64_t i = 0; i < n; ++i) hcold[i] = ColdRec{vx[i], vy[i], id[i], 0u};
         HIP_TRY(hipMemcpy(b.z, z, n * sizeof(double), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(b.vx, vx, n * sizeof(float), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(b.vy, vy, n * sizeof(float), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(b.vz, vz, n * sizeof(float), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(b.id, id, n * sizeof(uint32_t), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(b.tc, tc, n * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b.cold, hcold.data(), n * sizeof(ColdRec), hipMemcpyHostToDevice));
     }
     int32_t nn = (int32_t)n;
     HIP_TRY(hipMemcpy(&h->hD[diode].st->n[species], &nn, sizeof(nn), hipMemcpyHostToDevice));

@@ -1,8 +1,9 @@
 // pic_internal.h -- device-resident data layout of the gfx950 PIC-MCC library.
 //
 // Every diode of a handle owns, inside the caller's workspace:
-//   * two structure-of-arrays particle buffers per species (ping-pong for the
-//     cell re-sort): z f64, vz f32, vx f32, vy f32, id u32, tc u32;
+//   * two particle buffers per species (ping-pong for the cell re-sort):
+//     arrays z f64, vz f32, tc u32 and an array of 16-byte {vx, vy, id}
+//     records;
 //   * three fixed-point deposit histograms (int64, N+1 nodes) plus copies of
 //     the last step's, phi and E (f64, N+1), time-average accumulators;
 //   * sort scratch (one int32 per cell and species), the ionisation queue,
@@ -43,10 +44,20 @@ constexpr double MASS_HE = 6.6464731e-27;
 constexpr double E_EXC = 19.82;
 constexpr double E_ION = 24.59;
 
+// Fields touched only by collision candidates, absorbed particles, births
+// and the re-sort, kept together so that such a particle costs one 16-byte
+// access instead of three scattered 4-byte ones.
+struct ColdRec {
+    float vx, vy;
+    uint32_t id;
+    uint32_t pad;
+};
+
 struct SpeciesBuf {
-    double *z;
-    float *vz, *vx, *vy;
-    uint32_t *id, *tc;
+    double *z;          // streamed every step
+    float *vz;          // streamed every step
+    uint32_t *tc;       // streamed every step (read)
+    ColdRec *cold;      // v_x, v_y, id
 };
 
 // Mutable per-diode state (device).

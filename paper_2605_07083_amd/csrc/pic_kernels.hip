@@ -101,10 +101,13 @@ __device__ __forceinline__ void cic(double z, double invdz, int N, int &j, doubl
     f = s - fl;
 }
 
+// rne(f 2^32) for f in [0, 1]: the product is exact, the rounded value lies
+// in [0, 2^32], and only the end point 2^32 does not fit a 32-bit conversion.
 __device__ __forceinline__ unsigned long long fixed_right(double f)
 {
 #pragma clang fp contract(off)
-    return (unsigned long long)(long long)rint(f * TWO32);
+    const double r = rint(f * TWO32);
+    return r >= TWO32 ? (1ull << 32) : (unsigned long long)(unsigned int)r;
 }
 
 __device__ __forceinline__ int wave_min(int v)
@@ -267,8 +270,9 @@ __device__ __forceinline__ float mcc_one(const Diode &dd, int s, const SpeciesBu
                         float vzn, RareTally *cc)
 {
     const int ion = (s == SP_I);
-    float vx = b.vx[i], vy = b.vy[i], vz = vzn;
-    const uint32_t id = b.id[i];
+    const ColdRec cr = b.cold[i];
+    float vx = cr.vx, vy = cr.vy, vz = vzn;
+    const uint32_t id = cr.id;
     // The three counter blocks are generated one at a time, each consumed
     // before the next (scheduling barriers keep their rounds from being
     // interleaved, which would hold all of them live at once).
@@ -354,8 +358,7 @@ __device__ __forceinline__ float mcc_one(const Diode &dd, int s, const SpeciesBu
             vy = cy + fM * gp * st * sp;
             vz = cz + fM * gp * ct;
         }
-        b.vx[i] = vx;
-        b.vy[i] = vy;
+        b.cold[i] = ColdRec{vx, vy, id, 0u};
     }
     b.vz[i] = vz;
     b.tc[i] = tcn;
@@ -417,7 +420,8 @@ __device__ __forceinline__ void load_chunk(ChunkRegs<PPT> &C, const SpeciesBuf &
 __device__ __forceinline__ void rare_absorbed(const Diode &dd, int s, const SpeciesBuf &b, int i, int wall, float vzn,
                                               RareTally *rt)
 {
-    const double vx = b.vx[i], vy = b.vy[i], vz = vzn;
+    const ColdRec cr = b.cold[i];
+    const double vx = cr.vx, vy = cr.vy, vz = vzn;
     const double ke = 0.5 * dd.mass[s] * (vx * vx + vy * vy + vz * vz);
     atomicAdd(&rt->abs_count[s][wall], 1u);
     atomicAdd(&rt->abs_energy[s][wall], ke);
@@ -714,10 +718,8 @@ __global__ __launch_bounds__(256) void k_load(const Diode *__restrict__ D, const
     const double sig = s == SP_P ? dd.sig_e0 : dd.sig_i0;
     const SpeciesBuf b = dd.buf[0][s];
     b.z[i] = dd.L * u53(b1.x, b1.y);
-    b.vx[i] = (float)(sig * n1);
-    b.vy[i] = (float)(sig * n2);
+    b.cold[i] = ColdRec{(float)(sig * n1), (float)(sig * n2), id, 0u};
     b.vz[i] = (float)(sig * n3);
-    b.id[i] = id;
     uint32_t tc = next_candidate(0u, dd.lam[s == SP_I], b1.z, b1.w);
     if (tc != NEVER) tc -= 1u;
     b.tc[i] = tc;
@@ -820,10 +822,8 @@ __global__ __launch_bounds__(256) void k_profile_fill(const Diode *__restrict__ 
         bm32(b0.x, b0.y, n1, n2);
         bm32(b0.z, b0.w, n3, n4);
         b.z[i] = ((double)c + u53(b1.x, b1.y)) * dd.dz;
-        b.vx[i] = (float)(sig * n1);
-        b.vy[i] = (float)(sig * n2);
+        b.cold[i] = ColdRec{(float)(sig * n1), (float)(sig * n2), id, 0u};
         b.vz[i] = (float)(sig * n3);
-        b.id[i] = id;
         uint32_t tc = next_candidate(0u, lam, b1.z, b1.w);
         if (tc != NEVER) tc -= 1u;
         b.tc[i] = tc;
@@ -1039,9 +1039,7 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
             const int dest = rank[k] >= 0 ? cnt[j[k] - w0] + rank[k] : -1 - rank[k];
             dst.z[dest] = z[k];
             dst.vz[dest] = src.vz[t0 + k];
-            dst.vx[dest] = src.vx[t0 + k];
-            dst.vy[dest] = src.vy[t0 + k];
-            dst.id[dest] = src.id[t0 + k];
+            dst.cold[dest] = src.cold[t0 + k];
             dst.tc[dest] = src.tc[t0 + k];
         }
         lds_barrier();
@@ -1138,7 +1136,8 @@ __device__ __forceinline__ void deposit_global(const Diode &dd, int s, double z)
 __device__ void write_particle(const SpeciesBuf &b, int i, double z, float vx, float vy, float vz, uint32_t id,
                                uint32_t tc)
 {
-    b.z[i] = z; b.vx[i] = vx; b.vy[i] = vy; b.vz[i] = vz; b.id[i] = id; b.tc[i] = tc;
+    b.z[i] = z; b.vz[i] = vz; b.tc[i] = tc;
+    b.cold[i] = ColdRec{vx, vy, id, 0u};
 }
 
 // Births of one step, one thread per newborn: ionisation products in
