@@ -6,7 +6,7 @@
 //     records;
 //   * three fixed-point deposit histograms (int64, N+1 nodes) plus copies of
 //     the last step's, phi and E (f64, N+1), time-average accumulators;
-//   * sort scratch (one int32 per cell and species), the ionisation queue,
+//   * sort scratch (one int32 per 32-cell bin and species), the ionisation queue,
 //     the mutable state block, cumulative tallies and a ring of snapshots.
 // The hot loop streams z (r/w), vz (r/w) and tc (r) only; vx, vy and id are
 // touched for null-collision candidates and absorbed particles, which the hot
@@ -146,7 +146,7 @@ struct Diode {
     long long *Hlast[NSP];
     long long *Hsum[NSP];
     double *phi, *E, *phi_sum;
-    int32_t *cell_cnt[NSP];
+    int32_t *cell_cnt[NSP];     // per-bin counts / offsets of the re-sort
     IzEvent *izq;
     DiodeState *st;
     DiodeTally *tally;

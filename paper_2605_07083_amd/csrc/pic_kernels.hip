@@ -22,6 +22,14 @@ constexpr int NW = NT / 64;        // wavefronts per particle block
 constexpr int WMAX = 512;          // LDS window (nodes) of the field tile / histogram
 constexpr int QW_SLACK = 1024;     // per-wave LDS queue of rare items: 64 PPT + QW_SLACK entries
 constexpr int DRIFT = 96;          // cells of drift since the last re-sort kept in the LDS window
+constexpr int BIN_SHIFT = 5;       // the re-sort orders particles by bins of 32 cells
+constexpr int DRIFT_B = (DRIFT >> BIN_SHIFT) + 1;   // the drift margin in bins
+
+__host__ __device__ constexpr int nbins_of(int N) { return ((N - 1) >> BIN_SHIFT) + 1; }
+// The counter / offset of bin b lives at cell slot b << BIN_SHIFT of the count
+// array: 128 bytes apart, so that the device-scope atomics of many blocks on
+// the bins spread over memory channels instead of queueing on one.
+__device__ __forceinline__ int bin_slot(int b) { return b << BIN_SHIFT; }
 constexpr int FT = 1024;           // threads of the sources / field blocks
 constexpr int FW = FT / 64;
 constexpr double TWO32 = 4294967296.0;
@@ -369,11 +377,11 @@ __device__ __forceinline__ float mcc_one(const Diode &dd, int s, const SpeciesBu
 // Particle kernel.  mode 0: full step; mode 1: deposit only (load / refield).
 //
 // Each block owns a contiguous range of chunks; each thread owns PPT
-// consecutive slots of a chunk, which after the cell re-sort mostly share a
-// cell.  Runs of chunks of one (diode, species) share one LDS window: the
-// field tile of the gather and the fixed-point histogram of the deposit cover
-// the cells of the run's first and last particle plus a drift margin;
-// particles outside it use global memory.  The deposit sums a thread's
+// consecutive slots of a chunk; the re-sort orders them by 32-cell bins.
+// Runs of chunks of one (diode, species) share one LDS window: the field tile
+// of the gather and the fixed-point histogram of the deposit cover the bins
+// of the run's first and last particle plus a drift margin; particles outside
+// it use global memory.  The deposit sums a thread's
 // consecutive same-cell particles in registers and touches LDS only when the
 // cell changes; a wave whose lanes end in one cell combines them first.
 // Inside a run the chunk loop has no barrier and the next chunk's particle
@@ -552,8 +560,10 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             double f;
             cic(b.z[slot0], invdz, N, ja, f);
             cic(b.z[max(last_slot, slot0)], invdz, N, jb, f);
-            w0 = uni(max(0, min(ja, jb) - DRIFT));
-            wn = uni(min(min(N, max(ja, jb) + 1 + DRIFT) - w0 + 1, WMAX + 1));
+            // the re-sort orders by bins: the run spans whole bins between its ends
+            const int ba = min(ja, jb) >> BIN_SHIFT, bb = max(ja, jb) >> BIN_SHIFT;
+            w0 = uni(max(0, (ba << BIN_SHIFT) - DRIFT));
+            wn = uni(min(min(N, ((bb + 1) << BIN_SHIFT) + DRIFT) - w0 + 1, WMAX + 1));
         }
         for (int t = tid; t < wn; t += NT) {
             if (mode == 0) etile[t] = dd.E[w0 + t];
@@ -841,10 +851,40 @@ __global__ __launch_bounds__(256) void k_profile_clear(const Diode *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Cell re-sort: count -> scan -> scatter -> finalize (compacts holes too).
+// Re-sort by bins of 32 cells: count -> scan -> scatter -> finalize (compacts
+// holes too).  Bins rather than cells: the LDS windows only need each run of
+// chunks confined to a narrow range of cells, and with electrons drifting
+// tens of cells between re-sorts a chunk then writes a few long destination
+// ranges instead of a hundred short ones.
 // ---------------------------------------------------------------------------
-// Window of a run of chunks for the re-sort: cells of its first and last
-// particle plus the drift margin (cells, not nodes).
+// Wave-level grouping of equal keys (key < 0: no item).  For each distinct
+// key the lowest lane adds the group size to the counter `add` picks (LDS
+// window or global) and every member gets that atomic's old value plus its
+// rank among the group's lanes.  With few distinct keys per wave (the
+// re-sort's bins) this is one atomic per key instead of one per lane.
+template <class AddFn>
+__device__ __forceinline__ int wave_group_rank(int key, AddFn add)
+{
+    const int lane = lane_id();
+    const bool valid = key >= 0;
+    unsigned long long todo = __ballot(valid);
+    int rank = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int kl = __shfl(key, leader, 64);
+        const unsigned long long m = __ballot(valid && key == kl);
+        int base = 0;
+        if (lane == leader) base = add(kl, __popcll(m));
+        base = __shfl(base, leader, 64);
+        if (valid && key == kl)
+            rank = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        todo &= ~m;
+    }
+    return rank;
+}
+
+// Window of a run of chunks for the re-sort: bins of its first and last
+// particle plus the drift margin (bins).
 __device__ __forceinline__ void sort_window(const Diode &dd, const SpeciesBuf &b, int slot0, int last_slot, int &w0,
                                             int &wn)
 {
@@ -852,8 +892,10 @@ __device__ __forceinline__ void sort_window(const Diode &dd, const SpeciesBuf &b
     double f;
     cic(b.z[slot0], dd.invdz, dd.N, ja, f);
     cic(b.z[max(last_slot, slot0)], dd.invdz, dd.N, jb, f);
-    w0 = max(0, min(ja, jb) - DRIFT);
-    wn = min(min(dd.N - 1, max(ja, jb) + DRIFT) - w0 + 1, WMAX + 1);
+    ja >>= BIN_SHIFT;
+    jb >>= BIN_SHIFT;
+    w0 = uni(max(0, min(ja, jb) - DRIFT_B));
+    wn = uni(min(min(nbins_of(dd.N) - 1, max(ja, jb) + DRIFT_B) - w0 + 1, WMAX + 1));
 }
 
 // Cell counts of the live particles.  Each thread counts runs of equal cells
@@ -886,63 +928,46 @@ __global__ __launch_bounds__(NT) void k_sort_count(const Diode *__restrict__ D, 
         for (int t = tid; t < wn; t += NT) cnt[t] = 0;
         lds_barrier();
         int *gc = dd.cell_cnt[s];
+        auto add = [&](int key, int m) {
+            const int jl = key - w0;
+            if (jl >= 0 && jl < wn) atomicAdd(&cnt[jl], m);
+            else atomicAdd(&gc[bin_slot(key)], m);
+            return 0;
+        };
         for (int cc_ = c; cc_ < run_end; ++cc_) {
             const int t0 = (cc_ - segbase) * CHUNK + tid * PPT;
-            int jcur = -1, run = 0;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const double z = b.z[t0 + k];
+                int j = -1;
                 if (t0 + k < n && z >= 0.0) {
-                    int j;
                     double f;
                     cic(z, dd.invdz, dd.N, j, f);
-                    if (j != jcur) {
-                        if (run) {
-                            const int jl = jcur - w0;
-                            if (jl >= 0 && jl < wn) atomicAdd(&cnt[jl], run);
-                            else atomicAdd(&gc[jcur], run);
-                        }
-                        jcur = j;
-                        run = 1;
-                    } else {
-                        ++run;
-                    }
+                    j >>= BIN_SHIFT;
                 }
-            }
-            const int j0w = __shfl(jcur, 0, 64);
-            int tot = run;
-            if (__all(jcur == j0w)) {
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
-                if (lane_id() != 0) run = 0;
-                else run = tot;
-            }
-            if (run) {
-                const int jl = jcur - w0;
-                if (jl >= 0 && jl < wn) atomicAdd(&cnt[jl], run);
-                else atomicAdd(&gc[jcur], run);
+                wave_group_rank(j, add);
             }
         }
         lds_barrier();
         for (int t = tid; t < wn; t += NT)
-            if (cnt[t]) atomicAdd(&gc[w0 + t], cnt[t]);
+            if (cnt[t]) atomicAdd(&gc[bin_slot(w0 + t)], cnt[t]);
         lds_barrier();
         c = run_end;
     }
 }
 
-// One workgroup per (diode, species): exclusive scan of the cell counts.
+// One workgroup per (diode, species): exclusive scan of the bin counts.
 __global__ __launch_bounds__(1024) void k_sort_scan(const Diode *__restrict__ D)
 {
     __shared__ int part[1024];
     const int d = blockIdx.x / NSP, s = blockIdx.x % NSP;
     const Diode &dd = D[d];
-    const int N = dd.N;
+    const int N = nbins_of(dd.N);
     int *cc = dd.cell_cnt[s];
     const int per = (N + 1023) / 1024;
     const int j0 = threadIdx.x * per;
     int local = 0;
-    for (int j = j0; j < min(N, j0 + per); ++j) local += cc[j];
+    for (int j = j0; j < min(N, j0 + per); ++j) local += cc[bin_slot(j)];
     part[threadIdx.x] = local;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -953,8 +978,8 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const Diode *__restrict__ D)
     }
     int run = part[threadIdx.x] - local;
     for (int j = j0; j < min(N, j0 + per); ++j) {
-        int v = cc[j];
-        cc[j] = run;
+        int v = cc[bin_slot(j)];
+        cc[bin_slot(j)] = run;
         run += v;
     }
     if (threadIdx.x == 1023) dd.st->n_new[s] = part[1023];
@@ -1002,35 +1027,29 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
             if (t0 + k < n && z[k] >= 0.0) {
                 double f;
                 cic(z[k], dd.invdz, dd.N, j[k], f);
+                j[k] >>= BIN_SHIFT;
             }
         }
-        // runs of equal cells: one LDS atomic per run gives the run's base rank
-        int base = 0, pos = 0;
+        // ranks within the block from one LDS atomic per (wave, bin); an
+        // outlier bin takes global slots directly (stored as -1 - slot)
+        auto add = [&](int key, int m) {
+            const int jl = key - w0;
+            if (jl >= 0 && jl < wn) return atomicAdd(&cnt[jl], m);
+            return -1 - atomicAdd(&cur[bin_slot(key)], m) - (m - 1);
+        };
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            rank[k] = 0;
-            if (j[k] < 0) continue;
-            const bool head = (k == 0) || (j[k] != j[k > 0 ? k - 1 : 0]);
-            if (head) {
-                int len = 1;
-                bool same = true;
-#pragma unroll
-                for (int m = k + 1; m < PPT; ++m) {
-                    same = same && (j[m] == j[k]);
-                    len += same ? 1 : 0;
-                }
-                const int jl = j[k] - w0;
-                if (jl >= 0 && jl < wn) base = atomicAdd(&cnt[jl], len);
-                else base = -1 - atomicAdd(&cur[j[k]], len);       // outlier: global slots
-                pos = 0;
-            }
-            rank[k] = base >= 0 ? base + pos : base - pos;
-            ++pos;
+            const int jl = j[k] - w0;
+            const bool inw = j[k] >= 0 && jl >= 0 && jl < wn;
+            const int r = wave_group_rank(j[k], add);
+            // global slot g + i is encoded as -1 - (g + i): the rank of an outlier
+            // counts down from -1 - g - (m - 1)
+            rank[k] = (j[k] < 0) ? 0 : (inw ? r : r);
         }
         lds_barrier();
         for (int t = tid; t < wn; t += NT) {
             const int v = cnt[t];
-            if (v) cnt[t] = atomicAdd(&cur[w0 + t], v);
+            if (v) cnt[t] = atomicAdd(&cur[bin_slot(w0 + t)], v);
         }
         lds_barrier();
 #pragma unroll
