@@ -236,10 +236,11 @@ int pic_set_tuning(pic_handle *h, int ppt, int grid, int sort_period, int use_gr
 int pic_get_tuning(pic_handle *h, int *ppt, int *grid, int *sort_period, int *use_graph);
 
 /* Choose the launch schedule by timing candidates on the handle's own
- * diodes (coordinate descent over particles per thread, re-sort period, grid
- * size and graph replay; each candidate runs whole re-sort periods of at least
- * trial_steps real steps, so the diodes advance).  Leaves the best schedule
- * set and returns it with its time per step.  Synchronises. */
+ * diodes: every combination of particles per thread {1, 2, 4}, re-sort period
+ * {16, 32, 64, 128} and grid {2048, 4096, 8192}, then graph replay on or off
+ * for the best one.  Each candidate runs whole re-sort periods of at least
+ * trial_steps real steps, so the diodes advance.  Leaves the best schedule set
+ * and returns it with its time per step.  Synchronises. */
 int pic_autotune(pic_handle *h, int64_t trial_steps, int *ppt, int *grid, int *sort_period, int *use_graph,
                  double *ms_per_step);
 

@@ -169,6 +169,7 @@ void layout(const pic_config *cfgs, int nd, const std::vector<pic_derived> &der,
         D.E = bp.take<double>(nn);
         D.phi_sum = bp.take<double>(nn);
         D.agg = bp.take<FieldAgg>((nn + 1023) / 1024);
+        D.tacc = bp.take<TallyCopy>(TALLY_COPIES);
     }
     zero_end = bp.off;
     for (int d = 0; d < nd; ++d) {
@@ -1036,20 +1037,14 @@ int pic_autotune(pic_handle *h, int64_t trial_steps, int *ppt, int *grid, int *s
     int bg = h->grid;
     double best = 1e300, ms;
     int rc;
-    for (int p : {1, 2, 4}) {
-        if ((rc = timed(p, 0, bk, bu, ms))) return rc;
-        if (ms < best) { best = ms; bp = p; bg = h->grid; }
-    }
-    for (int k : {16, 32, 64}) {
-        if ((rc = timed(bp, 0, k, bu, ms))) return rc;
-        if (ms < best * 0.999 || k == bk) {
-            if (ms < best * 0.999) { best = ms; bk = k; }
-        }
-    }
-    for (int g : {512, 1024, 2048, 4096, 8192}) {
-        if ((rc = timed(bp, g, bk, bu, ms))) return rc;
-        if (ms < best * 0.999) { best = ms; bg = g; }
-    }
+    // full search over particles per thread, re-sort period and grid (the
+    // coordinate-wise search stalled in local optima), then graph replay
+    for (int p : {1, 2, 4})
+        for (int k : {16, 32, 64, 128})
+            for (int g : {2048, 4096, 8192}) {
+                if ((rc = timed(p, g, k, bu, ms))) return rc;
+                if (ms < best) { best = ms; bp = p; bk = k; bg = h->grid; }
+            }
     for (int u : {0, 1}) {
         if ((rc = timed(bp, bg, bk, u, ms))) return rc;
         if (ms < best * 0.999) { best = ms; bu = u; }

@@ -110,6 +110,15 @@ struct RareTally {
     double abs_energy[NSP][2];
 };
 
+// The particle kernel's blocks add their tallies into TALLY_COPIES copies,
+// 256 bytes apart (block b into copy b mod TALLY_COPIES): device-scope
+// atomics on one address from thousands of blocks would queue on one memory
+// channel.  The sources kernel folds the copies into the tallies each step.
+constexpr int TALLY_COPIES = 64;
+struct alignas(256) TallyCopy {
+    RareTally t;
+};
+
 // Per-tile aggregates of the tiled field solve: A = sum of rho over the tile,
 // B (128-bit, lo/hi) = sum over its interior nodes of the in-tile inclusive
 // prefix of rho, n = its interior node count.
@@ -153,6 +162,7 @@ struct Diode {
     TallySnap *ring;
     FieldAgg *agg;         // one per FT-node tile of the field solve
     uint32_t *rare[NSP];   // the step's rare items per species: slot | kind << 30
+    TallyCopy *tacc;       // TALLY_COPIES accumulators of the particle kernel's tallies
 };
 
 }  // namespace pic

@@ -457,23 +457,59 @@ __device__ __forceinline__ void process_rare(const Diode &dd, const DiodeState *
     }
 }
 
-// Add a block-run tally to the diode's tallies with device atomics (the
-// particle kernel's runs end at different times, so these rarely contend).
+// Add a block-run tally to this block's accumulator copy (device atomics).
 __device__ __forceinline__ void flush_tally(const Diode &dd, const RareTally &t)
 {
+    RareTally &a = dd.tacc[blockIdx.x % TALLY_COPIES].t;
     for (int ion = 0; ion < 2; ++ion)
-        if (t.cand[ion]) atomicAdd(&dd.tally->cand[ion], (unsigned long long)t.cand[ion]);
+        if (t.cand[ion]) atomicAdd(&a.cand[ion], t.cand[ion]);
 #pragma unroll
     for (int k = 0; k < NCH; ++k)
-        if (t.coll[k]) atomicAdd(&dd.tally->coll[k], (unsigned long long)t.coll[k]);
+        if (t.coll[k]) atomicAdd(&a.coll[k], t.coll[k]);
 #pragma unroll
     for (int sp = 0; sp < NSP; ++sp)
         for (int w = 0; w < 2; ++w)
             if (t.abs_count[sp][w]) {
-                atomicAdd(&dd.tally->abs_count[sp][w], (unsigned long long)t.abs_count[sp][w]);
-                atomicAdd(&dd.tally->abs_energy[sp][w], t.abs_energy[sp][w]);
+                atomicAdd(&a.abs_count[sp][w], t.abs_count[sp][w]);
+                atomicAdd(&a.abs_energy[sp][w], t.abs_energy[sp][w]);
             }
-    if (t.ion_lost) atomicAdd(&dd.st->ion_lost, t.ion_lost);
+    if (t.ion_lost) atomicAdd(&a.ion_lost, t.ion_lost);
+}
+
+// Fold the accumulator copies into rt (LDS) and clear them: the first wave
+// of the block, one copy per lane, a fixed shuffle tree per field.
+__device__ __forceinline__ void fold_tally_copies(const Diode &dd, RareTally *rt)
+{
+    static_assert(TALLY_COPIES == 64, "one copy per lane of the first wave");
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    RareTally v = dd.tacc[lane].t;
+    dd.tacc[lane].t = RareTally{};
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) v.cand[k] += __shfl_xor(v.cand[k], o, 64);
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) v.coll[k] += __shfl_xor(v.coll[k], o, 64);
+#pragma unroll
+        for (int sp = 0; sp < NSP; ++sp)
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                v.abs_count[sp][w] += __shfl_xor(v.abs_count[sp][w], o, 64);
+                v.abs_energy[sp][w] += __shfl_xor(v.abs_energy[sp][w], o, 64);
+            }
+        v.ion_lost += __shfl_xor(v.ion_lost, o, 64);
+    }
+    if (lane == 0) {
+        for (int k = 0; k < 2; ++k) rt->cand[k] += v.cand[k];
+        for (int k = 0; k < NCH; ++k) rt->coll[k] += v.coll[k];
+        for (int sp = 0; sp < NSP; ++sp)
+            for (int w = 0; w < 2; ++w) {
+                rt->abs_count[sp][w] += v.abs_count[sp][w];
+                rt->abs_energy[sp][w] += v.abs_energy[sp][w];
+            }
+        rt->ion_lost += v.ion_lost;
+    }
 }
 
 // Add a block tally to the diode's cumulative tallies and ion-loss count.
@@ -1303,6 +1339,8 @@ __device__ __forceinline__ void step_sources(const Diode &dd, DiodeState *st, un
     if (tid == 0) rare_tally_zero(rt);
     __syncthreads();
     process_rare(dd, st, parity, step, tid, FT, rt);
+    __syncthreads();
+    fold_tally_copies(dd, rt);
     __syncthreads();
     if (tid == 0) apply_tally(dd, st, *rt);
     __syncthreads();
