@@ -29,6 +29,7 @@ extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int n
 extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
                                                 int parity, hipStream_t s);
 extern "C" hipError_t picx_prepare(void);
+extern "C" int picx_sources_field_kernels(int max_nodes, int mode);
 extern "C" hipError_t picx_launch_profile_load(const Diode *D, const double *dens, int nd, int max_cells,
                                                hipStream_t s);
 extern "C" hipError_t picx_launch_sort(const Diode *D, DiodeState *S, int nd, int ppt, int grid, int parity,
@@ -249,7 +250,7 @@ struct pic_handle {
     bool sort_next = true;      // force a re-sort before the next step
     int ppt = 2;
     int grid = 1024;
-    int sort_period = 16;
+    int sort_period = 64;
     bool use_graph = true;
     hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
     hipGraphExec_t graph[2] = {nullptr, nullptr};   // re-sort + sort_period steps, per start parity
@@ -281,7 +282,7 @@ int grid_for(const pic_handle *h)
     int64_t chunks = 0;
     for (int d = 0; d < h->nd; ++d)
         for (int s = 0; s < NSP; ++s) chunks += (h->der[d].capacity[s] + 256 * h->ppt - 1) / (256 * h->ppt);
-    int64_t g = std::min<int64_t>(chunks, 4096);
+    int64_t g = std::min<int64_t>(chunks, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     return (int)g;
 }
@@ -386,12 +387,14 @@ int ensure_timed_graph(pic_handle *h, int p)
             return bail("dependency query failed");
         cur = nout ? next : nullptr;
     }
-    if ((int)chain.size() < 2 * K + 1) return bail("unexpected captured period");
-    const int first = (int)chain.size() - 2 * K;      // particle kernel of step 0
+    // a step is the particle kernel and the sources / field kernels after it
+    const int B = 1 + picx_sources_field_kernels(h->max_nodes, 0);
+    if ((int)chain.size() < B * K + 1) return bail("unexpected captured period");
+    const int first = (int)chain.size() - B * K;      // particle kernel of step 0
     std::vector<hipGraphNode_t> marks(2 * K);
     for (int k = 0; k < K; ++k) {
-        hipGraphNode_t pred = chain[first + 2 * k - 1], part = chain[first + 2 * k];
-        hipGraphNode_t field = chain[first + 2 * k + 1];
+        hipGraphNode_t pred = chain[first + B * k - 1], part = chain[first + B * k];
+        hipGraphNode_t field = chain[first + B * k + 1];
         if (hipGraphRemoveDependencies(g, &pred, &part, 1) != hipSuccess ||
             hipGraphRemoveDependencies(g, &part, &field, 1) != hipSuccess ||
             hipGraphAddEventRecordNode(&marks[2 * k], g, &pred, 1, h->tev[0]) != hipSuccess ||
@@ -562,7 +565,7 @@ static int init_impl(const pic_config *cfgs, int n_diodes, void *dev_workspace, 
     h->bytes = bytes;
     h->stream = static_cast<hipStream_t>(hip_stream);
     h->live_offset.assign(n_diodes, std::array<int64_t, NSP>{0, 0, 0});
-    h->sort_period = cfgs[0].sort_period > 0 ? cfgs[0].sort_period : 16;
+    h->sort_period = cfgs[0].sort_period > 0 ? cfgs[0].sort_period : 64;
     Bump bp{h->ws};
     size_t zend;
     layout(cfgs, n_diodes, h->der, bp, h->hD, h->dD, h->dNload, zend);

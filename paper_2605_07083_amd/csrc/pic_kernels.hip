@@ -1701,6 +1701,13 @@ extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int n
 // tile aggregates and the tiled solve run as three kernels over many CUs.
 constexpr int FIELD_TILE_MIN = 8192;
 
+// Kernels picx_launch_sources_field enqueues for a step (timed graphs need it).
+extern "C" int picx_sources_field_kernels(int max_nodes, int mode)
+{
+    if (max_nodes <= FIELD_TILE_MIN) return 1;
+    return mode == 0 ? 3 : 2;
+}
+
 extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
                                                 int parity, hipStream_t s)
 {

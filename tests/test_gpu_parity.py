@@ -242,3 +242,23 @@ def test_tiled_field_path_ragged(pic, O):
         assert field_matches(O, cfg, h, s, d) == []
     assert restart_step_check(O, big, h, 8, d=0) == []
     assert restart_step_check(O, small, h, 4, d=1) == []
+
+
+@pytest.mark.parametrize("N", [2048, 9000])
+def test_step_timed_measures_the_particle_kernel(pic, N):
+    """The live timing of the particle kernel (events spliced around it in the
+    replayed graph) agrees with the plain-stream timing, on the single-block
+    and the tiled field paths, and stays below the whole step."""
+    _say("case: step_timed, N = %d" % N)
+    cfg = presets.scaled(presets.tiny(), N=N, L=5e-3 * N / 256, n_load=200 * N)
+    h = pic.Handle(cfg)
+    res = {}
+    for g in (0, 1):
+        h.set_tuning(ppt=2, grid=0, sort_period=16, use_graph=g)
+        h.step(32)
+        r = h.step_timed(64)
+        res[g] = r
+        assert 0.0 < r["particle_kernel_ms"] < r["total_ms"] / 64
+    a, b = res[0]["particle_kernel_ms"], res[1]["particle_kernel_ms"]
+    _say("  particle kernel: stream %.1f us, graph %.1f us" % (a * 1e3, b * 1e3))
+    assert abs(a - b) < 0.35 * max(a, b)
