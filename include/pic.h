@@ -265,6 +265,21 @@ int pic_steady_from_series(const double *br, const double *n_live, int nblocks, 
 /* Message of the last failing call on this thread. */
 const char *pic_last_error(void);
 
+/* Checkpoint / restart.  pic_save writes a host image of every diode's
+ * state at the current step boundary: configuration, state block, tallies,
+ * snapshot ring, node arrays (deposits, their sums, phi, E) and the particle
+ * slots of the current buffer.  pic_checkpoint_size gives the bytes it needs
+ * (it grows with the live counts).  pic_load restores such an image into a
+ * handle created with the same configurations (physics fields compared;
+ * PIC_EINVAL otherwise, PIC_ENOSPACE if the particles exceed its capacity);
+ * the next step re-sorts.  A restored run continues as the saved one would
+ * have: particles, deposits and integer tallies bit for bit (the FP64
+ * absorbed-energy sums up to the order of their additions).  All three
+ * synchronise; the buffer is the caller's. */
+int pic_checkpoint_size(pic_handle *h, size_t *bytes);
+int pic_save(pic_handle *h, void *host_buf, size_t bytes, size_t *written);
+int pic_load(pic_handle *h, const void *host_buf, size_t bytes);
+
 /* Release the handle (not the caller's workspace or stream). */
 void pic_destroy(pic_handle *h);
 

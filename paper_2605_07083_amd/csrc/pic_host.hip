@@ -1136,6 +1136,213 @@ int pic_steady_state(pic_handle *h, int diode, int block_tallies, double tol_pp,
     return PIC_OK;
 }
 
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Checkpoint: a self-describing host image of every diode's state at a step
+// boundary.  Layout: header {magic, version, n_diodes, bytes}, then per diode
+// its configuration, state block, tallies, snapshot ring, live-count offsets,
+// node arrays (H, last H, H sums, phi, E, phi sum) and per species the slot
+// count and the slots (z, v_z, t_c, {v_x, v_y, id}) of the current buffer.
+// ----------------------------------------------------------------------------
+namespace {
+
+constexpr char CKPT_MAGIC[8] = {'P', 'I', 'C', 'C', 'K', 'P', 'T', '1'};
+constexpr uint32_t CKPT_VERSION = 1;
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t nd;
+    uint64_t bytes;
+};
+
+bool same_physics(const pic_config &a, const pic_config &b)
+{
+    return a.L == b.L && a.N == b.N && a.V == b.V && a.n0 == b.n0 && a.Te0 == b.Te0 && a.Ti0 == b.Ti0 &&
+           a.n_load == b.n_load && a.gamma_emit == b.gamma_emit && a.Tc == b.Tc && a.ng == b.ng &&
+           a.Tne == b.Tne && a.Tni == b.Tni && a.dt == b.dt && a.sig_el == b.sig_el && a.sig_x0 == b.sig_x0 &&
+           a.lotz_a == b.lotz_a && a.sig_cx == b.sig_cx && a.sig_iel == b.sig_iel && a.channels == b.channels &&
+           a.replenish == b.replenish && a.seed == b.seed && a.diode == b.diode &&
+           a.tally_period == b.tally_period;
+}
+
+size_t ckpt_bytes(const pic_handle *h, const std::vector<DiodeState> &st)
+{
+    size_t b = sizeof(CkptHeader);
+    for (int d = 0; d < h->nd; ++d) {
+        const size_t nn = (size_t)h->cfg[d].N + 1;
+        b += sizeof(pic_config) + sizeof(DiodeState) + sizeof(DiodeTally) + sizeof(TallySnap) * RING +
+             sizeof(int64_t) * NSP;
+        b += nn * (3 * 3 * sizeof(int64_t) + 3 * sizeof(double));
+        for (int s = 0; s < NSP; ++s)
+            b += sizeof(int32_t) + (size_t)st[d].n[s] * (sizeof(double) + sizeof(float) + sizeof(uint32_t) +
+                                                          sizeof(ColdRec));
+    }
+    return b;
+}
+
+int read_states(pic_handle *h, std::vector<DiodeState> &st)
+{
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    st.resize(h->nd);
+    HIP_TRY(hipMemcpy(st.data(), h->hD[0].st, sizeof(DiodeState) * h->nd, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+// device <-> host copy of one region, advancing the host cursor
+template <bool SAVE>
+int xfer(char *&cur, void *dev, size_t n)
+{
+    if (n == 0) return PIC_OK;
+    if (SAVE) HIP_TRY(hipMemcpy(cur, dev, n, hipMemcpyDeviceToHost));
+    else HIP_TRY(hipMemcpy(dev, cur, n, hipMemcpyHostToDevice));
+    cur += n;
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_checkpoint_size(pic_handle *h, size_t *bytes)
+{
+    if (!h || !bytes) return fail(PIC_EINVAL, "bad arguments");
+    std::vector<DiodeState> st;
+    int rc = read_states(h, st);
+    if (rc) return rc;
+    *bytes = ckpt_bytes(h, st);
+    return PIC_OK;
+}
+
+int pic_save(pic_handle *h, void *host_buf, size_t bytes, size_t *written)
+{
+    if (!h || !host_buf) return fail(PIC_EINVAL, "bad arguments");
+    std::vector<DiodeState> st;
+    int rc = read_states(h, st);
+    if (rc) return rc;
+    const size_t need = ckpt_bytes(h, st);
+    if (bytes < need) return fail(PIC_ENOSPACE, "checkpoint buffer too small (pic_checkpoint_size)");
+    char *cur = static_cast<char *>(host_buf);
+    CkptHeader hd;
+    std::memcpy(hd.magic, CKPT_MAGIC, 8);
+    hd.version = CKPT_VERSION;
+    hd.nd = h->nd;
+    hd.bytes = need;
+    std::memcpy(cur, &hd, sizeof(hd));
+    cur += sizeof(hd);
+    for (int d = 0; d < h->nd; ++d) {
+        const Diode &D = h->hD[d];
+        const size_t nn = (size_t)h->cfg[d].N + 1;
+        std::memcpy(cur, &h->cfg[d], sizeof(pic_config));
+        cur += sizeof(pic_config);
+        std::memcpy(cur, &st[d], sizeof(DiodeState));
+        cur += sizeof(DiodeState);
+        if ((rc = xfer<true>(cur, D.tally, sizeof(DiodeTally))) || (rc = xfer<true>(cur, D.ring, sizeof(TallySnap) * RING)))
+            return rc;
+        std::memcpy(cur, h->live_offset[d].data(), sizeof(int64_t) * NSP);
+        cur += sizeof(int64_t) * NSP;
+        for (int s = 0; s < NSP; ++s)
+            if ((rc = xfer<true>(cur, D.H[s], nn * 8)) || (rc = xfer<true>(cur, D.Hlast[s], nn * 8)) ||
+                (rc = xfer<true>(cur, D.Hsum[s], nn * 8)))
+                return rc;
+        if ((rc = xfer<true>(cur, D.phi, nn * 8)) || (rc = xfer<true>(cur, D.E, nn * 8)) ||
+            (rc = xfer<true>(cur, D.phi_sum, nn * 8)))
+            return rc;
+        for (int s = 0; s < NSP; ++s) {
+            const SpeciesBuf &b = D.buf[st[d].parity][s];
+            const int32_t n = st[d].n[s];
+            std::memcpy(cur, &n, sizeof(n));
+            cur += sizeof(n);
+            if ((rc = xfer<true>(cur, b.z, (size_t)n * 8)) || (rc = xfer<true>(cur, b.vz, (size_t)n * 4)) ||
+                (rc = xfer<true>(cur, b.tc, (size_t)n * 4)) || (rc = xfer<true>(cur, b.cold, (size_t)n * sizeof(ColdRec))))
+                return rc;
+        }
+    }
+    if (written) *written = need;
+    return PIC_OK;
+}
+
+int pic_load(pic_handle *h, const void *host_buf, size_t bytes)
+{
+    if (!h || !host_buf || bytes < sizeof(CkptHeader)) return fail(PIC_EINVAL, "bad arguments");
+    CkptHeader hd;
+    std::memcpy(&hd, host_buf, sizeof(hd));
+    if (std::memcmp(hd.magic, CKPT_MAGIC, 8) != 0 || hd.version != CKPT_VERSION)
+        return fail(PIC_EINVAL, "not a checkpoint of this library version");
+    if (hd.nd != h->nd) return fail(PIC_EINVAL, "checkpoint holds a different number of diodes");
+    if (hd.bytes > bytes) return fail(PIC_EINVAL, "checkpoint truncated");
+    // validate every diode before touching the device
+    const char *cur = static_cast<const char *>(host_buf) + sizeof(hd);
+    const char *end = static_cast<const char *>(host_buf) + hd.bytes;
+    std::vector<DiodeState> st(h->nd);
+    {
+        const char *c = cur;
+        for (int d = 0; d < h->nd; ++d) {
+            pic_config cfg;
+            if (c + sizeof(pic_config) + sizeof(DiodeState) > end) return fail(PIC_EINVAL, "checkpoint truncated");
+            std::memcpy(&cfg, c, sizeof(cfg));
+            if (!same_physics(cfg, h->cfg[d])) return fail(PIC_EINVAL, "checkpoint of a different configuration");
+            c += sizeof(pic_config);
+            std::memcpy(&st[d], c, sizeof(DiodeState));
+            c += sizeof(DiodeState) + sizeof(DiodeTally) + sizeof(TallySnap) * RING + sizeof(int64_t) * NSP;
+            const size_t nn = (size_t)cfg.N + 1;
+            c += nn * (3 * 3 * 8 + 3 * 8);
+            for (int s = 0; s < NSP; ++s) {
+                int32_t n;
+                if (c + sizeof(n) > end) return fail(PIC_EINVAL, "checkpoint truncated");
+                std::memcpy(&n, c, sizeof(n));
+                if (n < 0 || n > h->der[d].capacity[s] || n != st[d].n[s])
+                    return fail(PIC_ENOSPACE, "checkpoint particles exceed this handle's capacity");
+                c += sizeof(n) + (size_t)n * (8 + 4 + 4 + sizeof(ColdRec));
+            }
+            if (c > end) return fail(PIC_EINVAL, "checkpoint truncated");
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    char *cc = const_cast<char *>(cur);
+    int rc;
+    for (int d = 0; d < h->nd; ++d) {
+        const Diode &D = h->hD[d];
+        const size_t nn = (size_t)h->cfg[d].N + 1;
+        cc += sizeof(pic_config);
+        DiodeState s0 = st[d];
+        s0.parity = h->parity;   // the slots go into this handle's current buffer
+        cc += sizeof(DiodeState);
+        if ((rc = xfer<false>(cc, D.tally, sizeof(DiodeTally))) || (rc = xfer<false>(cc, D.ring, sizeof(TallySnap) * RING)))
+            return rc;
+        std::memcpy(h->live_offset[d].data(), cc, sizeof(int64_t) * NSP);
+        cc += sizeof(int64_t) * NSP;
+        for (int s = 0; s < NSP; ++s)
+            if ((rc = xfer<false>(cc, D.H[s], nn * 8)) || (rc = xfer<false>(cc, D.Hlast[s], nn * 8)) ||
+                (rc = xfer<false>(cc, D.Hsum[s], nn * 8)))
+                return rc;
+        if ((rc = xfer<false>(cc, D.phi, nn * 8)) || (rc = xfer<false>(cc, D.E, nn * 8)) ||
+            (rc = xfer<false>(cc, D.phi_sum, nn * 8)))
+            return rc;
+        for (int s = 0; s < NSP; ++s) {
+            const SpeciesBuf &b = D.buf[h->parity][s];
+            int32_t n;
+            std::memcpy(&n, cc, sizeof(n));
+            cc += sizeof(n);
+            if ((rc = xfer<false>(cc, b.z, (size_t)n * 8)) || (rc = xfer<false>(cc, b.vz, (size_t)n * 4)) ||
+                (rc = xfer<false>(cc, b.tc, (size_t)n * 4)) ||
+                (rc = xfer<false>(cc, b.cold, (size_t)n * sizeof(ColdRec))))
+                return rc;
+        }
+        HIP_TRY(hipMemcpy(D.st, &s0, sizeof(DiodeState), hipMemcpyHostToDevice));
+        // per-step scratch starts clear
+        for (int s = 0; s < NSP; ++s) HIP_TRY(hipMemset(D.cell_cnt[s], 0, nn * sizeof(int32_t)));
+        HIP_TRY(hipMemset(D.tacc, 0, sizeof(TallyCopy) * TALLY_COPIES));
+    }
+    h->sort_next = true;
+    return PIC_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
 void pic_destroy(pic_handle *h) { delete h; }
 
 }  // extern "C"

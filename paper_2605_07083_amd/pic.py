@@ -65,7 +65,7 @@ class PicDerived(C.Structure):
 SYMBOLS = ["pic_derive", "pic_workspace_size", "pic_init", "pic_init_from_profiles", "pic_step", "pic_sync", "pic_get_tally",
            "pic_diagnostics", "pic_get_fields", "pic_avg_reset", "pic_avg_control", "pic_get_hist", "pic_get_efield",
            "pic_get_particles", "pic_set_particles", "pic_set_counters", "pic_refield",
-           "pic_step_timed", "pic_set_tuning", "pic_get_tuning", "pic_autotune", "pic_steady_state", "pic_steady_from_series", "pic_last_error",
+           "pic_step_timed", "pic_set_tuning", "pic_get_tuning", "pic_autotune", "pic_steady_state", "pic_steady_from_series", "pic_checkpoint_size", "pic_save", "pic_load", "pic_last_error",
            "pic_destroy"]
 
 _lib = None
@@ -104,6 +104,9 @@ def lib():
         "pic_autotune": ([P, i64, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(d)], i),
         "pic_steady_state": ([P, i, i, d, d, C.POINTER(PicSteady)], i),
         "pic_steady_from_series": ([P, P, i, d, d, C.POINTER(i), C.POINTER(d), C.POINTER(i)], i),
+        "pic_checkpoint_size": ([P, C.POINTER(C.c_size_t)], i),
+        "pic_save": ([P, P, C.c_size_t, C.POINTER(C.c_size_t)], i),
+        "pic_load": ([P, P, C.c_size_t], i),
         "pic_last_error": ([], C.c_char_p),
         "pic_destroy": ([P], None),
     }
@@ -323,6 +326,20 @@ class Handle:
         v = [C.c_int() for _ in range(4)]
         _check(lib().pic_get_tuning(self.h, *[C.byref(x) for x in v]))
         return dict(zip(("ppt", "grid", "sort_period", "use_graph"), [x.value for x in v]))
+
+    def save(self):
+        """Checkpoint image of every diode (numpy uint8 array, host memory)."""
+        n = C.c_size_t()
+        _check(lib().pic_checkpoint_size(self.h, C.byref(n)))
+        buf = np.empty(n.value, np.uint8)
+        w = C.c_size_t()
+        _check(lib().pic_save(self.h, _ptr(buf), buf.size, C.byref(w)))
+        return buf[:w.value]
+
+    def load(self, image):
+        """Restore a checkpoint image written by save() of a handle with the same configurations."""
+        buf = np.ascontiguousarray(image, np.uint8)
+        _check(lib().pic_load(self.h, _ptr(buf), buf.size))
 
     def set_counters(self, d, step, next_id):
         _check(lib().pic_set_counters(self.h, d, int(step), int(next_id)))

@@ -262,3 +262,41 @@ def test_step_timed_measures_the_particle_kernel(pic, N):
     a, b = res[0]["particle_kernel_ms"], res[1]["particle_kernel_ms"]
     _say("  particle kernel: stream %.1f us, graph %.1f us" % (a * 1e3, b * 1e3))
     assert abs(a - b) < 0.35 * max(a, b)
+
+
+def test_checkpoint_restart_is_exact(pic):
+    """A run restored from a checkpoint continues as the saved run does:
+    particles, deposits, fields and integer tallies identical; the FP64
+    absorbed-energy sums to rounding.  Two diodes, one batch."""
+    _say("case: checkpoint / restart")
+    cfgs = [presets.scaled(presets.tiny(), gamma_emit=1e21, diode=0),
+            presets.scaled(presets.tiny(), gamma_emit=3e21, Te0=10.0, ng=3.2e22, diode=1)]
+    a = pic.Handle(cfgs)
+    a.step(40)
+    img = a.save()
+    a.step(30)
+    b = pic.Handle(cfgs)
+    b.step(3)                      # a different state, overwritten by the image
+    b.load(img)
+    b.step(30)
+    for d in range(2):
+        ta, tb = a.tally(d), b.tally(d)
+        assert ta["step"] == tb["step"] == 70 and ta["next_id"] == tb["next_id"]
+        for k in ("abs_count", "cand", "coll", "n_live"):
+            assert np.array_equal(ta[k], tb[k]), k
+        for k in ("n_emit", "n_repl", "n_iz"):
+            assert ta[k] == tb[k], k
+        assert np.allclose(ta["abs_energy"], tb["abs_energy"], rtol=1e-12, atol=0)
+        for sp in range(3):
+            pa, pb = by_id(a.particles(d, sp)), by_id(b.particles(d, sp))
+            for k in ("id", "z", "vx", "vy", "vz", "tc"):
+                assert np.array_equal(pa[k], pb[k]), (d, sp, k)
+            assert np.array_equal(a.hist(d, sp), b.hist(d, sp))
+        assert np.array_equal(a.fields(d)["phi"], b.fields(d)["phi"])
+    # a handle of another configuration refuses the image
+    c = pic.Handle([presets.scaled(cfgs[0], V=5.0), cfgs[1]])
+    with pytest.raises(pic.PicError) as e:
+        c.load(img)
+    assert e.value.code == pic.PIC_EINVAL
+    with pytest.raises(pic.PicError):
+        b.load(img[:100])
