@@ -20,7 +20,7 @@ namespace pic {
 constexpr int NT = 256;            // threads per particle block
 constexpr int NW = NT / 64;        // wavefronts per particle block
 constexpr int WMAX = 512;          // LDS window (nodes) of the field tile / histogram
-constexpr int QW_SLACK = 1024;     // per-wave LDS queue of rare items: 64 PPT + QW_SLACK entries
+constexpr int QW_SLACK = 384;      // per-wave LDS queue of rare items: 64 PPT + QW_SLACK entries
 constexpr int DRIFT = 96;          // cells of drift since the last re-sort kept in the LDS window
 constexpr int BIN_SHIFT = 5;       // the re-sort orders particles by bins of 32 cells
 constexpr int DRIFT_B = (DRIFT >> BIN_SHIFT) + 1;   // the drift margin in bins
@@ -274,8 +274,9 @@ __device__ __forceinline__ void rare_tally_zero(RareTally *t)
     *t = RareTally{};
 }
 
-__device__ __forceinline__ float mcc_one(const Diode &dd, int s, const SpeciesBuf &b, int i, uint32_t step, double zn,
-                        float vzn, RareTally *cc)
+// vzn: v_z after the push; the position is read back only for an ionization.
+__device__ __forceinline__ void mcc_one(const Diode &dd, int s, const SpeciesBuf &b, int i, uint32_t step, float vzn,
+                                        RareTally *cc)
 {
     const int ion = (s == SP_I);
     const ColdRec cr = b.cold[i];
@@ -350,7 +351,7 @@ __device__ __forceinline__ float mcc_one(const Diode &dd, int s, const SpeciesBu
                 int q = atomicAdd(&dd.st->iz_count, 1);
                 if (q < IZQ_CAP) {
                     IzEvent ev;
-                    ev.z = zn;
+                    ev.z = b.z[i];
                     ev.parent = id;
                     ev.ve[0] = cx + fM * gs * st2 * cp2;
                     ev.ve[1] = cy + fM * gs * st2 * sp2;
@@ -370,7 +371,6 @@ __device__ __forceinline__ float mcc_one(const Diode &dd, int s, const SpeciesBu
     }
     b.vz[i] = vz;
     b.tc[i] = tcn;
-    return vz;
 }
 
 // ---------------------------------------------------------------------------
@@ -381,9 +381,11 @@ __device__ __forceinline__ float mcc_one(const Diode &dd, int s, const SpeciesBu
 // Runs of chunks of one (diode, species) share one LDS window: the field tile
 // of the gather and the fixed-point histogram of the deposit cover the bins
 // of the run's first and last particle plus a drift margin; particles outside
-// it use global memory.  The deposit sums a thread's
-// consecutive same-cell particles in registers and touches LDS only when the
-// cell changes; a wave whose lanes end in one cell combines them first.
+// it use global memory.  The LDS histogram holds one packed word per cell
+// (count and sum of a), one LDS atomic per particle, unpacked into node
+// values when the run's window is flushed.  A thread sums its consecutive
+// same-cell particles in registers and touches LDS only when the cell
+// changes; a wave whose lanes end in one cell combines them first.
 // Inside a run the chunk loop has no barrier and the next chunk's particle
 // data is loaded while the current one is processed.  Rare work (candidates,
 // absorbed particles) is queued in LDS and done in batches.
@@ -396,8 +398,9 @@ __device__ __forceinline__ void lds_barrier()
 }
 
 // Rare work item: slot index with the kind in the top two bits
-// (0 candidate, 1 absorbed at the cathode, 2 absorbed at the anode).  Its
-// position and new v_z are re-read from the buffers, stored by the main loop.
+// (0 candidate, 1 absorbed at the cathode, 2 absorbed at the anode).  The
+// wave's queue keeps the new v_z beside it; items moved to the global list
+// re-read v_z from the buffer, stored by the main loop.
 constexpr uint32_t RARE_SHIFT = 30;
 constexpr uint32_t RARE_MASK = (1u << RARE_SHIFT) - 1u;
 
@@ -451,7 +454,7 @@ __device__ __forceinline__ void process_rare(const Diode &dd, const DiodeState *
             const uint32_t item = dd.rare[s][k];
             const int i = (int)(item & RARE_MASK);
             const uint32_t kind = item >> RARE_SHIFT;
-            if (kind == 0u) mcc_one(dd, s, b, i, step, b.z[i], b.vz[i], rt);
+            if (kind == 0u) mcc_one(dd, s, b, i, step, b.vz[i], rt);
             else rare_absorbed(dd, s, b, i, (int)kind - 1, b.vz[i], rt);
         }
     }
@@ -536,15 +539,26 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// Add (L, A) to nodes (j, j+1): the LDS window when inside it, else global.
-__device__ __forceinline__ void flush_run(int j, unsigned long long L, unsigned long long A, int w0, int wn,
+// Packed deposit word of cell j: (particle count << PK_SHIFT) + sum of a.
+// The cell's particles give node j  count * 2^32 - sum a  and node j+1  sum a,
+// so one word per cell carries both.  A run holds at most RUN_PARTICLES
+// particles, so the sum of a (each <= 2^32) stays below 2^PK_SHIFT and the
+// count below 2^(64 - PK_SHIFT).
+constexpr int PK_SHIFT = 48;
+constexpr unsigned long long PK_MASK = (1ull << PK_SHIFT) - 1ull;
+constexpr int RUN_PARTICLES = 65535;
+
+// Add a packed cell word to the LDS window when the cell is inside it, else
+// its two node contributions to global memory.
+__device__ __forceinline__ void flush_run(int j, unsigned long long P, int w0, int wn,
                                           unsigned long long *hist, unsigned long long *H)
 {
     const int jl = j - w0;
     if (jl >= 0 && jl + 1 < wn) {
-        if (L) atomicAdd(&hist[jl], L);
-        if (A) atomicAdd(&hist[jl + 1], A);
+        atomicAdd(&hist[jl], P);
     } else {
+        const unsigned long long A = P & PK_MASK;
+        const unsigned long long L = ((P >> PK_SHIFT) << 32) - A;
         if (L) atomicAdd(&H[j], L);
         if (A) atomicAdd(&H[j + 1], A);
     }
@@ -564,6 +578,7 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
     __shared__ unsigned long long hist[WMAX + 2];
     constexpr int QW = 64 * PPT + QW_SLACK;
     __shared__ uint32_t rq_i[NW][QW];   // slot | kind << 30
+    __shared__ float rq_v[NW][QW];      // v_z after the push
     __shared__ int q_n[NW];
     __shared__ RareTally rt;
 
@@ -577,7 +592,7 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
 
     for (int c = c_begin; c < c_end;) {
         const int seg = uni(find_seg(seg_end, cm.nseg, c));
-        const int run_end = uni(min(c_end, seg_end[seg]));
+        const int run_end = uni(min(min(c_end, seg_end[seg]), c + max(1, RUN_PARTICLES / CHUNK)));
         const int segbase = uni(seg ? seg_end[seg - 1] : 0);
         const int d = seg / NSP, s = seg - d * NSP;
         const Diode &dd = D[d];
@@ -605,7 +620,6 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             if (mode == 0) etile[t] = dd.E[w0 + t];
             hist[t] = 0ull;
         }
-        if (tid < NW) q_n[tid] = 0;
         lds_barrier();
 
         const double qmdt = dd.qmdt[s], dt = dd.dt, L = dd.L;
@@ -620,28 +634,27 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
         const int w = tid >> 6, lane = tid & 63;
         uint32_t *rare = dd.rare[s];
         ChunkRegs<PPT> A, Bn;
+        int qn = 0;     // the wave's queue length (wave-uniform)
         if (c < run_end) load_chunk<PPT>(A, b, (c - segbase) * CHUNK + tid * PPT, mode);
         for (int cc_ = c; cc_ < run_end; ++cc_) {
-            if (mode == 0) {
-                const int qn = q_n[w];
-                if (qn > QW - 64 * PPT) {
-                    int base = 0;
-                    if (lane == 0) base = atomicAdd(&dd.st->rare_n[s], qn);
-                    base = __shfl(base, 0, 64);
-                    for (int q = lane; q < qn; q += 64) rare[base + q] = rq_i[w][q];
-                    if (lane == 0) q_n[w] = 0;
-                }
+            if (mode == 0 && qn > QW - 64 * PPT) {
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&dd.st->rare_n[s], qn);
+                base = __shfl(base, 0, 64);
+                for (int q = lane; q < qn; q += 64) rare[base + q] = rq_i[w][q];
+                qn = 0;
             }
             const int t0 = (cc_ - segbase) * CHUNK + tid * PPT;
             if (cc_ + 1 < run_end) load_chunk<PPT>(Bn, b, t0 + CHUNK, mode);
             int jcur = -1;
-            unsigned long long accL = 0ull, accA = 0ull;
+            unsigned long long accP = 0ull;
             double zw[PPT];
             float vw[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const int i = t0 + k;
                 bool alive = i < n && A.z[k] >= 0.0;
+                uint32_t item = NEVER;
                 double z = A.z[k];
                 zw[k] = A.z[k];
                 vw[k] = A.vz[k];
@@ -661,7 +674,6 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                     const float vzn = (float)((double)A.vz[k] + qmdt * Ep);
                     const double zn = z + (double)vzn * dt;
                     vw[k] = vzn;
-                    uint32_t item = NEVER;
                     if (zn <= 0.0 || zn >= L) {
                         // absorbing electrodes: tallied with the rare work
                         zw[k] = -1.0;
@@ -673,24 +685,31 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                         zw[k] = zn;
                         if (A.tc[k] == step) item = (uint32_t)i;
                     }
-                    if (item != NEVER) {
-                        const int q = atomicAdd(&q_n[w], 1);
-                        rq_i[w][q] = item;
+                }
+                if (mode == 0) {
+                    // append to the wave's queue: slot from the ballot, no LDS atomics
+                    const unsigned long long m = __ballot(item != NEVER);
+                    if (m) {
+                        const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        if (item != NEVER) {
+                            rq_i[w][pos] = item;
+                            rq_v[w][pos] = vw[k];
+                        }
+                        qn = uni(qn + __popcll(m));
                     }
                 }
                 if (alive) {
                     int j;
                     double f;
                     cic(z, invdz, N, j, f);
-                    const unsigned long long a = fixed_right(f);
+                    const unsigned long long p = (1ull << PK_SHIFT) + fixed_right(f);
                     if (j != jcur) {
-                        if (jcur >= 0) flush_run(jcur, accL, accA, w0, wn, hist, H);
+                        if (jcur >= 0) flush_run(jcur, accP, w0, wn, hist, H);
                         jcur = j;
-                        accL = (1ull << 32) - a;
-                        accA = a;
+                        accP = p;
                     } else {
-                        accL += (1ull << 32) - a;
-                        accA += a;
+                        accP += p;
                     }
                 }
             }
@@ -704,17 +723,21 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             // last run of every lane: combine across the wave when all lanes agree
             const int j0w = __shfl(jcur, 0, 64);
             if (__all(jcur == j0w)) {
-                const unsigned long long sL = wave_sum_u64(accL), sA = wave_sum_u64(accA);
-                if (lane == 0 && j0w >= 0) flush_run(j0w, sL, sA, w0, wn, hist, H);
+                const unsigned long long sP = wave_sum_u64(accP);
+                if (lane == 0 && j0w >= 0) flush_run(j0w, sP, w0, wn, hist, H);
             } else if (jcur >= 0) {
-                flush_run(jcur, accL, accA, w0, wn, hist, H);
+                flush_run(jcur, accP, w0, wn, hist, H);
             }
             A = Bn;
         }
+        if (lane == 0) q_n[w] = qn;
         // the main loop's z, v_z stores precede the rare work's reads (workgroup scope)
         __syncthreads();
+        // node w0 + t: cell t's  count * 2^32 - sum a  plus cell t-1's  sum a
         for (int t = tid; t < wn; t += NT) {
-            const unsigned long long v = hist[t];
+            const unsigned long long P = hist[t];
+            const unsigned long long Pm = t > 0 ? hist[t - 1] : 0ull;
+            const unsigned long long v = ((P >> PK_SHIFT) << 32) - (P & PK_MASK) + (Pm & PK_MASK);
             if (v) atomicAdd(&H[w0 + t], v);
         }
         if (mode == 0) {
@@ -729,8 +752,8 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                 const uint32_t item = rq_i[wq][k];
                 const int i = (int)(item & RARE_MASK);
                 const uint32_t kind = item >> RARE_SHIFT;
-                if (kind == 0u) mcc_one(dd, s, b, i, step, b.z[i], b.vz[i], &rt);
-                else rare_absorbed(dd, s, b, i, (int)kind - 1, b.vz[i], &rt);
+                if (kind == 0u) mcc_one(dd, s, b, i, step, rq_v[wq][k], &rt);
+                else rare_absorbed(dd, s, b, i, (int)kind - 1, rq_v[wq][k], &rt);
             }
             lds_barrier();
             if (tid == 0) {
