@@ -30,6 +30,49 @@ __host__ __device__ constexpr int nbins_of(int N) { return ((N - 1) >> BIN_SHIFT
 // array: 128 bytes apart, so that the device-scope atomics of many blocks on
 // the bins spread over memory channels instead of queueing on one.
 __device__ __forceinline__ int bin_slot(int b) { return b << BIN_SHIFT; }
+
+// Device views of the particle and grid arrays in the global address space.
+// Pointers loaded from the Diode block are generic, and generic accesses
+// compile to flat_* instructions, which count in the LDS counter as well as
+// the vector-memory one: every wait for an LDS result would then also wait
+// for all flat loads and stores in flight, the next chunk's prefetch
+// included.  global_* instructions count only in the vector-memory counter.
+#define GLB __attribute__((address_space(1)))
+struct GBuf {
+    GLB double *z;
+    GLB float *vz;
+    GLB uint32_t *tc;
+    GLB ColdRec *cold;
+};
+__device__ __forceinline__ GBuf gbuf(const SpeciesBuf &b)
+{
+    return GBuf{(GLB double *)b.z, (GLB float *)b.vz, (GLB uint32_t *)b.tc, (GLB ColdRec *)b.cold};
+}
+template <class T>
+__device__ __forceinline__ GLB T *glb(T *p)
+{
+    return (GLB T *)p;
+}
+__device__ __forceinline__ void gadd(GLB unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int gadd(GLB int *p, int v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Cold records move as one 16-byte vector (a struct cannot be assigned in
+// another address space).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ ColdRec get_cold(const GLB ColdRec *p)
+{
+    const u32x4 v = *(const GLB u32x4 *)p;
+    return ColdRec{__uint_as_float(v.x), __uint_as_float(v.y), v.z, v.w};
+}
+__device__ __forceinline__ void put_cold(GLB ColdRec *p, float vx, float vy, uint32_t id)
+{
+    *(GLB u32x4 *)p = u32x4{__float_as_uint(vx), __float_as_uint(vy), id, 0u};
+}
 constexpr int FT = 1024;           // threads of the sources / field blocks
 constexpr int FW = FT / 64;
 constexpr double TWO32 = 4294967296.0;
@@ -275,11 +318,11 @@ __device__ __forceinline__ void rare_tally_zero(RareTally *t)
 }
 
 // vzn: v_z after the push; the position is read back only for an ionization.
-__device__ __forceinline__ void mcc_one(const Diode &dd, int s, const SpeciesBuf &b, int i, uint32_t step, float vzn,
+__device__ __forceinline__ void mcc_one(const Diode &dd, int s, const GBuf &b, int i, uint32_t step, float vzn,
                                         RareTally *cc)
 {
     const int ion = (s == SP_I);
-    const ColdRec cr = b.cold[i];
+    const ColdRec cr = get_cold(&b.cold[i]);
     float vx = cr.vx, vy = cr.vy, vz = vzn;
     const uint32_t id = cr.id;
     // The three counter blocks are generated one at a time, each consumed
@@ -367,9 +410,11 @@ __device__ __forceinline__ void mcc_one(const Diode &dd, int s, const SpeciesBuf
             vy = cy + fM * gp * st * sp;
             vz = cz + fM * gp * ct;
         }
-        b.cold[i] = ColdRec{vx, vy, id, 0u};
+        put_cold(&b.cold[i], vx, vy, id);
+        b.vz[i] = vz;
     }
-    b.vz[i] = vz;
+    // a null collision leaves v_z as the push stored it: only the countdown
+    // changes (each store here is a partial line written back on its own)
     b.tc[i] = tcn;
 }
 
@@ -414,7 +459,7 @@ struct ChunkRegs {
 // Slots [t0, t0 + PPT) of one thread; capacities are multiples of the largest
 // chunk, so the whole range is always inside the buffer.
 template <int PPT>
-__device__ __forceinline__ void load_chunk(ChunkRegs<PPT> &C, const SpeciesBuf &b, int t0, int mode)
+__device__ __forceinline__ void load_chunk(ChunkRegs<PPT> &C, const GBuf &b, int t0, int mode)
 {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) C.z[k] = b.z[t0 + k];
@@ -428,10 +473,10 @@ __device__ __forceinline__ void load_chunk(ChunkRegs<PPT> &C, const SpeciesBuf &
 }
 
 // vzn: v_z at the crossing (v^{n+1/2})
-__device__ __forceinline__ void rare_absorbed(const Diode &dd, int s, const SpeciesBuf &b, int i, int wall, float vzn,
+__device__ __forceinline__ void rare_absorbed(const Diode &dd, int s, const GBuf &b, int i, int wall, float vzn,
                                               RareTally *rt)
 {
-    const ColdRec cr = b.cold[i];
+    const ColdRec cr = get_cold(&b.cold[i]);
     const double vx = cr.vx, vy = cr.vy, vz = vzn;
     const double ke = 0.5 * dd.mass[s] * (vx * vx + vy * vy + vz * vz);
     atomicAdd(&rt->abs_count[s][wall], 1u);
@@ -449,7 +494,7 @@ __device__ __forceinline__ void process_rare(const Diode &dd, const DiodeState *
 #pragma unroll 1
     for (int s = 0; s < NSP; ++s) {
         const int n = st->rare_n[s];
-        const SpeciesBuf b = dd.buf[parity][s];
+        const GBuf b = gbuf(dd.buf[parity][s]);
         for (int k = first; k < n; k += stride) {
             const uint32_t item = dd.rare[s][k];
             const int i = (int)(item & RARE_MASK);
@@ -551,7 +596,7 @@ constexpr int RUN_PARTICLES = 65535;
 // Add a packed cell word to the LDS window when the cell is inside it, else
 // its two node contributions to global memory.
 __device__ __forceinline__ void flush_run(int j, unsigned long long P, int w0, int wn,
-                                          unsigned long long *hist, unsigned long long *H)
+                                          unsigned long long *hist, GLB unsigned long long *H)
 {
     const int jl = j - w0;
     if (jl >= 0 && jl + 1 < wn) {
@@ -559,8 +604,8 @@ __device__ __forceinline__ void flush_run(int j, unsigned long long P, int w0, i
     } else {
         const unsigned long long A = P & PK_MASK;
         const unsigned long long L = ((P >> PK_SHIFT) << 32) - A;
-        if (L) atomicAdd(&H[j], L);
-        if (A) atomicAdd(&H[j + 1], A);
+        if (L) gadd(&H[j], L);
+        if (A) gadd(&H[j + 1], A);
     }
 }
 
@@ -596,13 +641,16 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
         const int segbase = uni(seg ? seg_end[seg - 1] : 0);
         const int d = seg / NSP, s = seg - d * NSP;
         const Diode &dd = D[d];
-        const SpeciesBuf b = dd.buf[parity][s];
+        const GBuf b = gbuf(dd.buf[parity][s]);
         const int N = dd.N;
         const double invdz = dd.invdz;
         const int n = uni(seg_n[seg]);
         const int slot0 = (c - segbase) * CHUNK;
 
         const uint32_t step = (uint32_t)uni((int)S[d].step);
+        // the run's first chunk is loaded while the window and field tile are set up
+        ChunkRegs<PPT> A, Bn;
+        load_chunk<PPT>(A, b, slot0 + tid * PPT, mode);
         // window of the run from its first and last particle
         const int last_slot = min(n, (run_end - segbase) * CHUNK) - 1;
         int w0, wn;
@@ -617,13 +665,13 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             wn = uni(min(min(N, ((bb + 1) << BIN_SHIFT) + DRIFT) - w0 + 1, WMAX + 1));
         }
         for (int t = tid; t < wn; t += NT) {
-            if (mode == 0) etile[t] = dd.E[w0 + t];
+            if (mode == 0) etile[t] = glb(dd.E)[w0 + t];
             hist[t] = 0ull;
         }
         lds_barrier();
 
         const double qmdt = dd.qmdt[s], dt = dd.dt, L = dd.L;
-        unsigned long long *H = dd.H[s];
+        GLB unsigned long long *H = glb(dd.H[s]);
         // The chunks of the run have no barrier: each wave streams its share of
         // every chunk, holding the next chunk's particle registers in flight
         // while it works on the current one.  Rare items (collision candidates,
@@ -632,20 +680,34 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
         // its items to the species' list in global memory instead, which the
         // sources kernels work through.
         const int w = tid >> 6, lane = tid & 63;
-        uint32_t *rare = dd.rare[s];
-        ChunkRegs<PPT> A, Bn;
+        GLB uint32_t *rare = glb(dd.rare[s]);
         int qn = 0;     // the wave's queue length (wave-uniform)
-        if (c < run_end) load_chunk<PPT>(A, b, (c - segbase) * CHUNK + tid * PPT, mode);
+        // The z, v_z stores of a chunk are issued one iteration later, after the
+        // next prefetch: loads and stores share one completion counter whose
+        // order between the two kinds is not kept, so the wait for the
+        // prefetched registers also waits for every store issued before it.
+        double zs[PPT];
+        float vs[PPT];
+        int ts = -1;
         for (int cc_ = c; cc_ < run_end; ++cc_) {
             if (mode == 0 && qn > QW - 64 * PPT) {
                 int base = 0;
-                if (lane == 0) base = atomicAdd(&dd.st->rare_n[s], qn);
+                if (lane == 0)
+                    base = __hip_atomic_fetch_add(glb(&dd.st->rare_n[s]), qn, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
                 base = __shfl(base, 0, 64);
                 for (int q = lane; q < qn; q += 64) rare[base + q] = rq_i[w][q];
                 qn = 0;
             }
             const int t0 = (cc_ - segbase) * CHUNK + tid * PPT;
             if (cc_ + 1 < run_end) load_chunk<PPT>(Bn, b, t0 + CHUNK, mode);
+            if (mode == 0 && ts >= 0) {
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    b.z[ts + k] = zs[k];
+                    b.vz[ts + k] = vs[k];
+                }
+            }
             int jcur = -1;
             unsigned long long accP = 0ull;
             double zw[PPT];
@@ -662,14 +724,25 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                     int jo;
                     double fo;
                     cic(z, invdz, N, jo, fo);
-                    double e0, e1;
                     const int jl = jo - w0;
-                    if (jl >= 0 && jl + 1 < wn) { e0 = etile[jl]; e1 = etile[jl + 1]; }
-                    else { e0 = dd.E[jo]; e1 = dd.E[jo + 1]; }
+                    const bool inw = jl >= 0 && jl + 1 < wn;
                     double Ep;
-                    {
+                    if (__builtin_expect(__ballot(!inw) != 0ull, 0)) {
+                        // a lane outside the window: this wave reads E from global
+                        // memory and waits for it here, so the common path below
+                        // carries no wait on a global load (which would also wait
+                        // for the next chunk's prefetch)
+                        double e0, e1;
+                        if (inw) { e0 = etile[jl]; e1 = etile[jl + 1]; }
+                        else { e0 = glb(dd.E)[jo]; e1 = glb(dd.E)[jo + 1]; }
+                        {
 #pragma clang fp contract(off)
-                        Ep = (1.0 - fo) * e0 + fo * e1;
+                            Ep = (1.0 - fo) * e0 + fo * e1;
+                        }
+                        asm volatile("" : "+v"(Ep));
+                    } else {
+#pragma clang fp contract(off)
+                        Ep = (1.0 - fo) * etile[jl] + fo * etile[jl + 1];
                     }
                     const float vzn = (float)((double)A.vz[k] + qmdt * Ep);
                     const double zn = z + (double)vzn * dt;
@@ -680,7 +753,9 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                         alive = false;
                         item = (uint32_t)i | ((zn <= 0.0 ? 1u : 2u) << RARE_SHIFT);
                     } else {
-                        if (!(zn == zn)) atomicOr(&dd.st->err, ERR_NAN);
+                        if (!(zn == zn))
+                            __hip_atomic_fetch_or(glb(&dd.st->err), (unsigned)ERR_NAN, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
                         z = zn;
                         zw[k] = zn;
                         if (A.tc[k] == step) item = (uint32_t)i;
@@ -716,9 +791,10 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             if (mode == 0) {
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    b.z[t0 + k] = zw[k];
-                    b.vz[t0 + k] = vw[k];
+                    zs[k] = zw[k];
+                    vs[k] = vw[k];
                 }
+                ts = t0;
             }
             // last run of every lane: combine across the wave when all lanes agree
             const int j0w = __shfl(jcur, 0, 64);
@@ -730,6 +806,13 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             }
             A = Bn;
         }
+        if (mode == 0 && ts >= 0) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                b.z[ts + k] = zs[k];
+                b.vz[ts + k] = vs[k];
+            }
+        }
         if (lane == 0) q_n[w] = qn;
         // the main loop's z, v_z stores precede the rare work's reads (workgroup scope)
         __syncthreads();
@@ -738,7 +821,7 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             const unsigned long long P = hist[t];
             const unsigned long long Pm = t > 0 ? hist[t - 1] : 0ull;
             const unsigned long long v = ((P >> PK_SHIFT) << 32) - (P & PK_MASK) + (Pm & PK_MASK);
-            if (v) atomicAdd(&H[w0 + t], v);
+            if (v) gadd(&H[w0 + t], v);
         }
         if (mode == 0) {
             // the run's rare items with the whole block, while their lines are
@@ -785,9 +868,9 @@ __global__ __launch_bounds__(256) void k_load(const Diode *__restrict__ D, const
     bm32(b0.x, b0.y, n1, n2);
     bm32(b0.z, b0.w, n3, n4);
     const double sig = s == SP_P ? dd.sig_e0 : dd.sig_i0;
-    const SpeciesBuf b = dd.buf[0][s];
+    const GBuf b = gbuf(dd.buf[0][s]);
     b.z[i] = dd.L * u53(b1.x, b1.y);
-    b.cold[i] = ColdRec{(float)(sig * n1), (float)(sig * n2), id, 0u};
+    put_cold(&b.cold[i], (float)(sig * n1), (float)(sig * n2), id);
     b.vz[i] = (float)(sig * n3);
     uint32_t tc = next_candidate(0u, dd.lam[s == SP_I], b1.z, b1.w);
     if (tc != NEVER) tc -= 1u;
@@ -882,7 +965,7 @@ __global__ __launch_bounds__(256) void k_profile_fill(const Diode *__restrict__ 
     const uint32_t id0 = s == SP_P ? 0u : (uint32_t)dd.cell_cnt[SP_P][dd.N];
     const double sig = s == SP_P ? dd.sig_e0 : dd.sig_i0;
     const double lam = dd.lam[s == SP_I];
-    const SpeciesBuf b = dd.buf[0][s];
+    const GBuf b = gbuf(dd.buf[0][s]);
     for (int i = a + lane; i < e; i += 64) {
         const uint32_t id = id0 + (uint32_t)i;
         const uint4 b0 = philox(LOAD_STEP, EV_LOAD, 0u, 0u, id, dd.kseed);
@@ -891,7 +974,7 @@ __global__ __launch_bounds__(256) void k_profile_fill(const Diode *__restrict__ 
         bm32(b0.x, b0.y, n1, n2);
         bm32(b0.z, b0.w, n3, n4);
         b.z[i] = ((double)c + u53(b1.x, b1.y)) * dd.dz;
-        b.cold[i] = ColdRec{(float)(sig * n1), (float)(sig * n2), id, 0u};
+        put_cold(&b.cold[i], (float)(sig * n1), (float)(sig * n2), id);
         b.vz[i] = (float)(sig * n3);
         uint32_t tc = next_candidate(0u, lam, b1.z, b1.w);
         if (tc != NEVER) tc -= 1u;
@@ -944,7 +1027,7 @@ __device__ __forceinline__ int wave_group_rank(int key, AddFn add)
 
 // Window of a run of chunks for the re-sort: bins of its first and last
 // particle plus the drift margin (bins).
-__device__ __forceinline__ void sort_window(const Diode &dd, const SpeciesBuf &b, int slot0, int last_slot, int &w0,
+__device__ __forceinline__ void sort_window(const Diode &dd, const GBuf &b, int slot0, int last_slot, int &w0,
                                             int &wn)
 {
     int ja, jb;
@@ -979,18 +1062,18 @@ __global__ __launch_bounds__(NT) void k_sort_count(const Diode *__restrict__ D, 
         const int segbase = seg ? seg_end[seg - 1] : 0;
         const int d = seg / NSP, s = seg - d * NSP;
         const Diode &dd = D[d];
-        const SpeciesBuf b = dd.buf[parity][s];
+        const GBuf b = gbuf(dd.buf[parity][s]);
         const int n = seg_n[seg];
         const int slot0 = (c - segbase) * CHUNK;
         int w0, wn;
         sort_window(dd, b, slot0, min(n, (run_end - segbase) * CHUNK) - 1, w0, wn);
         for (int t = tid; t < wn; t += NT) cnt[t] = 0;
         lds_barrier();
-        int *gc = dd.cell_cnt[s];
+        GLB int *gc = glb(dd.cell_cnt[s]);
         auto add = [&](int key, int m) {
             const int jl = key - w0;
             if (jl >= 0 && jl < wn) atomicAdd(&cnt[jl], m);
-            else atomicAdd(&gc[bin_slot(key)], m);
+            else gadd(&gc[bin_slot(key)], m);
             return 0;
         };
         for (int cc_ = c; cc_ < run_end; ++cc_) {
@@ -1009,7 +1092,7 @@ __global__ __launch_bounds__(NT) void k_sort_count(const Diode *__restrict__ D, 
         }
         lds_barrier();
         for (int t = tid; t < wn; t += NT)
-            if (cnt[t]) atomicAdd(&gc[bin_slot(w0 + t)], cnt[t]);
+            if (cnt[t]) gadd(&gc[bin_slot(w0 + t)], cnt[t]);
         lds_barrier();
         c = run_end;
     }
@@ -1068,14 +1151,14 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
         const int run_end = c + 1;
         const int d = seg / NSP, s = seg - d * NSP;
         const Diode &dd = D[d];
-        const SpeciesBuf src = dd.buf[parity][s], dst = dd.buf[parity ^ 1][s];
+        const GBuf src = gbuf(dd.buf[parity][s]), dst = gbuf(dd.buf[parity ^ 1][s]);
         const int n = seg_n[seg];
         const int slot0 = (c - segbase) * CHUNK;
         int w0, wn;
         sort_window(dd, src, slot0, min(n, (run_end - segbase) * CHUNK) - 1, w0, wn);
         for (int t = tid; t < wn; t += NT) cnt[t] = 0;
         lds_barrier();
-        int *cur = dd.cell_cnt[s];
+        GLB int *cur = glb(dd.cell_cnt[s]);
         const int t0 = slot0 + tid * PPT;
         int j[PPT], rank[PPT];
         double z[PPT];
@@ -1094,7 +1177,7 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
         auto add = [&](int key, int m) {
             const int jl = key - w0;
             if (jl >= 0 && jl < wn) return atomicAdd(&cnt[jl], m);
-            return -1 - atomicAdd(&cur[bin_slot(key)], m) - (m - 1);
+            return -1 - gadd(&cur[bin_slot(key)], m) - (m - 1);
         };
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -1108,7 +1191,7 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
         lds_barrier();
         for (int t = tid; t < wn; t += NT) {
             const int v = cnt[t];
-            if (v) cnt[t] = atomicAdd(&cur[bin_slot(w0 + t)], v);
+            if (v) cnt[t] = gadd(&cur[bin_slot(w0 + t)], v);
         }
         lds_barrier();
 #pragma unroll
@@ -1117,7 +1200,7 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
             const int dest = rank[k] >= 0 ? cnt[j[k] - w0] + rank[k] : -1 - rank[k];
             dst.z[dest] = z[k];
             dst.vz[dest] = src.vz[t0 + k];
-            dst.cold[dest] = src.cold[t0 + k];
+            *(GLB u32x4 *)&dst.cold[dest] = *(const GLB u32x4 *)&src.cold[t0 + k];
             dst.tc[dest] = src.tc[t0 + k];
         }
         lds_barrier();
@@ -1207,15 +1290,15 @@ __device__ __forceinline__ void deposit_global(const Diode &dd, int s, double z)
     double f;
     cic(z, dd.invdz, dd.N, j, f);
     unsigned long long a = fixed_right(f);
-    atomicAdd(&dd.H[s][j], (1ull << 32) - a);
-    atomicAdd(&dd.H[s][j + 1], a);
+    gadd(&glb(dd.H[s])[j], (1ull << 32) - a);
+    gadd(&glb(dd.H[s])[j + 1], a);
 }
 
-__device__ void write_particle(const SpeciesBuf &b, int i, double z, float vx, float vy, float vz, uint32_t id,
+__device__ void write_particle(const GBuf &b, int i, double z, float vx, float vy, float vz, uint32_t id,
                                uint32_t tc)
 {
     b.z[i] = z; b.vz[i] = vz; b.tc[i] = tc;
-    b.cold[i] = ColdRec{vx, vy, id, 0u};
+    put_cold(&b.cold[i], vx, vy, id);
 }
 
 // Births of one step, one thread per newborn: ionisation products in
@@ -1250,7 +1333,7 @@ __device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, unsigne
     __syncthreads();
     const int q = s_q, R = s_R, ne = s_ne;
     const uint32_t id0 = s_id0;
-    const SpeciesBuf bP = dd.buf[parity][SP_P], bE = dd.buf[parity][SP_E], bI = dd.buf[parity][SP_I];
+    const GBuf bP = gbuf(dd.buf[parity][SP_P]), bE = gbuf(dd.buf[parity][SP_E]), bI = gbuf(dd.buf[parity][SP_I]);
 
     if (q > 0) {
         int np2 = 1;
