@@ -220,10 +220,10 @@ int pic_set_counters(pic_handle *h, int diode, int64_t step, uint32_t next_id);
 int pic_refield(pic_handle *h);
 
 /* Per-kernel timing: run nsteps steps on the current schedule with HIP events
- * around sampled launches of the particle kernel on the bound stream (with
- * graph replay: the first particle kernel of every replayed re-sort period)
- * and return their mean duration (ms), the mean live-particle count and the
- * total time (ms).  Synchronises. */
+ * around launches of the particle kernel on the bound stream (with graph
+ * replay: every particle kernel of the first 4096 replayed steps; on the plain
+ * stream: one launch in max(1, nsteps / 512)) and return their mean duration
+ * (ms), the mean live-particle count and the total time (ms).  Synchronises. */
 int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *mean_live,
                    double *total_ms);
 
@@ -237,7 +237,7 @@ int pic_get_tuning(pic_handle *h, int *ppt, int *grid, int *sort_period, int *us
 
 /* Choose the launch schedule by timing candidates on the handle's own
  * diodes: every combination of particles per thread {1, 2, 4}, re-sort period
- * {16, 32, 64, 128} and grid {2048, 4096, 8192}, then graph replay on or off
+ * {16, 32, 64, 128} and grid {2048, 4096, 8192, 16384}, then graph replay on or off
  * for the best one.  Each candidate runs whole re-sort periods of at least
  * trial_steps real steps, so the diodes advance.  Leaves the best schedule set
  * and returns it with its time per step.  Synchronises. */

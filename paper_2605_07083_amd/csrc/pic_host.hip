@@ -254,11 +254,10 @@ struct pic_handle {
     bool use_graph = true;
     hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
     hipGraphExec_t graph[2] = {nullptr, nullptr};   // re-sort + sort_period steps, per start parity
-    // the same graphs with event-record nodes around the first particle kernel
+    // the same graphs with event-record nodes around every particle kernel
     hipGraphExec_t tgraph[2] = {nullptr, nullptr};
     hipGraph_t tsrc[2] = {nullptr, nullptr};  // kept alive: its node handles address the exec's nodes
     std::vector<hipGraphNode_t> tnode[2];   // (start, end) per step of the period
-    int tpos[2] = {-1, -1};                 // step whose pair holds pool events
     hipEvent_t tev[2] = {nullptr, nullptr}; // placeholders recorded by the other steps
     ~pic_handle()
     {
@@ -282,7 +281,7 @@ int grid_for(const pic_handle *h)
     int64_t chunks = 0;
     for (int d = 0; d < h->nd; ++d)
         for (int s = 0; s < NSP; ++s) chunks += (h->der[d].capacity[s] + 256 * h->ppt - 1) / (256 * h->ppt);
-    int64_t g = std::min<int64_t>(chunks, 8192);
+    int64_t g = std::min<int64_t>(chunks, 16384);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     return (int)g;
 }
@@ -411,7 +410,6 @@ int ensure_timed_graph(pic_handle *h, int p)
     }
     h->tsrc[p] = g;
     h->tnode[p] = marks;
-    h->tpos[p] = -1;
     return PIC_OK;
 }
 
@@ -884,8 +882,10 @@ int pic_refield(pic_handle *h)
 int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *mean_live, double *total_ms)
 {
     if (!h || nsteps < 1) return fail(PIC_EINVAL, "bad arguments");
+    // events for every particle kernel of graph replays, one launch in `every`
+    // on the plain stream
     const int64_t every = std::max<int64_t>(1, nsteps / 512);
-    const int64_t nev = nsteps / std::max<int64_t>(1, std::min<int64_t>(every, h->sort_period)) + 2;
+    const int64_t nev = (h->use_graph ? std::min<int64_t>(nsteps, 4096) : nsteps / every) + 2;
     std::vector<hipEvent_t> ev(2 * nev);
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     hipEvent_t t0, t1;
@@ -912,19 +912,20 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
     while (left > 0) {
         if (h->use_graph && h->sort_period > 1 && !h->sort_next && h->issued % h->sort_period == 0 &&
             left >= h->sort_period && k_ev < nev) {
-            // one re-sort period replayed from its graph, first particle kernel timed
+            // one re-sort period replayed from its graph, every particle kernel
+            // timed (the kernel slows down over a period as particles drift
+            // from their sorted places, so no single position is typical)
             const int p = h->parity;
             if ((rc = ensure_timed_graph(h, p))) return rc;
-            const int pos = (int)(k_ev % h->sort_period);
-            if (h->tpos[p] >= 0) {
-                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * h->tpos[p]], h->tev[0]));
-                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * h->tpos[p] + 1], h->tev[1]));
+            for (int pos = 0; pos < h->sort_period; ++pos) {
+                const bool real = k_ev < nev;
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos],
+                                                            real ? ev[2 * k_ev] : h->tev[0]));
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos + 1],
+                                                            real ? ev[2 * k_ev + 1] : h->tev[1]));
+                if (real) ++k_ev;
             }
-            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos], ev[2 * k_ev]));
-            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos + 1], ev[2 * k_ev + 1]));
-            h->tpos[p] = pos;
             HIP_TRY(hipGraphLaunch(h->tgraph[p], h->stream));
-            ++k_ev;
             h->parity ^= 1;
             h->issued += h->sort_period;
             left -= h->sort_period;
@@ -1044,7 +1045,7 @@ int pic_autotune(pic_handle *h, int64_t trial_steps, int *ppt, int *grid, int *s
     // coordinate-wise search stalled in local optima), then graph replay
     for (int p : {1, 2, 4})
         for (int k : {16, 32, 64, 128})
-            for (int g : {2048, 4096, 8192}) {
+            for (int g : {2048, 4096, 8192, 16384}) {
                 if ((rc = timed(p, g, k, bu, ms))) return rc;
                 if (ms < best) { best = ms; bp = p; bk = k; bg = h->grid; }
             }

@@ -21,7 +21,7 @@ constexpr int NT = 256;            // threads per particle block
 constexpr int NW = NT / 64;        // wavefronts per particle block
 constexpr int WMAX = 512;          // LDS window (nodes) of the field tile / histogram
 constexpr int QW_SLACK = 384;      // per-wave LDS queue of rare items: 64 PPT + QW_SLACK entries
-constexpr int DRIFT = 96;          // cells of drift since the last re-sort kept in the LDS window
+constexpr int DRIFT = 160;         // cells of drift since the last re-sort kept in the LDS window
 constexpr int BIN_SHIFT = 5;       // the re-sort orders particles by bins of 32 cells
 constexpr int DRIFT_B = (DRIFT >> BIN_SHIFT) + 1;   // the drift margin in bins
 
@@ -488,12 +488,12 @@ __device__ __forceinline__ void rare_absorbed(const Diode &dd, int s, const GBuf
 // The step's rare items of one diode (all species): collisions of candidates,
 // tallies of absorbed particles, into the block's LDS tally.  Items
 // [first, n) with stride `stride` of each list.
-__device__ __forceinline__ void process_rare(const Diode &dd, const DiodeState *st, int parity, uint32_t step,
+__device__ __forceinline__ void process_rare(const Diode &dd, const int *rare_n, int parity, uint32_t step,
                                              int first, int stride, RareTally *rt)
 {
 #pragma unroll 1
     for (int s = 0; s < NSP; ++s) {
-        const int n = st->rare_n[s];
+        const int n = rare_n[s];
         const GBuf b = gbuf(dd.buf[parity][s]);
         for (int k = first; k < n; k += stride) {
             const uint32_t item = dd.rare[s][k];
@@ -560,21 +560,35 @@ __device__ __forceinline__ void fold_tally_copies(const Diode &dd, RareTally *rt
     }
 }
 
-// Add a block tally to the diode's cumulative tallies and ion-loss count.
-__device__ __forceinline__ void apply_tally(const Diode &dd, DiodeState *st, const RareTally &t)
+// Add a step's tally to the diode's cumulative tallies (one thread; atomics
+// without return, so nothing waits for the old values).
+__device__ __forceinline__ void apply_tally(const Diode &dd, const RareTally &t)
 {
+    DiodeTally *T = dd.tally;
     for (int ion = 0; ion < 2; ++ion)
-        if (t.cand[ion]) dd.tally->cand[ion] += t.cand[ion];
+        if (t.cand[ion]) atomicAdd(&T->cand[ion], (unsigned long long)t.cand[ion]);
 #pragma unroll
     for (int k = 0; k < NCH; ++k)
-        if (t.coll[k]) dd.tally->coll[k] += t.coll[k];
+        if (t.coll[k]) atomicAdd(&T->coll[k], (unsigned long long)t.coll[k]);
 #pragma unroll
     for (int sp = 0; sp < NSP; ++sp)
-        for (int w = 0; w < 2; ++w) {
-            dd.tally->abs_count[sp][w] += t.abs_count[sp][w];
-            dd.tally->abs_energy[sp][w] += t.abs_energy[sp][w];
-        }
-    if (t.ion_lost) atomicAdd(&st->ion_lost, t.ion_lost);
+        for (int w = 0; w < 2; ++w)
+            if (t.abs_count[sp][w]) {
+                atomicAdd(&T->abs_count[sp][w], (unsigned long long)t.abs_count[sp][w]);
+                atomicAdd(&T->abs_energy[sp][w], t.abs_energy[sp][w]);
+            }
+}
+
+// The diode's counters, one lane of the calling wave per 32-bit field, read
+// at agent scope (other kernels' atomics land in L2).
+__device__ __forceinline__ void load_state(const DiodeState *st, DiodeState *out)
+{
+    constexpr int W = (int)(sizeof(DiodeState) / 4);
+    static_assert(W <= 64, "one lane per field");
+    const int lane = threadIdx.x & 63;
+    if (lane < W)
+        reinterpret_cast<uint32_t *>(out)[lane] = __hip_atomic_load(
+            glb(reinterpret_cast<const uint32_t *>(st)) + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
@@ -1306,24 +1320,25 @@ __device__ void write_particle(const GBuf &b, int i, double z, float vx, float v
 // Tc placed at z = v_z dt), pair replenishment (one e-ion pair per ion lost,
 // shared uniform position, Maxwellian at the initial temperatures).
 // Newborns deposit directly into the global histograms.
-__device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, unsigned long long *keys, uint32_t step,
-                                        int parity)
+// S: the diode's counters as read at the start of the step's sources (LDS);
+// lost: ions absorbed this step.
+__device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, const DiodeState &S, int lost,
+                                        unsigned long long *keys, uint32_t step, int parity)
 {
     const int tid = threadIdx.x;
     __shared__ int s_ne, s_q, s_R, s_bP, s_bE, s_bI, s_okP, s_okE, s_okI;
     __shared__ uint32_t s_id0;
     if (tid == 0) {
-        // counters bumped with atomics at L2 in this kernel too: read them there
-        const int q = min(__hip_atomic_load(&st->iz_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), IZQ_CAP);
-        const int R = dd.replenish ? __hip_atomic_load(&st->ion_lost, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        const int q = min(S.iz_count, IZQ_CAP);
+        const int R = dd.replenish ? S.ion_lost + lost : 0;
         int ne = 0;
         if (dd.emit_x > 0.0) {
             const double fl = floor(dd.emit_x);
             uint4 be = philox(step, EV_EMIT, 0u, 0u, 0xFFFFFFFFu, dd.kseed);
             ne = (int)fl + (u53(be.x, be.y) < dd.emit_x - fl ? 1 : 0);
         }
-        s_q = q; s_R = R; s_ne = ne; s_id0 = st->next_id;
-        s_bP = st->n[SP_P]; s_bE = st->n[SP_E]; s_bI = st->n[SP_I];
+        s_q = q; s_R = R; s_ne = ne; s_id0 = S.next_id;
+        s_bP = S.n[SP_P]; s_bE = S.n[SP_E]; s_bI = S.n[SP_I];
         // births that do not fit are dropped and flagged
         s_okP = min(q + R, dd.cap[SP_P] - s_bP);
         s_okE = min(ne, dd.cap[SP_E] - s_bE);
@@ -1425,9 +1440,9 @@ __device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, unsigne
         st->n[SP_E] = s_bE + s_okE;
         st->n[SP_I] = s_bI + s_okI;
         st->next_id = id0 + 2u * q + ne + 2u * R;
-        dd.tally->n_emit += ne;
-        dd.tally->n_repl += R;
-        dd.tally->n_iz += q;
+        if (ne) atomicAdd(&dd.tally->n_emit, (unsigned long long)ne);
+        if (R) atomicAdd(&dd.tally->n_repl, (unsigned long long)R);
+        if (q) atomicAdd(&dd.tally->n_iz, (unsigned long long)q);
         st->iz_count = 0;
         st->ion_lost = 0;
 #pragma unroll
@@ -1438,19 +1453,29 @@ __device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, unsigne
 // The sources part of a step for one diode, by one block of FT threads: the
 // rare items the particle kernel could not hold in LDS (normally none), then
 // the births.  keys: IZQ_CAP u64 of LDS scratch.
+// The step's sources for one diode (one block): the particle kernel's tally
+// copies and counters are read together, up front, so the chain of global
+// round trips is one load deep in the usual case.
 __device__ __forceinline__ void step_sources(const Diode &dd, DiodeState *st, unsigned long long *keys,
                                              uint32_t step, int parity, RareTally *rt)
 {
+    __shared__ DiodeState s_st;
     const int tid = threadIdx.x;
     if (tid == 0) rare_tally_zero(rt);
+    if (tid >= 64 && tid < 128) load_state(st, &s_st);
     __syncthreads();
-    process_rare(dd, st, parity, step, tid, FT, rt);
+    fold_tally_copies(dd, rt);       // first wave
+    if (s_st.rare_n[SP_P] | s_st.rare_n[SP_E] | s_st.rare_n[SP_I]) {
+        // items the particle kernel's queues could not hold: they may queue
+        // ionisations, so the counters are read again afterwards
+        __syncthreads();
+        process_rare(dd, s_st.rare_n, parity, step, tid, FT, rt);
+        __syncthreads();
+        if (tid >= 64 && tid < 128) load_state(st, &s_st);
+    }
     __syncthreads();
-    fold_tally_copies(dd, rt);
-    __syncthreads();
-    if (tid == 0) apply_tally(dd, st, *rt);
-    __syncthreads();
-    sources(dd, st, keys, step, parity);
+    if (tid == 0) apply_tally(dd, *rt);
+    sources(dd, st, s_st, rt->ion_lost, keys, step, parity);
 }
 
 __device__ __forceinline__ long long wave_incl_scan_i64(long long x)
