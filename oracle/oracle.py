@@ -11,6 +11,9 @@ import numpy as np
 from . import build_oracle
 
 NSP = 3
+# warm-start state rows and quantile levels (pic_oracle.h, o_load_state)
+STATE_ROWS = 39
+STATE_LEVELS = (0.0, 0.02, 0.1, 0.25, 0.5, 0.75, 0.9, 0.98, 1.0)
 _lib = None
 
 
@@ -61,6 +64,8 @@ def lib():
             getattr(L, f).restype = C.c_int
         L.o_load_profiles.argtypes = [P, P, P]
         L.o_load_profiles.restype = C.c_int
+        L.o_load_state.argtypes = [P, P]
+        L.o_load_state.restype = C.c_int
         L.o_count.argtypes = [P, C.c_int]
         L.o_count.restype = i64
         L.o_stepno.argtypes = [P]
@@ -196,6 +201,18 @@ class Sim:
             raise ValueError("oracle: negative or non-finite density")
         if rc != 0:
             raise RuntimeError("oracle profile load failed")
+
+    def load_state(self, prof):
+        """Warm start from a late-time state prof [39][N]: n_e, n_i (m^-3),
+        phi (V), then per species (electrons, ions) nine quantiles of v_z and
+        nine of |v_perp| (m/s) at the levels STATE_LEVELS."""
+        prof = np.ascontiguousarray(prof, dtype=np.float64)
+        assert prof.shape == (STATE_ROWS, self.N)
+        rc = lib().o_load_state(self.h, _ptr(prof))
+        if rc == -2:
+            raise ValueError("oracle: negative density or non-finite state entry")
+        if rc != 0:
+            raise RuntimeError("oracle state load failed")
 
     def step(self, n=1):
         for _ in range(n):

@@ -493,6 +493,99 @@ int o_load_profiles(osim *o, const double *ne, const double *ni)
     return o_refield(o);
 }
 
+/* Warm start with velocity distributions (a reading: the paper starts every
+ * run from a uniform Maxwellian plasma).  A late-time run's particles in one
+ * cell are summarised per species by quantiles of v_z and of the transverse
+ * speed |v_perp| at nine levels; a loaded particle draws each from the
+ * piecewise-linear inverse of its cell's quantile function and a uniform
+ * azimuth for (v_x, v_y).  The quantiles are first sorted (monotone
+ * rearrangement).  A kinetic energy above what the null-collision bound
+ * allows after the particle's later fall through the potential (ions toward
+ * the cathode, electrons toward the anode) is scaled down to that limit. */
+static const double OQ_LEVELS[OQ] = {0.0, 0.02, 0.1, 0.25, 0.5, 0.75, 0.9, 0.98, 1.0};
+
+static void sort9(double q[OQ])
+{
+    for (int a = 1; a < OQ; ++a)
+        for (int b = a; b > 0 && q[b - 1] > q[b]; --b) {
+            double t = q[b];
+            q[b] = q[b - 1];
+            q[b - 1] = t;
+        }
+}
+
+static double inv_quantile(const double q[OQ], double u)
+{
+    int k = 0;
+    while (k < OQ - 2 && u >= OQ_LEVELS[k + 1]) ++k;
+    double t = (u - OQ_LEVELS[k]) / (OQ_LEVELS[k + 1] - OQ_LEVELS[k]);
+    return q[k] + t * (q[k + 1] - q[k]);
+}
+
+int o_load_state(osim *o, const double *prof)
+{
+    const ocfg *c = &o->c;
+    const int64_t N = c->N;
+    for (int64_t r = 0; r < OSTATE_ROWS * N; ++r)
+        if (!isfinite(prof[r])) return -2;
+    for (int s = 0; s < ONSP; ++s) o->sp[s].n = 0;
+    memset(&o->t, 0, sizeof(o->t));
+    o->step = 0;
+    uint32_t id = 0;
+    const int load_sp[2] = {OSP_P, OSP_I};
+    for (int q = 0; q < 2; ++q) {
+        const int s = load_sp[q];
+        const double *dens = prof + (int64_t)q * N;
+        const double lam = o->d.lam[q];
+        const double m = o->d.mass[s];
+        /* energy allowed at load (eV) before the fall through the potential */
+        const double cap = q ? fabs(c->V) + 20.0 * c->Ti0 : fabs(c->V) + 20.0 * c->Te0 + 20.0 * c->Tc;
+        for (int32_t j = 0; j < c->N; ++j) {
+            const double x = dens[j] * o->d.dz / o->d.w0;
+            if (!(x >= 0.0) || x > 1073741824.0) return -2;
+            double qz[OQ], qp[OQ];
+            for (int k = 0; k < OQ; ++k) {
+                qz[k] = prof[(int64_t)(3 + 18 * q + k) * N + j];
+                qp[k] = prof[(int64_t)(12 + 18 * q + k) * N + j];
+            }
+            sort9(qz);
+            sort9(qp);
+            const double phi = prof[2 * N + j];
+            double fall = q ? phi : c->V - phi;
+            fall = fmin(fmax(fall, 0.0), fabs(c->V));
+            const double emax = Q_E * (cap - fall);     /* J */
+            const double fl = floor(x);
+            uint32_t bc[4];
+            draw((uint32_t)j, kseed(o), LOAD_STEP, EV_PROFILE, (uint32_t)q, bc);
+            const int64_t cnt = (int64_t)fl + (o_u53(bc[0], bc[1]) < x - fl ? 1 : 0);
+            if (sp_reserve(&o->sp[s], o->sp[s].n + cnt)) return -1;
+            for (int64_t p = 0; p < cnt; ++p, ++id) {
+                uint32_t b0[4], b1[4], b2[4];
+                draw(id, kseed(o), LOAD_STEP, EV_LOAD, 0, b0);
+                draw(id, kseed(o), LOAD_STEP, EV_LOAD, 1, b1);
+                draw(id, kseed(o), LOAD_STEP, EV_LOAD, 2, b2);
+                double vz = inv_quantile(qz, o_u53(b0[0], b0[1]));
+                double vp = fmax(0.0, inv_quantile(qp, o_u53(b0[2], b0[3])));
+                const double az = 2.0 * PI_D * o_u53(b2[0], b2[1]);
+                double vx = vp * cos(az), vy = vp * sin(az);
+                const double e = 0.5 * m * (vx * vx + vy * vy + vz * vz);
+                if (e > emax) {
+                    const double f = emax > 0.0 ? sqrt(emax / e) : 0.0;
+                    vx *= f;
+                    vy *= f;
+                    vz *= f;
+                }
+                const double z = ((double)j + o_u53(b1[0], b1[1])) * o->d.dz;
+                uint32_t tc = next_candidate(0u, lam, b1[2], b1[3]);
+                if (tc != NEVER) tc -= 1u;
+                sp_push(&o->sp[s], z, vx, vy, vz, id, tc);
+            }
+        }
+    }
+    o->next_id = id;
+    return o_refield(o);
+}
+
 /* ------------------------------------------------------------------------ */
 /* MCC ("Emission and collisions": Monte Carlo collisions with a uniform    */
 /* helium background; the neutral target velocity is drawn from a           */

@@ -83,6 +83,17 @@ int o_load(osim *o);
 /* Load from cell-centre densities n_e, n_i (N values each, m^-3); -2 on a
  * negative or non-finite density. */
 int o_load_profiles(osim *o, const double *ne, const double *ni);
+
+/* Warm start from a late-time state on the N cells: prof[r][c], rows
+ *   0 n_e, 1 n_i (m^-3), 2 phi (V),
+ *   3..11 electron v_z quantiles, 12..20 electron |v_perp| quantiles (m/s),
+ *   21..29 ion v_z quantiles, 30..38 ion |v_perp| quantiles,
+ * at the levels OQ_LEVELS.  Counts, ids, positions and free flights as in
+ * o_load_profiles; velocities from the quantiles.  -2: negative density or a
+ * non-finite entry. */
+#define OSTATE_ROWS 39
+#define OQ 9
+int o_load_state(osim *o, const double *prof);
 int o_step(osim *o);
 int o_refield(osim *o);
 int64_t o_count(const osim *o, int sp);

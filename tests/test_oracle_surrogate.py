@@ -31,7 +31,7 @@ import torch
 from oracle import surrogate_oracle as S
 from paper_2605_07083_amd import presets
 
-from _helpers import M_E, Q_E
+from _helpers import M_E, M_I, Q_E
 
 
 def _brute_conv(a, w, bias):
@@ -261,3 +261,114 @@ def test_profile_rejects_negative_and_loads_nothing_for_zero(O):
         s.load_profiles(np.full(N, -1.0), np.zeros(N))
     s.load_profiles(np.zeros(N), np.zeros(N))
     assert s.count(0) == 0 and s.count(2) == 0
+
+
+# ---------------------------------------------------------------------------
+# warm start with velocity quantiles (o_load_state)
+# ---------------------------------------------------------------------------
+def _state(O, c, nper, qz_e, qp_e, qz_i, qp_i, phi=None):
+    """State rows for densities of `nper` particles per cell and the given
+    nine-level quantile vectors (the same in every cell)."""
+    d = O.derive(c)
+    N = c["N"]
+    prof = np.zeros((O.STATE_ROWS, N))
+    prof[0] = prof[1] = nper * d["w0"] / d["dz"]
+    prof[2] = 0.5 * c["V"] if phi is None else phi
+    for r0, q in ((3, qz_e), (12, qp_e), (21, qz_i), (30, qp_i)):
+        prof[r0:r0 + 9] = np.asarray(q, float)[:, None]
+    return prof
+
+
+def test_state_uniform_quantiles_give_uniform_speeds(O):
+    """Quantiles of U[a, b] at any levels are a + level (b - a), and the
+    piecewise-linear inverse of that quantile function is exact: v_z must be
+    uniform on [a, b] (mean, variance, KS) and the azimuth uniform."""
+    from scipy import stats
+    c = _cfg()
+    L = np.array(O.STATE_LEVELS)
+    a, b = -5.0e3, 1.2e4          # ions below the load's energy limit (6 eV here)
+    qz = a + L * (b - a)
+    qp = 1.0e3 + L * 2.0e3
+    s = O.Sim(c)
+    s.load_state(_state(O, c, 100, qz * 30, qp * 30, qz, qp))
+    I = s.particles(2)
+    v = I["vz"]
+    assert stats.kstest((v - a) / (b - a), "uniform").pvalue > 1e-3
+    vp = np.hypot(I["vx"], I["vy"])
+    assert stats.kstest((vp - 1.0e3) / 2.0e3, "uniform").pvalue > 1e-3
+    az = np.arctan2(I["vy"], I["vx"])
+    assert stats.kstest((az + np.pi) / (2 * np.pi), "uniform").pvalue > 1e-3
+    E = s.particles(0)["vz"]
+    assert stats.kstest((E / 30 - a) / (b - a), "uniform").pvalue > 1e-3
+
+
+def test_state_degenerate_quantiles_and_rearrangement(O):
+    """Equal quantiles give that value for every particle; reversed quantile
+    vectors load exactly what the sorted ones do."""
+    c = _cfg()
+    L = np.array(O.STATE_LEVELS)
+    s = O.Sim(c)
+    s.load_state(_state(O, c, 20, np.full(9, 1.0e5), np.full(9, 3.0e4), np.full(9, -2.0e3), np.full(9, 500.0)))
+    P, I = s.particles(0), s.particles(2)
+    assert np.all(P["vz"] == 1.0e5) and np.all(I["vz"] == -2.0e3)
+    assert np.allclose(np.hypot(P["vx"], P["vy"]), 3.0e4, rtol=1e-12)
+    assert np.allclose(np.hypot(I["vx"], I["vy"]), 500.0, rtol=1e-12)
+    q = 1.0e4 * (L - 0.3) ** 3
+    s1, s2 = O.Sim(c), O.Sim(c)
+    s1.load_state(_state(O, c, 20, q, np.abs(q), q / 50, np.abs(q) / 50))
+    s2.load_state(_state(O, c, 20, q[::-1], np.abs(q)[::-1], q[::-1] / 50, np.abs(q)[::-1] / 50))
+    for sp in (0, 2):
+        A, B = s1.particles(sp), s2.particles(sp)
+        for k in ("z", "vx", "vy", "vz", "id", "tc"):
+            assert np.array_equal(A[k], B[k]), k
+
+
+def test_state_positions_ids_and_flights_match_profile_load(O):
+    """Counts, ids, positions and free flights use the draws of the profile
+    loader, so they are identical to it for the same densities."""
+    c = _cfg()
+    d = O.derive(c)
+    N = c["N"]
+    x = 0.3 + 2.0 * (np.arange(N) % 7) / 7.0
+    ne = x * d["w0"] / d["dz"]
+    ni = ne[::-1].copy()
+    L = np.array(O.STATE_LEVELS)
+    prof = _state(O, c, 1, 1e5 * (L - 0.5), 1e5 * L, 1e3 * (L - 0.5), 1e3 * L)
+    prof[0], prof[1] = ne, ni
+    a, b = O.Sim(c), O.Sim(c)
+    a.load_profiles(ne, ni)
+    b.load_state(prof)
+    for sp in (0, 2):
+        A, B = a.particles(sp), b.particles(sp)
+        for k in ("z", "id", "tc"):
+            assert np.array_equal(A[k], B[k]), k
+    assert a.next_id == b.next_id
+
+
+def test_state_energy_clamp(O):
+    """Kinetic energy at load is scaled down to e (|V| + 20 T0 - fall) with
+    the fall |phi| for ions and |V - phi| for electrons, so the later fall
+    through the potential keeps every particle under the null-collision cap."""
+    c = _cfg()
+    N = c["N"]
+    phi = np.linspace(0.0, c["V"], N)
+    huge = np.full(9, 5.0e7)
+    s = O.Sim(c)
+    s.load_state(_state(O, c, 20, huge, huge, huge / 1e3, huge / 1e3, phi=phi))
+    d = O.derive(c)
+    for sp, m, T0, fall in ((0, M_E, c["Te0"] + c["Tc"], c["V"] - phi), (2, M_I, c["Ti0"], phi)):
+        P = s.particles(sp)
+        cell = np.floor(P["z"] / d["dz"]).astype(int)
+        ke = 0.5 * m * (P["vx"] ** 2 + P["vy"] ** 2 + P["vz"] ** 2) / Q_E
+        cap = abs(c["V"]) + 20.0 * T0 - np.clip(fall[cell], 0.0, abs(c["V"]))
+        assert np.all(ke <= cap * (1 + 1e-12))
+        assert np.all(ke >= cap * (1 - 1e-9))       # every particle was above it
+
+
+def test_state_rejects_non_finite(O):
+    c = _cfg()
+    L = np.array(O.STATE_LEVELS)
+    prof = _state(O, c, 5, L, L, L, L)
+    prof[25, 3] = np.nan
+    with pytest.raises(ValueError):
+        O.Sim(c).load_state(prof)
