@@ -165,6 +165,32 @@ int pic_init(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t b
 int pic_init_from_profiles(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes,
                            void *hip_stream, const double *dev_dens, pic_handle **out);
 
+/* Warm start from a late-time state: as pic_init_from_profiles, with the
+ * velocities drawn from per-cell summaries of a late-time velocity
+ * distribution instead of the load Maxwellians (a reading: the paper starts
+ * every run from the uniform Maxwellian load).  dev_state is a device array
+ * [n_diodes][PIC_STATE_ROWS][Nmax] of doubles on the N cell centres:
+ *   row 0 n_e, row 1 n_i (m^-3; as the two rows of pic_init_from_profiles),
+ *   row 2 the potential phi (V),
+ *   rows 3..11 electron v_z quantiles, rows 12..20 electron |v_perp|
+ *   quantiles, rows 21..29 ion v_z quantiles, rows 30..38 ion |v_perp|
+ *   quantiles (m/s), at the levels 0, 0.02, 0.1, 0.25, 0.5, 0.75, 0.9, 0.98, 1.
+ * Counts, ids, positions and free flights are those of
+ * pic_init_from_profiles for the same densities.  Each nine-vector is sorted
+ * first; v_z and |v_perp| are drawn from the piecewise-linear inverse of the
+ * cell's quantile function with two uniform draws, the azimuth of (v_x, v_y)
+ * uniformly with a third (Philox keyed by the particle id, event LOAD, counter
+ * word 2 = 0, 0, 2).  A particle whose kinetic energy exceeds
+ * e (|V| + 20 Te0 + 20 Tc - fall) (electrons) or e (|V| + 20 Ti0 - fall)
+ * (ions), fall = the potential it can still fall through (V - phi for
+ * electrons, phi for ions, clamped to [0, |V|]), is scaled down to that
+ * energy, which keeps the later motion inside the null-collision bound.
+ * Reads the array before return.  PIC_ENAN for a negative density or a
+ * non-finite entry, PIC_ENOSPACE as for pic_init_from_profiles. */
+#define PIC_STATE_ROWS 39
+int pic_init_from_state(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes,
+                        void *hip_stream, const double *dev_state, pic_handle **out);
+
 /* Advance every diode nsteps steps.  Asynchronous on the bound stream. */
 int pic_step(pic_handle *h, int64_t nsteps);
 

@@ -30,7 +30,7 @@ extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, i
                                                 int parity, hipStream_t s);
 extern "C" hipError_t picx_prepare(void);
 extern "C" int picx_sources_field_kernels(int max_nodes, int mode);
-extern "C" hipError_t picx_launch_profile_load(const Diode *D, const double *dens, int nd, int max_cells,
+extern "C" hipError_t picx_launch_profile_load(const Diode *D, const double *dens, int rows, int nd, int max_cells,
                                                hipStream_t s);
 extern "C" hipError_t picx_launch_sort(const Diode *D, DiodeState *S, int nd, int ppt, int grid, int parity,
                                        hipStream_t s);
@@ -225,6 +225,10 @@ void fill_params(const pic_config &c, const pic_derived &der, Diode &D)
     D.sig_c = std::sqrt(Q_E * c.Tc / MASS_E);
     D.sig_e0 = std::sqrt(Q_E * c.Te0 / MASS_E);
     D.sig_i0 = std::sqrt(Q_E * c.Ti0 / mi);
+    // a state-loaded particle may still fall through up to |V|: half of the
+    // null-collision bound's thermal allowance is left for its own energy
+    D.load_cap_ev[0] = std::fabs(c.V) + 20.0 * c.Te0 + 20.0 * c.Tc;
+    D.load_cap_ev[1] = std::fabs(c.V) + 20.0 * c.Ti0;
     D.kseed = c.seed ^ c.diode;
     D.channels = c.channels;
     D.replenish = c.replenish;
@@ -543,8 +547,10 @@ int pic_workspace_size(const pic_config *cfgs, int n_diodes, size_t *bytes)
 
 // dens == nullptr: uniform load; else the warm-start loader over dens
 // [n_diodes][2][max N] (device).
+// dens: null for the uniform load, else [n_diodes][rows][max N] with rows 2
+// (densities) or PIC_STATE_ROWS (densities, potential, velocity quantiles)
 static int init_impl(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes, void *hip_stream,
-                     const double *dens, pic_handle **out)
+                     const double *dens, int rows, pic_handle **out)
 {
     if (!cfgs || !out || !dev_workspace || n_diodes < 1 || n_diodes > PIC_MAX_DIODES)
         return fail(PIC_EINVAL, "bad arguments");
@@ -599,7 +605,7 @@ static int init_impl(const pic_config *cfgs, int n_diodes, void *dev_workspace, 
     } else {
         int max_cells = 0;
         for (int d = 0; d < n_diodes; ++d) max_cells = std::max(max_cells, cfgs[d].N);
-        if (picx_launch_profile_load(h->dD, dens, n_diodes, max_cells, h->stream) != hipSuccess)
+        if (picx_launch_profile_load(h->dD, dens, rows, n_diodes, max_cells, h->stream) != hipSuccess)
             return cleanup(fail(PIC_EHIP, "profile load launch failed"));
     }
     // the staging vectors die here: wait for the copies
@@ -615,7 +621,8 @@ static int init_impl(const pic_config *cfgs, int n_diodes, void *dev_workspace, 
             h->live_offset[d][SP_I] = (int64_t)sd.n[SP_I] - cfgs[d].n_load;
             if (err & ERR_NAN)
                 return cleanup(fail(PIC_ENAN, "diode " + std::to_string(d) +
-                                                  ": density profile negative, not finite or above 2^30 per cell"));
+                                                  ": density profile negative, not finite or above 2^30 per cell, "
+                                                  "or a state entry not finite"));
             if (err & ERR_CAPACITY)
                 return cleanup(fail(PIC_ENOSPACE, "diode " + std::to_string(d) +
                                                       ": profile holds more particles than the capacity "
@@ -631,14 +638,23 @@ static int init_impl(const pic_config *cfgs, int n_diodes, void *dev_workspace, 
 int pic_init(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes, void *hip_stream,
              pic_handle **out)
 {
-    return init_impl(cfgs, n_diodes, dev_workspace, bytes, hip_stream, nullptr, out);
+    return init_impl(cfgs, n_diodes, dev_workspace, bytes, hip_stream, nullptr, 0, out);
 }
 
 int pic_init_from_profiles(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes,
                            void *hip_stream, const double *dev_dens, pic_handle **out)
 {
     if (!dev_dens) return fail(PIC_EINVAL, "null density profiles");
-    return init_impl(cfgs, n_diodes, dev_workspace, bytes, hip_stream, dev_dens, out);
+    return init_impl(cfgs, n_diodes, dev_workspace, bytes, hip_stream, dev_dens, 2, out);
+}
+
+static_assert(PIC_STATE_ROWS == STATE_ROWS, "state layout of the ABI and the kernels");
+
+int pic_init_from_state(const pic_config *cfgs, int n_diodes, void *dev_workspace, size_t bytes, void *hip_stream,
+                        const double *dev_state, pic_handle **out)
+{
+    if (!dev_state) return fail(PIC_EINVAL, "null state");
+    return init_impl(cfgs, n_diodes, dev_workspace, bytes, hip_stream, dev_state, PIC_STATE_ROWS, out);
 }
 
 int pic_step(pic_handle *h, int64_t nsteps)

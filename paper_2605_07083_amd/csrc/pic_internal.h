@@ -37,6 +37,9 @@ constexpr uint32_t ERR_IZQ = 8u;
 
 // physical constants (CODATA 2018)
 constexpr double Q_E = 1.602176634e-19;
+// rows of a warm-start state per diode: n_e, n_i, phi, then per species
+// (electrons, ions) nine quantiles of v_z and nine of |v_perp|
+constexpr int STATE_ROWS = 39;
 constexpr double K_B = 1.380649e-23;
 constexpr double EPS0 = 8.8541878128e-12;
 constexpr double MASS_E = 9.1093837015e-31;
@@ -148,6 +151,7 @@ struct Diode {
     float ng, sig_el, sig_x0, lotz_a2, sig_cx, sig_iel;
     double emit_x;         // Gamma dt / w0
     double sig_c, sig_e0, sig_i0;
+    double load_cap_ev[2]; // state load: kinetic energy limit before the fall (eV), electrons / ions
     uint32_t kseed, channels;
     int32_t replenish, tally_period;
     SpeciesBuf buf[2][NSP];

@@ -900,7 +900,7 @@ __global__ __launch_bounds__(256) void k_load(const Diode *__restrict__ D, const
 // counts and the next id; errors are sticky bits that skip the fill.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_profile_count(const Diode *__restrict__ D, const double *__restrict__ dens,
-                                                        int max_cells)
+                                                        int rows, int max_cells)
 {
     const Diode &dd = D[blockIdx.x];
     const int N = dd.N, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -911,7 +911,7 @@ __global__ __launch_bounds__(1024) void k_profile_count(const Diode *__restrict_
     long long tot[2];
     for (int q = 0; q < 2; ++q) {
         const int s = q == 0 ? SP_P : SP_I;
-        const double *n = dens + ((size_t)blockIdx.x * 2 + q) * max_cells;
+        const double *n = dens + ((size_t)blockIdx.x * rows + q) * max_cells;
         int *off = dd.cell_cnt[s];
         if (tid == 0) base_s = 0;
         __syncthreads();
@@ -966,13 +966,49 @@ __global__ __launch_bounds__(1024) void k_profile_count(const Diode *__restrict_
     }
 }
 
-// One wave per (cell, species): the cell's particles, drawn exactly as in the
-// uniform load (keyed by id) except for the position, uniform in the cell.
-__global__ __launch_bounds__(256) void k_profile_fill(const Diode *__restrict__ D)
+// Quantile levels of the state load's velocity summaries.
+__constant__ double QLEV[9] = {0.0, 0.02, 0.1, 0.25, 0.5, 0.75, 0.9, 0.98, 1.0};
+
+// Sampling from nine quantiles: sorted first (so an unordered prediction is
+// read as its monotone rearrangement), then inverted piecewise-linearly.
+__device__ __forceinline__ void sort_q9(double q[9])
+{
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+#pragma unroll
+        for (int j = 8; j >= i; --j) {
+            const double lo = fmin(q[j - 1], q[j]), hi = fmax(q[j - 1], q[j]);
+            q[j - 1] = lo;
+            q[j] = hi;
+        }
+}
+__device__ __forceinline__ double from_q9(const double q[9], double u)
+{
+    int k = 0;
+#pragma unroll
+    for (int m = 1; m < 8; ++m) k += (u >= QLEV[m]) ? 1 : 0;
+    const double t = (u - QLEV[k]) / (QLEV[k + 1] - QLEV[k]);
+    double lo = q[0], hi = q[1];
+#pragma unroll
+    for (int m = 1; m < 8; ++m)
+        if (k == m) { lo = q[m]; hi = q[m + 1]; }
+    return lo + t * (hi - lo);
+}
+
+// One wave per (cell, species): the cell's particles, keyed by id as in the
+// uniform load, positions uniform in the cell.  state == null: velocities
+// Maxwellian at the load temperature, drawn as in the uniform load.  Else
+// state [diode][STATE_ROWS][max_cells]: v_z and |v_perp| from the cell's
+// quantiles (rows 3 + 18 q and 12 + 18 q, q = 0 electrons, 1 ions), a uniform
+// azimuth, and the kinetic energy limited to load_cap_ev minus the potential
+// the particle can still fall through (row 2).
+__global__ __launch_bounds__(256) void k_profile_fill(const Diode *__restrict__ D, const double *__restrict__ state,
+                                                      int max_cells)
 {
     const Diode &dd = D[blockIdx.y];
     const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int s = blockIdx.z == 0 ? SP_P : SP_I;
+    const int q = blockIdx.z;
+    const int s = q == 0 ? SP_P : SP_I;
     if (c >= dd.N || dd.st->err) return;
     const int *off = dd.cell_cnt[s];
     const int a = off[c], e = off[c + 1];
@@ -980,16 +1016,58 @@ __global__ __launch_bounds__(256) void k_profile_fill(const Diode *__restrict__ 
     const double sig = s == SP_P ? dd.sig_e0 : dd.sig_i0;
     const double lam = dd.lam[s == SP_I];
     const GBuf b = gbuf(dd.buf[0][s]);
+    double qz[9], qp[9], emax = 0.0;
+    if (state) {
+        const double *row = state + (size_t)blockIdx.y * STATE_ROWS * max_cells + c;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            qz[k] = row[(size_t)(3 + 18 * q + k) * max_cells];
+            qp[k] = row[(size_t)(12 + 18 * q + k) * max_cells];
+        }
+        const double phi = row[(size_t)2 * max_cells];
+        bool fin = isfinite(phi);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) fin = fin && isfinite(qz[k]) && isfinite(qp[k]);
+        if (!fin) {
+            if (lane == 0) atomicOr(&dd.st->err, ERR_NAN);
+            return;
+        }
+        sort_q9(qz);
+        sort_q9(qp);
+        const double fall = fmin(fmax(q ? phi : dd.V - phi, 0.0), fabs(dd.V));
+        emax = Q_E * (dd.load_cap_ev[q] - fall);
+    }
     for (int i = a + lane; i < e; i += 64) {
         const uint32_t id = id0 + (uint32_t)i;
         const uint4 b0 = philox(LOAD_STEP, EV_LOAD, 0u, 0u, id, dd.kseed);
         const uint4 b1 = philox(LOAD_STEP, EV_LOAD, 1u, 0u, id, dd.kseed);
-        double n1, n2, n3, n4;
-        bm32(b0.x, b0.y, n1, n2);
-        bm32(b0.z, b0.w, n3, n4);
+        double vx, vy, vz;
+        if (state) {
+            const uint4 b2 = philox(LOAD_STEP, EV_LOAD, 2u, 0u, id, dd.kseed);
+            vz = from_q9(qz, u53(b0.x, b0.y));
+            const double vp = fmax(0.0, from_q9(qp, u53(b0.z, b0.w)));
+            double sa, ca;
+            sincospi(2.0 * u53(b2.x, b2.y), &sa, &ca);
+            vx = vp * ca;
+            vy = vp * sa;
+            const double ke = 0.5 * dd.mass[s] * (vx * vx + vy * vy + vz * vz);
+            if (ke > emax) {
+                const double f = emax > 0.0 ? sqrt(emax / ke) : 0.0;
+                vx *= f;
+                vy *= f;
+                vz *= f;
+            }
+        } else {
+            double n1, n2, n3, n4;
+            bm32(b0.x, b0.y, n1, n2);
+            bm32(b0.z, b0.w, n3, n4);
+            vx = sig * n1;
+            vy = sig * n2;
+            vz = sig * n3;
+        }
         b.z[i] = ((double)c + u53(b1.x, b1.y)) * dd.dz;
-        put_cold(&b.cold[i], (float)(sig * n1), (float)(sig * n2), id);
-        b.vz[i] = (float)(sig * n3);
+        put_cold(&b.cold[i], (float)vx, (float)vy, id);
+        b.vz[i] = (float)vz;
         uint32_t tc = next_candidate(0u, lam, b1.z, b1.w);
         if (tc != NEVER) tc -= 1u;
         b.tc[i] = tc;
@@ -1802,11 +1880,12 @@ extern "C" hipError_t picx_launch_load(const Diode *D, const long long *n_load, 
 }
 
 // max_cells: the largest N over the diodes (row length of dens)
-extern "C" hipError_t picx_launch_profile_load(const Diode *D, const double *dens, int nd, int max_cells,
+extern "C" hipError_t picx_launch_profile_load(const Diode *D, const double *dens, int rows, int nd, int max_cells,
                                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_profile_count, dim3(nd), dim3(1024), 0, s, D, dens, max_cells);
-    hipLaunchKernelGGL(k_profile_fill, dim3((max_cells + 3) / 4, nd, 2), dim3(256), 0, s, D);
+    hipLaunchKernelGGL(k_profile_count, dim3(nd), dim3(1024), 0, s, D, dens, rows, max_cells);
+    hipLaunchKernelGGL(k_profile_fill, dim3((max_cells + 3) / 4, nd, 2), dim3(256), 0, s, D,
+                       rows == STATE_ROWS ? dens : nullptr, max_cells);
     hipLaunchKernelGGL(k_profile_clear, dim3(nd), dim3(256), 0, s, D);
     return hipGetLastError();
 }

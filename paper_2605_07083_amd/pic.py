@@ -14,6 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_ENOSPACE, PIC_EHIP, PIC_ENULLCOLL, PIC_ENAN, PIC_ERANGE = 0, -1, -2, -3, -4, -5, -6
+# warm-start state: rows per diode and quantile levels (include/pic.h, pic_init_from_state)
+STATE_ROWS = 39
+STATE_LEVELS = (0.0, 0.02, 0.1, 0.25, 0.5, 0.75, 0.9, 0.98, 1.0)
 NSP, NCH = 3, 5
 
 
@@ -62,7 +65,7 @@ class PicDerived(C.Structure):
                 ("emit_per_step", C.c_double), ("capacity", C.c_int64 * 3)]
 
 
-SYMBOLS = ["pic_derive", "pic_workspace_size", "pic_init", "pic_init_from_profiles", "pic_step", "pic_sync", "pic_get_tally",
+SYMBOLS = ["pic_derive", "pic_workspace_size", "pic_init", "pic_init_from_profiles", "pic_init_from_state", "pic_step", "pic_sync", "pic_get_tally",
            "pic_diagnostics", "pic_get_fields", "pic_avg_reset", "pic_avg_control", "pic_get_hist", "pic_get_efield",
            "pic_get_particles", "pic_set_particles", "pic_set_counters", "pic_refield",
            "pic_step_timed", "pic_set_tuning", "pic_get_tuning", "pic_autotune", "pic_steady_state", "pic_steady_from_series", "pic_checkpoint_size", "pic_save", "pic_load", "pic_last_error",
@@ -85,6 +88,7 @@ def lib():
         "pic_workspace_size": ([C.POINTER(PicConfig), i, C.POINTER(C.c_size_t)], i),
         "pic_init": ([C.POINTER(PicConfig), i, P, C.c_size_t, P, C.POINTER(P)], i),
         "pic_init_from_profiles": ([C.POINTER(PicConfig), i, P, C.c_size_t, P, P, C.POINTER(P)], i),
+        "pic_init_from_state": ([C.POINTER(PicConfig), i, P, C.c_size_t, P, P, C.POINTER(P)], i),
         "pic_step": ([P, i64], i),
         "pic_sync": ([P], i),
         "pic_get_tally": ([P, i, C.POINTER(PicTally)], i),
@@ -185,9 +189,11 @@ def steady_from_series(br, n_live, tol_pp=1.0, tol_rel=0.01):
 class Handle:
     """One or more diodes advanced together on one GPU."""
 
-    def __init__(self, cfgs, device="cuda:0", ppt=None, grid=None, densities=None):
+    def __init__(self, cfgs, device="cuda:0", ppt=None, grid=None, densities=None, state=None):
         """densities: optional device tensor [n_diodes][2][max N] float64 of
-        cell-centre electron and ion densities (m^-3) for the warm start."""
+        cell-centre electron and ion densities (m^-3) for the warm start;
+        state: optional device tensor [n_diodes][STATE_ROWS][max N] float64,
+        densities, potential and velocity quantiles (pic_init_from_state)."""
         import torch
         if isinstance(cfgs, dict):
             cfgs = [cfgs]
@@ -202,7 +208,18 @@ class Handle:
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             self.stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
-        if densities is None:
+        if densities is not None and state is not None:
+            raise ValueError("give densities or state, not both")
+        if state is not None:
+            nmax = max(c["N"] for c in cfgs)
+            if (state.device != self.device or state.dtype != torch.float64
+                    or tuple(state.shape) != (self.nd, STATE_ROWS, nmax) or not state.is_contiguous()):
+                raise ValueError("state must be a contiguous float64 [%d, %d, %d] tensor on %s"
+                                 % (self.nd, STATE_ROWS, nmax, self.device))
+            _check(lib().pic_init_from_state(self._arr, self.nd, C.c_void_p(self.ws.data_ptr()), nbytes,
+                                             C.c_void_p(self.stream.cuda_stream),
+                                             C.c_void_p(state.data_ptr()), C.byref(h)))
+        elif densities is None:
             _check(lib().pic_init(self._arr, self.nd, C.c_void_p(self.ws.data_ptr()), nbytes,
                                   C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         else:

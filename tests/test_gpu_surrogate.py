@@ -240,3 +240,80 @@ def test_profile_load_errors(torch):
     h.sync()
     with pytest.raises(ValueError):
         pic.Handle(cfg, densities=torch.zeros((1, 2, N + 1), dtype=torch.float64, device="cuda:0"))
+
+
+# ---------------------------------------------------------------------------
+# warm-start state loader (densities, potential, velocity quantiles)
+# ---------------------------------------------------------------------------
+def _state(cfg, seed, scale=1.0):
+    """Densities as _profiles, a sheath-like potential and per-cell quantile
+    vectors of a skewed, drifting distribution (unsorted in some cells), with
+    a few cells above the energy limit so the clamp is exercised."""
+    from paper_2605_07083_amd import pic
+    rng = np.random.default_rng(seed + 100)
+    N = cfg["N"]
+    ne, ni = _profiles(cfg, seed, scale)
+    u = (np.arange(N) + 0.5) / N
+    L = np.array(pic.STATE_LEVELS)
+    st = np.zeros((pic.STATE_ROWS, N))
+    st[0], st[1] = ne, ni
+    st[2] = cfg["V"] * u ** 0.7
+    for q, (vth, drift) in enumerate(((6e5, 2e5), (2.5e3, -8e3))):
+        base_z = drift * (1 - u)[None, :] + vth * (L[:, None] - 0.5) * (1 + 0.3 * rng.random((9, N)))
+        base_p = vth * (0.2 + L[:, None]) * (1 + 0.2 * rng.random((9, N)))
+        base_z[:, ::17] = base_z[::-1, ::17]           # unordered quantiles in some cells
+        base_z[8, ::31] *= 40.0                         # some far above the energy limit
+        st[3 + 18 * q:12 + 18 * q] = base_z
+        st[12 + 18 * q:21 + 18 * q] = base_p
+    return st
+
+
+def test_state_load_matches_oracle(torch, O):
+    from paper_2605_07083_amd import pic
+    cfg = presets.scaled(presets.tiny(), gamma_emit=1e21)
+    st = _state(cfg, 3)
+    _say("case: state load, tiny diode")
+    h = pic.Handle(cfg, state=torch.tensor(st[None], dtype=torch.float64, device="cuda:0"))
+    g, t = gpu_state(h, 0)
+    s = O.Sim(cfg)
+    s.load_state(st)
+    for sp in (0, 2):
+        a, o = by_id(g[sp]), by_id(s.particles(sp))
+        assert np.array_equal(a["id"], o["id"])
+        assert np.array_equal(a["z"], o["z"])
+        assert np.array_equal(a["tc"], o["tc"])
+        for c in ("vx", "vy", "vz"):
+            assert np.max(np.abs(a[c] - o[c].astype(np.float32)) / np.abs(o[c]).max()) < 1e-6, (sp, c)
+    assert t["next_id"] == s.next_id
+    assert deposit_matches(O, cfg, h, g, 0) == []
+    assert field_matches(O, cfg, h, oracle_from_gpu(O, cfg, g, t), 0) == []
+    _say("case: restart parity from the state load, 20 steps")
+    assert restart_step_check(O, cfg, h, 20) == []
+
+
+def test_state_load_batched_and_errors(torch, O):
+    from paper_2605_07083_amd import pic
+    cfgs = [presets.scaled(presets.tiny(), diode=d, gamma_emit=1e21) for d in range(2)]
+    cfgs[1]["N"] = 128
+    nmax = 256
+    arr = np.zeros((2, pic.STATE_ROWS, nmax))
+    sts = [_state(c, 20 + d, 0.7 + 0.3 * d) for d, c in enumerate(cfgs)]
+    for d, st in enumerate(sts):
+        arr[d, :, :st.shape[1]] = st
+    _say("case: state load, 2 diodes (N 256/128)")
+    h = pic.Handle(cfgs, state=torch.tensor(arr, device="cuda:0"))
+    for d in range(2):
+        g, t = gpu_state(h, d)
+        s = O.Sim(cfgs[d])
+        s.load_state(sts[d])
+        for sp in (0, 2):
+            a, o = by_id(g[sp]), by_id(s.particles(sp))
+            assert np.array_equal(a["z"], o["z"]) and np.array_equal(a["id"], o["id"])
+            assert np.max(np.abs(a["vz"] - o["vz"].astype(np.float32)) / np.abs(o["vz"]).max()) < 1e-6
+    bad = arr[:1].copy()
+    bad[0, 25, 7] = np.nan
+    with pytest.raises(pic.PicError) as e:
+        pic.Handle(cfgs[0], state=torch.tensor(bad, device="cuda:0"))
+    assert e.value.code == pic.PIC_ENAN
+    with pytest.raises(ValueError):
+        pic.Handle(cfgs[0], state=torch.zeros((1, 3, 256), dtype=torch.float64, device="cuda:0"))
