@@ -3,13 +3,18 @@
  * A surrogate maps the four quantities the paper varies or fixes per run --
  * emission flux Gamma ("Benchmark cases", Table 2), cathode temperature T_c,
  * bias V and neutral density n_g ("Model", "Emission and collisions") -- to
- * the late-time profiles it reports ("Results": time-averaged potential and
- * densities) on X cell centres:
- *     out[b][0][x] = phi / V,  out[b][1][x] = ln(n_e / n0),  out[b][2][x] = ln(n_i / n0).
- * The profiles seed pic_init_from_profiles so that a run starts near its late
- * state.  The paper has no surrogate; the network is a reading: six 1D
- * convolutions (kernel 5, zero padding 2) with channels 16 -> 64 (x5) -> 3
- * and tanh between layers, on bfloat16 weights and activations with FP32
+ * the late-time state on X cell centres: the profiles the paper reports
+ * ("Results": time-averaged potential and densities) and, per species, the
+ * shape of the late-time velocity distribution:
+ *     out[b][0][x] = phi / V,  out[b][1][x] = ln(n_e / n0),  out[b][2][x] = ln(n_i / n0),
+ *     out[b][3..11][x], out[b][12..20][x]: electron v_z and |v_perp| quantiles / sqrt(e / m_e),
+ *     out[b][21..29][x], out[b][30..38][x]: ion v_z and |v_perp| quantiles / sqrt(e / m_i),
+ * quantiles at the levels of pic_init_from_state (speeds in units of the
+ * 1 eV thermal speed).  sur_state turns them into the state that
+ * pic_init_from_state loads, so that a run starts near its late state.  The
+ * paper has no surrogate; the network is a reading: six 1D convolutions
+ * (kernel 5, zero padding 2) with channels 16 -> 64 (x5) -> 39 (padded to 48
+ * on the matrix cores) and tanh between layers, on bfloat16 weights and activations with FP32
  * accumulation (gfx950 matrix cores), trained by mean squared error with Adam
  * (beta1 0.9, beta2 0.999, eps 1e-8) on FP32 master weights.
  *
@@ -41,10 +46,10 @@ extern "C" {
 #define SUR_LAYERS 6
 #define SUR_IN 16
 #define SUR_HIDDEN 64
-#define SUR_OUT 3
+#define SUR_OUT 39
 #define SUR_KS 5
-#define SUR_WEIGHTS 88000   /* 64*16*5 + 4*64*64*5 + 3*64*5 */
-#define SUR_BIASES 323      /* 5*64 + 3 */
+#define SUR_WEIGHTS 99520   /* 64*16*5 + 4*64*64*5 + 39*64*5 */
+#define SUR_BIASES 359      /* 5*64 + 39 */
 
 typedef struct sur_net sur_net;
 
@@ -70,14 +75,14 @@ int sur_get_weights(sur_net *n, float *w, float *b);
 int sur_get_grads(sur_net *n, float *w, float *b);
 
 /* Forward pass.  dev_params [batch][4] = (Gamma, T_c K, V, n_g) FP32 on the
- * device; dev_out [batch][3][cells] FP32 on the device. */
+ * device; dev_out [batch][SUR_OUT][cells] FP32 on the device. */
 int sur_forward(sur_net *n, const float *dev_params, int batch, float *dev_out);
 
 /* One training step on a batch: forward, loss = mean over (b, c, x) of
  * (out - target)^2, backward (input and weight gradients on the matrix
  * cores; the gradient entering each layer rounded to bfloat16), one Adam
  * update of every master weight and bias, re-quantisation to bfloat16.
- * dev_target [batch][3][cells] FP32.  If loss != NULL the call synchronises
+ * dev_target [batch][SUR_OUT][cells] FP32.  If loss != NULL the call synchronises
  * and stores the loss of this batch before the update. */
 int sur_train_step(sur_net *n, const float *dev_params, const float *dev_target, int batch, float lr,
                    double *loss);
@@ -88,6 +93,13 @@ int sur_train_step(sur_net *n, const float *dev_params, const float *dev_target,
 int sur_densities(sur_net *n, const float *dev_params, const double *dev_n0, int batch, double *dev_dens);
 
 /* Message of the last failing surrogate call on this thread. */
+/* The loader's state for a batch: dev_state [batch][39][cells] doubles with
+ * row 0 n0 exp(out[1]), row 1 n0 exp(out[2]) (m^-3), row 2 V out[0] (V, with
+ * V = params[b][2]) and rows 3..38 the quantile channels times their 1 eV
+ * speeds (m/s): the layout pic_init_from_state reads (PIC_STATE_ROWS rows,
+ * cells = N).  dev_n0: [batch] doubles.  Asynchronous. */
+int sur_state(sur_net *n, const float *dev_params, const double *dev_n0, int batch, double *dev_state);
+
 const char *sur_last_error(void);
 
 /* Release the handle (not the caller's workspace or stream). */

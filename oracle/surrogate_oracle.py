@@ -7,7 +7,7 @@ cathode temperature, bias, neutral density; the swept quantities of "Benchmark
 cases" and the operating point of "Model") to the late-time profiles the
 paper plots (potential, electron and ion densities; "Results") at the X cell
 centres.  The paper has no surrogate; its architecture is a reading: a stack
-of six 1D convolutions, kernel 5, zero padding 2, channels 16 -> 64 x 5 -> 3,
+of six 1D convolutions, kernel 5, zero padding 2, channels 16 -> 64 x 5 -> 39,
 tanh between layers, mean squared error, Adam.
 
 Quantised mode (what the BF16 matrix-core path computes, written as a
@@ -24,9 +24,9 @@ import torch
 
 KS = 5
 PAD = 2
-LAYERS = [(16, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 3)]
+LAYERS = [(16, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 39)]
 N_IN = 16
-N_OUT = 3
+N_OUT = 39
 ADAM_B1 = 0.9
 ADAM_B2 = 0.999
 ADAM_EPS = 1e-8
@@ -98,7 +98,7 @@ def conv(a, w, bias):
 
 
 def forward(W, b, feat, quantize=True, keep=False):
-    """Network output [B][3][X].  W, b: lists of arrays or tensors; feat
+    """Network output [B][N_OUT][X].  W, b: lists of arrays or tensors; feat
     [B][16][X].  With keep=True also returns the leaf tensors (for grads)."""
     Wt = [torch.as_tensor(np.asarray(w, dtype=np.float64)).requires_grad_(keep) for w in W]
     bt = [torch.as_tensor(np.asarray(v, dtype=np.float64)).requires_grad_(keep) for v in b]

@@ -28,6 +28,8 @@ hipError_t surx_adam(float *w, float *m, float *v, const float *g, int n, float 
                      float c1, float c2, hipStream_t s);
 hipError_t surx_requant(const float *wm, __bf16 *Wf, __bf16 *Wb, int cin, int coutp, int cout_real, int kp, int kpb,
                         hipStream_t s);
+hipError_t surx_to_state(const float *out, const float *params, const double *n0, double *state, int X, int B,
+                         hipStream_t s);
 hipError_t surx_init_weights(float *wm, int cin, int coutp, int cout_real, int kp, uint32_t layer, uint32_t seed,
                              hipStream_t s);
 hipError_t surx_to_densities(const float *out, const double *n0, double *dens, int X, int B, hipStream_t s);
@@ -52,8 +54,8 @@ int fail(int code, const std::string &msg)
 
 constexpr size_t ALIGN = 256;
 constexpr int CIN[SUR_LAYERS] = {16, 64, 64, 64, 64, 64};
-constexpr int COUT[SUR_LAYERS] = {64, 64, 64, 64, 64, 3};
-constexpr int COUTP[SUR_LAYERS] = {64, 64, 64, 64, 64, 16};
+constexpr int COUT[SUR_LAYERS] = {64, 64, 64, 64, 64, SUR_OUT};
+constexpr int COUTP[SUR_LAYERS] = {64, 64, 64, 64, 64, 48};
 constexpr float B1 = 0.9f, B2 = 0.999f, EPS = 1e-8f;
 
 int pad32(int k) { return (k + 31) / 32 * 32; }
@@ -341,6 +343,16 @@ int sur_densities(sur_net *n, const float *dev_params, const double *dev_n0, int
     int rc = forward(n, dev_params, batch, false);
     if (rc) return rc;
     SUR_TRY(surx_to_densities(n->yf[SUR_LAYERS - 1], dev_n0, dev_dens, n->X, batch, n->stream));
+    return PIC_OK;
+}
+
+int sur_state(sur_net *n, const float *dev_params, const double *dev_n0, int batch, double *dev_state)
+{
+    if (!n || !dev_params || !dev_n0 || !dev_state) return fail(PIC_EINVAL, "bad arguments");
+    if (batch < 1 || batch > n->bmax) return fail(PIC_EINVAL, "batch exceeds the workspace's max_batch");
+    int rc = forward(n, dev_params, batch, false);
+    if (rc) return rc;
+    SUR_TRY(surx_to_state(n->yf[SUR_LAYERS - 1], dev_params, dev_n0, dev_state, n->X, batch, n->stream));
     return PIC_OK;
 }
 

@@ -26,6 +26,8 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int KS = 5;     // kernel size
+constexpr int OUT = 39;   // output channels: phi / V, ln n_e / n0, ln n_i / n0, 36 velocity quantiles
+constexpr int OUTP = 48;  // padded to whole 16-column matrix-core tiles
 constexpr int PAD = 2;
 
 __device__ __forceinline__ bf16x8 zero8()
@@ -157,28 +159,27 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ in,
 }
 
 // ---------------------------------------------------------------------------
-// Loss: mean over (b, channel < 3, x) of (out - target)^2.  Writes
-// dZ = 2 (out - target) / count as BF16 in the padded 16-channel layout.
-// target[b][c][x], out[b][x][16].
+// Loss: mean over (b, channel < OUT, x) of (out - target)^2.  Writes
+// dZ = 2 (out - target) / count as BF16 in the padded OUTP-channel layout.
+// target[b][c][x], out[b][x][OUTP].
 // ---------------------------------------------------------------------------
 __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ target, __bf16 *__restrict__ dz,
                        __bf16 *__restrict__ dzT, double *__restrict__ loss, int X, int B)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    const double inv = 1.0 / (3.0 * (double)X * (double)B);
+    const double inv = 1.0 / ((double)OUT * (double)X * (double)B);
     double acc = 0.0;
     if (idx < X * B) {
         const int b = idx / X, x = idx - b * X;
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
+        for (int c = 0; c < OUTP; ++c) {
             float g = 0.0f;
-            if (c < 3) {
-                const float d = out[(size_t)idx * 16 + c] - target[((size_t)b * 3 + c) * X + x];
+            if (c < OUT) {
+                const float d = out[(size_t)idx * OUTP + c] - target[((size_t)b * OUT + c) * X + x];
                 acc += (double)d * d;
                 g = (float)(2.0 * inv) * d;
             }
-            dz[(size_t)idx * 16 + c] = (__bf16)g;
-            dzT[((size_t)b * 16 + c) * X + x] = (__bf16)g;
+            dz[(size_t)idx * OUTP + c] = (__bf16)g;
+            dzT[((size_t)b * OUTP + c) * X + x] = (__bf16)g;
         }
     }
     // wave reduction, one atomic per wave
@@ -401,18 +402,37 @@ __global__ void k_to_densities(const float *__restrict__ out, const double *__re
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= X * B) return;
     const int b = idx / X, x = idx - b * X;
-    dens[((size_t)b * 2 + 0) * X + x] = n0[b] * exp((double)out[(size_t)idx * 16 + 1]);
-    dens[((size_t)b * 2 + 1) * X + x] = n0[b] * exp((double)out[(size_t)idx * 16 + 2]);
+    dens[((size_t)b * 2 + 0) * X + x] = n0[b] * exp((double)out[(size_t)idx * OUTP + 1]);
+    dens[((size_t)b * 2 + 1) * X + x] = n0[b] * exp((double)out[(size_t)idx * OUTP + 2]);
 }
 
-// Network output [b][x][16] -> caller layout [b][3][x].
+// Network output -> the state the warm-start loader reads, [b][OUT][x]:
+// densities as k_to_densities, phi = V out[0], the electron quantiles
+// (channels 3..20) times the 1 eV electron speed sqrt(e / m_e), the ion ones
+// (21..38) times the 1 eV ion speed sqrt(e / m_i).  params[b][2] is V.
+__global__ void k_to_state(const float *__restrict__ out, const float *__restrict__ params,
+                           const double *__restrict__ n0, double *__restrict__ state, int X, int B)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= X * B) return;
+    const int b = idx / X, x = idx - b * X;
+    const float *o = out + (size_t)idx * OUTP;
+    double *st = state + (size_t)b * OUT * X + x;
+    const double ve = sqrt(1.602176634e-19 / 9.1093837015e-31);
+    const double vi = sqrt(1.602176634e-19 / (6.6464731e-27 - 9.1093837015e-31));
+    st[0] = n0[b] * exp((double)o[1]);
+    st[(size_t)X] = n0[b] * exp((double)o[2]);
+    st[(size_t)2 * X] = (double)params[(size_t)b * 4 + 2] * (double)o[0];
+    for (int c = 3; c < OUT; ++c) st[(size_t)c * X] = (double)o[c] * (c < 21 ? ve : vi);
+}
+
+// Network output [b][x][OUTP] -> caller layout [b][OUT][x].
 __global__ void k_unpack(const float *__restrict__ y, float *__restrict__ out, int X, int B)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= X * B) return;
     const int b = idx / X, x = idx - b * X;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) out[((size_t)b * 3 + c) * X + x] = y[(size_t)idx * 16 + c];
+    for (int c = 0; c < OUT; ++c) out[((size_t)b * OUT + c) * X + x] = y[(size_t)idx * OUTP + c];
 }
 
 }  // namespace sur
@@ -435,7 +455,7 @@ extern "C" hipError_t surx_conv_fwd(int layer, const __bf16 *in, const __bf16 *W
     dim3 g(X / 64 * B), t(256);
     if (layer == 0) hipLaunchKernelGGL((k_conv_fwd<16, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
     else if (layer < 5) hipLaunchKernelGGL((k_conv_fwd<64, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
-    else hipLaunchKernelGGL((k_conv_fwd<64, 16, false>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
+    else hipLaunchKernelGGL((k_conv_fwd<64, OUTP, false>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
     return hipGetLastError();
 }
 
@@ -451,7 +471,7 @@ extern "C" hipError_t surx_conv_dgrad(int layer, const __bf16 *dz, const __bf16 
                                       __bf16 *dzprev, __bf16 *dzprevT, int X, int B, hipStream_t s)
 {
     dim3 g(X / 64 * B), t(256);
-    if (layer == 5) hipLaunchKernelGGL((k_conv_dgrad<64, 16>), g, t, 0, s, dz, Wb, yprev, dzprev, dzprevT, X, B);
+    if (layer == 5) hipLaunchKernelGGL((k_conv_dgrad<64, OUTP>), g, t, 0, s, dz, Wb, yprev, dzprev, dzprevT, X, B);
     else hipLaunchKernelGGL((k_conv_dgrad<64, 64>), g, t, 0, s, dz, Wb, yprev, dzprev, dzprevT, X, B);
     return hipGetLastError();
 }
@@ -466,7 +486,7 @@ extern "C" hipError_t surx_conv_wgrad(int layer, const __bf16 *dzT, const __bf16
     else if (layer < 5)
         hipLaunchKernelGGL((k_conv_wgrad<64, 64>), blocks(4 * 20), dim3(256), 0, s, dzT, inT, dW, db, X, B);
     else
-        hipLaunchKernelGGL((k_conv_wgrad<64, 16>), blocks(1 * 20), dim3(256), 0, s, dzT, inT, dW, db, X, B);
+        hipLaunchKernelGGL((k_conv_wgrad<64, OUTP>), blocks(OUTP / 16 * 20), dim3(256), 0, s, dzT, inT, dW, db, X, B);
     return hipGetLastError();
 }
 
@@ -503,6 +523,13 @@ extern "C" hipError_t surx_init_weights(float *wm, int cin, int coutp, int cout_
 extern "C" hipError_t surx_to_densities(const float *out, const double *n0, double *dens, int X, int B, hipStream_t s)
 {
     hipLaunchKernelGGL(k_to_densities, dim3((X * B + 255) / 256), dim3(256), 0, s, out, n0, dens, X, B);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t surx_to_state(const float *out, const float *params, const double *n0, double *state, int X,
+                                    int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_state, dim3((X * B + 255) / 256), dim3(256), 0, s, out, params, n0, state, X, B);
     return hipGetLastError();
 }
 

@@ -117,7 +117,7 @@ def surrogate_cases(n, seed):
     return out
 
 
-SURROGATE_LAYERS = [(16, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 3)]
+SURROGATE_LAYERS = [(16, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 39)]
 
 
 def surrogate_test_weights(seed, scale=1.0):

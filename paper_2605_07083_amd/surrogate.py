@@ -8,13 +8,14 @@ import numpy as np
 
 from . import pic
 
-LAYERS = [(16, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 3)]
+LAYERS = [(16, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 39)]
 KS = 5
 N_WEIGHTS = sum(ci * co * KS for ci, co in LAYERS)
 N_BIASES = sum(co for _, co in LAYERS)
+N_OUT = LAYERS[-1][1]
 
 SYMBOLS = ["sur_workspace_size", "sur_create", "sur_set_weights", "sur_get_weights", "sur_get_grads",
-           "sur_forward", "sur_train_step", "sur_densities", "sur_last_error", "sur_destroy"]
+           "sur_forward", "sur_train_step", "sur_densities", "sur_state", "sur_last_error", "sur_destroy"]
 
 _bound = False
 
@@ -33,6 +34,7 @@ def lib():
             "sur_forward": ([P, P, i, P], i),
             "sur_train_step": ([P, P, P, i, f, C.POINTER(d)], i),
             "sur_densities": ([P, P, P, i, P], i),
+            "sur_state": ([P, P, P, i, P], i),
             "sur_last_error": ([], C.c_char_p),
             "sur_destroy": ([P], None),
         }
@@ -121,11 +123,11 @@ class Surrogate:
         return unpack(w, b)
 
     def forward(self, params, out=None):
-        """params [B, 4] (Gamma, T_c K, V, n_g) -> [B, 3, cells] float32 on the GPU."""
+        """params [B, 4] (Gamma, T_c K, V, n_g) -> [B, N_OUT, cells] float32 on the GPU."""
         import torch
         p = self._params(params)
         if out is None:
-            out = torch.empty((p.shape[0], 3, self.cells), dtype=torch.float32, device=self.device)
+            out = torch.empty((p.shape[0], N_OUT, self.cells), dtype=torch.float32, device=self.device)
         _check(lib().sur_forward(self.h, C.c_void_p(p.data_ptr()), p.shape[0], C.c_void_p(out.data_ptr())))
         return out
 
@@ -133,8 +135,8 @@ class Surrogate:
         import torch
         p = self._params(params)
         t = torch.as_tensor(target, dtype=torch.float32).to(self.device).contiguous()
-        if tuple(t.shape) != (p.shape[0], 3, self.cells):
-            raise ValueError("target must be [B, 3, cells]")
+        if tuple(t.shape) != (p.shape[0], N_OUT, self.cells):
+            raise ValueError("target must be [B, %d, cells]" % N_OUT)
         loss = C.c_double()
         _check(lib().sur_train_step(self.h, C.c_void_p(p.data_ptr()), C.c_void_p(t.data_ptr()), p.shape[0],
                                     float(lr), C.byref(loss) if want_loss else None))
@@ -150,4 +152,17 @@ class Surrogate:
         out = torch.empty((p.shape[0], 2, self.cells), dtype=torch.float64, device=self.device)
         _check(lib().sur_densities(self.h, C.c_void_p(p.data_ptr()), C.c_void_p(n0.data_ptr()), p.shape[0],
                                    C.c_void_p(out.data_ptr())))
+        return out
+
+    def state(self, params, n0):
+        """Warm-start state [B, 39, cells] float64 for pic_init_from_state
+        (densities, potential, velocity quantiles in m/s)."""
+        import torch
+        p = self._params(params)
+        n0 = torch.as_tensor(n0, dtype=torch.float64).to(self.device).reshape(-1).contiguous()
+        if n0.shape[0] != p.shape[0]:
+            raise ValueError("one n0 per sample")
+        out = torch.empty((p.shape[0], N_OUT, self.cells), dtype=torch.float64, device=self.device)
+        _check(lib().sur_state(self.h, C.c_void_p(p.data_ptr()), C.c_void_p(n0.data_ptr()), p.shape[0],
+                               C.c_void_p(out.data_ptr())))
         return out

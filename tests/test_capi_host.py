@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= set(pic.SYMBOLS)
     from paper_2605_07083_amd import surrogate
     names = _declared("surrogate.h", "sur")
-    assert len(names) == 10
+    assert len(names) == 11
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(surrogate.SYMBOLS)
@@ -41,12 +41,13 @@ def test_library_exports_every_declared_symbol():
 
 def test_surrogate_workspace_and_shapes():
     from paper_2605_07083_amd import surrogate
-    assert surrogate.N_WEIGHTS == 88000 and surrogate.N_BIASES == 323
+    assert surrogate.N_WEIGHTS == 99520 and surrogate.N_BIASES == 359 and surrogate.N_OUT == 39
     a = surrogate.workspace_size(1, 2048)
     b = surrogate.workspace_size(32, 2048)
-    # per position: features 2 x 16 bf16, outputs 5 x 64 + 16 FP32, hidden bf16
-    # copies 2 x 5 x 64, two gradient buffers 2 x 2 x 64 bf16 = 3200 bytes
-    per_pos = 2 * 16 * 2 + (5 * 64 + 16) * 4 + 2 * 5 * 64 * 2 + 2 * 2 * 64 * 2
+    # per position: features 2 x 16 bf16, outputs 5 x 64 + 48 FP32 (39 channels
+    # padded to 48), hidden bf16 copies 2 x 5 x 64, two gradient buffers
+    # 2 x 2 x 64 bf16 = 3328 bytes
+    per_pos = 2 * 16 * 2 + (5 * 64 + 48) * 4 + 2 * 5 * 64 * 2 + 2 * 2 * 64 * 2
     assert abs((b - a) - per_pos * 31 * 2048) < 64 * 1024
     for bad in ((0, 2048), (4, 100), (4, 0)):
         with pytest.raises(pic.PicError) as e:

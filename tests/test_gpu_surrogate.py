@@ -55,6 +55,16 @@ def _params(n, seed):
     return np.stack([d["gamma_emit"], d["T_K"], d["V"], d["ng"]], axis=1)
 
 
+def _target39(u, k):
+    """Smooth targets for all output channels: the three profiles, then
+    quantile-like channels increasing with the channel index."""
+    rows = [u * (1 + 0.1 * k), np.log(0.2 + u), np.log(1.2 - u)]
+    for c in range(3, SO.N_OUT):
+        j = (c - 3) % 9
+        rows.append(0.3 * (j - 4) + 0.2 * np.sin(3 * u + c + k))
+    return np.stack(rows)
+
+
 def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
 
@@ -86,7 +96,7 @@ def test_gradients_and_adam_match_oracle(sur, torch):
     p = _params(B, 22)
     rng = np.random.default_rng(5)
     u = (np.arange(X) + 0.5) / X
-    target = np.stack([np.stack([u * (1 + 0.1 * k), -0.5 + 0.2 * np.sin(3 * u + k), -0.3 * u ** 2]) for k in range(B)])
+    target = np.stack([_target39(u, k) for k in range(B)])
     target = (target + 0.01 * rng.normal(size=target.shape)).astype(np.float32)
     net = sur.Surrogate(B, X, device="cuda:0")
     net.set_weights(W, b)
@@ -116,7 +126,7 @@ def test_training_trajectory_matches_oracle(sur, torch):
     W, b = presets.surrogate_test_weights(13)
     p = _params(B, 23)
     u = (np.arange(X) + 0.5) / X
-    target = np.stack([np.stack([u, np.log(0.2 + u), np.log(1.2 - u)]) for _ in range(B)]).astype(np.float32)
+    target = np.stack([_target39(u, 0) for _ in range(B)]).astype(np.float32)
     net = sur.Surrogate(B, X, device="cuda:0")
     net.set_weights(W, b)
     f = SO.features(p.astype(np.float32).astype(np.float64), X)
@@ -147,6 +157,14 @@ def test_densities_are_exp_of_forward(sur, torch):
     d = net.densities(p, n0).cpu().numpy()
     assert np.allclose(d[:, 0, :], n0[:, None] * np.exp(out[:, 1, :]), rtol=1e-12)
     assert np.allclose(d[:, 1, :], n0[:, None] * np.exp(out[:, 2, :]), rtol=1e-12)
+    # the loader's state: densities, V phi/V, quantile channels times the 1 eV speeds
+    st = net.state(p, n0).cpu().numpy()
+    q_e, m_e, m_i = 1.602176634e-19, 9.1093837015e-31, 6.6464731e-27 - 9.1093837015e-31
+    V = p[:, 2].astype(np.float32).astype(np.float64)
+    assert np.allclose(st[:, 0:2, :], d, rtol=1e-12)
+    assert np.allclose(st[:, 2, :], V[:, None] * out[:, 0, :], rtol=1e-12)
+    assert np.allclose(st[:, 3:21, :], out[:, 3:21, :] * np.sqrt(q_e / m_e), rtol=1e-12)
+    assert np.allclose(st[:, 21:39, :], out[:, 21:39, :] * np.sqrt(q_e / m_i), rtol=1e-12)
 
 
 def test_surrogate_rejects_bad_shapes(sur, torch):

@@ -89,7 +89,7 @@ def test_backward_matches_finite_differences():
     rng = np.random.default_rng(8)
     p = np.array([[2e19, 2100.0, 15.0, 5e21], [9e19, 1850.0, 6.0, 1.5e21]])
     f = S.features(p, 12)
-    t = rng.normal(size=(2, 3, 12))
+    t = rng.normal(size=(2, S.N_OUT, 12))
     loss, gW, gb = S.loss_and_grads(W, b, f, t, quantize=False)
     assert loss == pytest.approx(_loss(W, b, f, t), rel=1e-14)
     h = 1e-5
