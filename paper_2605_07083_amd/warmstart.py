@@ -4,8 +4,9 @@ evaluation, driving the library's kernels through the C ABI.
 Host orchestration only: the particle runs are pic_step graphs, the steady
 detector is pic_steady_state, the profiles come from the device's time
 averages, the surrogate's forward, backward and Adam steps are sur_* calls,
-and the warm load is pic_init_from_profiles.  What runs here is batching,
-bookkeeping and the conversion of node fields into training targets.
+and the warm load is pic_init_from_state.  What runs here is batching,
+bookkeeping and the conversion of node fields and particle snapshots into
+training targets (per-cell velocity quantiles, averaged over snapshots).
 
 Steady state (the paper's late-time windows of "Benchmark cases", read as in
 pic_steady_state): blocks of `block_steps`; a diode is steady at the end of
@@ -31,6 +32,11 @@ from . import pic, presets
 
 DENSITY_FLOOR = 1e-4      # targets use ln(max(n, floor n0) / n0)
 BATCH_DIODES = 32
+BLOCK_STEPS = 2500        # detector blocks (5 tallies of 500 steps)
+AVG_BLOCKS = 8            # late-time window of 20000 steps
+SNAPSHOTS = 4             # particle snapshots per window for the velocity quantiles
+Q_E, M_E, M_HE = 1.602176634e-19, 9.1093837015e-31, 6.6464731e-27
+V1 = (math.sqrt(Q_E / M_E), math.sqrt(Q_E / (M_HE - M_E)))   # 1 eV speeds: electrons, ions
 
 
 def _log(msg):
@@ -51,19 +57,80 @@ def targets_from_fields(cfg, f):
                      np.log(np.maximum(c(f["n_i"]), fl) / n0)])
 
 
-def run_to_steady(cfgs, densities=None, block_steps=5000, tol_pp=1.0, tol_rel=5e-4, avg_blocks=4,
-                  max_steps=300000, label=""):
+def cell_quantiles(cfg, z, v):
+    """Per-cell quantiles [9][N] of v at pic.STATE_LEVELS (linear
+    interpolation between order statistics); cells without particles get 0."""
+    N = cfg["N"]
+    cell = np.clip((z * (N / cfg["L"])).astype(np.int64), 0, N - 1)
+    o = np.lexsort((v, cell))
+    cs, vs = cell[o], v[o]
+    cnt = np.bincount(cs, minlength=N)
+    start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    out = np.zeros((len(pic.STATE_LEVELS), N))
+    has = cnt > 0
+    for k, lev in enumerate(pic.STATE_LEVELS):
+        h = lev * np.maximum(cnt - 1, 0)
+        lo = np.floor(h).astype(np.int64)
+        hi = np.minimum(lo + 1, np.maximum(cnt - 1, 0))
+        fr = h - lo
+        a = vs[np.minimum(start + lo, len(vs) - 1)] if len(vs) else np.zeros(N)
+        b = vs[np.minimum(start + hi, len(vs) - 1)] if len(vs) else np.zeros(N)
+        out[k] = np.where(has, a + fr * (b - a), 0.0)
+    return out
+
+
+def velocity_quantiles(h, d, cfg):
+    """The 36 normalised quantile rows of one diode's current particles:
+    electrons (plasma and emitted) then ions, v_z then |v_perp|, each in units
+    of the species' 1 eV speed."""
+    rows = []
+    for q, sps in enumerate(((0, 1), (2,))):
+        parts = [h.particles(d, sp) for sp in sps]
+        z = np.concatenate([p["z"] for p in parts])
+        live = z >= 0.0
+        z = z[live]
+        vz = np.concatenate([p["vz"] for p in parts]).astype(np.float64)[live]
+        vx = np.concatenate([p["vx"] for p in parts]).astype(np.float64)[live]
+        vy = np.concatenate([p["vy"] for p in parts]).astype(np.float64)[live]
+        rows.append(cell_quantiles(cfg, z, vz) / V1[q])
+        rows.append(cell_quantiles(cfg, z, np.hypot(vx, vy)) / V1[q])
+    return np.concatenate(rows)
+
+
+def state_from_targets(cfg, t):
+    """Targets [39][N] -> the state pic_init_from_state reads (the host
+    counterpart of sur_state)."""
+    n0 = cfg["n0"]
+    st = np.empty_like(t, dtype=np.float64)
+    st[0] = n0 * np.exp(t[1])
+    st[1] = n0 * np.exp(t[2])
+    st[2] = cfg["V"] * t[0]
+    st[3:21] = t[3:21] * V1[0]
+    st[21:39] = t[21:39] * V1[1]
+    return st
+
+
+def run_to_steady(cfgs, densities=None, state=None, block_steps=BLOCK_STEPS, tol_pp=1.0, tol_rel=None,
+                  avg_blocks=AVG_BLOCKS, max_steps=300000, label="", velocities=False):
     """Run a batch of diodes until each is steady and averaged.  Returns one
     dict per diode: steady_step (-1 if never), backflow_pct over the averaging
-    window, targets [3][N] (None if never steady), steps (run length)."""
+    window, targets [3][N] (or [39][N] with velocities: the quantile rows
+    averaged over SNAPSHOTS particle snapshots of the window; None if never
+    steady), steps (run length).  tol_rel defaults to 1e-7 per step of a
+    block (2.5e-4 for blocks of 2500)."""
     import torch
     nd = len(cfgs)
     tp = cfgs[0]["tally_period"]
     if block_steps % tp or any(c["tally_period"] != tp for c in cfgs):
         raise ValueError("block_steps must be a multiple of one common tally period")
     bt = block_steps // tp
+    if tol_rel is None:
+        tol_rel = 1e-7 * block_steps
     t0 = time.time()
-    h = pic.Handle(cfgs, densities=densities)
+    h = pic.Handle(cfgs, densities=densities, state=state)
+    vq = [None] * nd
+    nsnap = [0] * nd
+    snap_every = avg_blocks * block_steps // SNAPSHOTS
     phase = ["relax"] * nd
     res = [{"steady_step": -1, "backflow_pct": float("nan"), "targets": None, "steps": 0} for _ in range(nd)]
     avg_start = [0] * nd
@@ -71,6 +138,12 @@ def run_to_steady(cfgs, densities=None, block_steps=5000, tol_pp=1.0, tol_rel=5e
     while step < max_steps and any(p != "done" for p in phase):
         h.step(block_steps)
         step += block_steps
+        if velocities:
+            for d in range(nd):
+                if phase[d] == "avg" and (step - avg_start[d]) % snap_every == 0:
+                    q = velocity_quantiles(h, d, cfgs[d])
+                    vq[d] = q if vq[d] is None else vq[d] + q
+                    nsnap[d] += 1
         for d in range(nd):
             if phase[d] == "relax":
                 s = h.steady_state(d, block_tallies=bt, tol_pp=tol_pp, tol_rel=tol_rel)
@@ -83,6 +156,8 @@ def run_to_steady(cfgs, densities=None, block_steps=5000, tol_pp=1.0, tol_rel=5e
                 f = h.fields(d, time_avg=True)
                 dg = h.diagnostics(d, window_steps=step - avg_start[d])
                 res[d]["targets"] = targets_from_fields(cfgs[d], f)
+                if velocities:
+                    res[d]["targets"] = np.concatenate([res[d]["targets"], vq[d] / max(nsnap[d], 1)])
                 res[d]["backflow_pct"] = float(dg["backflow_pct"])
                 res[d]["steps"] = step
                 h.avg_control(d, False)
@@ -99,33 +174,44 @@ def run_to_steady(cfgs, densities=None, block_steps=5000, tol_pp=1.0, tol_rel=5e
     return res
 
 
-def generate(n, seed, out, **kw):
-    cfgs = presets.surrogate_cases(n, seed)
+def generate(n, seed, out, first=0, count=None, **kw):
+    """Steady states of cases [first, first + count) of surrogate_cases(n, seed)."""
+    n_total = n
+    cfgs = presets.surrogate_cases(n, seed)[first:None if count is None else first + count]
+    n = len(cfgs)
     P, T, S, B, R = [], [], [], [], []
     for b0 in range(0, n, BATCH_DIODES):
         batch = cfgs[b0:b0 + BATCH_DIODES]
-        res = run_to_steady(batch, label="generate %d-%d" % (b0, b0 + len(batch) - 1), **kw)
+        res = run_to_steady(batch, label="generate %d-%d" % (b0, b0 + len(batch) - 1), velocities=True, **kw)
         for c, r in zip(batch, res):
             P.append(params_of(c))
-            T.append(r["targets"] if r["targets"] is not None else np.full((3, c["N"]), np.nan))
+            T.append(r["targets"] if r["targets"] is not None else np.full((pic.STATE_ROWS, c["N"]), np.nan))
             S.append(r["steady_step"])
             B.append(r["backflow_pct"])
             R.append(r["steps"])
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
-    np.savez(out, params=np.array(P), targets=np.array(T, np.float32), steady_step=np.array(S),
-             backflow_pct=np.array(B), steps=np.array(R), seed=seed)
+    # targets stored as float16 (rounding below the surrogate's fit error), compressed
+    np.savez_compressed(out, params=np.array(P), targets=np.array(T, np.float16), steady_step=np.array(S),
+             backflow_pct=np.array(B), steps=np.array(R), seed=seed, first=first, n_total=n_total)
     ok = np.array(S) >= 0
     _log("generated %d cases (%d steady), median steps-to-steady %s -> %s" % (
         n, ok.sum(), np.median(np.array(S)[ok]) if ok.any() else "n/a", out))
 
 
+def _load_sets(data):
+    """One or more generated .npz files (a path or a list) -> params, targets."""
+    paths = [data] if isinstance(data, str) else list(data)
+    zs = [np.load(p) for p in paths]
+    return np.concatenate([z["params"] for z in zs]), np.concatenate([z["targets"] for z in zs])
+
+
 def train(data, out, epochs=600, batch=32, lr=2e-3, seed=7, heldout=None):
     import torch
     from .surrogate import Surrogate
-    z = np.load(data)
-    ok = np.isfinite(z["targets"]).all(axis=(1, 2))
-    P = torch.tensor(z["params"][ok], dtype=torch.float32, device="cuda:0")
-    T = torch.tensor(z["targets"][ok], dtype=torch.float32, device="cuda:0")
+    params, targets = _load_sets(data)
+    ok = np.isfinite(targets).all(axis=(1, 2))
+    P = torch.tensor(params[ok], dtype=torch.float32, device="cuda:0")
+    T = torch.tensor(targets[ok], dtype=torch.float32, device="cuda:0")
     n, X = T.shape[0], T.shape[2]
     net = Surrogate(batch, X, seed=seed)
     g = torch.Generator(device="cpu").manual_seed(seed)
@@ -177,15 +263,19 @@ def load_weights(path):
     return [z["W%d" % l] for l in range(6)], [z["b%d" % l] for l in range(6)]
 
 
-def evaluate(data, weights=None, out=None, **kw):
+def evaluate(data, weights=None, out=None, profiles_only=False, **kw):
     """Warm runs of the held-out cases against their cold runs (stored in
-    `data`).  With weights: from the surrogate's profiles.  Without: from the
-    cold runs' own late-time profiles (the best any predictor can do)."""
+    `data`).  With weights: from the surrogate's predicted state.  Without:
+    from the cold runs' own late-time state (profiles and velocity quantiles:
+    the best this representation allows).  profiles_only: densities alone
+    (pic_init_from_profiles), velocities Maxwellian at the load temperatures."""
     import torch
     z = np.load(data)
     seed = int(z["seed"])
     n = len(z["params"])
-    cfgs = presets.surrogate_cases(n, seed)
+    first = int(z["first"]) if "first" in z.files else 0
+    n_total = int(z["n_total"]) if "n_total" in z.files else n
+    cfgs = presets.surrogate_cases(n_total, seed)[first:first + n]
     net = None
     if weights:
         from .surrogate import Surrogate
@@ -198,11 +288,16 @@ def evaluate(data, weights=None, out=None, **kw):
         n0 = torch.tensor([c["n0"] for c in batch], dtype=torch.float64, device="cuda:0")
         if net is not None:
             p = torch.tensor([params_of(c) for c in batch], dtype=torch.float32, device="cuda:0")
-            dens = net.densities(p, n0).contiguous()
+            st = net.state(p, n0).contiguous()
         else:
             t = np.nan_to_num(z["targets"][b0:b0 + len(batch)].astype(np.float64), nan=0.0)
-            dens = (n0[:, None, None] * torch.exp(torch.tensor(t[:, 1:3], device="cuda:0"))).contiguous()
-        res = run_to_steady(batch, densities=dens, label="warm %d-%d" % (b0, b0 + len(batch) - 1), **kw)
+            st = torch.tensor(np.stack([state_from_targets(c, tt) for c, tt in zip(batch, t)]),
+                              device="cuda:0").contiguous()
+        if profiles_only:
+            res = run_to_steady(batch, densities=st[:, 0:2].contiguous(),
+                                label="warm (profiles) %d-%d" % (b0, b0 + len(batch) - 1), **kw)
+        else:
+            res = run_to_steady(batch, state=st, label="warm %d-%d" % (b0, b0 + len(batch) - 1), **kw)
         for k, r in enumerate(res):
             i = b0 + k
             rows.append({"case": i, "cold_steady_step": int(z["steady_step"][i]),
@@ -233,8 +328,10 @@ def main(argv=None):
     g.add_argument("--seed", default="train", help="'train', 'heldout' or an integer")
     g.add_argument("--out", required=True)
     g.add_argument("--max-steps", type=int, default=300000)
+    g.add_argument("--first", type=int, default=0, help="first case of the n")
+    g.add_argument("--count", type=int, default=None, help="number of cases from --first (default: the rest)")
     t = sub.add_parser("train")
-    t.add_argument("--data", required=True)
+    t.add_argument("--data", required=True, nargs="+")
     t.add_argument("--heldout")
     t.add_argument("--out", required=True)
     t.add_argument("--epochs", type=int, default=600)
@@ -243,19 +340,21 @@ def main(argv=None):
     t.add_argument("--report")
     e = sub.add_parser("evaluate")
     e.add_argument("--data", required=True)
-    e.add_argument("--weights", help="surrogate weights; omitted: the cold runs' own profiles")
+    e.add_argument("--weights", help="surrogate weights; omitted: the cold runs' own late-time state")
+    e.add_argument("--profiles-only", action="store_true", help="load densities only (Maxwellian velocities)")
     e.add_argument("--out")
     e.add_argument("--max-steps", type=int, default=300000)
     a = ap.parse_args(argv)
     if a.cmd == "generate":
         seed = {"train": presets.SURROGATE_TRAIN_SEED, "heldout": presets.SURROGATE_HELDOUT_SEED}.get(a.seed)
-        generate(a.n, int(a.seed, 0) if seed is None else seed, a.out, max_steps=a.max_steps)
+        generate(a.n, int(a.seed, 0) if seed is None else seed, a.out, first=a.first, count=a.count,
+                 max_steps=a.max_steps)
     elif a.cmd == "train":
         rep = train(a.data, a.out, epochs=a.epochs, batch=a.batch, lr=a.lr, heldout=a.heldout)
         if a.report:
             json.dump(rep, open(a.report, "w"), indent=1)
     else:
-        evaluate(a.data, a.weights, a.out, max_steps=a.max_steps)
+        evaluate(a.data, a.weights, a.out, profiles_only=a.profiles_only, max_steps=a.max_steps)
 
 
 if __name__ == "__main__":
