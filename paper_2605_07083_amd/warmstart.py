@@ -34,7 +34,7 @@ DENSITY_FLOOR = 1e-4      # targets use ln(max(n, floor n0) / n0)
 BATCH_DIODES = 32
 BLOCK_STEPS = 2500        # detector blocks (5 tallies of 500 steps)
 AVG_BLOCKS = 8            # late-time window of 20000 steps
-SNAPSHOTS = 4             # particle snapshots per window for the velocity quantiles
+SNAPSHOT_AT = (0.75, 1.0)  # particle snapshots for the velocity quantiles, as fractions of the window
 Q_E, M_E, M_HE = 1.602176634e-19, 9.1093837015e-31, 6.6464731e-27
 V1 = (math.sqrt(Q_E / M_E), math.sqrt(Q_E / (M_HE - M_E)))   # 1 eV speeds: electrons, ions
 
@@ -115,7 +115,8 @@ def run_to_steady(cfgs, densities=None, state=None, block_steps=BLOCK_STEPS, tol
     """Run a batch of diodes until each is steady and averaged.  Returns one
     dict per diode: steady_step (-1 if never), backflow_pct over the averaging
     window, targets [3][N] (or [39][N] with velocities: the quantile rows
-    averaged over SNAPSHOTS particle snapshots of the window; None if never
+    averaged over particle snapshots at the SNAPSHOT_AT fractions of the
+    window, its late part, where the distributions are most relaxed; None if never
     steady), steps (run length).  tol_rel defaults to 1e-7 per step of a
     block (2.5e-4 for blocks of 2500)."""
     import torch
@@ -130,7 +131,8 @@ def run_to_steady(cfgs, densities=None, state=None, block_steps=BLOCK_STEPS, tol
     h = pic.Handle(cfgs, densities=densities, state=state)
     vq = [None] * nd
     nsnap = [0] * nd
-    snap_every = avg_blocks * block_steps // SNAPSHOTS
+    window = avg_blocks * block_steps
+    snap_steps = {int(round(f * window / block_steps)) * block_steps for f in SNAPSHOT_AT}
     phase = ["relax"] * nd
     res = [{"steady_step": -1, "backflow_pct": float("nan"), "targets": None, "steps": 0} for _ in range(nd)]
     avg_start = [0] * nd
@@ -140,7 +142,7 @@ def run_to_steady(cfgs, densities=None, state=None, block_steps=BLOCK_STEPS, tol
         step += block_steps
         if velocities:
             for d in range(nd):
-                if phase[d] == "avg" and (step - avg_start[d]) % snap_every == 0:
+                if phase[d] == "avg" and (step - avg_start[d]) in snap_steps:
                     q = velocity_quantiles(h, d, cfgs[d])
                     vq[d] = q if vq[d] is None else vq[d] + q
                     nsnap[d] += 1
