@@ -285,7 +285,7 @@ int grid_for(const pic_handle *h)
     int64_t chunks = 0;
     for (int d = 0; d < h->nd; ++d)
         for (int s = 0; s < NSP; ++s) chunks += (h->der[d].capacity[s] + 256 * h->ppt - 1) / (256 * h->ppt);
-    int64_t g = std::min<int64_t>(chunks, 16384);
+    int64_t g = std::min<int64_t>(chunks, 8192);
     g = std::max<int64_t>(8, (g + 7) / 8 * 8);
     return (int)g;
 }
