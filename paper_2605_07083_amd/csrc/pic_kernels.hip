@@ -457,11 +457,12 @@ struct ChunkRegs {
 };
 
 // Slots [t0, t0 + PPT) of one thread; capacities are multiples of the largest
-// chunk, so the whole range is always inside the buffer.  The particle
-// streams are read and written with the non-temporal hint: each line is
-// touched once per step, and keeping them from displacing the lines that are
-// reused (field tiles, histograms, the collision candidates' records and
-// countdowns) is worth a fifth of the kernel's time.
+// chunk, so the whole range is always inside the buffer.  z and v_z are read
+// and written with the non-temporal hint: each line is touched once per step,
+// and keeping them from displacing the lines that are reused (field tiles,
+// histograms, the collision candidates' records) is worth a fifth of the
+// kernel's time.  The countdown is read normally: its lines stay in L2 for
+// the candidates' new countdowns, written after the run, to merge into.
 template <int PPT>
 __device__ __forceinline__ void load_chunk(ChunkRegs<PPT> &C, const GBuf &b, int t0, int mode)
 {
@@ -471,7 +472,7 @@ __device__ __forceinline__ void load_chunk(ChunkRegs<PPT> &C, const GBuf &b, int
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             C.vz[k] = __builtin_nontemporal_load(&b.vz[t0 + k]);
-            C.tc[k] = __builtin_nontemporal_load(&b.tc[t0 + k]);
+            C.tc[k] = b.tc[t0 + k];
         }
     }
 }
