@@ -149,6 +149,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune-steps", type=int, default=192)
+    ap.add_argument("--schedule", default="", help="ppt,grid,sort_period,use_graph: fixed schedule, no autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -178,7 +179,13 @@ def main():
                                                                     args.steps), file=sys.stderr, flush=True)
     h = pic.Handle(cfgs, device="cuda:0")
     h.step(args.warmup)
-    tune = h.autotune(trial_steps=args.tune_steps) if args.tune_steps > 0 else h.tuning()
+    if args.schedule:
+        ppt, grid, K, g = (int(x) for x in args.schedule.split(","))
+        h.set_tuning(ppt=ppt, grid=grid, sort_period=K, use_graph=g)
+        h.step(2 * K)
+        tune = h.tuning()
+    else:
+        tune = h.autotune(trial_steps=args.tune_steps) if args.tune_steps > 0 else h.tuning()
     print("bench: schedule %s" % tune, file=sys.stderr, flush=True)
     h.sync()
     torch.cuda.synchronize()
