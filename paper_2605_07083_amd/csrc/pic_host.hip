@@ -52,6 +52,7 @@ int fail(int code, const std::string &msg)
     } while (0)
 
 constexpr size_t ALIGN = 256;
+constexpr int TPOS = 8;   // particle kernels timed per replayed period (pic_step_timed)
 
 // ----------------------------------------------------------------------------
 // Derived quantities ("Model": w0 = n0 dz / N_ppc, dt and grid; MCC bound).
@@ -262,6 +263,7 @@ struct pic_handle {
     hipGraphExec_t tgraph[2] = {nullptr, nullptr};
     hipGraph_t tsrc[2] = {nullptr, nullptr};  // kept alive: its node handles address the exec's nodes
     std::vector<hipGraphNode_t> tnode[2];   // (start, end) per step of the period
+    std::vector<int> tset[2];               // steps whose nodes hold this call's events
     hipEvent_t tev[2] = {nullptr, nullptr}; // placeholders recorded by the other steps
     ~pic_handle()
     {
@@ -414,6 +416,7 @@ int ensure_timed_graph(pic_handle *h, int p)
     }
     h->tsrc[p] = g;
     h->tnode[p] = marks;
+    h->tset[p].clear();
     return PIC_OK;
 }
 
@@ -898,8 +901,8 @@ int pic_refield(pic_handle *h)
 int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *mean_live, double *total_ms)
 {
     if (!h || nsteps < 1) return fail(PIC_EINVAL, "bad arguments");
-    // events for every particle kernel of graph replays, one launch in `every`
-    // on the plain stream
+    // events for TPOS particle kernels per graph replay, one launch in
+    // `every` on the plain stream
     const int64_t every = std::max<int64_t>(1, nsteps / 512);
     const int64_t nev = (h->use_graph ? std::min<int64_t>(nsteps, 4096) : nsteps / every) + 2;
     std::vector<hipEvent_t> ev(2 * nev);
@@ -924,23 +927,33 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
     int rc = live_sum(live0);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(t0, h->stream));
-    int64_t k_ev = 0, left = nsteps, k = 0;
+    int64_t k_ev = 0, left = nsteps, k = 0, replay = 0;
     while (left > 0) {
         if (h->use_graph && h->sort_period > 1 && !h->sort_next && h->issued % h->sort_period == 0 &&
             left >= h->sort_period && k_ev < nev) {
-            // one re-sort period replayed from its graph, every particle kernel
-            // timed (the kernel slows down over a period as particles drift
-            // from their sorted places, so no single position is typical)
+            // one re-sort period replayed from its graph with TPOS particle
+            // kernels timed, spread evenly over the period and shifted by one
+            // position per replay (the kernel slows down over a period as
+            // particles drift from their sorted places, so no single position
+            // is typical; setting every node each replay would cost more host
+            // time than a short period takes on the GPU)
             const int p = h->parity;
             if ((rc = ensure_timed_graph(h, p))) return rc;
-            for (int pos = 0; pos < h->sort_period; ++pos) {
-                const bool real = k_ev < nev;
-                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos],
-                                                            real ? ev[2 * k_ev] : h->tev[0]));
-                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos + 1],
-                                                            real ? ev[2 * k_ev + 1] : h->tev[1]));
-                if (real) ++k_ev;
+            const int K = h->sort_period;
+            for (int pos : h->tset[p]) {
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos], h->tev[0]));
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos + 1], h->tev[1]));
             }
+            h->tset[p].clear();
+            const int ns = std::min(TPOS, K);
+            for (int j = 0; j < ns && k_ev < nev; ++j) {
+                const int pos = (int)((j * (int64_t)K / ns + replay) % K);
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos], ev[2 * k_ev]));
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos + 1], ev[2 * k_ev + 1]));
+                h->tset[p].push_back(pos);
+                ++k_ev;
+            }
+            ++replay;
             HIP_TRY(hipGraphLaunch(h->tgraph[p], h->stream));
             h->parity ^= 1;
             h->issued += h->sort_period;
@@ -976,6 +989,14 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
     float tot = 0.f;
     HIP_TRY(hipEventElapsedTime(&tot, t0, t1));
     if ((rc = live_sum(live1))) return rc;
+    // the replayed graphs must not keep this call's events
+    for (int p = 0; p < 2; ++p) {
+        for (int pos : h->tset[p]) {
+            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos], h->tev[0]));
+            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos + 1], h->tev[1]));
+        }
+        h->tset[p].clear();
+    }
     for (auto &e : ev) (void)hipEventDestroy(e);
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
