@@ -34,7 +34,7 @@ DENSITY_FLOOR = 1e-4      # targets use ln(max(n, floor n0) / n0)
 BATCH_DIODES = 32
 BLOCK_STEPS = 2500        # detector blocks (5 tallies of 500 steps)
 AVG_BLOCKS = 8            # late-time window of 20000 steps
-SNAPSHOT_AT = (0.75, 1.0)  # particle snapshots for the velocity quantiles, as fractions of the window
+SNAPSHOT_AT = (1.0,)      # particle snapshots for the velocity quantiles, as fractions of the window
 Q_E, M_E, M_HE = 1.602176634e-19, 9.1093837015e-31, 6.6464731e-27
 V1 = (math.sqrt(Q_E / M_E), math.sqrt(Q_E / (M_HE - M_E)))   # 1 eV speeds: electrons, ions
 
@@ -114,9 +114,10 @@ def run_to_steady(cfgs, densities=None, state=None, block_steps=BLOCK_STEPS, tol
                   avg_blocks=AVG_BLOCKS, max_steps=300000, label="", velocities=False):
     """Run a batch of diodes until each is steady and averaged.  Returns one
     dict per diode: steady_step (-1 if never), backflow_pct over the averaging
-    window, targets [3][N] (or [39][N] with velocities: the quantile rows
-    averaged over particle snapshots at the SNAPSHOT_AT fractions of the
-    window, its late part, where the distributions are most relaxed; None if never
+    window, targets [3][N] (or [39][N] with velocities: the quantile rows of
+    the particles at the SNAPSHOT_AT fractions of the window -- its end, where
+    the distributions are most relaxed (pooling a snapshot 5000 steps earlier
+    measured slower warm starts); None if never
     steady), steps (run length).  tol_rel defaults to 1e-7 per step of a
     block (2.5e-4 for blocks of 2500)."""
     import torch
