@@ -180,11 +180,10 @@ int pic_init_from_profiles(const pic_config *cfgs, int n_diodes, void *dev_works
  * first; v_z and |v_perp| are drawn from the piecewise-linear inverse of the
  * cell's quantile function with two uniform draws, the azimuth of (v_x, v_y)
  * uniformly with a third (Philox keyed by the particle id, event LOAD, counter
- * word 2 = 0, 0, 2).  A particle whose kinetic energy exceeds
- * e (|V| + 20 Te0 + 20 Tc - fall) (electrons) or e (|V| + 20 Ti0 - fall)
- * (ions), fall = the potential it can still fall through (V - phi for
- * electrons, phi for ions, clamped to [0, |V|]), is scaled down to that
- * energy, which keeps the later motion inside the null-collision bound.
+ * word 2 = 0, 0, 2).  A particle whose kinetic energy exceeds the
+ * null-collision bound's energy cap, e (|V| + 40 Te0 + 40 Tc) (electrons) or
+ * e (|V| + 40 Ti0) (ions), is scaled down to it.  Row 2 (phi) is checked
+ * for being finite and otherwise not read.
  * Reads the array before return.  PIC_ENAN for a negative density or a
  * non-finite entry, PIC_ENOSPACE as for pic_init_from_profiles. */
 #define PIC_STATE_ROWS 39

@@ -499,9 +499,8 @@ int o_load_profiles(osim *o, const double *ne, const double *ni)
  * speed |v_perp| at nine levels; a loaded particle draws each from the
  * piecewise-linear inverse of its cell's quantile function and a uniform
  * azimuth for (v_x, v_y).  The quantiles are first sorted (monotone
- * rearrangement).  A kinetic energy above what the null-collision bound
- * allows after the particle's later fall through the potential (ions toward
- * the cathode, electrons toward the anode) is scaled down to that limit. */
+ * rearrangement).  A kinetic energy above the null-collision bound's energy
+ * cap (the energy up to which the bound was scanned) is scaled down to it. */
 static const double OQ_LEVELS[OQ] = {0.0, 0.02, 0.1, 0.25, 0.5, 0.75, 0.9, 0.98, 1.0};
 
 static void sort9(double q[OQ])
@@ -538,8 +537,8 @@ int o_load_state(osim *o, const double *prof)
         const double *dens = prof + (int64_t)q * N;
         const double lam = o->d.lam[q];
         const double m = o->d.mass[s];
-        /* energy allowed at load (eV) before the fall through the potential */
-        const double cap = q ? fabs(c->V) + 20.0 * c->Ti0 : fabs(c->V) + 20.0 * c->Te0 + 20.0 * c->Tc;
+        /* the null-collision bound's energy cap (eV) */
+        const double cap = q ? fabs(c->V) + 40.0 * c->Ti0 : fabs(c->V) + 40.0 * c->Te0 + 40.0 * c->Tc;
         for (int32_t j = 0; j < c->N; ++j) {
             const double x = dens[j] * o->d.dz / o->d.w0;
             if (!(x >= 0.0) || x > 1073741824.0) return -2;
@@ -550,10 +549,7 @@ int o_load_state(osim *o, const double *prof)
             }
             sort9(qz);
             sort9(qp);
-            const double phi = prof[2 * N + j];
-            double fall = q ? phi : c->V - phi;
-            fall = fmin(fmax(fall, 0.0), fabs(c->V));
-            const double emax = Q_E * (cap - fall);     /* J */
+            const double emax = Q_E * cap;     /* J */
             const double fl = floor(x);
             uint32_t bc[4];
             draw((uint32_t)j, kseed(o), LOAD_STEP, EV_PROFILE, (uint32_t)q, bc);

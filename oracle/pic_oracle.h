@@ -85,11 +85,12 @@ int o_load(osim *o);
 int o_load_profiles(osim *o, const double *ne, const double *ni);
 
 /* Warm start from a late-time state on the N cells: prof[r][c], rows
- *   0 n_e, 1 n_i (m^-3), 2 phi (V),
+ *   0 n_e, 1 n_i (m^-3), 2 phi (V; carried with the state, not used by the load),
  *   3..11 electron v_z quantiles, 12..20 electron |v_perp| quantiles (m/s),
  *   21..29 ion v_z quantiles, 30..38 ion |v_perp| quantiles,
  * at the levels OQ_LEVELS.  Counts, ids, positions and free flights as in
- * o_load_profiles; velocities from the quantiles.  -2: negative density or a
+ * o_load_profiles; velocities from the quantiles, kinetic energies capped at
+ * the null-collision bound's energy cap.  -2: negative density or a
  * non-finite entry. */
 #define OSTATE_ROWS 39
 #define OQ 9

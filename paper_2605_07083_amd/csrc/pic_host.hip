@@ -226,10 +226,10 @@ void fill_params(const pic_config &c, const pic_derived &der, Diode &D)
     D.sig_c = std::sqrt(Q_E * c.Tc / MASS_E);
     D.sig_e0 = std::sqrt(Q_E * c.Te0 / MASS_E);
     D.sig_i0 = std::sqrt(Q_E * c.Ti0 / mi);
-    // a state-loaded particle may still fall through up to |V|: half of the
-    // null-collision bound's thermal allowance is left for its own energy
-    D.load_cap_ev[0] = std::fabs(c.V) + 20.0 * c.Te0 + 20.0 * c.Tc;
-    D.load_cap_ev[1] = std::fabs(c.V) + 20.0 * c.Ti0;
+    // a state-loaded particle starts inside the energy range the null-collision
+    // bound was scanned over (numax_of)
+    D.load_cap_ev[0] = std::fabs(c.V) + 40.0 * c.Te0 + 40.0 * c.Tc;
+    D.load_cap_ev[1] = std::fabs(c.V) + 40.0 * c.Ti0;
     D.kseed = c.seed ^ c.diode;
     D.channels = c.channels;
     D.replenish = c.replenish;

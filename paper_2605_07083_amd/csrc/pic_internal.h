@@ -151,7 +151,7 @@ struct Diode {
     float ng, sig_el, sig_x0, lotz_a2, sig_cx, sig_iel;
     double emit_x;         // Gamma dt / w0
     double sig_c, sig_e0, sig_i0;
-    double load_cap_ev[2]; // state load: kinetic energy limit before the fall (eV), electrons / ions
+    double load_cap_ev[2]; // state load: kinetic energy limit (eV), electrons / ions
     uint32_t kseed, channels;
     int32_t replenish, tally_period;
     SpeciesBuf buf[2][NSP];

@@ -1005,8 +1005,8 @@ __device__ __forceinline__ double from_q9(const double q[9], double u)
 // Maxwellian at the load temperature, drawn as in the uniform load.  Else
 // state [diode][STATE_ROWS][max_cells]: v_z and |v_perp| from the cell's
 // quantiles (rows 3 + 18 q and 12 + 18 q, q = 0 electrons, 1 ions), a uniform
-// azimuth, and the kinetic energy limited to load_cap_ev minus the potential
-// the particle can still fall through (row 2).
+// azimuth, and the kinetic energy limited to load_cap_ev (the null-collision
+// bound's energy cap).
 __global__ __launch_bounds__(256) void k_profile_fill(const Diode *__restrict__ D, const double *__restrict__ state,
                                                       int max_cells)
 {
@@ -1029,8 +1029,7 @@ __global__ __launch_bounds__(256) void k_profile_fill(const Diode *__restrict__ 
             qz[k] = row[(size_t)(3 + 18 * q + k) * max_cells];
             qp[k] = row[(size_t)(12 + 18 * q + k) * max_cells];
         }
-        const double phi = row[(size_t)2 * max_cells];
-        bool fin = isfinite(phi);
+        bool fin = isfinite(row[(size_t)2 * max_cells]);
 #pragma unroll
         for (int k = 0; k < 9; ++k) fin = fin && isfinite(qz[k]) && isfinite(qp[k]);
         if (!fin) {
@@ -1039,8 +1038,7 @@ __global__ __launch_bounds__(256) void k_profile_fill(const Diode *__restrict__ 
         }
         sort_q9(qz);
         sort_q9(qp);
-        const double fall = fmin(fmax(q ? phi : dd.V - phi, 0.0), fabs(dd.V));
-        emax = Q_E * (dd.load_cap_ev[q] - fall);
+        emax = Q_E * dd.load_cap_ev[q];
     }
     for (int i = a + lane; i < e; i += 64) {
         const uint32_t id = id0 + (uint32_t)i;
