@@ -208,7 +208,7 @@ def _load_sets(data):
     return np.concatenate([z["params"] for z in zs]), np.concatenate([z["targets"] for z in zs])
 
 
-def train(data, out, epochs=600, batch=32, lr=2e-3, seed=7, heldout=None):
+def train(data, out, epochs=4000, batch=32, lr=2e-3, seed=7, heldout=None):
     import torch
     from .surrogate import Surrogate
     params, targets = _load_sets(data)
@@ -337,7 +337,7 @@ def main(argv=None):
     t.add_argument("--data", required=True, nargs="+")
     t.add_argument("--heldout")
     t.add_argument("--out", required=True)
-    t.add_argument("--epochs", type=int, default=600)
+    t.add_argument("--epochs", type=int, default=4000)
     t.add_argument("--batch", type=int, default=32)
     t.add_argument("--lr", type=float, default=2e-3)
     t.add_argument("--report")
