@@ -246,9 +246,9 @@ int pic_refield(pic_handle *h);
 
 /* Per-kernel timing: run nsteps steps on the current schedule with HIP events
  * around launches of the particle kernel on the bound stream (with graph
- * replay: 8 particle kernels per replayed re-sort period, spread evenly over
- * the period and shifted by one step each replay, until 4096 are timed; on
- * the plain stream: one launch in max(1, nsteps / 512)) and return their mean
+ * replay: the particle kernels of 8 steps spread evenly over each replayed
+ * re-sort period, until 4096 are timed; on the plain stream: one launch in
+ * max(1, nsteps / 512)) and return their mean
  * duration (ms), the mean live-particle count and the total time (ms).
  * Synchronises. */
 int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *mean_live,

@@ -262,8 +262,8 @@ struct pic_handle {
     // the same graphs with event-record nodes around every particle kernel
     hipGraphExec_t tgraph[2] = {nullptr, nullptr};
     hipGraph_t tsrc[2] = {nullptr, nullptr};  // kept alive: its node handles address the exec's nodes
-    std::vector<hipGraphNode_t> tnode[2];   // (start, end) per step of the period
-    std::vector<int> tset[2];               // steps whose nodes hold this call's events
+    std::vector<hipGraphNode_t> tnode[2];   // (start, end) per timed step of the period
+    std::vector<int> tset[2];               // timed steps whose nodes hold this call's events
     hipEvent_t tev[2] = {nullptr, nullptr}; // placeholders recorded by the other steps
     ~pic_handle()
     {
@@ -396,16 +396,20 @@ int ensure_timed_graph(pic_handle *h, int p)
     const int B = 1 + picx_sources_field_kernels(h->max_nodes, 0);
     if ((int)chain.size() < B * K + 1) return bail("unexpected captured period");
     const int first = (int)chain.size() - B * K;      // particle kernel of step 0
-    std::vector<hipGraphNode_t> marks(2 * K);
-    for (int k = 0; k < K; ++k) {
+    // event nodes around TPOS particle kernels spread evenly over the period
+    // (each pair of event nodes costs a few microseconds of idle GPU)
+    const int ns = std::min(TPOS, K);
+    std::vector<hipGraphNode_t> marks(2 * ns);
+    for (int j = 0; j < ns; ++j) {
+        const int k = (int)((int64_t)j * K / ns);
         hipGraphNode_t pred = chain[first + B * k - 1], part = chain[first + B * k];
         hipGraphNode_t field = chain[first + B * k + 1];
         if (hipGraphRemoveDependencies(g, &pred, &part, 1) != hipSuccess ||
             hipGraphRemoveDependencies(g, &part, &field, 1) != hipSuccess ||
-            hipGraphAddEventRecordNode(&marks[2 * k], g, &pred, 1, h->tev[0]) != hipSuccess ||
-            hipGraphAddDependencies(g, &marks[2 * k], &part, 1) != hipSuccess ||
-            hipGraphAddEventRecordNode(&marks[2 * k + 1], g, &part, 1, h->tev[1]) != hipSuccess ||
-            hipGraphAddDependencies(g, &marks[2 * k + 1], &field, 1) != hipSuccess)
+            hipGraphAddEventRecordNode(&marks[2 * j], g, &pred, 1, h->tev[0]) != hipSuccess ||
+            hipGraphAddDependencies(g, &marks[2 * j], &part, 1) != hipSuccess ||
+            hipGraphAddEventRecordNode(&marks[2 * j + 1], g, &part, 1, h->tev[1]) != hipSuccess ||
+            hipGraphAddDependencies(g, &marks[2 * j + 1], &field, 1) != hipSuccess)
             return bail("splicing event nodes failed");
     }
     hipError_t e = hipGraphInstantiate(&h->tgraph[p], g, nullptr, nullptr, 0);
@@ -927,33 +931,28 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
     int rc = live_sum(live0);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(t0, h->stream));
-    int64_t k_ev = 0, left = nsteps, k = 0, replay = 0;
+    int64_t k_ev = 0, left = nsteps, k = 0;
     while (left > 0) {
         if (h->use_graph && h->sort_period > 1 && !h->sort_next && h->issued % h->sort_period == 0 &&
             left >= h->sort_period && k_ev < nev) {
-            // one re-sort period replayed from its graph with TPOS particle
-            // kernels timed, spread evenly over the period and shifted by one
-            // position per replay (the kernel slows down over a period as
-            // particles drift from their sorted places, so no single position
-            // is typical; setting every node each replay would cost more host
-            // time than a short period takes on the GPU)
+            // one re-sort period replayed from its graph with the particle
+            // kernels at TPOS positions spread evenly over the period timed
+            // (the kernel slows down over a period as particles drift from
+            // their sorted places, so no single position is typical)
             const int p = h->parity;
             if ((rc = ensure_timed_graph(h, p))) return rc;
-            const int K = h->sort_period;
-            for (int pos : h->tset[p]) {
-                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos], h->tev[0]));
-                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos + 1], h->tev[1]));
+            for (int j : h->tset[p]) {
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * j], h->tev[0]));
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * j + 1], h->tev[1]));
             }
             h->tset[p].clear();
-            const int ns = std::min(TPOS, K);
+            const int ns = (int)(h->tnode[p].size() / 2);
             for (int j = 0; j < ns && k_ev < nev; ++j) {
-                const int pos = (int)((j * (int64_t)K / ns + replay) % K);
-                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos], ev[2 * k_ev]));
-                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos + 1], ev[2 * k_ev + 1]));
-                h->tset[p].push_back(pos);
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * j], ev[2 * k_ev]));
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * j + 1], ev[2 * k_ev + 1]));
+                h->tset[p].push_back(j);
                 ++k_ev;
             }
-            ++replay;
             HIP_TRY(hipGraphLaunch(h->tgraph[p], h->stream));
             h->parity ^= 1;
             h->issued += h->sort_period;
@@ -991,9 +990,9 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
     if ((rc = live_sum(live1))) return rc;
     // the replayed graphs must not keep this call's events
     for (int p = 0; p < 2; ++p) {
-        for (int pos : h->tset[p]) {
-            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos], h->tev[0]));
-            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * pos + 1], h->tev[1]));
+        for (int j : h->tset[p]) {
+            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * j], h->tev[0]));
+            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * j + 1], h->tev[1]));
         }
         h->tset[p].clear();
     }

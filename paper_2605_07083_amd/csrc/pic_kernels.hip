@@ -530,14 +530,20 @@ __device__ __forceinline__ void flush_tally(const Diode &dd, const RareTally &t)
 }
 
 // Fold the accumulator copies into rt (LDS) and clear them: the first wave
-// of the block, one copy per lane, a fixed shuffle tree per field.
-__device__ __forceinline__ void fold_tally_copies(const Diode &dd, RareTally *rt)
+// of the block, one copy per lane (read and cleared by take_tally_copy), a
+// fixed shuffle tree per field.
+__device__ __forceinline__ RareTally take_tally_copy(const Diode &dd)
 {
     static_assert(TALLY_COPIES == 64, "one copy per lane of the first wave");
+    const int lane = threadIdx.x & 63;
+    const RareTally v = dd.tacc[lane].t;
+    dd.tacc[lane].t = RareTally{};
+    return v;
+}
+__device__ __forceinline__ void fold_tally_copies(RareTally v, RareTally *rt)
+{
     if (threadIdx.x >= 64) return;
     const int lane = threadIdx.x;
-    RareTally v = dd.tacc[lane].t;
-    dd.tacc[lane].t = RareTally{};
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
@@ -1544,10 +1550,12 @@ __device__ __forceinline__ void step_sources(const Diode &dd, DiodeState *st, un
 {
     __shared__ DiodeState s_st;
     const int tid = threadIdx.x;
+    RareTally copy{};
+    if (tid < 64) copy = take_tally_copy(dd);      // in flight together with the counters
     if (tid == 0) rare_tally_zero(rt);
     if (tid >= 64 && tid < 128) load_state(st, &s_st);
     __syncthreads();
-    fold_tally_copies(dd, rt);       // first wave
+    fold_tally_copies(copy, rt);     // first wave
     if (s_st.rare_n[SP_P] | s_st.rare_n[SP_E] | s_st.rare_n[SP_I]) {
         // items the particle kernel's queues could not hold: they may queue
         // ionisations, so the counters are read again afterwards
