@@ -78,7 +78,10 @@ def cpu_baseline(cfg, seconds=12.0):
 # FLOPs of one surrogate training step per position: forward and weight
 # gradients 2 * 88000 each (88000 = multiply-adds of the six layers per
 # position), input gradients of layers 1-5 2 * 82880.
-SUR_FLOP_PER_POSITION = 2 * 88000 + 2 * 88000 + 2 * 82880
+# model flops per position and training step (real channels, not the padding):
+# forward and weight gradients 2 x 99520 each, input gradients of layers 1-5
+# 2 x (4 x 64 x 64 x 5 + 39 x 64 x 5) = 2 x 94400
+SUR_FLOP_PER_POSITION = 2 * 99520 + 2 * 99520 + 2 * 94400
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
@@ -93,8 +96,11 @@ def surrogate_bench(args):
     P = torch.tensor(np.stack([q["gamma_emit"], q["T_K"], q["V"], q["ng"]], 1), dtype=torch.float32,
                      device="cuda:0")
     u = np.linspace(0.5 / X, 1 - 0.5 / X, X)
-    T = torch.tensor(np.stack([np.stack([u * (1 + 0.01 * k), np.log(0.3 + u), np.log(1.3 - u)])
-                               for k in range(B)]), dtype=torch.float32, device="cuda:0")
+    def target(k):
+        rows = [u * (1 + 0.01 * k), np.log(0.3 + u), np.log(1.3 - u)]
+        rows += [0.3 * ((c - 3) % 9 - 4) + 0.2 * np.sin(3 * u + c + k) for c in range(3, 39)]
+        return np.stack(rows)
+    T = torch.tensor(np.stack([target(k) for k in range(B)]), dtype=torch.float32, device="cuda:0")
     net = Surrogate(B, X, seed=1)
     for _ in range(args.warmup):
         net.train_step(P, T, 1e-3, want_loss=False)
