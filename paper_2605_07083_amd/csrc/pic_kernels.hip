@@ -849,8 +849,8 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             if (v) gadd(&H[w0 + t], v);
         }
         if (mode == 0) {
-            // the run's rare items with the whole block, while their lines are
-            // still in cache: collisions of candidates, tallies of absorbed
+            // the run's rare items with the whole block, soon after the run
+            // (the countdown lines are still in L2): collisions of candidates, tallies of absorbed
             int tot = 0;
 #pragma unroll
             for (int q = 0; q < NW; ++q) tot += q_n[q];
