@@ -1238,7 +1238,17 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
     constexpr int CHUNK = NT * PPT;
     __shared__ int seg_end[NSP * MAX_DIODES];
     __shared__ int seg_n[NSP * MAX_DIODES];
-    __shared__ int cnt[WMAX + 2];
+    __shared__ int cnt[WMAX + 2];       // the block's count per window bin, then its global base
+    __shared__ int loc[WMAX + 2];       // start of each window bin in the block's staging order
+    __shared__ int s_nin;
+    // The chunk's in-window particles are staged in LDS in destination order
+    // and written out by consecutive threads: each bin's run of the block then
+    // leaves as contiguous stores rather than as lanes scattered over the bins.
+    __shared__ double st_z[CHUNK];
+    __shared__ float st_vz[CHUNK];
+    __shared__ uint32_t st_tc[CHUNK];
+    __shared__ int st_dest[CHUNK];
+    __shared__ u32x4 st_cold[CHUNK];
     ChunkMap cm;
     build_chunk_map(S, nd, CHUNK, false, seg_end, cm, seg_n);
     const int tid = threadIdx.x;
@@ -1290,6 +1300,25 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
             rank[k] = (j[k] < 0) ? 0 : (inw ? r : r);
         }
         lds_barrier();
+        // staging starts of the window bins: exclusive scan of the block's
+        // counts by the first wave
+        if (tid < 64) {
+            int run = 0;
+            for (int b0 = 0; b0 < wn; b0 += 64) {
+                const int t = b0 + tid;
+                const int v = t < wn ? cnt[t] : 0;
+                int inc = v;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int u = __shfl_up(inc, o, 64);
+                    if (tid >= o) inc += u;
+                }
+                if (t < wn) loc[t] = run + inc - v;
+                run += __shfl(inc, 63, 64);
+            }
+            if (tid == 0) s_nin = run;
+        }
+        lds_barrier();
         for (int t = tid; t < wn; t += NT) {
             const int v = cnt[t];
             if (v) cnt[t] = gadd(&cur[bin_slot(w0 + t)], v);
@@ -1298,13 +1327,34 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             if (j[k] < 0) continue;
-            const int dest = rank[k] >= 0 ? cnt[j[k] - w0] + rank[k] : -1 - rank[k];
-            // (non-temporal hints here measured slightly slower: the scattered
-            // writes gain from merging in L2)
-            dst.z[dest] = z[k];
-            dst.vz[dest] = src.vz[t0 + k];
-            *(GLB u32x4 *)&dst.cold[dest] = *(const GLB u32x4 *)&src.cold[t0 + k];
-            dst.tc[dest] = src.tc[t0 + k];
+            const float vz = src.vz[t0 + k];
+            const u32x4 cr = *(const GLB u32x4 *)&src.cold[t0 + k];
+            const uint32_t tc = src.tc[t0 + k];
+            if (rank[k] >= 0) {
+                const int jl = j[k] - w0;
+                const int L = loc[jl] + rank[k];
+                st_z[L] = z[k];
+                st_vz[L] = vz;
+                st_cold[L] = cr;
+                st_tc[L] = tc;
+                st_dest[L] = cnt[jl] + rank[k];
+            } else {
+                // an outlier bin's slot came from its global counter directly
+                const int dest = -1 - rank[k];
+                dst.z[dest] = z[k];
+                dst.vz[dest] = vz;
+                *(GLB u32x4 *)&dst.cold[dest] = cr;
+                dst.tc[dest] = tc;
+            }
+        }
+        lds_barrier();
+        const int nin = s_nin;
+        for (int L = tid; L < nin; L += NT) {
+            const int dest = st_dest[L];
+            dst.z[dest] = st_z[L];
+            dst.vz[dest] = st_vz[L];
+            *(GLB u32x4 *)&dst.cold[dest] = st_cold[L];
+            dst.tc[dest] = st_tc[L];
         }
         lds_barrier();
         c = run_end;
