@@ -151,6 +151,60 @@ def solve(N, dz, V, rho):
     return phi
 
 
+Q_E = 1.602176634e-19
+EPS0 = 8.8541878128e-12
+
+
+def solve_exact(N, dz, V, R, w0):
+    """The Dirichlet Poisson system of the model section (phi_0 = 0,
+    phi_N = V, phi_{j-1} - 2 phi_j + phi_{j+1} = -rho_j dz^2 / eps0 on the
+    interior nodes) for the charge of the fixed-point deposit,
+    rho_j = e w0 R_j / (2^32 dz) with integer R_j, eliminated in exact
+    rational arithmetic and rounded to FP64 once per node.  Slow and exact:
+    the reference for grids where the FP64 sweep of ``solve`` loses digits
+    to rounding."""
+    from fractions import Fraction
+    N = int(N)
+    phi = np.zeros(N + 1, dtype=np.float64)
+    phi[N] = V
+    k = Fraction(Q_E) * Fraction(w0) / (Fraction(2**32) * Fraction(dz))
+    alpha = k * Fraction(dz) * Fraction(dz) / Fraction(EPS0)
+    psi = solve_exact_psi(N, R)
+    Vf = Fraction(V)
+    for j in range(1, N):
+        phi[j] = float(Vf * j / N + alpha * psi[j])
+    return phi
+
+
+def solve_exact_psi(N, R):
+    """psi with psi_{j-1} - 2 psi_j + psi_{j+1} = -R_j (j = 1..N-1),
+    psi_0 = psi_N = 0, as exact Fractions: the Thomas forward sweep and back
+    substitution on rationals (so phi_j = V j / N + alpha psi_j with
+    alpha = e w0 dz / (2^32 eps0))."""
+    from fractions import Fraction
+    N = int(N)
+    n = N - 1
+    psi = [Fraction(0)] * (N + 1)
+    if n <= 0:
+        return psi
+    cp = [Fraction(0)] * n
+    dp = [Fraction(0)] * n
+    for i in range(n):
+        rhs = Fraction(-int(R[i + 1]))
+        cc = 1 if i < n - 1 else 0
+        if i == 0:
+            cp[i] = Fraction(cc, -2)
+            dp[i] = rhs / -2
+        else:
+            m = -2 - cp[i - 1]
+            cp[i] = cc / m
+            dp[i] = (rhs - dp[i - 1]) / m
+    psi[n] = dp[n - 1]
+    for i in range(n - 2, -1, -1):
+        psi[i + 1] = dp[i] - cp[i] * psi[i + 2]
+    return psi
+
+
 def efield(N, dz, phi):
     phi = np.ascontiguousarray(phi, dtype=np.float64)
     E = np.zeros(N + 1, dtype=np.float64)

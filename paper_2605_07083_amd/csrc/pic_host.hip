@@ -171,6 +171,8 @@ void layout(const pic_config *cfgs, int nd, const std::vector<pic_derived> &der,
         D.E = bp.take<double>(nn);
         D.phi_sum = bp.take<double>(nn);
         D.agg = bp.take<FieldAgg>((nn + 1023) / 1024);
+        D.bagg = bp.take<FieldAgg>((nn + 1023) / 1024);
+        for (int s = 0; s < NSP; ++s) D.Hb[s] = bp.take<unsigned long long>(nn);
         D.tacc = bp.take<TallyCopy>(TALLY_COPIES);
     }
     zero_end = bp.off;

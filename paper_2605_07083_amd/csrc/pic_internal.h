@@ -165,6 +165,8 @@ struct Diode {
     DiodeTally *tally;
     TallySnap *ring;
     FieldAgg *agg;         // one per FT-node tile of the field solve
+    FieldAgg *bagg;        // the births' share of each tile's aggregates (tiled step)
+    unsigned long long *Hb[NSP];   // the births' deposits (tiled step; zero between steps)
     uint32_t *rare[NSP];   // the step's rare items per species: slot | kind << 30
     TallyCopy *tacc;       // TALLY_COPIES accumulators of the particle kernel's tallies
 };

@@ -1437,14 +1437,47 @@ __device__ __forceinline__ I128 shfl_up_i128(I128 a, int o)
     return r;
 }
 
-__device__ __forceinline__ void deposit_global(const Diode &dd, int s, double z)
+// Where the births deposit.  The single-block step adds them to H; the tiled
+// step runs the births beside the tile aggregates, which read H, so there the
+// births deposit into the side histograms Hb and sum their share of each
+// tile's aggregates in LDS: A_t (charge) and B_t (charge times the number of
+// the tile's interior nodes at or after its node), B_t as a 128-bit integer.
+constexpr int MAX_TILES = 32768 / FT;    // N <= 32767
+struct BirthSink {
+    unsigned long long *bA;      // [MAX_TILES] LDS, or nullptr: deposit into H
+    unsigned long long *bBlo;
+    unsigned long long *bBhi;
+};
+
+__device__ __forceinline__ void tile_share(const Diode &dd, const BirthSink &k, int j, long long v)
+{
+    if (j < 1 || j > dd.N - 1 || v == 0) return;
+    const int t = j / FT;
+    const long long x = v * (long long)(min((t + 1) * FT, dd.N) - j);    // |x| < 2^43
+    atomicAdd(&k.bA[t], (unsigned long long)v);
+    // 128-bit add of the sign-extended x: the carry out of the low word is
+    // taken from the value this add found there
+    const unsigned long long old = atomicAdd(&k.bBlo[t], (unsigned long long)x);
+    const unsigned long long hi = (x < 0 ? ~0ull : 0ull) + (old + (unsigned long long)x < old ? 1ull : 0ull);
+    if (hi) atomicAdd(&k.bBhi[t], hi);
+}
+
+__device__ __forceinline__ void deposit_birth(const Diode &dd, const BirthSink &k, int s, double z)
 {
     int j;
     double f;
     cic(z, dd.invdz, dd.N, j, f);
-    unsigned long long a = fixed_right(f);
-    gadd(&glb(dd.H[s])[j], (1ull << 32) - a);
-    gadd(&glb(dd.H[s])[j + 1], a);
+    const unsigned long long a = fixed_right(f), l = (1ull << 32) - a;
+    if (!k.bA) {
+        gadd(&glb(dd.H[s])[j], l);
+        gadd(&glb(dd.H[s])[j + 1], a);
+        return;
+    }
+    gadd(&glb(dd.Hb[s])[j], l);
+    gadd(&glb(dd.Hb[s])[j + 1], a);
+    const long long sg = s == SP_I ? 1 : -1;     // charge: ions minus electrons
+    tile_share(dd, k, j, sg * (long long)l);
+    tile_share(dd, k, j + 1, sg * (long long)a);
 }
 
 __device__ void write_particle(const GBuf &b, int i, double z, float vx, float vy, float vz, uint32_t id,
@@ -1462,7 +1495,8 @@ __device__ void write_particle(const GBuf &b, int i, double z, float vx, float v
 // S: the diode's counters as read at the start of the step's sources (LDS);
 // lost: ions absorbed this step.
 __device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, const DiodeState &S, int lost,
-                                        unsigned long long *keys, uint32_t step, int parity)
+                                        unsigned long long *keys, uint32_t step, int parity,
+                                        const BirthSink &sink)
 {
     const int tid = threadIdx.x;
     __shared__ int s_ne, s_q, s_R, s_bP, s_bE, s_bI, s_okP, s_okE, s_okI;
@@ -1520,12 +1554,12 @@ __device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, const D
             if (r < s_okP) {
                 write_particle(bP, s_bP + r, ev.z, ev.ve[0], ev.ve[1], ev.ve[2], ide,
                                next_candidate(step, dd.lam[0], be.z, be.w));
-                deposit_global(dd, SP_P, ev.z);
+                deposit_birth(dd, sink, SP_P, ev.z);
             }
             if (r < s_okI) {
                 write_particle(bI, s_bI + r, ev.z, ev.vi[0], ev.vi[1], ev.vi[2], idi,
                                next_candidate(step, dd.lam[1], bi.z, bi.w));
-                deposit_global(dd, SP_I, ev.z);
+                deposit_birth(dd, sink, SP_I, ev.z);
             }
         } else if (x < q + ne) {
             const int i = x - q;
@@ -1546,7 +1580,7 @@ __device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, const D
                     write_particle(bE, s_bE + i, -1.0, vx, vy, vz, idn, tc);
                 } else {
                     write_particle(bE, s_bE + i, z, vx, vy, vz, idn, tc);
-                    deposit_global(dd, SP_E, z);
+                    deposit_birth(dd, sink, SP_E, z);
                 }
             }
         } else {
@@ -1563,14 +1597,14 @@ __device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, const D
             if (q + r < s_okP) {
                 write_particle(bP, s_bP + q + r, z, (float)(dd.sig_e0 * a1), (float)(dd.sig_e0 * a2),
                                (float)(dd.sig_e0 * a3), ide, next_candidate(step, dd.lam[0], e1.z, e1.w));
-                deposit_global(dd, SP_P, z);
+                deposit_birth(dd, sink, SP_P, z);
             }
             bm32(i0.x, i0.y, a1, a2);
             bm32(i0.z, i0.w, a3, a4);
             if (q + r < s_okI) {
                 write_particle(bI, s_bI + q + r, z, (float)(dd.sig_i0 * a1), (float)(dd.sig_i0 * a2),
                                (float)(dd.sig_i0 * a3), idi, next_candidate(step, dd.lam[1], i1.z, i1.w));
-                deposit_global(dd, SP_I, z);
+                deposit_birth(dd, sink, SP_I, z);
             }
         }
     }
@@ -1596,7 +1630,7 @@ __device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, const D
 // copies and counters are read together, up front, so the chain of global
 // round trips is one load deep in the usual case.
 __device__ __forceinline__ void step_sources(const Diode &dd, DiodeState *st, unsigned long long *keys,
-                                             uint32_t step, int parity, RareTally *rt)
+                                             uint32_t step, int parity, RareTally *rt, const BirthSink &sink)
 {
     __shared__ DiodeState s_st;
     const int tid = threadIdx.x;
@@ -1616,7 +1650,7 @@ __device__ __forceinline__ void step_sources(const Diode &dd, DiodeState *st, un
     }
     __syncthreads();
     if (tid == 0) apply_tally(dd, *rt);
-    sources(dd, st, s_st, rt->ion_lost, keys, step, parity);
+    sources(dd, st, s_st, rt->ion_lost, keys, step, parity, sink);
 }
 
 __device__ __forceinline__ long long wave_incl_scan_i64(long long x)
@@ -1703,7 +1737,8 @@ __global__ __launch_bounds__(FT) void k_sources_field_lds(const Diode *__restric
     __shared__ RareTally rt;
     const uint32_t step = st->step;
 
-    if (mode == 0) step_sources(dd, st, reinterpret_cast<unsigned long long *>(nodes), step, parity, &rt);
+    if (mode == 0)
+        step_sources(dd, st, reinterpret_cast<unsigned long long *>(nodes), step, parity, &rt, BirthSink{});
     __syncthreads();
 
     const int N = dd.N;
@@ -1781,22 +1816,45 @@ __global__ __launch_bounds__(FT) void k_sources_field_lds(const Diode *__restric
 // ---------------------------------------------------------------------------
 // Large grids: the same step spread over tiles of FT nodes, so that the node
 // arrays move through many CUs instead of one.
-//   k_births       overflow rare items and births (one block per diode).
 //   k_field_agg    per tile: A_t = sum of rho over the tile, B_t = sum over the
-//                  tile's interior nodes of the in-tile inclusive prefix of rho.
+//                  tile's interior nodes of the in-tile inclusive prefix of
+//                  rho; with births (mode 0), one more block per diode runs
+//                  the overflow rare items and the births at the same time,
+//                  its deposits kept apart (Hb, bagg) because the tiles are
+//                  reading H meanwhile.
 //   k_field_solve  per tile: with P_t = sum_{u<t} A_u (= S1 before the tile),
 //                  Q_t = sum_{u<t} (n_u P_u + B_u) (= T before the tile) and
-//                  T_N from all tiles, the exact S1_j and T_j of its nodes and
-//                  of one halo node on each side, phi_j and E_j as in the
-//                  single-block kernel, and the node bookkeeping.
+//                  T_N from all tiles (births' shares added), the exact S1_j
+//                  and T_j of its nodes and of one halo node on each side,
+//                  phi_j and E_j as in the single-block kernel, and the node
+//                  bookkeeping.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FT) void k_births(const Diode *__restrict__ D, int parity)
+__device__ __forceinline__ void births_block(const Diode &dd, int parity)
 {
     extern __shared__ long long nodes[];
     __shared__ RareTally rt;
-    const Diode &dd = D[blockIdx.x];
+    __shared__ unsigned long long bA[MAX_TILES], bBlo[MAX_TILES], bBhi[MAX_TILES];
+    const int tid = threadIdx.x;
+    if (tid < MAX_TILES) {
+        bA[tid] = 0ull;
+        bBlo[tid] = 0ull;
+        bBhi[tid] = 0ull;
+    }
     DiodeState *st = dd.st;
-    step_sources(dd, st, reinterpret_cast<unsigned long long *>(nodes), st->step, parity, &rt);
+    // step_sources synchronises the block before the first deposit
+    step_sources(dd, st, reinterpret_cast<unsigned long long *>(nodes), st->step, parity, &rt,
+                 BirthSink{bA, bBlo, bBhi});
+    __syncthreads();
+    const int nt = (dd.N + 1 + FT - 1) / FT;
+    if (tid < nt) {
+        FieldAgg g;
+        g.A = (long long)bA[tid];
+        g.B_lo = bBlo[tid];
+        g.B_hi = (long long)bBhi[tid];
+        g.n = 0;
+        g.pad = 0;
+        dd.bagg[tid] = g;
+    }
 }
 
 __device__ __forceinline__ long long node_rho(const Diode &dd, int j)
@@ -1805,10 +1863,21 @@ __device__ __forceinline__ long long node_rho(const Diode &dd, int j)
     return (long long)(dd.H[SP_I][j] - dd.H[SP_P][j] - dd.H[SP_E][j]);
 }
 
-__global__ __launch_bounds__(FT) void k_field_agg(const Diode *__restrict__ D)
+__device__ __forceinline__ long long node_rho_births(const Diode &dd, int j)
+{
+    if (j < 1 || j > dd.N - 1) return 0;
+    return (long long)(dd.Hb[SP_I][j] - dd.Hb[SP_P][j] - dd.Hb[SP_E][j]);
+}
+
+// births: 1 with the births blocks (blockIdx.x == 0 of each diode), else 0
+__global__ __launch_bounds__(FT) void k_field_agg(const Diode *__restrict__ D, int births, int parity)
 {
     const Diode &dd = D[blockIdx.y];
-    const int t = blockIdx.x, nn = dd.N + 1;
+    if ((int)blockIdx.x < births) {
+        births_block(dd, parity);
+        return;
+    }
+    const int t = (int)blockIdx.x - births, nn = dd.N + 1;
     const int a = t * FT;
     if (a >= nn) return;
     __shared__ long long sh64[FW];
@@ -1852,31 +1921,46 @@ __global__ __launch_bounds__(FT) void k_field_solve(const Diode *__restrict__ D,
     __shared__ double ph[FT + 2];
     __shared__ long long s_P;
     __shared__ I128 s_Q, s_TN;
-    if (threadIdx.x == 0) {
-        long long P = 0, Pt = 0;
-        I128 Q = i128(0), TN = i128(0);
+    const int j = a + threadIdx.x;
+    // in flight during the combine below
+    const long long r = j < b ? node_rho(dd, j) + (mode == 0 ? node_rho_births(dd, j) : 0) : 0;
+    if (threadIdx.x < 64) {
+        // The first wave reads every tile's aggregates at once, one lane per
+        // tile (N <= 32767 gives at most 32 tiles), and combines them with
+        // wave scans: P_u = sum_{v<u} A_v, the sum of S1 over tile u
+        // s_u = n_u P_u + B_u, Q_t = sum_{u<t} s_u and T_N = sum_u s_u.
+        const int u = threadIdx.x;
         const int nt = min(ntiles, (nn + FT - 1) / FT);
-        for (int u = 0; u < nt; ++u) {
+        long long A = 0;
+        I128 Bu = i128(0);
+        int n = 0;
+        if (u < nt) {
             const FieldAgg g = dd.agg[u];
-            I128 Bu;
+            A = g.A;
             Bu.lo = g.B_lo;
             Bu.hi = g.B_hi;
-            // S1 summed over tile u: its n interior nodes each carry P_u, plus B_u
-            const I128 su = add(mul_small(i128(P), (unsigned)g.n), Bu);
-            if (u < t) Q = add(Q, su);
-            if (u == t) Pt = P;
-            TN = add(TN, su);
-            P += g.A;
+            n = g.n;
+            if (mode == 0) {
+                const FieldAgg gb = dd.bagg[u];
+                I128 bb;
+                bb.lo = gb.B_lo;
+                bb.hi = gb.B_hi;
+                A += gb.A;
+                Bu = add(Bu, bb);
+            }
         }
-        s_P = Pt;
-        s_Q = Q;
-        s_TN = TN;
+        const long long Pu = wave_incl_scan_i64(A) - A;
+        const I128 su = add(mul_small(i128(Pu), (unsigned)n), Bu);
+        const I128 incl = wave_incl_scan_i128(su);
+        if (u == t) {
+            s_P = Pu;
+            s_Q = add(incl, neg(su));
+        }
+        if (u == 63) s_TN = incl;
     }
     __syncthreads();
     const long long P = s_P;
     const I128 Q = s_Q, T_N = s_TN;
-    const int j = a + threadIdx.x;
-    const long long r = j < b ? node_rho(dd, j) : 0;
     long long Aloc;
     const long long S1 = P + block_scan_excl_i64(r, sh64, Aloc) + r;      // inclusive S1_j
     const bool interior = j >= 1 && j <= N - 1 && j < b;
@@ -1907,7 +1991,11 @@ __global__ __launch_bounds__(FT) void k_field_solve(const Diode *__restrict__ D,
         const int avg = st->avg_on;
 #pragma unroll
         for (int sp = 0; sp < NSP; ++sp) {
-            const long long h = (long long)dd.H[sp][j];
+            long long h = (long long)dd.H[sp][j];
+            if (mode == 0) {
+                h += (long long)dd.Hb[sp][j];
+                dd.Hb[sp][j] = 0ull;
+            }
             dd.Hlast[sp][j] = h;
             dd.H[sp][j] = 0ull;
             if (avg) dd.Hsum[sp][j] += h;
@@ -1977,8 +2065,8 @@ constexpr int FIELD_TILE_MIN = 8192;
 // Kernels picx_launch_sources_field enqueues for a step (timed graphs need it).
 extern "C" int picx_sources_field_kernels(int max_nodes, int mode)
 {
-    if (max_nodes <= FIELD_TILE_MIN) return 1;
-    return mode == 0 ? 3 : 2;
+    (void)mode;
+    return max_nodes <= FIELD_TILE_MIN ? 1 : 2;
 }
 
 extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
@@ -1991,8 +2079,8 @@ extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, i
         return hipGetLastError();
     }
     const int tiles = (max_nodes + FT - 1) / FT;
-    if (mode == 0) hipLaunchKernelGGL(k_births, dim3(nd), dim3(FT), keys, s, D, parity);
-    hipLaunchKernelGGL(k_field_agg, dim3(tiles, nd), dim3(FT), 0, s, D);
+    const int births = mode == 0 ? 1 : 0;
+    hipLaunchKernelGGL(k_field_agg, dim3(tiles + births, nd), dim3(FT), births ? keys : 0, s, D, births, parity);
     hipLaunchKernelGGL(k_field_solve, dim3(tiles, nd), dim3(FT), 0, s, D, S, mode, tiles);
     return hipGetLastError();
 }

@@ -246,6 +246,23 @@ def test_tiled_field_path_ragged(pic, O):
     assert restart_step_check(O, small, h, 4, d=1) == []
 
 
+def test_tiled_field_path_maximum_grid(pic, O):
+    """The largest grid the library accepts (32767 cells: 32 tiles of the
+    field solve, combined by one wave): load field and deposit, then restart
+    parity over steps with births.  The potential is checked against the
+    exact rational solve of the oracle's deposit, since the oracle's FP64
+    sweep rounds by ~1e-10 of the maximum at this size."""
+    _say("case: tiled field path, N = 32767")
+    cfg = presets.scaled(presets.tiny(), N=32767, L=5e-3 * 32767 / 256, n_load=131068, gamma_emit=3e22)
+    h = pic.Handle(cfg)
+    st, t = gpu_state(h)
+    assert deposit_matches(O, cfg, h, st) == []
+    s = oracle_from_gpu(O, cfg, st, t)
+    assert field_matches(O, cfg, h, s, exact=True) == []
+    probs = restart_step_check(O, cfg, h, 4, exact_field=True)
+    assert probs == [], "\n".join(probs[:20])
+
+
 def test_particles_outside_the_window(pic, O):
     """With no re-sort for 800 steps, electrons drift past the 160-cell margin
     of their run's LDS window and births sit unsorted at the end of the

@@ -2,7 +2,9 @@
 
 Poisson ("Model": potential from the charge density, Dirichlet electrodes
 phi(0) = 0, phi(L) = V; field from its gradient) is checked against closed
-forms (Laplace, uniform charge) and against scipy's banded solver.  The
+forms (Laplace, uniform charge), against scipy's banded solver and against
+an exact rational elimination (itself pinned by zero residual and a closed
+form), which also bounds the FP64 sweep's rounding on the largest grid.  The
 fixed-point CIC deposit is checked against exact rational arithmetic,
 its conservation and first-moment invariants, and permutation invariance.
 """
@@ -116,3 +118,54 @@ def test_deposit_wall_clamp(O):
     H = O.deposit(np.array([np.nextafter(L, 0)]), N, N / L)
     # z within an ulp below L lands on the last node
     assert H[N] + H[N - 1] == 2**32 and H[N] >= H[N - 1]
+
+
+def test_exact_solve_definition(O):
+    """The exact rational solve satisfies its difference equations with zero
+    residual, its boundary values, and the closed form of a uniform charge
+    (psi_j = c j (N - j) / 2), including the smallest grid."""
+    from fractions import Fraction
+    rng = np.random.default_rng(257)
+    for N in (2, 3, 257):
+        R = np.zeros(N + 1, dtype=np.int64)
+        R[1:N] = rng.integers(-2**40, 2**40, N - 1)
+        psi = O.solve_exact_psi(N, R)
+        assert psi[0] == 0 and psi[N] == 0
+        for j in range(1, N):
+            assert psi[j - 1] - 2 * psi[j] + psi[j + 1] == -int(R[j])
+    N, c = 101, 3 * 2**33 + 7
+    psi = O.solve_exact_psi(N, np.full(N + 1, c, dtype=np.int64))
+    assert all(psi[j] == Fraction(c * j * (N - j), 2) for j in range(N + 1))
+
+
+def test_exact_solve_agrees_with_fp64_sweep_on_small_grids(O):
+    rng = np.random.default_rng(5)
+    N, L, V, w0 = 257, 5e-3, 10.0, 1e9
+    dz = L / N
+    R = np.zeros(N + 1, dtype=np.int64)
+    R[1:N] = rng.integers(-2**36, 2**36, N - 1)
+    k = O.Q_E * w0 / (2.0**32 * dz)
+    phi = O.solve(N, dz, V, k * R.astype(np.float64))
+    ex = O.solve_exact(N, dz, V, R, w0)
+    assert ex[0] == 0.0 and ex[N] == V
+    assert np.max(np.abs(phi - ex)) < 1e-12 * np.max(np.abs(ex))
+
+
+def test_fp64_sweep_rounding_at_the_largest_grid(O):
+    """The oracle's FP64 Thomas sweep loses digits as the grid grows: on the
+    seeded load of the largest grid the library accepts (32767 cells) it
+    stays within 5e-10 of the maximum potential of the exact solution (about
+    1.3e-10 measured), so field comparisons there take the exact solve as
+    their reference."""
+    from paper_2605_07083_amd import presets
+    N = 32767
+    cfg = presets.scaled(presets.tiny(), N=N, L=5e-3 * N / 256, n_load=131068, gamma_emit=3e22)
+    s = O.Sim(cfg)
+    s.load()
+    H = [s.hist(sp).astype(np.int64) for sp in range(3)]
+    R = H[2] - H[0] - H[1]
+    R[0] = R[N] = 0
+    d = O.derive(cfg)
+    ex = O.solve_exact(N, d["dz"], cfg["V"], R, d["w0"])
+    err = np.max(np.abs(s.phi() - ex)) / np.max(np.abs(ex))
+    assert err < 5e-10
