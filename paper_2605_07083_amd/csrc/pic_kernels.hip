@@ -1141,6 +1141,19 @@ __device__ __forceinline__ void sort_window(const Diode &dd, const GBuf &b, int 
     wn = uni(min(min(nbins_of(dd.N) - 1, max(ja, jb) + DRIFT_B) - w0 + 1, WMAX + 1));
 }
 
+// The same window from the two positions.
+__device__ __forceinline__ void sort_window_z(const Diode &dd, double za, double zb, int &w0, int &wn)
+{
+    int ja, jb;
+    double f;
+    cic(za, dd.invdz, dd.N, ja, f);
+    cic(zb, dd.invdz, dd.N, jb, f);
+    ja >>= BIN_SHIFT;
+    jb >>= BIN_SHIFT;
+    w0 = uni(max(0, min(ja, jb) - DRIFT_B));
+    wn = uni(min(min(nbins_of(dd.N) - 1, max(ja, jb) + DRIFT_B) - w0 + 1, WMAX + 1));
+}
+
 // Cell counts of the live particles.  Each thread counts runs of equal cells
 // over its PPT consecutive slots and adds them to the block's LDS window.
 template <int PPT>
@@ -1168,6 +1181,10 @@ __global__ __launch_bounds__(NT) void k_sort_count(const Diode *__restrict__ D, 
         const int slot0 = (c - segbase) * CHUNK;
         int w0, wn;
         sort_window(dd, b, slot0, min(n, (run_end - segbase) * CHUNK) - 1, w0, wn);
+        // the next chunk's positions are in flight while a chunk is counted
+        double zn[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) zn[k] = b.z[slot0 + tid * PPT + k];
         for (int t = tid; t < wn; t += NT) cnt[t] = 0;
         lds_barrier();
         GLB int *gc = glb(dd.cell_cnt[s]);
@@ -1179,13 +1196,19 @@ __global__ __launch_bounds__(NT) void k_sort_count(const Diode *__restrict__ D, 
         };
         for (int cc_ = c; cc_ < run_end; ++cc_) {
             const int t0 = (cc_ - segbase) * CHUNK + tid * PPT;
+            double zc[PPT];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) zc[k] = zn[k];
+            if (cc_ + 1 < run_end) {
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) zn[k] = b.z[t0 + CHUNK + k];
+            }
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                const double z = b.z[t0 + k];
                 int j = -1;
-                if (t0 + k < n && z >= 0.0) {
+                if (t0 + k < n && zc[k] >= 0.0) {
                     double f;
-                    cic(z, dd.invdz, dd.N, j, f);
+                    cic(zc[k], dd.invdz, dd.N, j, f);
                     j >>= BIN_SHIFT;
                 }
                 wave_group_rank(j, add);
@@ -1249,33 +1272,75 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
     __shared__ uint32_t st_tc[CHUNK];
     __shared__ int st_dest[CHUNK];
     __shared__ u32x4 st_cold[CHUNK];
+    __shared__ double s_zw[2];          // positions of the chunk's first and last slot
     ChunkMap cm;
     build_chunk_map(S, nd, CHUNK, false, seg_end, cm, seg_n);
     const int tid = threadIdx.x;
     const int per_block = (cm.total + gridDim.x - 1) / gridDim.x;
     const int c_begin = blockIdx.x * per_block;
     const int c_end = min(cm.total, c_begin + per_block);
-    for (int c = c_begin; c < c_end;) {
-        const int seg = find_seg(seg_end, cm.nseg, c);
-        const int segbase = seg ? seg_end[seg - 1] : 0;
-        // one chunk per window here: ranks of the whole chunk must fit in registers
-        const int run_end = c + 1;
-        const int d = seg / NSP, s = seg - d * NSP;
-        const Diode &dd = D[d];
-        const GBuf src = gbuf(dd.buf[parity][s]), dst = gbuf(dd.buf[parity ^ 1][s]);
-        const int n = seg_n[seg];
-        const int slot0 = (c - segbase) * CHUNK;
-        int w0, wn;
-        sort_window(dd, src, slot0, min(n, (run_end - segbase) * CHUNK) - 1, w0, wn);
-        for (int t = tid; t < wn; t += NT) cnt[t] = 0;
-        lds_barrier();
-        GLB int *cur = glb(dd.cell_cnt[s]);
-        const int t0 = slot0 + tid * PPT;
-        int j[PPT], rank[PPT];
-        double z[PPT];
+    // A chunk's records are loaded one chunk ahead, into registers, so the
+    // loads of the next chunk are in flight while this one is ranked and
+    // written; the window comes from the chunk's own first and last slot.
+    double zq[PPT];
+    float vq[PPT];
+    u32x4 cq[PPT];
+    uint32_t tq[PPT];
+    auto fetch = [&](int cidx) {
+        const int sg = find_seg(seg_end, cm.nseg, cidx);
+        const int sb = sg ? seg_end[sg - 1] : 0;
+        const int dq = sg / NSP, sq = sg - dq * NSP;
+        const GBuf src = gbuf(D[dq].buf[parity][sq]);
+        const int nq = seg_n[sg];
+        const int t0 = (cidx - sb) * CHUNK + tid * PPT;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            z[k] = src.z[t0 + k];
+            zq[k] = -1.0;
+            if (t0 + k < nq) {
+                zq[k] = src.z[t0 + k];
+                vq[k] = src.vz[t0 + k];
+                cq[k] = *(const GLB u32x4 *)&src.cold[t0 + k];
+                tq[k] = src.tc[t0 + k];
+            }
+        }
+    };
+    if (c_begin < c_end) fetch(c_begin);
+    for (int c = c_begin; c < c_end; ++c) {
+        const int seg = find_seg(seg_end, cm.nseg, c);
+        const int segbase = seg ? seg_end[seg - 1] : 0;
+        const int d = seg / NSP, s = seg - d * NSP;
+        const Diode &dd = D[d];
+        const GBuf dst = gbuf(dd.buf[parity ^ 1][s]);
+        const int n = seg_n[seg];
+        const int slot0 = (c - segbase) * CHUNK;
+        const int t0 = slot0 + tid * PPT;
+        double z[PPT];
+        float vzr[PPT];
+        u32x4 cold[PPT];
+        uint32_t tcr[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            z[k] = zq[k];
+            vzr[k] = vq[k];
+            cold[k] = cq[k];
+            tcr[k] = tq[k];
+        }
+        if (c + 1 < c_end) fetch(c + 1);
+        const int lo = min(n, slot0 + CHUNK) - 1 - slot0;     // chunk offset of its last slot
+        if (tid == 0) s_zw[0] = z[0];
+        if (tid == lo / PPT) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                if (k == lo % PPT) s_zw[1] = z[k];
+        }
+        for (int t = tid; t < WMAX + 2; t += NT) cnt[t] = 0;
+        lds_barrier();
+        int w0, wn;
+        sort_window_z(dd, s_zw[0], s_zw[1], w0, wn);
+        GLB int *cur = glb(dd.cell_cnt[s]);
+        int j[PPT], rank[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
             j[k] = -1;
             if (t0 + k < n && z[k] >= 0.0) {
                 double f;
@@ -1327,9 +1392,9 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             if (j[k] < 0) continue;
-            const float vz = src.vz[t0 + k];
-            const u32x4 cr = *(const GLB u32x4 *)&src.cold[t0 + k];
-            const uint32_t tc = src.tc[t0 + k];
+            const float vz = vzr[k];
+            const u32x4 cr = cold[k];
+            const uint32_t tc = tcr[k];
             if (rank[k] >= 0) {
                 const int jl = j[k] - w0;
                 const int L = loc[jl] + rank[k];
@@ -1357,7 +1422,6 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
             dst.tc[dest] = st_tc[L];
         }
         lds_barrier();
-        c = run_end;
     }
 }
 
