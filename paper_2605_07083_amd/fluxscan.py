@@ -1,0 +1,156 @@
+"""Baseline emission-flux scan of the paper's benchmark diode.
+
+The eleven imposed fluxes of the paper's benchmark suite ("Benchmark cases";
+results in "Flux-scan results", Table 2 for the emitted-electron transport
+and Table 4 for the boundary energy terms) run as one batch of diodes on the
+paper's preset (10 cm helium gap, 40 V, elastic and charge-exchange
+collisions only).  Reported per flux: late-time averages of the backflow,
+net and anode fluxes, the backflow ratio and efficiencies, the boundary
+energy terms, the depth and position of the potential minimum in front of
+the cathode (time-averaged potential), and the backflow ratio's time series.
+
+Host orchestration only: the steps are the library's graph-replayed step,
+the averages come from pic_diagnostics over the tally snapshot ring and from
+the device's time-averaged potential.
+
+    python -m paper_2605_07083_amd.fluxscan --ppc 100 --steps 4500000 --out scan.json
+    python -m paper_2605_07083_amd.fluxscan --ppc 1000 --fluxes 7.0e19 7.25e19 --out transition.json
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import pic, presets
+
+FLUXES = (1.5e19, 2.0e19, 4.5e19, 5.0e19, 6.0e19, 7.0e19, 7.25e19, 7.5e19, 8.0e19, 1.0e20, 1.2e20)
+TALLY_PERIOD = 1000
+RING = 1024                   # snapshots the device keeps
+NEAR_CATHODE = 0.1            # fraction of the gap searched for the potential minimum
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def configs(ppc, fluxes=FLUXES):
+    """One diode per flux on the paper's preset, ppc particles per cell and
+    species (the paper loads 1000)."""
+    base = presets.paper()
+    return [presets.scaled(base, gamma_emit=float(g), diode=d, n_load=int(ppc) * base["N"],
+                           tally_period=TALLY_PERIOD) for d, g in enumerate(fluxes)]
+
+
+def check_windows(steps, window, chunk):
+    """The averaging window and the series' chunk are whole tally periods
+    that the snapshot ring still holds, and the window is whole chunks."""
+    if window <= 0 or chunk <= 0 or steps <= window:
+        raise ValueError("need 0 < window < steps and chunk > 0")
+    if window % TALLY_PERIOD or chunk % TALLY_PERIOD:
+        raise ValueError("window and chunk must be multiples of %d steps" % TALLY_PERIOD)
+    if window > RING * TALLY_PERIOD or chunk > RING * TALLY_PERIOD:
+        raise ValueError("window and chunk must be at most %d steps" % (RING * TALLY_PERIOD))
+    if window % chunk:
+        raise ValueError("window must be a multiple of chunk")
+
+
+def potential_minimum(cfg, phi):
+    """Depth (V, relative to the cathode) and position (m) of the lowest
+    potential within NEAR_CATHODE of the gap from the cathode."""
+    n = max(2, int(NEAR_CATHODE * cfg["N"]))
+    j = int(np.argmin(phi[:n + 1]))
+    return float(phi[j]), j * cfg["L"] / cfg["N"]
+
+
+def run(ppc=100, steps=4500000, window=1000000, chunk=250000, max_seconds=0.0, fluxes=FLUXES, tune_steps=256):
+    check_windows(steps, window, chunk)
+    cfgs = configs(ppc, fluxes)
+    h = pic.Handle(cfgs)
+    tuning = h.autotune(trial_steps=tune_steps)
+    step = h.diagnostics(0, 0)["step_end"]
+    pad = -step % chunk                       # the series starts on a chunk boundary
+    if pad:
+        h.step(pad)
+        step += pad
+    _log("fluxscan: %d diodes, %d particles per species each, schedule %s, from step %d"
+         % (len(cfgs), cfgs[0]["n_load"], {k: tuning[k] for k in ("ppt", "grid", "sort_period", "use_graph")},
+            step))
+    series = [[] for _ in cfgs]
+    averaging = False
+    t0 = time.time()
+    step0 = step
+    stopped_early = False
+    while step < steps:
+        if not averaging and steps - step <= window:
+            h.avg_control(-1, True)
+            averaging = True
+            avg_from = step
+        n = min(chunk, steps - step)
+        h.step(n)
+        h.sync()
+        step += n
+        for d in range(len(cfgs)):
+            g = h.diagnostics(d, n)
+            series[d].append([step, g["backflow_pct"], g["gamma_net"], float(np.sum(g["n_live"]))])
+        el = time.time() - t0
+        _log("fluxscan: step %d of %d, %.0f s, %.1f us per step; backflow %% %s"
+             % (step, steps, el, 1e6 * el / (step - step0),
+                " ".join("%.1f" % series[d][-1][1] for d in range(len(cfgs)))))
+        if max_seconds and el > max_seconds and step < steps:
+            stopped_early = True
+            break
+    wall = time.time() - t0
+    # late-time window: the requested one, or what the run reached
+    win = window if not stopped_early else min(window, step - step0)
+    out = {"ppc": ppc, "steps": step, "steps_requested": steps, "window": win, "stopped_early": stopped_early,
+           "wall_s": wall, "schedule": tuning, "diodes": []}
+    for d, cfg in enumerate(cfgs):
+        g = h.diagnostics(d, win)
+        rec = {k: g[k] for k in pic._DIAG_SCALARS + pic._DIAG_SCALARS2}
+        rec["q_back_em_cath"] = float(g["q_abs"][1][0])
+        rec["q_back_p_cath"] = float(g["q_abs"][0][0])
+        rec["q_ion_cath"] = float(g["q_abs"][2][0])
+        rec["n_live"] = [float(x) for x in g["n_live"]]
+        if averaging:
+            phi = h.fields(d, time_avg=True)["phi"]
+            rec["phi_min_V"], rec["phi_min_z_m"] = potential_minimum(cfg, phi)
+            rec["avg_from_step"] = avg_from
+        rec["series"] = series[d]
+        out["diodes"].append(rec)
+    h.close()
+    return out
+
+
+def table(res):
+    rows = ["| Γ_emit (1e19) | Γ_ref | Γ_net | Γ_anode | backflow % | q_cool1 | q_cool2 | q_anode1 | φ_min (V) |",
+            "|---|---|---|---|---|---|---|---|---|"]
+    for r in res["diodes"]:
+        rows.append("| %.2f | %.2f | %.2f | %.2f | %.2f | %.2f | %.2f | %.2f | %s |" % (
+            r["gamma_emit"] / 1e19, r["gamma_ref"] / 1e19, r["gamma_net"] / 1e19, r["gamma_anode"] / 1e19,
+            r["backflow_pct"], r["q_cool1"], r["q_cool2"], r["q_anode1"],
+            "%.3f" % r["phi_min_V"] if "phi_min_V" in r else "—"))
+    return "\n".join(rows)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--ppc", type=int, default=100, help="particles per cell and species (paper: 1000)")
+    ap.add_argument("--steps", type=int, default=4500000)
+    ap.add_argument("--window", type=int, default=1000000, help="late-time averaging window (steps)")
+    ap.add_argument("--chunk", type=int, default=250000, help="steps per series point")
+    ap.add_argument("--max-seconds", type=float, default=0.0, help="stop stepping after this wall time")
+    ap.add_argument("--fluxes", type=float, nargs="+", default=list(FLUXES), help="imposed fluxes (m^-2 s^-1)")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    res = run(a.ppc, a.steps, a.window, a.chunk, a.max_seconds, fluxes=a.fluxes)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+    print(table(res))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

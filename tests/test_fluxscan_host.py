@@ -1,0 +1,47 @@
+"""Host logic of the paper-preset flux scan (no GPU): the batch it builds,
+its window checks and the potential-minimum search."""
+import numpy as np
+import pytest
+
+from paper_2605_07083_amd import fluxscan, presets
+
+
+def test_batch_is_the_papers_suite_on_its_preset():
+    cfgs = fluxscan.configs(100)
+    # the benchmark suite's eleven imposed fluxes ("Benchmark cases")
+    assert [c["gamma_emit"] for c in cfgs] == [1.5e19, 2.0e19, 4.5e19, 5.0e19, 6.0e19, 7.0e19, 7.25e19,
+                                               7.5e19, 8.0e19, 1.0e20, 1.2e20]
+    base = presets.paper()
+    for d, c in enumerate(cfgs):
+        assert c["diode"] == d and c["n_load"] == 100 * base["N"]
+        for k in ("L", "N", "V", "n0", "Te0", "Ti0", "Tc", "ng", "Tne", "Tni", "dt", "channels", "seed"):
+            assert c[k] == base[k], k
+    # elastic and charge exchange only
+    assert base["channels"] == presets.CH_EEL | presets.CH_CX
+
+
+@pytest.mark.parametrize("steps,window,chunk", [
+    (4500000, 0, 250000), (1000000, 1000000, 250000), (4500000, 1000500, 250000),
+    (4500000, 2000000, 250000), (4500000, 1000000, 300000)])
+def test_bad_windows_rejected(steps, window, chunk):
+    with pytest.raises(ValueError):
+        fluxscan.check_windows(steps, window, chunk)
+
+
+def test_good_windows_accepted():
+    fluxscan.check_windows(4500000, 1000000, 250000)
+    fluxscan.check_windows(20000, 4000, 2000)
+
+
+def test_potential_minimum_near_cathode():
+    cfg = presets.paper()
+    N, L = cfg["N"], cfg["L"]
+    z = np.arange(N + 1) * L / N
+    # a dip of -1.5 V at 2 mm on the vacuum ramp; a deeper value beyond the
+    # searched tenth of the gap is ignored
+    phi = cfg["V"] * z / L - 1.5 * np.exp(-((z - 2e-3) / 5e-4) ** 2)
+    phi[N // 2] = -5.0
+    depth, pos = fluxscan.potential_minimum(cfg, phi)
+    assert pos == pytest.approx(2e-3, abs=2 * L / N)
+    assert depth == pytest.approx(phi[int(round(2e-3 / (L / N)))], abs=0.01)
+    assert depth < 0
