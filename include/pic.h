@@ -225,6 +225,25 @@ int pic_get_hist(pic_handle *h, int diode, int species, int64_t *out);
 /* Field at the nodes used by the next push (N+1 doubles).  Synchronises. */
 int pic_get_efield(pic_handle *h, int diode, double *out);
 
+/* Phase-space histogram of one species of one diode (the kinetic diagnostics
+ * of "Phase-space and velocity-distribution characteristics": (z, v_z)
+ * phase space, and by summing rows, the gap-integrated and the regional axial
+ * velocity distributions).  Adds to dev_out (device memory, caller-owned and
+ * caller-cleared, nz rows of nv + 2 uint64, row-major) the number of live
+ * particles in each bin as they stand after all work enqueued so far:
+ *   row    iz = min(nz - 1, floor(z * (nz / L)))
+ *   column with x = (v_z - vmin) * (nv / (vmax - vmin)), both factors in FP64:
+ *          0 if x < 0, 1 + floor(x) if 0 <= x < nv, nv + 1 if x >= nv.
+ * v_z is the stored leapfrog velocity (m/s, half a step behind z).  Species
+ * 0 plasma electrons, 1 emitted electrons, 2 ions.  Requires nz >= 1,
+ * nv >= 1, nz * (nv + 2) <= PIC_PHASE_MAX_BINS and finite vmin < vmax
+ * (else PIC_EINVAL).  Enqueued on the handle's stream; does not synchronise.
+ * Calls that add into one buffer accumulate (a late-time average is a sum of
+ * samples). */
+#define PIC_PHASE_MAX_BINS 32768
+int pic_phase_space(pic_handle *h, int diode, int species, int nz, int nv, double vmin, double vmax,
+                    uint64_t *dev_out);
+
 /* Live particles of one species, sorted by id, into host arrays of capacity
  * cap; *n_out receives the count (PIC_ENOSPACE if cap is too small).  Any
  * array may be NULL.  tc is the step at which the particle is next a

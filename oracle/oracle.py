@@ -205,6 +205,27 @@ def solve_exact_psi(N, R):
     return psi
 
 
+def phase_space(z, vz, L, nz, nv, vmin, vmax):
+    """Counts of particles per (z, v_z) bin (the kinetic diagnostics of
+    "Phase-space and velocity-distribution characteristics"), in FP64: row
+    min(nz - 1, floor(z nz / L)); with x = (v_z - vmin) nv / (vmax - vmin),
+    column 0 below vmin, 1 + floor(x) inside, nv + 1 at or above vmax.
+    Holes (z < 0) are skipped."""
+    z = np.asarray(z, dtype=np.float64)
+    v = np.asarray(vz, dtype=np.float64)
+    live = z >= 0.0
+    z, v = z[live], v[live]
+    sz = nz / L
+    sv = nv / (vmax - vmin)
+    iz = np.minimum(nz - 1, np.floor(z * sz).astype(np.int64))
+    x = (v - vmin) * sv
+    inside = 1 + np.floor(np.clip(x, 0.0, nv - 1)).astype(np.int64)
+    iv = np.where(x >= nv, nv + 1, np.where(x >= 0.0, inside, 0))
+    H = np.zeros((nz, nv + 2), dtype=np.int64)
+    np.add.at(H, (iz, iv), 1)
+    return H
+
+
 def efield(N, dz, phi):
     phi = np.ascontiguousarray(phi, dtype=np.float64)
     E = np.zeros(N + 1, dtype=np.float64)

@@ -29,6 +29,9 @@ extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int n
 extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
                                                 int parity, hipStream_t s);
 extern "C" hipError_t picx_prepare(void);
+extern "C" hipError_t picx_launch_phase_hist(const Diode *D, const DiodeState *S, int d, int s, int parity, int nz,
+                                             int nv, double sz, double vmin, double sv, unsigned long long *out,
+                                             int blocks, hipStream_t st);
 extern "C" int picx_sources_field_kernels(int max_nodes, int mode);
 extern "C" hipError_t picx_launch_profile_load(const Diode *D, const double *dens, int rows, int nd, int max_cells,
                                                hipStream_t s);
@@ -806,6 +809,26 @@ int pic_get_hist(pic_handle *h, int diode, int species, int64_t *out)
     HIP_TRY(hipStreamSynchronize(h->stream));
     HIP_TRY(hipMemcpy(out, h->hD[diode].Hlast[species], (h->cfg[diode].N + 1) * sizeof(int64_t),
                       hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+static_assert(PIC_PHASE_MAX_BINS == PHASE_MAX_BINS, "phase-space bin limit");
+
+int pic_phase_space(pic_handle *h, int diode, int species, int nz, int nv, double vmin, double vmax,
+                    uint64_t *dev_out)
+{
+    if (!h || !dev_out || diode < 0 || diode >= h->nd || species < 0 || species >= NSP)
+        return fail(PIC_EINVAL, "bad arguments");
+    if (nz < 1 || nv < 1 || (int64_t)nz * (nv + 2) > PIC_PHASE_MAX_BINS)
+        return fail(PIC_EINVAL, "need nz >= 1, nv >= 1 and nz * (nv + 2) <= PIC_PHASE_MAX_BINS");
+    if (!std::isfinite(vmin) || !std::isfinite(vmax) || !(vmax > vmin))
+        return fail(PIC_EINVAL, "need finite vmin < vmax");
+    const double sz = (double)nz / h->cfg[diode].L;
+    const double sv = (double)nv / (vmax - vmin);
+    const int64_t cap = h->der[diode].capacity[species];
+    const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (cap + 4095) / 4096));
+    HIP_TRY(picx_launch_phase_hist(h->dD, h->dS, diode, species, h->parity, nz, nv, sz, vmin, sv,
+                                   reinterpret_cast<unsigned long long *>(dev_out), blocks, h->stream));
     return PIC_OK;
 }
 

@@ -28,6 +28,7 @@ constexpr uint32_t NEVER = 0xFFFFFFFFu;
 constexpr int RING = 1024;           // tally snapshots kept per diode
 constexpr int IZQ_CAP = 4096;        // ionisation events per diode per step
 constexpr int MAX_DIODES = 256;
+constexpr int PHASE_MAX_BINS = 32768;   // LDS counts of the phase-space histogram (128 KB)
 
 // sticky device error bits
 constexpr uint32_t ERR_CAPACITY = 1u;

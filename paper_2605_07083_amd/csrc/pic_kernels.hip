@@ -1094,6 +1094,53 @@ __global__ __launch_bounds__(256) void k_profile_clear(const Diode *__restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Phase-space histogram ("Phase-space and velocity-distribution
+// characteristics"): live particles of one species of one diode counted per
+// (z, v_z) bin.  Row iz = min(nz - 1, floor(z sz)), sz = nz / L; with
+// x = (v_z - vmin) sv, sv = nv / (vmax - vmin): column 0 for x < 0, 1 + floor(x)
+// for 0 <= x < nv, nv + 1 for x >= nv.  Each block counts a contiguous slot
+// range (a narrow range of cells once sorted) in LDS and adds its nonzero bins
+// to the caller's uint64 counts.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_phase_hist(const Diode *__restrict__ D, const DiodeState *__restrict__ S,
+                                                    int d, int s, int parity, int nz, int nv, double sz, double vmin,
+                                                    double sv, unsigned long long *__restrict__ out)
+{
+    extern __shared__ uint32_t ph_hist[];
+    const int W = nv + 2, nb = nz * W, tid = threadIdx.x;
+    for (int i = tid; i < nb; i += 256) ph_hist[i] = 0u;
+    const Diode &dd = D[d];
+    const GBuf b = gbuf(dd.buf[parity][s]);
+    const int n = S[d].n[s];
+    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int i0 = (int)blockIdx.x * per, i1 = min(n, i0 + per);
+    __syncthreads();
+    for (int i = i0 + tid; i < i1; i += 256) {
+        const double z = b.z[i];
+        if (!(z >= 0.0)) continue;                     // hole
+        const int iz = min(nz - 1, (int)(z * sz));
+        const double x = ((double)b.vz[i] - vmin) * sv;
+        const int iv = x >= (double)nv ? nv + 1 : (x >= 0.0 ? 1 + (int)x : 0);
+        atomicAdd(&ph_hist[iz * W + iv], 1u);
+    }
+    __syncthreads();
+    for (int i = tid; i < nb; i += 256) {
+        const uint32_t c = ph_hist[i];
+        if (c) atomicAdd(&out[i], (unsigned long long)c);
+    }
+}
+
+extern "C" hipError_t picx_launch_phase_hist(const Diode *D, const DiodeState *S, int d, int s, int parity, int nz,
+                                             int nv, double sz, double vmin, double sv, unsigned long long *out,
+                                             int blocks, hipStream_t st)
+{
+    const size_t lds = (size_t)nz * (nv + 2) * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_phase_hist, dim3(blocks), dim3(256), lds, st, D, S, d, s, parity, nz, nv, sz, vmin, sv,
+                       out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Re-sort by bins of 32 cells: count -> scan -> scatter -> finalize (compacts
 // holes too).  Bins rather than cells: the LDS windows only need each run of
 // chunks confined to a narrow range of cells, and with electrons drifting
@@ -2162,6 +2209,9 @@ extern "C" hipError_t picx_launch_sort(const Diode *D, DiodeState *S, int nd, in
 
 extern "C" hipError_t picx_prepare(void)
 {
-    return hipFuncSetAttribute((const void *)k_sources_field_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)LDS_FIELD_BYTES);
+    hipError_t e = hipFuncSetAttribute((const void *)k_sources_field_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)LDS_FIELD_BYTES);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_phase_hist, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(PHASE_MAX_BINS * sizeof(uint32_t)));
 }

@@ -15,6 +15,7 @@ the device's time-averaged potential.
 
     python -m paper_2605_07083_amd.fluxscan --ppc 100 --steps 4500000 --out scan.json
     python -m paper_2605_07083_amd.fluxscan --ppc 1000 --fluxes 7.0e19 7.25e19 --out transition.json
+    python -m paper_2605_07083_amd.fluxscan --ppc 100 --sensitivity --out sensitivity.json
 """
 import argparse
 import json
@@ -43,6 +44,36 @@ def configs(ppc, fluxes=FLUXES):
                            tally_period=TALLY_PERIOD) for d, g in enumerate(fluxes)]
 
 
+# The paper's selected sensitivity cases ("Selected sensitivity to collisional
+# modeling details", Table 3, cases 1-7): label, flux, changes to the preset.
+SENSITIVITY = (
+    ("excitation on", 1.5e19, {"exc": True}),
+    ("excitation on", 4.5e19, {"exc": True}),
+    ("excitation on", 5.0e19, {"exc": True}),
+    ("excitation on", 8.0e19, {"exc": True}),
+    ("excitation on", 1.0e20, {"exc": True}),
+    ("electron-side neutral target 1740 K", 7.0e19, {"Tne_K": 1740.0}),
+    ("charge exchange off", 1.0e20, {"cx": False}),
+)
+
+
+def sensitivity_configs(ppc):
+    base = presets.paper()
+    out = []
+    for d, (label, g, ch) in enumerate(SENSITIVITY):
+        kw = dict(gamma_emit=float(g), diode=d, n_load=int(ppc) * base["N"], tally_period=TALLY_PERIOD)
+        channels = base["channels"]
+        if ch.get("exc"):
+            channels |= presets.CH_EXC
+        if ch.get("cx") is False:
+            channels &= ~presets.CH_CX
+        kw["channels"] = channels
+        if "Tne_K" in ch:
+            kw["Tne"] = ch["Tne_K"] * presets.KB_OVER_E
+        out.append(presets.scaled(base, **kw))
+    return out
+
+
 def check_windows(steps, window, chunk):
     """The averaging window and the series' chunk are whole tally periods
     that the snapshot ring still holds, and the window is whole chunks."""
@@ -64,9 +95,11 @@ def potential_minimum(cfg, phi):
     return float(phi[j]), j * cfg["L"] / cfg["N"]
 
 
-def run(ppc=100, steps=4500000, window=1000000, chunk=250000, max_seconds=0.0, fluxes=FLUXES, tune_steps=256):
+def run(ppc=100, steps=4500000, window=1000000, chunk=250000, max_seconds=0.0, fluxes=FLUXES, tune_steps=256,
+        cfgs=None, labels=None):
     check_windows(steps, window, chunk)
-    cfgs = configs(ppc, fluxes)
+    if cfgs is None:
+        cfgs = configs(ppc, fluxes)
     h = pic.Handle(cfgs)
     tuning = h.autotune(trial_steps=tune_steps)
     step = h.diagnostics(0, 0)["step_end"]
@@ -109,6 +142,9 @@ def run(ppc=100, steps=4500000, window=1000000, chunk=250000, max_seconds=0.0, f
     for d, cfg in enumerate(cfgs):
         g = h.diagnostics(d, win)
         rec = {k: g[k] for k in pic._DIAG_SCALARS + pic._DIAG_SCALARS2}
+        rec["label"] = labels[d] if labels else "baseline"
+        rec["channels"] = cfg["channels"]
+        rec["Tne_eV"] = cfg["Tne"]
         rec["q_back_em_cath"] = float(g["q_abs"][1][0])
         rec["q_back_p_cath"] = float(g["q_abs"][0][0])
         rec["q_ion_cath"] = float(g["q_abs"][2][0])
@@ -124,11 +160,11 @@ def run(ppc=100, steps=4500000, window=1000000, chunk=250000, max_seconds=0.0, f
 
 
 def table(res):
-    rows = ["| Γ_emit (1e19) | Γ_ref | Γ_net | Γ_anode | backflow % | q_cool1 | q_cool2 | q_anode1 | φ_min (V) |",
-            "|---|---|---|---|---|---|---|---|---|"]
+    rows = ["| case | Γ_emit (1e19) | Γ_ref | Γ_net | Γ_anode | backflow % | q_cool1 | q_cool2 | q_anode1 | φ_min (V) |",
+            "|---|---|---|---|---|---|---|---|---|---|"]
     for r in res["diodes"]:
-        rows.append("| %.2f | %.2f | %.2f | %.2f | %.2f | %.2f | %.2f | %.2f | %s |" % (
-            r["gamma_emit"] / 1e19, r["gamma_ref"] / 1e19, r["gamma_net"] / 1e19, r["gamma_anode"] / 1e19,
+        rows.append("| %s | %.2f | %.2f | %.2f | %.2f | %.2f | %.2f | %.2f | %.2f | %s |" % (
+            r["label"], r["gamma_emit"] / 1e19, r["gamma_ref"] / 1e19, r["gamma_net"] / 1e19, r["gamma_anode"] / 1e19,
             r["backflow_pct"], r["q_cool1"], r["q_cool2"], r["q_anode1"],
             "%.3f" % r["phi_min_V"] if "phi_min_V" in r else "—"))
     return "\n".join(rows)
@@ -142,9 +178,14 @@ def main(argv=None):
     ap.add_argument("--chunk", type=int, default=250000, help="steps per series point")
     ap.add_argument("--max-seconds", type=float, default=0.0, help="stop stepping after this wall time")
     ap.add_argument("--fluxes", type=float, nargs="+", default=list(FLUXES), help="imposed fluxes (m^-2 s^-1)")
+    ap.add_argument("--sensitivity", action="store_true", help="the paper's sensitivity cases instead of the scan")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    res = run(a.ppc, a.steps, a.window, a.chunk, a.max_seconds, fluxes=a.fluxes)
+    if a.sensitivity:
+        res = run(a.ppc, a.steps, a.window, a.chunk, a.max_seconds, cfgs=sensitivity_configs(a.ppc),
+                  labels=[c[0] for c in SENSITIVITY])
+    else:
+        res = run(a.ppc, a.steps, a.window, a.chunk, a.max_seconds, fluxes=a.fluxes)
     if a.out:
         with open(a.out, "w") as f:
             json.dump(res, f, indent=1)

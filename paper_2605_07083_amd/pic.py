@@ -66,7 +66,7 @@ class PicDerived(C.Structure):
 
 
 SYMBOLS = ["pic_derive", "pic_workspace_size", "pic_init", "pic_init_from_profiles", "pic_init_from_state", "pic_step", "pic_sync", "pic_get_tally",
-           "pic_diagnostics", "pic_get_fields", "pic_avg_reset", "pic_avg_control", "pic_get_hist", "pic_get_efield",
+           "pic_diagnostics", "pic_get_fields", "pic_avg_reset", "pic_avg_control", "pic_get_hist", "pic_get_efield", "pic_phase_space",
            "pic_get_particles", "pic_set_particles", "pic_set_counters", "pic_refield",
            "pic_step_timed", "pic_set_tuning", "pic_get_tuning", "pic_autotune", "pic_steady_state", "pic_steady_from_series", "pic_checkpoint_size", "pic_save", "pic_load", "pic_last_error",
            "pic_destroy"]
@@ -98,6 +98,7 @@ def lib():
         "pic_avg_control": ([P, i, i], i),
         "pic_get_hist": ([P, i, i, P], i),
         "pic_get_efield": ([P, i, P], i),
+        "pic_phase_space": ([P, i, i, i, i, d, d, P], i),
         "pic_get_particles": ([P, i, i, i64, C.POINTER(i64), P, P, P, P, P, P], i),
         "pic_set_particles": ([P, i, i, i64, P, P, P, P, P, P], i),
         "pic_set_counters": ([P, i, i64, C.c_uint32], i),
@@ -299,6 +300,21 @@ class Handle:
         H = np.zeros(self.cfgs[d]["N"] + 1, np.int64)
         _check(lib().pic_get_hist(self.h, d, sp, _ptr(H)))
         return H
+
+    def phase_space(self, d, sp, nz, nv, vmin, vmax, out=None):
+        """(z, v_z) counts of species sp of diode d, nz rows of nv + 2 columns
+        (under- and overflow of v_z at the ends); added to `out` (a device
+        int64 tensor of that shape) when given, else to a new zeroed one.
+        Stream-ordered: read it after sync()."""
+        import torch
+        if out is None:
+            with torch.cuda.stream(self.stream):
+                out = torch.zeros((nz, nv + 2), dtype=torch.int64, device=self.device)
+        if out.dtype != torch.int64 or tuple(out.shape) != (nz, nv + 2) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int64 tensor of shape (nz, nv + 2)")
+        _check(lib().pic_phase_space(self.h, int(d), int(sp), int(nz), int(nv), float(vmin), float(vmax),
+                                     C.c_void_p(out.data_ptr())))
+        return out
 
     def efield(self, d=0):
         E = np.zeros(self.cfgs[d]["N"] + 1)

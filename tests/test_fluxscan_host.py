@@ -45,3 +45,17 @@ def test_potential_minimum_near_cathode():
     assert pos == pytest.approx(2e-3, abs=2 * L / N)
     assert depth == pytest.approx(phi[int(round(2e-3 / (L / N)))], abs=0.01)
     assert depth < 0
+
+
+def test_sensitivity_cases_follow_table3():
+    cfgs = fluxscan.sensitivity_configs(100)
+    base = presets.paper()
+    assert [c["gamma_emit"] for c in cfgs] == [1.5e19, 4.5e19, 5.0e19, 8.0e19, 1.0e20, 7.0e19, 1.0e20]
+    exc = [bool(c["channels"] & presets.CH_EXC) for c in cfgs]
+    cx = [bool(c["channels"] & presets.CH_CX) for c in cfgs]
+    assert exc == [True] * 5 + [False] * 2
+    assert cx == [True] * 6 + [False]
+    assert all(c["channels"] & presets.CH_EEL for c in cfgs)
+    assert cfgs[5]["Tne"] == pytest.approx(1740.0 * presets.KB_OVER_E)
+    assert all(c["Tne"] == base["Tne"] for i, c in enumerate(cfgs) if i != 5)
+    assert [c["diode"] for c in cfgs] == list(range(7))

@@ -127,6 +127,42 @@ def test_large_scale_parity(pic, O):
     h.step(3)
     probs = restart_step_check(O, cfg, h, 1)
     assert probs == [], "\n".join(probs[:20])
+    _say("  phase space of the plasma electrons, all 16.4M")
+    out = h.phase_space(0, 0, 64, 100, -4e6, 4e6)
+    h.sync()
+    p = h.particles(0, 0)
+    assert np.array_equal(out.cpu().numpy(), O.phase_space(p["z"], p["vz"], cfg["L"], 64, 100, -4e6, 4e6))
+
+
+def test_phase_space_matches_oracle(pic, O):
+    """(z, v_z) counts of every species against the oracle's on the GPU's own
+    particles, bit for bit, with wide and narrow velocity ranges (the under-
+    and overflow columns); a second call into the same buffer accumulates;
+    bad arguments are rejected."""
+    cfg = presets.scaled(presets.tiny(), gamma_emit=1e21, Te0=10.0, ng=3.2e22)
+    _say("case: phase space, tiny diode after 60 steps")
+    h = pic.Handle(cfg)
+    h.step(60)
+    cases = [(0, 16, 40, -4e6, 4e6), (1, 16, 40, -4e6, 4e6), (2, 16, 40, -3e4, 3e4),
+             (0, 7, 9, -1e5, 2e5), (2, 1, 1, -1.0, 1.0), (0, 256, 126, -4e6, 4e6)]
+    for sp, nz, nv, lo, hi in cases:
+        out = h.phase_space(0, sp, nz, nv, lo, hi)
+        h.sync()
+        p = h.particles(0, sp)
+        ref = O.phase_space(p["z"], p["vz"], cfg["L"], nz, nv, lo, hi)
+        g = out.cpu().numpy()
+        assert np.array_equal(g, ref), (sp, nz, nv)
+        assert g.sum() == np.count_nonzero(p["z"] >= 0) > 0
+        h.phase_space(0, sp, nz, nv, lo, hi, out=out)
+        h.sync()
+        assert np.array_equal(out.cpu().numpy(), 2 * ref)
+    # the narrow ranges put counts in the under- and overflow columns
+    ref = O.phase_space(h.particles(0, 0)["z"], h.particles(0, 0)["vz"], cfg["L"], 7, 9, -1e5, 2e5)
+    assert ref[:, 0].sum() > 0 and ref[:, -1].sum() > 0
+    for bad in [(0, 0, 200, 200, -1.0, 1.0), (0, 0, 4, 4, 1.0, 1.0), (0, 3, 4, 4, -1.0, 1.0),
+                (1, 0, 4, 4, -1.0, 1.0), (0, 0, 0, 4, -1.0, 1.0), (0, 0, 4, 4, float("nan"), 1.0)]:
+        with pytest.raises(pic.PicError):
+            h.phase_space(*bad)
 
 
 def test_edge_cases(pic, O):
