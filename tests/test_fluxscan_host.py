@@ -59,3 +59,28 @@ def test_sensitivity_cases_follow_table3():
     assert cfgs[5]["Tne"] == pytest.approx(1740.0 * presets.KB_OVER_E)
     assert all(c["Tne"] == base["Tne"] for i, c in enumerate(cfgs) if i != 5)
     assert [c["diode"] for c in cfgs] == list(range(7))
+
+
+def test_kinetic_summary_of_a_maxwellian():
+    """Counts drawn from the T_e0 Maxwellian give a small distance from it,
+    the Maxwellian's slow share and half the electrons moving toward the
+    cathode; a shifted beam is far from it."""
+    from math import erf, sqrt
+    rng = np.random.default_rng(3)
+    nz, nv, vmax = fluxscan.PHASE_NZ, fluxscan.PHASE_NV, fluxscan.PHASE_VMAX
+    edges = np.linspace(-vmax, vmax, nv + 1)
+    ph = np.zeros((2, nz, nv + 2))
+    for r in range(nz):
+        x = rng.normal(0.0, 1.0, 4000)
+        ph[0, r, 1:nv + 1] = np.histogram(x, edges)[0]
+    ph[1, :5, 1 + nv // 2 + 30] = 100.0            # a few emitted electrons at +3 v_te near the cathode
+    k = fluxscan.kinetic_summary(ph)
+    g = k["gap"]
+    assert g["l1_from_maxwellian"] < 0.05
+    assert g["slow_share"] == pytest.approx(erf(0.2 / sqrt(2.0)), abs=0.01)
+    assert g["toward_cathode"] == pytest.approx(0.5, abs=0.01)
+    assert len(k["regions"]) == nz // fluxscan.REGION_ROWS
+    assert k["regions"][0]["emitted_share"] > 0 and k["regions"][-1]["emitted_share"] == 0
+    beam = np.zeros_like(ph)
+    beam[0, :, 1 + nv // 2 + 40] = 1.0
+    assert fluxscan.kinetic_summary(beam)["gap"]["l1_from_maxwellian"] > 0.9
