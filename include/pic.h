@@ -236,8 +236,8 @@ int pic_get_efield(pic_handle *h, int diode, double *out);
  *          0 if x < 0, 1 + floor(x) if 0 <= x < nv, nv + 1 if x >= nv.
  * v_z is the stored leapfrog velocity (m/s, half a step behind z).  Species
  * 0 plasma electrons, 1 emitted electrons, 2 ions.  Requires nz >= 1,
- * nv >= 1, nz * (nv + 2) <= PIC_PHASE_MAX_BINS and finite vmin < vmax
- * (else PIC_EINVAL).  Enqueued on the handle's stream; does not synchronise.
+ * nv >= 1, nz * (nv + 2) <= PIC_PHASE_MAX_BINS, finite vmin < vmax and
+ * dev_out in device memory of the handle's GPU (else PIC_EINVAL).  Enqueued on the handle's stream; does not synchronise.
  * Calls that add into one buffer accumulate (a late-time average is a sum of
  * samples). */
 #define PIC_PHASE_MAX_BINS 32768

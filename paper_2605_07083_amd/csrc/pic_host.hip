@@ -814,6 +814,17 @@ int pic_get_hist(pic_handle *h, int diode, int species, int64_t *out)
 
 static_assert(PIC_PHASE_MAX_BINS == PHASE_MAX_BINS, "phase-space bin limit");
 
+// p is device memory on the GPU that holds ref (the handle's workspace).
+static bool device_memory_beside(const void *p, const void *ref)
+{
+    hipPointerAttribute_t a{}, b{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess || hipPointerGetAttributes(&b, ref) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice && a.device == b.device;
+}
+
 int pic_phase_space(pic_handle *h, int diode, int species, int nz, int nv, double vmin, double vmax,
                     uint64_t *dev_out)
 {
@@ -823,6 +834,8 @@ int pic_phase_space(pic_handle *h, int diode, int species, int nz, int nv, doubl
         return fail(PIC_EINVAL, "need nz >= 1, nv >= 1 and nz * (nv + 2) <= PIC_PHASE_MAX_BINS");
     if (!std::isfinite(vmin) || !std::isfinite(vmax) || !(vmax > vmin))
         return fail(PIC_EINVAL, "need finite vmin < vmax");
+    if (!device_memory_beside(dev_out, h->ws))
+        return fail(PIC_EINVAL, "dev_out must be device memory on the handle's GPU");
     const double sz = (double)nz / h->cfg[diode].L;
     const double sv = (double)nv / (vmax - vmin);
     const int64_t cap = h->der[diode].capacity[species];

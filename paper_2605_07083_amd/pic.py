@@ -310,8 +310,9 @@ class Handle:
         if out is None:
             with torch.cuda.stream(self.stream):
                 out = torch.zeros((nz, nv + 2), dtype=torch.int64, device=self.device)
-        if out.dtype != torch.int64 or tuple(out.shape) != (nz, nv + 2) or not out.is_contiguous():
-            raise ValueError("out must be a contiguous int64 tensor of shape (nz, nv + 2)")
+        if (out.dtype != torch.int64 or tuple(out.shape) != (nz, nv + 2) or not out.is_contiguous()
+                or out.device != self.device):
+            raise ValueError("out must be a contiguous int64 tensor of shape (nz, nv + 2) on the handle's device")
         _check(lib().pic_phase_space(self.h, int(d), int(sp), int(nz), int(nv), float(vmin), float(vmax),
                                      C.c_void_p(out.data_ptr())))
         return out

@@ -163,6 +163,13 @@ def test_phase_space_matches_oracle(pic, O):
                 (1, 0, 4, 4, -1.0, 1.0), (0, 0, 0, 4, -1.0, 1.0), (0, 0, 4, 4, float("nan"), 1.0)]:
         with pytest.raises(pic.PicError):
             h.phase_space(*bad)
+    # host memory is refused by the library, a tensor on another device by the binding
+    import ctypes
+    import torch
+    host = np.zeros((4, 6), dtype=np.int64)
+    assert pic.lib().pic_phase_space(h.h, 0, 0, 4, 4, -1.0, 1.0, host.ctypes.data_as(ctypes.c_void_p)) == pic.PIC_EINVAL
+    with pytest.raises(ValueError):
+        h.phase_space(0, 0, 4, 4, -1.0, 1.0, out=torch.zeros((4, 6), dtype=torch.int64))
 
 
 def test_edge_cases(pic, O):
