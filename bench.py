@@ -7,7 +7,7 @@ replenishment), Poisson solve and field.  Inputs are resident in HBM before
 the timed region; the metric is live particle-steps per second.
 
 Prints one JSON line.  Options: --gpus (must be 1), --steps, --warmup,
---workload {large,bench,tiny,sweep,surrogate} (default large: the 16384-cell,
+--workload {large,bench,tiny,sweep,paper,paperscan,surrogate} (default large: the 16384-cell,
 16.4M-per-species diode, the one configuration whose per-step working set
 exceeds the 256 MB last-level cache), --no-cpu-baseline.  --copy-probe BYTES
 runs a plain device copy of that size instead (counter calibration).
@@ -52,6 +52,13 @@ def workload(name):
         return "16384-cell collisional helium diode, 16.4M macro-particles per species", [presets.large()]
     if name == "sweep":
         return "32-diode emission sweep 1e19-1.2e20 m^-2 s^-1, 100-600k per species", presets.sweep()
+    if name == "paper":
+        return ("the paper's benchmark diode (10 cm helium gap, 4096 cells, 40 V), 4.1M macro-particles per "
+                "species, emission 7.25e19 m^-2 s^-1", [presets.paper()])
+    if name == "paperscan":
+        from paper_2605_07083_amd import fluxscan
+        return ("the paper's eleven-flux scan as one batch of its benchmark diode, 409.6k macro-particles per "
+                "species per diode", fluxscan.configs(100))
     raise SystemExit("unknown workload " + name)
 
 

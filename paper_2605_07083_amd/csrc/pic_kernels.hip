@@ -2169,9 +2169,10 @@ extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int n
 }
 
 // max_nodes: the largest N + 1 over the diodes.  Up to FIELD_TILE_MIN nodes
-// one block per diode does the whole step (fewest launches); above, births,
-// tile aggregates and the tiled solve run as three kernels over many CUs.
-constexpr int FIELD_TILE_MIN = 8192;
+// one block per diode does the whole step (fewest launches); above, the births
+// beside the tile aggregates and the tiled solve run as two kernels over many
+// CUs.  Measured crossover: 2049 nodes are faster in one block, 4097 in tiles.
+constexpr int FIELD_TILE_MIN = 4096;
 
 // Kernels picx_launch_sources_field enqueues for a step (timed graphs need it).
 extern "C" int picx_sources_field_kernels(int max_nodes, int mode)
