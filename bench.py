@@ -166,7 +166,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        raise SystemExit("bench.py measures one GPU only: this build has no multi-GPU path "
+        raise SystemExit("bench.py measures one GPU only: the library has no multi-GPU path "
                          "(the design notes describe how it would shard)")
 
     import torch
