@@ -203,6 +203,8 @@ class Handle:
         self.cfgs = [dict(c) for c in cfgs]
         self.nd = len(cfgs)
         self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
         self._arr = _cfg_array(cfgs)
         nbytes = pic_workspace_size(cfgs)
         with torch.cuda.device(self.device):
