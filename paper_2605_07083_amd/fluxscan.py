@@ -66,10 +66,13 @@ SENSITIVITY = (
 )
 
 
-def sensitivity_configs(ppc):
+def sensitivity_configs(ppc, cases=None):
+    """The SENSITIVITY cases (all, or the listed indices) as one batch."""
     base = presets.paper()
     out = []
     for d, (label, g, ch) in enumerate(SENSITIVITY):
+        if cases is not None and d not in cases:
+            continue
         kw = dict(gamma_emit=float(g), diode=d, n_load=int(ppc) * base["N"], tally_period=TALLY_PERIOD)
         channels = base["channels"]
         if ch.get("exc"):
@@ -276,6 +279,7 @@ def main(argv=None):
     ap.add_argument("--max-seconds", type=float, default=0.0, help="stop stepping after this wall time")
     ap.add_argument("--fluxes", type=float, nargs="+", default=list(FLUXES), help="imposed fluxes (m^-2 s^-1)")
     ap.add_argument("--sensitivity", action="store_true", help="the paper's sensitivity cases instead of the scan")
+    ap.add_argument("--cases", type=int, nargs="+", default=None, help="with --sensitivity: case indices (0-6)")
     ap.add_argument("--phase", action="store_true",
                     help="the three states of the paper's phase-space figure, with electron phase space")
     ap.add_argument("--phase-every", type=int, default=10000, help="steps between phase-space samples")
@@ -285,8 +289,9 @@ def main(argv=None):
         res = run(a.ppc, a.steps, a.window, a.chunk, a.max_seconds, fluxes=list(PHASE_FLUXES),
                   phase_every=a.phase_every)
     elif a.sensitivity:
-        res = run(a.ppc, a.steps, a.window, a.chunk, a.max_seconds, cfgs=sensitivity_configs(a.ppc),
-                  labels=[c[0] for c in SENSITIVITY])
+        picked = [i for i in range(len(SENSITIVITY)) if a.cases is None or i in a.cases]
+        res = run(a.ppc, a.steps, a.window, a.chunk, a.max_seconds, cfgs=sensitivity_configs(a.ppc, picked),
+                  labels=[SENSITIVITY[i][0] for i in picked])
     else:
         res = run(a.ppc, a.steps, a.window, a.chunk, a.max_seconds, fluxes=a.fluxes)
     if a.out:

@@ -84,3 +84,10 @@ def test_kinetic_summary_of_a_maxwellian():
     beam = np.zeros_like(ph)
     beam[0, :, 1 + nv // 2 + 40] = 1.0
     assert fluxscan.kinetic_summary(beam)["gap"]["l1_from_maxwellian"] > 0.9
+
+
+def test_sensitivity_case_selection():
+    cfgs = fluxscan.sensitivity_configs(1000, [6])
+    assert len(cfgs) == 1 and cfgs[0]["gamma_emit"] == 1.0e20
+    assert not cfgs[0]["channels"] & presets.CH_CX and cfgs[0]["diode"] == 6
+    assert cfgs[0]["n_load"] == 1000 * presets.paper()["N"]
