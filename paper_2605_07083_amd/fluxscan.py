@@ -279,7 +279,7 @@ def main(argv=None):
     ap.add_argument("--max-seconds", type=float, default=0.0, help="stop stepping after this wall time")
     ap.add_argument("--fluxes", type=float, nargs="+", default=list(FLUXES), help="imposed fluxes (m^-2 s^-1)")
     ap.add_argument("--sensitivity", action="store_true", help="the paper's sensitivity cases instead of the scan")
-    ap.add_argument("--cases", type=int, nargs="+", default=None, help="with --sensitivity: case indices (0-6)")
+    ap.add_argument("--cases", type=int, nargs="+", default=None, help="with --sensitivity: case indices 0-6 (the paper's cases 1-7)")
     ap.add_argument("--phase", action="store_true",
                     help="the three states of the paper's phase-space figure, with electron phase space")
     ap.add_argument("--phase-every", type=int, default=10000, help="steps between phase-space samples")
