@@ -122,7 +122,7 @@ def test_paper_setup_values(O):
             name, val, tol = line.split()
             assert vals[name] == pytest.approx(float(val), rel=float(tol)), name
     # the time step rule dt = 0.2 dz / v_te
-    assert p["dt"] == pytest.approx(0.2 * d["dz"] / vte, rel=1e-3)
+    assert p["dt"] == pytest.approx(0.2 * d["dz"] / vte, rel=1e-3, abs=0.0)
     # lambda/L ratios of the benchmark
     assert vals["lambda_e_m"] / p["L"] == pytest.approx(0.05, rel=2e-3)
     assert vals["lambda_i_m"] / p["L"] == pytest.approx(0.2, rel=2e-3)

@@ -46,9 +46,9 @@ def test_sigma_special_values(O):
     assert O.sigma(p, 3, 1.0) == presets.SIG_CX
     assert O.sigma(p, 1, E_EXC) == 0.0 and O.sigma(p, 2, E_ION) == 0.0
     # ln(x)/x peaks at x = e with value 1/e
-    assert O.sigma(p, 1, np.e * E_EXC) == pytest.approx(presets.SIG_X0 / np.e, rel=1e-12)
+    assert O.sigma(p, 1, np.e * E_EXC) == pytest.approx(presets.SIG_X0 / np.e, rel=1e-12, abs=0.0)
     # Lotz: a q ln(eps/E)/(eps E) at eps = e E_iz is a q / (e E_iz^2)
-    assert O.sigma(p, 2, np.e * E_ION) == pytest.approx(presets.LOTZ_A * 2 / (np.e * E_ION**2), rel=1e-12)
+    assert O.sigma(p, 2, np.e * E_ION) == pytest.approx(presets.LOTZ_A * 2 / (np.e * E_ION**2), rel=1e-12, abs=0.0)
     q = dict(p, channels=presets.CH_EEL)
     assert O.sigma(q, 1, 60.0) == 0.0
 
