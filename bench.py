@@ -14,6 +14,7 @@ runs a plain device copy of that size instead (counter calibration).
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -62,10 +63,26 @@ def workload(name):
     raise SystemExit("unknown workload " + name)
 
 
-def cpu_baseline(cfg, seconds=12.0):
-    """The FP64 oracle, single-threaded, on a bounded sample of the same diode."""
+def _host():
+    """Host CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return model, cores
+
+
+def _oracle_rate(cfg, seconds, omp):
     from oracle import oracle as O
-    s = O.Sim(cfg)
+    s = O.Sim(cfg, omp=omp)
     s.load()
     s.step(2)
     live = sum(s.count(sp) for sp in range(3))
@@ -77,9 +94,21 @@ def cpu_baseline(cfg, seconds=12.0):
         s.step(1)
         steps += 1
     dt = time.perf_counter() - t0
-    return {"value": ps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%d steps of the same diode from its initial load (%d live particles), FP64, one thread"
-                      % (steps, live)}
+    return ps / dt, steps, live, O.threads(omp)
+
+
+def cpu_baseline(cfg, seconds=12.0):
+    """The FP64 oracle on a bounded sample of the same diode: its OpenMP build
+    on every host core (the reported value) and its single-threaded build."""
+    model, cores = _host()
+    v1, n1, live, _ = _oracle_rate(cfg, seconds, omp=False)
+    vp, npar, _, threads = _oracle_rate(cfg, seconds, omp=True)
+    return {"value": vp, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": "%d steps of the same diode from its initial load (%d live particles), FP64, "
+                      "OpenMP build on %d threads" % (npar, live, threads),
+            "host_cores": cores, "cpu_model": model,
+            "single_thread": {"value": v1, "unit": "particle-steps/s", "cores": 1,
+                              "sample": "%d steps of the same sample, single-threaded build" % n1}}
 
 
 # FLOPs of one surrogate training step per position: forward and weight
@@ -156,14 +185,14 @@ def surrogate_bench(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=4096)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="large")
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune-steps", type=int, default=192)
     ap.add_argument("--schedule", default="", help="ppt,grid,sort_period,use_graph: fixed schedule, no autotuning")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
         raise SystemExit("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -200,17 +229,37 @@ def main():
     else:
         tune = h.autotune(trial_steps=args.tune_steps) if args.tune_steps > 0 else h.tuning()
     print("bench: schedule %s" % tune, file=sys.stderr, flush=True)
+    K = tune["sort_period"]
+
+    def align():
+        # run to the next re-sort boundary, so the timed steps start with a re-sort
+        t = h.tally(0)["step"]
+        h.step((K - t % K) % K)
+
+    # untimed: two passes of the same length from the same schedule position
+    # as the timed pass.  Each re-sort flips the particle buffer, and the
+    # graphs are captured per buffer: the timed pass starts on the buffer of
+    # one of the two passes (the sequence repeats if both started on the
+    # same), so every graph it replays is captured before it starts.
+    for _ in range(2):
+        align()
+        h.step_timed(args.steps)
+    align()
     h.sync()
+    live0 = h.live_total()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = h.step_timed(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     h.sync()
-    live = r["mean_live"]
+    live = 0.5 * (live0 + h.live_total())
     value = live * args.steps / wall
+    if not (r["particle_kernel_ms"] > 0.0 and math.isfinite(r["particle_kernel_ms"])):
+        raise SystemExit("bench: the particle kernel was not timed (%r)" % r)
     kern_s = r["particle_kernel_ms"] * 1e-3
     achieved = BYTES_PER_PARTICLE_STEP * live / kern_s / 1e9
+    step_gbs = BYTES_PER_PARTICLE_STEP * live * args.steps / wall / 1e9
     out = {
         "metric": "particle-steps/s (push+MCC+deposit) on 1 GPU",
         "value": value,
@@ -226,19 +275,22 @@ def main():
         "data": "synthetic (seeded Philox load of the stated diode)",
         "config": {"workload": desc, "n_diodes": len(cfgs), "cells": cfgs[0]["N"],
                    "particles_per_species": cfgs[0]["n_load"], "live_particles": live,
-                   "schedule": {k: tune[k] for k in ("ppt", "grid", "sort_period", "use_graph")}},
+                   "schedule": {k: tune[k] for k in ("ppt", "grid", "sort_period", "use_graph")},
+                   "timed_from": "a re-sort boundary (the timed steps include ceil(steps / sort_period) re-sorts)",
+                   "events_ms": r["total_ms"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if args.workload == "large" else None,
                      "traffic_unit": "bytes per launch",
                      "algorithmic_bytes_per_launch": BYTES_PER_PARTICLE_STEP * live,
                      "kernel": "k_particles", "kernel_ms": r["particle_kernel_ms"],
-                     "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP},
+                     "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP,
+                     "whole_step_achieved": step_gbs, "whole_step_frac": step_gbs / HBM_PEAK_GBS},
     }
     if not args.no_cpu_baseline and len(cfgs) == 1:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfgs[0], args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":

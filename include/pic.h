@@ -44,7 +44,10 @@ extern "C" {
 #define PIC_EHIP (-3)       /* HIP runtime error */
 #define PIC_ENULLCOLL (-4)  /* a candidate's collision frequency exceeded nu_max */
 #define PIC_ENAN (-5)       /* non-finite particle state */
-#define PIC_ERANGE (-6)     /* a queue or histogram bound was exceeded */
+#define PIC_ERANGE (-6)     /* a queue or histogram bound was exceeded: the ionisation queue
+                               (4096 events per diode and step), or a node's deposit reaching
+                               2^53 (2^21 particles of one species on one node), beyond which
+                               FP64 densities are no longer exact */
 
 #define PIC_MAX_DIODES 256
 
@@ -87,6 +90,9 @@ typedef struct pic_tally {
     int64_t coll[5];              /* real collisions per channel */
     uint32_t next_id;             /* next particle id */
     uint32_t err_bits;            /* sticky device error bits */
+    int64_t rare_spill;           /* collision candidates and absorbed particles that the particle
+                                     kernel's per-wave queues could not hold and handed to the
+                                     sources kernel (a work-list counter, not physics) */
 } pic_tally;
 
 /* Boundary diagnostics over a window ("Benchmark cases", eqs. 1-10). */
@@ -199,6 +205,13 @@ int pic_sync(pic_handle *h);
 /* Raw cumulative tallies of one diode.  Synchronises. */
 int pic_get_tally(pic_handle *h, int diode, pic_tally *out);
 
+/* The tallies of one diode as they stood at the end of step `step` (a
+ * multiple of tally_period, taken from the snapshot ring, so at most 1024
+ * tally periods back; step 0 gives zeros).  next_id is 0; err_bits is the
+ * current value.  PIC_EINVAL for a step that is not a tally step or not yet
+ * reached, PIC_ERANGE once it has left the ring.  Synchronises. */
+int pic_get_snapshot(pic_handle *h, int diode, int64_t step, pic_tally *out);
+
 /* Boundary diagnostics of one diode over the last window_steps steps
  * (a multiple of tally_period and at most tally_period * 1024 steps back), or
  * since the initial load when window_steps == 0.  Synchronises. */
@@ -252,7 +265,10 @@ int pic_get_particles(pic_handle *h, int diode, int species, int64_t cap, int64_
                       double *z, float *vx, float *vy, float *vz, uint32_t *id, uint32_t *tc);
 
 /* Replace one species of one diode by n host particles (cell order need not be
- * kept: the next step re-sorts).  Synchronises. */
+ * kept: the next step re-sorts).  Every z must lie in (0, L) (PIC_EINVAL
+ * otherwise) and every velocity component be finite (PIC_ENAN otherwise);
+ * nothing is changed on an error.  tc is the step at which the particle is
+ * next a null-collision candidate.  Synchronises. */
 int pic_set_particles(pic_handle *h, int diode, int species, int64_t n, const double *z,
                       const float *vx, const float *vy, const float *vz, const uint32_t *id,
                       const uint32_t *tc);
@@ -263,15 +279,16 @@ int pic_set_counters(pic_handle *h, int diode, int64_t step, uint32_t next_id);
 /* Re-deposit the current particles and re-solve the field without stepping. */
 int pic_refield(pic_handle *h);
 
-/* Per-kernel timing: run nsteps steps on the current schedule with HIP events
- * around launches of the particle kernel on the bound stream (with graph
- * replay: the particle kernels of 8 steps spread evenly over each replayed
- * re-sort period, until 4096 are timed; on the plain stream: one launch in
- * max(1, nsteps / 512)) and return their mean
- * duration (ms), the mean live-particle count and the total time (ms).
- * Synchronises. */
-int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *mean_live,
-                   double *total_ms);
+/* Per-kernel timing: run nsteps steps on the current schedule -- with graph
+ * replay, each run up to the next re-sort boundary is one replayed graph, as
+ * in pic_step -- with HIP events around launches of the particle kernel on
+ * the bound stream (with graph replay: the particle kernels of up to 8 steps
+ * spread evenly over each replayed run; on the plain stream: one launch in
+ * max(1, nsteps / 512); at most 4096 in all) and return their mean duration
+ * and the time from the first enqueued step to the end of the last (ms).
+ * Events are created on first use and kept by the handle.  Synchronises at
+ * the end only. */
+int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *total_ms);
 
 /* Launch schedule of the hot loop: particles per thread in the particle and
  * sort kernels (1, 2, 4 or 8; 0 keeps), persistent grid size (0: default),

@@ -47,6 +47,9 @@ class ODiag(C.Structure):
                                   "q_ion_anode_recomb", "q_anode1", "q_anode2", "phi_vc_eff")]
 
 
+_lib_omp = None
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -55,55 +58,78 @@ def lib():
         path = os.environ.get("PIC_ORACLE_LIB") or build_oracle.LIB
         if path == build_oracle.LIB and not os.path.exists(path):
             build_oracle.build()
-        L = C.CDLL(path)
-        P = C.c_void_p
-        d, i64, u32, i32 = C.c_double, C.c_int64, C.c_uint32, C.c_int32
-        L.o_create.restype = P
-        L.o_create.argtypes = [C.POINTER(OCfg)]
-        L.o_destroy.argtypes = [P]
-        for f in ("o_load", "o_step", "o_refield"):
-            getattr(L, f).argtypes = [P]
-            getattr(L, f).restype = C.c_int
-        L.o_load_profiles.argtypes = [P, P, P]
-        L.o_load_profiles.restype = C.c_int
-        L.o_load_state.argtypes = [P, P]
-        L.o_load_state.restype = C.c_int
-        L.o_count.argtypes = [P, C.c_int]
-        L.o_count.restype = i64
-        L.o_stepno.argtypes = [P]
-        L.o_stepno.restype = i64
-        L.o_next_id.argtypes = [P]
-        L.o_next_id.restype = u32
-        L.o_set_counters.argtypes = [P, i64, u32]
-        L.o_get_particles.argtypes = [P, C.c_int] + [P] * 6
-        L.o_set_particles.argtypes = [P, C.c_int, i64] + [P] * 6
-        L.o_set_particles.restype = C.c_int
-        for f in ("o_get_hist",):
-            getattr(L, f).argtypes = [P, C.c_int, P]
-        L.o_get_phi.argtypes = [P, P]
-        L.o_get_E.argtypes = [P, P]
-        L.o_get_tally.argtypes = [P, C.POINTER(OTally)]
-        L.o_get_derived.argtypes = [P, C.POINTER(ODerived)]
-        L.o_philox4x32_10.argtypes = [P, P, P]
-        L.o_u24.argtypes = [u32]
-        L.o_u24.restype = d
-        L.o_u32.argtypes = [u32]
-        L.o_u32.restype = d
-        L.o_u53.argtypes = [u32, u32]
-        L.o_u53.restype = d
-        L.o_sigma.argtypes = [C.POINTER(OCfg), C.c_int, d]
-        L.o_sigma.restype = d
-        L.o_derive.argtypes = [C.POINTER(OCfg), C.POINTER(ODerived)]
-        L.o_derive.restype = C.c_int
-        L.o_deposit.argtypes = [i64, P, i32, d, P]
-        L.o_solve.argtypes = [i32, d, d, P, P]
-        L.o_solve.restype = C.c_int
-        L.o_efield.argtypes = [i32, d, P, P]
-        L.o_diag.argtypes = [d, d, d, d, P, P, d, C.POINTER(ODiag)]
-        L.o_eta_vc.argtypes = [d, d, d]
-        L.o_eta_vc.restype = d
-        _lib = L
+        _lib = _setup(C.CDLL(path))
     return _lib
+
+
+def lib_omp():
+    """The same oracle built with OpenMP over its per-particle loops."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(build_oracle.LIB_OMP):
+            build_oracle.build()
+        _lib_omp = _setup(C.CDLL(build_oracle.LIB_OMP))
+    return _lib_omp
+
+
+def threads(omp=False):
+    return (lib_omp() if omp else lib()).o_threads()
+
+
+def _setup(L):
+    P = C.c_void_p
+    d, i64, u32, i32 = C.c_double, C.c_int64, C.c_uint32, C.c_int32
+    L.o_create.restype = P
+    L.o_create.argtypes = [C.POINTER(OCfg)]
+    L.o_destroy.argtypes = [P]
+    for f in ("o_load", "o_step", "o_refield"):
+        getattr(L, f).argtypes = [P]
+        getattr(L, f).restype = C.c_int
+    L.o_load_profiles.argtypes = [P, P, P]
+    L.o_load_profiles.restype = C.c_int
+    L.o_load_state.argtypes = [P, P]
+    L.o_load_state.restype = C.c_int
+    L.o_count.argtypes = [P, C.c_int]
+    L.o_count.restype = i64
+    L.o_stepno.argtypes = [P]
+    L.o_stepno.restype = i64
+    L.o_next_id.argtypes = [P]
+    L.o_next_id.restype = u32
+    L.o_set_counters.argtypes = [P, i64, u32]
+    L.o_get_particles.argtypes = [P, C.c_int] + [P] * 6
+    L.o_set_particles.argtypes = [P, C.c_int, i64] + [P] * 6
+    L.o_set_particles.restype = C.c_int
+    for f in ("o_get_hist",):
+        getattr(L, f).argtypes = [P, C.c_int, P]
+    L.o_get_phi.argtypes = [P, P]
+    L.o_get_E.argtypes = [P, P]
+    L.o_get_tally.argtypes = [P, C.POINTER(OTally)]
+    L.o_get_derived.argtypes = [P, C.POINTER(ODerived)]
+    L.o_philox4x32_10.argtypes = [P, P, P]
+    L.o_u24.argtypes = [u32]
+    L.o_u24.restype = d
+    L.o_u32.argtypes = [u32]
+    L.o_u32.restype = d
+    L.o_u53.argtypes = [u32, u32]
+    L.o_u53.restype = d
+    L.o_sigma.argtypes = [C.POINTER(OCfg), C.c_int, d]
+    L.o_sigma.restype = d
+    L.o_derive.argtypes = [C.POINTER(OCfg), C.POINTER(ODerived)]
+    L.o_derive.restype = C.c_int
+    L.o_deposit.argtypes = [i64, P, i32, d, P]
+    L.o_solve.argtypes = [i32, d, d, P, P]
+    L.o_solve.restype = C.c_int
+    L.o_efield.argtypes = [i32, d, P, P]
+    L.o_diag.argtypes = [d, d, d, d, P, P, d, C.POINTER(ODiag)]
+    L.o_eta_vc.argtypes = [d, d, d]
+    L.o_eta_vc.restype = d
+    L.o_threads.argtypes = []
+    L.o_threads.restype = C.c_int
+    L.o_last_moves.argtypes = [P, C.c_int] + [P] * 5
+    L.o_last_moves.restype = i64
+    L.o_last_moves_count.argtypes = [P, C.c_int]
+    L.o_last_moves_count.restype = i64
+    return L
 
 
 def make_cfg(p: dict) -> OCfg:
@@ -251,21 +277,23 @@ def diag(gamma_emit, Tc, w0, window_s, count, energy, n_emit):
 class Sim:
     """One oracle diode."""
 
-    def __init__(self, p: dict):
+    def __init__(self, p: dict, omp=False):
+        """omp: run on the OpenMP build (identical results, all host cores)."""
         self.p = dict(p)
         self._cfg = make_cfg(p)
-        self.h = lib().o_create(C.byref(self._cfg))
+        self.L = lib_omp() if omp else lib()
+        self.h = self.L.o_create(C.byref(self._cfg))
         if not self.h:
             raise ValueError("oracle: invalid configuration")
         self.N = p["N"]
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().o_destroy(self.h)
+            self.L.o_destroy(self.h)
             self.h = None
 
     def load(self):
-        if lib().o_load(self.h) != 0:
+        if self.L.o_load(self.h) != 0:
             raise RuntimeError("oracle load failed")
 
     def load_profiles(self, ne, ni):
@@ -273,7 +301,7 @@ class Sim:
         ne = np.ascontiguousarray(ne, dtype=np.float64)
         ni = np.ascontiguousarray(ni, dtype=np.float64)
         assert ne.shape == (self.N,) and ni.shape == (self.N,)
-        rc = lib().o_load_profiles(self.h, _ptr(ne), _ptr(ni))
+        rc = self.L.o_load_profiles(self.h, _ptr(ne), _ptr(ni))
         if rc == -2:
             raise ValueError("oracle: negative or non-finite density")
         if rc != 0:
@@ -285,7 +313,7 @@ class Sim:
         nine of |v_perp| (m/s) at the levels STATE_LEVELS."""
         prof = np.ascontiguousarray(prof, dtype=np.float64)
         assert prof.shape == (STATE_ROWS, self.N)
-        rc = lib().o_load_state(self.h, _ptr(prof))
+        rc = self.L.o_load_state(self.h, _ptr(prof))
         if rc == -2:
             raise ValueError("oracle: negative density or non-finite state entry")
         if rc != 0:
@@ -293,59 +321,71 @@ class Sim:
 
     def step(self, n=1):
         for _ in range(n):
-            if lib().o_step(self.h) != 0:
+            if self.L.o_step(self.h) != 0:
                 raise RuntimeError("oracle step failed")
 
     def refield(self):
-        lib().o_refield(self.h)
+        self.L.o_refield(self.h)
 
     @property
     def stepno(self):
-        return lib().o_stepno(self.h)
+        return self.L.o_stepno(self.h)
 
     @property
     def next_id(self):
-        return lib().o_next_id(self.h)
+        return self.L.o_next_id(self.h)
 
     def set_counters(self, step, next_id):
-        lib().o_set_counters(self.h, int(step), int(next_id))
+        self.L.o_set_counters(self.h, int(step), int(next_id))
 
     def count(self, sp):
-        return lib().o_count(self.h, sp)
+        return self.L.o_count(self.h, sp)
 
     def particles(self, sp):
         n = self.count(sp)
         z, vx, vy, vz = (np.zeros(n) for _ in range(4))
         pid, tc = np.zeros(n, np.uint32), np.zeros(n, np.uint32)
-        lib().o_get_particles(self.h, sp, _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), _ptr(pid), _ptr(tc))
+        self.L.o_get_particles(self.h, sp, _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), _ptr(pid), _ptr(tc))
         return {"z": z, "vx": vx, "vy": vy, "vz": vz, "id": pid, "tc": tc}
 
     def set_particles(self, sp, d):
         n = len(d["z"])
         arrs = [np.ascontiguousarray(d[k], dtype=np.float64) for k in ("z", "vx", "vy", "vz")]
         arrs += [np.ascontiguousarray(d[k], dtype=np.uint32) for k in ("id", "tc")]
-        if lib().o_set_particles(self.h, sp, n, *[_ptr(a) for a in arrs]) != 0:
+        if self.L.o_set_particles(self.h, sp, n, *[_ptr(a) for a in arrs]) != 0:
             raise MemoryError
         self._keep = getattr(self, "_keep", []) + [arrs]
 
+    def last_moves(self, sp):
+        """The last step's moves of species sp in that step's particle order:
+        id, z after the push, fate (0 stays, 1 cathode, 2 anode), channel (-1
+        none, -2 not a candidate) and channel-choice margin (relative to
+        nu_max) of the candidates."""
+        n = self.L.o_last_moves_count(self.h, sp)
+        m = {"id": np.zeros(n, np.uint32), "z": np.zeros(n), "fate": np.zeros(n, np.int32),
+             "ch": np.zeros(n, np.int32), "margin": np.zeros(n)}
+        self.L.o_last_moves(self.h, sp, _ptr(m["id"]), _ptr(m["z"]), _ptr(m["fate"]), _ptr(m["ch"]),
+                            _ptr(m["margin"]))
+        return m
+
     def hist(self, sp):
         H = np.zeros(self.N + 1, np.int64)
-        lib().o_get_hist(self.h, sp, _ptr(H))
+        self.L.o_get_hist(self.h, sp, _ptr(H))
         return H
 
     def phi(self):
         a = np.zeros(self.N + 1)
-        lib().o_get_phi(self.h, _ptr(a))
+        self.L.o_get_phi(self.h, _ptr(a))
         return a
 
     def E(self):
         a = np.zeros(self.N + 1)
-        lib().o_get_E(self.h, _ptr(a))
+        self.L.o_get_E(self.h, _ptr(a))
         return a
 
     def tally(self):
         t = OTally()
-        lib().o_get_tally(self.h, C.byref(t))
+        self.L.o_get_tally(self.h, C.byref(t))
         return {"abs_count": np.array([[t.abs_count[s][w] for w in range(2)] for s in range(3)]),
                 "abs_energy": np.array([[t.abs_energy[s][w] for w in range(2)] for s in range(3)]),
                 "n_emit": t.n_emit, "n_repl": t.n_repl, "n_iz": t.n_iz,
@@ -354,5 +394,5 @@ class Sim:
 
     def derived(self):
         d = ODerived()
-        lib().o_get_derived(self.h, C.byref(d))
+        self.L.o_get_derived(self.h, C.byref(d))
         return {"dz": d.dz, "invdz": d.invdz, "w0": d.w0, "numax": list(d.numax), "lam": list(d.lam)}

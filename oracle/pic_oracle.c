@@ -24,6 +24,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* CODATA 2018 exact / recommended values. */
 #define Q_E 1.602176634e-19
@@ -199,6 +202,22 @@ typedef struct {
     double vi[3];   /* new ion (the neutral's velocity) */
 } oiz;
 
+/* One particle's move in the step being taken: where the push put it, what
+ * the walls and the collision did to it.  Filled for every particle before
+ * any of them is tallied, so that the per-particle work can run on several
+ * threads while the order-dependent work (tallies, ionisation products,
+ * compaction) stays in particle order. */
+typedef struct {
+    double z;         /* position after the push */
+    double vz_push;   /* v_z after the push, before any collision */
+    double v[3];      /* velocity after the collision (= after the push if none) */
+    uint32_t id, tc;
+    int8_t fate;      /* 0 stays, 1 absorbed at the cathode, 2 at the anode */
+    int8_t cand;      /* 1 if a null-collision candidate this step */
+    int8_t ch;        /* channel taken, -1 none */
+    double margin;    /* candidates: channel-choice margin (relative to nu_max) */
+} omove;
+
 struct osim {
     ocfg c;
     oderived d;
@@ -209,6 +228,7 @@ struct osim {
     uint32_t next_id;
     otally t;
     oiz *iz; int64_t niz, cap_iz;
+    omove *mv[ONSP]; int64_t nmv[ONSP], cap_mv[ONSP];   /* the last step's moves per species */
 };
 
 static int sp_reserve(ospecies *s, int64_t need)
@@ -261,7 +281,7 @@ void o_destroy(osim *o)
     if (!o) return;
     for (int s = 0; s < ONSP; ++s) {
         free(o->sp[s].z); free(o->sp[s].vx); free(o->sp[s].vy); free(o->sp[s].vz);
-        free(o->sp[s].id); free(o->sp[s].tc); free(o->H[s]);
+        free(o->sp[s].id); free(o->sp[s].tc); free(o->H[s]); free(o->mv[s]);
     }
     free(o->rho); free(o->phi); free(o->E); free(o->iz);
     free(o);
@@ -286,6 +306,8 @@ static void cic(double z, int32_t N, double invdz, int32_t *j, double *f)
 
 void o_deposit(int64_t n, const double *z, int32_t N, double invdz, int64_t *H)
 {
+    /* integer sums: any split over threads gives the same histogram */
+#pragma omp parallel for schedule(static) reduction(+ : H[0 : N + 1])
     for (int64_t p = 0; p < n; ++p) {
         int32_t j; double f;
         cic(z[p], N, invdz, &j, &f);
@@ -426,20 +448,28 @@ int o_load(osim *o)
         double T = (s == OSP_I) ? c->Ti0 : c->Te0;
         double sig = sqrt(Q_E * T / o->d.mass[s]);
         double lam = o->d.lam[s == OSP_I ? 1 : 0];
-        if (sp_reserve(&o->sp[s], c->n_load)) return -1;
-        for (int64_t p = 0; p < c->n_load; ++p, ++id) {
+        ospecies *S = &o->sp[s];
+        if (sp_reserve(S, c->n_load)) return -1;
+        /* particle p of the species has id id0 + p and its own draws */
+        const uint32_t id0 = id;
+#pragma omp parallel for schedule(static)
+        for (int64_t p = 0; p < c->n_load; ++p) {
+            const uint32_t pid = id0 + (uint32_t)p;
             uint32_t b0[4], b1[4];
-            draw(id, kseed(o), LOAD_STEP, EV_LOAD, 0, b0);
-            draw(id, kseed(o), LOAD_STEP, EV_LOAD, 1, b1);
+            draw(pid, kseed(o), LOAD_STEP, EV_LOAD, 0, b0);
+            draw(pid, kseed(o), LOAD_STEP, EV_LOAD, 1, b1);
             double n1, n2, n3, n4;
             normal_pair32(b0[0], b0[1], &n1, &n2);
             normal_pair32(b0[2], b0[3], &n3, &n4);
-            double z = c->L * o_u53(b1[0], b1[1]);
             /* first candidate step: the first whole step of the free flight */
             uint32_t tc = next_candidate(0u, lam, b1[2], b1[3]);
             if (tc != NEVER) tc -= 1u;
-            sp_push(&o->sp[s], z, sig * n1, sig * n2, sig * n3, id, tc);
+            S->z[p] = c->L * o_u53(b1[0], b1[1]);
+            S->vx[p] = sig * n1; S->vy[p] = sig * n2; S->vz[p] = sig * n3;
+            S->id[p] = pid; S->tc[p] = tc;
         }
+        S->n = c->n_load;
+        id += (uint32_t)c->n_load;
     }
     o->next_id = id;
     return o_refield(o);
@@ -599,8 +629,8 @@ static void iso_dir(uint32_t wc, uint32_t wp, double d[3])
 
 /* Returns the channel taken (-1 null).  v (3) is updated in place.  For
  * ionisation the secondary electron and new ion velocities are returned. */
-static int mcc(osim *o, int sp, uint32_t id, uint32_t n, double v[3], double ve[3], double vi[3],
-               uint32_t *tc)
+static int mcc(const osim *o, int sp, uint32_t id, uint32_t n, double v[3], double ve[3], double vi[3],
+               uint32_t *tc, int *exceeded, double *margin)
 {
     const ocfg *c = &o->c;
     const oderived *d = &o->d;
@@ -628,11 +658,16 @@ static int mcc(osim *o, int sp, uint32_t id, uint32_t n, double v[3], double ve[
     double r = o_u24(C1[0]) * numax;
     double cum = 0.0;
     int taken = -1;
+    /* margin: distance of r from the nearest cumulative boundary, relative
+     * to numax (how close the channel choice came to another outcome) */
+    double mg = INFINITY;
     for (int q = 0; q < nch; ++q) {
         cum += c->ng * o_sigma(c, chs[q], eps) * gm;
         if (taken < 0 && r < cum) taken = chs[q];
+        if (fabs(r - cum) < mg) mg = fabs(r - cum);
     }
-    if (cum > numax) o->t.nullcoll_exceed++;
+    *margin = numax > 0.0 ? mg / numax : INFINITY;
+    *exceeded = cum > numax;
     *tc = next_candidate(n, d->lam[ion], C2[2], C2[3]);
     if (taken < 0) return -1;
 
@@ -709,8 +744,20 @@ int o_step(osim *o)
 
     for (int sp = 0; sp < ONSP; ++sp) {
         ospecies *s = &o->sp[sp];
-        int64_t keep = 0;
+        const int ion = (sp == OSP_I);
+        if (s->n > o->cap_mv[sp]) {
+            omove *m = realloc(o->mv[sp], s->n * sizeof(omove));
+            if (!m) return -1;
+            o->mv[sp] = m;
+            o->cap_mv[sp] = s->n;
+        }
+        omove *mv = o->mv[sp];
+        o->nmv[sp] = s->n;
+        int64_t exceed = 0;
+        /* per particle: gather, push, wall test, collision */
+#pragma omp parallel for schedule(static) reduction(+ : exceed)
         for (int64_t p = 0; p < s->n; ++p) {
+            omove *m = &mv[p];
             /* gather (CIC, same weights as the deposit) */
             int32_t j; double f;
             cic(s->z[p], c->N, d->invdz, &j, &f);
@@ -719,25 +766,46 @@ int o_step(osim *o)
             /* leapfrog: v^{n+1/2} = v^{n-1/2} + (q/m) E dt ; z^{n+1} = z^n + v dt */
             double vz = s->vz[p] + d->qm[sp] * Ep * c->dt;
             double z = s->z[p] + vz * c->dt;
-            double vx = s->vx[p], vy = s->vy[p];
-            uint32_t tc = s->tc[p];
+            m->id = s->id[p];
+            m->tc = s->tc[p];
+            m->vz_push = vz;
+            m->v[0] = s->vx[p]; m->v[1] = s->vy[p]; m->v[2] = vz;
+            m->cand = 0; m->ch = -1; m->margin = INFINITY; m->fate = 0;
             if (c->periodic) {
                 while (z < 0.0) z += c->L;
                 while (z >= c->L) z -= c->L;
             } else if (z <= 0.0 || z >= c->L) {
-                /* absorbing electrodes */
-                tally_abs(o, sp, z <= 0.0 ? 0 : 1, vx, vy, vz);
-                if (sp == OSP_I) ion_lost++;
+                m->fate = z <= 0.0 ? 1 : 2;   /* absorbing electrodes */
+            } else if (m->tc == n) {
+                double ve[3], vi[3];
+                int ex = 0;
+                m->cand = 1;
+                m->ch = (int8_t)mcc(o, sp, m->id, n, m->v, ve, vi, &m->tc, &ex, &m->margin);
+                exceed += ex;
+            }
+            m->z = z;
+        }
+        o->t.nullcoll_exceed += exceed;
+        /* in particle order: tallies, ionisation events, compaction */
+        int64_t keep = 0;
+        for (int64_t p = 0; p < s->n; ++p) {
+            const omove *m = &mv[p];
+            if (m->fate) {
+                tally_abs(o, sp, m->fate - 1, m->v[0], m->v[1], m->v[2]);
+                if (ion) ion_lost++;
                 continue;
             }
-            if (!c->periodic && tc == n) {
-                int ion = (sp == OSP_I);
+            if (m->cand) {
                 o->t.cand[ion]++;
-                double v[3] = {vx, vy, vz}, ve[3], vi[3];
-                int ch = mcc(o, sp, s->id[p], n, v, ve, vi, &tc);
-                if (ch >= 0) o->t.coll[ch]++;
-                vx = v[0]; vy = v[1]; vz = v[2];
-                if (ch == OCH_IZ) {
+                if (m->ch >= 0) o->t.coll[m->ch]++;
+                if (m->ch == OCH_IZ) {
+                    /* the products: the same (pure) collision once more from the
+                     * pre-collision velocity */
+                    double v[3] = {s->vx[p], s->vy[p], m->vz_push}, ve[3], vi[3];
+                    uint32_t tc2;
+                    int ex;
+                    double mg;
+                    mcc(o, sp, m->id, n, v, ve, vi, &tc2, &ex, &mg);
                     if (o->niz == o->cap_iz) {
                         int64_t nc = o->cap_iz ? 2 * o->cap_iz : 64;
                         oiz *t = realloc(o->iz, nc * sizeof(oiz));
@@ -745,12 +813,12 @@ int o_step(osim *o)
                         o->iz = t; o->cap_iz = nc;
                     }
                     oiz *e = &o->iz[o->niz++];
-                    e->parent = s->id[p]; e->parent_sp = sp; e->z = z;
+                    e->parent = m->id; e->parent_sp = sp; e->z = m->z;
                     for (int k = 0; k < 3; ++k) { e->ve[k] = ve[k]; e->vi[k] = vi[k]; }
                 }
             }
-            s->z[keep] = z; s->vx[keep] = vx; s->vy[keep] = vy; s->vz[keep] = vz;
-            s->id[keep] = s->id[p]; s->tc[keep] = tc;
+            s->z[keep] = m->z; s->vx[keep] = m->v[0]; s->vy[keep] = m->v[1]; s->vz[keep] = m->v[2];
+            s->id[keep] = m->id; s->tc[keep] = m->tc;
             keep++;
         }
         s->n = keep;
@@ -820,6 +888,42 @@ int o_step(osim *o)
 /* Accessors                                                                */
 /* ------------------------------------------------------------------------ */
 int64_t o_count(const osim *o, int sp) { return o->sp[sp].n; }
+
+/* Threads this build runs the per-particle loops on (1 without OpenMP). */
+int o_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        {
+#ifdef _OPENMP
+            n = omp_get_num_threads();
+#endif
+        }
+    }
+    return n;
+}
+
+int64_t o_last_moves_count(const osim *o, int sp) { return o->nmv[sp]; }
+
+/* The last step's moves of one species, in the particle order of that step:
+ * id, position after the push, fate (0 stays, 1 cathode, 2 anode), channel
+ * (-1 none; -2 not a candidate) and the channel-choice margin of candidates.
+ * Returns the count (arrays must hold o_count before the step). */
+int64_t o_last_moves(const osim *o, int sp, uint32_t *id, double *z, int32_t *fate, int32_t *ch,
+                     double *margin)
+{
+    for (int64_t p = 0; p < o->nmv[sp]; ++p) {
+        const omove *m = &o->mv[sp][p];
+        id[p] = m->id;
+        z[p] = m->z;
+        fate[p] = m->fate;
+        ch[p] = m->cand ? m->ch : -2;
+        margin[p] = m->margin;
+    }
+    return o->nmv[sp];
+}
 int64_t o_stepno(const osim *o) { return o->step; }
 uint32_t o_next_id(const osim *o) { return o->next_id; }
 void o_set_counters(osim *o, int64_t step, uint32_t next_id) { o->step = step; o->next_id = next_id; }

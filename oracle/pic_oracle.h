@@ -98,6 +98,10 @@ int o_load_state(osim *o, const double *prof);
 int o_step(osim *o);
 int o_refield(osim *o);
 int64_t o_count(const osim *o, int sp);
+int o_threads(void);
+int64_t o_last_moves_count(const osim *o, int sp);
+int64_t o_last_moves(const osim *o, int sp, uint32_t *id, double *z, int32_t *fate, int32_t *ch,
+                     double *margin);
 int64_t o_stepno(const osim *o);
 uint32_t o_next_id(const osim *o);
 void o_set_counters(osim *o, int64_t step, uint32_t next_id);

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <numeric>
 #include <string>
@@ -55,7 +56,9 @@ int fail(int code, const std::string &msg)
     } while (0)
 
 constexpr size_t ALIGN = 256;
-constexpr int TPOS = 8;   // particle kernels timed per replayed period (pic_step_timed)
+constexpr int TPOS = 8;   // particle kernels timed per replayed graph (pic_step_timed)
+constexpr size_t GRAPH_CACHE = 16;   // captured step runs kept per handle
+constexpr int64_t TIMED_MAX = 4096;   // particle kernels timed per pic_step_timed call
 
 // ----------------------------------------------------------------------------
 // Derived quantities ("Model": w0 = n0 dz / N_ppc, dt and grid; MCC bound).
@@ -243,6 +246,16 @@ void fill_params(const pic_config &c, const pic_derived &der, Diode &D)
 
 }  // namespace
 
+// A captured run of steps: an optional re-sort, then r steps (particle kernel
+// and sources / field kernels each).  Timed variants carry event-record
+// nodes around some of the particle kernels.
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t src = nullptr;             // timed: kept alive, its node handles address the exec's nodes
+    std::vector<hipGraphNode_t> marks;    // timed: (start, end) event nodes per timed step
+    uint64_t last_use = 0;
+};
+
 struct pic_handle {
     int nd = 0;
     std::vector<pic_config> cfg;
@@ -263,22 +276,28 @@ struct pic_handle {
     int sort_period = 64;
     bool use_graph = true;
     hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
-    hipGraphExec_t graph[2] = {nullptr, nullptr};   // re-sort + sort_period steps, per start parity
-    // the same graphs with event-record nodes around every particle kernel
-    hipGraphExec_t tgraph[2] = {nullptr, nullptr};
-    hipGraph_t tsrc[2] = {nullptr, nullptr};  // kept alive: its node handles address the exec's nodes
-    std::vector<hipGraphNode_t> tnode[2];   // (start, end) per timed step of the period
-    std::vector<int> tset[2];               // timed steps whose nodes hold this call's events
-    hipEvent_t tev[2] = {nullptr, nullptr}; // placeholders recorded by the other steps
+    // captured runs keyed by (parity, re-sort first, timed, steps); the least
+    // recently used is dropped beyond GRAPH_CACHE entries
+    std::map<int64_t, GraphEntry> graphs;
+    uint64_t use_clock = 0;
+    std::vector<hipEvent_t> evpool;         // pic_step_timed's events, created on demand, reused
+    hipEvent_t tev[2] = {nullptr, nullptr}; // placeholders for event nodes not timed in a replay
+    hipEvent_t tt[2] = {nullptr, nullptr};  // start and end of a timed run
+    void drop_graphs()
+    {
+        for (auto &kv : graphs) {
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+            if (kv.second.src) (void)hipGraphDestroy(kv.second.src);
+        }
+        graphs.clear();
+    }
     ~pic_handle()
     {
-        for (auto g : graph)
-            if (g) (void)hipGraphExecDestroy(g);
-        for (auto g : tgraph)
-            if (g) (void)hipGraphExecDestroy(g);
-        for (auto g : tsrc)
-            if (g) (void)hipGraphDestroy(g);
+        drop_graphs();
+        for (auto e : evpool) (void)hipEventDestroy(e);
         for (auto e : tev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto e : tt)
             if (e) (void)hipEventDestroy(e);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
@@ -330,60 +349,41 @@ int launch_step(pic_handle *h)
     return PIC_OK;
 }
 
-// A captured graph of one re-sort and sort_period steps, replayed whenever the
-// schedule reaches a re-sort boundary with at least that many steps to go.
-int ensure_graph(pic_handle *h, int p)
+// Steps from the current schedule position to the next re-sort boundary (at
+// most `left`): the run one graph replays.
+int64_t run_length(const pic_handle *h, int64_t left)
 {
-    if (h->graph[p]) return PIC_OK;
-    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-    hipGraph_t g;
-    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_sort(h, h->cap_stream, p);
-    for (int k = 0; rc == PIC_OK && k < h->sort_period; ++k) rc = enqueue_body(h, h->cap_stream, p ^ 1);
-    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
-    if (rc) return rc;
-    if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&h->graph[p], g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        h->graph[p] = nullptr;
-        return fail(PIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    }
-    return PIC_OK;
+    int64_t r = left;
+    if (h->sort_period > 0) r = std::min<int64_t>(r, h->sort_period - h->issued % h->sort_period);
+    return std::max<int64_t>(r, 1);
 }
 
-// Timed variant of a re-sort period graph.  The captured period is a chain
-// (re-sort kernels, then particle and field kernel per step); event-record
-// nodes are spliced in around every step's particle kernel.  Before each
-// replay one step's pair is pointed at fresh events (the step rotates from
-// replay to replay, so the sample covers the whole period); the other pairs
-// record placeholders.
-int ensure_timed_graph(pic_handle *h, int p)
+// Schedule bookkeeping after a run of r steps that began with a re-sort or not.
+void advance(pic_handle *h, bool sorted, int64_t r)
 {
-    if (h->tgraph[p]) return PIC_OK;
-    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-    for (auto &e : h->tev)
-        if (!e) HIP_TRY(hipEventCreate(&e));
-    const int K = h->sort_period;
-    hipGraph_t g;
-    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_sort(h, h->cap_stream, p);
-    for (int k = 0; rc == PIC_OK && k < K; ++k) rc = enqueue_body(h, h->cap_stream, p ^ 1);
-    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
-    if (rc) return rc;
-    if (e2 != hipSuccess) return fail(PIC_EHIP, "graph capture of the timed period failed");
-    auto bail = [&](const char *m) { (void)hipGraphDestroy(g); return fail(PIC_EHIP, m); };
-    // walk the chain from its root
+    if (sorted) {
+        h->parity ^= 1;
+        h->sort_next = false;
+    }
+    h->issued += r;
+}
+
+// Splice event-record nodes around ns particle kernels spread evenly over the
+// r steps of a captured chain (optional re-sort kernels, then per step the
+// particle kernel and the sources / field kernels).
+int splice_timing(pic_handle *h, hipGraph_t g, int r, std::vector<hipGraphNode_t> &marks)
+{
     size_t nn = 0;
-    if (hipGraphGetNodes(g, nullptr, &nn) != hipSuccess) return bail("hipGraphGetNodes failed");
+    if (hipGraphGetNodes(g, nullptr, &nn) != hipSuccess) return fail(PIC_EHIP, "hipGraphGetNodes failed");
     std::vector<hipGraphNode_t> nodes(nn), chain;
-    if (hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) return bail("hipGraphGetNodes failed");
+    if (hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) return fail(PIC_EHIP, "hipGraphGetNodes failed");
     hipGraphNode_t cur = nullptr;
     for (auto nd : nodes) {
         size_t nd_in = 0;
-        if (hipGraphNodeGetDependencies(nd, nullptr, &nd_in) != hipSuccess) return bail("dependency query failed");
+        if (hipGraphNodeGetDependencies(nd, nullptr, &nd_in) != hipSuccess)
+            return fail(PIC_EHIP, "dependency query failed");
         if (nd_in == 0) {
-            if (cur) return bail("captured period is not a chain");
+            if (cur) return fail(PIC_EHIP, "captured run is not a chain");
             cur = nd;
         }
     }
@@ -391,61 +391,104 @@ int ensure_timed_graph(pic_handle *h, int p)
         chain.push_back(cur);
         size_t nout = 0;
         if (hipGraphNodeGetDependentNodes(cur, nullptr, &nout) != hipSuccess || nout > 1)
-            return bail("captured period is not a chain");
+            return fail(PIC_EHIP, "captured run is not a chain");
         hipGraphNode_t next = nullptr;
         if (nout == 1 && hipGraphNodeGetDependentNodes(cur, &next, &nout) != hipSuccess)
-            return bail("dependency query failed");
+            return fail(PIC_EHIP, "dependency query failed");
         cur = nout ? next : nullptr;
     }
-    // a step is the particle kernel and the sources / field kernels after it
-    const int B = 1 + picx_sources_field_kernels(h->max_nodes, 0);
-    if ((int)chain.size() < B * K + 1) return bail("unexpected captured period");
-    const int first = (int)chain.size() - B * K;      // particle kernel of step 0
-    // event nodes around TPOS particle kernels spread evenly over the period
-    // (each pair of event nodes costs a few microseconds of idle GPU)
-    const int ns = std::min(TPOS, K);
-    std::vector<hipGraphNode_t> marks(2 * ns);
+    const int B = 1 + picx_sources_field_kernels(h->max_nodes, 0);   // kernels per step
+    if ((int)chain.size() < B * r) return fail(PIC_EHIP, "unexpected captured run");
+    const int first = (int)chain.size() - B * r;      // particle kernel of the run's first step
+    const int ns = std::min(TPOS, r);
+    marks.assign(2 * ns, nullptr);
     for (int j = 0; j < ns; ++j) {
-        const int k = (int)((int64_t)j * K / ns);
-        hipGraphNode_t pred = chain[first + B * k - 1], part = chain[first + B * k];
-        hipGraphNode_t field = chain[first + B * k + 1];
-        if (hipGraphRemoveDependencies(g, &pred, &part, 1) != hipSuccess ||
+        const int k = (int)((int64_t)j * r / ns);
+        const int at = first + B * k;
+        hipGraphNode_t part = chain[at], field = chain[at + 1];
+        hipGraphNode_t pred = at > 0 ? chain[at - 1] : nullptr;
+        const size_t npred = pred ? 1 : 0;
+        if ((pred && hipGraphRemoveDependencies(g, &pred, &part, 1) != hipSuccess) ||
             hipGraphRemoveDependencies(g, &part, &field, 1) != hipSuccess ||
-            hipGraphAddEventRecordNode(&marks[2 * j], g, &pred, 1, h->tev[0]) != hipSuccess ||
+            hipGraphAddEventRecordNode(&marks[2 * j], g, pred ? &pred : nullptr, npred, h->tev[0]) != hipSuccess ||
             hipGraphAddDependencies(g, &marks[2 * j], &part, 1) != hipSuccess ||
             hipGraphAddEventRecordNode(&marks[2 * j + 1], g, &part, 1, h->tev[1]) != hipSuccess ||
             hipGraphAddDependencies(g, &marks[2 * j + 1], &field, 1) != hipSuccess)
-            return bail("splicing event nodes failed");
+            return fail(PIC_EHIP, "splicing event nodes failed");
     }
-    hipError_t e = hipGraphInstantiate(&h->tgraph[p], g, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        h->tgraph[p] = nullptr;
-        return fail(PIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    }
-    h->tsrc[p] = g;
-    h->tnode[p] = marks;
-    h->tset[p].clear();
     return PIC_OK;
 }
 
+// The captured run (parity p, re-sort first or not, r steps, timed or not),
+// captured and instantiated on first use.
+int get_graph(pic_handle *h, int p, bool sorted, int64_t r, bool timed, GraphEntry **out)
+{
+    const int64_t key = (int64_t)p | (int64_t)sorted << 1 | (int64_t)timed << 2 | r << 3;
+    auto it = h->graphs.find(key);
+    if (it != h->graphs.end()) {
+        it->second.last_use = ++h->use_clock;
+        *out = &it->second;
+        return PIC_OK;
+    }
+    if (h->graphs.size() >= GRAPH_CACHE) {
+        // drop the least recently used; nothing of it may still be in flight
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        auto lru = h->graphs.begin();
+        for (auto q = h->graphs.begin(); q != h->graphs.end(); ++q)
+            if (q->second.last_use < lru->second.last_use) lru = q;
+        if (lru->second.exec) (void)hipGraphExecDestroy(lru->second.exec);
+        if (lru->second.src) (void)hipGraphDestroy(lru->second.src);
+        h->graphs.erase(lru);
+    }
+    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    for (auto &e : h->tev)
+        if (!e) HIP_TRY(hipEventCreate(&e));
+    hipGraph_t g;
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = sorted ? enqueue_sort(h, h->cap_stream, p) : PIC_OK;
+    const int q = sorted ? p ^ 1 : p;
+    for (int64_t k = 0; rc == PIC_OK && k < r; ++k) rc = enqueue_body(h, h->cap_stream, q);
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    GraphEntry ent;
+    if (timed && (rc = splice_timing(h, g, (int)r, ent.marks))) {
+        (void)hipGraphDestroy(g);
+        return rc;
+    }
+    e = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(PIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    if (timed) ent.src = g;     // the exec's event nodes are addressed through it
+    else (void)hipGraphDestroy(g);
+    ent.last_use = ++h->use_clock;
+    *out = &(h->graphs[key] = ent);
+    return PIC_OK;
+}
+
+// Enqueue nsteps steps.  With graph replay each run up to the next re-sort
+// boundary is one graph launch (whole re-sort periods once the schedule is
+// aligned); otherwise every step is launched on the stream.
 int run_steps(pic_handle *h, int64_t nsteps)
 {
     int64_t left = nsteps;
     while (left > 0) {
-        if (h->use_graph && h->sort_period > 1 && !h->sort_next && h->issued % h->sort_period == 0 &&
-            left >= h->sort_period) {
-            int rc = ensure_graph(h, h->parity);
+        if (!h->use_graph) {
+            int rc = launch_step(h);
             if (rc) return rc;
-            HIP_TRY(hipGraphLaunch(h->graph[h->parity], h->stream));
-            h->parity ^= 1;
-            h->issued += h->sort_period;
-            left -= h->sort_period;
+            --left;
             continue;
         }
-        int rc = launch_step(h);
+        const bool sorted = sort_due(h);
+        const int64_t r = run_length(h, left);
+        GraphEntry *g;
+        int rc = get_graph(h, h->parity, sorted, r, false, &g);
         if (rc) return rc;
-        --left;
+        HIP_TRY(hipGraphLaunch(g->exec, h->stream));
+        advance(h, sorted, r);
+        left -= r;
     }
     return PIC_OK;
 }
@@ -482,6 +525,8 @@ int err_code(uint32_t bits)
     if (bits & ERR_CAPACITY) return fail(PIC_ENOSPACE, "particle capacity exceeded on the device");
     if (bits & ERR_NULLCOLL) return fail(PIC_ENULLCOLL, "collision frequency exceeded the null-collision bound");
     if (bits & ERR_IZQ) return fail(PIC_ERANGE, "ionisation queue overflow");
+    if (bits & ERR_RANGE)
+        return fail(PIC_ERANGE, "a node's deposit reached 2^53 (2^21 particles of one species on one node)");
     if (bits & ERR_NAN) return fail(PIC_ENAN, "non-finite particle position");
     return PIC_OK;
 }
@@ -687,15 +732,9 @@ int pic_sync(pic_handle *h)
     return PIC_OK;
 }
 
-int pic_get_tally(pic_handle *h, int diode, pic_tally *out)
+static void fill_tally(const pic_handle *h, int diode, const DiodeTally &t, pic_tally *out)
 {
-    if (!h || !out || diode < 0 || diode >= h->nd) return fail(PIC_EINVAL, "bad arguments");
-    DiodeState st;
-    DiodeTally t;
-    int rc = read_state(h, diode, st, t);
-    if (rc) return rc;
     std::memset(out, 0, sizeof(*out));
-    out->step = st.step;
     live_counts(h, diode, t, out->n_live);
     for (int s = 0; s < NSP; ++s)
         for (int w = 0; w < 2; ++w) {
@@ -707,6 +746,42 @@ int pic_get_tally(pic_handle *h, int diode, pic_tally *out)
     out->n_iz = (int64_t)t.n_iz;
     for (int k = 0; k < 2; ++k) out->cand[k] = (int64_t)t.cand[k];
     for (int k = 0; k < NCH; ++k) out->coll[k] = (int64_t)t.coll[k];
+    out->rare_spill = (int64_t)t.rare_spill;
+}
+
+int pic_get_snapshot(pic_handle *h, int diode, int64_t step, pic_tally *out)
+{
+    if (!h || !out || diode < 0 || diode >= h->nd || step < 0) return fail(PIC_EINVAL, "bad arguments");
+    const int64_t D = h->cfg[diode].tally_period;
+    if (step % D) return fail(PIC_EINVAL, "step must be a multiple of tally_period");
+    DiodeState st;
+    DiodeTally now;
+    int rc = read_state(h, diode, st, now);
+    if (rc) return rc;
+    if (step > (int64_t)st.step) return fail(PIC_EINVAL, "step not reached yet");
+    DiodeTally t;
+    std::memset(&t, 0, sizeof(t));
+    if (step > 0) {
+        TallySnap sn;
+        HIP_TRY(hipMemcpy(&sn, h->hD[diode].ring + (step / D) % RING, sizeof(sn), hipMemcpyDeviceToHost));
+        if ((int64_t)sn.step != step) return fail(PIC_ERANGE, "snapshot no longer in the ring");
+        t = sn.t;
+    }
+    fill_tally(h, diode, t, out);
+    out->step = step;
+    out->err_bits = st.err;
+    return PIC_OK;
+}
+
+int pic_get_tally(pic_handle *h, int diode, pic_tally *out)
+{
+    if (!h || !out || diode < 0 || diode >= h->nd) return fail(PIC_EINVAL, "bad arguments");
+    DiodeState st;
+    DiodeTally t;
+    int rc = read_state(h, diode, st, t);
+    if (rc) return rc;
+    fill_tally(h, diode, t, out);
+    out->step = st.step;
     out->next_id = st.next_id;
     out->err_bits = st.err;
     return PIC_OK;
@@ -900,8 +975,11 @@ int pic_set_particles(pic_handle *h, int diode, int species, int64_t n, const do
         return fail(PIC_EINVAL, "bad arguments");
     if (n > 0 && (!z || !vx || !vy || !vz || !id || !tc)) return fail(PIC_EINVAL, "null array");
     if (n > h->der[diode].capacity[species]) return fail(PIC_ENOSPACE, "more particles than capacity");
-    for (int64_t i = 0; i < n; ++i)
+    for (int64_t i = 0; i < n; ++i) {
         if (!(z[i] > 0.0 && z[i] < h->cfg[diode].L)) return fail(PIC_EINVAL, "particle outside (0, L)");
+        if (!std::isfinite(vx[i]) || !std::isfinite(vy[i]) || !std::isfinite(vz[i]))
+            return fail(PIC_ENAN, "non-finite particle velocity");
+    }
     DiodeState st;
     DiodeTally t;
     int rc = read_state(h, diode, st, t);
@@ -940,109 +1018,81 @@ int pic_refield(pic_handle *h)
     return refield(h);
 }
 
-int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *mean_live, double *total_ms)
+int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *total_ms)
 {
     if (!h || nsteps < 1) return fail(PIC_EINVAL, "bad arguments");
-    // events for TPOS particle kernels per graph replay, one launch in
-    // `every` on the plain stream
+    // events: up to TPOS particle kernels per replayed graph, or one launch in
+    // `every` on the plain stream, at most TIMED_MAX kernels in all
     const int64_t every = std::max<int64_t>(1, nsteps / 512);
-    const int64_t nev = (h->use_graph ? std::min<int64_t>(nsteps, 4096) : nsteps / every) + 2;
-    std::vector<hipEvent_t> ev(2 * nev);
-    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-    hipEvent_t t0, t1;
-    HIP_TRY(hipEventCreate(&t0));
-    HIP_TRY(hipEventCreate(&t1));
-    auto live_sum = [&](int64_t out[NSP]) -> int {
-        DiodeState st;
-        DiodeTally t;
-        int64_t sum[NSP] = {0, 0, 0}, l[NSP];
-        for (int d = 0; d < h->nd; ++d) {
-            int rc = read_state(h, d, st, t);
-            if (rc) return rc;
-            live_counts(h, d, t, l);
-            for (int s = 0; s < NSP; ++s) sum[s] += l[s];
+    auto pair = [&](int64_t k, hipEvent_t &a, hipEvent_t &b) -> int {
+        while ((int64_t)h->evpool.size() < 2 * (k + 1)) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            h->evpool.push_back(e);
         }
-        std::copy(sum, sum + NSP, out);
+        a = h->evpool[2 * k];
+        b = h->evpool[2 * k + 1];
         return PIC_OK;
     };
-    int64_t live0[NSP], live1[NSP];
-    int rc = live_sum(live0);
-    if (rc) return rc;
-    HIP_TRY(hipEventRecord(t0, h->stream));
+    for (auto &e : h->tt)
+        if (!e) HIP_TRY(hipEventCreate(&e));
+    int rc;
+    HIP_TRY(hipEventRecord(h->tt[0], h->stream));
     int64_t k_ev = 0, left = nsteps, k = 0;
     while (left > 0) {
-        if (h->use_graph && h->sort_period > 1 && !h->sort_next && h->issued % h->sort_period == 0 &&
-            left >= h->sort_period && k_ev < nev) {
-            // one re-sort period replayed from its graph with the particle
-            // kernels at TPOS positions spread evenly over the period timed
-            // (the kernel slows down over a period as particles drift from
-            // their sorted places, so no single position is typical)
-            const int p = h->parity;
-            if ((rc = ensure_timed_graph(h, p))) return rc;
-            for (int j : h->tset[p]) {
-                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * j], h->tev[0]));
-                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * j + 1], h->tev[1]));
+        const bool sorted = sort_due(h);
+        if (h->use_graph) {
+            const int64_t r = run_length(h, left);
+            GraphEntry *g;
+            if ((rc = get_graph(h, h->parity, sorted, r, true, &g))) return rc;
+            // every event node of the replay gets a fresh pooled event, or a
+            // placeholder once TIMED_MAX kernels are timed
+            for (size_t j = 0; j + 1 < g->marks.size(); j += 2) {
+                hipEvent_t a = h->tev[0], b = h->tev[1];
+                if (k_ev < TIMED_MAX) {
+                    if ((rc = pair(k_ev, a, b))) return rc;
+                    ++k_ev;
+                }
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(g->exec, g->marks[j], a));
+                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(g->exec, g->marks[j + 1], b));
             }
-            h->tset[p].clear();
-            const int ns = (int)(h->tnode[p].size() / 2);
-            for (int j = 0; j < ns && k_ev < nev; ++j) {
-                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * j], ev[2 * k_ev]));
-                HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * j + 1], ev[2 * k_ev + 1]));
-                h->tset[p].push_back(j);
-                ++k_ev;
-            }
-            HIP_TRY(hipGraphLaunch(h->tgraph[p], h->stream));
-            h->parity ^= 1;
-            h->issued += h->sort_period;
-            left -= h->sort_period;
-            k += h->sort_period;
+            HIP_TRY(hipGraphLaunch(g->exec, h->stream));
+            advance(h, sorted, r);
+            left -= r;
+            k += r;
             continue;
         }
-        if (sort_due(h)) {
+        if (sorted) {
             if ((rc = enqueue_sort(h, h->stream, h->parity))) return rc;
             h->parity ^= 1;
             h->sort_next = false;
         }
-        const bool rec = !h->use_graph && (k % every) == 0 && k_ev < nev;
-        if (rec) HIP_TRY(hipEventRecord(ev[2 * k_ev], h->stream));
-        HIP_TRY(picx_launch_particles(h->dD, h->dS, h->nd, 0, h->ppt, h->grid, h->parity, h->stream));
+        hipEvent_t a = nullptr, b = nullptr;
+        const bool rec = (k % every) == 0 && k_ev < TIMED_MAX;
         if (rec) {
-            HIP_TRY(hipEventRecord(ev[2 * k_ev + 1], h->stream));
+            if ((rc = pair(k_ev, a, b))) return rc;
             ++k_ev;
+            HIP_TRY(hipEventRecord(a, h->stream));
         }
+        HIP_TRY(picx_launch_particles(h->dD, h->dS, h->nd, 0, h->ppt, h->grid, h->parity, h->stream));
+        if (rec) HIP_TRY(hipEventRecord(b, h->stream));
         HIP_TRY(picx_launch_sources_field(h->dD, h->dS, h->nd, 0, h->max_nodes, h->parity, h->stream));
         h->issued++;
         --left;
         ++k;
     }
-    HIP_TRY(hipEventRecord(t1, h->stream));
-    HIP_TRY(hipEventSynchronize(t1));
+    HIP_TRY(hipEventRecord(h->tt[1], h->stream));
+    HIP_TRY(hipEventSynchronize(h->tt[1]));
     double acc = 0.0;
     for (int64_t q = 0; q < k_ev; ++q) {
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]));
+        HIP_TRY(hipEventElapsedTime(&ms, h->evpool[2 * q], h->evpool[2 * q + 1]));
         acc += ms;
     }
     float tot = 0.f;
-    HIP_TRY(hipEventElapsedTime(&tot, t0, t1));
-    if ((rc = live_sum(live1))) return rc;
-    // the replayed graphs must not keep this call's events
-    for (int p = 0; p < 2; ++p) {
-        for (int j : h->tset[p]) {
-            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * j], h->tev[0]));
-            HIP_TRY(hipGraphExecEventRecordNodeSetEvent(h->tgraph[p], h->tnode[p][2 * j + 1], h->tev[1]));
-        }
-        h->tset[p].clear();
-    }
-    for (auto &e : ev) (void)hipEventDestroy(e);
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    if (particle_kernel_ms) *particle_kernel_ms = k_ev ? acc / (double)k_ev : NAN;
-    if (mean_live) {
-        double a = 0, b = 0;
-        for (int s = 0; s < NSP; ++s) { a += live0[s]; b += live1[s]; }
-        *mean_live = 0.5 * (a + b);
-    }
+    HIP_TRY(hipEventElapsedTime(&tot, h->tt[0], h->tt[1]));
+    if (k_ev == 0) return fail(PIC_EHIP, "no particle kernel was timed");
+    if (particle_kernel_ms) *particle_kernel_ms = acc / (double)k_ev;
     if (total_ms) *total_ms = tot;
     return PIC_OK;
 }
@@ -1057,21 +1107,7 @@ int pic_set_tuning(pic_handle *h, int ppt, int grid, int sort_period, int use_gr
     h->grid = grid ? (grid + 7) / 8 * 8 : grid_for(h);
     if (sort_period) h->sort_period = sort_period;
     if (use_graph >= 0) h->use_graph = use_graph != 0;
-    for (auto &g : h->graph)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
-    for (auto &g : h->tgraph)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
-    for (auto &g : h->tsrc)
-        if (g) {
-            (void)hipGraphDestroy(g);
-            g = nullptr;
-        }
+    h->drop_graphs();
     return PIC_OK;
 }
 
@@ -1223,7 +1259,7 @@ int pic_steady_state(pic_handle *h, int diode, int block_tallies, double tol_pp,
 namespace {
 
 constexpr char CKPT_MAGIC[8] = {'P', 'I', 'C', 'C', 'K', 'P', 'T', '1'};
-constexpr uint32_t CKPT_VERSION = 1;
+constexpr uint32_t CKPT_VERSION = 2;
 
 struct CkptHeader {
     char magic[8];
@@ -1369,7 +1405,22 @@ int pic_load(pic_handle *h, const void *host_buf, size_t bytes)
                 std::memcpy(&n, c, sizeof(n));
                 if (n < 0 || n > h->der[d].capacity[s] || n != st[d].n[s])
                     return fail(PIC_ENOSPACE, "checkpoint particles exceed this handle's capacity");
-                c += sizeof(n) + (size_t)n * (8 + 4 + 4 + sizeof(ColdRec));
+                c += sizeof(n);
+                if (c + (size_t)n * (8 + 4 + 4 + sizeof(ColdRec)) > end) return fail(PIC_EINVAL, "checkpoint truncated");
+                // slots hold live particles (0 < z < L) or holes (z < 0); velocities finite
+                const char *zc = c, *vc = c + (size_t)n * 8, *cc0 = c + (size_t)n * 16;
+                for (int32_t i = 0; i < n; ++i) {
+                    double z;
+                    float vz;
+                    ColdRec cr;
+                    std::memcpy(&z, zc + (size_t)i * 8, 8);
+                    std::memcpy(&vz, vc + (size_t)i * 4, 4);
+                    std::memcpy(&cr, cc0 + (size_t)i * sizeof(ColdRec), sizeof(ColdRec));
+                    if (!std::isfinite(z) || !std::isfinite(vz) || !std::isfinite(cr.vx) || !std::isfinite(cr.vy))
+                        return fail(PIC_ENAN, "checkpoint holds a non-finite particle");
+                    if (z >= cfg.L || z == 0.0) return fail(PIC_EINVAL, "checkpoint particle outside the gap");
+                }
+                c += (size_t)n * (8 + 4 + 4 + sizeof(ColdRec));
             }
             if (c > end) return fail(PIC_EINVAL, "checkpoint truncated");
         }

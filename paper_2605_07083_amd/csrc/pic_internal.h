@@ -35,6 +35,8 @@ constexpr uint32_t ERR_CAPACITY = 1u;
 constexpr uint32_t ERR_NULLCOLL = 2u;
 constexpr uint32_t ERR_NAN = 4u;
 constexpr uint32_t ERR_IZQ = 8u;
+constexpr uint32_t ERR_RANGE = 16u;   // a node's deposit reached 2^53 (2^21 particles of one species)
+constexpr unsigned long long DEPOSIT_LIMIT = 1ull << 53;
 
 // physical constants (CODATA 2018)
 constexpr double Q_E = 1.602176634e-19;
@@ -87,6 +89,7 @@ struct DiodeTally {
     unsigned long long n_emit, n_repl, n_iz;
     unsigned long long cand[2];
     unsigned long long coll[NCH];
+    unsigned long long rare_spill;   // rare items the particle kernel moved to the global lists
 };
 
 struct TallySnap {

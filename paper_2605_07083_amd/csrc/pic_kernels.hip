@@ -1755,6 +1755,9 @@ __device__ __forceinline__ void step_sources(const Diode &dd, DiodeState *st, un
         // items the particle kernel's queues could not hold: they may queue
         // ionisations, so the counters are read again afterwards
         __syncthreads();
+        if (tid == 0)
+            atomicAdd(&dd.tally->rare_spill,
+                      (unsigned long long)(s_st.rare_n[SP_P] + s_st.rare_n[SP_E] + s_st.rare_n[SP_I]));
         process_rare(dd, s_st.rare_n, parity, step, tid, FT, rt);
         __syncthreads();
         if (tid >= 64 && tid < 128) load_state(st, &s_st);
@@ -1904,7 +1907,9 @@ __global__ __launch_bounds__(FT) void k_sources_field_lds(const Diode *__restric
         dd.E[j] = E;
 #pragma unroll
         for (int s = 0; s < NSP; ++s) {
-            const long long h = (long long)dd.H[s][j];
+            const unsigned long long hu = dd.H[s][j];
+            if (hu >= DEPOSIT_LIMIT) atomicOr(&st->err, ERR_RANGE);
+            const long long h = (long long)hu;
             dd.Hlast[s][j] = h;
             dd.H[s][j] = 0ull;
             if (avg) dd.Hsum[s][j] += h;
@@ -2102,11 +2107,13 @@ __global__ __launch_bounds__(FT) void k_field_solve(const Diode *__restrict__ D,
         const int avg = st->avg_on;
 #pragma unroll
         for (int sp = 0; sp < NSP; ++sp) {
-            long long h = (long long)dd.H[sp][j];
+            unsigned long long hu = dd.H[sp][j];
             if (mode == 0) {
-                h += (long long)dd.Hb[sp][j];
+                hu += dd.Hb[sp][j];
                 dd.Hb[sp][j] = 0ull;
             }
+            if (hu >= DEPOSIT_LIMIT) atomicOr(&st->err, ERR_RANGE);
+            const long long h = (long long)hu;
             dd.Hlast[sp][j] = h;
             dd.H[sp][j] = 0ull;
             if (avg) dd.Hsum[sp][j] += h;

@@ -36,7 +36,7 @@ class PicTally(C.Structure):
     _fields_ = [("step", C.c_int64), ("n_live", C.c_int64 * 3), ("abs_count", (C.c_int64 * 2) * 3),
                 ("abs_energy", (C.c_double * 2) * 3), ("n_emit", C.c_int64), ("n_repl", C.c_int64),
                 ("n_iz", C.c_int64), ("cand", C.c_int64 * 2), ("coll", C.c_int64 * 5),
-                ("next_id", C.c_uint32), ("err_bits", C.c_uint32)]
+                ("next_id", C.c_uint32), ("err_bits", C.c_uint32), ("rare_spill", C.c_int64)]
 
 
 _DIAG_SCALARS = ("gamma_emit", "gamma_emit_meas", "gamma_ref", "gamma_net", "gamma_anode",
@@ -65,7 +65,7 @@ class PicDerived(C.Structure):
                 ("emit_per_step", C.c_double), ("capacity", C.c_int64 * 3)]
 
 
-SYMBOLS = ["pic_derive", "pic_workspace_size", "pic_init", "pic_init_from_profiles", "pic_init_from_state", "pic_step", "pic_sync", "pic_get_tally",
+SYMBOLS = ["pic_derive", "pic_workspace_size", "pic_init", "pic_init_from_profiles", "pic_init_from_state", "pic_step", "pic_sync", "pic_get_tally", "pic_get_snapshot",
            "pic_diagnostics", "pic_get_fields", "pic_avg_reset", "pic_avg_control", "pic_get_hist", "pic_get_efield", "pic_phase_space",
            "pic_get_particles", "pic_set_particles", "pic_set_counters", "pic_refield",
            "pic_step_timed", "pic_set_tuning", "pic_get_tuning", "pic_autotune", "pic_steady_state", "pic_steady_from_series", "pic_checkpoint_size", "pic_save", "pic_load", "pic_last_error",
@@ -92,6 +92,7 @@ def lib():
         "pic_step": ([P, i64], i),
         "pic_sync": ([P], i),
         "pic_get_tally": ([P, i, C.POINTER(PicTally)], i),
+        "pic_get_snapshot": ([P, i, i64, C.POINTER(PicTally)], i),
         "pic_diagnostics": ([P, i, i64, C.POINTER(PicDiag)], i),
         "pic_get_fields": ([P, i, P, P, P, i], i),
         "pic_avg_reset": ([P, i], i),
@@ -103,7 +104,7 @@ def lib():
         "pic_set_particles": ([P, i, i, i64, P, P, P, P, P, P], i),
         "pic_set_counters": ([P, i, i64, C.c_uint32], i),
         "pic_refield": ([P], i),
-        "pic_step_timed": ([P, i64, C.POINTER(d), C.POINTER(d), C.POINTER(d)], i),
+        "pic_step_timed": ([P, i64, C.POINTER(d), C.POINTER(d)], i),
         "pic_set_tuning": ([P, i, i, i, i], i),
         "pic_get_tuning": ([P, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i)], i),
         "pic_autotune": ([P, i64, C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(i), C.POINTER(d)], i),
@@ -187,6 +188,15 @@ def steady_from_series(br, n_live, tol_pp=1.0, tol_rel=0.01):
     return {"steady_block": b.value, "backflow_pct": v.value, "blocks_averaged": m.value}
 
 
+def _tally_dict(t):
+    return {"step": t.step, "n_live": np.array(list(t.n_live)),
+            "abs_count": np.array([[t.abs_count[s][w] for w in range(2)] for s in range(3)]),
+            "abs_energy": np.array([[t.abs_energy[s][w] for w in range(2)] for s in range(3)]),
+            "n_emit": t.n_emit, "n_repl": t.n_repl, "n_iz": t.n_iz,
+            "cand": np.array(list(t.cand)), "coll": np.array(list(t.coll)),
+            "next_id": t.next_id, "err_bits": t.err_bits, "rare_spill": t.rare_spill}
+
+
 class Handle:
     """One or more diodes advanced together on one GPU."""
 
@@ -257,21 +267,29 @@ class Handle:
     def refield(self):
         _check(lib().pic_refield(self.h))
 
+    def live_total(self):
+        """Live particles summed over every diode and species (synchronises)."""
+        return int(sum(self.tally(d)["n_live"].sum() for d in range(self.nd)))
+
     def step_timed(self, n):
-        k, live, tot = C.c_double(), C.c_double(), C.c_double()
-        _check(lib().pic_step_timed(self.h, int(n), C.byref(k), C.byref(live), C.byref(tot)))
-        return {"particle_kernel_ms": k.value, "mean_live": live.value, "total_ms": tot.value}
+        """pic_step_timed: mean particle-kernel duration and the events' total
+        (ms).  Nothing is read from the device inside; the caller reads live
+        counts before and after (live_total)."""
+        k, tot = C.c_double(), C.c_double()
+        _check(lib().pic_step_timed(self.h, int(n), C.byref(k), C.byref(tot)))
+        return {"particle_kernel_ms": k.value, "total_ms": tot.value}
 
     # --- state access ---------------------------------------------------
     def tally(self, d=0):
         t = PicTally()
         _check(lib().pic_get_tally(self.h, d, C.byref(t)))
-        return {"step": t.step, "n_live": np.array(list(t.n_live)),
-                "abs_count": np.array([[t.abs_count[s][w] for w in range(2)] for s in range(3)]),
-                "abs_energy": np.array([[t.abs_energy[s][w] for w in range(2)] for s in range(3)]),
-                "n_emit": t.n_emit, "n_repl": t.n_repl, "n_iz": t.n_iz,
-                "cand": np.array(list(t.cand)), "coll": np.array(list(t.coll)),
-                "next_id": t.next_id, "err_bits": t.err_bits}
+        return _tally_dict(t)
+
+    def snapshot(self, d, step):
+        """Tallies of diode d at the end of tally step `step` (pic_get_snapshot)."""
+        t = PicTally()
+        _check(lib().pic_get_snapshot(self.h, d, int(step), C.byref(t)))
+        return _tally_dict(t)
 
     def diagnostics(self, d=0, window_steps=0):
         o = PicDiag()

@@ -306,21 +306,35 @@ def evaluate(data, weights=None, out=None, profiles_only=False, **kw):
             rows.append({"case": i, "cold_steady_step": int(z["steady_step"][i]),
                          "warm_steady_step": r["steady_step"], "cold_backflow_pct": float(z["backflow_pct"][i]),
                          "warm_backflow_pct": r["backflow_pct"]})
-    ok = [r for r in rows if r["cold_steady_step"] > 0 and r["warm_steady_step"] > 0]
-    ratio = np.array([r["cold_steady_step"] / r["warm_steady_step"] for r in ok])
-    dbr = np.array([abs(r["warm_backflow_pct"] - r["cold_backflow_pct"]) for r in ok])
-    summ = {"cases": n, "both_steady": len(ok),
-            "median_cold_steps": float(np.median([r["cold_steady_step"] for r in ok])) if ok else None,
-            "median_warm_steps": float(np.median([r["warm_steady_step"] for r in ok])) if ok else None,
-            "median_speedup": float(np.median(ratio)) if ok else None,
-            "frac_speedup_ge_3": float(np.mean(ratio >= 3)) if ok else None,
-            "median_abs_dBR_pp": float(np.median(dbr)) if ok else None,
-            "frac_dBR_le_1pp": float(np.mean(dbr <= 1.0)) if ok else None,
-            "frac_speedup_ge_3_and_dBR_le_1pp": float(np.mean((ratio >= 3) & (dbr <= 1.0))) if ok else None}
+    summ = summarize(rows)
+    summ["cases"] = n
     _log("evaluate: %s" % summ)
     if out:
         json.dump({"summary": summ, "rows": rows}, open(out, "w"), indent=1)
     return summ
+
+
+def summarize(rows):
+    """Warm-vs-cold summary over the cases whose cold run reached steady.  A
+    warm run that never reached steady counts as a failure: speedup 0 and
+    backflow error infinite (so it lowers the medians and the shares instead
+    of dropping out)."""
+    base = [r for r in rows if r["cold_steady_step"] > 0]
+    ratio = np.array([r["cold_steady_step"] / r["warm_steady_step"] if r["warm_steady_step"] > 0 else 0.0
+                      for r in base])
+    dbr = np.array([abs(r["warm_backflow_pct"] - r["cold_backflow_pct"]) if r["warm_steady_step"] > 0
+                    else np.inf for r in base])
+    warm_ok = [r for r in base if r["warm_steady_step"] > 0]
+    have = len(base) > 0
+    return {"cold_steady": len(base), "warm_never_steady": len(base) - len(warm_ok),
+            "median_cold_steps": float(np.median([r["cold_steady_step"] for r in base])) if have else None,
+            "median_warm_steps": float(np.median([r["warm_steady_step"] if r["warm_steady_step"] > 0 else np.inf
+                                                  for r in base])) if have else None,
+            "median_speedup": float(np.median(ratio)) if have else None,
+            "frac_speedup_ge_3": float(np.mean(ratio >= 3)) if have else None,
+            "median_abs_dBR_pp": float(np.median(dbr)) if have else None,
+            "frac_dBR_le_1pp": float(np.mean(dbr <= 1.0)) if have else None,
+            "frac_speedup_ge_3_and_dBR_le_1pp": float(np.mean((ratio >= 3) & (dbr <= 1.0))) if have else None}
 
 
 def main(argv=None):
@@ -347,17 +361,23 @@ def main(argv=None):
     e.add_argument("--profiles-only", action="store_true", help="load densities only (Maxwellian velocities)")
     e.add_argument("--out")
     e.add_argument("--max-steps", type=int, default=300000)
+    for q in (g, e):
+        q.add_argument("--block-steps", type=int, default=BLOCK_STEPS, help="detector block (steps)")
+        q.add_argument("--tol-rel", type=float, default=None,
+                       help="detector live-count tolerance per block (default 1e-7 per step)")
+        q.add_argument("--avg-blocks", type=int, default=AVG_BLOCKS, help="blocks averaged after steady")
     a = ap.parse_args(argv)
     if a.cmd == "generate":
         seed = {"train": presets.SURROGATE_TRAIN_SEED, "heldout": presets.SURROGATE_HELDOUT_SEED}.get(a.seed)
         generate(a.n, int(a.seed, 0) if seed is None else seed, a.out, first=a.first, count=a.count,
-                 max_steps=a.max_steps)
+                 max_steps=a.max_steps, block_steps=a.block_steps, tol_rel=a.tol_rel, avg_blocks=a.avg_blocks)
     elif a.cmd == "train":
         rep = train(a.data, a.out, epochs=a.epochs, batch=a.batch, lr=a.lr, heldout=a.heldout)
         if a.report:
             json.dump(rep, open(a.report, "w"), indent=1)
     else:
-        evaluate(a.data, a.weights, a.out, profiles_only=a.profiles_only, max_steps=a.max_steps)
+        evaluate(a.data, a.weights, a.out, profiles_only=a.profiles_only, max_steps=a.max_steps,
+                 block_steps=a.block_steps, tol_rel=a.tol_rel, avg_blocks=a.avg_blocks)
 
 
 if __name__ == "__main__":

@@ -78,23 +78,67 @@ def compare_particles(cfg, gp, op, sp, rel=REL):
     return probs
 
 
-def compare_tallies(gt0, gt1, ot0, ot1, rel=REL):
+def compare_tallies(gt0, gt1, ot0, ot1, rel=REL, slack=0):
+    """Counts must agree exactly; with slack > 0 (a step with that many
+    near-ties) each count may differ by up to slack and the energies are not
+    compared."""
     probs = []
     for k in ("abs_count", "cand", "coll"):
         dg = np.asarray(gt1[k]) - np.asarray(gt0[k])
         do = np.asarray(ot1[k]) - np.asarray(ot0[k])
-        if not np.array_equal(dg, do):
+        if np.abs(dg - do).max() > slack:
             probs.append("%s: gpu %s oracle %s" % (k, dg.tolist(), do.tolist()))
     for k in ("n_emit", "n_repl", "n_iz"):
         dg, do = gt1[k] - gt0[k], ot1[k] - ot0[k]
-        if dg != do:
+        if abs(dg - do) > slack:
             probs.append("%s: gpu %d oracle %d" % (k, dg, do))
+    if slack:
+        return probs
     eg = np.asarray(gt1["abs_energy"]) - np.asarray(gt0["abs_energy"])
     eo = np.asarray(ot1["abs_energy"]) - np.asarray(ot0["abs_energy"])
     scale = np.maximum(np.abs(eo), 1e-30)
     if (np.abs(eg - eo) / scale > rel).any():
         probs.append("abs_energy: gpu %s oracle %s" % (eg.tolist(), eo.tolist()))
     return probs
+
+
+# A decision taken in FP32 on the GPU and in FP64 by the oracle may fall on
+# different sides when the particle sat within rounding of it: a wall
+# crossing within WALL_TIE of the electrode, or a channel choice whose uniform
+# lay within CHANNEL_TIE (relative to nu_max) of a cumulative boundary.
+WALL_TIE = 1e-9       # of L
+CHANNEL_TIE = 1e-6
+
+
+def near_ties(cfg, s, gpu_after, rel=REL):
+    """Particles whose outcome in the oracle's last step differs from the
+    GPU's: (species, id, kind, margin, tie).  tie is True when the margin is
+    within the rounding band of the decision (a legitimate near-tie)."""
+    L = cfg["L"]
+    out = []
+    for sp in range(3):
+        m = s.last_moves(sp)
+        g, o = gpu_after[sp], s.particles(sp)
+        gi = {int(i): k for k, i in enumerate(g["id"])}
+        oi = {int(i): k for k, i in enumerate(o["id"])}
+        vt = vth(cfg, sp)
+        for k in range(len(m["id"])):
+            pid = int(m["id"][k])
+            ig, io = gi.get(pid), oi.get(pid)
+            if (ig is None) != (io is None):
+                z = m["z"][k]
+                margin = min(abs(z), abs(L - z)) / L
+                out.append((sp, pid, "wall", margin, margin < WALL_TIE))
+            elif ig is not None and m["ch"][k] >= -1:
+                dv = max(abs(float(g[c][ig]) - o[c][io]) / max(abs(o[c][io]), vt) for c in ("vx", "vy", "vz"))
+                if dv > rel:
+                    out.append((sp, pid, "channel", m["margin"][k], m["margin"][k] < CHANNEL_TIE))
+    return out
+
+
+def _without(p, ids, newborn_from):
+    keep = ~np.isin(p["id"], list(ids)) & (p["id"] < newborn_from)
+    return {k: np.asarray(v)[keep] for k, v in p.items()}
 
 
 def deposit_matches(O, cfg, h, st, d=0):
@@ -140,9 +184,14 @@ def field_matches(O, cfg, h, s, d=0, tol=1e-10, exact=False):
     return probs
 
 
-def restart_step_check(O, cfg, h, nsteps, d=0, check_every=1, exact_field=False):
-    """Advance GPU and oracle from the same state one step at a time; collect problems."""
+def restart_step_check(O, cfg, h, nsteps, d=0, check_every=1, exact_field=False, max_ties=1, ties=None):
+    """Advance GPU and oracle from the same state one step at a time; collect
+    problems.  A step whose disagreement is fully explained by near-ties
+    (near_ties) passes and is reported, up to max_ties over the run; a
+    near-tie step's newborns are not compared (their ids may shift).  The
+    near-ties found are appended to `ties` when given."""
     probs = []
+    n_ties = 0
     for k in range(nsteps):
         st, gt0 = gpu_state(h, d)
         if k % check_every == 0:
@@ -155,13 +204,34 @@ def restart_step_check(O, cfg, h, nsteps, d=0, check_every=1, exact_field=False)
         h.step(1)
         if k % check_every == 0:
             st1, gt1 = gpu_state(h, d)
+            step_probs = []
             for sp in range(3):
-                for p in compare_particles(cfg, st1[sp], s.particles(sp), sp):
-                    probs.append("step %d: %s" % (gt0["step"], p))
-            for p in compare_tallies(gt0, gt1, ot0, ot1):
-                probs.append("step %d: %s" % (gt0["step"], p))
+                step_probs += compare_particles(cfg, st1[sp], s.particles(sp), sp)
+            step_probs += compare_tallies(gt0, gt1, ot0, ot1)
             if gt1["next_id"] != s.next_id:
-                probs.append("step %d: next_id gpu %d oracle %d" % (gt0["step"], gt1["next_id"], s.next_id))
+                step_probs.append("next_id gpu %d oracle %d" % (gt1["next_id"], s.next_id))
+            if step_probs:
+                found = near_ties(cfg, s, st1)
+                real = [t for t in found if not t[4]]
+                if found and not real and n_ties + len(found) <= max_ties:
+                    ids = {t[1] for t in found}
+                    nb = int(gt0["next_id"])
+                    again = []
+                    for sp in range(3):
+                        again += compare_particles(cfg, _without(st1[sp], ids, nb), _without(s.particles(sp), ids, nb),
+                                                   sp)
+                    again += compare_tallies(gt0, gt1, ot0, ot1, slack=len(found))
+                    if not again:
+                        n_ties += len(found)
+                        for t in found:
+                            print("near-tie at step %d: species %d id %d, %s margin %.3g" % (
+                                gt0["step"], t[0], t[1], t[2], t[3]), flush=True)
+                        if ties is not None:
+                            ties.extend(found)
+                        step_probs = []
+                if step_probs and found:
+                    step_probs.append("decisions that differ: %s" % (found[:5],))
+            probs += ["step %d: %s" % (gt0["step"], p) for p in step_probs]
         if len(probs) > 20:
             break
     return probs

@@ -29,20 +29,20 @@ TALLIES = "tests/test_oracle_tallies.py"
 
 MUTANTS = [
     ("energy at the previous half step",
-     "tally_abs(o, sp, z <= 0.0 ? 0 : 1, vx, vy, vz);",
-     "tally_abs(o, sp, z <= 0.0 ? 0 : 1, vx, vy, s->vz[p]);",
+     "tally_abs(o, sp, m->fate - 1, m->v[0], m->v[1], m->v[2]);",
+     "tally_abs(o, sp, m->fate - 1, m->v[0], m->v[1], s->vz[p]);",
      TALLIES + "::test_absorbed_energy_is_full_3v_energy_at_crossing"),
     ("energy without v_x, v_y",
-     "tally_abs(o, sp, z <= 0.0 ? 0 : 1, vx, vy, vz);",
-     "tally_abs(o, sp, z <= 0.0 ? 0 : 1, 0.0, 0.0, vz);",
+     "tally_abs(o, sp, m->fate - 1, m->v[0], m->v[1], m->v[2]);",
+     "tally_abs(o, sp, m->fate - 1, 0.0, 0.0, m->v[2]);",
      TALLIES + "::test_absorbed_energy_is_full_3v_energy_at_crossing"),
     ("newborn beyond the anode not tallied",
      "if (z >= c->L) { tally_abs(o, sp, 1, vx, vy, vz); return 0; }",
      "if (z >= c->L) { return 0; }",
      TALLIES + "::test_newborn_beyond_the_anode_is_absorbed_at_once"),
     ("load on half the gap",
-     "double z = c->L * o_u53(b1[0], b1[1]);",
-     "double z = 0.5 * c->L * o_u53(b1[0], b1[1]);",
+     "S->z[p] = c->L * o_u53(b1[0], b1[1]);",
+     "S->z[p] = 0.5 * c->L * o_u53(b1[0], b1[1]);",
      TALLIES + "::test_initial_load_uniform_and_maxwellian"),
     ("ions loaded at the electron temperature",
      "        double T = (s == OSP_I) ? c->Ti0 : c->Te0;\n        double sig",
