@@ -232,9 +232,11 @@ def main():
     K = tune["sort_period"]
 
     def align():
-        # run to the next re-sort boundary, so the timed steps start with a re-sort
+        # position the schedule so that the timed steps end at a re-sort
+        # boundary: they then hold floor(steps / K) whole re-sort periods, each
+        # with its re-sort, after the last steps of the period before them
         t = h.tally(0)["step"]
-        h.step((K - t % K) % K)
+        h.step((K - (t + args.steps) % K) % K)
 
     # untimed: two passes of the same length from the same schedule position
     # as the timed pass.  Each re-sort flips the particle buffer, and the
@@ -276,7 +278,8 @@ def main():
         "config": {"workload": desc, "n_diodes": len(cfgs), "cells": cfgs[0]["N"],
                    "particles_per_species": cfgs[0]["n_load"], "live_particles": live,
                    "schedule": {k: tune[k] for k in ("ppt", "grid", "sort_period", "use_graph")},
-                   "timed_from": "a re-sort boundary (the timed steps include ceil(steps / sort_period) re-sorts)",
+                   "timed_window": "ends at a re-sort boundary: floor(steps / sort_period) re-sorts inside, "
+                                   "after the last steps % sort_period steps of the period before them",
                    "events_ms": r["total_ms"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
