@@ -78,6 +78,20 @@ int sur_get_grads(sur_net *n, float *w, float *b);
  * device; dev_out [batch][SUR_OUT][cells] FP32 on the device. */
 int sur_forward(sur_net *n, const float *dev_params, int batch, float *dev_out);
 
+/* sur_forward for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same output bit for bit, with the activations in a
+ * library-held static device array of 12 MiB per GPU instead of the handle's
+ * workspace, so any batch size runs (in chunks of samples that fit it: 8
+ * samples of 2048 cells).  Allocates nothing: no hipMalloc, hipFree or
+ * allocating library call.  The handle's GPU must be current (PIC_EINVAL
+ * otherwise); cells beyond 17096 per sample do not fit the array and are
+ * refused (PIC_EINVAL).  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (on different streams, or from several threads)
+ * race and must be ordered by the caller.  Asynchronous on the handle's
+ * stream. */
+int sur_forward_noalloc(sur_net *n, const float *dev_params, int batch, float *dev_out);
+
 /* One training step on a batch: forward, loss = mean over (b, c, x) of
  * (out - target)^2, backward (input and weight gradients on the matrix
  * cores; the gradient entering each layer rounded to bfloat16), one Adam

@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -85,6 +87,8 @@ struct Bump {
 
 struct sur_net {
     int X = 0, bmax = 0;
+    int device = -1;              // the GPU current at sur_create
+    char *scratch = nullptr;      // that GPU's copy of the allocation-free forward's scratch array
     hipStream_t stream = nullptr;
     char *ws = nullptr;
     size_t param_bytes = 0;       // weights, moments, grads: the first bytes of ws
@@ -206,6 +210,49 @@ int copy_out(sur_net *n, bool grads, float *w, float *b)
     return PIC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free forward pass (sur_forward_noalloc): one
+// file-scope device array, so that the call needs no device memory beyond
+// the handle's weights and the caller's inputs and outputs.  Every GPU the
+// library runs on holds its own copy until the process ends.  In host code
+// the array's name is not a device address: its address on a GPU comes from
+// hipGetSymbolAddress with that GPU current (scratch_on_current_device).
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = (size_t)12 << 20;
+// per sample and cell: features (16 bf16), a hidden output in FP32 (64,
+// overwritten layer after layer), the last layer's FP32 output (48 padded
+// channels) and two bf16 ping-pong copies of the hidden activations (64 each)
+constexpr size_t SCRATCH_PER_POSITION = 16 * 2 + 64 * 4 + 48 * 4 + 2 * 64 * 2;
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The scratch array's address on the current GPU, looked up once per GPU.
+int scratch_on_current_device(int *device, char **ptr)
+{
+    int dev = -1;
+    SUR_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(PIC_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PIC_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<char *>(p);
+    }
+    *device = dev;
+    *ptr = g_scratch_ptr[dev];
+    return PIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -242,6 +289,8 @@ int sur_create(int max_batch, int cells, void *dev_workspace, size_t bytes, void
     Bump bp{n->ws};
     layout(*n, bp);
     auto cleanup = [&](int code) { delete n; return code; };
+    // the allocation-free forward's scratch on this GPU (set-up, once per GPU)
+    if ((rc = scratch_on_current_device(&n->device, &n->scratch))) return cleanup(rc);
     if (hipMemsetAsync(n->ws, 0, n->param_bytes, n->stream) != hipSuccess)
         return cleanup(fail(PIC_EHIP, "hipMemsetAsync failed"));
     for (int l = 0; l < SUR_LAYERS; ++l) {
@@ -290,6 +339,39 @@ int sur_forward(sur_net *n, const float *dev_params, int batch, float *dev_out)
     int rc = forward(n, dev_params, batch, false);
     if (rc) return rc;
     SUR_TRY(surx_unpack(n->yf[SUR_LAYERS - 1], dev_out, n->X, batch, n->stream));
+    return PIC_OK;
+}
+
+int sur_forward_noalloc(sur_net *n, const float *dev_params, int batch, float *dev_out)
+{
+    if (!n || !dev_params || !dev_out) return fail(PIC_EINVAL, "bad arguments");
+    if (batch < 1) return fail(PIC_EINVAL, "batch must be positive");
+    const size_t per_sample = SCRATCH_PER_POSITION * (size_t)n->X;
+    const int chunk = (int)std::min<size_t>(SCRATCH_BYTES / per_sample, (size_t)batch);
+    if (chunk < 1)
+        return fail(PIC_EINVAL, "cells beyond the scratch array: at most " +
+                                    std::to_string(SCRATCH_BYTES / SCRATCH_PER_POSITION) + " per sample");
+    int dev = -1;
+    SUR_TRY(hipGetDevice(&dev));
+    if (dev != n->device) return fail(PIC_EINVAL, "the handle's GPU is not the current device");
+    char *base = n->scratch;     // the array's address on this GPU, never its host-side name
+    const size_t P = (size_t)chunk * n->X;
+    __bf16 *feat = reinterpret_cast<__bf16 *>(base);
+    float *yf = reinterpret_cast<float *>(base + P * 16 * 2);
+    float *yout = reinterpret_cast<float *>(base + P * (16 * 2 + 64 * 4));
+    __bf16 *yb[2] = {reinterpret_cast<__bf16 *>(base + P * (16 * 2 + 64 * 4 + 48 * 4)),
+                     reinterpret_cast<__bf16 *>(base + P * (16 * 2 + 64 * 4 + 48 * 4 + 64 * 2))};
+    for (int b0 = 0; b0 < batch; b0 += chunk) {
+        const int nb = std::min(chunk, batch - b0);
+        SUR_TRY(surx_features(dev_params + (size_t)4 * b0, feat, nullptr, n->X, nb, n->stream));
+        for (int l = 0; l < SUR_LAYERS; ++l) {
+            const __bf16 *in = l == 0 ? feat : yb[(l - 1) & 1];
+            const bool last = l == SUR_LAYERS - 1;
+            SUR_TRY(surx_conv_fwd(l, in, n->L[l].wf, n->L[l].bias, last ? yout : yf, last ? nullptr : yb[l & 1],
+                                  nullptr, n->X, nb, n->stream));
+        }
+        SUR_TRY(surx_unpack(yout, dev_out + (size_t)b0 * SUR_OUT * n->X, n->X, nb, n->stream));
+    }
     return PIC_OK;
 }
 

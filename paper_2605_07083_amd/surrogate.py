@@ -15,7 +15,8 @@ N_BIASES = sum(co for _, co in LAYERS)
 N_OUT = LAYERS[-1][1]
 
 SYMBOLS = ["sur_workspace_size", "sur_create", "sur_set_weights", "sur_get_weights", "sur_get_grads",
-           "sur_forward", "sur_train_step", "sur_densities", "sur_state", "sur_last_error", "sur_destroy"]
+           "sur_forward", "sur_forward_noalloc", "sur_train_step", "sur_densities", "sur_state", "sur_last_error",
+           "sur_destroy"]
 
 _bound = False
 
@@ -32,6 +33,7 @@ def lib():
             "sur_get_weights": ([P, P, P], i),
             "sur_get_grads": ([P, P, P], i),
             "sur_forward": ([P, P, i, P], i),
+            "sur_forward_noalloc": ([P, P, i, P], i),
             "sur_train_step": ([P, P, P, i, f, C.POINTER(d)], i),
             "sur_densities": ([P, P, P, i, P], i),
             "sur_state": ([P, P, P, i, P], i),

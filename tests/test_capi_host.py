@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= set(pic.SYMBOLS)
     from paper_2605_07083_amd import surrogate
     names = _declared("surrogate.h", "sur")
-    assert len(names) == 11
+    assert len(names) == 12
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(surrogate.SYMBOLS)
