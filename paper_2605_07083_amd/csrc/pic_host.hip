@@ -1434,6 +1434,8 @@ int pic_load(pic_handle *h, const void *host_buf, size_t bytes)
         cc += sizeof(pic_config);
         DiodeState s0 = st[d];
         s0.parity = h->parity;   // the slots go into this handle's current buffer
+        s0.arrive = 0;           // no field step is in flight at a step boundary
+        s0.spill_flag = 0u;
         cc += sizeof(DiodeState);
         if ((rc = xfer<false>(cc, D.tally, sizeof(DiodeTally))) || (rc = xfer<false>(cc, D.ring, sizeof(TallySnap) * RING)))
             return rc;

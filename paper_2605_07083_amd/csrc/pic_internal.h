@@ -79,6 +79,8 @@ struct DiodeState {
     int32_t avg_on;
     int32_t avg_steps;
     int32_t rare_n[NSP];   // rare items (candidates, absorbed) listed this step
+    int32_t arrive;        // field step: blocks that have read this step's counters
+    uint32_t spill_flag;   // field step: step + 1 once the spilled rare items are done
     uint32_t pad;
 };
 

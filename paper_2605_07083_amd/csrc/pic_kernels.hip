@@ -1,15 +1,17 @@
 // pic_kernels.hip -- gfx950 kernels of the 1D3V PIC-MCC thermionic diode.
 //
-// One step of every diode is three launches (plus a cell re-sort every K
+// One step of every diode is two launches (plus a cell re-sort every K
 // steps):
 //   k_particles       gather (LDS field tile) -> leapfrog push -> electrode
 //                     absorption -> null-collision MCC (compacted candidate
 //                     queue) -> 64-bit fixed-point CIC deposit into an LDS
 //                     window histogram flushed with global integer atomics;
-//   k_sources_field   one workgroup per diode: ionisation products (ordered
-//                     by parent id), thermionic emission, pair replenishment,
-//                     then the exact-integer double prefix-scan Poisson
-//                     solve and the field, tallies and snapshots.
+//   k_field_step      one block per tile of 512 nodes of every diode:
+//                     ionisation products (ordered by parent id), thermionic
+//                     emission, pair replenishment, then the exact-integer
+//                     double prefix-scan Poisson solve and the field, tallies
+//                     and snapshots (grids above 16385 nodes: k_field_agg and
+//                     k_field_solve instead).
 // Particles are processed in chunks of 256*PPT slots; the chunk list spans all
 // (diode, species) segments and is walked by a persistent grid whose
 // block -> chunk map keeps consecutive chunks on one XCD.
@@ -1538,7 +1540,6 @@ __device__ __forceinline__ double to_double(I128 a)
 // Sources and field: one workgroup of 1024 threads per diode.
 // mode 0: births, solve, field, tallies, step + 1; mode 1: solve and field only.
 // ---------------------------------------------------------------------------
-constexpr size_t LDS_FIELD_BYTES = 148 * 1024;   // node arrays staged in LDS up to 18944 nodes
 
 __device__ __forceinline__ I128 shfl_up_i128(I128 a, int o)
 {
@@ -1548,14 +1549,14 @@ __device__ __forceinline__ I128 shfl_up_i128(I128 a, int o)
     return r;
 }
 
-// Where the births deposit.  The single-block step adds them to H; the tiled
-// step runs the births beside the tile aggregates, which read H, so there the
-// births deposit into the side histograms Hb and sum their share of each
-// tile's aggregates in LDS: A_t (charge) and B_t (charge times the number of
-// the tile's interior nodes at or after its node), B_t as a 128-bit integer.
+// Where the births of the two-kernel step (grids above 16385 nodes) deposit:
+// they run beside the tile aggregates, which read H, so they deposit into the
+// side histograms Hb and sum their share of each tile's aggregates in LDS:
+// A_t (charge) and B_t (charge times the number of the tile's interior nodes
+// at or after its node), B_t as a 128-bit integer.
 constexpr int MAX_TILES = 32768 / FT;    // N <= 32767
 struct BirthSink {
-    unsigned long long *bA;      // [MAX_TILES] LDS, or nullptr: deposit into H
+    unsigned long long *bA;      // [MAX_TILES] LDS
     unsigned long long *bBlo;
     unsigned long long *bBhi;
 };
@@ -1579,11 +1580,6 @@ __device__ __forceinline__ void deposit_birth(const Diode &dd, const BirthSink &
     double f;
     cic(z, dd.invdz, dd.N, j, f);
     const unsigned long long a = fixed_right(f), l = (1ull << 32) - a;
-    if (!k.bA) {
-        gadd(&glb(dd.H[s])[j], l);
-        gadd(&glb(dd.H[s])[j + 1], a);
-        return;
-    }
     gadd(&glb(dd.Hb[s])[j], l);
     gadd(&glb(dd.Hb[s])[j + 1], a);
     const long long sg = s == SP_I ? 1 : -1;     // charge: ions minus electrons
@@ -1799,9 +1795,8 @@ __device__ __forceinline__ I128 wave_incl_scan_i128(I128 x)
 // phi_j = V j / N + alpha (j T_N - N T_j) / N: the direct solution of the
 // constant-coefficient Dirichlet system, rounded once at the end.
 // ---------------------------------------------------------------------------
-// Same step with the node arrays staged in LDS (dynamic shared memory of
-// nn * 8 bytes): coalesced loads, then each thread walks PER consecutive nodes
-// serially in registers, with two block scans of the per-thread totals.
+// Block scans of the per-thread totals, for the field kernels whose threads
+// each walk consecutive nodes serially in registers.
 __device__ __forceinline__ long long block_scan_excl_i64(long long v, long long *sh, long long &total)
 {
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -1838,100 +1833,9 @@ __device__ __forceinline__ I128 block_scan_excl_i128(I128 v, I128 *sh, I128 &tot
     return add(off, add(incl, neg(v)));
 }
 
-__global__ __launch_bounds__(FT) void k_sources_field_lds(const Diode *__restrict__ D, DiodeState *S,
-                                                          int mode, int parity)
-{
-    // births use the array first as their sort keys, the solve then as R_j and phi_j
-    extern __shared__ long long nodes[];
-    const Diode &dd = D[blockIdx.x];
-    DiodeState *st = dd.st;   // the pointer the rare-item code also writes through
-    const int tid = threadIdx.x;
-    __shared__ long long sh64[FW];
-    __shared__ I128 sh128[FW];
-    __shared__ RareTally rt;
-    const uint32_t step = st->step;
-
-    if (mode == 0)
-        step_sources(dd, st, reinterpret_cast<unsigned long long *>(nodes), step, parity, &rt, BirthSink{});
-    __syncthreads();
-
-    const int N = dd.N;
-    const int nn = N + 1;
-    for (int j = tid; j < nn; j += FT) {
-        long long r = 0;
-        if (j >= 1 && j <= N - 1) r = (long long)(dd.H[SP_I][j] - dd.H[SP_P][j] - dd.H[SP_E][j]);
-        nodes[j] = r;
-    }
-    __syncthreads();
-    const int per = (nn + FT - 1) / FT;
-    const int j0 = tid * per, j1 = min(nn, j0 + per);
-    long long loc = 0;
-    for (int j = j0; j < j1; ++j) loc += nodes[j];
-    long long tot;
-    const long long s1off = block_scan_excl_i64(loc, sh64, tot);
-    I128 tl = i128(0);
-    {
-        long long S1 = s1off;
-        for (int j = j0; j < j1; ++j) {
-            S1 += nodes[j];
-            if (j >= 1 && j <= N - 1) tl = add(tl, i128(S1));
-        }
-    }
-    I128 T_N;
-    I128 T = block_scan_excl_i128(tl, sh128, T_N);
-    const double alpha_n = dd.alpha / (double)N;
-    {
-        long long S1 = s1off;
-        for (int j = j0; j < j1; ++j) {
-            S1 += nodes[j];
-            double v = 0.0;
-            if (j == N) v = dd.V;
-            else if (j >= 1) {
-                const I128 x = add(mul_small(T_N, (unsigned)j), neg(mul_small(T, (unsigned)N)));
-                v = dd.V * (double)j / (double)N + alpha_n * to_double(x);
-            }
-            nodes[j] = __double_as_longlong(v);
-            if (j >= 1 && j <= N - 1) T = add(T, i128(S1));
-        }
-    }
-    __syncthreads();
-    const double inv2dz = 1.0 / (2.0 * dd.dz);
-    const int avg = st->avg_on;
-    for (int j = tid; j < nn; j += FT) {
-        const double pc = __longlong_as_double(nodes[j]);
-        double E;
-        if (j == 0) E = (pc - __longlong_as_double(nodes[1])) / dd.dz;
-        else if (j == N) E = (__longlong_as_double(nodes[N - 1]) - pc) / dd.dz;
-        else E = (__longlong_as_double(nodes[j - 1]) - __longlong_as_double(nodes[j + 1])) * inv2dz;
-        dd.phi[j] = pc;
-        dd.E[j] = E;
-#pragma unroll
-        for (int s = 0; s < NSP; ++s) {
-            const unsigned long long hu = dd.H[s][j];
-            if (hu >= DEPOSIT_LIMIT) atomicOr(&st->err, ERR_RANGE);
-            const long long h = (long long)hu;
-            dd.Hlast[s][j] = h;
-            dd.H[s][j] = 0ull;
-            if (avg) dd.Hsum[s][j] += h;
-        }
-        if (avg) dd.phi_sum[j] += pc;
-    }
-    __syncthreads();
-    if (mode == 0 && tid == 0) {
-        const uint32_t nstep = step + 1u;
-        st->step = nstep;
-        if (avg) st->avg_steps += 1;
-        if (dd.tally_period > 0 && nstep % (uint32_t)dd.tally_period == 0u) {
-            TallySnap &sn = dd.ring[(nstep / (uint32_t)dd.tally_period) % RING];
-            sn.step = nstep;
-            sn.t = *dd.tally;
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Large grids: the same step spread over tiles of FT nodes, so that the node
-// arrays move through many CUs instead of one.
+// Grids above 16385 nodes (whose charge does not fit one block's LDS): the
+// same step over tiles of FT nodes in two kernels.
 //   k_field_agg    per tile: A_t = sum of rho over the tile, B_t = sum over the
 //                  tile's interior nodes of the in-tile inclusive prefix of
 //                  rho; with births (mode 0), one more block per diode runs
@@ -1942,7 +1846,7 @@ __global__ __launch_bounds__(FT) void k_sources_field_lds(const Diode *__restric
 //                  Q_t = sum_{u<t} (n_u P_u + B_u) (= T before the tile) and
 //                  T_N from all tiles (births' shares added), the exact S1_j
 //                  and T_j of its nodes and of one halo node on each side,
-//                  phi_j and E_j as in the single-block kernel, and the node
+//                  phi_j and E_j as in k_field_step, and the node
 //                  bookkeeping.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void births_block(const Diode &dd, int parity)
@@ -2132,6 +2036,384 @@ __global__ __launch_bounds__(FT) void k_field_solve(const Diode *__restrict__ D,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Sources and field in one pass, for grids of up to FUSED_MAX_NODES nodes.
+//
+// Grid (tiles, diodes); block t of a diode writes the nodes [t TILE, (t+1) TILE)
+// of its tile.  No block waits for another's results: every block reads all
+// nodes' charge into LDS, works out the step's births itself (the same
+// counter-based draws, so every block finds the same newborns) and adds their
+// charge, then runs the exact integer double prefix scans over all nodes and
+// evaluates phi and E on its own tile and halo.  The last block of the diode
+// (the writer) also writes the newborn records and the absorbed-at-birth
+// tallies, and -- once every other block of the diode has read this step's
+// counters and tally copies (a counter the others bump) -- applies the
+// tallies, clears the copies and advances the counters.  When the particle
+// kernel spilled rare items to the global lists (normally never), block 0
+// works them off first and the others wait for its flag before reading the
+// counters those items change.  Both waits are on blocks dispatched earlier.
+// ---------------------------------------------------------------------------
+constexpr int TILE = 512;                 // nodes written per block
+constexpr int FUSED_MAX_NODES = 16385;    // every node's charge staged in LDS (128 KB)
+constexpr int PER_MAX = (FUSED_MAX_NODES + FT - 1) / FT;   // nodes loaded per thread
+
+struct BirthPlan {
+    int q, R, ne;              // ionisation events, replenished pairs, emitted electrons
+    int bP, bE, bI;            // first free slot per species
+    int okP, okE, okI;         // births that fit per species
+    uint32_t id0;              // first newborn id
+    int sorted;                // ionisation events taken in parent-id order (perm)
+};
+
+// A newborn's charge into the all-node charge R (interior nodes, ions
+// positive) and its species deposit into the own tile's counts hb.
+__device__ __forceinline__ void fused_deposit(const Diode &dd, long long *R, unsigned long long (*hb)[TILE], int a0,
+                                              int b0, int s, double z)
+{
+    int j;
+    double f;
+    cic(z, dd.invdz, dd.N, j, f);
+    const unsigned long long a = fixed_right(f), l = (1ull << 32) - a;
+    const long long sg = s == SP_I ? 1 : -1;
+    if (j >= 1) atomicAdd(reinterpret_cast<unsigned long long *>(&R[j]), (unsigned long long)(sg * (long long)l));
+    if (j + 1 <= dd.N - 1)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&R[j + 1]), (unsigned long long)(sg * (long long)a));
+    if (j >= a0 && j < b0) atomicAdd(&hb[s][j - a0], l);
+    if (j + 1 >= a0 && j + 1 < b0) atomicAdd(&hb[s][j + 1 - a0], a);
+}
+
+// The step's births (ionisation products in increasing parent id, thermionic
+// emission at z = v_z dt from the flux-weighted half-Maxwellian at Tc, pair
+// replenishment at a shared uniform position, Maxwellian at Te0 / Ti0), one
+// thread per newborn (pair).  Every block deposits them; the writer also
+// stores the records and tallies a newborn placed beyond the anode.
+__device__ __forceinline__ void fused_births(const Diode &dd, const BirthPlan &bp, const uint16_t *perm, bool writer,
+                                             uint32_t step, int parity, long long *R,
+                                             unsigned long long (*hb)[TILE], int a0, int b0)
+{
+    const int q = bp.q, ne = bp.ne, total = q + ne + bp.R;
+    const GBuf bP = gbuf(dd.buf[parity][SP_P]), bE = gbuf(dd.buf[parity][SP_E]), bI = gbuf(dd.buf[parity][SP_I]);
+    for (int x = threadIdx.x; x < total; x += FT) {
+        if (x < q) {
+            const int r = x;
+            const IzEvent ev = dd.izq[bp.sorted ? (int)perm[r] : r];
+            if (r < bp.okP) fused_deposit(dd, R, hb, a0, b0, SP_P, ev.z);
+            if (r < bp.okI) fused_deposit(dd, R, hb, a0, b0, SP_I, ev.z);
+            if (writer) {
+                const uint32_t ide = bp.id0 + 2u * r, idi = ide + 1u;
+                const uint4 be = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
+                const uint4 bi = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
+                if (r < bp.okP)
+                    write_particle(bP, bp.bP + r, ev.z, ev.ve[0], ev.ve[1], ev.ve[2], ide,
+                                   next_candidate(step, dd.lam[0], be.z, be.w));
+                if (r < bp.okI)
+                    write_particle(bI, bp.bI + r, ev.z, ev.vi[0], ev.vi[1], ev.vi[2], idi,
+                                   next_candidate(step, dd.lam[1], bi.z, bi.w));
+            }
+        } else if (x < q + ne) {
+            const int i = x - q;
+            if (i >= bp.okE) continue;
+            const uint32_t idn = bp.id0 + 2u * q + i;
+            const uint4 b0w = philox(step, EV_BIRTH, 0u, 0u, idn, dd.kseed);
+            const float vz = (float)(dd.sig_c * sqrt(-2.0 * log(u53(b0w.z, b0w.w))));
+            const double z = (double)vz * dd.dt;
+            if (z < dd.L) fused_deposit(dd, R, hb, a0, b0, SP_E, z);
+            if (writer) {
+                const uint4 b1w = philox(step, EV_BIRTH, 1u, 0u, idn, dd.kseed);
+                double n1, n2;
+                bm32(b0w.x, b0w.y, n1, n2);
+                const float vx = (float)(dd.sig_c * n1), vy = (float)(dd.sig_c * n2);
+                const uint32_t tc = next_candidate(step, dd.lam[0], b1w.z, b1w.w);
+                if (z >= dd.L) {
+                    const double ke = 0.5 * dd.mass[SP_E] * ((double)vx * vx + (double)vy * vy + (double)vz * vz);
+                    atomicAdd(&dd.tally->abs_count[SP_E][1], 1ull);
+                    atomicAdd(&dd.tally->abs_energy[SP_E][1], ke);
+                    write_particle(bE, bp.bE + i, -1.0, vx, vy, vz, idn, tc);
+                } else {
+                    write_particle(bE, bp.bE + i, z, vx, vy, vz, idn, tc);
+                }
+            }
+        } else {
+            const int r = x - q - ne;
+            const uint32_t ide = bp.id0 + 2u * q + ne + 2u * r, idi = ide + 1u;
+            const uint4 e1 = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
+            const double z = dd.L * u53(e1.x, e1.y);
+            if (q + r < bp.okP) fused_deposit(dd, R, hb, a0, b0, SP_P, z);
+            if (q + r < bp.okI) fused_deposit(dd, R, hb, a0, b0, SP_I, z);
+            if (writer) {
+                const uint4 e0 = philox(step, EV_BIRTH, 0u, 0u, ide, dd.kseed);
+                const uint4 i0 = philox(step, EV_BIRTH, 0u, 0u, idi, dd.kseed);
+                const uint4 i1 = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
+                double a1, a2, a3, a4;
+                bm32(e0.x, e0.y, a1, a2);
+                bm32(e0.z, e0.w, a3, a4);
+                if (q + r < bp.okP)
+                    write_particle(bP, bp.bP + q + r, z, (float)(dd.sig_e0 * a1), (float)(dd.sig_e0 * a2),
+                                   (float)(dd.sig_e0 * a3), ide, next_candidate(step, dd.lam[0], e1.z, e1.w));
+                bm32(i0.x, i0.y, a1, a2);
+                bm32(i0.z, i0.w, a3, a4);
+                if (q + r < bp.okI)
+                    write_particle(bI, bp.bI + q + r, z, (float)(dd.sig_i0 * a1), (float)(dd.sig_i0 * a2),
+                                   (float)(dd.sig_i0 * a3), idi, next_candidate(step, dd.lam[1], i1.z, i1.w));
+            }
+        }
+    }
+}
+
+// The particle kernel's tally copies, read without clearing (the writer
+// clears them once every block has read them).
+__device__ __forceinline__ RareTally read_tally_copy(const Diode &dd)
+{
+    return dd.tacc[threadIdx.x & 63].t;
+}
+
+__global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, int mode, int parity)
+{
+    extern __shared__ long long R[];          // all nodes' charge (first: the ionisation sort keys)
+    __shared__ unsigned long long hb[NSP][TILE];
+    __shared__ uint16_t perm[IZQ_CAP];
+    __shared__ long long sh64[FW];
+    __shared__ I128 sh128[FW];
+    __shared__ double ph[TILE + 2];
+    __shared__ RareTally rt, rs;
+    __shared__ DiodeState s_st;
+    __shared__ BirthPlan bp;
+    const Diode &dd = D[blockIdx.y];
+    DiodeState *st = dd.st;
+    const int N = dd.N, nn = N + 1;
+    const int T = (nn + TILE - 1) / TILE;
+    const int t = blockIdx.x;
+    if (t >= T) return;
+    const int a0 = t * TILE, b0 = min(nn, a0 + TILE);
+    const bool writer = t == T - 1;
+    const int tid = threadIdx.x;
+
+    // counters and the particle kernel's tally copies, with every node's
+    // charge and the own tile's deposits in flight meanwhile
+    RareTally copy{};
+    if (mode == 0) {
+        if (tid < 64) copy = read_tally_copy(dd);
+        if (tid >= 64 && tid < 128) load_state(st, &s_st);
+        if (tid == 0) {
+            rare_tally_zero(&rt);
+            rare_tally_zero(&rs);
+        }
+    }
+    long long rr[PER_MAX];
+    unsigned long long own[NSP] = {0ull, 0ull, 0ull};
+    int ownj = -1;
+#pragma unroll
+    for (int k = 0; k < PER_MAX; ++k) {
+        const int j = tid + k * FT;
+        rr[k] = 0;
+        if (j < nn) {
+            const unsigned long long hp = glb(dd.H[SP_P])[j], he = glb(dd.H[SP_E])[j], hi = glb(dd.H[SP_I])[j];
+            if (j >= 1 && j <= N - 1) rr[k] = (long long)(hi - hp - he);
+            if (j >= a0 && j < b0) {
+                own[SP_P] = hp;
+                own[SP_E] = he;
+                own[SP_I] = hi;
+                ownj = j;
+            }
+        }
+    }
+    const uint32_t step = mode == 0 ? (uint32_t)uni((int)st->step) : 0u;
+    __syncthreads();
+    if (mode == 0) {
+        fold_tally_copies(copy, &rt);   // first wave
+        if (s_st.rare_n[SP_P] | s_st.rare_n[SP_E] | s_st.rare_n[SP_I]) {
+            // items the particle kernel's queues could not hold: block 0
+            // collides them (they may queue ionisations and lose ions), then
+            // raises the flag the other blocks wait for
+            if (t == 0) {
+                if (tid == 0)
+                    atomicAdd(&dd.tally->rare_spill,
+                              (unsigned long long)(s_st.rare_n[SP_P] + s_st.rare_n[SP_E] + s_st.rare_n[SP_I]));
+                process_rare(dd, s_st.rare_n, parity, step, tid, FT, &rs);
+                __syncthreads();
+                if (tid == 0) {
+                    apply_tally(dd, rs);
+                    if (rs.ion_lost) atomicAdd(&st->ion_lost, rs.ion_lost);
+                    __threadfence();
+                    __hip_atomic_store(glb(&st->spill_flag), step + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            } else if (tid == 0) {
+                while (__hip_atomic_load(glb(&st->spill_flag), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) !=
+                       step + 1u)
+                    __builtin_amdgcn_s_sleep(2);
+            }
+            __syncthreads();
+            if (tid >= 64 && tid < 128) load_state(st, &s_st);
+        }
+        __syncthreads();
+        // this block is done with the counters and the copies
+        if (!writer && tid == 0) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) {
+            const DiodeState &S = s_st;
+            BirthPlan p;
+            p.q = min(S.iz_count, IZQ_CAP);
+            p.R = dd.replenish ? S.ion_lost + rt.ion_lost : 0;
+            p.ne = 0;
+            if (dd.emit_x > 0.0) {
+                const double fl = floor(dd.emit_x);
+                const uint4 be = philox(step, EV_EMIT, 0u, 0u, 0xFFFFFFFFu, dd.kseed);
+                p.ne = (int)fl + (u53(be.x, be.y) < dd.emit_x - fl ? 1 : 0);
+            }
+            p.id0 = S.next_id;
+            p.bP = S.n[SP_P];
+            p.bE = S.n[SP_E];
+            p.bI = S.n[SP_I];
+            // births that do not fit are dropped (and flagged by the writer)
+            p.okP = min(p.q + p.R, dd.cap[SP_P] - p.bP);
+            p.okE = min(p.ne, dd.cap[SP_E] - p.bE);
+            p.okI = min(p.q + p.R, dd.cap[SP_I] - p.bI);
+            // the parent-id order names the ionisation products (the writer)
+            // and, when some do not fit, decides which are dropped (all)
+            p.sorted = p.q > 1 && (writer || p.okP < p.q || p.okI < p.q);
+            bp = p;
+        }
+        __syncthreads();
+        if (bp.sorted) {
+            // bitonic sort of (parent id, event) in the charge array's space
+            unsigned long long *keys = reinterpret_cast<unsigned long long *>(R);
+            const int q = bp.q;
+            int np2 = 1;
+            while (np2 < q) np2 <<= 1;
+            for (int i = tid; i < np2; i += FT)
+                keys[i] = i < q ? ((unsigned long long)dd.izq[i].parent << 32) | (unsigned)i : ~0ull;
+            __syncthreads();
+            for (int k = 2; k <= np2; k <<= 1) {
+                for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                    for (int i = tid; i < np2; i += FT) {
+                        const int pi = i ^ jj;
+                        if (pi > i) {
+                            const unsigned long long u = keys[i], v = keys[pi];
+                            const bool up = (i & k) == 0;
+                            if ((u > v) == up) { keys[i] = v; keys[pi] = u; }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int i = tid; i < q; i += FT) perm[i] = (uint16_t)(keys[i] & 0xFFFFull);
+            __syncthreads();
+        }
+    }
+    // the charge of every node and the own tile's deposits into LDS
+#pragma unroll
+    for (int k = 0; k < PER_MAX; ++k) {
+        const int j = tid + k * FT;
+        if (j < nn) R[j] = rr[k];
+    }
+    if (ownj >= 0) {
+#pragma unroll
+        for (int s = 0; s < NSP; ++s) hb[s][ownj - a0] = own[s];
+    }
+    __syncthreads();
+    if (mode == 0) {
+        fused_births(dd, bp, perm, writer, step, parity, R, hb, a0, b0);
+        __syncthreads();
+    }
+
+    // phi_j = V j / N + alpha (j T_N - N T_j) / N with the exact sums
+    // S1_j = sum_{k<=j} R_k and T_j = sum_{m=1..j-1} S1_m; each thread walks
+    // per consecutive nodes, phi kept for the own tile and its halo
+    const int per = (nn + FT - 1) / FT;
+    const int j0 = tid * per, j1 = min(nn, j0 + per);
+    long long loc = 0;
+    for (int j = j0; j < j1; ++j) loc += R[j];
+    long long tot;
+    const long long s1off = block_scan_excl_i64(loc, sh64, tot);
+    I128 tl = i128(0);
+    {
+        long long S1 = s1off;
+        for (int j = j0; j < j1; ++j) {
+            S1 += R[j];
+            if (j >= 1 && j <= N - 1) tl = add(tl, i128(S1));
+        }
+    }
+    I128 T_N;
+    I128 Tacc = block_scan_excl_i128(tl, sh128, T_N);
+    const double alpha_n = dd.alpha / (double)N;
+    {
+        long long S1 = s1off;
+        for (int j = j0; j < j1; ++j) {
+            S1 += R[j];
+            if (j >= a0 - 1 && j <= b0) {
+                double v = 0.0;
+                if (j == N) v = dd.V;
+                else if (j >= 1) {
+                    const I128 x = add(mul_small(T_N, (unsigned)j), neg(mul_small(Tacc, (unsigned)N)));
+                    v = dd.V * (double)j / (double)N + alpha_n * to_double(x);
+                }
+                ph[j - a0 + 1] = v;
+            }
+            if (j >= 1 && j <= N - 1) Tacc = add(Tacc, i128(S1));
+        }
+    }
+    __syncthreads();
+    // the own tile: field, potential, deposits of the step and their sums
+    const int avg = uni(__hip_atomic_load(glb(&st->avg_on), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const int j = a0 + tid;
+    if (tid < TILE && j < b0) {
+        const int k = tid + 1;
+        const double pc = ph[k];
+        double E;
+        if (j == 0) E = (pc - ph[k + 1]) / dd.dz;
+        else if (j == N) E = (ph[k - 1] - pc) / dd.dz;
+        else E = (ph[k - 1] - ph[k + 1]) * (1.0 / (2.0 * dd.dz));
+        glb(dd.phi)[j] = pc;
+        glb(dd.E)[j] = E;
+#pragma unroll
+        for (int s = 0; s < NSP; ++s) {
+            const unsigned long long hu = hb[s][tid];
+            if (hu >= DEPOSIT_LIMIT) atomicOr(&st->err, ERR_RANGE);
+            glb(dd.Hlast[s])[j] = (long long)hu;
+            glb(dd.H[s])[j] = 0ull;
+            if (avg) glb(dd.Hsum[s])[j] += (long long)hu;
+        }
+        if (avg) glb(dd.phi_sum)[j] += pc;
+    }
+    if (mode != 0 || !writer) return;
+    // the writer: once every other block has read the counters and copies,
+    // the step's tallies, counters and snapshot
+    if (tid == 0) {
+        while (__hip_atomic_load(glb(&st->arrive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < T - 1)
+            __builtin_amdgcn_s_sleep(2);
+        __hip_atomic_store(glb(&st->arrive), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (tid < 64) dd.tacc[tid].t = RareTally{};
+    if (tid == 0) {
+        const BirthPlan &p = bp;
+        if (p.okP < p.q + p.R || p.okE < p.ne || p.okI < p.q + p.R) atomicOr(&st->err, ERR_CAPACITY);
+        apply_tally(dd, rt);
+        st->n[SP_P] = p.bP + p.okP;
+        st->n[SP_E] = p.bE + p.okE;
+        st->n[SP_I] = p.bI + p.okI;
+        st->next_id = p.id0 + 2u * p.q + p.ne + 2u * p.R;
+        if (p.ne) atomicAdd(&dd.tally->n_emit, (unsigned long long)p.ne);
+        if (p.R) atomicAdd(&dd.tally->n_repl, (unsigned long long)p.R);
+        if (p.q) atomicAdd(&dd.tally->n_iz, (unsigned long long)p.q);
+        st->iz_count = 0;
+        st->ion_lost = 0;
+        st->spill_flag = 0u;
+#pragma unroll
+        for (int sp = 0; sp < NSP; ++sp) st->rare_n[sp] = 0;
+        st->step = step + 1u;
+        if (avg) st->avg_steps += 1;
+    }
+    // every tally update of the block (births beyond the anode, the step's
+    // totals) is complete before the snapshot reads the tallies
+    __syncthreads();
+    const uint32_t nstep = step + 1u;
+    if (tid == 0 && dd.tally_period > 0 && nstep % (uint32_t)dd.tally_period == 0u) {
+        TallySnap &sn = dd.ring[(nstep / (uint32_t)dd.tally_period) % RING];
+        sn.step = nstep;
+        sn.t = *dd.tally;
+    }
+}
+
 }  // namespace pic
 
 // ---------------------------------------------------------------------------
@@ -2175,26 +2457,25 @@ extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int n
     return hipGetLastError();
 }
 
-// max_nodes: the largest N + 1 over the diodes.  Up to FIELD_TILE_MIN nodes
-// one block per diode does the whole step (fewest launches); above, the births
-// beside the tile aggregates and the tiled solve run as two kernels over many
-// CUs.  Measured crossover: 2049 nodes are faster in one block, 4097 in tiles.
-constexpr int FIELD_TILE_MIN = 4096;
-
+// max_nodes: the largest N + 1 over the diodes.  Up to FUSED_MAX_NODES nodes
+// the sources and field are one kernel over the tiles of every diode
+// (k_field_step); above (whose charge does not fit one block's LDS), the
+// births beside the tile aggregates and the tiled solve run as two kernels.
 // Kernels picx_launch_sources_field enqueues for a step (timed graphs need it).
 extern "C" int picx_sources_field_kernels(int max_nodes, int mode)
 {
     (void)mode;
-    return max_nodes <= FIELD_TILE_MIN ? 1 : 2;
+    return max_nodes <= FUSED_MAX_NODES ? 1 : 2;
 }
 
 extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
                                                 int parity, hipStream_t s)
 {
     const size_t keys = (size_t)IZQ_CAP * 8;
-    if (max_nodes <= FIELD_TILE_MIN) {
+    if (max_nodes <= FUSED_MAX_NODES) {
         const size_t bytes = std::max((size_t)max_nodes * 8, keys);
-        hipLaunchKernelGGL(k_sources_field_lds, dim3(nd), dim3(FT), bytes, s, D, S, mode, parity);
+        const int tiles = (max_nodes + TILE - 1) / TILE;
+        hipLaunchKernelGGL(k_field_step, dim3(tiles, nd), dim3(FT), bytes, s, D, mode, parity);
         return hipGetLastError();
     }
     const int tiles = (max_nodes + FT - 1) / FT;
@@ -2217,8 +2498,8 @@ extern "C" hipError_t picx_launch_sort(const Diode *D, DiodeState *S, int nd, in
 
 extern "C" hipError_t picx_prepare(void)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)k_sources_field_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)LDS_FIELD_BYTES);
+    hipError_t e = hipFuncSetAttribute((const void *)k_field_step, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(FUSED_MAX_NODES * sizeof(long long)));
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)k_phase_hist, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(PHASE_MAX_BINS * sizeof(uint32_t)));

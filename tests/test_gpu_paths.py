@@ -60,6 +60,22 @@ def test_rare_queue_spill_parity(pic, O):
     assert t["coll"][0] > 0 and t["abs_count"].sum() > 0
 
 
+def test_rare_queue_spill_parity_tiled_field(pic, O):
+    """The spill on a grid of several field tiles: block 0 of the field step
+    works the spilled items off and the other tiles wait for it before they
+    read the counters those items change."""
+    cfg = presets.scaled(presets.tiny(), N=2048, L=5e-3 * 8, n_load=40 * 2048, ng=3.2e23, Te0=5.0,
+                         gamma_emit=1e21)
+    _say("case: rare-item spill with 5 field tiles (2048 cells), grid 8")
+    h = pic.Handle(cfg)
+    h.set_tuning(ppt=4, grid=8, sort_period=16, use_graph=0)
+    h.step(3)
+    s0 = h.tally()["rare_spill"]
+    probs = restart_step_check(O, cfg, h, 6)
+    assert probs == [], "\n".join(probs[:20])
+    assert h.tally()["rare_spill"] - s0 > 1000
+
+
 PAPER_CASES = [
     ("baseline: elastic + charge exchange, T_n 300 / 1740 K", {}),
     ("Table 3: charge exchange off", dict(channels=presets.CH_EEL)),
