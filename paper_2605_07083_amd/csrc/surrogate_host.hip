@@ -16,18 +16,21 @@
 #include "../../include/surrogate.h"
 
 extern "C" {
-hipError_t surx_features(const float *params, __bf16 *feat, __bf16 *featT, int X, int B, hipStream_t s);
+hipError_t surx_features(const float *params, __bf16 *feat, __bf16 *featT, double *loss0, int X, int B,
+                         hipStream_t s);
 hipError_t surx_conv_fwd(int layer, const __bf16 *in, const __bf16 *Wf, const float *bias, float *yf, __bf16 *yb,
                          __bf16 *ybT, int X, int B, hipStream_t s);
 hipError_t surx_loss(const float *out, const float *target, __bf16 *dz, __bf16 *dzT, double *loss, int X, int B,
                      hipStream_t s);
 hipError_t surx_conv_dgrad(int layer, const __bf16 *dz, const __bf16 *Wb, const float *yprev, __bf16 *dzprev,
                            __bf16 *dzprevT, int X, int B, hipStream_t s);
-hipError_t surx_conv_wgrad(int layer, const __bf16 *dzT, const __bf16 *inT, float *dW, float *db, int X, int B,
-                           hipStream_t s);
-hipError_t surx_zero(float *p, size_t n, hipStream_t s);
-hipError_t surx_adam(float *w, float *m, float *v, const float *g, int n, float lr, float b1, float b2, float eps,
-                     float c1, float c2, hipStream_t s);
+hipError_t surx_conv_wgrad_part(int layer, const __bf16 *dzT, const __bf16 *inT, float *part, float *pbias, int X,
+                                int B, hipStream_t s);
+int surx_wgrad_parts(int X, int B);
+hipError_t surx_reduce_adam(const float *part, const float *pbias, int P, float *wm, float *mw, float *vw, float *dw,
+                            float *bias, float *mb, float *vb, float *db, __bf16 *Wf, __bf16 *Wb, int cin, int coutp,
+                            int cout_real, int kp, int kpb, float lr, float b1, float b2, float eps, float c1,
+                            float c2, hipStream_t s);
 hipError_t surx_requant(const float *wm, __bf16 *Wf, __bf16 *Wb, int cin, int coutp, int cout_real, int kp, int kpb,
                         hipStream_t s);
 hipError_t surx_to_state(const float *out, const float *params, const double *n0, double *state, int X, int B,
@@ -100,6 +103,8 @@ struct sur_net {
     __bf16 *ybT[SUR_LAYERS - 1];  // channels-first copies [bmax][64][X]
     __bf16 *dz[2];                // [bmax][X][64]
     __bf16 *dzT[2];               // [bmax][64][X]
+    float *part = nullptr;        // a layer's partial weight gradients [parts][64][320]
+    float *pbias = nullptr;       // and bias gradients [parts][64]
     double *loss = nullptr;
     long long t = 0;              // Adam steps taken
 };
@@ -141,6 +146,9 @@ void layout(sur_net &n, Bump &bp)
         n.dz[k] = bp.take<__bf16>(P * SUR_HIDDEN);
         n.dzT[k] = bp.take<__bf16>(P * SUR_HIDDEN);
     }
+    const size_t parts = (size_t)surx_wgrad_parts(n.X, n.bmax);
+    n.part = bp.take<float>(parts * SUR_HIDDEN * pad32(SUR_KS * SUR_HIDDEN));
+    n.pbias = bp.take<float>(parts * SUR_HIDDEN);
 }
 
 int check_shape(int batch, int cells)
@@ -162,7 +170,8 @@ int requant_all(sur_net *n)
 // train: also write the channels-first copies the weight gradients read
 int forward(sur_net *n, const float *params, int B, bool train)
 {
-    SUR_TRY(surx_features(params, n->feat, train ? n->featT : nullptr, n->X, B, n->stream));
+    SUR_TRY(surx_features(params, n->feat, train ? n->featT : nullptr, train ? n->loss : nullptr, n->X, B,
+                          n->stream));
     for (int l = 0; l < SUR_LAYERS; ++l) {
         const __bf16 *in = l == 0 ? n->feat : n->yb[l - 1];
         __bf16 *yb = l < SUR_LAYERS - 1 ? n->yb[l] : nullptr;
@@ -363,7 +372,7 @@ int sur_forward_noalloc(sur_net *n, const float *dev_params, int batch, float *d
                      reinterpret_cast<__bf16 *>(base + P * (16 * 2 + 64 * 4 + 48 * 4 + 64 * 2))};
     for (int b0 = 0; b0 < batch; b0 += chunk) {
         const int nb = std::min(chunk, batch - b0);
-        SUR_TRY(surx_features(dev_params + (size_t)4 * b0, feat, nullptr, n->X, nb, n->stream));
+        SUR_TRY(surx_features(dev_params + (size_t)4 * b0, feat, nullptr, nullptr, n->X, nb, n->stream));
         for (int l = 0; l < SUR_LAYERS; ++l) {
             const __bf16 *in = l == 0 ? feat : yb[(l - 1) & 1];
             const bool last = l == SUR_LAYERS - 1;
@@ -381,36 +390,30 @@ int sur_train_step(sur_net *n, const float *dev_params, const float *dev_target,
     if (batch < 1 || batch > n->bmax) return fail(PIC_EINVAL, "batch exceeds the workspace's max_batch");
     if (!(lr > 0.0f)) return fail(PIC_EINVAL, "learning rate must be positive");
     const int X = n->X;
+    // the forward pass zeroes the loss accumulator (features kernel)
     int rc = forward(n, dev_params, batch, true);
     if (rc) return rc;
-    SUR_TRY(surx_zero(reinterpret_cast<float *>(n->loss), 2, n->stream));
     SUR_TRY(surx_loss(n->yf[SUR_LAYERS - 1], dev_target, n->dz[0], n->dzT[0], n->loss, X, batch, n->stream));
-    for (int l = 0; l < SUR_LAYERS; ++l) {
-        const Layer &L = n->L[l];
-        SUR_TRY(surx_zero(L.dw, (size_t)L.coutp * L.kp, n->stream));
-        SUR_TRY(surx_zero(L.db, (size_t)L.coutp, n->stream));
-    }
+    n->t += 1;
+    const float c1 = (float)(1.0 - std::pow((double)B1, (double)n->t));
+    const float c2 = (float)(1.0 - std::pow((double)B2, (double)n->t));
+    const int parts = surx_wgrad_parts(X, batch);
+    // per layer, last to first: partial weight gradients, the input gradient
+    // (which still needs this layer's weights), then the layer's gradient
+    // summed from the partials, its Adam update and BF16 copies
     int cur = 0;
     for (int l = SUR_LAYERS - 1; l >= 0; --l) {
         const Layer &L = n->L[l];
         const __bf16 *inT = l == 0 ? n->featT : n->ybT[l - 1];
-        SUR_TRY(surx_conv_wgrad(l, n->dzT[cur], inT, L.dw, L.db, X, batch, n->stream));
+        SUR_TRY(surx_conv_wgrad_part(l, n->dzT[cur], inT, n->part, n->pbias, X, batch, n->stream));
         if (l > 0) {
             SUR_TRY(surx_conv_dgrad(l, n->dz[cur], L.wb, n->yf[l - 1], n->dz[cur ^ 1], n->dzT[cur ^ 1], X, batch,
                                     n->stream));
             cur ^= 1;
         }
+        SUR_TRY(surx_reduce_adam(n->part, n->pbias, parts, L.wm, L.mw, L.vw, L.dw, L.bias, L.mb, L.vb, L.db, L.wf,
+                                 L.wb, L.cin, L.coutp, L.cout, L.kp, L.kpb, lr, B1, B2, EPS, c1, c2, n->stream));
     }
-    n->t += 1;
-    const float c1 = (float)(1.0 - std::pow((double)B1, (double)n->t));
-    const float c2 = (float)(1.0 - std::pow((double)B2, (double)n->t));
-    for (int l = 0; l < SUR_LAYERS; ++l) {
-        const Layer &L = n->L[l];
-        SUR_TRY(surx_adam(L.wm, L.mw, L.vw, L.dw, L.coutp * L.kp, lr, B1, B2, EPS, c1, c2, n->stream));
-        SUR_TRY(surx_adam(L.bias, L.mb, L.vb, L.db, L.coutp, lr, B1, B2, EPS, c1, c2, n->stream));
-    }
-    rc = requant_all(n);
-    if (rc) return rc;
     if (loss) {
         SUR_TRY(hipMemcpyAsync(loss, n->loss, sizeof(double), hipMemcpyDeviceToHost, n->stream));
         SUR_TRY(hipStreamSynchronize(n->stream));

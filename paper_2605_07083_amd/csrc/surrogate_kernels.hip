@@ -59,9 +59,10 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
 // density); the position features resolve both sheaths and the interior.
 // ---------------------------------------------------------------------------
 __global__ void k_features(const float *__restrict__ params, __bf16 *__restrict__ feat, __bf16 *__restrict__ featT,
-                           int X, int B)
+                           double *__restrict__ loss0, int X, int B)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx == 0 && loss0) *loss0 = 0.0;     // the training step's loss accumulator
     if (idx >= X * B) return;
     const int b = idx / X, x = idx - b * X;
     const float g = params[4 * b + 0], T = params[4 * b + 1], V = params[4 * b + 2], ng = params[4 * b + 3];
@@ -104,9 +105,27 @@ __device__ __forceinline__ void store4T(__bf16 *p, float v0, float v1, float v2,
 }
 
 // ---------------------------------------------------------------------------
+// Weights of a layer staged in LDS once per block: rows of the padded K
+// length plus 8 elements, so that the 16 rows one matrix-core fragment reads
+// fall on different banks.
+// ---------------------------------------------------------------------------
+constexpr int BLOCK_POS = 256;   // positions per block of the forward and input-gradient kernels
+
+template <int ROWS, int KP>
+__device__ __forceinline__ void stage_rows(__bf16 *lds, const __bf16 *__restrict__ src)
+{
+    constexpr int V = KP / 8;    // 16-byte vectors per row
+    for (int v = threadIdx.x; v < ROWS * V; v += blockDim.x) {
+        const int r = v / V, c = (v - r * V) * 8;
+        *reinterpret_cast<bf16x8 *>(lds + r * (KP + 8) + c) = load8(src + (size_t)r * KP + c);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Forward conv: out[b][x][co] = act(bias[co] + sum_{t, ci} W[co][t][ci] in[b][x+t-2][ci]).
-// GEMM M = positions, N = COUT, K = 5*CIN (padded to KP).  A wave computes 16
-// positions x COUT; a block of 4 waves 64 positions.
+// GEMM M = positions, N = COUT, K = 5*CIN (padded to KP).  A block of 4
+// waves covers BLOCK_POS positions of one sample with the layer's weights in
+// LDS; a wave computes 16 positions x COUT at a time.
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT, bool TANH>
 __global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ in, const __bf16 *__restrict__ Wf,
@@ -116,16 +135,20 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ in,
     constexpr int K = KS * CIN;
     constexpr int KP = (K + 31) / 32 * 32;
     constexpr int NT = COUT / 16;
+    __shared__ __bf16 wl[COUT * (KP + 8)];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int tiles = X / 64;
+    const int tiles = (X + BLOCK_POS - 1) / BLOCK_POS;
     const int b = blockIdx.x / tiles;
-    const int x0 = (blockIdx.x - b * tiles) * 64 + w * 16;
     if (b >= B) return;
+    stage_rows<COUT, KP>(wl, Wf);
+    __syncthreads();
     const int m = lane & 15, kb = lane >> 4;
+    const __bf16 *inb = in + (size_t)b * X * CIN;
+    const int xb = (blockIdx.x - b * tiles) * BLOCK_POS;
+    for (int x0 = xb + w * 16; x0 < min(X, xb + BLOCK_POS); x0 += 64) {
     f32x4 acc[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    const __bf16 *inb = in + (size_t)b * X * CIN;
 #pragma unroll
     for (int ks = 0; ks < KP / 32; ++ks) {
         const int kappa = ks * 32 + kb * 8;
@@ -137,7 +160,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ in,
         }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            const bf16x8 bw = load8(Wf + (size_t)(nt * 16 + m) * KP + kappa);
+            const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(wl + (nt * 16 + m) * (KP + 8) + kappa);
             acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[nt], 0, 0, 0);
         }
     }
@@ -155,6 +178,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ in,
             if (yb) yb[o] = (__bf16)v[i];
         }
         if (ybT) store4T(ybT + ((size_t)b * COUT + co) * X + x0 + kb * 4, v[0], v[1], v[2], v[3]);
+    }
     }
 }
 
@@ -201,16 +225,20 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const __bf16 *__restrict__ d
     constexpr int K = KS * COUT;
     constexpr int KP = (K + 31) / 32 * 32;
     constexpr int NT = CIN / 16;
+    __shared__ __bf16 wl[CIN * (KP + 8)];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int tiles = X / 64;
+    const int tiles = (X + BLOCK_POS - 1) / BLOCK_POS;
     const int b = blockIdx.x / tiles;
-    const int x0 = (blockIdx.x - b * tiles) * 64 + w * 16;
     if (b >= B) return;
+    stage_rows<CIN, KP>(wl, Wb);
+    __syncthreads();
     const int m = lane & 15, kb = lane >> 4;
+    const __bf16 *dzb = dz + (size_t)b * X * COUT;
+    const int xb = (blockIdx.x - b * tiles) * BLOCK_POS;
+    for (int x0 = xb + w * 16; x0 < min(X, xb + BLOCK_POS); x0 += 64) {
     f32x4 acc[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    const __bf16 *dzb = dz + (size_t)b * X * COUT;
 #pragma unroll
     for (int ks = 0; ks < KP / 32; ++ks) {
         const int kappa = ks * 32 + kb * 8;
@@ -222,7 +250,7 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const __bf16 *__restrict__ d
         }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            const bf16x8 bw = load8(Wb + (size_t)(nt * 16 + m) * KP + kappa);
+            const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(wl + (nt * 16 + m) * (KP + 8) + kappa);
             acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[nt], 0, 0, 0);
         }
     }
@@ -240,17 +268,16 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const __bf16 *__restrict__ d
         }
         store4T(dzprevT + ((size_t)b * CIN + ci) * X + x0 + kb * 4, v[0], v[1], v[2], v[3]);
     }
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Weight and bias gradients: dW[co][t*CIN+ci] += sum_x dZ[b][co][x] in[b][ci][x+t-2],
-// db[co] += sum_x dZ[b][co][x], from the channels-first copies.  GEMM M = COUT,
-// N = 5*CIN (16-wide tiles, one tap t per tile), K = positions, 32 per MFMA.
-// A wave owns one (co tile, kappa tile) over one sample; the samples are
-// summed with FP32 atomics.  Lane (m, kb) reads 8 consecutive positions as
-// one 16-byte load for A; for B the same 8 positions shifted by t - 2, taken
-// from a 12-element window (16 bytes plus one dword on each side, zero
-// outside the sample).  The kappa tiles starting at 0 also sum dZ for db.
+// Weight and bias gradients: dW[co][t*CIN+ci] = sum_{b,x} dZ[b][co][x] in[b][ci][x+t-2],
+// db[co] = sum_{b,x} dZ[b][co][x], from the channels-first copies.  GEMM M =
+// COUT, N = 5*CIN (16-wide tiles, one tap t per tile), K = positions, 32 per
+// MFMA.  Lane (m, kb) reads 8 consecutive positions as one 16-byte load for
+// A; for B the same 8 positions shifted by t - 2, taken from a 12-element
+// window (16 bytes plus one dword on each side, zero outside the sample).
 // ---------------------------------------------------------------------------
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -270,92 +297,135 @@ __device__ __forceinline__ bf16x8 window8(uint32_t w0, uint32_t w1, uint32_t w2,
     return __builtin_bit_cast(bf16x8, r);
 }
 
-template <int T>
-__device__ __forceinline__ f32x4 wgrad_tile(const __bf16 *__restrict__ arow, const __bf16 *__restrict__ brow, int X,
-                                            int kb, bool bias_tile, float &bsum)
-{
-    f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
-    const uint32_t *bw = reinterpret_cast<const uint32_t *>(brow);
-    for (int x0 = 0; x0 < X; x0 += 32) {
-        const int xa = x0 + kb * 8;
-        const bf16x8 a = load8(arow + xa);
-        const u32x4 mid = *reinterpret_cast<const u32x4 *>(brow + xa);
-        const uint32_t lo = xa > 0 ? bw[(xa >> 1) - 1] : 0u;
-        const uint32_t hi = xa + 8 < X ? bw[(xa >> 1) + 4] : 0u;
-        const bf16x8 b = window8<T>(lo, mid[0], mid[1], mid[2], mid[3], hi);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-        if (bias_tile) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) bsum += (float)a[i];
-        }
-    }
-    return acc;
-}
+// ---------------------------------------------------------------------------
+// Weight and bias gradients as partial sums over slices of WG_SLICE positions
+// of one sample: block p = (sample, slice) writes part[p][co][kappa] and
+// pbias[p][co]; k_reduce_adam sums the partials in a fixed order.  Wave w of
+// the block takes output-channel tile w % MT and half of the input-channel
+// tiles (c = w / MT, w / MT + 2, ...), all five taps of each: for every 32
+// positions one 16-byte load of dZ (A) is shared by up to 10 MFMAs, and one
+// 16-byte window of the input per input tile (B) by its five taps.
+// ---------------------------------------------------------------------------
+constexpr int WG_SLICE = 512;
 
 template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv_wgrad(const __bf16 *__restrict__ dzT, const __bf16 *__restrict__ inT,
-                                                    float *__restrict__ dW, float *__restrict__ db, int X, int B)
+__global__ __launch_bounds__(512) void k_conv_wgrad_part(const __bf16 *__restrict__ dzT, const __bf16 *__restrict__ inT,
+                                                         float *__restrict__ part, float *__restrict__ pbias, int X)
 {
     constexpr int K = KS * CIN;
     constexpr int KP = (K + 31) / 32 * 32;
-    constexpr int MT = COUT / 16, NTK = K / 16;    // tiles past K are padding: dW stays 0 there
-    static_assert(CIN % 16 == 0 && K % 16 == 0, "a kappa tile must lie within one tap");
-    const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int tile = wave % (MT * NTK), b = wave / (MT * NTK);
-    if (b >= B) return;
-    const int mt = tile / NTK, nk = tile - mt * NTK;
+    constexpr int MT = COUT / 16, CT = CIN / 16;
+    constexpr int CH = CT >= 2 ? 2 : 1;           // waves per output tile
+    constexpr int CPW = CT / CH;                  // input tiles per wave
+    static_assert(CIN % 16 == 0 && CT % CH == 0, "whole input-channel tiles");
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (w >= MT * CH) return;
+    const int mt = w % MT, ch = w / MT;
+    const int slices = (X + WG_SLICE - 1) / WG_SLICE;
+    const int p = blockIdx.x, b = p / slices;
+    const int xb = (p - b * slices) * WG_SLICE, xe = min(X, xb + WG_SLICE);
     const int m = lane & 15, kb = lane >> 4;
     const int co = mt * 16 + m;
-    const int kappa = nk * 16 + m;
-    const int t = (nk * 16) / CIN, ci = kappa - t * CIN;
     const __bf16 *arow = dzT + ((size_t)b * COUT + co) * X;
-    const __bf16 *brow = inT + ((size_t)b * CIN + ci) * X;
-    const bool bias_tile = nk == 0;
-    float bsum = 0.0f;
-    f32x4 acc;
-    switch (t) {   // the tap, hence the shift t - 2, is uniform over the wave
-    case 0: acc = wgrad_tile<0>(arow, brow, X, kb, bias_tile, bsum); break;
-    case 1: acc = wgrad_tile<1>(arow, brow, X, kb, bias_tile, bsum); break;
-    case 2: acc = wgrad_tile<2>(arow, brow, X, kb, bias_tile, bsum); break;
-    case 3: acc = wgrad_tile<3>(arow, brow, X, kb, bias_tile, bsum); break;
-    default: acc = wgrad_tile<4>(arow, brow, X, kb, bias_tile, bsum); break;
-    }
+    const __bf16 *brow[CPW];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = mt * 16 + kb * 4 + i;     // co
-        atomicAdd(&dW[(size_t)row * KP + kappa], acc[i]);
+    for (int c = 0; c < CPW; ++c) brow[c] = inT + ((size_t)b * CIN + (ch + CH * c) * 16 + m) * X;
+    f32x4 acc[KS][CPW];
+#pragma unroll
+    for (int t = 0; t < KS; ++t)
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) acc[t][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.0f;
+    for (int x0 = xb; x0 < xe; x0 += 32) {
+        const int xa = x0 + kb * 8;
+        const bf16x8 a = load8(arow + xa);
+        if (ch == 0) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) bsum += (float)a[i];
+        }
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            const uint32_t *bw = reinterpret_cast<const uint32_t *>(brow[c]);
+            const u32x4 mid = *reinterpret_cast<const u32x4 *>(brow[c] + xa);
+            const uint32_t lo = xa > 0 ? bw[(xa >> 1) - 1] : 0u;
+            const uint32_t hi = xa + 8 < X ? bw[(xa >> 1) + 4] : 0u;
+            acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, window8<0>(lo, mid[0], mid[1], mid[2], mid[3], hi),
+                                                                acc[0][c], 0, 0, 0);
+            acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, window8<1>(lo, mid[0], mid[1], mid[2], mid[3], hi),
+                                                                acc[1][c], 0, 0, 0);
+            acc[2][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, window8<2>(lo, mid[0], mid[1], mid[2], mid[3], hi),
+                                                                acc[2][c], 0, 0, 0);
+            acc[3][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, window8<3>(lo, mid[0], mid[1], mid[2], mid[3], hi),
+                                                                acc[3][c], 0, 0, 0);
+            acc[4][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, window8<4>(lo, mid[0], mid[1], mid[2], mid[3], hi),
+                                                                acc[4][c], 0, 0, 0);
+        }
     }
-    if (bias_tile) {
+    float *out = part + (size_t)p * COUT * KP;
+#pragma unroll
+    for (int t = 0; t < KS; ++t)
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            const int kappa = t * CIN + (ch + CH * c) * 16 + m;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[(size_t)(mt * 16 + kb * 4 + i) * KP + kappa] = acc[t][c][i];
+        }
+    if (ch == 0) {
         bsum += __shfl_xor(bsum, 16, 64);
         bsum += __shfl_xor(bsum, 32, 64);
-        if (kb == 0) atomicAdd(&db[co], bsum);
+        if (kb == 0) pbias[(size_t)p * COUT + co] = bsum;
     }
 }
 
-__global__ void k_zero(float *__restrict__ p, size_t n)
-{
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0.0f;
-}
-
-// ---------------------------------------------------------------------------
-// Adam on the FP32 master weights of one layer (weights in the padded
-// forward layout [COUTP][KP], only co < cout_real and kappa < 5*CIN live),
-// then the BF16 forward and transposed copies.
-// ---------------------------------------------------------------------------
-__global__ void k_adam(float *__restrict__ w, float *__restrict__ mo, float *__restrict__ ve,
-                       const float *__restrict__ g, int n, float lr, float b1, float b2, float eps, float c1,
-                       float c2)
+// The gradient of one layer from its partials (summed in partial order),
+// then Adam on the FP32 master weights and biases and the BF16 copies of the
+// weights: forward layout Wf[co][kappa] and transposed Wb[ci][t*COUTP + co].
+// One thread per weight (padded [COUTP][KP]) and per bias.
+__global__ void k_reduce_adam(const float *__restrict__ part, const float *__restrict__ pbias, int P,
+                              float *__restrict__ wm, float *__restrict__ mw, float *__restrict__ vw,
+                              float *__restrict__ dw, float *__restrict__ bias, float *__restrict__ mb,
+                              float *__restrict__ vb, float *__restrict__ db, __bf16 *__restrict__ Wf,
+                              __bf16 *__restrict__ Wb, int cin, int coutp, int cout_real, int kp, int kpb, float lr,
+                              float b1, float b2, float eps, float c1, float c2)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float gi = g[i];
-    const float m1 = b1 * mo[i] + (1.0f - b1) * gi;
-    const float v1 = b2 * ve[i] + (1.0f - b2) * gi * gi;
-    mo[i] = m1;
-    ve[i] = v1;
-    w[i] -= lr * (m1 / c1) / (sqrtf(v1 / c2) + eps);
+    const int nw = coutp * kp;
+    if (i >= nw + coutp) return;
+    float *w, *mo, *ve, *g;
+    int co, kappa = 0, stride, at;
+    if (i < nw) {
+        co = i / kp;
+        kappa = i - co * kp;
+        w = wm + i; mo = mw + i; ve = vw + i; g = dw + i;
+        stride = nw;
+        at = i;
+    } else {
+        co = i - nw;
+        w = bias + co; mo = mb + co; ve = vb + co; g = db + co;
+        stride = coutp;
+        at = co;
+    }
+    const bool live = co < cout_real && (i >= nw || kappa < KS * cin);
+    float gi = 0.0f;
+    if (live) {
+        const float *src = i < nw ? part : pbias;
+        for (int q = 0; q < P; ++q) gi += src[(size_t)q * stride + at];
+    }
+    *g = gi;
+    const float m1 = b1 * *mo + (1.0f - b1) * gi;
+    const float v1 = b2 * *ve + (1.0f - b2) * gi * gi;
+    *mo = m1;
+    *ve = v1;
+    const float nwv = *w - lr * (m1 / c1) / (sqrtf(v1 / c2) + eps);
+    *w = nwv;
+    if (i < nw) {
+        const __bf16 v = (__bf16)(live ? nwv : 0.0f);
+        Wf[i] = v;
+        if (kappa < KS * cin) {
+            const int t = kappa / cin, ci = kappa - t * cin;
+            Wb[(size_t)ci * kpb + t * coutp + co] = v;
+        }
+    }
 }
 
 // masters [COUTP][KP] (kappa = t*CIN + ci) -> Wf (same layout, bf16) and
@@ -442,9 +512,10 @@ __global__ void k_unpack(const float *__restrict__ y, float *__restrict__ out, i
 // ---------------------------------------------------------------------------
 using namespace sur;
 
-extern "C" hipError_t surx_features(const float *params, __bf16 *feat, __bf16 *featT, int X, int B, hipStream_t s)
+extern "C" hipError_t surx_features(const float *params, __bf16 *feat, __bf16 *featT, double *loss0, int X, int B,
+                                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_features, dim3((X * B + 255) / 256), dim3(256), 0, s, params, feat, featT, X, B);
+    hipLaunchKernelGGL(k_features, dim3((X * B + 255) / 256), dim3(256), 0, s, params, feat, featT, loss0, X, B);
     return hipGetLastError();
 }
 
@@ -452,7 +523,7 @@ extern "C" hipError_t surx_features(const float *params, __bf16 *feat, __bf16 *f
 extern "C" hipError_t surx_conv_fwd(int layer, const __bf16 *in, const __bf16 *Wf, const float *bias, float *yf,
                                     __bf16 *yb, __bf16 *ybT, int X, int B, hipStream_t s)
 {
-    dim3 g(X / 64 * B), t(256);
+    dim3 g((X + BLOCK_POS - 1) / BLOCK_POS * B), t(256);
     if (layer == 0) hipLaunchKernelGGL((k_conv_fwd<16, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
     else if (layer < 5) hipLaunchKernelGGL((k_conv_fwd<64, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
     else hipLaunchKernelGGL((k_conv_fwd<64, OUTP, false>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
@@ -470,36 +541,36 @@ extern "C" hipError_t surx_loss(const float *out, const float *target, __bf16 *d
 extern "C" hipError_t surx_conv_dgrad(int layer, const __bf16 *dz, const __bf16 *Wb, const float *yprev,
                                       __bf16 *dzprev, __bf16 *dzprevT, int X, int B, hipStream_t s)
 {
-    dim3 g(X / 64 * B), t(256);
+    dim3 g((X + BLOCK_POS - 1) / BLOCK_POS * B), t(256);
     if (layer == 5) hipLaunchKernelGGL((k_conv_dgrad<64, OUTP>), g, t, 0, s, dz, Wb, yprev, dzprev, dzprevT, X, B);
     else hipLaunchKernelGGL((k_conv_dgrad<64, 64>), g, t, 0, s, dz, Wb, yprev, dzprev, dzprevT, X, B);
     return hipGetLastError();
 }
 
-// weight and bias gradients of layer `layer` from the channels-first copies
-extern "C" hipError_t surx_conv_wgrad(int layer, const __bf16 *dzT, const __bf16 *inT, float *dW, float *db, int X,
-                                      int B, hipStream_t s)
+// partial weight and bias gradients of layer `layer` (grid: batch x slices)
+extern "C" hipError_t surx_conv_wgrad_part(int layer, const __bf16 *dzT, const __bf16 *inT, float *part, float *pbias,
+                                           int X, int B, hipStream_t s)
 {
-    auto blocks = [&](int tiles) { return dim3((unsigned)((tiles * B + 3) / 4)); };
+    const dim3 g((unsigned)(B * ((X + WG_SLICE - 1) / WG_SLICE))), t(512);
     if (layer == 0)
-        hipLaunchKernelGGL((k_conv_wgrad<16, 64>), blocks(4 * 5), dim3(256), 0, s, dzT, inT, dW, db, X, B);
+        hipLaunchKernelGGL((k_conv_wgrad_part<16, 64>), g, t, 0, s, dzT, inT, part, pbias, X);
     else if (layer < 5)
-        hipLaunchKernelGGL((k_conv_wgrad<64, 64>), blocks(4 * 20), dim3(256), 0, s, dzT, inT, dW, db, X, B);
+        hipLaunchKernelGGL((k_conv_wgrad_part<64, 64>), g, t, 0, s, dzT, inT, part, pbias, X);
     else
-        hipLaunchKernelGGL((k_conv_wgrad<64, OUTP>), blocks(OUTP / 16 * 20), dim3(256), 0, s, dzT, inT, dW, db, X, B);
+        hipLaunchKernelGGL((k_conv_wgrad_part<64, OUTP>), g, t, 0, s, dzT, inT, part, pbias, X);
     return hipGetLastError();
 }
 
-extern "C" hipError_t surx_zero(float *p, size_t n, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, s, p, n);
-    return hipGetLastError();
-}
+extern "C" int surx_wgrad_parts(int X, int B) { return B * ((X + WG_SLICE - 1) / WG_SLICE); }
 
-extern "C" hipError_t surx_adam(float *w, float *m, float *v, const float *g, int n, float lr, float b1, float b2,
-                                float eps, float c1, float c2, hipStream_t s)
+extern "C" hipError_t surx_reduce_adam(const float *part, const float *pbias, int P, float *wm, float *mw, float *vw,
+                                       float *dw, float *bias, float *mb, float *vb, float *db, __bf16 *Wf, __bf16 *Wb,
+                                       int cin, int coutp, int cout_real, int kp, int kpb, float lr, float b1,
+                                       float b2, float eps, float c1, float c2, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps, c1, c2);
+    const int n = coutp * kp + coutp;
+    hipLaunchKernelGGL(k_reduce_adam, dim3((n + 255) / 256), dim3(256), 0, s, part, pbias, P, wm, mw, vw, dw, bias,
+                       mb, vb, db, Wf, Wb, cin, coutp, cout_real, kp, kpb, lr, b1, b2, eps, c1, c2);
     return hipGetLastError();
 }
 
