@@ -6,12 +6,12 @@
 //                     absorption -> null-collision MCC (compacted candidate
 //                     queue) -> 64-bit fixed-point CIC deposit into an LDS
 //                     window histogram flushed with global integer atomics;
-//   k_field_step      one block per tile of 512 nodes of every diode:
-//                     ionisation products (ordered by parent id), thermionic
-//                     emission, pair replenishment, then the exact-integer
-//                     double prefix-scan Poisson solve and the field, tallies
-//                     and snapshots (grids above 16385 nodes: k_field_agg and
-//                     k_field_solve instead).
+//   k_field_step      one block per tile of 512 nodes of every diode plus one
+//                     for the newborn records: ionisation products (ordered
+//                     by parent id), thermionic emission, pair replenishment,
+//                     then the exact-integer double prefix-scan Poisson solve
+//                     and the field, tallies and snapshots (grids above 4097
+//                     nodes: k_field_agg and k_field_solve instead).
 // Particles are processed in chunks of 256*PPT slots; the chunk list spans all
 // (diode, species) segments and is walked by a persistent grid whose
 // block -> chunk map keeps consecutive chunks on one XCD.
@@ -1549,7 +1549,7 @@ __device__ __forceinline__ I128 shfl_up_i128(I128 a, int o)
     return r;
 }
 
-// Where the births of the two-kernel step (grids above 16385 nodes) deposit:
+// Where the births of the two-kernel step (grids above 4097 nodes) deposit:
 // they run beside the tile aggregates, which read H, so they deposit into the
 // side histograms Hb and sum their share of each tile's aggregates in LDS:
 // A_t (charge) and B_t (charge times the number of the tile's interior nodes
@@ -1834,8 +1834,9 @@ __device__ __forceinline__ I128 block_scan_excl_i128(I128 v, I128 *sh, I128 &tot
 }
 
 // ---------------------------------------------------------------------------
-// Grids above 16385 nodes (whose charge does not fit one block's LDS): the
-// same step over tiles of FT nodes in two kernels.
+// Grids above 4097 nodes: the same step over tiles of FT nodes in two kernels
+// (every block loading every node, as k_field_step does, costs more there than
+// the second launch).
 //   k_field_agg    per tile: A_t = sum of rho over the tile, B_t = sum over the
 //                  tile's interior nodes of the in-tile inclusive prefix of
 //                  rho; with births (mode 0), one more block per diode runs
@@ -2037,32 +2038,30 @@ __global__ __launch_bounds__(FT) void k_field_solve(const Diode *__restrict__ D,
 }
 
 // ---------------------------------------------------------------------------
-// Sources and field in one pass, for grids of up to FUSED_MAX_NODES nodes.
+// Sources and field in one kernel, for grids of up to FUSED_MAX_NODES nodes.
 //
-// Grid (tiles, diodes); block t of a diode writes the nodes [t TILE, (t+1) TILE)
-// of its tile.  No block waits for another's results: every block reads all
-// nodes' charge into LDS, works out the step's births itself (the same
-// counter-based draws, so every block finds the same newborns) and adds their
-// charge, then runs the exact integer double prefix scans over all nodes and
-// evaluates phi and E on its own tile and halo.  The last block of the diode
-// (the writer) also writes the newborn records and the absorbed-at-birth
-// tallies, and -- once every other block of the diode has read this step's
-// counters and tally copies (a counter the others bump) -- applies the
-// tallies, clears the copies and advances the counters.  When the particle
-// kernel spilled rare items to the global lists (normally never), block 0
-// works them off first and the others wait for its flag before reading the
-// counters those items change.  Both waits are on blocks dispatched earlier.
+// Grid (tiles + 1, diodes).  Block 0 of a diode writes the newborn records;
+// block t + 1 writes the nodes [t TILE, (t+1) TILE) of tile t:
+// it stages every node's charge in LDS, works out the positions of the step's
+// newborns (the same counter-based draws, so every block finds the same ones)
+// and adds their charge, runs the exact integer double prefix scans over all
+// nodes and evaluates phi and E on its own tile and halo.  The last tile's
+// block (the writer) applies the step's tallies, clears the tally copies and
+// advances the counters once every other block of the diode has read them (a
+// counter they bump).  When the particle kernel spilled rare items to the
+// global lists (normally never), the record block works them off first and
+// the others wait for its flag before they read the counters those items
+// change.  Every wait is on blocks of the same diode dispatched earlier.
 // ---------------------------------------------------------------------------
-constexpr int TILE = 512;                 // nodes written per block
-constexpr int FUSED_MAX_NODES = 16385;    // every node's charge staged in LDS (128 KB)
-constexpr int PER_MAX = (FUSED_MAX_NODES + FT - 1) / FT;   // nodes loaded per thread
+constexpr int TILE = 512;                 // nodes written per tile block
+constexpr int FUSED_MAX_NODES = 4097;     // every node's charge staged in each block's LDS
 
 struct BirthPlan {
     int q, R, ne;              // ionisation events, replenished pairs, emitted electrons
     int bP, bE, bI;            // first free slot per species
     int okP, okE, okI;         // births that fit per species
     uint32_t id0;              // first newborn id
-    int sorted;                // ionisation events taken in parent-id order (perm)
+    int sorted;                // ionisation events taken in parent-id order (keys)
 };
 
 // A newborn's charge into the all-node charge R (interior nodes, ions
@@ -2082,34 +2081,27 @@ __device__ __forceinline__ void fused_deposit(const Diode &dd, long long *R, uns
     if (j + 1 >= a0 && j + 1 < b0) atomicAdd(&hb[s][j + 1 - a0], a);
 }
 
-// The step's births (ionisation products in increasing parent id, thermionic
-// emission at z = v_z dt from the flux-weighted half-Maxwellian at Tc, pair
-// replenishment at a shared uniform position, Maxwellian at Te0 / Ti0), one
-// thread per newborn (pair).  Every block deposits them; the writer also
-// stores the records and tallies a newborn placed beyond the anode.
-__device__ __forceinline__ void fused_births(const Diode &dd, const BirthPlan &bp, const uint16_t *perm, bool writer,
-                                             uint32_t step, int parity, long long *R,
-                                             unsigned long long (*hb)[TILE], int a0, int b0)
+// Index of the ionisation event of rank r (parent-id order when sorted).
+__device__ __forceinline__ int iz_index(const BirthPlan &bp, const unsigned long long *keys, int r)
+{
+    return bp.sorted ? (int)(keys[r] & 0xFFFFull) : r;
+}
+
+// The positions of the step's newborns (ionisation products at their parent,
+// thermionic electrons at z = v_z dt with v_z from the flux-weighted
+// half-Maxwellian at Tc, replenished pairs at a shared uniform position),
+// one thread per newborn (pair), deposited into the block's LDS.  The writer
+// also tallies a thermionic electron placed beyond the anode.
+__device__ __forceinline__ void births_deposit(const Diode &dd, const BirthPlan &bp, const unsigned long long *keys,
+                                               bool writer, uint32_t step, long long *R,
+                                               unsigned long long (*hb)[TILE], int a0, int b0)
 {
     const int q = bp.q, ne = bp.ne, total = q + ne + bp.R;
-    const GBuf bP = gbuf(dd.buf[parity][SP_P]), bE = gbuf(dd.buf[parity][SP_E]), bI = gbuf(dd.buf[parity][SP_I]);
     for (int x = threadIdx.x; x < total; x += FT) {
         if (x < q) {
-            const int r = x;
-            const IzEvent ev = dd.izq[bp.sorted ? (int)perm[r] : r];
-            if (r < bp.okP) fused_deposit(dd, R, hb, a0, b0, SP_P, ev.z);
-            if (r < bp.okI) fused_deposit(dd, R, hb, a0, b0, SP_I, ev.z);
-            if (writer) {
-                const uint32_t ide = bp.id0 + 2u * r, idi = ide + 1u;
-                const uint4 be = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
-                const uint4 bi = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
-                if (r < bp.okP)
-                    write_particle(bP, bp.bP + r, ev.z, ev.ve[0], ev.ve[1], ev.ve[2], ide,
-                                   next_candidate(step, dd.lam[0], be.z, be.w));
-                if (r < bp.okI)
-                    write_particle(bI, bp.bI + r, ev.z, ev.vi[0], ev.vi[1], ev.vi[2], idi,
-                                   next_candidate(step, dd.lam[1], bi.z, bi.w));
-            }
+            const double z = dd.izq[iz_index(bp, keys, x)].z;
+            if (x < bp.okP) fused_deposit(dd, R, hb, a0, b0, SP_P, z);
+            if (x < bp.okI) fused_deposit(dd, R, hb, a0, b0, SP_I, z);
         } else if (x < q + ne) {
             const int i = x - q;
             if (i >= bp.okE) continue;
@@ -2117,44 +2109,83 @@ __device__ __forceinline__ void fused_births(const Diode &dd, const BirthPlan &b
             const uint4 b0w = philox(step, EV_BIRTH, 0u, 0u, idn, dd.kseed);
             const float vz = (float)(dd.sig_c * sqrt(-2.0 * log(u53(b0w.z, b0w.w))));
             const double z = (double)vz * dd.dt;
-            if (z < dd.L) fused_deposit(dd, R, hb, a0, b0, SP_E, z);
-            if (writer) {
-                const uint4 b1w = philox(step, EV_BIRTH, 1u, 0u, idn, dd.kseed);
+            if (z < dd.L) {
+                fused_deposit(dd, R, hb, a0, b0, SP_E, z);
+            } else if (writer) {
                 double n1, n2;
                 bm32(b0w.x, b0w.y, n1, n2);
-                const float vx = (float)(dd.sig_c * n1), vy = (float)(dd.sig_c * n2);
-                const uint32_t tc = next_candidate(step, dd.lam[0], b1w.z, b1w.w);
-                if (z >= dd.L) {
-                    const double ke = 0.5 * dd.mass[SP_E] * ((double)vx * vx + (double)vy * vy + (double)vz * vz);
-                    atomicAdd(&dd.tally->abs_count[SP_E][1], 1ull);
-                    atomicAdd(&dd.tally->abs_energy[SP_E][1], ke);
-                    write_particle(bE, bp.bE + i, -1.0, vx, vy, vz, idn, tc);
-                } else {
-                    write_particle(bE, bp.bE + i, z, vx, vy, vz, idn, tc);
-                }
+                const double vx = (float)(dd.sig_c * n1), vy = (float)(dd.sig_c * n2);
+                const double ke = 0.5 * dd.mass[SP_E] * (vx * vx + vy * vy + (double)vz * vz);
+                atomicAdd(&dd.tally->abs_count[SP_E][1], 1ull);
+                atomicAdd(&dd.tally->abs_energy[SP_E][1], ke);
             }
+        } else {
+            const int r = x - q - ne;
+            const uint32_t ide = bp.id0 + 2u * q + ne + 2u * r;
+            const uint4 e1 = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
+            const double z = dd.L * u53(e1.x, e1.y);
+            if (q + r < bp.okP) fused_deposit(dd, R, hb, a0, b0, SP_P, z);
+            if (q + r < bp.okI) fused_deposit(dd, R, hb, a0, b0, SP_I, z);
+        }
+    }
+}
+
+// The newborn records (positions as births_deposit, velocities, ids and
+// first free flights), one thread per newborn (pair).
+__device__ __forceinline__ void births_records(const Diode &dd, const BirthPlan &bp, const unsigned long long *keys,
+                                               uint32_t step, int parity)
+{
+    const int q = bp.q, ne = bp.ne, total = q + ne + bp.R;
+    const GBuf bP = gbuf(dd.buf[parity][SP_P]), bE = gbuf(dd.buf[parity][SP_E]), bI = gbuf(dd.buf[parity][SP_I]);
+    for (int x = threadIdx.x; x < total; x += FT) {
+        if (x < q) {
+            const int r = x;
+            const IzEvent ev = dd.izq[iz_index(bp, keys, r)];
+            const uint32_t ide = bp.id0 + 2u * r, idi = ide + 1u;
+            if (r < bp.okP) {
+                const uint4 be = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
+                write_particle(bP, bp.bP + r, ev.z, ev.ve[0], ev.ve[1], ev.ve[2], ide,
+                               next_candidate(step, dd.lam[0], be.z, be.w));
+            }
+            if (r < bp.okI) {
+                const uint4 bi = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
+                write_particle(bI, bp.bI + r, ev.z, ev.vi[0], ev.vi[1], ev.vi[2], idi,
+                               next_candidate(step, dd.lam[1], bi.z, bi.w));
+            }
+        } else if (x < q + ne) {
+            const int i = x - q;
+            if (i >= bp.okE) continue;
+            const uint32_t idn = bp.id0 + 2u * q + i;
+            const uint4 b0w = philox(step, EV_BIRTH, 0u, 0u, idn, dd.kseed);
+            const uint4 b1w = philox(step, EV_BIRTH, 1u, 0u, idn, dd.kseed);
+            double n1, n2;
+            bm32(b0w.x, b0w.y, n1, n2);
+            const float vz = (float)(dd.sig_c * sqrt(-2.0 * log(u53(b0w.z, b0w.w))));
+            const float vx = (float)(dd.sig_c * n1), vy = (float)(dd.sig_c * n2);
+            const double z = (double)vz * dd.dt;
+            const uint32_t tc = next_candidate(step, dd.lam[0], b1w.z, b1w.w);
+            // a newborn beyond the anode is absorbed at once (a hole; tallied by the writer)
+            write_particle(bE, bp.bE + i, z >= dd.L ? -1.0 : z, vx, vy, vz, idn, tc);
         } else {
             const int r = x - q - ne;
             const uint32_t ide = bp.id0 + 2u * q + ne + 2u * r, idi = ide + 1u;
             const uint4 e1 = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
             const double z = dd.L * u53(e1.x, e1.y);
-            if (q + r < bp.okP) fused_deposit(dd, R, hb, a0, b0, SP_P, z);
-            if (q + r < bp.okI) fused_deposit(dd, R, hb, a0, b0, SP_I, z);
-            if (writer) {
+            double a1, a2, a3, a4;
+            if (q + r < bp.okP) {
                 const uint4 e0 = philox(step, EV_BIRTH, 0u, 0u, ide, dd.kseed);
-                const uint4 i0 = philox(step, EV_BIRTH, 0u, 0u, idi, dd.kseed);
-                const uint4 i1 = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
-                double a1, a2, a3, a4;
                 bm32(e0.x, e0.y, a1, a2);
                 bm32(e0.z, e0.w, a3, a4);
-                if (q + r < bp.okP)
-                    write_particle(bP, bp.bP + q + r, z, (float)(dd.sig_e0 * a1), (float)(dd.sig_e0 * a2),
-                                   (float)(dd.sig_e0 * a3), ide, next_candidate(step, dd.lam[0], e1.z, e1.w));
+                write_particle(bP, bp.bP + q + r, z, (float)(dd.sig_e0 * a1), (float)(dd.sig_e0 * a2),
+                               (float)(dd.sig_e0 * a3), ide, next_candidate(step, dd.lam[0], e1.z, e1.w));
+            }
+            if (q + r < bp.okI) {
+                const uint4 i0 = philox(step, EV_BIRTH, 0u, 0u, idi, dd.kseed);
+                const uint4 i1 = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
                 bm32(i0.x, i0.y, a1, a2);
                 bm32(i0.z, i0.w, a3, a4);
-                if (q + r < bp.okI)
-                    write_particle(bI, bp.bI + q + r, z, (float)(dd.sig_i0 * a1), (float)(dd.sig_i0 * a2),
-                                   (float)(dd.sig_i0 * a3), idi, next_candidate(step, dd.lam[1], i1.z, i1.w));
+                write_particle(bI, bp.bI + q + r, z, (float)(dd.sig_i0 * a1), (float)(dd.sig_i0 * a2),
+                               (float)(dd.sig_i0 * a3), idi, next_candidate(step, dd.lam[1], i1.z, i1.w));
             }
         }
     }
@@ -2169,12 +2200,12 @@ __device__ __forceinline__ RareTally read_tally_copy(const Diode &dd)
 
 __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, int mode, int parity)
 {
-    extern __shared__ long long R[];          // all nodes' charge (first: the ionisation sort keys)
-    __shared__ unsigned long long hb[NSP][TILE];
-    __shared__ uint16_t perm[IZQ_CAP];
+    __shared__ long long R[FUSED_MAX_NODES];          // the charge of every node
+    __shared__ unsigned long long keys[IZQ_CAP];      // ionisation events by parent id
+    __shared__ unsigned long long hb[NSP][TILE];      // the own tile's deposits per species
     __shared__ long long sh64[FW];
     __shared__ I128 sh128[FW];
-    __shared__ double ph[TILE + 2];
+    __shared__ double ph[TILE + 2];                   // phi on the own tile and its halo
     __shared__ RareTally rt, rs;
     __shared__ DiodeState s_st;
     __shared__ BirthPlan bp;
@@ -2182,14 +2213,15 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     DiodeState *st = dd.st;
     const int N = dd.N, nn = N + 1;
     const int T = (nn + TILE - 1) / TILE;
-    const int t = blockIdx.x;
-    if (t >= T) return;
-    const int a0 = t * TILE, b0 = min(nn, a0 + TILE);
+    if ((int)blockIdx.x > T || (blockIdx.x == 0 && mode != 0)) return;
+    const bool records = blockIdx.x == 0;             // the newborn-record block
+    const int t = (int)blockIdx.x - 1;                // the tile of the others
     const bool writer = t == T - 1;
+    const int a0 = t * TILE, b0 = min(nn, a0 + TILE);
     const int tid = threadIdx.x;
 
-    // counters and the particle kernel's tally copies, with every node's
-    // charge and the own tile's deposits in flight meanwhile
+    // the counters and the particle kernel's tally copies; tile blocks load
+    // every node's charge and their own tile's deposits meanwhile
     RareTally copy{};
     if (mode == 0) {
         if (tid < 64) copy = read_tally_copy(dd);
@@ -2199,33 +2231,34 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
             rare_tally_zero(&rs);
         }
     }
-    long long rr[PER_MAX];
-    unsigned long long own[NSP] = {0ull, 0ull, 0ull};
-    int ownj = -1;
+    if (!records) {
+        for (int j = tid; j < nn; j += FT) {
+            long long r = 0;
+            if (j >= 1 && j <= N - 1)
+                r = (long long)(glb(dd.H[SP_I])[j] - glb(dd.H[SP_P])[j] - glb(dd.H[SP_E])[j]);
+            R[j] = r;
+        }
+        for (int i = tid; i < b0 - a0; i += FT) {
 #pragma unroll
-    for (int k = 0; k < PER_MAX; ++k) {
-        const int j = tid + k * FT;
-        rr[k] = 0;
-        if (j < nn) {
-            const unsigned long long hp = glb(dd.H[SP_P])[j], he = glb(dd.H[SP_E])[j], hi = glb(dd.H[SP_I])[j];
-            if (j >= 1 && j <= N - 1) rr[k] = (long long)(hi - hp - he);
-            if (j >= a0 && j < b0) {
-                own[SP_P] = hp;
-                own[SP_E] = he;
-                own[SP_I] = hi;
-                ownj = j;
-            }
+            for (int s = 0; s < NSP; ++s) hb[s][i] = glb(dd.H[s])[a0 + i];
         }
     }
     const uint32_t step = mode == 0 ? (uint32_t)uni((int)st->step) : 0u;
     __syncthreads();
     if (mode == 0) {
-        fold_tally_copies(copy, &rt);   // first wave
+        if (writer) {
+            fold_tally_copies(copy, &rt);     // the step's totals, applied by the writer
+        } else if (tid < 64) {
+            int v = copy.ion_lost;            // the others need the ions lost only
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (tid == 0) rt.ion_lost = v;
+        }
         if (s_st.rare_n[SP_P] | s_st.rare_n[SP_E] | s_st.rare_n[SP_I]) {
-            // items the particle kernel's queues could not hold: block 0
-            // collides them (they may queue ionisations and lose ions), then
-            // raises the flag the other blocks wait for
-            if (t == 0) {
+            // items the particle kernel's queues could not hold: the record
+            // block collides them (they may queue ionisations and lose ions),
+            // then raises the flag the other blocks wait for
+            if (records) {
                 if (tid == 0)
                     atomicAdd(&dd.tally->rare_spill,
                               (unsigned long long)(s_st.rare_n[SP_P] + s_st.rare_n[SP_E] + s_st.rare_n[SP_I]));
@@ -2246,9 +2279,9 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
             if (tid >= 64 && tid < 128) load_state(st, &s_st);
         }
         __syncthreads();
-        // this block is done with the counters and the copies
-        if (!writer && tid == 0) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (tid == 0) {
+            // this block is done with the counters and the copies
+            if (!writer) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const DiodeState &S = s_st;
             BirthPlan p;
             p.q = min(S.iz_count, IZQ_CAP);
@@ -2267,15 +2300,13 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
             p.okP = min(p.q + p.R, dd.cap[SP_P] - p.bP);
             p.okE = min(p.ne, dd.cap[SP_E] - p.bE);
             p.okI = min(p.q + p.R, dd.cap[SP_I] - p.bI);
-            // the parent-id order names the ionisation products (the writer)
-            // and, when some do not fit, decides which are dropped (all)
-            p.sorted = p.q > 1 && (writer || p.okP < p.q || p.okI < p.q);
+            // the parent-id order names the ionisation products (the record
+            // block) and, when some do not fit, decides which are dropped
+            p.sorted = p.q > 1 && (records || p.okP < p.q || p.okI < p.q);
             bp = p;
         }
         __syncthreads();
         if (bp.sorted) {
-            // bitonic sort of (parent id, event) in the charge array's space
-            unsigned long long *keys = reinterpret_cast<unsigned long long *>(R);
             const int q = bp.q;
             int np2 = 1;
             while (np2 < q) np2 <<= 1;
@@ -2295,23 +2326,12 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
                     __syncthreads();
                 }
             }
-            for (int i = tid; i < q; i += FT) perm[i] = (uint16_t)(keys[i] & 0xFFFFull);
-            __syncthreads();
         }
-    }
-    // the charge of every node and the own tile's deposits into LDS
-#pragma unroll
-    for (int k = 0; k < PER_MAX; ++k) {
-        const int j = tid + k * FT;
-        if (j < nn) R[j] = rr[k];
-    }
-    if (ownj >= 0) {
-#pragma unroll
-        for (int s = 0; s < NSP; ++s) hb[s][ownj - a0] = own[s];
-    }
-    __syncthreads();
-    if (mode == 0) {
-        fused_births(dd, bp, perm, writer, step, parity, R, hb, a0, b0);
+        if (records) {
+            births_records(dd, bp, keys, step, parity);
+            return;
+        }
+        births_deposit(dd, bp, keys, writer, step, R, hb, a0, b0);
         __syncthreads();
     }
 
@@ -2335,7 +2355,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     I128 T_N;
     I128 Tacc = block_scan_excl_i128(tl, sh128, T_N);
     const double alpha_n = dd.alpha / (double)N;
-    {
+    if (j1 > a0 - 1 && j0 <= b0) {
         long long S1 = s1off;
         for (int j = j0; j < j1; ++j) {
             S1 += R[j];
@@ -2375,10 +2395,11 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
         if (avg) glb(dd.phi_sum)[j] += pc;
     }
     if (mode != 0 || !writer) return;
-    // the writer: once every other block has read the counters and copies,
-    // the step's tallies, counters and snapshot
+    // the writer: once every other block of the diode (the other tiles and
+    // the record block) has read the counters and copies, the step's tallies,
+    // counters and snapshot
     if (tid == 0) {
-        while (__hip_atomic_load(glb(&st->arrive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < T - 1)
+        while (__hip_atomic_load(glb(&st->arrive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < T)
             __builtin_amdgcn_s_sleep(2);
         __hip_atomic_store(glb(&st->arrive), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -2457,10 +2478,6 @@ extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int n
     return hipGetLastError();
 }
 
-// max_nodes: the largest N + 1 over the diodes.  Up to FUSED_MAX_NODES nodes
-// the sources and field are one kernel over the tiles of every diode
-// (k_field_step); above (whose charge does not fit one block's LDS), the
-// births beside the tile aggregates and the tiled solve run as two kernels.
 // Kernels picx_launch_sources_field enqueues for a step (timed graphs need it).
 extern "C" int picx_sources_field_kernels(int max_nodes, int mode)
 {
@@ -2468,14 +2485,19 @@ extern "C" int picx_sources_field_kernels(int max_nodes, int mode)
     return max_nodes <= FUSED_MAX_NODES ? 1 : 2;
 }
 
+// max_nodes: the largest N + 1 over the diodes.  Up to FUSED_MAX_NODES nodes
+// the sources and field are one kernel over the tiles of every diode
+// (k_field_step); above, where loading every node into every block costs more
+// than a second launch, the births beside the tile aggregates and the tiled
+// solve run as two kernels.
+
 extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
                                                 int parity, hipStream_t s)
 {
     const size_t keys = (size_t)IZQ_CAP * 8;
     if (max_nodes <= FUSED_MAX_NODES) {
-        const size_t bytes = std::max((size_t)max_nodes * 8, keys);
         const int tiles = (max_nodes + TILE - 1) / TILE;
-        hipLaunchKernelGGL(k_field_step, dim3(tiles, nd), dim3(FT), bytes, s, D, mode, parity);
+        hipLaunchKernelGGL(k_field_step, dim3(tiles + 1, nd), dim3(FT), 0, s, D, mode, parity);
         return hipGetLastError();
     }
     const int tiles = (max_nodes + FT - 1) / FT;
@@ -2498,9 +2520,6 @@ extern "C" hipError_t picx_launch_sort(const Diode *D, DiodeState *S, int nd, in
 
 extern "C" hipError_t picx_prepare(void)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)k_field_step, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(FUSED_MAX_NODES * sizeof(long long)));
-    if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)k_phase_hist, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(PHASE_MAX_BINS * sizeof(uint32_t)));
 }

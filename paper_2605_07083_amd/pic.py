@@ -81,6 +81,10 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libpic.so is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    # PyTorch ships its own HIP runtime: load it first, so that this library
+    # binds to the same one (a library loaded before torch would bind to the
+    # system runtime, and the two would not share kernels or memory)
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P, i, i64, d = C.c_void_p, C.c_int, C.c_int64, C.c_double
     sig = {

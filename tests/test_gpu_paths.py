@@ -60,13 +60,15 @@ def test_rare_queue_spill_parity(pic, O):
     assert t["coll"][0] > 0 and t["abs_count"].sum() > 0
 
 
-def test_rare_queue_spill_parity_tiled_field(pic, O):
-    """The spill on a grid of several field tiles: block 0 of the field step
-    works the spilled items off and the other tiles wait for it before they
-    read the counters those items change."""
-    cfg = presets.scaled(presets.tiny(), N=2048, L=5e-3 * 8, n_load=40 * 2048, ng=3.2e23, Te0=5.0,
+@pytest.mark.parametrize("cells", [2048, 8192])
+def test_rare_queue_spill_parity_tiled_field(pic, O, cells):
+    """The spill on a grid of several field tiles.  2048 cells: the record
+    block of the single field kernel works the spilled items off and the tile
+    blocks wait for it before they read the counters those items change.
+    8192 cells: the births block of the two-kernel field step works them off."""
+    cfg = presets.scaled(presets.tiny(), N=cells, L=5e-3 * cells / 256, n_load=40 * cells, ng=3.2e23, Te0=5.0,
                          gamma_emit=1e21)
-    _say("case: rare-item spill with 5 field tiles (2048 cells), grid 8")
+    _say("case: rare-item spill on %d cells, grid 8" % cells)
     h = pic.Handle(cfg)
     h.set_tuning(ppt=4, grid=8, sort_period=16, use_graph=0)
     h.step(3)
