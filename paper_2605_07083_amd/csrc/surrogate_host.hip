@@ -27,6 +27,7 @@ hipError_t surx_conv_dgrad(int layer, const __bf16 *dz, const __bf16 *Wb, const 
 hipError_t surx_conv_wgrad_part(int layer, const __bf16 *dzT, const __bf16 *inT, float *part, float *pbias, int X,
                                 int B, hipStream_t s);
 int surx_wgrad_parts(int X, int B);
+int surx_loss_slots(void);
 hipError_t surx_reduce_adam(const float *part, const float *pbias, int P, float *wm, float *mw, float *vw, float *dw,
                             float *bias, float *mb, float *vb, float *db, __bf16 *Wf, __bf16 *Wb, int cin, int coutp,
                             int cout_real, int kp, int kpb, float lr, float b1, float b2, float eps, float c1,
@@ -105,7 +106,7 @@ struct sur_net {
     __bf16 *dzT[2];               // [bmax][64][X]
     float *part = nullptr;        // a layer's partial weight gradients [parts][64][320]
     float *pbias = nullptr;       // and bias gradients [parts][64]
-    double *loss = nullptr;
+    double *loss = nullptr;       // surx_loss_slots() partial sums of the training loss
     long long t = 0;              // Adam steps taken
 };
 
@@ -133,7 +134,7 @@ void layout(sur_net &n, Bump &bp)
         L.wf = bp.take<__bf16>(nw);
         L.wb = bp.take<__bf16>((size_t)L.cin * L.kpb);
     }
-    n.loss = bp.take<double>(1);
+    n.loss = bp.take<double>((size_t)surx_loss_slots());
     n.param_bytes = bp.off;
     n.feat = bp.take<__bf16>(P * SUR_IN);
     n.featT = bp.take<__bf16>(P * SUR_IN);
@@ -390,7 +391,7 @@ int sur_train_step(sur_net *n, const float *dev_params, const float *dev_target,
     if (batch < 1 || batch > n->bmax) return fail(PIC_EINVAL, "batch exceeds the workspace's max_batch");
     if (!(lr > 0.0f)) return fail(PIC_EINVAL, "learning rate must be positive");
     const int X = n->X;
-    // the forward pass zeroes the loss accumulator (features kernel)
+    // the forward pass zeroes the loss accumulators (features kernel)
     int rc = forward(n, dev_params, batch, true);
     if (rc) return rc;
     SUR_TRY(surx_loss(n->yf[SUR_LAYERS - 1], dev_target, n->dz[0], n->dzT[0], n->loss, X, batch, n->stream));
@@ -415,8 +416,13 @@ int sur_train_step(sur_net *n, const float *dev_params, const float *dev_target,
                                  L.wb, L.cin, L.coutp, L.cout, L.kp, L.kpb, lr, B1, B2, EPS, c1, c2, n->stream));
     }
     if (loss) {
-        SUR_TRY(hipMemcpyAsync(loss, n->loss, sizeof(double), hipMemcpyDeviceToHost, n->stream));
+        std::vector<double> parts((size_t)surx_loss_slots());
+        SUR_TRY(hipMemcpyAsync(parts.data(), n->loss, parts.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               n->stream));
         SUR_TRY(hipStreamSynchronize(n->stream));
+        double sum = 0.0;
+        for (double v : parts) sum += v;
+        *loss = sum;
     }
     return PIC_OK;
 }

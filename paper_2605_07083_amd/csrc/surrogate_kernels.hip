@@ -29,6 +29,7 @@ constexpr int KS = 5;     // kernel size
 constexpr int OUT = 39;   // output channels: phi / V, ln n_e / n0, ln n_i / n0, 36 velocity quantiles
 constexpr int OUTP = 48;  // padded to whole 16-column matrix-core tiles
 constexpr int PAD = 2;
+constexpr int LOSS_SLOTS = 64;   // loss accumulators (see k_loss)
 
 __device__ __forceinline__ bf16x8 zero8()
 {
@@ -62,7 +63,7 @@ __global__ void k_features(const float *__restrict__ params, __bf16 *__restrict_
                            double *__restrict__ loss0, int X, int B)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx == 0 && loss0) *loss0 = 0.0;     // the training step's loss accumulator
+    if (idx < LOSS_SLOTS && loss0) loss0[idx] = 0.0;     // the training step's loss accumulators
     if (idx >= X * B) return;
     const int b = idx / X, x = idx - b * X;
     const float g = params[4 * b + 0], T = params[4 * b + 1], V = params[4 * b + 2], ng = params[4 * b + 3];
@@ -110,25 +111,34 @@ __device__ __forceinline__ void store4T(__bf16 *p, float v0, float v1, float v2,
 // fall on different banks.
 // ---------------------------------------------------------------------------
 constexpr int BLOCK_POS = 256;   // positions per block of the forward and input-gradient kernels
+constexpr int CONV_THREADS = 512;    // 8 waves: two 16-position tiles each
 
-template <int ROWS, int KP>
+template <int ROWS, int KP, int THREADS>
 __device__ __forceinline__ void stage_rows(__bf16 *lds, const __bf16 *__restrict__ src)
 {
     constexpr int V = KP / 8;    // 16-byte vectors per row
-    for (int v = threadIdx.x; v < ROWS * V; v += blockDim.x) {
-        const int r = v / V, c = (v - r * V) * 8;
-        *reinterpret_cast<bf16x8 *>(lds + r * (KP + 8) + c) = load8(src + (size_t)r * KP + c);
+    constexpr int N = (ROWS * V + THREADS - 1) / THREADS;
+    bf16x8 r[N];                 // every load in flight before the first store
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int v = threadIdx.x + k * THREADS;
+        r[k] = v < ROWS * V ? load8(src + (size_t)(v / V) * KP + (v % V) * 8) : zero8();
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int v = threadIdx.x + k * THREADS;
+        if (v < ROWS * V) *reinterpret_cast<bf16x8 *>(lds + (v / V) * (KP + 8) + (v % V) * 8) = r[k];
     }
 }
 
 // ---------------------------------------------------------------------------
 // Forward conv: out[b][x][co] = act(bias[co] + sum_{t, ci} W[co][t][ci] in[b][x+t-2][ci]).
-// GEMM M = positions, N = COUT, K = 5*CIN (padded to KP).  A block of 4
+// GEMM M = positions, N = COUT, K = 5*CIN (padded to KP).  A block of 16
 // waves covers BLOCK_POS positions of one sample with the layer's weights in
-// LDS; a wave computes 16 positions x COUT at a time.
+// LDS; a wave computes 16 positions x COUT.
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT, bool TANH>
-__global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ in, const __bf16 *__restrict__ Wf,
+__global__ __launch_bounds__(CONV_THREADS) void k_conv_fwd(const __bf16 *__restrict__ in, const __bf16 *__restrict__ Wf,
                                                   const float *__restrict__ bias, float *__restrict__ yf,
                                                   __bf16 *__restrict__ yb, __bf16 *__restrict__ ybT, int X, int B)
 {
@@ -140,12 +150,12 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ in,
     const int tiles = (X + BLOCK_POS - 1) / BLOCK_POS;
     const int b = blockIdx.x / tiles;
     if (b >= B) return;
-    stage_rows<COUT, KP>(wl, Wf);
+    stage_rows<COUT, KP, CONV_THREADS>(wl, Wf);
     __syncthreads();
     const int m = lane & 15, kb = lane >> 4;
     const __bf16 *inb = in + (size_t)b * X * CIN;
     const int xb = (blockIdx.x - b * tiles) * BLOCK_POS;
-    for (int x0 = xb + w * 16; x0 < min(X, xb + BLOCK_POS); x0 += 64) {
+    for (int x0 = xb + w * 16; x0 < min(X, xb + BLOCK_POS); x0 += CONV_THREADS / 4) {
     f32x4 acc[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -184,32 +194,73 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const __bf16 *__restrict__ in,
 
 // ---------------------------------------------------------------------------
 // Loss: mean over (b, channel < OUT, x) of (out - target)^2.  Writes
-// dZ = 2 (out - target) / count as BF16 in the padded OUTP-channel layout.
-// target[b][c][x], out[b][x][OUTP].
+// dZ = 2 (out - target) / count as BF16 in the padded OUTP-channel layout,
+// channels last and channels first.  target[b][c][x], out[b][x][OUTP].  A
+// block takes 64 positions of one sample: the output tile is read whole into
+// LDS, the target and dZ^T rows are read and written along x, dZ along c.
+// Each block adds its sum to one of LOSS_SLOTS accumulators (block % slots),
+// so that a thousand blocks do not queue on one address; the host adds them.
 // ---------------------------------------------------------------------------
-__global__ void k_loss(const float *__restrict__ out, const float *__restrict__ target, __bf16 *__restrict__ dz,
-                       __bf16 *__restrict__ dzT, double *__restrict__ loss, int X, int B)
+constexpr int LOSS_POS = 64;
+
+__global__ __launch_bounds__(256) void k_loss(const float *__restrict__ out, const float *__restrict__ target,
+                                              __bf16 *__restrict__ dz, __bf16 *__restrict__ dzT,
+                                              double *__restrict__ loss, int X, int B)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float so[LOSS_POS][OUTP + 1];
+    __shared__ double red[4];
+    const int tiles = X / LOSS_POS;
+    const int b = blockIdx.x / tiles;
+    if (b >= B) return;
+    const int x0 = (blockIdx.x - b * tiles) * LOSS_POS;
+    const int tid = threadIdx.x;
     const double inv = 1.0 / ((double)OUT * (double)X * (double)B);
-    double acc = 0.0;
-    if (idx < X * B) {
-        const int b = idx / X, x = idx - b * X;
-        for (int c = 0; c < OUTP; ++c) {
-            float g = 0.0f;
-            if (c < OUT) {
-                const float d = out[(size_t)idx * OUTP + c] - target[((size_t)b * OUT + c) * X + x];
-                acc += (double)d * d;
-                g = (float)(2.0 * inv) * d;
-            }
-            dz[(size_t)idx * OUTP + c] = (__bf16)g;
-            dzT[((size_t)b * OUTP + c) * X + x] = (__bf16)g;
-        }
+    constexpr int PER = LOSS_POS * OUTP / 256;      // elements per thread, every load issued up front
+    static_assert(LOSS_POS * OUTP % 256 == 0, "whole passes");
+    const float *ob = out + ((size_t)b * X + x0) * OUTP;
+    float r[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) r[k] = ob[tid + 256 * k];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + 256 * k;
+        so[e / OUTP][e % OUTP] = r[k];
     }
-    // wave reduction, one atomic per wave
+    // target rows along x (channels 0 .. OUT-1)
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + 256 * k, c = e / LOSS_POS, x = e % LOSS_POS;
+        r[k] = c < OUT ? target[((size_t)b * OUT + c) * X + x0 + x] : 0.0f;
+    }
+    __syncthreads();
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + 256 * k, c = e / LOSS_POS, x = e % LOSS_POS;
+        float g = 0.0f;
+        if (c < OUT) {
+            const float d = so[x][c] - r[k];
+            acc += (double)d * d;
+            g = (float)(2.0 * inv) * d;
+        }
+        so[x][c] = g;
+        dzT[((size_t)b * OUTP + c) * X + x0 + x] = (__bf16)g;
+    }
+    __syncthreads();
+    __bf16 *db = dz + ((size_t)b * X + x0) * OUTP;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + 256 * k;
+        db[e] = (__bf16)so[e / OUTP][e % OUTP];
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if ((threadIdx.x & 63) == 0 && acc != 0.0) atomicAdd(loss, acc * inv);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        const double t = (red[0] + red[1]) + (red[2] + red[3]);
+        if (t != 0.0) atomicAdd(loss + blockIdx.x % LOSS_SLOTS, t * inv);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -218,7 +269,7 @@ __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ 
 // N = CIN, K = 5*COUT (padded), B from the transposed weights Wb[ci][t*COUT+co].
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv_dgrad(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ Wb,
+__global__ __launch_bounds__(CONV_THREADS) void k_conv_dgrad(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ Wb,
                                                     const float *__restrict__ yprev, __bf16 *__restrict__ dzprev,
                                                     __bf16 *__restrict__ dzprevT, int X, int B)
 {
@@ -230,12 +281,12 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const __bf16 *__restrict__ d
     const int tiles = (X + BLOCK_POS - 1) / BLOCK_POS;
     const int b = blockIdx.x / tiles;
     if (b >= B) return;
-    stage_rows<CIN, KP>(wl, Wb);
+    stage_rows<CIN, KP, CONV_THREADS>(wl, Wb);
     __syncthreads();
     const int m = lane & 15, kb = lane >> 4;
     const __bf16 *dzb = dz + (size_t)b * X * COUT;
     const int xb = (blockIdx.x - b * tiles) * BLOCK_POS;
-    for (int x0 = xb + w * 16; x0 < min(X, xb + BLOCK_POS); x0 += 64) {
+    for (int x0 = xb + w * 16; x0 < min(X, xb + BLOCK_POS); x0 += CONV_THREADS / 4) {
     f32x4 acc[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -300,125 +351,315 @@ __device__ __forceinline__ bf16x8 window8(uint32_t w0, uint32_t w1, uint32_t w2,
 // ---------------------------------------------------------------------------
 // Weight and bias gradients as partial sums over slices of WG_SLICE positions
 // of one sample: block p = (sample, slice) writes part[p][co][kappa] and
-// pbias[p][co]; k_reduce_adam sums the partials in a fixed order.  Wave w of
-// the block takes output-channel tile w % MT and half of the input-channel
-// tiles (c = w / MT, w / MT + 2, ...), all five taps of each: for every 32
-// positions one 16-byte load of dZ (A) is shared by up to 10 MFMAs, and one
-// 16-byte window of the input per input tile (B) by its five taps.
+// pbias[p][co]; k_reduce_adam sums the partials in a fixed order.
+//
+// The slice goes through LDS in sub-slices of WG_SUB positions: dZ rows and
+// input rows (with a halo of 8 positions each side, zero outside the sample).
+// The global loads of the next sub-slice are in flight while the waves work
+// on the current one.  Wave w takes MW output-channel tiles x CW input-channel
+// tiles (all five taps: MW * CW * 5 accumulators) over a contiguous run of
+// 32-position groups of the sub-slice; the H waves of a tile pair split the
+// groups and add their sums through LDS in a fixed order at the end.
+//
+// Per group and input tile a lane needs the 12-element window of its 8
+// positions (two before, two after): the 16-byte chunk from LDS, the dword
+// before it and the dword after it from the neighbouring lanes (ds_bpermute;
+// lanes 16 apart hold adjacent chunks), the outer lanes' from the previous
+// and the next group, which the wave reads one group ahead.  Rows are padded
+// so that the 16-byte reads of 8 consecutive rows fall on different banks.
+// The bias gradient is one more MFMA per output tile and group, against a
+// column of ones.  The block's partial is assembled in LDS and written out in
+// 16-byte stores by every thread.
 // ---------------------------------------------------------------------------
 constexpr int WG_SLICE = 512;
+constexpr int WG_SUB = 128;
+constexpr int WG_THREADS = 512;
+constexpr int WG_HALO = 8;
+constexpr int WG_AROW = WG_SUB + 8;                    // dZ row in LDS
+constexpr int WG_BROW = WG_SUB + 2 * WG_HALO + 8;      // input row: positions -8 .. WG_SUB + 8 of the sub-slice
+
+__device__ __forceinline__ void store8(__bf16 *p, bf16x8 v) { *reinterpret_cast<bf16x8 *>(p) = v; }
 
 template <int CIN, int COUT>
-__global__ __launch_bounds__(512) void k_conv_wgrad_part(const __bf16 *__restrict__ dzT, const __bf16 *__restrict__ inT,
-                                                         float *__restrict__ part, float *__restrict__ pbias, int X)
+struct WgradShape {
+    static constexpr int K = KS * CIN, KP = (K + 31) / 32 * 32;
+    static constexpr int MT = COUT / 16, CT = CIN / 16;
+    static constexpr int MW = MT % 2 == 0 ? 2 : MT;         // output tiles per wave
+    static constexpr int CW = (MW == 2 && CT % 2 == 0) ? 2 : 1;   // input tiles per wave
+    static constexpr int PAIRS = (MT / MW) * (CT / CW);
+    static constexpr int WAVES = WG_THREADS / 64;
+    static constexpr int H = WAVES / PAIRS;                 // waves per tile pair (position runs)
+    static constexpr int RS = (MW * CW * KS + MW) * 4;      // weight and bias accumulators per lane
+    static constexpr int AV = WG_SUB / 8, BV = WG_SUB / 8 + 2;   // 16-byte vectors per row
+    static constexpr int NA = (COUT * AV + WG_THREADS - 1) / WG_THREADS;
+    static constexpr int NB = (CIN * BV + WG_THREADS - 1) / WG_THREADS;
+    static constexpr size_t LDS_A = (size_t)COUT * WG_AROW * 2;
+    static constexpr size_t LDS_OP = LDS_A + (size_t)CIN * WG_BROW * 2;
+    static constexpr size_t LDS_RED = (size_t)(H - 1) * PAIRS * RS * 64 * 4;
+    static constexpr size_t LDS_OUT = (size_t)COUT * (KP + 1) * 4;    // the block's partial, staged for wide stores
+    static constexpr size_t LDS_1 = LDS_OP > LDS_RED ? LDS_OP : LDS_RED;
+    static constexpr size_t LDS = LDS_1 > LDS_OUT ? LDS_1 : LDS_OUT;
+    static_assert(MT % MW == 0 && CT % CW == 0 && WAVES % PAIRS == 0 && H >= 1, "wave tiling");
+    static_assert((WG_SUB / 32) % H == 0, "whole groups per wave");
+};
+
+// Global loads of one sub-slice (positions xs .. xs + sl of sample b) into registers.
+template <int CIN, int COUT>
+__device__ __forceinline__ void wg_load(const __bf16 *__restrict__ dzT, const __bf16 *__restrict__ inT, int b, int xs,
+                                        int sl, int X, bf16x8 *ra, bf16x8 *rb)
 {
-    constexpr int K = KS * CIN;
-    constexpr int KP = (K + 31) / 32 * 32;
-    constexpr int MT = COUT / 16, CT = CIN / 16;
-    constexpr int CH = CT >= 2 ? 2 : 1;           // waves per output tile
-    constexpr int CPW = CT / CH;                  // input tiles per wave
-    static_assert(CIN % 16 == 0 && CT % CH == 0, "whole input-channel tiles");
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (w >= MT * CH) return;
-    const int mt = w % MT, ch = w / MT;
-    const int slices = (X + WG_SLICE - 1) / WG_SLICE;
-    const int p = blockIdx.x, b = p / slices;
-    const int xb = (p - b * slices) * WG_SLICE, xe = min(X, xb + WG_SLICE);
-    const int m = lane & 15, kb = lane >> 4;
-    const int co = mt * 16 + m;
-    const __bf16 *arow = dzT + ((size_t)b * COUT + co) * X;
-    const __bf16 *brow[CPW];
+    using S = WgradShape<CIN, COUT>;
 #pragma unroll
-    for (int c = 0; c < CPW; ++c) brow[c] = inT + ((size_t)b * CIN + (ch + CH * c) * 16 + m) * X;
-    f32x4 acc[KS][CPW];
-#pragma unroll
-    for (int t = 0; t < KS; ++t)
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) acc[t][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.0f;
-    for (int x0 = xb; x0 < xe; x0 += 32) {
-        const int xa = x0 + kb * 8;
-        const bf16x8 a = load8(arow + xa);
-        if (ch == 0) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) bsum += (float)a[i];
-        }
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            const uint32_t *bw = reinterpret_cast<const uint32_t *>(brow[c]);
-            const u32x4 mid = *reinterpret_cast<const u32x4 *>(brow[c] + xa);
-            const uint32_t lo = xa > 0 ? bw[(xa >> 1) - 1] : 0u;
-            const uint32_t hi = xa + 8 < X ? bw[(xa >> 1) + 4] : 0u;
-            acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, window8<0>(lo, mid[0], mid[1], mid[2], mid[3], hi),
-                                                                acc[0][c], 0, 0, 0);
-            acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, window8<1>(lo, mid[0], mid[1], mid[2], mid[3], hi),
-                                                                acc[1][c], 0, 0, 0);
-            acc[2][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, window8<2>(lo, mid[0], mid[1], mid[2], mid[3], hi),
-                                                                acc[2][c], 0, 0, 0);
-            acc[3][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, window8<3>(lo, mid[0], mid[1], mid[2], mid[3], hi),
-                                                                acc[3][c], 0, 0, 0);
-            acc[4][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, window8<4>(lo, mid[0], mid[1], mid[2], mid[3], hi),
-                                                                acc[4][c], 0, 0, 0);
-        }
+    for (int k = 0; k < S::NA; ++k) {
+        const int v = threadIdx.x + k * WG_THREADS, r = v / S::AV, c = (v % S::AV) * 8;
+        ra[k] = v < COUT * S::AV && c < sl ? load8(dzT + ((size_t)b * COUT + r) * X + xs + c) : zero8();
     }
-    float *out = part + (size_t)p * COUT * KP;
 #pragma unroll
-    for (int t = 0; t < KS; ++t)
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            const int kappa = t * CIN + (ch + CH * c) * 16 + m;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) out[(size_t)(mt * 16 + kb * 4 + i) * KP + kappa] = acc[t][c][i];
-        }
-    if (ch == 0) {
-        bsum += __shfl_xor(bsum, 16, 64);
-        bsum += __shfl_xor(bsum, 32, 64);
-        if (kb == 0) pbias[(size_t)p * COUT + co] = bsum;
+    for (int k = 0; k < S::NB; ++k) {
+        const int v = threadIdx.x + k * WG_THREADS, r = v / S::BV, c = (v % S::BV) * 8;
+        const int x = xs + c - WG_HALO;
+        rb[k] = v < CIN * S::BV && c < sl + 2 * WG_HALO && x >= 0 && x < X
+                    ? load8(inT + ((size_t)b * CIN + r) * X + x) : zero8();
     }
 }
 
-// The gradient of one layer from its partials (summed in partial order),
-// then Adam on the FP32 master weights and biases and the BF16 copies of the
-// weights: forward layout Wf[co][kappa] and transposed Wb[ci][t*COUTP + co].
-// One thread per weight (padded [COUTP][KP]) and per bias.
-__global__ void k_reduce_adam(const float *__restrict__ part, const float *__restrict__ pbias, int P,
-                              float *__restrict__ wm, float *__restrict__ mw, float *__restrict__ vw,
-                              float *__restrict__ dw, float *__restrict__ bias, float *__restrict__ mb,
-                              float *__restrict__ vb, float *__restrict__ db, __bf16 *__restrict__ Wf,
-                              __bf16 *__restrict__ Wb, int cin, int coutp, int cout_real, int kp, int kpb, float lr,
-                              float b1, float b2, float eps, float c1, float c2)
+template <int CIN, int COUT>
+__device__ __forceinline__ void wg_store(__bf16 *As, __bf16 *Bs, const bf16x8 *ra, const bf16x8 *rb)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    using S = WgradShape<CIN, COUT>;
+#pragma unroll
+    for (int k = 0; k < S::NA; ++k) {
+        const int v = threadIdx.x + k * WG_THREADS;
+        if (v < COUT * S::AV) store8(As + (v / S::AV) * WG_AROW + (v % S::AV) * 8, ra[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < S::NB; ++k) {
+        const int v = threadIdx.x + k * WG_THREADS;
+        if (v < CIN * S::BV) store8(Bs + (v / S::BV) * WG_BROW + (v % S::BV) * 8, rb[k]);
+    }
+}
+
+__device__ __forceinline__ uint32_t lane_from(int src_lane, uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane << 2, (int)v);
+}
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(WG_THREADS) void k_conv_wgrad_part(const __bf16 *__restrict__ dzT,
+                                                                const __bf16 *__restrict__ inT,
+                                                                float *__restrict__ part, float *__restrict__ pbias,
+                                                                int X)
+{
+    using S = WgradShape<CIN, COUT>;
+    constexpr int KP = S::KP, MW = S::MW, CW = S::CW, PAIRS = S::PAIRS, H = S::H, RS = S::RS;
+    constexpr int GPW = WG_SUB / 32 / H;                  // groups per wave per whole sub-slice
+    __shared__ __align__(16) char lds[S::LDS];
+    __bf16 *As = reinterpret_cast<__bf16 *>(lds);
+    __bf16 *Bs = reinterpret_cast<__bf16 *>(lds + S::LDS_A);
+    const int slices = (X + WG_SLICE - 1) / WG_SLICE;
+    const int p = blockIdx.x, b = p / slices;
+    const int xb = (p - b * slices) * WG_SLICE;
+    const int len = min(X, xb + WG_SLICE) - xb;           // a multiple of 64
+
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool active = w < PAIRS * H;
+    const int pair = w % PAIRS, h = w / PAIRS;
+    const int mw = pair % (S::MT / MW), cw = pair / (S::MT / MW);
+    const int m = lane & 15, kb = lane >> 4;
+    const int from_lo = (lane - 16) & 63, from_hi = (lane + 16) & 63;
+
+    f32x4 acc[MW][CW][KS], bacc[MW];
+#pragma unroll
+    for (int u = 0; u < MW; ++u) {
+        bacc[u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int v = 0; v < CW; ++v)
+#pragma unroll
+            for (int t = 0; t < KS; ++t) acc[u][v][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    }
+    bf16x8 ones;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ones[i] = (__bf16)1.0f;
+
+    bf16x8 ra[S::NA], rb[S::NB];
+    wg_load<CIN, COUT>(dzT, inT, b, xb, min(WG_SUB, len), X, ra, rb);
+    for (int xs = 0; xs < len; xs += WG_SUB) {
+        const int sl = min(WG_SUB, len - xs);
+        wg_store<CIN, COUT>(As, Bs, ra, rb);
+        __syncthreads();
+        if (xs + WG_SUB < len)     // the next sub-slice's loads fly while this one is worked on
+            wg_load<CIN, COUT>(dzT, inT, b, xb + xs + WG_SUB, min(WG_SUB, len - xs - WG_SUB), X, ra, rb);
+        const int g0 = h * GPW, g1 = min(g0 + GPW, sl / 32);
+        if (active && g0 < g1) {
+            // B chunk of a group for input tile v; columns clamped into the row
+            // (the clamped reads feed no result)
+            auto bchunk = [&](int v, int g) {
+                const int col = min(max(g * 32 + kb * 8 + WG_HALO, 0), WG_BROW - 8);
+                return *reinterpret_cast<const u32x4 *>(Bs + ((cw * CW + v) * 16 + m) * WG_BROW + col);
+            };
+            u32x4 cur[CW];
+            uint32_t prev3[CW];
+#pragma unroll
+            for (int v = 0; v < CW; ++v) {
+                cur[v] = bchunk(v, g0);
+                prev3[v] = bchunk(v, g0 - 1)[3];      // the lanes kb = 3 hold the group before's last chunk
+            }
+            for (int g = g0; g < g1; ++g) {
+                bf16x8 a[MW];
+#pragma unroll
+                for (int u = 0; u < MW; ++u) {
+                    a[u] = *reinterpret_cast<const bf16x8 *>(As + ((mw * MW + u) * 16 + m) * WG_AROW + g * 32 + kb * 8);
+                    bacc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], ones, bacc[u], 0, 0, 0);
+                }
+#pragma unroll
+                for (int v = 0; v < CW; ++v) {
+                    const u32x4 nxt = bchunk(v, g + 1);
+                    // dword before the chunk: lane kb - 1's last one (kb = 0: the
+                    // group before, held by lane kb = 3); dword after: lane kb + 1's
+                    // first one (kb = 3: the next group, read by lane kb = 0)
+                    const uint32_t lo = lane_from(from_lo, kb == 3 ? prev3[v] : cur[v][3]);
+                    const uint32_t hi = lane_from(from_hi, kb == 0 ? nxt[0] : cur[v][0]);
+                    const bf16x8 w0 = window8<0>(lo, cur[v][0], cur[v][1], cur[v][2], cur[v][3], hi);
+                    const bf16x8 w1 = window8<1>(lo, cur[v][0], cur[v][1], cur[v][2], cur[v][3], hi);
+                    const bf16x8 w2 = window8<2>(lo, cur[v][0], cur[v][1], cur[v][2], cur[v][3], hi);
+                    const bf16x8 w3 = window8<3>(lo, cur[v][0], cur[v][1], cur[v][2], cur[v][3], hi);
+                    const bf16x8 w4 = window8<4>(lo, cur[v][0], cur[v][1], cur[v][2], cur[v][3], hi);
+#pragma unroll
+                    for (int u = 0; u < MW; ++u) {
+                        acc[u][v][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], w0, acc[u][v][0], 0, 0, 0);
+                        acc[u][v][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], w1, acc[u][v][1], 0, 0, 0);
+                        acc[u][v][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], w2, acc[u][v][2], 0, 0, 0);
+                        acc[u][v][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], w3, acc[u][v][3], 0, 0, 0);
+                        acc[u][v][4] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], w4, acc[u][v][4], 0, 0, 0);
+                    }
+                    prev3[v] = cur[v][3];
+                    cur[v] = nxt;
+                }
+            }
+        }
+        __syncthreads();           // the sub-slice's LDS is read before the next one is stored
+    }
+
+    // the other position runs of a tile pair hand their sums to the first through LDS
+    float *R = reinterpret_cast<float *>(lds);
+    constexpr int NACC = MW * CW * KS;
+    if (H > 1 && active && h > 0) {
+        float *r = R + ((size_t)((h - 1) * PAIRS + pair) * RS) * 64 + lane;
+#pragma unroll
+        for (int u = 0; u < MW; ++u)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                for (int v = 0; v < CW; ++v)
+#pragma unroll
+                    for (int t = 0; t < KS; ++t) r[(((u * CW + v) * KS + t) * 4 + i) * 64] = acc[u][v][t][i];
+                r[((NACC + u) * 4 + i) * 64] = bacc[u][i];
+            }
+    }
+    __syncthreads();
+    if (active && h == 0) {
+#pragma unroll
+        for (int g = 1; g < H; ++g) {
+            const float *r = R + ((size_t)((g - 1) * PAIRS + pair) * RS) * 64 + lane;
+#pragma unroll
+            for (int u = 0; u < MW; ++u)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                    for (int v = 0; v < CW; ++v)
+#pragma unroll
+                        for (int t = 0; t < KS; ++t) acc[u][v][t][i] += r[(((u * CW + v) * KS + t) * 4 + i) * 64];
+                    bacc[u][i] += r[((NACC + u) * 4 + i) * 64];
+                }
+        }
+    }
+    __syncthreads();
+    // the block's partial [COUT][KP] (row stride KP + 1) and bias sums in LDS
+    float *O = reinterpret_cast<float *>(lds);
+    constexpr int OS = KP + 1;
+    if (active && h == 0) {
+#pragma unroll
+        for (int u = 0; u < MW; ++u)
+#pragma unroll
+            for (int v = 0; v < CW; ++v)
+#pragma unroll
+                for (int t = 0; t < KS; ++t) {
+                    const int kappa = t * CIN + (cw * CW + v) * 16 + m;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) O[((mw * MW + u) * 16 + kb * 4 + i) * OS + kappa] = acc[u][v][t][i];
+                }
+        // column n of the ones product holds the row sums: lanes n = 0
+        if (cw == 0 && m == 0) {
+#pragma unroll
+            for (int u = 0; u < MW; ++u)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pbias[(size_t)p * COUT + (mw * MW + u) * 16 + kb * 4 + i] = bacc[u][i];
+        }
+    }
+    __syncthreads();
+    float *out = part + (size_t)p * COUT * KP;
+    constexpr int Q = KP / 4;            // 16-byte stores per row
+    for (int e = threadIdx.x; e < COUT * Q; e += WG_THREADS) {
+        const int r = e / Q, c = (e % Q) * 4;
+        const float *o = O + r * OS + c;
+        *reinterpret_cast<float4 *>(out + (size_t)r * KP + c) = make_float4(o[0], o[1], o[2], o[3]);
+    }
+}
+
+// The gradient of one layer from its partials, then Adam on the FP32 master
+// weights and biases and the BF16 copies of the weights: forward layout
+// Wf[co][kappa] and transposed Wb[ci][t*COUTP + co].  A block takes 64
+// consecutive entries of the padded weights [COUTP][KP] followed by the
+// biases; wave w sums the partials w, w + 16, ... of each, and the first
+// wave adds the 16 sums in wave order and updates.
+// ---------------------------------------------------------------------------
+constexpr int RA_WAVES = 16;
+
+__global__ __launch_bounds__(RA_WAVES * 64) void k_reduce_adam(
+    const float *__restrict__ part, const float *__restrict__ pbias, int P, float *__restrict__ wm,
+    float *__restrict__ mw, float *__restrict__ vw, float *__restrict__ dw, float *__restrict__ bias,
+    float *__restrict__ mb, float *__restrict__ vb, float *__restrict__ db, __bf16 *__restrict__ Wf,
+    __bf16 *__restrict__ Wb, int cin, int coutp, int cout_real, int kp, int kpb, float lr, float b1, float b2,
+    float eps, float c1, float c2)
+{
+    __shared__ float red[RA_WAVES][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
     const int nw = coutp * kp;
-    if (i >= nw + coutp) return;
-    float *w, *mo, *ve, *g;
+    const bool isw = i < nw, inr = i < nw + coutp;
     int co, kappa = 0, stride, at;
-    if (i < nw) {
+    if (isw) {
         co = i / kp;
         kappa = i - co * kp;
-        w = wm + i; mo = mw + i; ve = vw + i; g = dw + i;
         stride = nw;
         at = i;
     } else {
         co = i - nw;
-        w = bias + co; mo = mb + co; ve = vb + co; g = db + co;
         stride = coutp;
         at = co;
     }
-    const bool live = co < cout_real && (i >= nw || kappa < KS * cin);
-    float gi = 0.0f;
+    const bool live = inr && co < cout_real && (!isw || kappa < KS * cin);
+    float sum = 0.0f;
     if (live) {
-        const float *src = i < nw ? part : pbias;
-        for (int q = 0; q < P; ++q) gi += src[(size_t)q * stride + at];
+        const float *src = (isw ? part : pbias) + at;
+#pragma unroll 4
+        for (int q = w; q < P; q += RA_WAVES) sum += src[(size_t)q * stride];
     }
-    *g = gi;
+    red[w][lane] = sum;
+    __syncthreads();
+    if (w != 0 || !inr) return;
+    float gi = 0.0f;
+#pragma unroll
+    for (int k = 0; k < RA_WAVES; ++k) gi += red[k][lane];
+    float *wp = isw ? wm + i : bias + co, *mo = isw ? mw + i : mb + co, *ve = isw ? vw + i : vb + co;
+    (isw ? dw[i] : db[co]) = gi;
     const float m1 = b1 * *mo + (1.0f - b1) * gi;
     const float v1 = b2 * *ve + (1.0f - b2) * gi * gi;
     *mo = m1;
     *ve = v1;
-    const float nwv = *w - lr * (m1 / c1) / (sqrtf(v1 / c2) + eps);
-    *w = nwv;
-    if (i < nw) {
+    const float nwv = *wp - lr * (m1 / c1) / (sqrtf(v1 / c2) + eps);
+    *wp = nwv;
+    if (isw) {
         const __bf16 v = (__bf16)(live ? nwv : 0.0f);
         Wf[i] = v;
         if (kappa < KS * cin) {
@@ -512,10 +753,14 @@ __global__ void k_unpack(const float *__restrict__ y, float *__restrict__ out, i
 // ---------------------------------------------------------------------------
 using namespace sur;
 
+extern "C" int surx_loss_slots(void) { return LOSS_SLOTS; }
+
+// loss0 (LOSS_SLOTS doubles, may be null) is cleared for the training step's loss
 extern "C" hipError_t surx_features(const float *params, __bf16 *feat, __bf16 *featT, double *loss0, int X, int B,
                                     hipStream_t s)
 {
-    hipLaunchKernelGGL(k_features, dim3((X * B + 255) / 256), dim3(256), 0, s, params, feat, featT, loss0, X, B);
+    const int n = X * B > LOSS_SLOTS ? X * B : LOSS_SLOTS;
+    hipLaunchKernelGGL(k_features, dim3((n + 255) / 256), dim3(256), 0, s, params, feat, featT, loss0, X, B);
     return hipGetLastError();
 }
 
@@ -523,7 +768,7 @@ extern "C" hipError_t surx_features(const float *params, __bf16 *feat, __bf16 *f
 extern "C" hipError_t surx_conv_fwd(int layer, const __bf16 *in, const __bf16 *Wf, const float *bias, float *yf,
                                     __bf16 *yb, __bf16 *ybT, int X, int B, hipStream_t s)
 {
-    dim3 g((X + BLOCK_POS - 1) / BLOCK_POS * B), t(256);
+    dim3 g((X + BLOCK_POS - 1) / BLOCK_POS * B), t(CONV_THREADS);
     if (layer == 0) hipLaunchKernelGGL((k_conv_fwd<16, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
     else if (layer < 5) hipLaunchKernelGGL((k_conv_fwd<64, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
     else hipLaunchKernelGGL((k_conv_fwd<64, OUTP, false>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
@@ -533,7 +778,7 @@ extern "C" hipError_t surx_conv_fwd(int layer, const __bf16 *in, const __bf16 *W
 extern "C" hipError_t surx_loss(const float *out, const float *target, __bf16 *dz, __bf16 *dzT, double *loss, int X,
                                 int B, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_loss, dim3((X * B + 255) / 256), dim3(256), 0, s, out, target, dz, dzT, loss, X, B);
+    hipLaunchKernelGGL(k_loss, dim3(X / LOSS_POS * B), dim3(256), 0, s, out, target, dz, dzT, loss, X, B);
     return hipGetLastError();
 }
 
@@ -541,7 +786,7 @@ extern "C" hipError_t surx_loss(const float *out, const float *target, __bf16 *d
 extern "C" hipError_t surx_conv_dgrad(int layer, const __bf16 *dz, const __bf16 *Wb, const float *yprev,
                                       __bf16 *dzprev, __bf16 *dzprevT, int X, int B, hipStream_t s)
 {
-    dim3 g((X + BLOCK_POS - 1) / BLOCK_POS * B), t(256);
+    dim3 g((X + BLOCK_POS - 1) / BLOCK_POS * B), t(CONV_THREADS);
     if (layer == 5) hipLaunchKernelGGL((k_conv_dgrad<64, OUTP>), g, t, 0, s, dz, Wb, yprev, dzprev, dzprevT, X, B);
     else hipLaunchKernelGGL((k_conv_dgrad<64, 64>), g, t, 0, s, dz, Wb, yprev, dzprev, dzprevT, X, B);
     return hipGetLastError();
@@ -551,7 +796,7 @@ extern "C" hipError_t surx_conv_dgrad(int layer, const __bf16 *dz, const __bf16 
 extern "C" hipError_t surx_conv_wgrad_part(int layer, const __bf16 *dzT, const __bf16 *inT, float *part, float *pbias,
                                            int X, int B, hipStream_t s)
 {
-    const dim3 g((unsigned)(B * ((X + WG_SLICE - 1) / WG_SLICE))), t(512);
+    const dim3 g((unsigned)(B * ((X + WG_SLICE - 1) / WG_SLICE))), t(WG_THREADS);
     if (layer == 0)
         hipLaunchKernelGGL((k_conv_wgrad_part<16, 64>), g, t, 0, s, dzT, inT, part, pbias, X);
     else if (layer < 5)
@@ -569,7 +814,7 @@ extern "C" hipError_t surx_reduce_adam(const float *part, const float *pbias, in
                                        float b2, float eps, float c1, float c2, hipStream_t s)
 {
     const int n = coutp * kp + coutp;
-    hipLaunchKernelGGL(k_reduce_adam, dim3((n + 255) / 256), dim3(256), 0, s, part, pbias, P, wm, mw, vw, dw, bias,
+    hipLaunchKernelGGL(k_reduce_adam, dim3((n + 63) / 64), dim3(RA_WAVES * 64), 0, s, part, pbias, P, wm, mw, vw, dw, bias,
                        mb, vb, db, Wf, Wb, cin, coutp, cout_real, kp, kpb, lr, b1, b2, eps, c1, c2);
     return hipGetLastError();
 }
