@@ -95,11 +95,20 @@ class Surrogate:
         _check(lib().sur_create(max_batch, cells, C.c_void_p(self.ws.data_ptr()), nbytes,
                                 C.c_void_p(self.stream.cuda_stream), seed, C.byref(h)))
         self.h = h
+        self._lib = lib()      # kept for close() at interpreter exit, when module globals may be gone
+
+    def close(self):
+        """Release the handle (the workspace tensor is released with the object)."""
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.stream.synchronize()
+            self._lib.sur_destroy(self.h)
+            self.h = None
 
     def __del__(self):
-        if getattr(self, "h", None) is not None and self.h.value:
-            lib().sur_destroy(self.h)
-            self.h = None
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def _params(self, params):
         import torch
