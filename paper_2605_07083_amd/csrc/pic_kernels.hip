@@ -26,6 +26,11 @@ constexpr int QW_SLACK = 384;      // per-wave LDS queue of rare items: 64 PPT +
 constexpr int DRIFT = 160;         // cells of drift since the last re-sort kept in the LDS window
 constexpr int BIN_SHIFT = 5;       // the re-sort orders particles by bins of 32 cells
 constexpr int DRIFT_B = (DRIFT >> BIN_SHIFT) + 1;   // the drift margin in bins
+// The re-sort's window margin (bins) around a run's first and last bin: wide
+// enough for the fastest electrons of a period (a particle outside takes a
+// global counter atomic and four partial-line stores of its own); the LDS
+// counts hold up to WMAX + 1 bins.
+constexpr int SORT_DRIFT_B = 64;
 
 __host__ __device__ constexpr int nbins_of(int N) { return ((N - 1) >> BIN_SHIFT) + 1; }
 // The counter / offset of bin b lives at cell slot b << BIN_SHIFT of the count
@@ -1176,7 +1181,7 @@ __device__ __forceinline__ int wave_group_rank(int key, AddFn add)
 }
 
 // Window of a run of chunks for the re-sort: bins of its first and last
-// particle plus the drift margin (bins).
+// particle plus the re-sort's drift margin (bins).
 __device__ __forceinline__ void sort_window(const Diode &dd, const GBuf &b, int slot0, int last_slot, int &w0,
                                             int &wn)
 {
@@ -1186,21 +1191,8 @@ __device__ __forceinline__ void sort_window(const Diode &dd, const GBuf &b, int 
     cic(b.z[max(last_slot, slot0)], dd.invdz, dd.N, jb, f);
     ja >>= BIN_SHIFT;
     jb >>= BIN_SHIFT;
-    w0 = uni(max(0, min(ja, jb) - DRIFT_B));
-    wn = uni(min(min(nbins_of(dd.N) - 1, max(ja, jb) + DRIFT_B) - w0 + 1, WMAX + 1));
-}
-
-// The same window from the two positions.
-__device__ __forceinline__ void sort_window_z(const Diode &dd, double za, double zb, int &w0, int &wn)
-{
-    int ja, jb;
-    double f;
-    cic(za, dd.invdz, dd.N, ja, f);
-    cic(zb, dd.invdz, dd.N, jb, f);
-    ja >>= BIN_SHIFT;
-    jb >>= BIN_SHIFT;
-    w0 = uni(max(0, min(ja, jb) - DRIFT_B));
-    wn = uni(min(min(nbins_of(dd.N) - 1, max(ja, jb) + DRIFT_B) - w0 + 1, WMAX + 1));
+    w0 = uni(max(0, min(ja, jb) - SORT_DRIFT_B));
+    wn = uni(min(min(nbins_of(dd.N) - 1, max(ja, jb) + SORT_DRIFT_B) - w0 + 1, WMAX + 1));
 }
 
 // Cell counts of the live particles.  Each thread counts runs of equal cells
@@ -1300,9 +1292,16 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const Diode *__restrict__ D)
     if (threadIdx.x == 1023) dd.st->n_new[s] = part[1023];
 }
 
-// Scatter into the other buffer in cell order (holes dropped).  Ranks within
-// a block come from LDS atomics on runs of equal cells, block bases from one
-// global atomic per (block, cell).
+// Scatter into the other buffer in bin order (holes dropped).  A block takes
+// its contiguous range of chunks run by run (a run lies in one diode and
+// species): it counts the run's particles per bin of the run's window in LDS,
+// reserves one contiguous range per bin with one global atomic each, then
+// streams the run again and gives every particle the next slot of its bin's
+// range from an LDS atomic.  A bin's particles of the run so leave as one
+// contiguous range written by one block (its lines fill in L2 before they are
+// written back), and the stream needs no barrier.  A particle outside the
+// window (a newborn of the unsorted tail, say) takes a slot from its bin's
+// global counter directly.
 template <int PPT>
 __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D, const DiodeState *__restrict__ S,
                                                      int nd, int parity)
@@ -1310,167 +1309,112 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
     constexpr int CHUNK = NT * PPT;
     __shared__ int seg_end[NSP * MAX_DIODES];
     __shared__ int seg_n[NSP * MAX_DIODES];
-    __shared__ int cnt[WMAX + 2];       // the block's count per window bin, then its global base
-    __shared__ int loc[WMAX + 2];       // start of each window bin in the block's staging order
-    __shared__ int s_nin;
-    // The chunk's in-window particles are staged in LDS in destination order
-    // and written out by consecutive threads: each bin's run of the block then
-    // leaves as contiguous stores rather than as lanes scattered over the bins.
-    __shared__ double st_z[CHUNK];
-    __shared__ float st_vz[CHUNK];
-    __shared__ uint32_t st_tc[CHUNK];
-    __shared__ int st_dest[CHUNK];
-    __shared__ u32x4 st_cold[CHUNK];
-    __shared__ double s_zw[2];          // positions of the chunk's first and last slot
+    __shared__ int cur[WMAX + 2];       // the run's count per window bin, then its next free slot
     ChunkMap cm;
     build_chunk_map(S, nd, CHUNK, false, seg_end, cm, seg_n);
     const int tid = threadIdx.x;
     const int per_block = (cm.total + gridDim.x - 1) / gridDim.x;
     const int c_begin = blockIdx.x * per_block;
     const int c_end = min(cm.total, c_begin + per_block);
-    // A chunk's records are loaded one chunk ahead, into registers, so the
-    // loads of the next chunk are in flight while this one is ranked and
-    // written; the window comes from the chunk's own first and last slot.
-    double zq[PPT];
-    float vq[PPT];
-    u32x4 cq[PPT];
-    uint32_t tq[PPT];
-    auto fetch = [&](int cidx) {
-        const int sg = find_seg(seg_end, cm.nseg, cidx);
-        const int sb = sg ? seg_end[sg - 1] : 0;
-        const int dq = sg / NSP, sq = sg - dq * NSP;
-        const GBuf src = gbuf(D[dq].buf[parity][sq]);
-        const int nq = seg_n[sg];
-        const int t0 = (cidx - sb) * CHUNK + tid * PPT;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            zq[k] = -1.0;
-            if (t0 + k < nq) {
-                zq[k] = src.z[t0 + k];
-                vq[k] = src.vz[t0 + k];
-                cq[k] = *(const GLB u32x4 *)&src.cold[t0 + k];
-                tq[k] = src.tc[t0 + k];
-            }
-        }
-    };
-    if (c_begin < c_end) fetch(c_begin);
-    for (int c = c_begin; c < c_end; ++c) {
+    for (int c = c_begin; c < c_end;) {
         const int seg = find_seg(seg_end, cm.nseg, c);
+        const int run_end = min(c_end, seg_end[seg]);
         const int segbase = seg ? seg_end[seg - 1] : 0;
         const int d = seg / NSP, s = seg - d * NSP;
         const Diode &dd = D[d];
+        const GBuf src = gbuf(dd.buf[parity][s]);
         const GBuf dst = gbuf(dd.buf[parity ^ 1][s]);
         const int n = seg_n[seg];
         const int slot0 = (c - segbase) * CHUNK;
-        const int t0 = slot0 + tid * PPT;
-        double z[PPT];
-        float vzr[PPT];
-        u32x4 cold[PPT];
-        uint32_t tcr[PPT];
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            z[k] = zq[k];
-            vzr[k] = vq[k];
-            cold[k] = cq[k];
-            tcr[k] = tq[k];
-        }
-        if (c + 1 < c_end) fetch(c + 1);
-        const int lo = min(n, slot0 + CHUNK) - 1 - slot0;     // chunk offset of its last slot
-        if (tid == 0) s_zw[0] = z[0];
-        if (tid == lo / PPT) {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k)
-                if (k == lo % PPT) s_zw[1] = z[k];
-        }
-        for (int t = tid; t < WMAX + 2; t += NT) cnt[t] = 0;
-        lds_barrier();
+        const int slot_end = min(n, (run_end - segbase) * CHUNK);
         int w0, wn;
-        sort_window_z(dd, s_zw[0], s_zw[1], w0, wn);
-        GLB int *cur = glb(dd.cell_cnt[s]);
-        int j[PPT], rank[PPT];
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            j[k] = -1;
-            if (t0 + k < n && z[k] >= 0.0) {
-                double f;
-                cic(z[k], dd.invdz, dd.N, j[k], f);
-                j[k] >>= BIN_SHIFT;
-            }
-        }
-        // ranks within the block from one LDS atomic per (wave, bin); an
-        // outlier bin takes global slots directly (stored as -1 - slot)
-        auto add = [&](int key, int m) {
-            const int jl = key - w0;
-            if (jl >= 0 && jl < wn) return atomicAdd(&cnt[jl], m);
-            return -1 - gadd(&cur[bin_slot(key)], m) - (m - 1);
+        sort_window(dd, src, slot0, slot_end - 1, w0, wn);
+        for (int t = tid; t < wn; t += NT) cur[t] = 0;
+        GLB int *gc = glb(dd.cell_cnt[s]);
+        auto bin_of = [&](double z) {
+            int j;
+            double f;
+            cic(z, dd.invdz, dd.N, j, f);
+            j >>= BIN_SHIFT;
+            return j;
         };
+        // the run's first chunk of records is in flight through the count
+        double zq[PPT];
+        float vq[PPT];
+        u32x4 cq[PPT];
+        uint32_t tq[PPT];
+        auto fetch = [&](int t0) {
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int jl = j[k] - w0;
-            const bool inw = j[k] >= 0 && jl >= 0 && jl < wn;
-            const int r = wave_group_rank(j[k], add);
-            // global slot g + i is encoded as -1 - (g + i): the rank of an outlier
-            // counts down from -1 - g - (m - 1)
-            rank[k] = (j[k] < 0) ? 0 : (inw ? r : r);
-        }
-        lds_barrier();
-        // staging starts of the window bins: exclusive scan of the block's
-        // counts by the first wave
-        if (tid < 64) {
-            int run = 0;
-            for (int b0 = 0; b0 < wn; b0 += 64) {
-                const int t = b0 + tid;
-                const int v = t < wn ? cnt[t] : 0;
-                int inc = v;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int u = __shfl_up(inc, o, 64);
-                    if (tid >= o) inc += u;
+            for (int k = 0; k < PPT; ++k) {
+                zq[k] = -1.0;
+                if (t0 + k < slot_end) {
+                    zq[k] = src.z[t0 + k];
+                    vq[k] = src.vz[t0 + k];
+                    cq[k] = *(const GLB u32x4 *)&src.cold[t0 + k];
+                    tq[k] = src.tc[t0 + k];
                 }
-                if (t < wn) loc[t] = run + inc - v;
-                run += __shfl(inc, 63, 64);
             }
-            if (tid == 0) s_nin = run;
-        }
+        };
+        fetch(slot0 + tid * PPT);
         lds_barrier();
-        for (int t = tid; t < wn; t += NT) {
-            const int v = cnt[t];
-            if (v) cnt[t] = gadd(&cur[bin_slot(w0 + t)], v);
-        }
-        lds_barrier();
+        // pass 1: the run's counts per window bin (positions one chunk ahead)
+        {
+            double zn[PPT];
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            if (j[k] < 0) continue;
-            const float vz = vzr[k];
-            const u32x4 cr = cold[k];
-            const uint32_t tc = tcr[k];
-            if (rank[k] >= 0) {
-                const int jl = j[k] - w0;
-                const int L = loc[jl] + rank[k];
-                st_z[L] = z[k];
-                st_vz[L] = vz;
-                st_cold[L] = cr;
-                st_tc[L] = tc;
-                st_dest[L] = cnt[jl] + rank[k];
-            } else {
-                // an outlier bin's slot came from its global counter directly
-                const int dest = -1 - rank[k];
-                dst.z[dest] = z[k];
-                dst.vz[dest] = vz;
-                *(GLB u32x4 *)&dst.cold[dest] = cr;
-                dst.tc[dest] = tc;
+            for (int k = 0; k < PPT; ++k) {
+                const int t = slot0 + tid * PPT + k;
+                zn[k] = t < slot_end ? src.z[t] : -1.0;
+            }
+            for (int t0 = slot0 + tid * PPT; t0 < slot_end; t0 += CHUNK) {
+                double zc[PPT];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    zc[k] = zn[k];
+                    const int t = t0 + CHUNK + k;
+                    zn[k] = t < slot_end ? src.z[t] : -1.0;
+                }
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    if (zc[k] < 0.0) continue;
+                    const int jl = bin_of(zc[k]) - w0;
+                    if (jl >= 0 && jl < wn) atomicAdd(&cur[jl], 1);
+                }
             }
         }
         lds_barrier();
-        const int nin = s_nin;
-        for (int L = tid; L < nin; L += NT) {
-            const int dest = st_dest[L];
-            dst.z[dest] = st_z[L];
-            dst.vz[dest] = st_vz[L];
-            *(GLB u32x4 *)&dst.cold[dest] = st_cold[L];
-            dst.tc[dest] = st_tc[L];
+        // one contiguous range per bin of the window
+        for (int t = tid; t < wn; t += NT) {
+            const int v = cur[t];
+            if (v) cur[t] = gadd(&gc[bin_slot(w0 + t)], v);
         }
         lds_barrier();
+        // pass 2: every particle to the next slot of its bin's range
+        for (int t0 = slot0 + tid * PPT; t0 < slot_end; t0 += CHUNK) {
+            double z[PPT];
+            float vzr[PPT];
+            u32x4 cold[PPT];
+            uint32_t tcr[PPT];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                z[k] = zq[k];
+                vzr[k] = vq[k];
+                cold[k] = cq[k];
+                tcr[k] = tq[k];
+            }
+            if (t0 + CHUNK < slot_end) fetch(t0 + CHUNK);
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                if (z[k] < 0.0) continue;
+                const int j = bin_of(z[k]), jl = j - w0;
+                const int dest = (jl >= 0 && jl < wn) ? atomicAdd(&cur[jl], 1) : gadd(&gc[bin_slot(j)], 1);
+                dst.z[dest] = z[k];
+                dst.vz[dest] = vzr[k];
+                *(GLB u32x4 *)&dst.cold[dest] = cold[k];
+                dst.tc[dest] = tcr[k];
+            }
+        }
+        lds_barrier();
+        c = run_end;
     }
 }
 
