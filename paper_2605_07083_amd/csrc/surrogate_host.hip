@@ -1,7 +1,8 @@
 // surrogate_host.hip -- host side of the surrogate C ABI (include/surrogate.h):
 // workspace layout, weight packing, and the launch sequence of the forward
-// pass, the training step (loss, input and weight gradients, Adam,
-// re-quantisation) and the conversion to warm-start densities.
+// pass, the training step (loss, one backward kernel per layer for the input
+// and weight gradients, Adam with re-quantisation) and the conversion to
+// warm-start densities.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -16,16 +17,12 @@
 #include "../../include/surrogate.h"
 
 extern "C" {
-hipError_t surx_features(const float *params, __bf16 *feat, __bf16 *featT, double *loss0, int X, int B,
-                         hipStream_t s);
+hipError_t surx_features(const float *params, __bf16 *feat, double *loss0, int X, int B, hipStream_t s);
 hipError_t surx_conv_fwd(int layer, const __bf16 *in, const __bf16 *Wf, const float *bias, float *yf, __bf16 *yb,
-                         __bf16 *ybT, int X, int B, hipStream_t s);
-hipError_t surx_loss(const float *out, const float *target, __bf16 *dz, __bf16 *dzT, double *loss, int X, int B,
-                     hipStream_t s);
-hipError_t surx_conv_dgrad(int layer, const __bf16 *dz, const __bf16 *Wb, const float *yprev, __bf16 *dzprev,
-                           __bf16 *dzprevT, int X, int B, hipStream_t s);
-hipError_t surx_conv_wgrad_part(int layer, const __bf16 *dzT, const __bf16 *inT, float *part, float *pbias, int X,
-                                int B, hipStream_t s);
+                         int X, int B, hipStream_t s);
+hipError_t surx_loss(const float *out, const float *target, __bf16 *dz, double *loss, int X, int B, hipStream_t s);
+hipError_t surx_conv_bwd(int layer, const __bf16 *dz, const float *yin, const __bf16 *feat, const __bf16 *Wb,
+                         __bf16 *dzprev, float *part, float *pbias, int X, int B, hipStream_t s);
 int surx_wgrad_parts(int X, int B);
 int surx_loss_slots(void);
 hipError_t surx_reduce_adam(const float *part, const float *pbias, int P, float *wm, float *mw, float *vw, float *dw,
@@ -98,12 +95,9 @@ struct sur_net {
     size_t param_bytes = 0;       // weights, moments, grads: the first bytes of ws
     Layer L[SUR_LAYERS];
     __bf16 *feat = nullptr;       // [bmax][X][16]
-    __bf16 *featT = nullptr;      // [bmax][16][X] (channels first, for weight gradients)
     float *yf[SUR_LAYERS];        // [bmax][X][coutp]
     __bf16 *yb[SUR_LAYERS - 1];   // bf16 copies of the hidden outputs
-    __bf16 *ybT[SUR_LAYERS - 1];  // channels-first copies [bmax][64][X]
-    __bf16 *dz[2];                // [bmax][X][64]
-    __bf16 *dzT[2];               // [bmax][64][X]
+    __bf16 *dz[2];                // output gradients of a layer [bmax][X][64], ping-pong
     float *part = nullptr;        // a layer's partial weight gradients [parts][64][320]
     float *pbias = nullptr;       // and bias gradients [parts][64]
     double *loss = nullptr;       // surx_loss_slots() partial sums of the training loss
@@ -137,16 +131,9 @@ void layout(sur_net &n, Bump &bp)
     n.loss = bp.take<double>((size_t)surx_loss_slots());
     n.param_bytes = bp.off;
     n.feat = bp.take<__bf16>(P * SUR_IN);
-    n.featT = bp.take<__bf16>(P * SUR_IN);
     for (int l = 0; l < SUR_LAYERS; ++l) n.yf[l] = bp.take<float>(P * COUTP[l]);
-    for (int l = 0; l < SUR_LAYERS - 1; ++l) {
-        n.yb[l] = bp.take<__bf16>(P * COUTP[l]);
-        n.ybT[l] = bp.take<__bf16>(P * COUTP[l]);
-    }
-    for (int k = 0; k < 2; ++k) {
-        n.dz[k] = bp.take<__bf16>(P * SUR_HIDDEN);
-        n.dzT[k] = bp.take<__bf16>(P * SUR_HIDDEN);
-    }
+    for (int l = 0; l < SUR_LAYERS - 1; ++l) n.yb[l] = bp.take<__bf16>(P * COUTP[l]);
+    for (int k = 0; k < 2; ++k) n.dz[k] = bp.take<__bf16>(P * SUR_HIDDEN);
     const size_t parts = (size_t)surx_wgrad_parts(n.X, n.bmax);
     n.part = bp.take<float>(parts * SUR_HIDDEN * pad32(SUR_KS * SUR_HIDDEN));
     n.pbias = bp.take<float>(parts * SUR_HIDDEN);
@@ -168,16 +155,14 @@ int requant_all(sur_net *n)
     return PIC_OK;
 }
 
-// train: also write the channels-first copies the weight gradients read
+// train: also clear the loss accumulators
 int forward(sur_net *n, const float *params, int B, bool train)
 {
-    SUR_TRY(surx_features(params, n->feat, train ? n->featT : nullptr, train ? n->loss : nullptr, n->X, B,
-                          n->stream));
+    SUR_TRY(surx_features(params, n->feat, train ? n->loss : nullptr, n->X, B, n->stream));
     for (int l = 0; l < SUR_LAYERS; ++l) {
         const __bf16 *in = l == 0 ? n->feat : n->yb[l - 1];
         __bf16 *yb = l < SUR_LAYERS - 1 ? n->yb[l] : nullptr;
-        __bf16 *ybT = train && l < SUR_LAYERS - 1 ? n->ybT[l] : nullptr;
-        SUR_TRY(surx_conv_fwd(l, in, n->L[l].wf, n->L[l].bias, n->yf[l], yb, ybT, n->X, B, n->stream));
+        SUR_TRY(surx_conv_fwd(l, in, n->L[l].wf, n->L[l].bias, n->yf[l], yb, n->X, B, n->stream));
     }
     return PIC_OK;
 }
@@ -373,12 +358,12 @@ int sur_forward_noalloc(sur_net *n, const float *dev_params, int batch, float *d
                      reinterpret_cast<__bf16 *>(base + P * (16 * 2 + 64 * 4 + 48 * 4 + 64 * 2))};
     for (int b0 = 0; b0 < batch; b0 += chunk) {
         const int nb = std::min(chunk, batch - b0);
-        SUR_TRY(surx_features(dev_params + (size_t)4 * b0, feat, nullptr, nullptr, n->X, nb, n->stream));
+        SUR_TRY(surx_features(dev_params + (size_t)4 * b0, feat, nullptr, n->X, nb, n->stream));
         for (int l = 0; l < SUR_LAYERS; ++l) {
             const __bf16 *in = l == 0 ? feat : yb[(l - 1) & 1];
             const bool last = l == SUR_LAYERS - 1;
-            SUR_TRY(surx_conv_fwd(l, in, n->L[l].wf, n->L[l].bias, last ? yout : yf, last ? nullptr : yb[l & 1],
-                                  nullptr, n->X, nb, n->stream));
+            SUR_TRY(surx_conv_fwd(l, in, n->L[l].wf, n->L[l].bias, last ? yout : yf, last ? nullptr : yb[l & 1], n->X,
+                                  nb, n->stream));
         }
         SUR_TRY(surx_unpack(yout, dev_out + (size_t)b0 * SUR_OUT * n->X, n->X, nb, n->stream));
     }
@@ -394,24 +379,25 @@ int sur_train_step(sur_net *n, const float *dev_params, const float *dev_target,
     // the forward pass zeroes the loss accumulators (features kernel)
     int rc = forward(n, dev_params, batch, true);
     if (rc) return rc;
-    SUR_TRY(surx_loss(n->yf[SUR_LAYERS - 1], dev_target, n->dz[0], n->dzT[0], n->loss, X, batch, n->stream));
+    SUR_TRY(surx_loss(n->yf[SUR_LAYERS - 1], dev_target, n->dz[0], n->loss, X, batch, n->stream));
     n->t += 1;
     const float c1 = (float)(1.0 - std::pow((double)B1, (double)n->t));
     const float c2 = (float)(1.0 - std::pow((double)B2, (double)n->t));
     const int parts = surx_wgrad_parts(X, batch);
-    // per layer, last to first: partial weight gradients, the input gradient
-    // (which still needs this layer's weights), then the layer's gradient
-    // summed from the partials, its Adam update and BF16 copies
+    // per layer, last to first: the input gradient (with this layer's weights
+    // before their update) and the partial weight gradients in one kernel,
+    // then the layer's gradient summed from the partials, its Adam update and
+    // BF16 copies
     int cur = 0;
     for (int l = SUR_LAYERS - 1; l >= 0; --l) {
         const Layer &L = n->L[l];
-        const __bf16 *inT = l == 0 ? n->featT : n->ybT[l - 1];
-        SUR_TRY(surx_conv_wgrad_part(l, n->dzT[cur], inT, n->part, n->pbias, X, batch, n->stream));
-        if (l > 0) {
-            SUR_TRY(surx_conv_dgrad(l, n->dz[cur], L.wb, n->yf[l - 1], n->dz[cur ^ 1], n->dzT[cur ^ 1], X, batch,
-                                    n->stream));
-            cur ^= 1;
-        }
+        if (l > 0)
+            SUR_TRY(surx_conv_bwd(l, n->dz[cur], n->yf[l - 1], nullptr, L.wb, n->dz[cur ^ 1], n->part, n->pbias, X,
+                                  batch, n->stream));
+        else
+            SUR_TRY(surx_conv_bwd(0, n->dz[cur], nullptr, n->feat, nullptr, nullptr, n->part, n->pbias, X, batch,
+                                  n->stream));
+        cur ^= 1;
         SUR_TRY(surx_reduce_adam(n->part, n->pbias, parts, L.wm, L.mw, L.vw, L.dw, L.bias, L.mb, L.vb, L.db, L.wf,
                                  L.wb, L.cin, L.coutp, L.cout, L.kp, L.kpb, lr, B1, B2, EPS, c1, c2, n->stream));
     }

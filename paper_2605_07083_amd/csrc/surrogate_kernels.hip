@@ -9,11 +9,12 @@
 // enter every layer as BF16, all products accumulate in FP32 on
 // v_mfma_f32_16x16x32_bf16.
 //
-// Layouts: activations channels last act[b][x][c] for the forward and input
-// gradient GEMMs (K runs over channels), plus channels-first copies
-// actT[b][c][x] for the weight gradient (K runs over positions); forward weights
-// Wf[co][t*Cin + ci] (K contiguous), transposed weights for the input gradient
-// Wb[ci][t*Cout + co]; both padded with zeros to a multiple of 32 in K.
+// Layouts: activations and gradients channels last, act[b][x][c]: the forward
+// and input-gradient GEMMs read them along K (channels) with 16-byte reads, the
+// weight gradient (K = positions) reads the same tiles transposed with
+// ds_read_b64_tr_b16; forward weights Wf[co][t*Cin + ci] (K contiguous),
+// transposed weights for the input gradient Wb[ci][t*Cout + co]; both padded
+// with zeros to a multiple of 32 in K.
 //
 // MFMA 16x16x32 (bf16) lane layout: lane l supplies A[l%16][8(l/16)+i] and
 // B[8(l/16)+i][l%16], i = 0..7, and receives D[4(l/16)+i][l%16], i = 0..3.
@@ -59,8 +60,8 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
 // mapped to [-1, 1] over the training ranges (log scale for the flux and the
 // density); the position features resolve both sheaths and the interior.
 // ---------------------------------------------------------------------------
-__global__ void k_features(const float *__restrict__ params, __bf16 *__restrict__ feat, __bf16 *__restrict__ featT,
-                           double *__restrict__ loss0, int X, int B)
+__global__ void k_features(const float *__restrict__ params, __bf16 *__restrict__ feat, double *__restrict__ loss0,
+                           int X, int B)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < LOSS_SLOTS && loss0) loss0[idx] = 0.0;     // the training step's loss accumulators
@@ -87,22 +88,6 @@ __global__ void k_features(const float *__restrict__ params, __bf16 *__restrict_
     __bf16 *o = feat + (size_t)idx * 16;
 #pragma unroll
     for (int c = 0; c < 16; ++c) o[c] = (__bf16)f[c];
-    if (featT) {
-#pragma unroll
-        for (int c = 0; c < 16; ++c) featT[((size_t)b * 16 + c) * X + x] = (__bf16)f[c];
-    }
-}
-
-// Four consecutive positions of one channel, stored as one 8-byte word.
-__device__ __forceinline__ void store4T(__bf16 *p, float v0, float v1, float v2, float v3)
-{
-    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-    bf16x4 q;
-    q[0] = (__bf16)v0;
-    q[1] = (__bf16)v1;
-    q[2] = (__bf16)v2;
-    q[3] = (__bf16)v3;
-    *reinterpret_cast<bf16x4 *>(p) = q;
 }
 
 // ---------------------------------------------------------------------------
@@ -133,14 +118,14 @@ __device__ __forceinline__ void stage_rows(__bf16 *lds, const __bf16 *__restrict
 
 // ---------------------------------------------------------------------------
 // Forward conv: out[b][x][co] = act(bias[co] + sum_{t, ci} W[co][t][ci] in[b][x+t-2][ci]).
-// GEMM M = positions, N = COUT, K = 5*CIN (padded to KP).  A block of 16
+// GEMM M = positions, N = COUT, K = 5*CIN (padded to KP).  A block of 8
 // waves covers BLOCK_POS positions of one sample with the layer's weights in
-// LDS; a wave computes 16 positions x COUT.
+// LDS; a wave computes 16 positions x COUT at a time.
 // ---------------------------------------------------------------------------
 template <int CIN, int COUT, bool TANH>
 __global__ __launch_bounds__(CONV_THREADS) void k_conv_fwd(const __bf16 *__restrict__ in, const __bf16 *__restrict__ Wf,
                                                   const float *__restrict__ bias, float *__restrict__ yf,
-                                                  __bf16 *__restrict__ yb, __bf16 *__restrict__ ybT, int X, int B)
+                                                  __bf16 *__restrict__ yb, int X, int B)
 {
     constexpr int K = KS * CIN;
     constexpr int KP = (K + 31) / 32 * 32;
@@ -187,7 +172,6 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv_fwd(const __bf16 *__restr
             yf[o] = v[i];
             if (yb) yb[o] = (__bf16)v[i];
         }
-        if (ybT) store4T(ybT + ((size_t)b * COUT + co) * X + x0 + kb * 4, v[0], v[1], v[2], v[3]);
     }
     }
 }
@@ -195,17 +179,16 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv_fwd(const __bf16 *__restr
 // ---------------------------------------------------------------------------
 // Loss: mean over (b, channel < OUT, x) of (out - target)^2.  Writes
 // dZ = 2 (out - target) / count as BF16 in the padded OUTP-channel layout,
-// channels last and channels first.  target[b][c][x], out[b][x][OUTP].  A
-// block takes 64 positions of one sample: the output tile is read whole into
-// LDS, the target and dZ^T rows are read and written along x, dZ along c.
+// channels last.  target[b][c][x], out[b][x][OUTP].  A block takes 64
+// positions of one sample: the output tile is read whole into LDS, the target
+// rows along x, and dZ is written along c.
 // Each block adds its sum to one of LOSS_SLOTS accumulators (block % slots),
 // so that a thousand blocks do not queue on one address; the host adds them.
 // ---------------------------------------------------------------------------
 constexpr int LOSS_POS = 64;
 
 __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ out, const float *__restrict__ target,
-                                              __bf16 *__restrict__ dz, __bf16 *__restrict__ dzT,
-                                              double *__restrict__ loss, int X, int B)
+                                              __bf16 *__restrict__ dz, double *__restrict__ loss, int X, int B)
 {
     __shared__ float so[LOSS_POS][OUTP + 1];
     __shared__ double red[4];
@@ -244,7 +227,6 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ out, con
             g = (float)(2.0 * inv) * d;
         }
         so[x][c] = g;
-        dzT[((size_t)b * OUTP + c) * X + x0 + x] = (__bf16)g;
     }
     __syncthreads();
     __bf16 *db = dz + ((size_t)b * X + x0) * OUTP;
@@ -263,73 +245,6 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ out, con
     }
 }
 
-// ---------------------------------------------------------------------------
-// Input gradient: dY[b][x][ci] = sum_{t, co} W[co][t][ci] dZ[b][x-t+2][co],
-// then (tanh) dZprev = dY (1 - y^2) stored as BF16.  GEMM M = positions,
-// N = CIN, K = 5*COUT (padded), B from the transposed weights Wb[ci][t*COUT+co].
-// ---------------------------------------------------------------------------
-template <int CIN, int COUT>
-__global__ __launch_bounds__(CONV_THREADS) void k_conv_dgrad(const __bf16 *__restrict__ dz, const __bf16 *__restrict__ Wb,
-                                                    const float *__restrict__ yprev, __bf16 *__restrict__ dzprev,
-                                                    __bf16 *__restrict__ dzprevT, int X, int B)
-{
-    constexpr int K = KS * COUT;
-    constexpr int KP = (K + 31) / 32 * 32;
-    constexpr int NT = CIN / 16;
-    __shared__ __bf16 wl[CIN * (KP + 8)];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int tiles = (X + BLOCK_POS - 1) / BLOCK_POS;
-    const int b = blockIdx.x / tiles;
-    if (b >= B) return;
-    stage_rows<CIN, KP, CONV_THREADS>(wl, Wb);
-    __syncthreads();
-    const int m = lane & 15, kb = lane >> 4;
-    const __bf16 *dzb = dz + (size_t)b * X * COUT;
-    const int xb = (blockIdx.x - b * tiles) * BLOCK_POS;
-    for (int x0 = xb + w * 16; x0 < min(X, xb + BLOCK_POS); x0 += CONV_THREADS / 4) {
-    f32x4 acc[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < KP / 32; ++ks) {
-        const int kappa = ks * 32 + kb * 8;
-        bf16x8 a = zero8();
-        if (kappa < K) {
-            const int t = kappa / COUT, co = kappa - t * COUT;
-            const int xs = x0 + m - t + PAD;
-            if (xs >= 0 && xs < X) a = load8(dzb + (size_t)xs * COUT + co);
-        }
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(wl + (nt * 16 + m) * (KP + 8) + kappa);
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[nt], 0, 0, 0);
-        }
-    }
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int ci = nt * 16 + m;
-        float v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int x = x0 + kb * 4 + i;
-            const size_t o = ((size_t)b * X + x) * CIN + ci;
-            const float y = yprev[o];
-            v[i] = acc[nt][i] * (1.0f - y * y);
-            dzprev[o] = (__bf16)v[i];
-        }
-        store4T(dzprevT + ((size_t)b * CIN + ci) * X + x0 + kb * 4, v[0], v[1], v[2], v[3]);
-    }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Weight and bias gradients: dW[co][t*CIN+ci] = sum_{b,x} dZ[b][co][x] in[b][ci][x+t-2],
-// db[co] = sum_{b,x} dZ[b][co][x], from the channels-first copies.  GEMM M =
-// COUT, N = 5*CIN (16-wide tiles, one tap t per tile), K = positions, 32 per
-// MFMA.  Lane (m, kb) reads 8 consecutive positions as one 16-byte load for
-// A; for B the same 8 positions shifted by t - 2, taken from a 12-element
-// window (16 bytes plus one dword on each side, zero outside the sample).
-// ---------------------------------------------------------------------------
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <int T>
@@ -348,125 +263,158 @@ __device__ __forceinline__ bf16x8 window8(uint32_t w0, uint32_t w1, uint32_t w2,
     return __builtin_bit_cast(bf16x8, r);
 }
 
-// ---------------------------------------------------------------------------
-// Weight and bias gradients as partial sums over slices of WG_SLICE positions
-// of one sample: block p = (sample, slice) writes part[p][co][kappa] and
-// pbias[p][co]; k_reduce_adam sums the partials in a fixed order.
-//
-// The slice goes through LDS in sub-slices of WG_SUB positions: dZ rows and
-// input rows (with a halo of 8 positions each side, zero outside the sample).
-// The global loads of the next sub-slice are in flight while the waves work
-// on the current one.  Wave w takes MW output-channel tiles x CW input-channel
-// tiles (all five taps: MW * CW * 5 accumulators) over a contiguous run of
-// 32-position groups of the sub-slice; the H waves of a tile pair split the
-// groups and add their sums through LDS in a fixed order at the end.
-//
-// Per group and input tile a lane needs the 12-element window of its 8
-// positions (two before, two after): the 16-byte chunk from LDS, the dword
-// before it and the dword after it from the neighbouring lanes (ds_bpermute;
-// lanes 16 apart hold adjacent chunks), the outer lanes' from the previous
-// and the next group, which the wave reads one group ahead.  Rows are padded
-// so that the 16-byte reads of 8 consecutive rows fall on different banks.
-// The bias gradient is one more MFMA per output tile and group, against a
-// column of ones.  The block's partial is assembled in LDS and written out in
-// 16-byte stores by every thread.
-// ---------------------------------------------------------------------------
-constexpr int WG_SLICE = 512;
-constexpr int WG_SUB = 128;
-constexpr int WG_THREADS = 512;
-constexpr int WG_HALO = 8;
-constexpr int WG_AROW = WG_SUB + 8;                    // dZ row in LDS
-constexpr int WG_BROW = WG_SUB + 2 * WG_HALO + 8;      // input row: positions -8 .. WG_SUB + 8 of the sub-slice
-
 __device__ __forceinline__ void store8(__bf16 *p, bf16x8 v) { *reinterpret_cast<bf16x8 *>(p) = v; }
 
-template <int CIN, int COUT>
-struct WgradShape {
-    static constexpr int K = KS * CIN, KP = (K + 31) / 32 * 32;
+// Transposed LDS read (ds_read_b64_tr_b16).  Within each group of 16 lanes,
+// lane s = 4e + q passes the address of 4 consecutive 16-bit elements (row
+// p_e, columns c + 4q .. c + 4q + 3 of a row-major tile); lane j of the group
+// then receives the column c + j at the rows p_0 .. p_3.
+__device__ __forceinline__ uint2 ldtr(const __bf16 *p)
+{
+    typedef short v4s __attribute__((ext_vector_type(4)));
+    const v4s r = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) v4s *)(p));
+    return __builtin_bit_cast(uint2, r);
+}
+
+// ---------------------------------------------------------------------------
+// Backward pass of one layer in one kernel, from the channels-last output
+// gradient dZ[b][x][co] (of the pre-activation) and the layer's input:
+//  * with DG (layers 2..6): the input gradient of the layer below,
+//    dZprev[b][x][ci] = (sum_{t, co} W[co][t][ci] dZ[b][x-t+2][co]) (1 - y^2)
+//    with y[b][x][ci] the FP32 input (the layer below's tanh output): GEMM
+//    M = positions, N = CIN, K = 5 COUT, the transposed weights in LDS;
+//  * the partial weight and bias gradients of the block's slice of one sample,
+//    dW[co][t*CIN+ci] = sum_x dZ[x][co] in[x+t-2][ci], db[co] = sum_x dZ[x][co]
+//    (in = y rounded to bfloat16, or the features for the first layer): GEMM
+//    M = COUT, N = CIN per tap, K = positions.
+// Block p = (sample, slice of BW_SLICE positions) writes part[p][co][kappa]
+// and pbias[p][co] (k_reduce_adam sums the partials in a fixed order).  The
+// slice goes through LDS in parts of BW_SUB positions plus two halo positions
+// on each side (zero outside the sample), dZ and the input as channels-last
+// bfloat16 tiles; the next part's global loads fly while a part is worked on.
+// The input gradient reads the tiles along channels (16-byte reads); the
+// weight gradient reads them transposed: a lane gets 4 consecutive positions
+// of one channel per read, 8 for an A fragment (dZ^T), the 12-position window
+// (two before, two after) of its 8 positions for the B fragments of the five
+// taps.  The part's own FP32 inputs stay in LDS for the tanh derivative.
+// Wave w of the weight gradient takes MW output x CW input channel
+// tiles over every H-th run of 32-position groups; the H runs of a tile pair
+// add their sums through LDS at the end; the bias is one more MFMA per output
+// tile against a column of ones.  Row strides are chosen so that the four
+// rows of a transposed read (32 bytes each) fall on different banks.
+// ---------------------------------------------------------------------------
+constexpr int BW_SLICE = 256;
+constexpr int BW_SUB = 128;
+constexpr int BW_THREADS = 512;
+constexpr int BW_ROWS = BW_SUB + 4;        // positions -2 .. BW_SUB + 1 of a part
+
+constexpr int bw_stride(int c) { return c == 64 ? 80 : c; }    // 160, 96 or 32 bytes per row
+
+template <int CIN, int COUT, bool DG>
+struct BwdShape {
+    static constexpr int K = KS * CIN, KP = (K + 31) / 32 * 32;           // weight-gradient partial layout
+    static constexpr int KD = KS * COUT, KPB = (KD + 31) / 32 * 32;       // input-gradient K
     static constexpr int MT = COUT / 16, CT = CIN / 16;
-    static constexpr int MW = MT % 2 == 0 ? 2 : MT;         // output tiles per wave
-    static constexpr int CW = (MW == 2 && CT % 2 == 0) ? 2 : 1;   // input tiles per wave
+    static constexpr int MW = MT % 2 == 0 ? 2 : MT;                       // output tiles per wave
+    static constexpr int CW = (MW == 2 && CT % 2 == 0) ? 2 : 1;           // input tiles per wave
     static constexpr int PAIRS = (MT / MW) * (CT / CW);
-    static constexpr int WAVES = WG_THREADS / 64;
-    static constexpr int H = WAVES / PAIRS;                 // waves per tile pair (position runs)
-    static constexpr int RS = (MW * CW * KS + MW) * 4;      // weight and bias accumulators per lane
-    static constexpr int AV = WG_SUB / 8, BV = WG_SUB / 8 + 2;   // 16-byte vectors per row
-    static constexpr int NA = (COUT * AV + WG_THREADS - 1) / WG_THREADS;
-    static constexpr int NB = (CIN * BV + WG_THREADS - 1) / WG_THREADS;
-    static constexpr size_t LDS_A = (size_t)COUT * WG_AROW * 2;
-    static constexpr size_t LDS_OP = LDS_A + (size_t)CIN * WG_BROW * 2;
+    static constexpr int WAVES = BW_THREADS / 64;
+    static constexpr int H = WAVES / PAIRS;
+    static constexpr int GPW = BW_SUB / 32 / H;                           // groups per wave per whole part
+    static constexpr int RS = (MW * CW * KS + MW) * 4;
+    static constexpr int SD = bw_stride(COUT), SI = bw_stride(CIN);
+    static constexpr int DV = COUT / 8;                                   // 16-byte vectors per dZ row
+    static constexpr int IV = DG ? CIN / 4 : CIN / 8;                     // float4 (y) or bf16x8 (features) per row
+    static constexpr int ND = (BW_ROWS * DV + BW_THREADS - 1) / BW_THREADS;
+    static constexpr int NI = (BW_ROWS * IV + BW_THREADS - 1) / BW_THREADS;
+    static constexpr size_t LDS_D = (size_t)BW_ROWS * SD * 2;
+    static constexpr size_t LDS_I = (size_t)BW_ROWS * SI * 2;
+    static constexpr size_t LDS_W = DG ? (size_t)CIN * (KPB + 8) * 2 : 0;
+    static constexpr int YS = CIN + 4;                                    // FP32 input rows of the part's own positions (DG)
+    static constexpr size_t LDS_Y = DG ? (size_t)BW_SUB * YS * 4 : 0;
+    static constexpr size_t LDS_OP = LDS_D + LDS_I + LDS_W + LDS_Y;
     static constexpr size_t LDS_RED = (size_t)(H - 1) * PAIRS * RS * 64 * 4;
-    static constexpr size_t LDS_OUT = (size_t)COUT * (KP + 1) * 4;    // the block's partial, staged for wide stores
+    static constexpr size_t LDS_OUT = (size_t)COUT * (KP + 1) * 4;
     static constexpr size_t LDS_1 = LDS_OP > LDS_RED ? LDS_OP : LDS_RED;
     static constexpr size_t LDS = LDS_1 > LDS_OUT ? LDS_1 : LDS_OUT;
     static_assert(MT % MW == 0 && CT % CW == 0 && WAVES % PAIRS == 0 && H >= 1, "wave tiling");
-    static_assert((WG_SUB / 32) % H == 0, "whole groups per wave");
+    static_assert((BW_SUB / 32) % H == 0 && BW_SUB / 16 == WAVES, "whole groups per wave, one input-gradient tile per wave");
+    static_assert(CIN % 16 == 0 && COUT % 16 == 0, "whole channel tiles");
 };
 
-// Global loads of one sub-slice (positions xs .. xs + sl of sample b) into registers.
-template <int CIN, int COUT>
-__device__ __forceinline__ void wg_load(const __bf16 *__restrict__ dzT, const __bf16 *__restrict__ inT, int b, int xs,
-                                        int sl, int X, bf16x8 *ra, bf16x8 *rb)
+template <int CIN, int COUT, bool DG>
+__global__ __launch_bounds__(BW_THREADS) void k_conv_bwd(const __bf16 *__restrict__ dz, const float *__restrict__ yin,
+                                                         const __bf16 *__restrict__ fin, const __bf16 *__restrict__ Wb,
+                                                         __bf16 *__restrict__ dzprev, float *__restrict__ part,
+                                                         float *__restrict__ pbias, int X)
 {
-    using S = WgradShape<CIN, COUT>;
-#pragma unroll
-    for (int k = 0; k < S::NA; ++k) {
-        const int v = threadIdx.x + k * WG_THREADS, r = v / S::AV, c = (v % S::AV) * 8;
-        ra[k] = v < COUT * S::AV && c < sl ? load8(dzT + ((size_t)b * COUT + r) * X + xs + c) : zero8();
-    }
-#pragma unroll
-    for (int k = 0; k < S::NB; ++k) {
-        const int v = threadIdx.x + k * WG_THREADS, r = v / S::BV, c = (v % S::BV) * 8;
-        const int x = xs + c - WG_HALO;
-        rb[k] = v < CIN * S::BV && c < sl + 2 * WG_HALO && x >= 0 && x < X
-                    ? load8(inT + ((size_t)b * CIN + r) * X + x) : zero8();
-    }
-}
-
-template <int CIN, int COUT>
-__device__ __forceinline__ void wg_store(__bf16 *As, __bf16 *Bs, const bf16x8 *ra, const bf16x8 *rb)
-{
-    using S = WgradShape<CIN, COUT>;
-#pragma unroll
-    for (int k = 0; k < S::NA; ++k) {
-        const int v = threadIdx.x + k * WG_THREADS;
-        if (v < COUT * S::AV) store8(As + (v / S::AV) * WG_AROW + (v % S::AV) * 8, ra[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < S::NB; ++k) {
-        const int v = threadIdx.x + k * WG_THREADS;
-        if (v < CIN * S::BV) store8(Bs + (v / S::BV) * WG_BROW + (v % S::BV) * 8, rb[k]);
-    }
-}
-
-__device__ __forceinline__ uint32_t lane_from(int src_lane, uint32_t v)
-{
-    return (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane << 2, (int)v);
-}
-
-template <int CIN, int COUT>
-__global__ __launch_bounds__(WG_THREADS) void k_conv_wgrad_part(const __bf16 *__restrict__ dzT,
-                                                                const __bf16 *__restrict__ inT,
-                                                                float *__restrict__ part, float *__restrict__ pbias,
-                                                                int X)
-{
-    using S = WgradShape<CIN, COUT>;
-    constexpr int KP = S::KP, MW = S::MW, CW = S::CW, PAIRS = S::PAIRS, H = S::H, RS = S::RS;
-    constexpr int GPW = WG_SUB / 32 / H;                  // groups per wave per whole sub-slice
+    using S = BwdShape<CIN, COUT, DG>;
+    constexpr int KP = S::KP, KPB = S::KPB, KD = S::KD, MW = S::MW, CW = S::CW, PAIRS = S::PAIRS, H = S::H;
+    constexpr int RS = S::RS, SD = S::SD, SI = S::SI, GPW = S::GPW;
     __shared__ __align__(16) char lds[S::LDS];
-    __bf16 *As = reinterpret_cast<__bf16 *>(lds);
-    __bf16 *Bs = reinterpret_cast<__bf16 *>(lds + S::LDS_A);
-    const int slices = (X + WG_SLICE - 1) / WG_SLICE;
+    __bf16 *Dt = reinterpret_cast<__bf16 *>(lds);                          // dZ rows of a part
+    __bf16 *It = reinterpret_cast<__bf16 *>(lds + S::LDS_D);               // input rows of a part
+    __bf16 *Wl = reinterpret_cast<__bf16 *>(lds + S::LDS_D + S::LDS_I);    // transposed weights (DG)
+    float *Yt = reinterpret_cast<float *>(lds + S::LDS_D + S::LDS_I + S::LDS_W);   // FP32 input, own positions (DG)
+    const int slices = (X + BW_SLICE - 1) / BW_SLICE;
     const int p = blockIdx.x, b = p / slices;
-    const int xb = (p - b * slices) * WG_SLICE;
-    const int len = min(X, xb + WG_SLICE) - xb;           // a multiple of 64
-
-    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const bool active = w < PAIRS * H;
-    const int pair = w % PAIRS, h = w / PAIRS;
-    const int mw = pair % (S::MT / MW), cw = pair / (S::MT / MW);
+    const int xb = (p - b * slices) * BW_SLICE;
+    const int len = min(X, xb + BW_SLICE) - xb;          // a multiple of 64
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int m = lane & 15, kb = lane >> 4;
-    const int from_lo = (lane - 16) & 63, from_hi = (lane + 16) & 63;
+    const int e = m >> 2, q = m & 3;                     // this lane's row and column group in a transposed read
+
+    // one part's global loads into registers: dZ and input rows of positions xs - 2 .. xs + BW_SUB + 1
+    bf16x8 rd[S::ND];
+    float4 ry[DG ? S::NI : 1];
+    bf16x8 rf[DG ? 1 : S::NI];
+    auto load_part = [&](int xs) {
+#pragma unroll
+        for (int k = 0; k < S::ND; ++k) {
+            const int v = tid + k * BW_THREADS, r = v / S::DV, c = (v % S::DV) * 8, x = xs - 2 + r;
+            rd[k] = v < BW_ROWS * S::DV && x >= 0 && x < X ? load8(dz + ((size_t)b * X + x) * COUT + c) : zero8();
+        }
+#pragma unroll
+        for (int k = 0; k < S::NI; ++k) {
+            const int v = tid + k * BW_THREADS, r = v / S::IV, x = xs - 2 + r;
+            const bool ok = v < BW_ROWS * S::IV && x >= 0 && x < X;
+            if constexpr (DG) {
+                const int c = (v % S::IV) * 4;
+                ry[k] = ok ? *reinterpret_cast<const float4 *>(yin + ((size_t)b * X + x) * CIN + c)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+            } else {
+                const int c = (v % S::IV) * 8;
+                rf[k] = ok ? load8(fin + ((size_t)b * X + x) * CIN + c) : zero8();
+            }
+        }
+    };
+    auto store_part = [&]() {
+#pragma unroll
+        for (int k = 0; k < S::ND; ++k) {
+            const int v = tid + k * BW_THREADS;
+            if (v < BW_ROWS * S::DV) store8(Dt + (v / S::DV) * SD + (v % S::DV) * 8, rd[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < S::NI; ++k) {
+            const int v = tid + k * BW_THREADS;
+            if (v >= BW_ROWS * S::IV) continue;
+            if constexpr (DG) {
+                typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+                bf16x4 h;
+                h[0] = (__bf16)ry[k].x;
+                h[1] = (__bf16)ry[k].y;
+                h[2] = (__bf16)ry[k].z;
+                h[3] = (__bf16)ry[k].w;
+                const int r = v / S::IV, c = (v % S::IV) * 4;
+                *reinterpret_cast<bf16x4 *>(It + r * SI + c) = h;
+                // the FP32 values of the part's own positions for the tanh derivative
+                if (r >= 2 && r < 2 + BW_SUB) *reinterpret_cast<float4 *>(Yt + (r - 2) * S::YS + c) = ry[k];
+            } else {
+                store8(It + (v / S::IV) * SI + (v % S::IV) * 8, rf[k]);
+            }
+        }
+    };
 
     f32x4 acc[MW][CW][KS], bacc[MW];
 #pragma unroll
@@ -480,50 +428,77 @@ __global__ __launch_bounds__(WG_THREADS) void k_conv_wgrad_part(const __bf16 *__
     bf16x8 ones;
 #pragma unroll
     for (int i = 0; i < 8; ++i) ones[i] = (__bf16)1.0f;
+    const bool active = w < PAIRS * H;
+    const int pair = w % PAIRS, h = w / PAIRS;
+    const int mw = pair % (S::MT / MW), cw = pair / (S::MT / MW);
 
-    bf16x8 ra[S::NA], rb[S::NB];
-    wg_load<CIN, COUT>(dzT, inT, b, xb, min(WG_SUB, len), X, ra, rb);
-    for (int xs = 0; xs < len; xs += WG_SUB) {
-        const int sl = min(WG_SUB, len - xs);
-        wg_store<CIN, COUT>(As, Bs, ra, rb);
+    load_part(xb);
+    if constexpr (DG) stage_rows<CIN, KPB, BW_THREADS>(Wl, Wb);
+    for (int xo = 0; xo < len; xo += BW_SUB) {
+        const int xs = xb + xo, sl = min(BW_SUB, len - xo);
+        store_part();
         __syncthreads();
-        if (xs + WG_SUB < len)     // the next sub-slice's loads fly while this one is worked on
-            wg_load<CIN, COUT>(dzT, inT, b, xb + xs + WG_SUB, min(WG_SUB, len - xs - WG_SUB), X, ra, rb);
+        if (xo + BW_SUB < len) load_part(xs + BW_SUB);
+
+        if constexpr (DG) {
+            // input gradient of the 16 positions x0 .. x0 + 15 of the part (one tile per wave)
+            const int x0 = w * 16;
+            if (x0 < sl) {
+                constexpr int NT = CIN / 16;
+                f32x4 dacc[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) dacc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < KPB / 32; ++ks) {
+                    const int kappa = ks * 32 + kb * 8;
+                    bf16x8 a = zero8();
+                    if (kappa < KD) {
+                        const int t = kappa / COUT, co = kappa - t * COUT;
+                        // dZ at position x0 + m - t + 2: row x0 + m - t + 4 of the part
+                        a = *reinterpret_cast<const bf16x8 *>(Dt + (x0 + m - t + 4) * SD + co);
+                    }
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(Wl + (nt * 16 + m) * (KPB + 8) + kappa);
+                        dacc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, dacc[nt], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int ci = nt * 16 + m;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int xl = x0 + kb * 4 + i;
+                        const float y = Yt[xl * S::YS + ci];
+                        dzprev[((size_t)b * X + xs + xl) * CIN + ci] = (__bf16)(dacc[nt][i] * (1.0f - y * y));
+                    }
+                }
+            }
+        }
+
+        // weight and bias gradients over this wave's groups of the part
         const int g0 = h * GPW, g1 = min(g0 + GPW, sl / 32);
         if (active && g0 < g1) {
-            // B chunk of a group for input tile v; columns clamped into the row
-            // (the clamped reads feed no result)
-            auto bchunk = [&](int v, int g) {
-                const int col = min(max(g * 32 + kb * 8 + WG_HALO, 0), WG_BROW - 8);
-                return *reinterpret_cast<const u32x4 *>(Bs + ((cw * CW + v) * 16 + m) * WG_BROW + col);
-            };
-            u32x4 cur[CW];
-            uint32_t prev3[CW];
-#pragma unroll
-            for (int v = 0; v < CW; ++v) {
-                cur[v] = bchunk(v, g0);
-                prev3[v] = bchunk(v, g0 - 1)[3];      // the lanes kb = 3 hold the group before's last chunk
-            }
             for (int g = g0; g < g1; ++g) {
+                const int r0 = g * 32 + kb * 8 + e;       // the part row of this lane's address (+2: halo)
                 bf16x8 a[MW];
 #pragma unroll
                 for (int u = 0; u < MW; ++u) {
-                    a[u] = *reinterpret_cast<const bf16x8 *>(As + ((mw * MW + u) * 16 + m) * WG_AROW + g * 32 + kb * 8);
+                    const __bf16 *pa = Dt + (r0 + 2) * SD + (mw * MW + u) * 16 + 4 * q;
+                    const uint2 a0 = ldtr(pa), a1 = ldtr(pa + 4 * SD);
+                    a[u] = __builtin_bit_cast(bf16x8, (u32x4){a0.x, a0.y, a1.x, a1.y});
                     bacc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], ones, bacc[u], 0, 0, 0);
                 }
 #pragma unroll
                 for (int v = 0; v < CW; ++v) {
-                    const u32x4 nxt = bchunk(v, g + 1);
-                    // dword before the chunk: lane kb - 1's last one (kb = 0: the
-                    // group before, held by lane kb = 3); dword after: lane kb + 1's
-                    // first one (kb = 3: the next group, read by lane kb = 0)
-                    const uint32_t lo = lane_from(from_lo, kb == 3 ? prev3[v] : cur[v][3]);
-                    const uint32_t hi = lane_from(from_hi, kb == 0 ? nxt[0] : cur[v][0]);
-                    const bf16x8 w0 = window8<0>(lo, cur[v][0], cur[v][1], cur[v][2], cur[v][3], hi);
-                    const bf16x8 w1 = window8<1>(lo, cur[v][0], cur[v][1], cur[v][2], cur[v][3], hi);
-                    const bf16x8 w2 = window8<2>(lo, cur[v][0], cur[v][1], cur[v][2], cur[v][3], hi);
-                    const bf16x8 w3 = window8<3>(lo, cur[v][0], cur[v][1], cur[v][2], cur[v][3], hi);
-                    const bf16x8 w4 = window8<4>(lo, cur[v][0], cur[v][1], cur[v][2], cur[v][3], hi);
+                    // the window of positions 8kb - 2 .. 8kb + 9 of the group
+                    const __bf16 *pb = It + r0 * SI + (cw * CW + v) * 16 + 4 * q;
+                    const uint2 b0 = ldtr(pb), b1 = ldtr(pb + 4 * SI), b2 = ldtr(pb + 8 * SI);
+                    const bf16x8 w0 = window8<0>(b0.x, b0.y, b1.x, b1.y, b2.x, b2.y);
+                    const bf16x8 w1 = window8<1>(b0.x, b0.y, b1.x, b1.y, b2.x, b2.y);
+                    const bf16x8 w2 = window8<2>(b0.x, b0.y, b1.x, b1.y, b2.x, b2.y);
+                    const bf16x8 w3 = window8<3>(b0.x, b0.y, b1.x, b1.y, b2.x, b2.y);
+                    const bf16x8 w4 = window8<4>(b0.x, b0.y, b1.x, b1.y, b2.x, b2.y);
 #pragma unroll
                     for (int u = 0; u < MW; ++u) {
                         acc[u][v][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], w0, acc[u][v][0], 0, 0, 0);
@@ -532,12 +507,10 @@ __global__ __launch_bounds__(WG_THREADS) void k_conv_wgrad_part(const __bf16 *__
                         acc[u][v][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], w3, acc[u][v][3], 0, 0, 0);
                         acc[u][v][4] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], w4, acc[u][v][4], 0, 0, 0);
                     }
-                    prev3[v] = cur[v][3];
-                    cur[v] = nxt;
                 }
             }
         }
-        __syncthreads();           // the sub-slice's LDS is read before the next one is stored
+        __syncthreads();           // the part's LDS is read before the next part is stored
     }
 
     // the other position runs of a tile pair hand their sums to the first through LDS
@@ -559,8 +532,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_conv_wgrad_part(const __bf16 *__
     __syncthreads();
     if (active && h == 0) {
 #pragma unroll
-        for (int g = 1; g < H; ++g) {
-            const float *r = R + ((size_t)((g - 1) * PAIRS + pair) * RS) * 64 + lane;
+        for (int gg = 1; gg < H; ++gg) {
+            const float *r = R + ((size_t)((gg - 1) * PAIRS + pair) * RS) * 64 + lane;
 #pragma unroll
             for (int u = 0; u < MW; ++u)
 #pragma unroll
@@ -574,7 +547,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_conv_wgrad_part(const __bf16 *__
         }
     }
     __syncthreads();
-    // the block's partial [COUT][KP] (row stride KP + 1) and bias sums in LDS
+    // the block's partial [COUT][KP] (row stride KP + 1) in LDS, then 16-byte stores
     float *O = reinterpret_cast<float *>(lds);
     constexpr int OS = KP + 1;
     if (active && h == 0) {
@@ -598,9 +571,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_conv_wgrad_part(const __bf16 *__
     }
     __syncthreads();
     float *out = part + (size_t)p * COUT * KP;
-    constexpr int Q = KP / 4;            // 16-byte stores per row
-    for (int e = threadIdx.x; e < COUT * Q; e += WG_THREADS) {
-        const int r = e / Q, c = (e % Q) * 4;
+    constexpr int Q = KP / 4;
+    for (int ee = tid; ee < COUT * Q; ee += BW_THREADS) {
+        const int r = ee / Q, c = (ee % Q) * 4;
         const float *o = O + r * OS + c;
         *reinterpret_cast<float4 *>(out + (size_t)r * KP + c) = make_float4(o[0], o[1], o[2], o[3]);
     }
@@ -756,57 +729,48 @@ using namespace sur;
 extern "C" int surx_loss_slots(void) { return LOSS_SLOTS; }
 
 // loss0 (LOSS_SLOTS doubles, may be null) is cleared for the training step's loss
-extern "C" hipError_t surx_features(const float *params, __bf16 *feat, __bf16 *featT, double *loss0, int X, int B,
-                                    hipStream_t s)
+extern "C" hipError_t surx_features(const float *params, __bf16 *feat, double *loss0, int X, int B, hipStream_t s)
 {
     const int n = X * B > LOSS_SLOTS ? X * B : LOSS_SLOTS;
-    hipLaunchKernelGGL(k_features, dim3((n + 255) / 256), dim3(256), 0, s, params, feat, featT, loss0, X, B);
+    hipLaunchKernelGGL(k_features, dim3((n + 255) / 256), dim3(256), 0, s, params, feat, loss0, X, B);
     return hipGetLastError();
 }
 
-// ybT may be null (inference: no weight gradient follows)
 extern "C" hipError_t surx_conv_fwd(int layer, const __bf16 *in, const __bf16 *Wf, const float *bias, float *yf,
-                                    __bf16 *yb, __bf16 *ybT, int X, int B, hipStream_t s)
+                                    __bf16 *yb, int X, int B, hipStream_t s)
 {
     dim3 g((X + BLOCK_POS - 1) / BLOCK_POS * B), t(CONV_THREADS);
-    if (layer == 0) hipLaunchKernelGGL((k_conv_fwd<16, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
-    else if (layer < 5) hipLaunchKernelGGL((k_conv_fwd<64, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
-    else hipLaunchKernelGGL((k_conv_fwd<64, OUTP, false>), g, t, 0, s, in, Wf, bias, yf, yb, ybT, X, B);
+    if (layer == 0) hipLaunchKernelGGL((k_conv_fwd<16, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, X, B);
+    else if (layer < 5) hipLaunchKernelGGL((k_conv_fwd<64, 64, true>), g, t, 0, s, in, Wf, bias, yf, yb, X, B);
+    else hipLaunchKernelGGL((k_conv_fwd<64, OUTP, false>), g, t, 0, s, in, Wf, bias, yf, yb, X, B);
     return hipGetLastError();
 }
 
-extern "C" hipError_t surx_loss(const float *out, const float *target, __bf16 *dz, __bf16 *dzT, double *loss, int X,
-                                int B, hipStream_t s)
+extern "C" hipError_t surx_loss(const float *out, const float *target, __bf16 *dz, double *loss, int X, int B,
+                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_loss, dim3(X / LOSS_POS * B), dim3(256), 0, s, out, target, dz, dzT, loss, X, B);
+    hipLaunchKernelGGL(k_loss, dim3(X / LOSS_POS * B), dim3(256), 0, s, out, target, dz, loss, X, B);
     return hipGetLastError();
 }
 
-// input gradient of layer `layer` (1..5; layer 0 has none)
-extern "C" hipError_t surx_conv_dgrad(int layer, const __bf16 *dz, const __bf16 *Wb, const float *yprev,
-                                      __bf16 *dzprev, __bf16 *dzprevT, int X, int B, hipStream_t s)
+// backward pass of layer `layer` (grid: batch x slices): layers 1..5 take the
+// FP32 input y (the layer below's output) and write the layer below's output
+// gradient dzprev; layer 0 takes the features and has no input gradient
+extern "C" hipError_t surx_conv_bwd(int layer, const __bf16 *dz, const float *yin, const __bf16 *feat,
+                                    const __bf16 *Wb, __bf16 *dzprev, float *part, float *pbias, int X, int B,
+                                    hipStream_t s)
 {
-    dim3 g((X + BLOCK_POS - 1) / BLOCK_POS * B), t(CONV_THREADS);
-    if (layer == 5) hipLaunchKernelGGL((k_conv_dgrad<64, OUTP>), g, t, 0, s, dz, Wb, yprev, dzprev, dzprevT, X, B);
-    else hipLaunchKernelGGL((k_conv_dgrad<64, 64>), g, t, 0, s, dz, Wb, yprev, dzprev, dzprevT, X, B);
-    return hipGetLastError();
-}
-
-// partial weight and bias gradients of layer `layer` (grid: batch x slices)
-extern "C" hipError_t surx_conv_wgrad_part(int layer, const __bf16 *dzT, const __bf16 *inT, float *part, float *pbias,
-                                           int X, int B, hipStream_t s)
-{
-    const dim3 g((unsigned)(B * ((X + WG_SLICE - 1) / WG_SLICE))), t(WG_THREADS);
+    const dim3 g((unsigned)(B * ((X + BW_SLICE - 1) / BW_SLICE))), t(BW_THREADS);
     if (layer == 0)
-        hipLaunchKernelGGL((k_conv_wgrad_part<16, 64>), g, t, 0, s, dzT, inT, part, pbias, X);
+        hipLaunchKernelGGL((k_conv_bwd<16, 64, false>), g, t, 0, s, dz, yin, feat, Wb, dzprev, part, pbias, X);
     else if (layer < 5)
-        hipLaunchKernelGGL((k_conv_wgrad_part<64, 64>), g, t, 0, s, dzT, inT, part, pbias, X);
+        hipLaunchKernelGGL((k_conv_bwd<64, 64, true>), g, t, 0, s, dz, yin, feat, Wb, dzprev, part, pbias, X);
     else
-        hipLaunchKernelGGL((k_conv_wgrad_part<64, OUTP>), g, t, 0, s, dzT, inT, part, pbias, X);
+        hipLaunchKernelGGL((k_conv_bwd<64, OUTP, true>), g, t, 0, s, dz, yin, feat, Wb, dzprev, part, pbias, X);
     return hipGetLastError();
 }
 
-extern "C" int surx_wgrad_parts(int X, int B) { return B * ((X + WG_SLICE - 1) / WG_SLICE); }
+extern "C" int surx_wgrad_parts(int X, int B) { return B * ((X + BW_SLICE - 1) / BW_SLICE); }
 
 extern "C" hipError_t surx_reduce_adam(const float *part, const float *pbias, int P, float *wm, float *mw, float *vw,
                                        float *dw, float *bias, float *mb, float *vb, float *db, __bf16 *Wf, __bf16 *Wb,

@@ -44,12 +44,12 @@ def test_surrogate_workspace_and_shapes():
     assert surrogate.N_WEIGHTS == 99520 and surrogate.N_BIASES == 359 and surrogate.N_OUT == 39
     a = surrogate.workspace_size(1, 2048)
     b = surrogate.workspace_size(32, 2048)
-    # per position: features 2 x 16 bf16, outputs 5 x 64 + 48 FP32 (39 channels
-    # padded to 48), hidden bf16 copies 2 x 5 x 64, two gradient buffers
-    # 2 x 2 x 64 bf16 = 3328 bytes; per sample, the partial weight and bias
-    # gradients of one layer over its slices of 512 positions
-    per_pos = 2 * 16 * 2 + (5 * 64 + 48) * 4 + 2 * 5 * 64 * 2 + 2 * 2 * 64 * 2
-    per_sample = (2048 // 512) * (64 * 320 + 64) * 4
+    # per position: features 16 bf16, outputs 5 x 64 + 48 FP32 (39 channels
+    # padded to 48), hidden bf16 copies 5 x 64, two gradient buffers 2 x 64
+    # bf16 = 2400 bytes; per sample, the partial weight and bias gradients of
+    # one layer over its slices of 256 positions
+    per_pos = 16 * 2 + (5 * 64 + 48) * 4 + 5 * 64 * 2 + 2 * 64 * 2
+    per_sample = (2048 // 256) * (64 * 320 + 64) * 4
     assert abs((b - a) - (per_pos * 2048 + per_sample) * 31) < 64 * 1024
     for bad in ((0, 2048), (4, 100), (4, 0)):
         with pytest.raises(pic.PicError) as e:
