@@ -119,9 +119,23 @@ __device__ __forceinline__ void stage_rows(__bf16 *lds, const __bf16 *__restrict
 // ---------------------------------------------------------------------------
 // Forward conv: out[b][x][co] = act(bias[co] + sum_{t, ci} W[co][t][ci] in[b][x+t-2][ci]).
 // GEMM M = positions, N = COUT, K = 5*CIN (padded to KP).  A block of 8
-// waves covers BLOCK_POS positions of one sample with the layer's weights in
-// LDS; a wave computes 16 positions x COUT at a time.
+// waves covers BLOCK_POS positions of one sample: the layer's weights and the
+// block's input rows (two halo positions each side, zero outside the sample)
+// are staged in LDS with one batch of loads; a wave computes 16 positions x
+// COUT at a time from LDS and writes its tile through LDS as whole rows
+// (16-byte stores of the FP32 output and its bfloat16 copy).  The input row
+// stride puts 8 consecutive rows on different 16-byte bank groups.
 // ---------------------------------------------------------------------------
+constexpr int FW_ROWS = BLOCK_POS + 4;
+constexpr int fw_in_stride(int c) { return c == 64 ? 72 : 24; }     // 144 or 48 bytes per row
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 template <int CIN, int COUT, bool TANH>
 __global__ __launch_bounds__(CONV_THREADS) void k_conv_fwd(const __bf16 *__restrict__ in, const __bf16 *__restrict__ Wf,
                                                   const float *__restrict__ bias, float *__restrict__ yf,
@@ -130,49 +144,95 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv_fwd(const __bf16 *__restr
     constexpr int K = KS * CIN;
     constexpr int KP = (K + 31) / 32 * 32;
     constexpr int NT = COUT / 16;
+    constexpr int SIN = fw_in_stride(CIN);
+    constexpr int IV = CIN / 8;                                  // 16-byte vectors per input row
+    constexpr int NI = (FW_ROWS * IV + CONV_THREADS - 1) / CONV_THREADS;
+    constexpr int OS = COUT + 4;                                 // staged output row (floats)
+    static_assert(CIN == 16 || CIN == 64, "input row stride");
     __shared__ __bf16 wl[COUT * (KP + 8)];
+    __shared__ __align__(16) __bf16 it[FW_ROWS * SIN];
+    __shared__ __align__(16) float ot[CONV_THREADS / 64][16 * OS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int tiles = (X + BLOCK_POS - 1) / BLOCK_POS;
     const int b = blockIdx.x / tiles;
     if (b >= B) return;
-    stage_rows<COUT, KP, CONV_THREADS>(wl, Wf);
+    const int xb = (blockIdx.x - b * tiles) * BLOCK_POS;
+    const __bf16 *inb = in + (size_t)b * X * CIN;
+    {
+        bf16x8 r[NI];
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int v = threadIdx.x + k * CONV_THREADS, x = xb - PAD + v / IV;
+            r[k] = v < FW_ROWS * IV && x >= 0 && x < X ? load8(inb + (size_t)x * CIN + (v % IV) * 8) : zero8();
+        }
+        stage_rows<COUT, KP, CONV_THREADS>(wl, Wf);
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int v = threadIdx.x + k * CONV_THREADS;
+            if (v < FW_ROWS * IV) *reinterpret_cast<bf16x8 *>(it + (v / IV) * SIN + (v % IV) * 8) = r[k];
+        }
+    }
     __syncthreads();
     const int m = lane & 15, kb = lane >> 4;
-    const __bf16 *inb = in + (size_t)b * X * CIN;
-    const int xb = (blockIdx.x - b * tiles) * BLOCK_POS;
+    float *o = ot[w];
     for (int x0 = xb + w * 16; x0 < min(X, xb + BLOCK_POS); x0 += CONV_THREADS / 4) {
-    f32x4 acc[NT];
+        f32x4 acc[NT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < KP / 32; ++ks) {
-        const int kappa = ks * 32 + kb * 8;
-        bf16x8 a = zero8();
-        if (kappa < K) {
-            const int t = kappa / CIN, ci = kappa - t * CIN;
-            const int xs = x0 + m + t - PAD;
-            if (xs >= 0 && xs < X) a = load8(inb + (size_t)xs * CIN + ci);
+        for (int ks = 0; ks < KP / 32; ++ks) {
+            const int kappa = ks * 32 + kb * 8;
+            bf16x8 a = zero8();
+            if (kappa < K) {
+                // in at position x0 + m + t - 2: row x0 - xb + m + t of the staged rows
+                const int t = kappa / CIN, ci = kappa - t * CIN;
+                a = *reinterpret_cast<const bf16x8 *>(it + (x0 - xb + m + t) * SIN + ci);
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(wl + (nt * 16 + m) * (KP + 8) + kappa);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[nt], 0, 0, 0);
+            }
         }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(wl + (nt * 16 + m) * (KP + 8) + kappa);
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[nt], 0, 0, 0);
-        }
-    }
+            const int co = nt * 16 + m;
+            const float bc = bias[co];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int co = nt * 16 + m;
-        float v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int x = x0 + kb * 4 + i;
-            v[i] = acc[nt][i] + bias[co];
-            if (TANH) v[i] = tanhf(v[i]);
-            const size_t o = ((size_t)b * X + x) * COUT + co;
-            yf[o] = v[i];
-            if (yb) yb[o] = (__bf16)v[i];
+            for (int i = 0; i < 4; ++i) {
+                float v = acc[nt][i] + bc;
+                if (TANH) v = tanhf(v);
+                o[(kb * 4 + i) * OS + co] = v;
+            }
         }
-    }
+        wave_lds_sync();
+        // the tile's 16 rows are contiguous in yf and yb
+        float *yrow = yf + ((size_t)b * X + x0) * COUT;
+        constexpr int Q4 = 16 * COUT / 4;
+#pragma unroll
+        for (int k = 0; k < (Q4 + 63) / 64; ++k) {
+            const int e = lane + 64 * k;
+            if (e < Q4) {
+                const int r = e / (COUT / 4), c = (e % (COUT / 4)) * 4;
+                *reinterpret_cast<float4 *>(yrow + r * COUT + c) = *reinterpret_cast<const float4 *>(o + r * OS + c);
+            }
+        }
+        if (yb) {
+            __bf16 *brow = yb + ((size_t)b * X + x0) * COUT;
+            constexpr int Q8 = 16 * COUT / 8;
+#pragma unroll
+            for (int k = 0; k < (Q8 + 63) / 64; ++k) {
+                const int e = lane + 64 * k;
+                if (e < Q8) {
+                    const int r = e / (COUT / 8), c = (e % (COUT / 8)) * 8;
+                    bf16x8 h;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) h[u] = (__bf16)o[r * OS + c + u];
+                    *reinterpret_cast<bf16x8 *>(brow + r * COUT + c) = h;
+                }
+            }
+        }
+        wave_lds_sync();
     }
 }
 
