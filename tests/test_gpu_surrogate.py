@@ -89,8 +89,12 @@ def test_forward_matches_oracle(sur, torch, B, X):
     assert all(np.array_equal(x, y) for x, y in zip(W, W2)) and all(np.array_equal(x, y) for x, y in zip(b, b2))
 
 
-def test_gradients_and_adam_match_oracle(sur, torch):
-    B, X, lr = 2, 256, 1e-3
+# X = 256: one whole slice of the backward kernel; 320: a second slice of 64
+# positions (a part shorter than the LDS part); 64: one short part with the
+# sample's zero padding on both sides; 2048: eight slices per sample
+@pytest.mark.parametrize("B,X", [(2, 256), (3, 320), (1, 64), (2, 2048)])
+def test_gradients_and_adam_match_oracle(sur, torch, B, X):
+    lr = 1e-3
     _say("case: surrogate gradients B=%d X=%d" % (B, X))
     W, b = presets.surrogate_test_weights(12)
     p = _params(B, 22)
