@@ -231,17 +231,27 @@ def test_diagnostics_window(pic, O):
     assert np.array_equal(win["n_live"], t["n_live"])
 
 
-def test_time_average_fields(pic):
+def test_time_average_fields(pic, O):
+    """The time-averaged potential and densities are the mean of the
+    instantaneous ones over the averaging window, and every instantaneous
+    field that enters the mean matches the oracle: each step is a restart
+    step against the oracle (deposit bit for bit, potential of the oracle's
+    solve, particles and tallies after the step), and so is the last state."""
     cfg = presets.tiny()
     _say("case: time-averaged fields")
     h = pic.Handle(cfg)
     h.step(5)
     h.avg_reset(True)
     acc = None
+    probs = []
     for _ in range(8):
-        h.step(1)
+        probs += restart_step_check(O, cfg, h, 1)        # one GPU step, checked
         f = h.fields(0)
         acc = {k: v.copy() for k, v in f.items()} if acc is None else {k: acc[k] + f[k] for k in f}
+    st, gt = gpu_state(h)
+    s = oracle_from_gpu(O, cfg, st, gt)
+    probs += deposit_matches(O, cfg, h, st) + field_matches(O, cfg, h, s)
+    assert probs == [], "\n".join(probs[:20])
     avg = h.fields(0, time_avg=True)
     for k in acc:
         assert np.allclose(avg[k], acc[k] / 8, rtol=1e-12, atol=1e-9 * np.abs(acc[k]).max())
