@@ -176,9 +176,8 @@ void layout(const pic_config *cfgs, int nd, const std::vector<pic_derived> &der,
         D.phi = bp.take<double>(nn);
         D.E = bp.take<double>(nn);
         D.phi_sum = bp.take<double>(nn);
-        D.agg = bp.take<FieldAgg>((nn + 1023) / 1024);
-        D.bagg = bp.take<FieldAgg>((nn + 1023) / 1024);
-        for (int s = 0; s < NSP; ++s) D.Hb[s] = bp.take<unsigned long long>(nn);
+        D.agg = bp.take<FieldAgg>((nn + 1023) / 1024);     // one per 1024-node tile
+        D.agg_flag = bp.take<uint32_t>((nn + 1023) / 1024);
         D.tacc = bp.take<TallyCopy>(TALLY_COPIES);
     }
     zero_end = bp.off;
@@ -842,6 +841,7 @@ int pic_avg_control(pic_handle *h, int diode, int on)
         HIP_TRY(hipMemsetAsync(D.phi_sum, 0, nn * sizeof(double), h->stream));
         int v[2] = {on ? 1 : 0, 0};
         HIP_TRY(hipMemcpyAsync(&D.st->avg_on, v, sizeof(v), hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipMemsetAsync(&D.st->phi_slope_sum, 0, sizeof(double), h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
     }
     return PIC_OK;
@@ -858,9 +858,10 @@ int pic_get_fields(pic_handle *h, int diode, double *phi, double *n_e, double *n
     const double navg = time_avg ? (double)std::max(st.avg_steps, 1) : 1.0;
     if (time_avg && st.avg_steps == 0) return fail(PIC_EINVAL, "no time average accumulated");
     if (phi) {
+        // the large-grid field step stores phi less phi_slope j (zero on smaller grids)
         HIP_TRY(hipMemcpy(phi, time_avg ? D.phi_sum : D.phi, nn * sizeof(double), hipMemcpyDeviceToHost));
-        if (time_avg)
-            for (int j = 0; j < nn; ++j) phi[j] /= navg;
+        const double slope = time_avg ? st.phi_slope_sum : st.phi_slope;
+        for (int j = 0; j < nn; ++j) phi[j] = (phi[j] + slope * (double)j) / navg;
     }
     std::vector<long long> H[NSP];
     for (int s = 0; s < NSP; ++s) {
@@ -924,7 +925,12 @@ int pic_get_efield(pic_handle *h, int diode, double *out)
 {
     if (!h || !out || diode < 0 || diode >= h->nd) return fail(PIC_EINVAL, "bad arguments");
     HIP_TRY(hipStreamSynchronize(h->stream));
-    HIP_TRY(hipMemcpy(out, h->hD[diode].E, (h->cfg[diode].N + 1) * sizeof(double), hipMemcpyDeviceToHost));
+    const int nn = h->cfg[diode].N + 1;
+    DiodeState st;
+    HIP_TRY(hipMemcpy(&st, h->hD[diode].st, sizeof(st), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(out, h->hD[diode].E, nn * sizeof(double), hipMemcpyDeviceToHost));
+    // the large-grid field step stores E less a uniform shift (zero on smaller grids)
+    for (int j = 0; j < nn; ++j) out[j] += st.e_shift;
     return PIC_OK;
 }
 
@@ -1259,7 +1265,7 @@ int pic_steady_state(pic_handle *h, int diode, int block_tallies, double tol_pp,
 namespace {
 
 constexpr char CKPT_MAGIC[8] = {'P', 'I', 'C', 'C', 'K', 'P', 'T', '1'};
-constexpr uint32_t CKPT_VERSION = 2;
+constexpr uint32_t CKPT_VERSION = 3;
 
 struct CkptHeader {
     char magic[8];
@@ -1436,6 +1442,7 @@ int pic_load(pic_handle *h, const void *host_buf, size_t bytes)
         s0.parity = h->parity;   // the slots go into this handle's current buffer
         s0.arrive = 0;           // no field step is in flight at a step boundary
         s0.spill_flag = 0u;
+        s0.field_epoch = 0u;     // with the tile flags cleared below
         cc += sizeof(DiodeState);
         if ((rc = xfer<false>(cc, D.tally, sizeof(DiodeTally))) || (rc = xfer<false>(cc, D.ring, sizeof(TallySnap) * RING)))
             return rc;
@@ -1462,6 +1469,7 @@ int pic_load(pic_handle *h, const void *host_buf, size_t bytes)
         // per-step scratch starts clear
         for (int s = 0; s < NSP; ++s) HIP_TRY(hipMemset(D.cell_cnt[s], 0, nn * sizeof(int32_t)));
         HIP_TRY(hipMemset(D.tacc, 0, sizeof(TallyCopy) * TALLY_COPIES));
+        HIP_TRY(hipMemset(D.agg_flag, 0, sizeof(uint32_t) * ((nn + 1023) / 1024)));
     }
     h->sort_next = true;
     return PIC_OK;

@@ -81,7 +81,14 @@ struct DiodeState {
     int32_t rare_n[NSP];   // rare items (candidates, absorbed) listed this step
     int32_t arrive;        // field step: blocks that have read this step's counters
     uint32_t spill_flag;   // field step: step + 1 once the spilled rare items are done
-    uint32_t pad;
+    uint32_t field_epoch;  // large-grid field step: launches so far (tile aggregate flags are epoch + 1)
+    // Large-grid field step (zero on smaller grids): the stored phi and E
+    // leave out phi_slope j and e_shift = -phi_slope / dz, the part of the
+    // potential that needs every tile; phi_slope_sum is the slope's sum over
+    // the steps of the time average.
+    double phi_slope;
+    double e_shift;
+    double phi_slope_sum;
 };
 
 // Cumulative tallies (device); all integers are order independent.
@@ -170,9 +177,8 @@ struct Diode {
     DiodeState *st;
     DiodeTally *tally;
     TallySnap *ring;
-    FieldAgg *agg;         // one per FT-node tile of the field solve
-    FieldAgg *bagg;        // the births' share of each tile's aggregates (tiled step)
-    unsigned long long *Hb[NSP];   // the births' deposits (tiled step; zero between steps)
+    FieldAgg *agg;         // the large-grid field step's tile aggregates
+    uint32_t *agg_flag;    // and their flags (field_epoch + 1 once published)
     uint32_t *rare[NSP];   // the step's rare items per species: slot | kind << 30
     TallyCopy *tacc;       // TALLY_COPIES accumulators of the particle kernel's tallies
 };

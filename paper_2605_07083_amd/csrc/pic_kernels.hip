@@ -6,12 +6,12 @@
 //                     absorption -> null-collision MCC (compacted candidate
 //                     queue) -> 64-bit fixed-point CIC deposit into an LDS
 //                     window histogram flushed with global integer atomics;
-//   k_field_step      one block per tile of 512 nodes of every diode plus one
-//                     for the newborn records: ionisation products (ordered
-//                     by parent id), thermionic emission, pair replenishment,
+//   k_field_step /    one block per node tile of every diode plus one for
+//   k_field_tiles     the newborn records: ionisation products (ordered by
+//                     parent id), thermionic emission, pair replenishment,
 //                     then the exact-integer double prefix-scan Poisson solve
-//                     and the field, tallies and snapshots (grids above 4097
-//                     nodes: k_field_agg and k_field_solve instead).
+//                     and the field, tallies and snapshots (k_field_tiles on
+//                     grids above 4097 nodes).
 // Particles are processed in chunks of 256*PPT slots; the chunk list spans all
 // (diode, species) segments and is walked by a persistent grid whose
 // block -> chunk map keeps consecutive chunks on one XCD.
@@ -25,7 +25,6 @@ constexpr int WMAX = 512;          // LDS window (nodes) of the field tile / his
 constexpr int QW_SLACK = 384;      // per-wave LDS queue of rare items: 64 PPT + QW_SLACK entries
 constexpr int DRIFT = 160;         // cells of drift since the last re-sort kept in the LDS window
 constexpr int BIN_SHIFT = 5;       // the re-sort orders particles by bins of 32 cells
-constexpr int DRIFT_B = (DRIFT >> BIN_SHIFT) + 1;   // the drift margin in bins
 // The re-sort's window margin (bins) around a run's first and last bin: wide
 // enough for the fastest electrons of a period (a particle outside takes a
 // global counter atomic and four partial-line stores of its own); the LDS
@@ -536,17 +535,8 @@ __device__ __forceinline__ void flush_tally(const Diode &dd, const RareTally &t)
     if (t.ion_lost) atomicAdd(&a.ion_lost, t.ion_lost);
 }
 
-// Fold the accumulator copies into rt (LDS) and clear them: the first wave
-// of the block, one copy per lane (read and cleared by take_tally_copy), a
-// fixed shuffle tree per field.
-__device__ __forceinline__ RareTally take_tally_copy(const Diode &dd)
-{
-    static_assert(TALLY_COPIES == 64, "one copy per lane of the first wave");
-    const int lane = threadIdx.x & 63;
-    const RareTally v = dd.tacc[lane].t;
-    dd.tacc[lane].t = RareTally{};
-    return v;
-}
+// Fold the accumulator copies (one per lane of the first wave, read by
+// read_tally_copy) into rt (LDS) with a fixed shuffle tree per field.
 __device__ __forceinline__ void fold_tally_copies(RareTally v, RareTally *rt)
 {
     if (threadIdx.x >= 64) return;
@@ -696,8 +686,10 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             w0 = uni(max(0, (ba << BIN_SHIFT) - DRIFT));
             wn = uni(min(min(N, ((bb + 1) << BIN_SHIFT) + DRIFT) - w0 + 1, WMAX + 1));
         }
+        // the large-grid field step leaves E short by one uniform shift per diode
+        const double eshift = S[d].e_shift;
         for (int t = tid; t < wn; t += NT) {
-            if (mode == 0) etile[t] = glb(dd.E)[w0 + t];
+            if (mode == 0) etile[t] = glb(dd.E)[w0 + t] + eshift;
             hist[t] = 0ull;
         }
         lds_barrier();
@@ -766,7 +758,7 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                         // for the next chunk's prefetch)
                         double e0, e1;
                         if (inw) { e0 = etile[jl]; e1 = etile[jl + 1]; }
-                        else { e0 = glb(dd.E)[jo]; e1 = glb(dd.E)[jo + 1]; }
+                        else { e0 = glb(dd.E)[jo] + eshift; e1 = glb(dd.E)[jo + 1] + eshift; }
                         {
 #pragma clang fp contract(off)
                             Ep = (1.0 - fo) * e0 + fo * e1;
@@ -1480,11 +1472,6 @@ __device__ __forceinline__ double to_double(I128 a)
     return negv ? -m : m;
 }
 
-// ---------------------------------------------------------------------------
-// Sources and field: one workgroup of 1024 threads per diode.
-// mode 0: births, solve, field, tallies, step + 1; mode 1: solve and field only.
-// ---------------------------------------------------------------------------
-
 __device__ __forceinline__ I128 shfl_up_i128(I128 a, int o)
 {
     I128 r;
@@ -1493,218 +1480,11 @@ __device__ __forceinline__ I128 shfl_up_i128(I128 a, int o)
     return r;
 }
 
-// Where the births of the two-kernel step (grids above 4097 nodes) deposit:
-// they run beside the tile aggregates, which read H, so they deposit into the
-// side histograms Hb and sum their share of each tile's aggregates in LDS:
-// A_t (charge) and B_t (charge times the number of the tile's interior nodes
-// at or after its node), B_t as a 128-bit integer.
-constexpr int MAX_TILES = 32768 / FT;    // N <= 32767
-struct BirthSink {
-    unsigned long long *bA;      // [MAX_TILES] LDS
-    unsigned long long *bBlo;
-    unsigned long long *bBhi;
-};
-
-__device__ __forceinline__ void tile_share(const Diode &dd, const BirthSink &k, int j, long long v)
-{
-    if (j < 1 || j > dd.N - 1 || v == 0) return;
-    const int t = j / FT;
-    const long long x = v * (long long)(min((t + 1) * FT, dd.N) - j);    // |x| < 2^43
-    atomicAdd(&k.bA[t], (unsigned long long)v);
-    // 128-bit add of the sign-extended x: the carry out of the low word is
-    // taken from the value this add found there
-    const unsigned long long old = atomicAdd(&k.bBlo[t], (unsigned long long)x);
-    const unsigned long long hi = (x < 0 ? ~0ull : 0ull) + (old + (unsigned long long)x < old ? 1ull : 0ull);
-    if (hi) atomicAdd(&k.bBhi[t], hi);
-}
-
-__device__ __forceinline__ void deposit_birth(const Diode &dd, const BirthSink &k, int s, double z)
-{
-    int j;
-    double f;
-    cic(z, dd.invdz, dd.N, j, f);
-    const unsigned long long a = fixed_right(f), l = (1ull << 32) - a;
-    gadd(&glb(dd.Hb[s])[j], l);
-    gadd(&glb(dd.Hb[s])[j + 1], a);
-    const long long sg = s == SP_I ? 1 : -1;     // charge: ions minus electrons
-    tile_share(dd, k, j, sg * (long long)l);
-    tile_share(dd, k, j + 1, sg * (long long)a);
-}
-
 __device__ void write_particle(const GBuf &b, int i, double z, float vx, float vy, float vz, uint32_t id,
                                uint32_t tc)
 {
     b.z[i] = z; b.vz[i] = vz; b.tc[i] = tc;
     put_cold(&b.cold[i], vx, vy, id);
-}
-
-// Births of one step, one thread per newborn: ionisation products in
-// increasing parent id, thermionic emission (flux-weighted half-Maxwellian at
-// Tc placed at z = v_z dt), pair replenishment (one e-ion pair per ion lost,
-// shared uniform position, Maxwellian at the initial temperatures).
-// Newborns deposit directly into the global histograms.
-// S: the diode's counters as read at the start of the step's sources (LDS);
-// lost: ions absorbed this step.
-__device__ __forceinline__ void sources(const Diode &dd, DiodeState *st, const DiodeState &S, int lost,
-                                        unsigned long long *keys, uint32_t step, int parity,
-                                        const BirthSink &sink)
-{
-    const int tid = threadIdx.x;
-    __shared__ int s_ne, s_q, s_R, s_bP, s_bE, s_bI, s_okP, s_okE, s_okI;
-    __shared__ uint32_t s_id0;
-    if (tid == 0) {
-        const int q = min(S.iz_count, IZQ_CAP);
-        const int R = dd.replenish ? S.ion_lost + lost : 0;
-        int ne = 0;
-        if (dd.emit_x > 0.0) {
-            const double fl = floor(dd.emit_x);
-            uint4 be = philox(step, EV_EMIT, 0u, 0u, 0xFFFFFFFFu, dd.kseed);
-            ne = (int)fl + (u53(be.x, be.y) < dd.emit_x - fl ? 1 : 0);
-        }
-        s_q = q; s_R = R; s_ne = ne; s_id0 = S.next_id;
-        s_bP = S.n[SP_P]; s_bE = S.n[SP_E]; s_bI = S.n[SP_I];
-        // births that do not fit are dropped and flagged
-        s_okP = min(q + R, dd.cap[SP_P] - s_bP);
-        s_okE = min(ne, dd.cap[SP_E] - s_bE);
-        s_okI = min(q + R, dd.cap[SP_I] - s_bI);
-        if (s_okP < q + R || s_okE < ne || s_okI < q + R) atomicOr(&st->err, ERR_CAPACITY);
-    }
-    __syncthreads();
-    const int q = s_q, R = s_R, ne = s_ne;
-    const uint32_t id0 = s_id0;
-    const GBuf bP = gbuf(dd.buf[parity][SP_P]), bE = gbuf(dd.buf[parity][SP_E]), bI = gbuf(dd.buf[parity][SP_I]);
-
-    if (q > 0) {
-        int np2 = 1;
-        while (np2 < q) np2 <<= 1;
-        for (int t = tid; t < np2; t += FT)
-            keys[t] = t < q ? ((unsigned long long)dd.izq[t].parent << 32) | (unsigned)t : ~0ull;
-        __syncthreads();
-        for (int k = 2; k <= np2; k <<= 1) {
-            for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                for (int t = tid; t < np2; t += FT) {
-                    const int p = t ^ jj;
-                    if (p > t) {
-                        const unsigned long long a = keys[t], bb = keys[p];
-                        const bool up = (t & k) == 0;
-                        if ((a > bb) == up) { keys[t] = bb; keys[p] = a; }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-    }
-    const int total = q + ne + R;
-    for (int x = tid; x < total; x += FT) {
-        if (x < q) {
-            const int r = x;
-            const IzEvent ev = dd.izq[(int)(keys[r] & 0xFFFFFFFFull)];
-            const uint32_t ide = id0 + 2u * r, idi = ide + 1u;
-            const uint4 be = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
-            const uint4 bi = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
-            if (r < s_okP) {
-                write_particle(bP, s_bP + r, ev.z, ev.ve[0], ev.ve[1], ev.ve[2], ide,
-                               next_candidate(step, dd.lam[0], be.z, be.w));
-                deposit_birth(dd, sink, SP_P, ev.z);
-            }
-            if (r < s_okI) {
-                write_particle(bI, s_bI + r, ev.z, ev.vi[0], ev.vi[1], ev.vi[2], idi,
-                               next_candidate(step, dd.lam[1], bi.z, bi.w));
-                deposit_birth(dd, sink, SP_I, ev.z);
-            }
-        } else if (x < q + ne) {
-            const int i = x - q;
-            const uint32_t idn = id0 + 2u * q + i;
-            const uint4 b0 = philox(step, EV_BIRTH, 0u, 0u, idn, dd.kseed);
-            const uint4 b1 = philox(step, EV_BIRTH, 1u, 0u, idn, dd.kseed);
-            double n1, n2;
-            bm32(b0.x, b0.y, n1, n2);
-            const float vz = (float)(dd.sig_c * sqrt(-2.0 * log(u53(b0.z, b0.w))));
-            const float vx = (float)(dd.sig_c * n1), vy = (float)(dd.sig_c * n2);
-            const double z = (double)vz * dd.dt;
-            const uint32_t tc = next_candidate(step, dd.lam[0], b1.z, b1.w);
-            if (i < s_okE) {
-                if (z >= dd.L) {
-                    const double ke = 0.5 * dd.mass[SP_E] * ((double)vx * vx + (double)vy * vy + (double)vz * vz);
-                    atomicAdd(&dd.tally->abs_count[SP_E][1], 1ull);
-                    atomicAdd(&dd.tally->abs_energy[SP_E][1], ke);
-                    write_particle(bE, s_bE + i, -1.0, vx, vy, vz, idn, tc);
-                } else {
-                    write_particle(bE, s_bE + i, z, vx, vy, vz, idn, tc);
-                    deposit_birth(dd, sink, SP_E, z);
-                }
-            }
-        } else {
-            const int r = x - q - ne;
-            const uint32_t ide = id0 + 2u * q + ne + 2u * r, idi = ide + 1u;
-            const uint4 e0 = philox(step, EV_BIRTH, 0u, 0u, ide, dd.kseed);
-            const uint4 e1 = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
-            const uint4 i0 = philox(step, EV_BIRTH, 0u, 0u, idi, dd.kseed);
-            const uint4 i1 = philox(step, EV_BIRTH, 1u, 0u, idi, dd.kseed);
-            const double z = dd.L * u53(e1.x, e1.y);
-            double a1, a2, a3, a4;
-            bm32(e0.x, e0.y, a1, a2);
-            bm32(e0.z, e0.w, a3, a4);
-            if (q + r < s_okP) {
-                write_particle(bP, s_bP + q + r, z, (float)(dd.sig_e0 * a1), (float)(dd.sig_e0 * a2),
-                               (float)(dd.sig_e0 * a3), ide, next_candidate(step, dd.lam[0], e1.z, e1.w));
-                deposit_birth(dd, sink, SP_P, z);
-            }
-            bm32(i0.x, i0.y, a1, a2);
-            bm32(i0.z, i0.w, a3, a4);
-            if (q + r < s_okI) {
-                write_particle(bI, s_bI + q + r, z, (float)(dd.sig_i0 * a1), (float)(dd.sig_i0 * a2),
-                               (float)(dd.sig_i0 * a3), idi, next_candidate(step, dd.lam[1], i1.z, i1.w));
-                deposit_birth(dd, sink, SP_I, z);
-            }
-        }
-    }
-    if (tid == 0) {
-        st->n[SP_P] = s_bP + s_okP;
-        st->n[SP_E] = s_bE + s_okE;
-        st->n[SP_I] = s_bI + s_okI;
-        st->next_id = id0 + 2u * q + ne + 2u * R;
-        if (ne) atomicAdd(&dd.tally->n_emit, (unsigned long long)ne);
-        if (R) atomicAdd(&dd.tally->n_repl, (unsigned long long)R);
-        if (q) atomicAdd(&dd.tally->n_iz, (unsigned long long)q);
-        st->iz_count = 0;
-        st->ion_lost = 0;
-#pragma unroll
-        for (int sp = 0; sp < NSP; ++sp) st->rare_n[sp] = 0;
-    }
-}
-
-// The sources part of a step for one diode, by one block of FT threads: the
-// rare items the particle kernel could not hold in LDS (normally none), then
-// the births.  keys: IZQ_CAP u64 of LDS scratch.
-// The step's sources for one diode (one block): the particle kernel's tally
-// copies and counters are read together, up front, so the chain of global
-// round trips is one load deep in the usual case.
-__device__ __forceinline__ void step_sources(const Diode &dd, DiodeState *st, unsigned long long *keys,
-                                             uint32_t step, int parity, RareTally *rt, const BirthSink &sink)
-{
-    __shared__ DiodeState s_st;
-    const int tid = threadIdx.x;
-    RareTally copy{};
-    if (tid < 64) copy = take_tally_copy(dd);      // in flight together with the counters
-    if (tid == 0) rare_tally_zero(rt);
-    if (tid >= 64 && tid < 128) load_state(st, &s_st);
-    __syncthreads();
-    fold_tally_copies(copy, rt);     // first wave
-    if (s_st.rare_n[SP_P] | s_st.rare_n[SP_E] | s_st.rare_n[SP_I]) {
-        // items the particle kernel's queues could not hold: they may queue
-        // ionisations, so the counters are read again afterwards
-        __syncthreads();
-        if (tid == 0)
-            atomicAdd(&dd.tally->rare_spill,
-                      (unsigned long long)(s_st.rare_n[SP_P] + s_st.rare_n[SP_E] + s_st.rare_n[SP_I]));
-        process_rare(dd, s_st.rare_n, parity, step, tid, FT, rt);
-        __syncthreads();
-        if (tid >= 64 && tid < 128) load_state(st, &s_st);
-    }
-    __syncthreads();
-    if (tid == 0) apply_tally(dd, *rt);
-    sources(dd, st, s_st, rt->ion_lost, keys, step, parity, sink);
 }
 
 __device__ __forceinline__ long long wave_incl_scan_i64(long long x)
@@ -1778,227 +1558,43 @@ __device__ __forceinline__ I128 block_scan_excl_i128(I128 v, I128 *sh, I128 &tot
 }
 
 // ---------------------------------------------------------------------------
-// Grids above 4097 nodes: the same step over tiles of FT nodes in two kernels
-// (every block loading every node, as k_field_step does, costs more there than
-// the second launch).
-//   k_field_agg    per tile: A_t = sum of rho over the tile, B_t = sum over the
-//                  tile's interior nodes of the in-tile inclusive prefix of
-//                  rho; with births (mode 0), one more block per diode runs
-//                  the overflow rare items and the births at the same time,
-//                  its deposits kept apart (Hb, bagg) because the tiles are
-//                  reading H meanwhile.
-//   k_field_solve  per tile: with P_t = sum_{u<t} A_u (= S1 before the tile),
-//                  Q_t = sum_{u<t} (n_u P_u + B_u) (= T before the tile) and
-//                  T_N from all tiles (births' shares added), the exact S1_j
-//                  and T_j of its nodes and of one halo node on each side,
-//                  phi_j and E_j as in k_field_step, and the node
-//                  bookkeeping.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void births_block(const Diode &dd, int parity)
-{
-    extern __shared__ long long nodes[];
-    __shared__ RareTally rt;
-    __shared__ unsigned long long bA[MAX_TILES], bBlo[MAX_TILES], bBhi[MAX_TILES];
-    const int tid = threadIdx.x;
-    if (tid < MAX_TILES) {
-        bA[tid] = 0ull;
-        bBlo[tid] = 0ull;
-        bBhi[tid] = 0ull;
-    }
-    DiodeState *st = dd.st;
-    // step_sources synchronises the block before the first deposit
-    step_sources(dd, st, reinterpret_cast<unsigned long long *>(nodes), st->step, parity, &rt,
-                 BirthSink{bA, bBlo, bBhi});
-    __syncthreads();
-    const int nt = (dd.N + 1 + FT - 1) / FT;
-    if (tid < nt) {
-        FieldAgg g;
-        g.A = (long long)bA[tid];
-        g.B_lo = bBlo[tid];
-        g.B_hi = (long long)bBhi[tid];
-        g.n = 0;
-        g.pad = 0;
-        dd.bagg[tid] = g;
-    }
-}
-
-__device__ __forceinline__ long long node_rho(const Diode &dd, int j)
-{
-    if (j < 1 || j > dd.N - 1) return 0;
-    return (long long)(dd.H[SP_I][j] - dd.H[SP_P][j] - dd.H[SP_E][j]);
-}
-
-__device__ __forceinline__ long long node_rho_births(const Diode &dd, int j)
-{
-    if (j < 1 || j > dd.N - 1) return 0;
-    return (long long)(dd.Hb[SP_I][j] - dd.Hb[SP_P][j] - dd.Hb[SP_E][j]);
-}
-
-// births: 1 with the births blocks (blockIdx.x == 0 of each diode), else 0
-__global__ __launch_bounds__(FT) void k_field_agg(const Diode *__restrict__ D, int births, int parity)
-{
-    const Diode &dd = D[blockIdx.y];
-    if ((int)blockIdx.x < births) {
-        births_block(dd, parity);
-        return;
-    }
-    const int t = (int)blockIdx.x - births, nn = dd.N + 1;
-    const int a = t * FT;
-    if (a >= nn) return;
-    __shared__ long long sh64[FW];
-    __shared__ I128 sh128[FW];
-    const int j = a + threadIdx.x;
-    const long long r = j < nn ? node_rho(dd, j) : 0;
-    long long A;
-    const long long excl = block_scan_excl_i64(r, sh64, A);
-    const bool interior = j >= 1 && j <= dd.N - 1;
-    I128 B;
-    block_scan_excl_i128(interior ? i128(excl + r) : i128(0), sh128, B);
-    if (threadIdx.x == 0) {
-        FieldAgg &g = dd.agg[t];
-        g.A = A;
-        g.B_lo = B.lo;
-        g.B_hi = B.hi;
-        g.n = max(0, min(a + FT, dd.N) - max(a, 1));
-    }
-}
-
-__device__ __forceinline__ double phi_node(const Diode &dd, int j, const I128 &T_N, const I128 &Tj)
-{
-    const int N = dd.N;
-    if (j <= 0) return 0.0;
-    if (j >= N) return dd.V;
-    const I128 x = add(mul_small(T_N, (unsigned)j), neg(mul_small(Tj, (unsigned)N)));
-    return dd.V * (double)j / (double)N + (dd.alpha / (double)N) * to_double(x);
-}
-
-__global__ __launch_bounds__(FT) void k_field_solve(const Diode *__restrict__ D, DiodeState *S, int mode,
-                                                    int ntiles)
-{
-    const Diode &dd = D[blockIdx.y];
-    DiodeState *st = dd.st;   // the pointer the rare-item code also writes through
-    const int t = blockIdx.x, N = dd.N, nn = N + 1;
-    const int a = t * FT;
-    if (a >= nn) return;
-    const int b = min(nn, a + FT);
-    __shared__ long long sh64[FW];
-    __shared__ I128 sh128[FW];
-    __shared__ double ph[FT + 2];
-    __shared__ long long s_P;
-    __shared__ I128 s_Q, s_TN;
-    const int j = a + threadIdx.x;
-    // in flight during the combine below
-    const long long r = j < b ? node_rho(dd, j) + (mode == 0 ? node_rho_births(dd, j) : 0) : 0;
-    if (threadIdx.x < 64) {
-        // The first wave reads every tile's aggregates at once, one lane per
-        // tile (N <= 32767 gives at most 32 tiles), and combines them with
-        // wave scans: P_u = sum_{v<u} A_v, the sum of S1 over tile u
-        // s_u = n_u P_u + B_u, Q_t = sum_{u<t} s_u and T_N = sum_u s_u.
-        const int u = threadIdx.x;
-        const int nt = min(ntiles, (nn + FT - 1) / FT);
-        long long A = 0;
-        I128 Bu = i128(0);
-        int n = 0;
-        if (u < nt) {
-            const FieldAgg g = dd.agg[u];
-            A = g.A;
-            Bu.lo = g.B_lo;
-            Bu.hi = g.B_hi;
-            n = g.n;
-            if (mode == 0) {
-                const FieldAgg gb = dd.bagg[u];
-                I128 bb;
-                bb.lo = gb.B_lo;
-                bb.hi = gb.B_hi;
-                A += gb.A;
-                Bu = add(Bu, bb);
-            }
-        }
-        const long long Pu = wave_incl_scan_i64(A) - A;
-        const I128 su = add(mul_small(i128(Pu), (unsigned)n), Bu);
-        const I128 incl = wave_incl_scan_i128(su);
-        if (u == t) {
-            s_P = Pu;
-            s_Q = add(incl, neg(su));
-        }
-        if (u == 63) s_TN = incl;
-    }
-    __syncthreads();
-    const long long P = s_P;
-    const I128 Q = s_Q, T_N = s_TN;
-    long long Aloc;
-    const long long S1 = P + block_scan_excl_i64(r, sh64, Aloc) + r;      // inclusive S1_j
-    const bool interior = j >= 1 && j <= N - 1 && j < b;
-    I128 Tsum;
-    const I128 Tloc = block_scan_excl_i128(interior ? i128(S1) : i128(0), sh128, Tsum);
-    const I128 Tj = add(Q, Tloc);                                        // sum_{m=1..j-1} S1_m
-    if (j < b) ph[threadIdx.x + 1] = phi_node(dd, j, T_N, Tj);
-    if (threadIdx.x == 0) {
-        // halo below: T_{a-1} = Q - S1_{a-1} if a-1 is interior, S1_{a-1} = P
-        if (a >= 1) {
-            const int jm = a - 1;
-            const I128 Tm = (jm >= 1 && jm <= N - 1) ? add(Q, neg(i128(P))) : Q;
-            ph[0] = phi_node(dd, jm, T_N, Tm);
-        }
-        // halo above: T_b = Q + (sum over the tile's interior nodes of S1)
-        if (b <= N) ph[b - a + 1] = phi_node(dd, b, T_N, add(Q, Tsum));
-    }
-    __syncthreads();
-    if (j < b) {
-        const int k = threadIdx.x + 1;
-        const double pc = ph[k];
-        double E;
-        if (j == 0) E = (pc - ph[k + 1]) / dd.dz;
-        else if (j == N) E = (ph[k - 1] - pc) / dd.dz;
-        else E = (ph[k - 1] - ph[k + 1]) * (1.0 / (2.0 * dd.dz));
-        dd.phi[j] = pc;
-        dd.E[j] = E;
-        const int avg = st->avg_on;
-#pragma unroll
-        for (int sp = 0; sp < NSP; ++sp) {
-            unsigned long long hu = dd.H[sp][j];
-            if (mode == 0) {
-                hu += dd.Hb[sp][j];
-                dd.Hb[sp][j] = 0ull;
-            }
-            if (hu >= DEPOSIT_LIMIT) atomicOr(&st->err, ERR_RANGE);
-            const long long h = (long long)hu;
-            dd.Hlast[sp][j] = h;
-            dd.H[sp][j] = 0ull;
-            if (avg) dd.Hsum[sp][j] += h;
-        }
-        if (avg) dd.phi_sum[j] += pc;
-    }
-    if (mode == 0 && t == 0 && threadIdx.x == 0) {
-        const uint32_t nstep = st->step + 1u;
-        st->step = nstep;
-        if (st->avg_on) st->avg_steps += 1;
-        if (dd.tally_period > 0 && nstep % (uint32_t)dd.tally_period == 0u) {
-            TallySnap &sn = dd.ring[(nstep / (uint32_t)dd.tally_period) % RING];
-            sn.step = nstep;
-            sn.t = *dd.tally;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Sources and field in one kernel, for grids of up to FUSED_MAX_NODES nodes.
+// Sources and field of a step in one kernel per step.
 //
-// Grid (tiles + 1, diodes).  Block 0 of a diode writes the newborn records;
-// block t + 1 writes the nodes [t TILE, (t+1) TILE) of tile t:
-// it stages every node's charge in LDS, works out the positions of the step's
-// newborns (the same counter-based draws, so every block finds the same ones)
-// and adds their charge, runs the exact integer double prefix scans over all
-// nodes and evaluates phi and E on its own tile and halo.  The last tile's
-// block (the writer) applies the step's tallies, clears the tally copies and
-// advances the counters once every other block of the diode has read them (a
-// counter they bump).  When the particle kernel spilled rare items to the
-// global lists (normally never), the record block works them off first and
-// the others wait for its flag before they read the counters those items
-// change.  Every wait is on blocks of the same diode dispatched earlier.
+// Grid (tiles + 1, diodes).  Block 0 of a diode writes the newborn records
+// (and works off any rare items the particle kernel spilled to the global
+// lists, normally none; the other blocks wait for its flag before they read
+// the counters those items change).  Block t + 1 takes tile t of the nodes:
+// it works out the positions of the step's newborns itself (the same
+// counter-based draws, so every block finds the same ones) and adds their
+// charge and deposits, solves for the potential with exact integer prefix
+// sums and writes phi, E and the node bookkeeping of its tile.  The last
+// tile's block (the writer) applies the step's tallies, clears the tally
+// copies and advances the counters once every other block of the diode has
+// read them (a counter they bump).  Every wait is on blocks of the same
+// diode dispatched earlier.
+//
+//   k_field_step   (N + 1 <= FUSED_MAX_NODES) tiles of TILE nodes; every tile
+//                  block stages the charge of every node in LDS and runs the
+//                  double prefix scans over all of them: phi exactly as
+//                  defined, rounded once.
+//   k_field_tiles  (larger grids) tiles of BIG_TILE nodes; a tile block
+//                  publishes its aggregates (A_t = sum of its charge, B_t =
+//                  sum over its interior nodes of the in-tile inclusive
+//                  prefix, n_t interior nodes) with a flag and combines the
+//                  aggregates of the tiles before it: P_t = sum_{u<t} A_u is
+//                  S1 before the tile, Q_t = sum_{u<t} (n_u P_u + B_u) is T
+//                  before it.  T_N needs every tile, so the tiles write
+//                  phi'_j = V j / N - alpha T_j and E' from phi'; the writer,
+//                  the last tile, has T_N and stores the correction
+//                  phi_j = phi'_j + j c, c = alpha T_N / N, which shifts every
+//                  node's E by -c / dz.  The particle kernel adds that shift
+//                  to the E it gathers, the host adds both to what it reads.
 // ---------------------------------------------------------------------------
-constexpr int TILE = 512;                 // nodes written per tile block
+constexpr int TILE = 512;                 // nodes per tile block of k_field_step
 constexpr int FUSED_MAX_NODES = 4097;     // every node's charge staged in each block's LDS
+constexpr int BIG_TILE = FT;              // nodes per tile block of k_field_tiles (one per thread)
+constexpr int MAX_TILES = 32768 / BIG_TILE;    // N <= 32767: the earlier tiles fit one wave
+static_assert(MAX_TILES <= 64, "one lane per earlier tile");
 
 struct BirthPlan {
     int q, R, ne;              // ionisation events, replenished pairs, emitted electrons
@@ -2008,19 +1604,21 @@ struct BirthPlan {
     int sorted;                // ionisation events taken in parent-id order (keys)
 };
 
-// A newborn's charge into the all-node charge R (interior nodes, ions
+// A newborn's charge into R for the nodes [r0, r1) (interior nodes, ions
 // positive) and its species deposit into the own tile's counts hb.
-__device__ __forceinline__ void fused_deposit(const Diode &dd, long long *R, unsigned long long (*hb)[TILE], int a0,
-                                              int b0, int s, double z)
+template <int HB>
+__device__ __forceinline__ void fused_deposit(const Diode &dd, long long *R, int r0, int r1,
+                                              unsigned long long (*hb)[HB], int a0, int b0, int s, double z)
 {
     int j;
     double f;
     cic(z, dd.invdz, dd.N, j, f);
     const unsigned long long a = fixed_right(f), l = (1ull << 32) - a;
     const long long sg = s == SP_I ? 1 : -1;
-    if (j >= 1) atomicAdd(reinterpret_cast<unsigned long long *>(&R[j]), (unsigned long long)(sg * (long long)l));
-    if (j + 1 <= dd.N - 1)
-        atomicAdd(reinterpret_cast<unsigned long long *>(&R[j + 1]), (unsigned long long)(sg * (long long)a));
+    if (j >= 1 && j >= r0 && j < r1)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&R[j - r0]), (unsigned long long)(sg * (long long)l));
+    if (j + 1 <= dd.N - 1 && j + 1 >= r0 && j + 1 < r1)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&R[j + 1 - r0]), (unsigned long long)(sg * (long long)a));
     if (j >= a0 && j < b0) atomicAdd(&hb[s][j - a0], l);
     if (j + 1 >= a0 && j + 1 < b0) atomicAdd(&hb[s][j + 1 - a0], a);
 }
@@ -2034,18 +1632,20 @@ __device__ __forceinline__ int iz_index(const BirthPlan &bp, const unsigned long
 // The positions of the step's newborns (ionisation products at their parent,
 // thermionic electrons at z = v_z dt with v_z from the flux-weighted
 // half-Maxwellian at Tc, replenished pairs at a shared uniform position),
-// one thread per newborn (pair), deposited into the block's LDS.  The writer
-// also tallies a thermionic electron placed beyond the anode.
+// one thread per newborn (pair), deposited into the block's LDS: the charge
+// of the nodes [r0, r1) into R, the species deposits of the own tile into
+// hb.  The writer also tallies a thermionic electron placed beyond the anode.
+template <int HB>
 __device__ __forceinline__ void births_deposit(const Diode &dd, const BirthPlan &bp, const unsigned long long *keys,
-                                               bool writer, uint32_t step, long long *R,
-                                               unsigned long long (*hb)[TILE], int a0, int b0)
+                                               bool writer, uint32_t step, long long *R, int r0, int r1,
+                                               unsigned long long (*hb)[HB], int a0, int b0)
 {
     const int q = bp.q, ne = bp.ne, total = q + ne + bp.R;
     for (int x = threadIdx.x; x < total; x += FT) {
         if (x < q) {
             const double z = dd.izq[iz_index(bp, keys, x)].z;
-            if (x < bp.okP) fused_deposit(dd, R, hb, a0, b0, SP_P, z);
-            if (x < bp.okI) fused_deposit(dd, R, hb, a0, b0, SP_I, z);
+            if (x < bp.okP) fused_deposit<HB>(dd, R, r0, r1, hb, a0, b0, SP_P, z);
+            if (x < bp.okI) fused_deposit<HB>(dd, R, r0, r1, hb, a0, b0, SP_I, z);
         } else if (x < q + ne) {
             const int i = x - q;
             if (i >= bp.okE) continue;
@@ -2054,7 +1654,7 @@ __device__ __forceinline__ void births_deposit(const Diode &dd, const BirthPlan 
             const float vz = (float)(dd.sig_c * sqrt(-2.0 * log(u53(b0w.z, b0w.w))));
             const double z = (double)vz * dd.dt;
             if (z < dd.L) {
-                fused_deposit(dd, R, hb, a0, b0, SP_E, z);
+                fused_deposit<HB>(dd, R, r0, r1, hb, a0, b0, SP_E, z);
             } else if (writer) {
                 double n1, n2;
                 bm32(b0w.x, b0w.y, n1, n2);
@@ -2068,8 +1668,8 @@ __device__ __forceinline__ void births_deposit(const Diode &dd, const BirthPlan 
             const uint32_t ide = bp.id0 + 2u * q + ne + 2u * r;
             const uint4 e1 = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
             const double z = dd.L * u53(e1.x, e1.y);
-            if (q + r < bp.okP) fused_deposit(dd, R, hb, a0, b0, SP_P, z);
-            if (q + r < bp.okI) fused_deposit(dd, R, hb, a0, b0, SP_I, z);
+            if (q + r < bp.okP) fused_deposit<HB>(dd, R, r0, r1, hb, a0, b0, SP_P, z);
+            if (q + r < bp.okI) fused_deposit<HB>(dd, R, r0, r1, hb, a0, b0, SP_I, z);
         }
     }
 }
@@ -2139,7 +1739,197 @@ __device__ __forceinline__ void births_records(const Diode &dd, const BirthPlan 
 // clears them once every block has read them).
 __device__ __forceinline__ RareTally read_tally_copy(const Diode &dd)
 {
+    static_assert(TALLY_COPIES == 64, "one copy per lane of the first wave");
     return dd.tacc[threadIdx.x & 63].t;
+}
+
+// The shared state of a field step's block.
+struct FieldShared {
+    RareTally rt, rs;          // the step's tallies (writer), the spilled items' (record block)
+    DiodeState s_st;           // the counters as this block read them
+    BirthPlan bp;
+};
+
+// The first reads of every block of a field step (mode 0): the particle
+// kernel's tally copies (first wave) and the counters (second wave).
+__device__ __forceinline__ RareTally field_step_reads(const Diode &dd, FieldShared &fs)
+{
+    const int tid = threadIdx.x;
+    RareTally copy{};
+    if (tid < 64) copy = read_tally_copy(dd);
+    if (tid >= 64 && tid < 128) load_state(dd.st, &fs.s_st);
+    if (tid == 0) {
+        rare_tally_zero(&fs.rt);
+        rare_tally_zero(&fs.rs);
+    }
+    return copy;
+}
+
+// After field_step_reads and a barrier: the writer folds every tally copy
+// into fs.rt, the others only the ions lost; the spilled rare items are
+// worked off (record block) or waited for; once the block is done with the
+// counters it bumps st->arrive (all but the writer), then works out the plan
+// of the step's births and, when the plan needs it, the ionisation events in
+// parent-id order in keys.
+__device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, bool records, bool writer,
+                                RareTally copy, FieldShared &fs, unsigned long long *keys)
+{
+    DiodeState *st = dd.st;
+    const int tid = threadIdx.x;
+    if (writer) {
+        fold_tally_copies(copy, &fs.rt);      // the step's totals, applied by the writer
+    } else if (tid < 64) {
+        int v = copy.ion_lost;                // the others need the ions lost only
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (tid == 0) fs.rt.ion_lost = v;
+    }
+    if (fs.s_st.rare_n[SP_P] | fs.s_st.rare_n[SP_E] | fs.s_st.rare_n[SP_I]) {
+        // items the particle kernel's queues could not hold: the record
+        // block collides them (they may queue ionisations and lose ions),
+        // then raises the flag the other blocks wait for
+        if (records) {
+            if (tid == 0)
+                atomicAdd(&dd.tally->rare_spill,
+                          (unsigned long long)(fs.s_st.rare_n[SP_P] + fs.s_st.rare_n[SP_E] + fs.s_st.rare_n[SP_I]));
+            process_rare(dd, fs.s_st.rare_n, parity, step, tid, FT, &fs.rs);
+            __syncthreads();
+            if (tid == 0) {
+                apply_tally(dd, fs.rs);
+                if (fs.rs.ion_lost) atomicAdd(&st->ion_lost, fs.rs.ion_lost);
+                __threadfence();
+                __hip_atomic_store(glb(&st->spill_flag), step + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else if (tid == 0) {
+            while (__hip_atomic_load(glb(&st->spill_flag), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != step + 1u)
+                __builtin_amdgcn_s_sleep(2);
+        }
+        __syncthreads();
+        if (tid >= 64 && tid < 128) load_state(st, &fs.s_st);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        // this block is done with the counters and the copies
+        if (!writer) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const DiodeState &S = fs.s_st;
+        BirthPlan p;
+        p.q = min(S.iz_count, IZQ_CAP);
+        p.R = dd.replenish ? S.ion_lost + fs.rt.ion_lost : 0;
+        p.ne = 0;
+        if (dd.emit_x > 0.0) {
+            const double fl = floor(dd.emit_x);
+            const uint4 be = philox(step, EV_EMIT, 0u, 0u, 0xFFFFFFFFu, dd.kseed);
+            p.ne = (int)fl + (u53(be.x, be.y) < dd.emit_x - fl ? 1 : 0);
+        }
+        p.id0 = S.next_id;
+        p.bP = S.n[SP_P];
+        p.bE = S.n[SP_E];
+        p.bI = S.n[SP_I];
+        // births that do not fit are dropped (and flagged by the writer)
+        p.okP = min(p.q + p.R, dd.cap[SP_P] - p.bP);
+        p.okE = min(p.ne, dd.cap[SP_E] - p.bE);
+        p.okI = min(p.q + p.R, dd.cap[SP_I] - p.bI);
+        // the parent-id order names the ionisation products (the record
+        // block) and, when some do not fit, decides which are dropped
+        p.sorted = p.q > 1 && (records || p.okP < p.q || p.okI < p.q);
+        fs.bp = p;
+    }
+    __syncthreads();
+    if (fs.bp.sorted) {
+        const int q = fs.bp.q;
+        int np2 = 1;
+        while (np2 < q) np2 <<= 1;
+        for (int i = tid; i < np2; i += FT)
+            keys[i] = i < q ? ((unsigned long long)dd.izq[i].parent << 32) | (unsigned)i : ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= np2; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int i = tid; i < np2; i += FT) {
+                    const int pi = i ^ jj;
+                    if (pi > i) {
+                        const unsigned long long u = keys[i], v = keys[pi];
+                        const bool up = (i & k) == 0;
+                        if ((u > v) == up) { keys[i] = v; keys[pi] = u; }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// The writer's end of a step (mode 0), once `others` blocks of the diode
+// have arrived: the tally copies cleared, the step's tallies applied, the
+// counters advanced, the snapshot taken.
+__device__ void field_step_tail(const Diode &dd, FieldShared &fs, uint32_t step, int avg, int others)
+{
+    DiodeState *st = dd.st;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        while (__hip_atomic_load(glb(&st->arrive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < others)
+            __builtin_amdgcn_s_sleep(2);
+        __hip_atomic_store(glb(&st->arrive), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (tid < 64) dd.tacc[tid].t = RareTally{};
+    if (tid == 0) {
+        const BirthPlan &p = fs.bp;
+        if (p.okP < p.q + p.R || p.okE < p.ne || p.okI < p.q + p.R) atomicOr(&st->err, ERR_CAPACITY);
+        apply_tally(dd, fs.rt);
+        st->n[SP_P] = p.bP + p.okP;
+        st->n[SP_E] = p.bE + p.okE;
+        st->n[SP_I] = p.bI + p.okI;
+        st->next_id = p.id0 + 2u * p.q + p.ne + 2u * p.R;
+        if (p.ne) atomicAdd(&dd.tally->n_emit, (unsigned long long)p.ne);
+        if (p.R) atomicAdd(&dd.tally->n_repl, (unsigned long long)p.R);
+        if (p.q) atomicAdd(&dd.tally->n_iz, (unsigned long long)p.q);
+        st->iz_count = 0;
+        st->ion_lost = 0;
+        st->spill_flag = 0u;
+#pragma unroll
+        for (int sp = 0; sp < NSP; ++sp) st->rare_n[sp] = 0;
+        st->step = step + 1u;
+        if (avg) st->avg_steps += 1;
+    }
+    // every tally update of the block (births beyond the anode, the step's
+    // totals) is complete before the snapshot reads the tallies
+    __syncthreads();
+    const uint32_t nstep = step + 1u;
+    if (tid == 0 && dd.tally_period > 0 && nstep % (uint32_t)dd.tally_period == 0u) {
+        TallySnap &sn = dd.ring[(nstep / (uint32_t)dd.tally_period) % RING];
+        sn.step = nstep;
+        sn.t = *dd.tally;
+    }
+}
+
+// A tile's node bookkeeping and field: E from phi on the tile and its halo
+// (ph[k] = phi at node a0 - 1 + k), the step's deposits of the tile (hb) into
+// the last-step and summed histograms, H cleared, phi (and its sum).
+template <int HB>
+__device__ __forceinline__ void field_tile_out(const Diode &dd, const double *ph, unsigned long long (*hb)[HB],
+                                               int a0, int b0, int avg)
+{
+    const int N = dd.N, tid = threadIdx.x;
+    const int j = a0 + tid;
+    if (tid < HB && j < b0) {
+        const int k = tid + 1;
+        const double pc = ph[k];
+        double E;
+        if (j == 0) E = (pc - ph[k + 1]) / dd.dz;
+        else if (j == N) E = (ph[k - 1] - pc) / dd.dz;
+        else E = (ph[k - 1] - ph[k + 1]) * (1.0 / (2.0 * dd.dz));
+        glb(dd.phi)[j] = pc;
+        glb(dd.E)[j] = E;
+#pragma unroll
+        for (int s = 0; s < NSP; ++s) {
+            const unsigned long long hu = hb[s][tid];
+            if (hu >= DEPOSIT_LIMIT) atomicOr(&dd.st->err, ERR_RANGE);
+            glb(dd.Hlast[s])[j] = (long long)hu;
+            glb(dd.H[s])[j] = 0ull;
+            if (avg) glb(dd.Hsum[s])[j] += (long long)hu;
+        }
+        if (avg) glb(dd.phi_sum)[j] += pc;
+    }
 }
 
 __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, int mode, int parity)
@@ -2150,9 +1940,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     __shared__ long long sh64[FW];
     __shared__ I128 sh128[FW];
     __shared__ double ph[TILE + 2];                   // phi on the own tile and its halo
-    __shared__ RareTally rt, rs;
-    __shared__ DiodeState s_st;
-    __shared__ BirthPlan bp;
+    __shared__ FieldShared fs;
     const Diode &dd = D[blockIdx.y];
     DiodeState *st = dd.st;
     const int N = dd.N, nn = N + 1;
@@ -2167,14 +1955,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     // the counters and the particle kernel's tally copies; tile blocks load
     // every node's charge and their own tile's deposits meanwhile
     RareTally copy{};
-    if (mode == 0) {
-        if (tid < 64) copy = read_tally_copy(dd);
-        if (tid >= 64 && tid < 128) load_state(st, &s_st);
-        if (tid == 0) {
-            rare_tally_zero(&rt);
-            rare_tally_zero(&rs);
-        }
-    }
+    if (mode == 0) copy = field_step_reads(dd, fs);
     if (!records) {
         for (int j = tid; j < nn; j += FT) {
             long long r = 0;
@@ -2190,92 +1971,12 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     const uint32_t step = mode == 0 ? (uint32_t)uni((int)st->step) : 0u;
     __syncthreads();
     if (mode == 0) {
-        if (writer) {
-            fold_tally_copies(copy, &rt);     // the step's totals, applied by the writer
-        } else if (tid < 64) {
-            int v = copy.ion_lost;            // the others need the ions lost only
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (tid == 0) rt.ion_lost = v;
-        }
-        if (s_st.rare_n[SP_P] | s_st.rare_n[SP_E] | s_st.rare_n[SP_I]) {
-            // items the particle kernel's queues could not hold: the record
-            // block collides them (they may queue ionisations and lose ions),
-            // then raises the flag the other blocks wait for
-            if (records) {
-                if (tid == 0)
-                    atomicAdd(&dd.tally->rare_spill,
-                              (unsigned long long)(s_st.rare_n[SP_P] + s_st.rare_n[SP_E] + s_st.rare_n[SP_I]));
-                process_rare(dd, s_st.rare_n, parity, step, tid, FT, &rs);
-                __syncthreads();
-                if (tid == 0) {
-                    apply_tally(dd, rs);
-                    if (rs.ion_lost) atomicAdd(&st->ion_lost, rs.ion_lost);
-                    __threadfence();
-                    __hip_atomic_store(glb(&st->spill_flag), step + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                }
-            } else if (tid == 0) {
-                while (__hip_atomic_load(glb(&st->spill_flag), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) !=
-                       step + 1u)
-                    __builtin_amdgcn_s_sleep(2);
-            }
-            __syncthreads();
-            if (tid >= 64 && tid < 128) load_state(st, &s_st);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            // this block is done with the counters and the copies
-            if (!writer) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const DiodeState &S = s_st;
-            BirthPlan p;
-            p.q = min(S.iz_count, IZQ_CAP);
-            p.R = dd.replenish ? S.ion_lost + rt.ion_lost : 0;
-            p.ne = 0;
-            if (dd.emit_x > 0.0) {
-                const double fl = floor(dd.emit_x);
-                const uint4 be = philox(step, EV_EMIT, 0u, 0u, 0xFFFFFFFFu, dd.kseed);
-                p.ne = (int)fl + (u53(be.x, be.y) < dd.emit_x - fl ? 1 : 0);
-            }
-            p.id0 = S.next_id;
-            p.bP = S.n[SP_P];
-            p.bE = S.n[SP_E];
-            p.bI = S.n[SP_I];
-            // births that do not fit are dropped (and flagged by the writer)
-            p.okP = min(p.q + p.R, dd.cap[SP_P] - p.bP);
-            p.okE = min(p.ne, dd.cap[SP_E] - p.bE);
-            p.okI = min(p.q + p.R, dd.cap[SP_I] - p.bI);
-            // the parent-id order names the ionisation products (the record
-            // block) and, when some do not fit, decides which are dropped
-            p.sorted = p.q > 1 && (records || p.okP < p.q || p.okI < p.q);
-            bp = p;
-        }
-        __syncthreads();
-        if (bp.sorted) {
-            const int q = bp.q;
-            int np2 = 1;
-            while (np2 < q) np2 <<= 1;
-            for (int i = tid; i < np2; i += FT)
-                keys[i] = i < q ? ((unsigned long long)dd.izq[i].parent << 32) | (unsigned)i : ~0ull;
-            __syncthreads();
-            for (int k = 2; k <= np2; k <<= 1) {
-                for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                    for (int i = tid; i < np2; i += FT) {
-                        const int pi = i ^ jj;
-                        if (pi > i) {
-                            const unsigned long long u = keys[i], v = keys[pi];
-                            const bool up = (i & k) == 0;
-                            if ((u > v) == up) { keys[i] = v; keys[pi] = u; }
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-        }
+        field_step_plan(dd, parity, step, records, writer, copy, fs, keys);
         if (records) {
-            births_records(dd, bp, keys, step, parity);
+            births_records(dd, fs.bp, keys, step, parity);
             return;
         }
-        births_deposit(dd, bp, keys, writer, step, R, hb, a0, b0);
+        births_deposit<TILE>(dd, fs.bp, keys, writer, step, R, 0, nn, hb, a0, b0);
         __syncthreads();
     }
 
@@ -2318,65 +2019,158 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     __syncthreads();
     // the own tile: field, potential, deposits of the step and their sums
     const int avg = uni(__hip_atomic_load(glb(&st->avg_on), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    const int j = a0 + tid;
-    if (tid < TILE && j < b0) {
-        const int k = tid + 1;
-        const double pc = ph[k];
-        double E;
-        if (j == 0) E = (pc - ph[k + 1]) / dd.dz;
-        else if (j == N) E = (ph[k - 1] - pc) / dd.dz;
-        else E = (ph[k - 1] - ph[k + 1]) * (1.0 / (2.0 * dd.dz));
-        glb(dd.phi)[j] = pc;
-        glb(dd.E)[j] = E;
-#pragma unroll
-        for (int s = 0; s < NSP; ++s) {
-            const unsigned long long hu = hb[s][tid];
-            if (hu >= DEPOSIT_LIMIT) atomicOr(&st->err, ERR_RANGE);
-            glb(dd.Hlast[s])[j] = (long long)hu;
-            glb(dd.H[s])[j] = 0ull;
-            if (avg) glb(dd.Hsum[s])[j] += (long long)hu;
-        }
-        if (avg) glb(dd.phi_sum)[j] += pc;
-    }
+    field_tile_out<TILE>(dd, ph, hb, a0, b0, avg);
     if (mode != 0 || !writer) return;
     // the writer: once every other block of the diode (the other tiles and
     // the record block) has read the counters and copies, the step's tallies,
     // counters and snapshot
+    field_step_tail(dd, fs, step, avg, T);
+}
+
+// phi' at node j (see k_field_tiles) from the exact T_j.
+__device__ __forceinline__ double phi_prime(const Diode &dd, int j, const I128 &Tj)
+{
+    if (j <= 0) return 0.0;
+    return dd.V * (double)j / (double)dd.N - dd.alpha * to_double(Tj);
+}
+
+__global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D, int mode, int parity)
+{
+    __shared__ long long R[BIG_TILE];                 // the own tile's charge
+    __shared__ unsigned long long keys[IZQ_CAP];      // ionisation events by parent id
+    __shared__ unsigned long long hb[NSP][BIG_TILE];  // the own tile's deposits per species
+    __shared__ long long sh64[FW];
+    __shared__ I128 sh128[FW];
+    __shared__ double ph[BIG_TILE + 2];               // phi' on the own tile and its halo
+    __shared__ FieldShared fs;
+    __shared__ long long s_P;
+    __shared__ I128 s_Q;
+    __shared__ uint32_t s_epoch;
+    const Diode &dd = D[blockIdx.y];
+    DiodeState *st = dd.st;
+    const int N = dd.N, nn = N + 1;
+    const int T = (nn + BIG_TILE - 1) / BIG_TILE;
+    if ((int)blockIdx.x > T || (blockIdx.x == 0 && mode != 0)) return;
+    const bool records = blockIdx.x == 0;             // the newborn-record block
+    const int t = (int)blockIdx.x - 1;                // the tile of the others
+    const bool writer = t == T - 1;
+    const int a0 = t * BIG_TILE, b0 = min(nn, a0 + BIG_TILE);
+    const int tid = threadIdx.x;
+    const int j = a0 + tid;                           // this thread's node
+
+    RareTally copy{};
+    if (mode == 0) copy = field_step_reads(dd, fs);
+    if (tid == 0) s_epoch = __hip_atomic_load(glb(&st->field_epoch), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!records) {
+        long long r = 0;
+        if (j < b0) {
+            unsigned long long h[NSP];
+#pragma unroll
+            for (int s = 0; s < NSP; ++s) {
+                h[s] = glb(dd.H[s])[j];
+                hb[s][tid] = h[s];
+            }
+            if (j >= 1 && j <= N - 1) r = (long long)(h[SP_I] - h[SP_P] - h[SP_E]);
+        }
+        R[tid] = r;
+    }
+    const uint32_t step = mode == 0 ? (uint32_t)uni((int)st->step) : 0u;
+    __syncthreads();
+    const uint32_t epoch = s_epoch;
+    if (mode == 0) {
+        field_step_plan(dd, parity, step, records, writer, copy, fs, keys);
+        if (records) {
+            births_records(dd, fs.bp, keys, step, parity);
+            return;
+        }
+        births_deposit<BIG_TILE>(dd, fs.bp, keys, writer, step, R, a0, b0, hb, a0, b0);
+        __syncthreads();
+    } else if (tid == 0 && !writer) {
+        // done with the epoch: the writer advances it once every tile has read it
+        __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+
+    // the tile's aggregates: the in-tile inclusive prefix s1l of the charge,
+    // A = its total, B = its sum over the tile's interior nodes (128-bit)
+    const long long r = R[tid];
+    long long A;
+    const long long s1l = block_scan_excl_i64(r, sh64, A) + r;
+    const bool interior = j >= 1 && j <= N - 1 && j < b0;
+    I128 B;
+    const I128 tl = block_scan_excl_i128(interior ? i128(s1l) : i128(0), sh128, B);
+    const int nint = max(0, min(b0, N) - max(a0, 1));   // interior nodes of the tile
     if (tid == 0) {
-        while (__hip_atomic_load(glb(&st->arrive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < T)
+        FieldAgg g;
+        g.A = A;
+        g.B_lo = B.lo;
+        g.B_hi = B.hi;
+        g.n = nint;
+        g.pad = 0;
+        dd.agg[t] = g;
+        __threadfence();
+        __hip_atomic_store(glb(&dd.agg_flag[t]), epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid < 64) {
+        // the tiles before this one, one lane each: P_u = sum_{v<u} A_v, the
+        // sum of S1 over tile u's interior nodes n_u P_u + B_u, and their sums
+        const int u = tid;
+        long long Au = 0;
+        I128 Bu = i128(0);
+        int nu = 0;
+        if (u < t) {
+            while (__hip_atomic_load(glb(&dd.agg_flag[u]), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch + 1u)
+                __builtin_amdgcn_s_sleep(1);
+            const FieldAgg g = dd.agg[u];
+            Au = g.A;
+            Bu.lo = g.B_lo;
+            Bu.hi = g.B_hi;
+            nu = g.n;
+        }
+        const long long Pu = wave_incl_scan_i64(Au) - Au;
+        const I128 incl = wave_incl_scan_i128(add(mul_small(i128(Pu), (unsigned)nu), Bu));
+        if (u == 63) {
+            s_P = Pu + Au;      // S1 before the tile
+            s_Q = incl;         // T before the tile
+        }
+    }
+    __syncthreads();
+    const long long P = s_P;
+    const I128 Q = s_Q;
+    // exact T_j = Q + (interior nodes of the tile before j) P + tl
+    if (j < b0) {
+        const int cnt = max(0, min(j, N) - max(a0, 1));
+        ph[tid + 1] = phi_prime(dd, j, add(add(Q, mul_small(i128(P), (unsigned)cnt)), tl));
+    }
+    const I128 Tb = add(add(Q, mul_small(i128(P), (unsigned)nint)), B);     // T at node b0
+    if (tid == 0) {
+        // halo below: T_{a0-1} = Q - S1_{a0-1} if a0 - 1 is interior, S1_{a0-1} = P;
+        // halo above: T_{b0}
+        if (a0 >= 1) {
+            const int jm = a0 - 1;
+            ph[0] = phi_prime(dd, jm, (jm >= 1 && jm <= N - 1) ? add(Q, neg(i128(P))) : Q);
+        }
+        if (b0 <= N) ph[b0 - a0 + 1] = phi_prime(dd, b0, Tb);
+    }
+    __syncthreads();
+    const int avg = uni(__hip_atomic_load(glb(&st->avg_on), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    field_tile_out<BIG_TILE>(dd, ph, hb, a0, b0, avg);
+    if (!writer) return;
+    // the writer's tile ends at node N: T_N = Q + n P + B, c = alpha T_N / N
+    if (tid == 0) {
+        const I128 TN = add(add(Q, mul_small(i128(P), (unsigned)nint)), B);
+        const double c = dd.alpha / (double)N * to_double(TN);
+        st->phi_slope = c;
+        st->e_shift = -c / dd.dz;
+        if (avg) st->phi_slope_sum += c;
+    }
+    if (mode == 0) {
+        field_step_tail(dd, fs, step, avg, T);
+    } else if (tid == 0) {
+        while (__hip_atomic_load(glb(&st->arrive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < T - 1)
             __builtin_amdgcn_s_sleep(2);
         __hip_atomic_store(glb(&st->arrive), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    if (tid < 64) dd.tacc[tid].t = RareTally{};
-    if (tid == 0) {
-        const BirthPlan &p = bp;
-        if (p.okP < p.q + p.R || p.okE < p.ne || p.okI < p.q + p.R) atomicOr(&st->err, ERR_CAPACITY);
-        apply_tally(dd, rt);
-        st->n[SP_P] = p.bP + p.okP;
-        st->n[SP_E] = p.bE + p.okE;
-        st->n[SP_I] = p.bI + p.okI;
-        st->next_id = p.id0 + 2u * p.q + p.ne + 2u * p.R;
-        if (p.ne) atomicAdd(&dd.tally->n_emit, (unsigned long long)p.ne);
-        if (p.R) atomicAdd(&dd.tally->n_repl, (unsigned long long)p.R);
-        if (p.q) atomicAdd(&dd.tally->n_iz, (unsigned long long)p.q);
-        st->iz_count = 0;
-        st->ion_lost = 0;
-        st->spill_flag = 0u;
-#pragma unroll
-        for (int sp = 0; sp < NSP; ++sp) st->rare_n[sp] = 0;
-        st->step = step + 1u;
-        if (avg) st->avg_steps += 1;
-    }
-    // every tally update of the block (births beyond the anode, the step's
-    // totals) is complete before the snapshot reads the tallies
-    __syncthreads();
-    const uint32_t nstep = step + 1u;
-    if (tid == 0 && dd.tally_period > 0 && nstep % (uint32_t)dd.tally_period == 0u) {
-        TallySnap &sn = dd.ring[(nstep / (uint32_t)dd.tally_period) % RING];
-        sn.step = nstep;
-        sn.t = *dd.tally;
-    }
+    if (tid == 0) st->field_epoch = epoch + 1u;
 }
 
 }  // namespace pic
@@ -2425,29 +2219,26 @@ extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int n
 // Kernels picx_launch_sources_field enqueues for a step (timed graphs need it).
 extern "C" int picx_sources_field_kernels(int max_nodes, int mode)
 {
+    (void)max_nodes;
     (void)mode;
-    return max_nodes <= FUSED_MAX_NODES ? 1 : 2;
+    return 1;
 }
 
 // max_nodes: the largest N + 1 over the diodes.  Up to FUSED_MAX_NODES nodes
-// the sources and field are one kernel over the tiles of every diode
-// (k_field_step); above, where loading every node into every block costs more
-// than a second launch, the births beside the tile aggregates and the tiled
-// solve run as two kernels.
+// every tile block stages the whole grid's charge (k_field_step); above, the
+// tiles combine the aggregates of the tiles before them (k_field_tiles).
 
 extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, int nd, int mode, int max_nodes,
                                                 int parity, hipStream_t s)
 {
-    const size_t keys = (size_t)IZQ_CAP * 8;
+    (void)S;
     if (max_nodes <= FUSED_MAX_NODES) {
         const int tiles = (max_nodes + TILE - 1) / TILE;
         hipLaunchKernelGGL(k_field_step, dim3(tiles + 1, nd), dim3(FT), 0, s, D, mode, parity);
-        return hipGetLastError();
+    } else {
+        const int tiles = (max_nodes + BIG_TILE - 1) / BIG_TILE;
+        hipLaunchKernelGGL(k_field_tiles, dim3(tiles + 1, nd), dim3(FT), 0, s, D, mode, parity);
     }
-    const int tiles = (max_nodes + FT - 1) / FT;
-    const int births = mode == 0 ? 1 : 0;
-    hipLaunchKernelGGL(k_field_agg, dim3(tiles + births, nd), dim3(FT), births ? keys : 0, s, D, births, parity);
-    hipLaunchKernelGGL(k_field_solve, dim3(tiles, nd), dim3(FT), 0, s, D, S, mode, tiles);
     return hipGetLastError();
 }
 
