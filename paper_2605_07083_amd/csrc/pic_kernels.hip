@@ -25,10 +25,11 @@ constexpr int WMAX = 512;          // LDS window (nodes) of the field tile / his
 constexpr int QW_SLACK = 384;      // per-wave LDS queue of rare items: 64 PPT + QW_SLACK entries
 constexpr int DRIFT = 160;         // cells of drift since the last re-sort kept in the LDS window
 constexpr int BIN_SHIFT = 5;       // the re-sort orders particles by bins of 32 cells
-// The re-sort's window margin (bins) around a run's first and last bin: wide
-// enough for the fastest electrons of a period (a particle outside takes a
-// global counter atomic and four partial-line stores of its own); the LDS
-// counts hold up to WMAX + 1 bins.
+// The re-sort counts bins in LDS (up to WMAX + 1 of them: every bin of grids
+// up to 16416 cells).  On larger grids a run's window is its first and last
+// bin with this margin, wide enough for the fastest electrons of a period (a
+// particle outside takes a global counter atomic and four partial-line
+// stores of its own).
 constexpr int SORT_DRIFT_B = 64;
 
 __host__ __device__ constexpr int nbins_of(int N) { return ((N - 1) >> BIN_SHIFT) + 1; }
@@ -1172,11 +1173,19 @@ __device__ __forceinline__ int wave_group_rank(int key, AddFn add)
     return rank;
 }
 
-// Window of a run of chunks for the re-sort: bins of its first and last
-// particle plus the re-sort's drift margin (bins).
+// Window of a run of chunks for the re-sort: every bin of the grid when they
+// fit the LDS counts, else the bins of the run's first and last particle plus
+// the re-sort's drift margin.
 __device__ __forceinline__ void sort_window(const Diode &dd, const GBuf &b, int slot0, int last_slot, int &w0,
                                             int &wn)
 {
+    const int nb = nbins_of(dd.N);
+    if (nb <= WMAX + 1) {
+        // every bin of the grid fits the LDS counts (N <= 16416): nothing falls outside
+        w0 = 0;
+        wn = nb;
+        return;
+    }
     int ja, jb;
     double f;
     cic(b.z[slot0], dd.invdz, dd.N, ja, f);
