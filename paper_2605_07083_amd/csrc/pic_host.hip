@@ -1158,13 +1158,40 @@ int pic_autotune(pic_handle *h, int64_t trial_steps, int *ppt, int *grid, int *s
     double best = 1e300, ms;
     int rc;
     // full search over particles per thread, re-sort period and grid (the
-    // coordinate-wise search stalled in local optima), then graph replay
+    // coordinate-wise search stalled in local optima)
+    struct Cand {
+        int p, k, g;
+        double sum;
+        int n;
+    };
+    std::vector<Cand> cands;
     for (int p : {1, 2, 4})
         for (int k : {16, 32, 64, 128})
             for (int g : {2048, 4096, 8192, 16384}) {
                 if ((rc = timed(p, g, k, bu, ms))) return rc;
-                if (ms < best) { best = ms; bp = p; bk = k; bg = h->grid; }
+                cands.push_back(Cand{p, k, h->grid, ms, 1});
             }
+    // the best few again, twice each and interleaved (the run drifts between
+    // trials, and one trial's noise is a few per cent, as large as the
+    // differences between the best schedules): the lowest mean wins
+    std::stable_sort(cands.begin(), cands.end(), [](const Cand &x, const Cand &y) { return x.sum < y.sum; });
+    const size_t top = std::min<size_t>(4, cands.size());
+    for (int r = 0; r < 2; ++r)
+        for (size_t c = 0; c < top; ++c) {
+            if ((rc = timed(cands[c].p, cands[c].g, cands[c].k, bu, ms))) return rc;
+            cands[c].sum += ms;
+            cands[c].n += 1;
+        }
+    for (size_t c = 0; c < top; ++c) {
+        const double mean = cands[c].sum / cands[c].n;
+        if (mean < best) {
+            best = mean;
+            bp = cands[c].p;
+            bk = cands[c].k;
+            bg = cands[c].g;
+        }
+    }
+    // then graph replay on or off
     for (int u : {0, 1}) {
         if ((rc = timed(bp, bg, bk, u, ms))) return rc;
         if (ms < best * 0.999) { best = ms; bu = u; }

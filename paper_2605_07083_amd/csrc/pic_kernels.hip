@@ -13,8 +13,9 @@
 //                     and the field, tallies and snapshots (k_field_tiles on
 //                     grids above 4097 nodes).
 // Particles are processed in chunks of 256*PPT slots; the chunk list spans all
-// (diode, species) segments and is walked by a persistent grid whose
-// block -> chunk map keeps consecutive chunks on one XCD.
+// (diode, species) segments.  Each block of the particle kernel takes an equal
+// share of it, in an order that puts every segment's unsorted tail (the
+// particles born since the last re-sort) before the sorted bodies.
 #include "pic_internal.h"
 
 namespace pic {
@@ -285,23 +286,6 @@ __device__ void build_chunk_map(const DiodeState *__restrict__ S, int nd, int ch
     cm.total = uni(seg_end[nseg - 1]);
 }
 
-// Chunks [first, total) with stride, XCD-grouped when the grid is a multiple of 8:
-// block b runs on XCD b % 8 and walks that XCD's contiguous share of chunks.
-__device__ __forceinline__ void chunk_range(int total, int &first, int &end, int &stride)
-{
-    int G = gridDim.x, b = blockIdx.x;
-    if ((G & 7) == 0) {
-        int x = b & 7, l = b >> 3, per = (total + 7) >> 3;
-        first = x * per + l;
-        end = min(total, (x + 1) * per);
-        stride = G >> 3;
-    } else {
-        first = b;
-        end = total;
-        stride = G;
-    }
-}
-
 __device__ __forceinline__ int find_seg(const int *seg_end, int nseg, int c)
 {
     int lo = 0, hi = nseg - 1;
@@ -310,6 +294,57 @@ __device__ __forceinline__ int find_seg(const int *seg_end, int nseg, int c)
         if (seg_end[mid] > c) hi = mid; else lo = mid + 1;
     }
     return lo;
+}
+
+// Chunk order of the particle kernel: the tails of all segments first, then
+// their bodies.  A segment's body is its whole chunks below the count the
+// last re-sort left (n_new), ordered by bin; its tail is the rest, the
+// particles born since (plus the chunk that straddles n_new).  Newborns of
+// ionisation lie anywhere in the gap, so a tail run gathers and deposits
+// mostly outside its window and costs a block several times a body run: at
+// the head of the order such blocks start first and end inside the kernel,
+// not after it.  tail_end and body_end are inclusive prefix sums of the
+// segments' tail and body chunk counts.
+struct TailFirstMap {
+    int nseg;
+    int ntail;   // tail chunks of all segments
+    int total;
+};
+
+__device__ void build_tail_first_map(const DiodeState *__restrict__ S, int nd, int chunk, int *tail_end,
+                                     int *body_end, int *seg_n, TailFirstMap &cm)
+{
+    const int nseg = nd * NSP;
+    if (threadIdx.x < 64) {
+        int carry_t = 0, carry_b = 0;
+        for (int b0 = 0; b0 < nseg; b0 += 64) {
+            const int sidx = b0 + (int)threadIdx.x;
+            int ct = 0, cb = 0;
+            if (sidx < nseg) {
+                const DiodeState &st = S[sidx / NSP];
+                const int n = st.n[sidx % NSP];
+                const int ns = min(max(st.n_new[sidx % NSP], 0), n);
+                cb = ns / chunk;
+                ct = (n + chunk - 1) / chunk - cb;
+                seg_n[sidx] = n;
+            }
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(ct, o, 64), u = __shfl_up(cb, o, 64);
+                if ((int)threadIdx.x >= o) { ct += t; cb += u; }
+            }
+            if (sidx < nseg) {
+                tail_end[sidx] = ct + carry_t;
+                body_end[sidx] = cb + carry_b;
+            }
+            carry_t += __shfl(ct, 63, 64);
+            carry_b += __shfl(cb, 63, 64);
+        }
+    }
+    __syncthreads();
+    cm.nseg = nseg;
+    cm.ntail = uni(tail_end[nseg - 1]);
+    cm.total = cm.ntail + uni(body_end[nseg - 1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -640,8 +675,9 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                                                   int nd, int mode, int parity)
 {
     constexpr int CHUNK = NT * PPT;
-    extern __shared__ int seg_dyn[];    // seg_end, seg_n: NSP * nd each
-    int *seg_end = seg_dyn, *seg_n = seg_dyn + NSP * nd;
+    constexpr int RUN_CHUNKS = RUN_PARTICLES / CHUNK < 1 ? 1 : RUN_PARTICLES / CHUNK;   // chunks per run at most
+    extern __shared__ int seg_dyn[];    // tail_end, body_end, seg_n: NSP * nd each
+    int *tail_end = seg_dyn, *body_end = seg_dyn + NSP * nd, *seg_n = seg_dyn + 2 * NSP * nd;
     __shared__ double etile[WMAX + 2];
     __shared__ unsigned long long hist[WMAX + 2];
     constexpr int QW = 64 * PPT + QW_SLACK;
@@ -651,37 +687,55 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
     __shared__ RareTally rt;
 
     if (threadIdx.x == 0) rare_tally_zero(&rt);
-    ChunkMap cm;
-    build_chunk_map(S, nd, CHUNK, false, seg_end, cm, seg_n);
+    TailFirstMap cm;
+    build_tail_first_map(S, nd, CHUNK, tail_end, body_end, seg_n, cm);
     const int tid = threadIdx.x;
+    const int w = tid >> 6, lane = tid & 63;
     const int per_block = (cm.total + gridDim.x - 1) / gridDim.x;
-    const int c_begin = blockIdx.x * per_block;
-    const int c_end = min(cm.total, c_begin + per_block);
+    const int v_begin = blockIdx.x * per_block;
+    const int v_end = min(cm.total, v_begin + per_block);
 
-    for (int c = c_begin; c < c_end;) {
-        const int seg = uni(find_seg(seg_end, cm.nseg, c));
-        const int run_end = uni(min(min(c_end, seg_end[seg]), c + max(1, RUN_PARTICLES / CHUNK)));
-        const int segbase = uni(seg ? seg_end[seg - 1] : 0);
+    for (int v = v_begin; v < v_end;) {
+        // the run: chunks [p0, p0 + nrun) of one segment's tail or body
+        const bool tail = v < cm.ntail;
+        int seg, p0, avail;
+        if (tail) {
+            seg = uni(find_seg(tail_end, cm.nseg, v));
+            const int tb = seg ? tail_end[seg - 1] : 0;
+            p0 = uni(body_end[seg] - (seg ? body_end[seg - 1] : 0) + v - tb);
+            avail = uni(tail_end[seg] - v);
+        } else {
+            const int u = v - cm.ntail;
+            seg = uni(find_seg(body_end, cm.nseg, u));
+            p0 = uni(u - (seg ? body_end[seg - 1] : 0));
+            avail = uni(body_end[seg] - u);
+        }
+        const int nrun = uni(min(min(v_end - v, avail), RUN_CHUNKS));
         const int d = seg / NSP, s = seg - d * NSP;
         const Diode &dd = D[d];
         const GBuf b = gbuf(dd.buf[parity][s]);
         const int N = dd.N;
         const double invdz = dd.invdz;
         const int n = uni(seg_n[seg]);
-        const int slot0 = (c - segbase) * CHUNK;
+        const int slot0 = p0 * CHUNK;
 
         const uint32_t step = (uint32_t)uni((int)S[d].step);
         // the run's first chunk is loaded while the window and field tile are set up
         ChunkRegs<PPT> A, Bn;
         load_chunk<PPT>(A, b, slot0 + tid * PPT, mode);
-        // window of the run from its first and last particle
-        const int last_slot = min(n, (run_end - segbase) * CHUNK) - 1;
+        // window of the run from its first and last particle (scalar loads,
+        // in flight with the chunk); a hole (an absorbed particle, z < 0) at
+        // one end gives way to the other end
+        const int p_end = p0 + nrun;
         int w0, wn;
         {
+            double za = b.z[slot0], zb = b.z[min(n, p_end * CHUNK) - 1];
+            if (za < 0.0) za = zb;
+            if (zb < 0.0) zb = za;
             int ja, jb;
             double f;
-            cic(b.z[slot0], invdz, N, ja, f);
-            cic(b.z[max(last_slot, slot0)], invdz, N, jb, f);
+            cic(za, invdz, N, ja, f);
+            cic(zb, invdz, N, jb, f);
             // the re-sort orders by bins: the run spans whole bins between its ends
             const int ba = min(ja, jb) >> BIN_SHIFT, bb = max(ja, jb) >> BIN_SHIFT;
             w0 = uni(max(0, (ba << BIN_SHIFT) - DRIFT));
@@ -704,7 +758,6 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
         // whole block after the run.  A wave whose queue could overflow moves
         // its items to the species' list in global memory instead, which the
         // sources kernels work through.
-        const int w = tid >> 6, lane = tid & 63;
         GLB uint32_t *rare = glb(dd.rare[s]);
         int qn = 0;     // the wave's queue length (wave-uniform)
         // The z, v_z stores of a chunk are issued one iteration later, after the
@@ -714,7 +767,7 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
         double zs[PPT];
         float vs[PPT];
         int ts = -1;
-        for (int cc_ = c; cc_ < run_end; ++cc_) {
+        for (int pc = p0; pc < p_end; ++pc) {
             if (mode == 0 && qn > QW - 64 * PPT) {
                 int base = 0;
                 if (lane == 0)
@@ -724,8 +777,8 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
                 for (int q = lane; q < qn; q += 64) rare[base + q] = rq_i[w][q];
                 qn = 0;
             }
-            const int t0 = (cc_ - segbase) * CHUNK + tid * PPT;
-            if (cc_ + 1 < run_end) load_chunk<PPT>(Bn, b, t0 + CHUNK, mode);
+            const int t0 = pc * CHUNK + tid * PPT;
+            if (pc + 1 < p_end) load_chunk<PPT>(Bn, b, t0 + CHUNK, mode);
             if (mode == 0 && ts >= 0) {
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
@@ -870,7 +923,7 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
             }
         }
         lds_barrier();
-        c = run_end;
+        v += nrun;
     }
 }
 
@@ -2220,7 +2273,7 @@ extern "C" hipError_t picx_launch_profile_load(const Diode *D, const double *den
 extern "C" hipError_t picx_launch_particles(const Diode *D, DiodeState *S, int nd, int mode, int ppt, int grid,
                                             int parity, hipStream_t s)
 {
-    const size_t seg_bytes = sizeof(int) * 2 * NSP * nd;
+    const size_t seg_bytes = sizeof(int) * 3 * NSP * nd;
     PPT_DISPATCH(ppt, hipLaunchKernelGGL(k_particles<P_>, dim3(grid), dim3(NT), seg_bytes, s, D, S, nd, mode, parity));
     return hipGetLastError();
 }
