@@ -93,6 +93,10 @@ typedef struct pic_tally {
     int64_t rare_spill;           /* collision candidates and absorbed particles that the particle
                                      kernel's per-wave queues could not hold and handed to the
                                      sources kernel (a work-list counter, not physics) */
+    int64_t resorts;              /* cell re-sorts of the particle stores so far */
+    int64_t resorts_ions_kept;    /* of them, those that left the ions where they were (they move a
+                                     fraction of a cell per re-sort period; a schedule counter, not
+                                     physics) */
 } pic_tally;
 
 /* Boundary diagnostics over a window ("Benchmark cases", eqs. 1-10). */

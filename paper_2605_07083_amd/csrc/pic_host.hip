@@ -746,6 +746,8 @@ static void fill_tally(const pic_handle *h, int diode, const DiodeTally &t, pic_
     for (int k = 0; k < 2; ++k) out->cand[k] = (int64_t)t.cand[k];
     for (int k = 0; k < NCH; ++k) out->coll[k] = (int64_t)t.coll[k];
     out->rare_spill = (int64_t)t.rare_spill;
+    out->resorts = (int64_t)t.resorts;
+    out->resorts_ions_kept = (int64_t)t.resorts_ions_kept;
 }
 
 int pic_get_snapshot(pic_handle *h, int diode, int64_t step, pic_tally *out)
@@ -944,7 +946,7 @@ int pic_get_particles(pic_handle *h, int diode, int species, int64_t cap, int64_
     int rc = read_state(h, diode, st, t);
     if (rc) return rc;
     const int n = st.n[species];
-    const SpeciesBuf &b = h->hD[diode].buf[st.parity][species];
+    const SpeciesBuf &b = h->hD[diode].buf[st.parity ^ st.flip[species]][species];
     std::vector<double> hz(n);
     std::vector<float> hvz(n);
     std::vector<uint32_t> htc(n);
@@ -990,7 +992,7 @@ int pic_set_particles(pic_handle *h, int diode, int species, int64_t n, const do
     DiodeTally t;
     int rc = read_state(h, diode, st, t);
     if (rc) return rc;
-    const SpeciesBuf &b = h->hD[diode].buf[st.parity][species];
+    const SpeciesBuf &b = h->hD[diode].buf[st.parity ^ st.flip[species]][species];
     if (n > 0) {
         std::vector<ColdRec> hcold(n);
         for (int64_t i = 0; i < n; ++i) hcold[i] = ColdRec{vx[i], vy[i], id[i], 0u};
@@ -999,8 +1001,11 @@ int pic_set_particles(pic_handle *h, int diode, int species, int64_t n, const do
         HIP_TRY(hipMemcpy(b.tc, tc, n * sizeof(uint32_t), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(b.cold, hcold.data(), n * sizeof(ColdRec), hipMemcpyHostToDevice));
     }
-    int32_t nn = (int32_t)n;
+    // the slots are unsorted: all of them are the tail (n_new = 0), which the
+    // next re-sort sorts
+    const int32_t nn = (int32_t)n, zero = 0;
     HIP_TRY(hipMemcpy(&h->hD[diode].st->n[species], &nn, sizeof(nn), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(&h->hD[diode].st->n_new[species], &zero, sizeof(zero), hipMemcpyHostToDevice));
     int64_t live[NSP];
     live_counts(h, diode, t, live);
     h->live_offset[diode][species] += n - live[species];
@@ -1292,7 +1297,7 @@ int pic_steady_state(pic_handle *h, int diode, int block_tallies, double tol_pp,
 namespace {
 
 constexpr char CKPT_MAGIC[8] = {'P', 'I', 'C', 'C', 'K', 'P', 'T', '1'};
-constexpr uint32_t CKPT_VERSION = 3;
+constexpr uint32_t CKPT_VERSION = 4;
 
 struct CkptHeader {
     char magic[8];
@@ -1394,7 +1399,7 @@ int pic_save(pic_handle *h, void *host_buf, size_t bytes, size_t *written)
             (rc = xfer<true>(cur, D.phi_sum, nn * 8)))
             return rc;
         for (int s = 0; s < NSP; ++s) {
-            const SpeciesBuf &b = D.buf[st[d].parity][s];
+            const SpeciesBuf &b = D.buf[st[d].parity ^ st[d].flip[s]][s];
             const int32_t n = st[d].n[s];
             std::memcpy(cur, &n, sizeof(n));
             cur += sizeof(n);
@@ -1467,6 +1472,10 @@ int pic_load(pic_handle *h, const void *host_buf, size_t bytes)
         cc += sizeof(pic_config);
         DiodeState s0 = st[d];
         s0.parity = h->parity;   // the slots go into this handle's current buffer
+        for (int s = 0; s < NSP; ++s) {
+            s0.flip[s] = 0;
+            s0.keep[s] = 0;
+        }
         s0.arrive = 0;           // no field step is in flight at a step boundary
         s0.spill_flag = 0u;
         s0.field_epoch = 0u;     // with the tile flags cleared below

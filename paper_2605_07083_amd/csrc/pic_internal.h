@@ -82,6 +82,13 @@ struct DiodeState {
     int32_t arrive;        // field step: blocks that have read this step's counters
     uint32_t spill_flag;   // field step: step + 1 once the spilled rare items are done
     uint32_t field_epoch;  // large-grid field step: launches so far (tile aggregate flags are epoch + 1)
+    // Species s lives in buffer parity ^ flip[s]: a re-sort that keeps a
+    // species where it is (keep[s], decided by the re-sort's scan) flips the
+    // diode's parity but not the species' buffer, so it toggles flip[s].
+    int32_t flip[NSP];
+    int32_t keep[NSP];
+    uint32_t resorts;      // re-sorts so far
+    uint32_t pad;
     // Large-grid field step (zero on smaller grids): the stored phi and E
     // leave out phi_slope j and e_shift = -phi_slope / dz, the part of the
     // potential that needs every tile; phi_slope_sum is the slope's sum over
@@ -99,6 +106,8 @@ struct DiodeTally {
     unsigned long long cand[2];
     unsigned long long coll[NCH];
     unsigned long long rare_spill;   // rare items the particle kernel moved to the global lists
+    unsigned long long resorts;      // re-sorts
+    unsigned long long resorts_ions_kept;   // of them, those that left the ions in place
 };
 
 struct TallySnap {

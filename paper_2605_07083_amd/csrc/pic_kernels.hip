@@ -256,8 +256,28 @@ struct ChunkMap {
     int total;
 };
 
-__device__ void build_chunk_map(const DiodeState *__restrict__ S, int nd, int chunk, bool use_new,
-                                int *seg_end, ChunkMap &cm, int *seg_n = nullptr)
+// Whether a re-sort keeps species s where it is instead of sorting it.  The
+// ions move a small fraction of a cell in a re-sort period, so their order
+// barely ages: only every ION_SORT_EVERY-th re-sort sorts them, and any
+// re-sort does when the tail born since they were last sorted has grown past
+// 1/16 of them (a store the host has just written has n_new = 0, all tail) or
+// when the free capacity is short (a sort drops the absorbed particles'
+// holes).  Decided from the counters as they stand before the re-sort.
+constexpr uint32_t ION_SORT_EVERY = 4;
+__device__ __forceinline__ bool sort_keeps(const Diode &dd, const DiodeState &st, int s)
+{
+    if (s != SP_I || st.resorts % ION_SORT_EVERY == 0u) return false;
+    const int n = st.n[s], ns = min(max(st.n_new[s], 0), n), tail = n - ns, cap = dd.cap[s];
+    return tail <= n / 16 && cap - n >= max(2 * tail, cap / 16);
+}
+
+// Segments of the chunk map: every one (SEGS_ALL), those the re-sort sorts,
+// judged from the counters before it (SEGS_SORT_PRE: the count pass, before
+// the scan has stored the decision), or as the scan stored it (SEGS_SORT).
+enum SegSel { SEGS_ALL, SEGS_SORT_PRE, SEGS_SORT };
+
+__device__ void build_chunk_map(const Diode *__restrict__ D, const DiodeState *__restrict__ S, int nd, int chunk,
+                                SegSel sel, int *seg_end, ChunkMap &cm, int *seg_n = nullptr)
 {
     int nseg = nd * NSP;
     if (threadIdx.x < 64) {
@@ -267,8 +287,12 @@ __device__ void build_chunk_map(const DiodeState *__restrict__ S, int nd, int ch
             int c = 0;
             if (sidx < nseg) {
                 const DiodeState &st = S[sidx / NSP];
-                int n = use_new ? st.n_new[sidx % NSP] : st.n[sidx % NSP];
-                c = (n + chunk - 1) / chunk;
+                const int sp = sidx % NSP;
+                const int n = st.n[sp];
+                const bool kept = sel == SEGS_SORT_PRE ? sort_keeps(D[sidx / NSP], st, sp)
+                                  : sel == SEGS_SORT   ? st.keep[sp] != 0
+                                                       : false;
+                c = kept ? 0 : (n + chunk - 1) / chunk;
                 if (seg_n) seg_n[sidx] = n;
             }
             // inclusive wave scan
@@ -535,13 +559,13 @@ __device__ __forceinline__ void rare_absorbed(const Diode &dd, int s, const GBuf
 // The step's rare items of one diode (all species): collisions of candidates,
 // tallies of absorbed particles, into the block's LDS tally.  Items
 // [first, n) with stride `stride` of each list.
-__device__ __forceinline__ void process_rare(const Diode &dd, const int *rare_n, int parity, uint32_t step,
-                                             int first, int stride, RareTally *rt)
+__device__ __forceinline__ void process_rare(const Diode &dd, const int *rare_n, const int *flip, int parity,
+                                             uint32_t step, int first, int stride, RareTally *rt)
 {
 #pragma unroll 1
     for (int s = 0; s < NSP; ++s) {
         const int n = rare_n[s];
-        const GBuf b = gbuf(dd.buf[parity][s]);
+        const GBuf b = gbuf(dd.buf[parity ^ flip[s]][s]);
         for (int k = first; k < n; k += stride) {
             const uint32_t item = dd.rare[s][k];
             const int i = (int)(item & RARE_MASK);
@@ -713,7 +737,7 @@ __global__ __launch_bounds__(NT, PIC_PARTICLE_MIN_WAVES) void k_particles(const 
         const int nrun = uni(min(min(v_end - v, avail), RUN_CHUNKS));
         const int d = seg / NSP, s = seg - d * NSP;
         const Diode &dd = D[d];
-        const GBuf b = gbuf(dd.buf[parity][s]);
+        const GBuf b = gbuf(dd.buf[parity ^ uni(S[d].flip[s])][s]);
         const int N = dd.N;
         const double invdz = dd.invdz;
         const int n = uni(seg_n[seg]);
@@ -1163,7 +1187,7 @@ __global__ __launch_bounds__(256) void k_phase_hist(const Diode *__restrict__ D,
     const int W = nv + 2, nb = nz * W, tid = threadIdx.x;
     for (int i = tid; i < nb; i += 256) ph_hist[i] = 0u;
     const Diode &dd = D[d];
-    const GBuf b = gbuf(dd.buf[parity][s]);
+    const GBuf b = gbuf(dd.buf[parity ^ S[d].flip[s]][s]);
     const int n = S[d].n[s];
     const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
     const int i0 = (int)blockIdx.x * per, i1 = min(n, i0 + per);
@@ -1260,7 +1284,7 @@ __global__ __launch_bounds__(NT) void k_sort_count(const Diode *__restrict__ D, 
     __shared__ int seg_n[NSP * MAX_DIODES];
     __shared__ int cnt[WMAX + 2];
     ChunkMap cm;
-    build_chunk_map(S, nd, CHUNK, false, seg_end, cm, seg_n);
+    build_chunk_map(D, S, nd, CHUNK, SEGS_SORT_PRE, seg_end, cm, seg_n);
     const int tid = threadIdx.x;
     const int per_block = (cm.total + gridDim.x - 1) / gridDim.x;
     const int c_begin = blockIdx.x * per_block;
@@ -1271,7 +1295,7 @@ __global__ __launch_bounds__(NT) void k_sort_count(const Diode *__restrict__ D, 
         const int segbase = seg ? seg_end[seg - 1] : 0;
         const int d = seg / NSP, s = seg - d * NSP;
         const Diode &dd = D[d];
-        const GBuf b = gbuf(dd.buf[parity][s]);
+        const GBuf b = gbuf(dd.buf[parity ^ S[d].flip[s]][s]);
         const int n = seg_n[seg];
         const int slot0 = (c - segbase) * CHUNK;
         int w0, wn;
@@ -1323,6 +1347,11 @@ __global__ __launch_bounds__(1024) void k_sort_scan(const Diode *__restrict__ D)
     __shared__ int part[1024];
     const int d = blockIdx.x / NSP, s = blockIdx.x % NSP;
     const Diode &dd = D[d];
+    // the decision of the count pass, from the same counters, stored for the
+    // scatter and the finalize (this block writes n_new[s] below)
+    const bool kept = sort_keeps(dd, *dd.st, s);
+    if (threadIdx.x == 0) dd.st->keep[s] = kept ? 1 : 0;
+    if (kept) return;
     const int N = nbins_of(dd.N);
     int *cc = dd.cell_cnt[s];
     const int per = (N + 1023) / 1024;
@@ -1365,7 +1394,7 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
     __shared__ int seg_n[NSP * MAX_DIODES];
     __shared__ int cur[WMAX + 2];       // the run's count per window bin, then its next free slot
     ChunkMap cm;
-    build_chunk_map(S, nd, CHUNK, false, seg_end, cm, seg_n);
+    build_chunk_map(D, S, nd, CHUNK, SEGS_SORT, seg_end, cm, seg_n);
     const int tid = threadIdx.x;
     const int per_block = (cm.total + gridDim.x - 1) / gridDim.x;
     const int c_begin = blockIdx.x * per_block;
@@ -1376,8 +1405,9 @@ __global__ __launch_bounds__(NT) void k_sort_scatter(const Diode *__restrict__ D
         const int segbase = seg ? seg_end[seg - 1] : 0;
         const int d = seg / NSP, s = seg - d * NSP;
         const Diode &dd = D[d];
-        const GBuf src = gbuf(dd.buf[parity][s]);
-        const GBuf dst = gbuf(dd.buf[parity ^ 1][s]);
+        const int bsel = parity ^ S[d].flip[s];
+        const GBuf src = gbuf(dd.buf[bsel][s]);
+        const GBuf dst = gbuf(dd.buf[bsel ^ 1][s]);
         const int n = seg_n[seg];
         const int slot0 = (c - segbase) * CHUNK;
         const int slot_end = min(n, (run_end - segbase) * CHUNK);
@@ -1480,8 +1510,16 @@ __global__ __launch_bounds__(256) void k_sort_finalize(const Diode *__restrict__
         for (int j = threadIdx.x; j < dd.N; j += 256) cc[j] = 0;
     }
     if (threadIdx.x == 0) {
-        for (int s = 0; s < NSP; ++s) dd.st->n[s] = dd.st->n_new[s];
-        dd.st->parity ^= 1;
+        DiodeState *st = dd.st;
+        dd.tally->resorts += 1ull;
+        if (st->keep[SP_I]) dd.tally->resorts_ions_kept += 1ull;
+        for (int s = 0; s < NSP; ++s) {
+            if (st->keep[s]) st->flip[s] ^= 1;    // left in place: its buffer is now parity ^ 1 ^ flip
+            else st->n[s] = st->n_new[s];
+            st->keep[s] = 0;
+        }
+        st->parity ^= 1;
+        st->resorts += 1u;
     }
 }
 
@@ -1739,10 +1777,11 @@ __device__ __forceinline__ void births_deposit(const Diode &dd, const BirthPlan 
 // The newborn records (positions as births_deposit, velocities, ids and
 // first free flights), one thread per newborn (pair).
 __device__ __forceinline__ void births_records(const Diode &dd, const BirthPlan &bp, const unsigned long long *keys,
-                                               uint32_t step, int parity)
+                                               uint32_t step, int parity, const int *flip)
 {
     const int q = bp.q, ne = bp.ne, total = q + ne + bp.R;
-    const GBuf bP = gbuf(dd.buf[parity][SP_P]), bE = gbuf(dd.buf[parity][SP_E]), bI = gbuf(dd.buf[parity][SP_I]);
+    const GBuf bP = gbuf(dd.buf[parity ^ flip[SP_P]][SP_P]), bE = gbuf(dd.buf[parity ^ flip[SP_E]][SP_E]),
+               bI = gbuf(dd.buf[parity ^ flip[SP_I]][SP_I]);
     for (int x = threadIdx.x; x < total; x += FT) {
         if (x < q) {
             const int r = x;
@@ -1854,7 +1893,7 @@ __device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, bool
             if (tid == 0)
                 atomicAdd(&dd.tally->rare_spill,
                           (unsigned long long)(fs.s_st.rare_n[SP_P] + fs.s_st.rare_n[SP_E] + fs.s_st.rare_n[SP_I]));
-            process_rare(dd, fs.s_st.rare_n, parity, step, tid, FT, &fs.rs);
+            process_rare(dd, fs.s_st.rare_n, fs.s_st.flip, parity, step, tid, FT, &fs.rs);
             __syncthreads();
             if (tid == 0) {
                 apply_tally(dd, fs.rs);
@@ -2035,7 +2074,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     if (mode == 0) {
         field_step_plan(dd, parity, step, records, writer, copy, fs, keys);
         if (records) {
-            births_records(dd, fs.bp, keys, step, parity);
+            births_records(dd, fs.bp, keys, step, parity, fs.s_st.flip);
             return;
         }
         births_deposit<TILE>(dd, fs.bp, keys, writer, step, R, 0, nn, hb, a0, b0);
@@ -2142,7 +2181,7 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     if (mode == 0) {
         field_step_plan(dd, parity, step, records, writer, copy, fs, keys);
         if (records) {
-            births_records(dd, fs.bp, keys, step, parity);
+            births_records(dd, fs.bp, keys, step, parity, fs.s_st.flip);
             return;
         }
         births_deposit<BIG_TILE>(dd, fs.bp, keys, writer, step, R, a0, b0, hb, a0, b0);

@@ -36,7 +36,8 @@ class PicTally(C.Structure):
     _fields_ = [("step", C.c_int64), ("n_live", C.c_int64 * 3), ("abs_count", (C.c_int64 * 2) * 3),
                 ("abs_energy", (C.c_double * 2) * 3), ("n_emit", C.c_int64), ("n_repl", C.c_int64),
                 ("n_iz", C.c_int64), ("cand", C.c_int64 * 2), ("coll", C.c_int64 * 5),
-                ("next_id", C.c_uint32), ("err_bits", C.c_uint32), ("rare_spill", C.c_int64)]
+                ("next_id", C.c_uint32), ("err_bits", C.c_uint32), ("rare_spill", C.c_int64),
+                ("resorts", C.c_int64), ("resorts_ions_kept", C.c_int64)]
 
 
 _DIAG_SCALARS = ("gamma_emit", "gamma_emit_meas", "gamma_ref", "gamma_net", "gamma_anode",
@@ -198,7 +199,8 @@ def _tally_dict(t):
             "abs_energy": np.array([[t.abs_energy[s][w] for w in range(2)] for s in range(3)]),
             "n_emit": t.n_emit, "n_repl": t.n_repl, "n_iz": t.n_iz,
             "cand": np.array(list(t.cand)), "coll": np.array(list(t.coll)),
-            "next_id": t.next_id, "err_bits": t.err_bits, "rare_spill": t.rare_spill}
+            "next_id": t.next_id, "err_bits": t.err_bits, "rare_spill": t.rare_spill,
+            "resorts": t.resorts, "resorts_ions_kept": t.resorts_ions_kept}
 
 
 class Handle:

@@ -15,6 +15,9 @@ reach, and the library's error reporting, through the C ABI.
   and the live timing covers them.
 * The steady-state verdict on the device ring equals the host criterion on
   the same snapshots.
+* Re-sorts that leave the ions in their buffer while the diode's buffer
+  parity flips: restart parity through them, phase-space counts and a
+  checkpoint read through the kept buffer.
 * Error reporting: the null-collision bound, non-finite particle input, a
   node deposit reaching 2^53.
 """
@@ -181,6 +184,47 @@ def test_steady_verdict_matches_series(pic):
             assert dev["backflow_pct"] == pytest.approx(ref["backflow_pct"], rel=1e-12, abs=1e-12)
         assert dev["last_backflow_pct"] == pytest.approx(br[-1], rel=1e-12, abs=1e-12)
     assert seen == {True, False}, "the tolerances should give both verdicts"
+
+
+def test_ions_kept_in_place_across_resorts(pic, O):
+    """The ions move a small fraction of a cell per re-sort period, so most
+    re-sorts leave them in their buffer (the diode's parity flips, the
+    ions' buffer does not) with the ions born since appended to their tail.
+    Restart parity runs through kept and sorting re-sorts; the phase-space
+    counts and a checkpoint taken while the ions sit in the other buffer than
+    the electrons read them from there."""
+    cfg = presets.scaled(presets.tiny(), gamma_emit=1e21, Te0=10.0, ng=3.2e22)
+    _say("case: ions kept in place across re-sorts, re-sort every 8 steps")
+    h = pic.Handle(cfg)
+    h.set_tuning(sort_period=8, use_graph=0)
+    h.step(12)
+    t0 = h.tally()
+    _say("  after 12 steps: %d re-sorts, %d kept the ions; live %s"
+         % (t0["resorts"], t0["resorts_ions_kept"], t0["n_live"].tolist()))
+    assert t0["resorts"] >= 2 and t0["resorts_ions_kept"] >= 1
+    out = h.phase_space(0, 2, 16, 40, -3e4, 3e4)
+    h.sync()
+    p = h.particles(0, 2)
+    assert np.array_equal(out.cpu().numpy(), O.phase_space(p["z"], p["vz"], cfg["L"], 16, 40, -3e4, 3e4))
+    img = h.save()
+    probs = restart_step_check(O, cfg, h, 30)
+    assert probs == [], "\n".join(probs[:20])
+    t1 = h.tally()
+    kept = t1["resorts_ions_kept"] - t0["resorts_ions_kept"]
+    _say("  30 more steps: %d re-sorts, %d kept the ions; %d ionisations"
+         % (t1["resorts"] - t0["resorts"], kept, t1["n_iz"] - t0["n_iz"]))
+    assert kept >= 1 and t1["resorts"] - t0["resorts"] - kept >= 1 and t1["n_iz"] > t0["n_iz"]
+    b = pic.Handle(cfg)
+    b.set_tuning(sort_period=8, use_graph=0)
+    b.load(img)
+    b.step(30)
+    ta, tb = h.tally(), b.tally()
+    assert ta["step"] == tb["step"] and np.array_equal(ta["n_live"], tb["n_live"])
+    for sp in range(3):
+        pa, pb = by_id(h.particles(0, sp)), by_id(b.particles(0, sp))
+        for k in ("id", "z", "vx", "vy", "vz", "tc"):
+            assert np.array_equal(pa[k], pb[k]), (sp, k)
+    assert np.array_equal(h.fields(0)["phi"], b.fields(0)["phi"])
 
 
 def test_nullcoll_bound_reported(pic, O):
