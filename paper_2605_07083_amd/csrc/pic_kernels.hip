@@ -1572,14 +1572,6 @@ __device__ __forceinline__ double to_double(I128 a)
     return negv ? -m : m;
 }
 
-__device__ __forceinline__ I128 shfl_up_i128(I128 a, int o)
-{
-    I128 r;
-    r.lo = __shfl_up(a.lo, o, 64);
-    r.hi = __shfl_up(a.hi, o, 64);
-    return r;
-}
-
 __device__ void write_particle(const GBuf &b, int i, double z, float vx, float vy, float vz, uint32_t id,
                                uint32_t tc)
 {
@@ -1587,25 +1579,51 @@ __device__ void write_particle(const GBuf &b, int i, double z, float vx, float v
     put_cold(&b.cold[i], vx, vy, id);
 }
 
+// Inclusive wave scans with DPP moves (ALU-latency lane exchanges, where a
+// shuffle goes through the LDS crossbar and waits for it): shifts by 1, 2, 4
+// and 8 lanes within each row of 16 (zero entering from the row's start),
+// then the row totals broadcast from lane 15 into rows 1 and 3 and from lane
+// 31 into rows 2 and 3.  Every lane of the wave must be active.
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROWS, 0xf, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROWS, 0xf, true);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ I128 dpp_i128(I128 v)
+{
+    I128 r;
+    r.lo = dpp_u64<CTRL, ROWS>(v.lo);
+    r.hi = (long long)dpp_u64<CTRL, ROWS>((unsigned long long)v.hi);
+    return r;
+}
+
 __device__ __forceinline__ long long wave_incl_scan_i64(long long x)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const long long y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    return x;
+    unsigned long long u = (unsigned long long)x;    // two's complement: the sums wrap as int64's do
+    u += dpp_u64<DPP_ROW_SHR1, 0xf>(u);
+    u += dpp_u64<DPP_ROW_SHR2, 0xf>(u);
+    u += dpp_u64<DPP_ROW_SHR4, 0xf>(u);
+    u += dpp_u64<DPP_ROW_SHR8, 0xf>(u);
+    u += dpp_u64<DPP_ROW_BCAST15, 0xa>(u);
+    u += dpp_u64<DPP_ROW_BCAST31, 0xc>(u);
+    return (long long)u;
 }
 
 __device__ __forceinline__ I128 wave_incl_scan_i128(I128 x)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const I128 y = shfl_up_i128(x, o);
-        if (lane >= o) x = add(x, y);
-    }
+    x = add(x, dpp_i128<DPP_ROW_SHR1, 0xf>(x));
+    x = add(x, dpp_i128<DPP_ROW_SHR2, 0xf>(x));
+    x = add(x, dpp_i128<DPP_ROW_SHR4, 0xf>(x));
+    x = add(x, dpp_i128<DPP_ROW_SHR8, 0xf>(x));
+    x = add(x, dpp_i128<DPP_ROW_BCAST15, 0xa>(x));
+    x = add(x, dpp_i128<DPP_ROW_BCAST31, 0xc>(x));
     return x;
 }
 
@@ -2003,33 +2021,65 @@ __device__ void field_step_tail(const Diode &dd, FieldShared &fs, uint32_t step,
     }
 }
 
+// What a tile's potential and output need of the diode, copied into LDS by
+// one thread at the start of a field block: read later, after the look-back's
+// acquire loads (which invalidate the caches), each of these fields would
+// cost a round trip to memory.
+struct TileConsts {
+    double V, alpha, dz;
+    int N;
+    double *phi, *E, *phi_sum;
+    unsigned long long *H[NSP];
+    long long *Hlast[NSP], *Hsum[NSP];
+    uint32_t *err;
+};
+
+__device__ __forceinline__ void tile_consts(const Diode &dd, TileConsts &fc)
+{
+    fc.V = dd.V;
+    fc.alpha = dd.alpha;
+    fc.dz = dd.dz;
+    fc.N = dd.N;
+    fc.phi = dd.phi;
+    fc.E = dd.E;
+    fc.phi_sum = dd.phi_sum;
+#pragma unroll
+    for (int s = 0; s < NSP; ++s) {
+        fc.H[s] = dd.H[s];
+        fc.Hlast[s] = dd.Hlast[s];
+        fc.Hsum[s] = dd.Hsum[s];
+    }
+    fc.err = &dd.st->err;
+}
+
 // A tile's node bookkeeping and field: E from phi on the tile and its halo
 // (ph[k] = phi at node a0 - 1 + k), the step's deposits of the tile (hb) into
 // the last-step and summed histograms, H cleared, phi (and its sum).
 template <int HB>
-__device__ __forceinline__ void field_tile_out(const Diode &dd, const double *ph, unsigned long long (*hb)[HB],
+__device__ __forceinline__ void field_tile_out(const TileConsts &fc, const double *ph, unsigned long long (*hb)[HB],
                                                int a0, int b0, int avg)
 {
-    const int N = dd.N, tid = threadIdx.x;
+    const int N = fc.N, tid = threadIdx.x;
     const int j = a0 + tid;
     if (tid < HB && j < b0) {
         const int k = tid + 1;
         const double pc = ph[k];
+        const double dz = fc.dz;
         double E;
-        if (j == 0) E = (pc - ph[k + 1]) / dd.dz;
-        else if (j == N) E = (ph[k - 1] - pc) / dd.dz;
-        else E = (ph[k - 1] - ph[k + 1]) * (1.0 / (2.0 * dd.dz));
-        glb(dd.phi)[j] = pc;
-        glb(dd.E)[j] = E;
+        if (j == 0) E = (pc - ph[k + 1]) / dz;
+        else if (j == N) E = (ph[k - 1] - pc) / dz;
+        else E = (ph[k - 1] - ph[k + 1]) * (1.0 / (2.0 * dz));
+        glb(fc.phi)[j] = pc;
+        glb(fc.E)[j] = E;
 #pragma unroll
         for (int s = 0; s < NSP; ++s) {
             const unsigned long long hu = hb[s][tid];
-            if (hu >= DEPOSIT_LIMIT) atomicOr(&dd.st->err, ERR_RANGE);
-            glb(dd.Hlast[s])[j] = (long long)hu;
-            glb(dd.H[s])[j] = 0ull;
-            if (avg) glb(dd.Hsum[s])[j] += (long long)hu;
+            if (hu >= DEPOSIT_LIMIT) atomicOr(fc.err, ERR_RANGE);
+            glb(fc.Hlast[s])[j] = (long long)hu;
+            glb(fc.H[s])[j] = 0ull;
+            if (avg) glb(fc.Hsum[s])[j] += (long long)hu;
         }
-        if (avg) glb(dd.phi_sum)[j] += pc;
+        if (avg) glb(fc.phi_sum)[j] += pc;
     }
 }
 
@@ -2042,6 +2092,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     __shared__ I128 sh128[FW];
     __shared__ double ph[TILE + 2];                   // phi on the own tile and its halo
     __shared__ FieldShared fs;
+    __shared__ TileConsts fc;
     const Diode &dd = D[blockIdx.y];
     DiodeState *st = dd.st;
     const int N = dd.N, nn = N + 1;
@@ -2057,6 +2108,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     // every node's charge and their own tile's deposits meanwhile
     RareTally copy{};
     if (mode == 0) copy = field_step_reads(dd, fs);
+    if (tid == 128) tile_consts(dd, fc);
     if (!records) {
         for (int j = tid; j < nn; j += FT) {
             long long r = 0;
@@ -2120,7 +2172,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     __syncthreads();
     // the own tile: field, potential, deposits of the step and their sums
     const int avg = uni(__hip_atomic_load(glb(&st->avg_on), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    field_tile_out<TILE>(dd, ph, hb, a0, b0, avg);
+    field_tile_out<TILE>(fc, ph, hb, a0, b0, avg);
     if (mode != 0 || !writer) return;
     // the writer: once every other block of the diode (the other tiles and
     // the record block) has read the counters and copies, the step's tallies,
@@ -2129,10 +2181,10 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
 }
 
 // phi' at node j (see k_field_tiles) from the exact T_j.
-__device__ __forceinline__ double phi_prime(const Diode &dd, int j, const I128 &Tj)
+__device__ __forceinline__ double phi_prime(const TileConsts &fc, int j, const I128 &Tj)
 {
     if (j <= 0) return 0.0;
-    return dd.V * (double)j / (double)dd.N - dd.alpha * to_double(Tj);
+    return fc.V * (double)j / (double)fc.N - fc.alpha * to_double(Tj);
 }
 
 __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D, int mode, int parity)
@@ -2140,13 +2192,16 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     __shared__ long long R[BIG_TILE];                 // the own tile's charge
     __shared__ unsigned long long keys[IZQ_CAP];      // ionisation events by parent id
     __shared__ unsigned long long hb[NSP][BIG_TILE];  // the own tile's deposits per species
-    __shared__ long long sh64[FW];
-    __shared__ I128 sh128[FW];
+    __shared__ long long w_A[FW];                     // per wave: sum of R,
+    __shared__ I128 w_C[FW];                          //   sum of the wave-local S1 over interior nodes,
+    __shared__ int w_n[FW];                           //   interior nodes
     __shared__ double ph[BIG_TILE + 2];               // phi' on the own tile and its halo
     __shared__ FieldShared fs;
     __shared__ long long s_P;
     __shared__ I128 s_Q;
     __shared__ uint32_t s_epoch;
+    __shared__ int s_avg;
+    __shared__ TileConsts fc;
     const Diode &dd = D[blockIdx.y];
     DiodeState *st = dd.st;
     const int N = dd.N, nn = N + 1;
@@ -2161,7 +2216,11 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
 
     RareTally copy{};
     if (mode == 0) copy = field_step_reads(dd, fs);
+    // the launch's epoch and whether the step is averaged (the host sets
+    // avg_on between steps), read with the counters at the start
     if (tid == 0) s_epoch = __hip_atomic_load(glb(&st->field_epoch), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 1) s_avg = __hip_atomic_load(glb(&st->avg_on), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 128) tile_consts(dd, fc);
     if (!records) {
         long long r = 0;
         if (j < b0) {
@@ -2178,6 +2237,7 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     const uint32_t step = mode == 0 ? (uint32_t)uni((int)st->step) : 0u;
     __syncthreads();
     const uint32_t epoch = s_epoch;
+    const int avg = uni(s_avg);
     if (mode == 0) {
         field_step_plan(dd, parity, step, records, writer, copy, fs, keys);
         if (records) {
@@ -2186,19 +2246,48 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
         }
         births_deposit<BIG_TILE>(dd, fs.bp, keys, writer, step, R, a0, b0, hb, a0, b0);
         __syncthreads();
+        // the writer's tallies and counters need only the births: done here,
+        // while the scans and the other tiles' flags are still to come
+        if (writer) field_step_tail(dd, fs, step, avg, T);
     } else if (tid == 0 && !writer) {
         // done with the epoch: the writer advances it once every tile has read it
         __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
-    // the tile's aggregates: the in-tile inclusive prefix s1l of the charge,
-    // A = its total, B = its sum over the tile's interior nodes (128-bit)
+    // The tile's aggregates with one barrier: per wave, the inclusive prefix
+    // a of the charge and the exclusive prefix c of a over the interior nodes;
+    // then each thread combines the totals of the waves before its own.  With
+    // P_w the charge of the earlier waves and Q_w their sum of S1 over
+    // interior nodes (sum over each earlier wave of C + n P), the in-tile
+    // prefix of the charge at j is s1l = P_w + a and the in-tile exclusive
+    // sum of s1l over the interior nodes before j is tl = Q_w + cnt P_w + c.
+    // A = the tile's charge, B = its sum of s1l over its interior nodes.
     const long long r = R[tid];
-    long long A;
-    const long long s1l = block_scan_excl_i64(r, sh64, A) + r;
     const bool interior = j >= 1 && j <= N - 1 && j < b0;
-    I128 B;
-    const I128 tl = block_scan_excl_i128(interior ? i128(s1l) : i128(0), sh128, B);
+    const int lane = tid & 63, wv = tid >> 6;
+    const long long a = wave_incl_scan_i64(r);
+    const I128 ci = interior ? i128(a) : i128(0);
+    const I128 c = add(wave_incl_scan_i128(ci), neg(ci));
+    const unsigned long long im = __ballot(interior);
+    const int cw = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(im >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)im, 0u));
+    if (lane == 63) {
+        w_A[wv] = a;
+        w_C[wv] = add(c, ci);
+        w_n[wv] = cw + (interior ? 1 : 0);
+    }
+    __syncthreads();
+    long long Pw = 0, A = 0;
+    I128 Qw = i128(0), B = i128(0);
+#pragma unroll
+    for (int q = 0; q < FW; ++q) {
+        if (q == wv) {
+            Pw = A;
+            Qw = B;
+        }
+        B = add(B, add(w_C[q], mul_small(i128(A), (unsigned)w_n[q])));
+        A += w_A[q];
+    }
+    const I128 tl = add(add(Qw, mul_small(i128(Pw), (unsigned)cw)), c);
     const int nint = max(0, min(b0, N) - max(a0, 1));   // interior nodes of the tile
     if (tid == 0) {
         FieldAgg g;
@@ -2240,33 +2329,27 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     // exact T_j = Q + (interior nodes of the tile before j) P + tl
     if (j < b0) {
         const int cnt = max(0, min(j, N) - max(a0, 1));
-        ph[tid + 1] = phi_prime(dd, j, add(add(Q, mul_small(i128(P), (unsigned)cnt)), tl));
+        ph[tid + 1] = phi_prime(fc, j, add(add(Q, mul_small(i128(P), (unsigned)cnt)), tl));
     }
-    const I128 Tb = add(add(Q, mul_small(i128(P), (unsigned)nint)), B);     // T at node b0
-    if (tid == 0) {
-        // halo below: T_{a0-1} = Q - S1_{a0-1} if a0 - 1 is interior, S1_{a0-1} = P;
-        // halo above: T_{b0}
-        if (a0 >= 1) {
-            const int jm = a0 - 1;
-            ph[0] = phi_prime(dd, jm, (jm >= 1 && jm <= N - 1) ? add(Q, neg(i128(P))) : Q);
-        }
-        if (b0 <= N) ph[b0 - a0 + 1] = phi_prime(dd, b0, Tb);
+    // halo below (a wave of its own): T_{a0-1} = Q - S1_{a0-1} if a0 - 1 is
+    // interior, S1_{a0-1} = P; halo above (another): T_{b0}
+    if (tid == 64 && a0 >= 1) {
+        const int jm = a0 - 1;
+        ph[0] = phi_prime(fc, jm, (jm >= 1 && jm <= N - 1) ? add(Q, neg(i128(P))) : Q);
     }
+    if (tid == 128 && b0 <= N) ph[b0 - a0 + 1] = phi_prime(fc, b0, add(add(Q, mul_small(i128(P), (unsigned)nint)), B));
     __syncthreads();
-    const int avg = uni(__hip_atomic_load(glb(&st->avg_on), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    field_tile_out<BIG_TILE>(dd, ph, hb, a0, b0, avg);
+    field_tile_out<BIG_TILE>(fc, ph, hb, a0, b0, avg);
     if (!writer) return;
-    // the writer's tile ends at node N: T_N = Q + n P + B, c = alpha T_N / N
+    // the writer's tile ends at node N: T_N = Q + n P + B, slope = alpha T_N / N
     if (tid == 0) {
         const I128 TN = add(add(Q, mul_small(i128(P), (unsigned)nint)), B);
-        const double c = dd.alpha / (double)N * to_double(TN);
-        st->phi_slope = c;
-        st->e_shift = -c / dd.dz;
-        if (avg) st->phi_slope_sum += c;
+        const double slope = dd.alpha / (double)N * to_double(TN);
+        st->phi_slope = slope;
+        st->e_shift = -slope / dd.dz;
+        if (avg) st->phi_slope_sum += slope;
     }
-    if (mode == 0) {
-        field_step_tail(dd, fs, step, avg, T);
-    } else if (tid == 0) {
+    if (mode != 0 && tid == 0) {
         while (__hip_atomic_load(glb(&st->arrive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < T - 1)
             __builtin_amdgcn_s_sleep(2);
         __hip_atomic_store(glb(&st->arrive), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
