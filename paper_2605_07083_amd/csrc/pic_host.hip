@@ -176,8 +176,8 @@ void layout(const pic_config *cfgs, int nd, const std::vector<pic_derived> &der,
         D.phi = bp.take<double>(nn);
         D.E = bp.take<double>(nn);
         D.phi_sum = bp.take<double>(nn);
-        D.agg = bp.take<FieldAgg>((nn + 1023) / 1024);     // one per 1024-node tile
-        D.agg_flag = bp.take<uint32_t>((nn + 1023) / 1024);
+        D.agg = bp.take<FieldAgg>((nn + FIELD_BIG_TILE - 1) / FIELD_BIG_TILE);     // one per large-grid tile
+        D.agg_flag = bp.take<uint32_t>((nn + FIELD_BIG_TILE - 1) / FIELD_BIG_TILE);
         D.tacc = bp.take<TallyCopy>(TALLY_COPIES);
     }
     zero_end = bp.off;
@@ -1505,7 +1505,7 @@ int pic_load(pic_handle *h, const void *host_buf, size_t bytes)
         // per-step scratch starts clear
         for (int s = 0; s < NSP; ++s) HIP_TRY(hipMemset(D.cell_cnt[s], 0, nn * sizeof(int32_t)));
         HIP_TRY(hipMemset(D.tacc, 0, sizeof(TallyCopy) * TALLY_COPIES));
-        HIP_TRY(hipMemset(D.agg_flag, 0, sizeof(uint32_t) * ((nn + 1023) / 1024)));
+        HIP_TRY(hipMemset(D.agg_flag, 0, sizeof(uint32_t) * ((nn + FIELD_BIG_TILE - 1) / FIELD_BIG_TILE)));
     }
     h->sort_next = true;
     return PIC_OK;

@@ -66,6 +66,9 @@ struct SpeciesBuf {
     ColdRec *cold;      // v_x, v_y, id
 };
 
+// Nodes per tile of the large-grid field kernel (one aggregate and flag each).
+constexpr int FIELD_BIG_TILE = 512;
+
 // Mutable per-diode state (device).
 struct DiodeState {
     int32_t n[NSP];        // slots in use in the current buffer (live + holes)

@@ -1710,7 +1710,10 @@ __device__ __forceinline__ I128 block_scan_excl_i128(I128 v, I128 *sh, I128 &tot
 // ---------------------------------------------------------------------------
 constexpr int TILE = 512;                 // nodes per tile block of k_field_step
 constexpr int FUSED_MAX_NODES = 4097;     // every node's charge staged in each block's LDS
-constexpr int BIG_TILE = FT;              // nodes per tile block of k_field_tiles (one per thread)
+// nodes per tile block of k_field_tiles (one per thread of its first half:
+// the per-node work of a tile runs on one CU, so smaller tiles spread it)
+constexpr int BIG_TILE = FIELD_BIG_TILE;
+static_assert(BIG_TILE <= FT && BIG_TILE % 64 == 0, "one thread per node of a tile, whole waves");
 constexpr int MAX_TILES = 32768 / BIG_TILE;    // N <= 32767: the earlier tiles fit one wave
 static_assert(MAX_TILES <= 64, "one lane per earlier tile");
 
@@ -1916,12 +1919,12 @@ __device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, bool
             if (tid == 0) {
                 apply_tally(dd, fs.rs);
                 if (fs.rs.ion_lost) atomicAdd(&st->ion_lost, fs.rs.ion_lost);
-                __threadfence();
                 __hip_atomic_store(glb(&st->spill_flag), step + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
         } else if (tid == 0) {
-            while (__hip_atomic_load(glb(&st->spill_flag), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != step + 1u)
+            while (__hip_atomic_load(glb(&st->spill_flag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != step + 1u)
                 __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the record block's queue and counters
         }
         __syncthreads();
         if (tid >= 64 && tid < 128) load_state(st, &fs.s_st);
@@ -2192,9 +2195,9 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     __shared__ long long R[BIG_TILE];                 // the own tile's charge
     __shared__ unsigned long long keys[IZQ_CAP];      // ionisation events by parent id
     __shared__ unsigned long long hb[NSP][BIG_TILE];  // the own tile's deposits per species
-    __shared__ long long w_A[FW];                     // per wave: sum of R,
-    __shared__ I128 w_C[FW];                          //   sum of the wave-local S1 over interior nodes,
-    __shared__ int w_n[FW];                           //   interior nodes
+    __shared__ long long w_A[BIG_TILE / 64];          // per wave of the tile: sum of R,
+    __shared__ I128 w_C[BIG_TILE / 64];               //   sum of the wave-local S1 over interior nodes,
+    __shared__ int w_n[BIG_TILE / 64];                //   interior nodes
     __shared__ double ph[BIG_TILE + 2];               // phi' on the own tile and its halo
     __shared__ FieldShared fs;
     __shared__ long long s_P;
@@ -2232,7 +2235,7 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
             }
             if (j >= 1 && j <= N - 1) r = (long long)(h[SP_I] - h[SP_P] - h[SP_E]);
         }
-        R[tid] = r;
+        if (tid < BIG_TILE) R[tid] = r;
     }
     const uint32_t step = mode == 0 ? (uint32_t)uni((int)st->step) : 0u;
     __syncthreads();
@@ -2262,24 +2265,31 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     // prefix of the charge at j is s1l = P_w + a and the in-tile exclusive
     // sum of s1l over the interior nodes before j is tl = Q_w + cnt P_w + c.
     // A = the tile's charge, B = its sum of s1l over its interior nodes.
-    const long long r = R[tid];
+    // The tile's nodes belong to the first TW waves; the others only take
+    // part in the barriers from here on.
+    constexpr int TW = BIG_TILE / 64;
     const bool interior = j >= 1 && j <= N - 1 && j < b0;
     const int lane = tid & 63, wv = tid >> 6;
-    const long long a = wave_incl_scan_i64(r);
-    const I128 ci = interior ? i128(a) : i128(0);
-    const I128 c = add(wave_incl_scan_i128(ci), neg(ci));
-    const unsigned long long im = __ballot(interior);
-    const int cw = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(im >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)im, 0u));
-    if (lane == 63) {
-        w_A[wv] = a;
-        w_C[wv] = add(c, ci);
-        w_n[wv] = cw + (interior ? 1 : 0);
+    long long a = 0;
+    I128 c = i128(0);
+    int cw = 0;
+    if (wv < TW) {
+        a = wave_incl_scan_i64(R[tid]);
+        const I128 ci = interior ? i128(a) : i128(0);
+        c = add(wave_incl_scan_i128(ci), neg(ci));
+        const unsigned long long im = __ballot(interior);
+        cw = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(im >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)im, 0u));
+        if (lane == 63) {
+            w_A[wv] = a;
+            w_C[wv] = add(c, ci);
+            w_n[wv] = cw + (interior ? 1 : 0);
+        }
     }
     __syncthreads();
     long long Pw = 0, A = 0;
     I128 Qw = i128(0), B = i128(0);
 #pragma unroll
-    for (int q = 0; q < FW; ++q) {
+    for (int q = 0; q < TW; ++q) {
         if (q == wv) {
             Pw = A;
             Qw = B;
@@ -2297,7 +2307,7 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
         g.n = nint;
         g.pad = 0;
         dd.agg[t] = g;
-        __threadfence();
+        // the release store orders the aggregate before the flag
         __hip_atomic_store(glb(&dd.agg_flag[t]), epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (tid < 64) {
@@ -2307,9 +2317,14 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
         long long Au = 0;
         I128 Bu = i128(0);
         int nu = 0;
+        // Relaxed polls, then one acquire fence for the wave: an acquire load
+        // invalidates the XCD's L2 on every poll (instructions included).
         if (u < t) {
-            while (__hip_atomic_load(glb(&dd.agg_flag[u]), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch + 1u)
+            while (__hip_atomic_load(glb(&dd.agg_flag[u]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch + 1u)
                 __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (u < t) {
             const FieldAgg g = dd.agg[u];
             Au = g.A;
             Bu.lo = g.B_lo;
