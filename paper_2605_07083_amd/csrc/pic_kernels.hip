@@ -2096,6 +2096,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     __shared__ double ph[TILE + 2];                   // phi on the own tile and its halo
     __shared__ FieldShared fs;
     __shared__ TileConsts fc;
+    __shared__ int s_avg;
     const Diode &dd = D[blockIdx.y];
     DiodeState *st = dd.st;
     const int N = dd.N, nn = N + 1;
@@ -2112,6 +2113,8 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     RareTally copy{};
     if (mode == 0) copy = field_step_reads(dd, fs);
     if (tid == 128) tile_consts(dd, fc);
+    // whether the step is averaged (the host sets avg_on between steps)
+    if (tid == 1) s_avg = __hip_atomic_load(glb(&st->avg_on), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!records) {
         for (int j = tid; j < nn; j += FT) {
             long long r = 0;
@@ -2126,6 +2129,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     }
     const uint32_t step = mode == 0 ? (uint32_t)uni((int)st->step) : 0u;
     __syncthreads();
+    const int avg = uni(s_avg);
     if (mode == 0) {
         field_step_plan(dd, parity, step, records, writer, copy, fs, keys);
         if (records) {
@@ -2134,6 +2138,11 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
         }
         births_deposit<TILE>(dd, fs.bp, keys, writer, step, R, 0, nn, hb, a0, b0);
         __syncthreads();
+        // the writer's tallies and counters need only the births: once every
+        // other block of the diode (the other tiles and the record block) has
+        // read the counters and copies, the step's tallies, counters and
+        // snapshot, while the solve is still to come
+        if (writer) field_step_tail(dd, fs, step, avg, T);
     }
 
     // phi_j = V j / N + alpha (j T_N - N T_j) / N with the exact sums
@@ -2174,13 +2183,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     }
     __syncthreads();
     // the own tile: field, potential, deposits of the step and their sums
-    const int avg = uni(__hip_atomic_load(glb(&st->avg_on), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     field_tile_out<TILE>(fc, ph, hb, a0, b0, avg);
-    if (mode != 0 || !writer) return;
-    // the writer: once every other block of the diode (the other tiles and
-    // the record block) has read the counters and copies, the step's tallies,
-    // counters and snapshot
-    field_step_tail(dd, fs, step, avg, T);
 }
 
 // phi' at node j (see k_field_tiles) from the exact T_j.
