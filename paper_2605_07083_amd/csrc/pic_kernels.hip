@@ -1685,11 +1685,12 @@ __device__ __forceinline__ I128 block_scan_excl_i128(I128 v, I128 *sh, I128 &tot
 // it works out the positions of the step's newborns itself (the same
 // counter-based draws, so every block finds the same ones) and adds their
 // charge and deposits, solves for the potential with exact integer prefix
-// sums and writes phi, E and the node bookkeeping of its tile.  The last
-// tile's block (the writer) applies the step's tallies, clears the tally
-// copies and advances the counters once every other block of the diode has
-// read them (a counter they bump).  Every wait is on blocks of the same
-// diode dispatched earlier.
+// sums and writes phi, E and the node bookkeeping of its tile.  Block T + 1,
+// dispatched last, applies the step's tallies, clears the tally copies and
+// advances the counters once every other block of the diode has read them
+// and the record block has written its tallies (a counter they bump), while
+// the tiles solve.  Every wait is on blocks of the same diode dispatched
+// earlier.
 //
 //   k_field_step   (N + 1 <= FUSED_MAX_NODES) tiles of TILE nodes; every tile
 //                  block stages the charge of every node in LDS and runs the
@@ -1702,8 +1703,8 @@ __device__ __forceinline__ I128 block_scan_excl_i128(I128 v, I128 *sh, I128 &tot
 //                  aggregates of the tiles before it: P_t = sum_{u<t} A_u is
 //                  S1 before the tile, Q_t = sum_{u<t} (n_u P_u + B_u) is T
 //                  before it.  T_N needs every tile, so the tiles write
-//                  phi'_j = V j / N - alpha T_j and E' from phi'; the writer,
-//                  the last tile, has T_N and stores the correction
+//                  phi'_j = V j / N - alpha T_j and E' from phi'; the
+//                  last tile (the writer) has T_N and stores the correction
 //                  phi_j = phi'_j + j c, c = alpha T_N / N, which shifts every
 //                  node's E by -c / dz.  The particle kernel adds that shift
 //                  to the E it gathers, the host adds both to what it reads.
@@ -1755,10 +1756,11 @@ __device__ __forceinline__ int iz_index(const BirthPlan &bp, const unsigned long
 // half-Maxwellian at Tc, replenished pairs at a shared uniform position),
 // one thread per newborn (pair), deposited into the block's LDS: the charge
 // of the nodes [r0, r1) into R, the species deposits of the own tile into
-// hb.  The writer also tallies a thermionic electron placed beyond the anode.
+// hb.  (A thermionic electron placed beyond the anode is tallied with the
+// records.)
 template <int HB>
 __device__ __forceinline__ void births_deposit(const Diode &dd, const BirthPlan &bp, const unsigned long long *keys,
-                                               bool writer, uint32_t step, long long *R, int r0, int r1,
+                                               uint32_t step, long long *R, int r0, int r1,
                                                unsigned long long (*hb)[HB], int a0, int b0)
 {
     const int q = bp.q, ne = bp.ne, total = q + ne + bp.R;
@@ -1774,16 +1776,7 @@ __device__ __forceinline__ void births_deposit(const Diode &dd, const BirthPlan 
             const uint4 b0w = philox(step, EV_BIRTH, 0u, 0u, idn, dd.kseed);
             const float vz = (float)(dd.sig_c * sqrt(-2.0 * log(u53(b0w.z, b0w.w))));
             const double z = (double)vz * dd.dt;
-            if (z < dd.L) {
-                fused_deposit<HB>(dd, R, r0, r1, hb, a0, b0, SP_E, z);
-            } else if (writer) {
-                double n1, n2;
-                bm32(b0w.x, b0w.y, n1, n2);
-                const double vx = (float)(dd.sig_c * n1), vy = (float)(dd.sig_c * n2);
-                const double ke = 0.5 * dd.mass[SP_E] * (vx * vx + vy * vy + (double)vz * vz);
-                atomicAdd(&dd.tally->abs_count[SP_E][1], 1ull);
-                atomicAdd(&dd.tally->abs_energy[SP_E][1], ke);
-            }
+            if (z < dd.L) fused_deposit<HB>(dd, R, r0, r1, hb, a0, b0, SP_E, z);
         } else {
             const int r = x - q - ne;
             const uint32_t ide = bp.id0 + 2u * q + ne + 2u * r;
@@ -1830,8 +1823,14 @@ __device__ __forceinline__ void births_records(const Diode &dd, const BirthPlan 
             const float vx = (float)(dd.sig_c * n1), vy = (float)(dd.sig_c * n2);
             const double z = (double)vz * dd.dt;
             const uint32_t tc = next_candidate(step, dd.lam[0], b1w.z, b1w.w);
-            // a newborn beyond the anode is absorbed at once (a hole; tallied by the writer)
+            // a newborn beyond the anode is absorbed at once: a hole, tallied here
             write_particle(bE, bp.bE + i, z >= dd.L ? -1.0 : z, vx, vy, vz, idn, tc);
+            if (z >= dd.L) {
+                const double dvx = vx, dvy = vy;
+                const double ke = 0.5 * dd.mass[SP_E] * (dvx * dvx + dvy * dvy + (double)vz * vz);
+                atomicAdd(&dd.tally->abs_count[SP_E][1], 1ull);
+                atomicAdd(&dd.tally->abs_energy[SP_E][1], ke);
+            }
         } else {
             const int r = x - q - ne;
             const uint32_t ide = bp.id0 + 2u * q + ne + 2u * r, idi = ide + 1u;
@@ -1857,7 +1856,7 @@ __device__ __forceinline__ void births_records(const Diode &dd, const BirthPlan 
     }
 }
 
-// The particle kernel's tally copies, read without clearing (the writer
+// The particle kernel's tally copies, read without clearing (the tail block
 // clears them once every block has read them).
 __device__ __forceinline__ RareTally read_tally_copy(const Diode &dd)
 {
@@ -1867,7 +1866,7 @@ __device__ __forceinline__ RareTally read_tally_copy(const Diode &dd)
 
 // The shared state of a field step's block.
 struct FieldShared {
-    RareTally rt, rs;          // the step's tallies (writer), the spilled items' (record block)
+    RareTally rt, rs;          // the step's tallies (tail block), the spilled items' (record block)
     DiodeState s_st;           // the counters as this block read them
     BirthPlan bp;
 };
@@ -1887,19 +1886,25 @@ __device__ __forceinline__ RareTally field_step_reads(const Diode &dd, FieldShar
     return copy;
 }
 
-// After field_step_reads and a barrier: the writer folds every tally copy
-// into fs.rt, the others only the ions lost; the spilled rare items are
-// worked off (record block) or waited for; once the block is done with the
-// counters it bumps st->arrive (all but the writer), then works out the plan
-// of the step's births and, when the plan needs it, the ionisation events in
+// After field_step_reads and a barrier: the tail block folds every tally
+// copy into fs.rt, the others only the ions lost; the spilled rare items are
+// worked off (record block) or waited for; once a tile block is done with the
+// counters it bumps st->arrive, then every block works out the plan of the
+// step's births and, when the plan needs it, the ionisation events in
 // parent-id order in keys.
-__device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, bool records, bool writer,
-                                RareTally copy, FieldShared &fs, unsigned long long *keys)
+// The roles of a field step's blocks (mode 0): block 0 writes the newborn
+// records, blocks 1..T take the node tiles, block T + 1 (dispatched last)
+// applies the step's tallies and advances the counters.
+enum FieldRole { ROLE_RECORDS, ROLE_TILE, ROLE_TAIL };
+
+__device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, FieldRole role, RareTally copy,
+                                FieldShared &fs, unsigned long long *keys)
 {
     DiodeState *st = dd.st;
     const int tid = threadIdx.x;
-    if (writer) {
-        fold_tally_copies(copy, &fs.rt);      // the step's totals, applied by the writer
+    const bool records = role == ROLE_RECORDS;
+    if (role == ROLE_TAIL) {
+        fold_tally_copies(copy, &fs.rt);      // the step's totals, applied by the tail block
     } else if (tid < 64) {
         int v = copy.ion_lost;                // the others need the ions lost only
 #pragma unroll
@@ -1931,8 +1936,8 @@ __device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, bool
     }
     __syncthreads();
     if (tid == 0) {
-        // this block is done with the counters and the copies
-        if (!writer) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // this tile block is done with the counters and the copies
+        if (role == ROLE_TILE) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const DiodeState &S = fs.s_st;
         BirthPlan p;
         p.q = min(S.iz_count, IZQ_CAP);
@@ -1947,13 +1952,13 @@ __device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, bool
         p.bP = S.n[SP_P];
         p.bE = S.n[SP_E];
         p.bI = S.n[SP_I];
-        // births that do not fit are dropped (and flagged by the writer)
+        // births that do not fit are dropped (and flagged by the tail block)
         p.okP = min(p.q + p.R, dd.cap[SP_P] - p.bP);
         p.okE = min(p.ne, dd.cap[SP_E] - p.bE);
         p.okI = min(p.q + p.R, dd.cap[SP_I] - p.bI);
         // the parent-id order names the ionisation products (the record
         // block) and, when some do not fit, decides which are dropped
-        p.sorted = p.q > 1 && (records || p.okP < p.q || p.okI < p.q);
+        p.sorted = p.q > 1 && role != ROLE_TAIL && (records || p.okP < p.q || p.okI < p.q);
         fs.bp = p;
     }
     __syncthreads();
@@ -1980,9 +1985,9 @@ __device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, bool
     }
 }
 
-// The writer's end of a step (mode 0), once `others` blocks of the diode
-// have arrived: the tally copies cleared, the step's tallies applied, the
-// counters advanced, the snapshot taken.
+// The tail block's end of a step (mode 0), once `others` blocks of the diode
+// (the tiles and the record block) have arrived: the tally copies cleared,
+// the step's tallies applied, the counters advanced, the snapshot taken.
 __device__ void field_step_tail(const Diode &dd, FieldShared &fs, uint32_t step, int avg, int others)
 {
     DiodeState *st = dd.st;
@@ -1991,6 +1996,8 @@ __device__ void field_step_tail(const Diode &dd, FieldShared &fs, uint32_t step,
         while (__hip_atomic_load(glb(&st->arrive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < others)
             __builtin_amdgcn_s_sleep(2);
         __hip_atomic_store(glb(&st->arrive), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the record block's tallies (released with its arrival) before the snapshot
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     if (tid < 64) dd.tacc[tid].t = RareTally{};
@@ -2101,10 +2108,10 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     DiodeState *st = dd.st;
     const int N = dd.N, nn = N + 1;
     const int T = (nn + TILE - 1) / TILE;
-    if ((int)blockIdx.x > T || (blockIdx.x == 0 && mode != 0)) return;
-    const bool records = blockIdx.x == 0;             // the newborn-record block
-    const int t = (int)blockIdx.x - 1;                // the tile of the others
-    const bool writer = t == T - 1;
+    if ((int)blockIdx.x > T + 1 || ((blockIdx.x == 0 || (int)blockIdx.x == T + 1) && mode != 0)) return;
+    const FieldRole role = blockIdx.x == 0 ? ROLE_RECORDS : (int)blockIdx.x == T + 1 ? ROLE_TAIL : ROLE_TILE;
+    const bool records = role == ROLE_RECORDS, tile = role == ROLE_TILE;
+    const int t = (int)blockIdx.x - 1;                // the tile of the tile blocks
     const int a0 = t * TILE, b0 = min(nn, a0 + TILE);
     const int tid = threadIdx.x;
 
@@ -2115,7 +2122,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     if (tid == 128) tile_consts(dd, fc);
     // whether the step is averaged (the host sets avg_on between steps)
     if (tid == 1) s_avg = __hip_atomic_load(glb(&st->avg_on), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (!records) {
+    if (tile) {
         for (int j = tid; j < nn; j += FT) {
             long long r = 0;
             if (j >= 1 && j <= N - 1)
@@ -2131,18 +2138,21 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     __syncthreads();
     const int avg = uni(s_avg);
     if (mode == 0) {
-        field_step_plan(dd, parity, step, records, writer, copy, fs, keys);
+        field_step_plan(dd, parity, step, role, copy, fs, keys);
         if (records) {
+            // the newborns' records and tallies, released to the tail block
             births_records(dd, fs.bp, keys, step, parity, fs.s_st.flip);
+            __syncthreads();
+            if (tid == 0) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
-        births_deposit<TILE>(dd, fs.bp, keys, writer, step, R, 0, nn, hb, a0, b0);
+        if (role == ROLE_TAIL) {
+            // the tiles and the record block: the step's tallies, counters and snapshot
+            field_step_tail(dd, fs, step, avg, T + 1);
+            return;
+        }
+        births_deposit<TILE>(dd, fs.bp, keys, step, R, 0, nn, hb, a0, b0);
         __syncthreads();
-        // the writer's tallies and counters need only the births: once every
-        // other block of the diode (the other tiles and the record block) has
-        // read the counters and copies, the step's tallies, counters and
-        // snapshot, while the solve is still to come
-        if (writer) field_step_tail(dd, fs, step, avg, T);
     }
 
     // phi_j = V j / N + alpha (j T_N - N T_j) / N with the exact sums
@@ -2212,10 +2222,11 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     DiodeState *st = dd.st;
     const int N = dd.N, nn = N + 1;
     const int T = (nn + BIG_TILE - 1) / BIG_TILE;
-    if ((int)blockIdx.x > T || (blockIdx.x == 0 && mode != 0)) return;
-    const bool records = blockIdx.x == 0;             // the newborn-record block
-    const int t = (int)blockIdx.x - 1;                // the tile of the others
-    const bool writer = t == T - 1;
+    if ((int)blockIdx.x > T + 1 || ((blockIdx.x == 0 || (int)blockIdx.x == T + 1) && mode != 0)) return;
+    const FieldRole role = blockIdx.x == 0 ? ROLE_RECORDS : (int)blockIdx.x == T + 1 ? ROLE_TAIL : ROLE_TILE;
+    const bool records = role == ROLE_RECORDS, tile = role == ROLE_TILE;
+    const int t = (int)blockIdx.x - 1;                // the tile of the tile blocks
+    const bool writer = t == T - 1;                   // the last tile: T_N
     const int a0 = t * BIG_TILE, b0 = min(nn, a0 + BIG_TILE);
     const int tid = threadIdx.x;
     const int j = a0 + tid;                           // this thread's node
@@ -2227,7 +2238,7 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     if (tid == 0) s_epoch = __hip_atomic_load(glb(&st->field_epoch), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (tid == 1) s_avg = __hip_atomic_load(glb(&st->avg_on), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (tid == 128) tile_consts(dd, fc);
-    if (!records) {
+    if (tile) {
         long long r = 0;
         if (j < b0) {
             unsigned long long h[NSP];
@@ -2245,16 +2256,23 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     const uint32_t epoch = s_epoch;
     const int avg = uni(s_avg);
     if (mode == 0) {
-        field_step_plan(dd, parity, step, records, writer, copy, fs, keys);
+        field_step_plan(dd, parity, step, role, copy, fs, keys);
         if (records) {
+            // the newborns' records and tallies, released to the tail block
             births_records(dd, fs.bp, keys, step, parity, fs.s_st.flip);
+            __syncthreads();
+            if (tid == 0) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
-        births_deposit<BIG_TILE>(dd, fs.bp, keys, writer, step, R, a0, b0, hb, a0, b0);
+        if (role == ROLE_TAIL) {
+            // once every tile has read the counters, the copies and the
+            // epoch: the step's tallies, counters and snapshot, the next epoch
+            field_step_tail(dd, fs, step, avg, T + 1);
+            if (tid == 0) st->field_epoch = epoch + 1u;
+            return;
+        }
+        births_deposit<BIG_TILE>(dd, fs.bp, keys, step, R, a0, b0, hb, a0, b0);
         __syncthreads();
-        // the writer's tallies and counters need only the births: done here,
-        // while the scans and the other tiles' flags are still to come
-        if (writer) field_step_tail(dd, fs, step, avg, T);
     } else if (tid == 0 && !writer) {
         // done with the epoch: the writer advances it once every tile has read it
         __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2368,11 +2386,13 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
         if (avg) st->phi_slope_sum += slope;
     }
     if (mode != 0 && tid == 0) {
+        // mode 1 has no record block: the writer advances the epoch once
+        // every other tile has read it
         while (__hip_atomic_load(glb(&st->arrive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < T - 1)
             __builtin_amdgcn_s_sleep(2);
         __hip_atomic_store(glb(&st->arrive), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st->field_epoch = epoch + 1u;
     }
-    if (tid == 0) st->field_epoch = epoch + 1u;
 }
 
 }  // namespace pic
@@ -2436,10 +2456,10 @@ extern "C" hipError_t picx_launch_sources_field(const Diode *D, DiodeState *S, i
     (void)S;
     if (max_nodes <= FUSED_MAX_NODES) {
         const int tiles = (max_nodes + TILE - 1) / TILE;
-        hipLaunchKernelGGL(k_field_step, dim3(tiles + 1, nd), dim3(FT), 0, s, D, mode, parity);
+        hipLaunchKernelGGL(k_field_step, dim3(tiles + 2, nd), dim3(FT), 0, s, D, mode, parity);
     } else {
         const int tiles = (max_nodes + BIG_TILE - 1) / BIG_TILE;
-        hipLaunchKernelGGL(k_field_tiles, dim3(tiles + 1, nd), dim3(FT), 0, s, D, mode, parity);
+        hipLaunchKernelGGL(k_field_tiles, dim3(tiles + 2, nd), dim3(FT), 0, s, D, mode, parity);
     }
     return hipGetLastError();
 }
