@@ -1637,17 +1637,22 @@ __device__ __forceinline__ I128 wave_incl_scan_i128(I128 x)
 // phi_j = V j / N + alpha (j T_N - N T_j) / N: the direct solution of the
 // constant-coefficient Dirichlet system, rounded once at the end.
 // ---------------------------------------------------------------------------
-// Block scans of the per-thread totals, for the field kernels whose threads
-// each walk consecutive nodes serially in registers.
+// Block scans of the per-thread totals of the first NWV waves (the other
+// waves pass zeros and only take part in the barriers), for the field kernels
+// whose threads each walk consecutive nodes serially in registers.
+template <int NWV>
 __device__ __forceinline__ long long block_scan_excl_i64(long long v, long long *sh, long long &total)
 {
     const int lane = lane_id(), w = threadIdx.x >> 6;
-    const long long incl = wave_incl_scan_i64(v);
-    if (lane == 63) sh[w] = incl;
+    long long incl = 0;
+    if (w < NWV) {
+        incl = wave_incl_scan_i64(v);
+        if (lane == 63) sh[w] = incl;
+    }
     __syncthreads();
     long long off = 0, tot = 0;
 #pragma unroll
-    for (int q = 0; q < FW; ++q) {
+    for (int q = 0; q < NWV; ++q) {
         const long long t = sh[q];
         if (q < w) off += t;
         tot += t;
@@ -1657,15 +1662,19 @@ __device__ __forceinline__ long long block_scan_excl_i64(long long v, long long 
     return off + incl - v;
 }
 
+template <int NWV>
 __device__ __forceinline__ I128 block_scan_excl_i128(I128 v, I128 *sh, I128 &total)
 {
     const int lane = lane_id(), w = threadIdx.x >> 6;
-    const I128 incl = wave_incl_scan_i128(v);
-    if (lane == 63) sh[w] = incl;
+    I128 incl = i128(0);
+    if (w < NWV) {
+        incl = wave_incl_scan_i128(v);
+        if (lane == 63) sh[w] = incl;
+    }
     __syncthreads();
     I128 off = i128(0), tot = i128(0);
 #pragma unroll
-    for (int q = 0; q < FW; ++q) {
+    for (int q = 0; q < NWV; ++q) {
         const I128 t = sh[q];
         if (q < w) off = add(off, t);
         tot = add(tot, t);
@@ -2101,6 +2110,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     __shared__ long long sh64[FW];
     __shared__ I128 sh128[FW];
     __shared__ double ph[TILE + 2];                   // phi on the own tile and its halo
+    __shared__ I128 tT[TILE + 2];                     // T_j on the own tile and its halo
     __shared__ FieldShared fs;
     __shared__ TileConsts fc;
     __shared__ int s_avg;
@@ -2156,14 +2166,18 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     }
 
     // phi_j = V j / N + alpha (j T_N - N T_j) / N with the exact sums
-    // S1_j = sum_{k<=j} R_k and T_j = sum_{m=1..j-1} S1_m; each thread walks
-    // per consecutive nodes, phi kept for the own tile and its halo
-    const int per = (nn + FT - 1) / FT;
-    const int j0 = tid * per, j1 = min(nn, j0 + per);
+    // S1_j = sum_{k<=j} R_k and T_j = sum_{m=1..j-1} S1_m.  The sums run on
+    // the first SCAN_WAVES waves, each thread walking `per` consecutive nodes
+    // serially (serial adds cost less than wave-wide steps of more waves);
+    // the T_j of the own tile and its halo go to LDS, and the potential is
+    // then worked out one node per thread.
+    constexpr int SCAN_WAVES = 8;
+    const int per = (nn + SCAN_WAVES * 64 - 1) / (SCAN_WAVES * 64);
+    const int j0 = tid < SCAN_WAVES * 64 ? tid * per : nn, j1 = min(nn, j0 + per);
     long long loc = 0;
     for (int j = j0; j < j1; ++j) loc += R[j];
     long long tot;
-    const long long s1off = block_scan_excl_i64(loc, sh64, tot);
+    const long long s1off = block_scan_excl_i64<SCAN_WAVES>(loc, sh64, tot);
     I128 tl = i128(0);
     {
         long long S1 = s1off;
@@ -2173,23 +2187,27 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
         }
     }
     I128 T_N;
-    I128 Tacc = block_scan_excl_i128(tl, sh128, T_N);
-    const double alpha_n = dd.alpha / (double)N;
+    I128 Tacc = block_scan_excl_i128<SCAN_WAVES>(tl, sh128, T_N);
     if (j1 > a0 - 1 && j0 <= b0) {
         long long S1 = s1off;
         for (int j = j0; j < j1; ++j) {
             S1 += R[j];
-            if (j >= a0 - 1 && j <= b0) {
-                double v = 0.0;
-                if (j == N) v = dd.V;
-                else if (j >= 1) {
-                    const I128 x = add(mul_small(T_N, (unsigned)j), neg(mul_small(Tacc, (unsigned)N)));
-                    v = dd.V * (double)j / (double)N + alpha_n * to_double(x);
-                }
-                ph[j - a0 + 1] = v;
-            }
+            if (j >= a0 - 1 && j <= b0) tT[j - a0 + 1] = Tacc;
             if (j >= 1 && j <= N - 1) Tacc = add(Tacc, i128(S1));
         }
+    }
+    __syncthreads();
+    const double alpha_n = fc.alpha / (double)N;
+    for (int k = tid; k < b0 - a0 + 2; k += FT) {
+        const int j = a0 - 1 + k;
+        if (j < 0 || j > N) continue;
+        double v = 0.0;
+        if (j == N) v = fc.V;
+        else if (j >= 1) {
+            const I128 x = add(mul_small(T_N, (unsigned)j), neg(mul_small(tT[k], (unsigned)N)));
+            v = fc.V * (double)j / (double)N + alpha_n * to_double(x);
+        }
+        ph[k] = v;
     }
     __syncthreads();
     // the own tile: field, potential, deposits of the step and their sums
