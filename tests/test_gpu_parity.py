@@ -300,7 +300,7 @@ def test_tiled_field_path_ragged(pic, O):
 
 
 def test_tiled_field_path_maximum_grid(pic, O):
-    """The largest grid the library accepts (32767 cells: 32 tiles of the
+    """The largest grid the library accepts (32767 cells: 64 tiles of the
     field solve, combined by one wave): load field and deposit, then restart
     parity over steps with births.  The potential is checked against the
     exact rational solve of the oracle's deposit, since the oracle's FP64

@@ -6,8 +6,8 @@ reach, and the library's error reporting, through the C ABI.
   the sources kernel: forced with a strongly collisional diode on a tiny grid.
 * The paper's benchmark diode ("Model": numerical setup; "Emission and
   collisions": elastic + charge exchange only, electron- and ion-side
-  neutral targets at 300 K and 1740 K, 40 V, 4096 cells -- the tiled field
-  path) and two of its sensitivity cases (Table 3: charge exchange off; the
+  neutral targets at 300 K and 1740 K, 40 V, 4096 cells -- the single field
+  kernel at its largest grid) and two of its sensitivity cases (Table 3: charge exchange off; the
   electron-side neutral target at 1740 K), at 20 particles per cell.
 * The 32-diode emission sweep (100k-600k particles per species per diode):
   one restart step against the oracle on three diodes of different sizes.
@@ -68,7 +68,8 @@ def test_rare_queue_spill_parity_tiled_field(pic, O, cells):
     """The spill on a grid of several field tiles.  2048 cells: the record
     block of the single field kernel works the spilled items off and the tile
     blocks wait for it before they read the counters those items change.
-    8192 cells: the births block of the two-kernel field step works them off."""
+    8192 cells: the record block of the tiled field kernel does, and its
+    tile blocks wait for it the same way."""
     cfg = presets.scaled(presets.tiny(), N=cells, L=5e-3 * cells / 256, n_load=40 * cells, ng=3.2e23, Te0=5.0,
                          gamma_emit=1e21)
     _say("case: rare-item spill on %d cells, grid 8" % cells)
