@@ -244,7 +244,7 @@ __device__ __forceinline__ void run_extent(int key, int &start, int &len)
 }
 
 // ---------------------------------------------------------------------------
-// Chunk map shared by the persistent particle and sort kernels.
+// Chunk maps of the particle kernel (tails first, below) and the re-sort.
 // ---------------------------------------------------------------------------
 // A block-uniform integer (read from LDS or loaded by every lane from one
 // address) made a scalar, so that what is derived from it (diode, species,
@@ -271,10 +271,10 @@ __device__ __forceinline__ bool sort_keeps(const Diode &dd, const DiodeState &st
     return tail <= n / 16 && cap - n >= max(2 * tail, cap / 16);
 }
 
-// Segments of the chunk map: every one (SEGS_ALL), those the re-sort sorts,
-// judged from the counters before it (SEGS_SORT_PRE: the count pass, before
-// the scan has stored the decision), or as the scan stored it (SEGS_SORT).
-enum SegSel { SEGS_ALL, SEGS_SORT_PRE, SEGS_SORT };
+// Segments of the re-sort's chunk map: those it sorts, judged from the
+// counters before it (SEGS_SORT_PRE: the count pass, before the scan has
+// stored the decision) or as the scan stored it (SEGS_SORT).
+enum SegSel { SEGS_SORT_PRE, SEGS_SORT };
 
 __device__ void build_chunk_map(const Diode *__restrict__ D, const DiodeState *__restrict__ S, int nd, int chunk,
                                 SegSel sel, int *seg_end, ChunkMap &cm, int *seg_n = nullptr)
@@ -289,9 +289,7 @@ __device__ void build_chunk_map(const Diode *__restrict__ D, const DiodeState *_
                 const DiodeState &st = S[sidx / NSP];
                 const int sp = sidx % NSP;
                 const int n = st.n[sp];
-                const bool kept = sel == SEGS_SORT_PRE ? sort_keeps(D[sidx / NSP], st, sp)
-                                  : sel == SEGS_SORT   ? st.keep[sp] != 0
-                                                       : false;
+                const bool kept = sel == SEGS_SORT_PRE ? sort_keeps(D[sidx / NSP], st, sp) : st.keep[sp] != 0;
                 c = kept ? 0 : (n + chunk - 1) / chunk;
                 if (seg_n) seg_n[sidx] = n;
             }
