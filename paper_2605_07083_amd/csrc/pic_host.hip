@@ -1132,9 +1132,10 @@ int pic_get_tuning(pic_handle *h, int *ppt, int *grid, int *sort_period, int *us
     return PIC_OK;
 }
 
-// Launch-schedule autotuner: coordinate descent over particles per thread,
-// re-sort period, grid size and graph replay, each candidate timed with HIP
-// events over whole re-sort periods of real steps (the diodes advance).
+// Launch-schedule autotuner: a full search over particles per thread, re-sort
+// period and grid size, the best four re-timed, then graph replay, each
+// candidate timed with HIP events over whole re-sort periods of real steps
+// (the diodes advance).
 int pic_autotune(pic_handle *h, int64_t trial_steps, int *ppt, int *grid, int *sort_period, int *use_graph,
                  double *ms_per_step)
 {
@@ -1170,12 +1171,30 @@ int pic_autotune(pic_handle *h, int64_t trial_steps, int *ppt, int *grid, int *s
         int n;
     };
     std::vector<Cand> cands;
-    for (int p : {1, 2, 4})
+    // besides the powers of two, the grid that gives each block eight chunks
+    // of the particles the stores hold now (eight chunks per block measured
+    // best where that grid falls between two powers of two)
+    std::vector<int64_t> slots;
+    for (int d = 0; d < h->nd; ++d) {
+        DiodeState st;
+        DiodeTally t;
+        if ((rc = read_state(h, d, st, t))) return rc;
+        for (int s = 0; s < NSP; ++s) slots.push_back(st.n[s]);
+    }
+    for (int p : {1, 2, 4}) {
+        int64_t chunks = 0;
+        for (int64_t n : slots) chunks += (n + 256 * p - 1) / (256 * p);
+        const int g8 = (int)std::min<int64_t>(65536, std::max<int64_t>(256, (chunks + 7) / 8));
+        std::vector<int> grids = {2048, 4096, 8192, 16384};
+        bool near = false;
+        for (int g : grids) near = near || std::abs(g - g8) * 10 < g;
+        if (!near) grids.push_back(g8);
         for (int k : {16, 32, 64, 128})
-            for (int g : {2048, 4096, 8192, 16384}) {
+            for (int g : grids) {
                 if ((rc = timed(p, g, k, bu, ms))) return rc;
                 cands.push_back(Cand{p, k, h->grid, ms, 1});
             }
+    }
     // the best few again, twice each and interleaved (the run drifts between
     // trials, and one trial's noise is a few per cent, as large as the
     // differences between the best schedules): the lowest mean wins
