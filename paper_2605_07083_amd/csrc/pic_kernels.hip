@@ -1837,6 +1837,8 @@ __device__ __forceinline__ void births_records(const Diode &dd, const BirthPlan 
                 const double ke = 0.5 * dd.mass[SP_E] * (dvx * dvx + dvy * dvy + (double)vz * vz);
                 atomicAdd(&dd.tally->abs_count[SP_E][1], 1ull);
                 atomicAdd(&dd.tally->abs_energy[SP_E][1], ke);
+                // complete before the block's arrival releases the tallies
+                __threadfence();
             }
         } else {
             const int r = x - q - ne;
@@ -1927,6 +1929,9 @@ __device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, Fiel
                 atomicAdd(&dd.tally->rare_spill,
                           (unsigned long long)(fs.s_st.rare_n[SP_P] + fs.s_st.rare_n[SP_E] + fs.s_st.rare_n[SP_I]));
             process_rare(dd, fs.s_st.rare_n, fs.s_st.flip, parity, step, tid, FT, &fs.rs);
+            // every thread's queue entries and counters complete before the
+            // flag (a barrier does not wait for other waves' global stores)
+            __threadfence();
             __syncthreads();
             if (tid == 0) {
                 apply_tally(dd, fs.rs);
