@@ -1146,9 +1146,12 @@ int pic_autotune(pic_handle *h, int64_t trial_steps, int *ppt, int *grid, int *s
     auto timed = [&](int p, int g, int k, int ug, double &ms) -> int {
         int rc = pic_set_tuning(h, p, g, k, ug);
         if (rc) return rc;
-        // align to a re-sort boundary and warm the new schedule for one period
+        // align to a re-sort boundary and warm the new schedule: one period,
+        // or two with graph replay, whose graphs are captured per buffer
+        // parity and the re-sort flips it every period (a capture inside the
+        // timed steps would count against replay)
         int64_t pad = (h->sort_period - h->issued % h->sort_period) % h->sort_period;
-        if ((rc = run_steps(h, pad + h->sort_period))) return rc;
+        if ((rc = run_steps(h, pad + (ug ? 2 : 1) * h->sort_period))) return rc;
         const int64_t n = std::max<int64_t>(1, (trial_steps + h->sort_period - 1) / h->sort_period) * h->sort_period;
         HIP_TRY(hipEventRecord(e0, h->stream));
         if ((rc = run_steps(h, n))) return rc;
