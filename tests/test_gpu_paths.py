@@ -9,6 +9,8 @@ reach, and the library's error reporting, through the C ABI.
   neutral targets at 300 K and 1740 K, 40 V, 4096 cells -- the single field
   kernel at its largest grid) and two of its sensitivity cases (Table 3: charge exchange off; the
   electron-side neutral target at 1740 K), at 20 particles per cell.
+* The largest batch (256 diodes, one on the tiled field grid), through
+  re-sorts with graph replay, then restart parity on three of them.
 * The 32-diode emission sweep (100k-600k particles per species per diode):
   one restart step against the oracle on three diodes of different sizes.
 * Graph replay of runs shorter than a re-sort period equals plain launches,
@@ -116,6 +118,33 @@ def test_sweep_32_diodes_parity(pic, O):
     h.step(4)
     for d in picks:
         probs = restart_step_check(O, cfgs[d], h, 1, d=d)
+        assert probs == [], "diode %d:\n%s" % (d, "\n".join(probs[:20]))
+
+
+def test_maximum_batch_of_diodes(pic, O):
+    """The largest batch a handle takes (256 diodes), one of them on a grid of
+    the tiled field kernel so that every diode's field step runs there: 64
+    steps through four re-sorts (three of them leaving the ions in place),
+    with graph replay; every diode's field step waits only on blocks
+    dispatched before it, so a batch that cannot be resident at once still
+    completes.  Then restart parity on the first, a middle and the last
+    diode."""
+    base = presets.scaled(presets.tiny(), n_load=2560)
+    cfgs = [presets.scaled(base, gamma_emit=1e20 * (1 + d % 7), diode=d) for d in range(255)]
+    cfgs.append(presets.scaled(presets.tiny(), N=5000, L=5e-3 * 5000 / 256, n_load=50000, gamma_emit=3e21,
+                               diode=255))
+    _say("case: 256 diodes in one handle (255 x 256 cells, 1 x 5000 cells), 64 steps")
+    h = pic.Handle(cfgs)
+    h.set_tuning(sort_period=16, use_graph=1)
+    h.step(64)
+    h.sync()
+    t = h.tally(0)
+    assert t["step"] == 64 and t["err_bits"] == 0 and t["resorts"] >= 4
+    for d in range(256):
+        assert h.tally(d)["step"] == 64 and h.tally(d)["err_bits"] == 0, d
+    for d in (0, 127, 255):
+        # each check steps the whole handle on from the state it finds
+        probs = restart_step_check(O, cfgs[d], h, 2, d=d)
         assert probs == [], "diode %d:\n%s" % (d, "\n".join(probs[:20]))
 
 
