@@ -11,7 +11,7 @@
 //                     parent id), thermionic emission, pair replenishment,
 //                     then the exact-integer double prefix-scan Poisson solve
 //                     and the field, tallies and snapshots (k_field_tiles on
-//                     grids above 4097 nodes).
+//                     grids above 2049 nodes).
 // Particles are processed in chunks of 256*PPT slots; the chunk list spans all
 // (diode, species) segments.  Each block of the particle kernel takes an equal
 // share of it, in an order that puts every segment's unsorted tail (the
@@ -1717,7 +1717,11 @@ __device__ __forceinline__ I128 block_scan_excl_i128(I128 v, I128 *sh, I128 &tot
 //                  to the E it gathers, the host adds both to what it reads.
 // ---------------------------------------------------------------------------
 constexpr int TILE = 512;                 // nodes per tile block of k_field_step
-constexpr int FUSED_MAX_NODES = 4097;     // every node's charge staged in each block's LDS
+// Every node's charge staged in each block's LDS.  Above 2049 nodes the tiles'
+// look-back costs less than every block scanning the whole grid (4097 nodes:
+// 60.6 against 62.8 us per step); at 2049 the whole-grid scans still win in
+// batches (32 diodes: 145.8 against 146.9 us per step).
+constexpr int FUSED_MAX_NODES = 2049;
 // nodes per tile block of k_field_tiles (one per thread of its first half:
 // the per-node work of a tile runs on one CU, so smaller tiles spread it)
 constexpr int BIG_TILE = FIELD_BIG_TILE;

@@ -283,7 +283,7 @@ def test_steady_state_on_device(pic):
 
 
 def test_tiled_field_path_ragged(pic, O):
-    """Grids above 4096 nodes take the multi-block field solve (births, tile
+    """Grids above 2049 nodes take the multi-block field solve (births, tile
     aggregates, tiled solve): a ragged 9001-node diode batched with a 257-node
     one, field and deposit against the oracle, then restart parity."""
     _say("case: tiled field path, N = 9000 with N = 256 in one batch")

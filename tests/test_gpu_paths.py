@@ -6,8 +6,8 @@ reach, and the library's error reporting, through the C ABI.
   the sources kernel: forced with a strongly collisional diode on a tiny grid.
 * The paper's benchmark diode ("Model": numerical setup; "Emission and
   collisions": elastic + charge exchange only, electron- and ion-side
-  neutral targets at 300 K and 1740 K, 40 V, 4096 cells -- the single field
-  kernel at its largest grid) and two of its sensitivity cases (Table 3: charge exchange off; the
+  neutral targets at 300 K and 1740 K, 40 V, 4096 cells -- the tiled field
+  kernel, nine tiles, the last of one node) and two of its sensitivity cases (Table 3: charge exchange off; the
   electron-side neutral target at 1740 K), at 20 particles per cell.
 * The largest batch (256 diodes, one on the tiled field grid), through
   re-sorts with graph replay, then restart parity on three of them.
