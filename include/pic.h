@@ -287,9 +287,12 @@ int pic_refield(pic_handle *h);
  * replay, each run up to the next re-sort boundary is one replayed graph, as
  * in pic_step -- with HIP events around launches of the particle kernel on
  * the bound stream (with graph replay: the particle kernels of up to 8 steps
- * spread evenly over each replayed run; on the plain stream: one launch in
- * max(1, nsteps / 512); at most 4096 in all) and return their mean duration
- * and the time from the first enqueued step to the end of the last (ms).
+ * spread evenly over each replayed run, at most 4096 in all; on the plain
+ * stream, where each pair of timestamps stalls the launches around it, at
+ * most 32: every launch when nsteps <= w, else one in s = ceil(nsteps / w)
+ * rounded up to an odd number, w = min(32, max(4, nsteps / 16))) and return
+ * their mean duration and the time from the first enqueued step to the end
+ * of the last (ms).
  * Events are created on first use and kept by the handle.  Synchronises at
  * the end only. */
 int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, double *total_ms);

@@ -59,6 +59,7 @@ constexpr size_t ALIGN = 256;
 constexpr int TPOS = 8;   // particle kernels timed per replayed graph (pic_step_timed)
 constexpr size_t GRAPH_CACHE = 16;   // captured step runs kept per handle
 constexpr int64_t TIMED_MAX = 4096;   // particle kernels timed per pic_step_timed call
+constexpr int64_t PLAIN_SAMPLES = 32; // of them, at most, on the plain stream
 
 // ----------------------------------------------------------------------------
 // Derived quantities ("Model": w0 = n0 dz / N_ppc, dt and grid; MCC bound).
@@ -1033,8 +1034,13 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
 {
     if (!h || nsteps < 1) return fail(PIC_EINVAL, "bad arguments");
     // events: up to TPOS particle kernels per replayed graph, or one launch in
-    // `every` on the plain stream, at most TIMED_MAX kernels in all
-    const int64_t every = std::max<int64_t>(1, nsteps / 512);
+    // `every` on the plain stream, at most TIMED_MAX kernels in all.  On the
+    // plain stream each timestamp pair stalls the launches around it, so few
+    // kernels are sampled there (at most PLAIN_SAMPLES; four on short runs),
+    // with an odd stride: the samples fall on every position of a re-sort
+    // period (whose length is a power of two), not on the same few.
+    const int64_t want = std::min<int64_t>(PLAIN_SAMPLES, std::max<int64_t>(4, nsteps / 16));
+    const int64_t every = nsteps <= want ? 1 : ((nsteps + want - 1) / want) | 1;
     auto pair = [&](int64_t k, hipEvent_t &a, hipEvent_t &b) -> int {
         while ((int64_t)h->evpool.size() < 2 * (k + 1)) {
             hipEvent_t e;
