@@ -1021,6 +1021,10 @@ int pic_set_counters(pic_handle *h, int diode, int64_t step, uint32_t next_id)
     uint32_t v[2] = {next_id, (uint32_t)step};
     static_assert(offsetof(DiodeState, step) == offsetof(DiodeState, next_id) + 4, "layout");
     HIP_TRY(hipMemcpy(&h->hD[diode].st->next_id, v, sizeof(v), hipMemcpyHostToDevice));
+    // the record block's flag holds the step it last finished + 1: cleared, it
+    // cannot match a step the counters were moved back to
+    const uint32_t zero = 0u;
+    HIP_TRY(hipMemcpy(&h->hD[diode].st->rec_flag, &zero, sizeof(zero), hipMemcpyHostToDevice));
     return PIC_OK;
 }
 

@@ -91,7 +91,7 @@ struct DiodeState {
     int32_t flip[NSP];
     int32_t keep[NSP];
     uint32_t resorts;      // re-sorts so far
-    uint32_t pad;
+    uint32_t rec_flag;     // field step: step + 1 once the record block's newborns and tallies are done
     // Large-grid field step (zero on smaller grids): the stored phi and E
     // leave out phi_slope j and e_shift = -phi_slope / dz, the part of the
     // potential that needs every tile; phi_slope_sum is the slope's sum over

@@ -1739,18 +1739,46 @@ struct BirthPlan {
 
 // A newborn's charge into R for the nodes [r0, r1) (interior nodes, ions
 // positive) and its species deposit into the own tile's counts hb.
+// What the plan and the newborns' charge need of the diode, copied into LDS
+// by one thread at the start of a field block, while the counters are read:
+// fetched where they are used, these fields would each cost a round trip to
+// memory on the step's critical path (the particle kernel before has evicted
+// them from the caches).
+struct BirthConsts {
+    double L, invdz, dt, emit_x, sig_c;
+    const IzEvent *izq;
+    uint32_t kseed;
+    int N, replenish;
+    int cap[NSP];
+};
+
+__device__ __forceinline__ void birth_consts(const Diode &dd, BirthConsts &bc)
+{
+    bc.L = dd.L;
+    bc.invdz = dd.invdz;
+    bc.dt = dd.dt;
+    bc.emit_x = dd.emit_x;
+    bc.sig_c = dd.sig_c;
+    bc.izq = dd.izq;
+    bc.kseed = dd.kseed;
+    bc.N = dd.N;
+    bc.replenish = dd.replenish;
+#pragma unroll
+    for (int s = 0; s < NSP; ++s) bc.cap[s] = dd.cap[s];
+}
+
 template <int HB>
-__device__ __forceinline__ void fused_deposit(const Diode &dd, long long *R, int r0, int r1,
+__device__ __forceinline__ void fused_deposit(const BirthConsts &bc, long long *R, int r0, int r1,
                                               unsigned long long (*hb)[HB], int a0, int b0, int s, double z)
 {
     int j;
     double f;
-    cic(z, dd.invdz, dd.N, j, f);
+    cic(z, bc.invdz, bc.N, j, f);
     const unsigned long long a = fixed_right(f), l = (1ull << 32) - a;
     const long long sg = s == SP_I ? 1 : -1;
     if (j >= 1 && j >= r0 && j < r1)
         atomicAdd(reinterpret_cast<unsigned long long *>(&R[j - r0]), (unsigned long long)(sg * (long long)l));
-    if (j + 1 <= dd.N - 1 && j + 1 >= r0 && j + 1 < r1)
+    if (j + 1 <= bc.N - 1 && j + 1 >= r0 && j + 1 < r1)
         atomicAdd(reinterpret_cast<unsigned long long *>(&R[j + 1 - r0]), (unsigned long long)(sg * (long long)a));
     if (j >= a0 && j < b0) atomicAdd(&hb[s][j - a0], l);
     if (j + 1 >= a0 && j + 1 < b0) atomicAdd(&hb[s][j + 1 - a0], a);
@@ -1770,31 +1798,31 @@ __device__ __forceinline__ int iz_index(const BirthPlan &bp, const unsigned long
 // hb.  (A thermionic electron placed beyond the anode is tallied with the
 // records.)
 template <int HB>
-__device__ __forceinline__ void births_deposit(const Diode &dd, const BirthPlan &bp, const unsigned long long *keys,
+__device__ __forceinline__ void births_deposit(const BirthConsts &bc, const BirthPlan &bp, const unsigned long long *keys,
                                                uint32_t step, long long *R, int r0, int r1,
                                                unsigned long long (*hb)[HB], int a0, int b0)
 {
     const int q = bp.q, ne = bp.ne, total = q + ne + bp.R;
     for (int x = threadIdx.x; x < total; x += FT) {
         if (x < q) {
-            const double z = dd.izq[iz_index(bp, keys, x)].z;
-            if (x < bp.okP) fused_deposit<HB>(dd, R, r0, r1, hb, a0, b0, SP_P, z);
-            if (x < bp.okI) fused_deposit<HB>(dd, R, r0, r1, hb, a0, b0, SP_I, z);
+            const double z = bc.izq[iz_index(bp, keys, x)].z;
+            if (x < bp.okP) fused_deposit<HB>(bc, R, r0, r1, hb, a0, b0, SP_P, z);
+            if (x < bp.okI) fused_deposit<HB>(bc, R, r0, r1, hb, a0, b0, SP_I, z);
         } else if (x < q + ne) {
             const int i = x - q;
             if (i >= bp.okE) continue;
             const uint32_t idn = bp.id0 + 2u * q + i;
-            const uint4 b0w = philox(step, EV_BIRTH, 0u, 0u, idn, dd.kseed);
-            const float vz = (float)(dd.sig_c * sqrt(-2.0 * log(u53(b0w.z, b0w.w))));
-            const double z = (double)vz * dd.dt;
-            if (z < dd.L) fused_deposit<HB>(dd, R, r0, r1, hb, a0, b0, SP_E, z);
+            const uint4 b0w = philox(step, EV_BIRTH, 0u, 0u, idn, bc.kseed);
+            const float vz = (float)(bc.sig_c * sqrt(-2.0 * log(u53(b0w.z, b0w.w))));
+            const double z = (double)vz * bc.dt;
+            if (z < bc.L) fused_deposit<HB>(bc, R, r0, r1, hb, a0, b0, SP_E, z);
         } else {
             const int r = x - q - ne;
             const uint32_t ide = bp.id0 + 2u * q + ne + 2u * r;
-            const uint4 e1 = philox(step, EV_BIRTH, 1u, 0u, ide, dd.kseed);
-            const double z = dd.L * u53(e1.x, e1.y);
-            if (q + r < bp.okP) fused_deposit<HB>(dd, R, r0, r1, hb, a0, b0, SP_P, z);
-            if (q + r < bp.okI) fused_deposit<HB>(dd, R, r0, r1, hb, a0, b0, SP_I, z);
+            const uint4 e1 = philox(step, EV_BIRTH, 1u, 0u, ide, bc.kseed);
+            const double z = bc.L * u53(e1.x, e1.y);
+            if (q + r < bp.okP) fused_deposit<HB>(bc, R, r0, r1, hb, a0, b0, SP_P, z);
+            if (q + r < bp.okI) fused_deposit<HB>(bc, R, r0, r1, hb, a0, b0, SP_I, z);
         }
     }
 }
@@ -1882,6 +1910,7 @@ struct FieldShared {
     RareTally rt, rs;          // the step's tallies (tail block), the spilled items' (record block)
     DiodeState s_st;           // the counters as this block read them
     BirthPlan bp;
+    BirthConsts bc;
 };
 
 // The first reads of every block of a field step (mode 0): the particle
@@ -1892,6 +1921,7 @@ __device__ __forceinline__ RareTally field_step_reads(const Diode &dd, FieldShar
     RareTally copy{};
     if (tid < 64) copy = read_tally_copy(dd);
     if (tid >= 64 && tid < 128) load_state(dd.st, &fs.s_st);
+    if (tid == 192) birth_consts(dd, fs.bc);
     if (tid == 0) {
         rare_tally_zero(&fs.rt);
         rare_tally_zero(&fs.rs);
@@ -1952,26 +1982,26 @@ __device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, Fiel
     }
     __syncthreads();
     if (tid == 0) {
-        // this tile block is done with the counters and the copies
-        if (role == ROLE_TILE) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // this tile or record block is done with the counters and the copies
+        if (role != ROLE_TAIL) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const DiodeState &S = fs.s_st;
         BirthPlan p;
         p.q = min(S.iz_count, IZQ_CAP);
-        p.R = dd.replenish ? S.ion_lost + fs.rt.ion_lost : 0;
+        p.R = fs.bc.replenish ? S.ion_lost + fs.rt.ion_lost : 0;
         p.ne = 0;
-        if (dd.emit_x > 0.0) {
-            const double fl = floor(dd.emit_x);
-            const uint4 be = philox(step, EV_EMIT, 0u, 0u, 0xFFFFFFFFu, dd.kseed);
-            p.ne = (int)fl + (u53(be.x, be.y) < dd.emit_x - fl ? 1 : 0);
+        if (fs.bc.emit_x > 0.0) {
+            const double fl = floor(fs.bc.emit_x);
+            const uint4 be = philox(step, EV_EMIT, 0u, 0u, 0xFFFFFFFFu, fs.bc.kseed);
+            p.ne = (int)fl + (u53(be.x, be.y) < fs.bc.emit_x - fl ? 1 : 0);
         }
         p.id0 = S.next_id;
         p.bP = S.n[SP_P];
         p.bE = S.n[SP_E];
         p.bI = S.n[SP_I];
         // births that do not fit are dropped (and flagged by the tail block)
-        p.okP = min(p.q + p.R, dd.cap[SP_P] - p.bP);
-        p.okE = min(p.ne, dd.cap[SP_E] - p.bE);
-        p.okI = min(p.q + p.R, dd.cap[SP_I] - p.bI);
+        p.okP = min(p.q + p.R, fs.bc.cap[SP_P] - p.bP);
+        p.okE = min(p.ne, fs.bc.cap[SP_E] - p.bE);
+        p.okI = min(p.q + p.R, fs.bc.cap[SP_I] - p.bI);
         // the parent-id order names the ionisation products (the record
         // block) and, when some do not fit, decides which are dropped
         p.sorted = p.q > 1 && role != ROLE_TAIL && (records || p.okP < p.q || p.okI < p.q);
@@ -1983,7 +2013,7 @@ __device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, Fiel
         int np2 = 1;
         while (np2 < q) np2 <<= 1;
         for (int i = tid; i < np2; i += FT)
-            keys[i] = i < q ? ((unsigned long long)dd.izq[i].parent << 32) | (unsigned)i : ~0ull;
+            keys[i] = i < q ? ((unsigned long long)fs.bc.izq[i].parent << 32) | (unsigned)i : ~0ull;
         __syncthreads();
         for (int k = 2; k <= np2; k <<= 1) {
             for (int jj = k >> 1; jj > 0; jj >>= 1) {
@@ -2002,8 +2032,10 @@ __device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, Fiel
 }
 
 // The tail block's end of a step (mode 0), once `others` blocks of the diode
-// (the tiles and the record block) have arrived: the tally copies cleared,
-// the step's tallies applied, the counters advanced, the snapshot taken.
+// (the tiles and the record block) are done with the counters and the tally
+// copies: the copies cleared, the step's tallies applied, the counters
+// advanced; on a snapshot step, once the record block has also released its
+// tallies (newborns placed beyond the anode), the snapshot taken.
 __device__ void field_step_tail(const Diode &dd, FieldShared &fs, uint32_t step, int avg, int others)
 {
     DiodeState *st = dd.st;
@@ -2012,8 +2044,6 @@ __device__ void field_step_tail(const Diode &dd, FieldShared &fs, uint32_t step,
         while (__hip_atomic_load(glb(&st->arrive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < others)
             __builtin_amdgcn_s_sleep(2);
         __hip_atomic_store(glb(&st->arrive), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // the record block's tallies (released with its arrival) before the snapshot
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     if (tid < 64) dd.tacc[tid].t = RareTally{};
@@ -2041,6 +2071,10 @@ __device__ void field_step_tail(const Diode &dd, FieldShared &fs, uint32_t step,
     __syncthreads();
     const uint32_t nstep = step + 1u;
     if (tid == 0 && dd.tally_period > 0 && nstep % (uint32_t)dd.tally_period == 0u) {
+        // the record block (dispatched before this block) sets the flag
+        while (__hip_atomic_load(glb(&st->rec_flag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != nstep)
+            __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         TallySnap &sn = dd.ring[(nstep / (uint32_t)dd.tally_period) % RING];
         sn.step = nstep;
         sn.t = *dd.tally;
@@ -2157,10 +2191,12 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     if (mode == 0) {
         field_step_plan(dd, parity, step, role, copy, fs, keys);
         if (records) {
-            // the newborns' records and tallies, released to the tail block
+            // the newborns' records and tallies; the flag releases the
+            // tallies to the tail block, which waits for them only when the
+            // step takes a snapshot
             births_records(dd, fs.bp, keys, step, parity, fs.s_st.flip);
             __syncthreads();
-            if (tid == 0) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (tid == 0) __hip_atomic_store(glb(&st->rec_flag), step + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
         if (role == ROLE_TAIL) {
@@ -2168,7 +2204,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
             field_step_tail(dd, fs, step, avg, T + 1);
             return;
         }
-        births_deposit<TILE>(dd, fs.bp, keys, step, R, 0, nn, hb, a0, b0);
+        births_deposit<TILE>(fs.bc, fs.bp, keys, step, R, 0, nn, hb, a0, b0);
         __syncthreads();
     }
 
@@ -2239,7 +2275,9 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     __shared__ double ph[BIG_TILE + 2];               // phi' on the own tile and its halo
     __shared__ FieldShared fs;
     __shared__ long long s_P;
-    __shared__ I128 s_Q;
+    __shared__ I128 s_Q, s_B;                         // S1, T before the tile; the tile's B
+    __shared__ long long s_Pw[BIG_TILE / 64];         // per wave of the tile: charge of the earlier waves,
+    __shared__ I128 s_Qw[BIG_TILE / 64];              //   their sum of S1 over interior nodes
     __shared__ uint32_t s_epoch;
     __shared__ int s_avg;
     __shared__ TileConsts fc;
@@ -2283,10 +2321,12 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     if (mode == 0) {
         field_step_plan(dd, parity, step, role, copy, fs, keys);
         if (records) {
-            // the newborns' records and tallies, released to the tail block
+            // the newborns' records and tallies; the flag releases the
+            // tallies to the tail block, which waits for them only when the
+            // step takes a snapshot
             births_records(dd, fs.bp, keys, step, parity, fs.s_st.flip);
             __syncthreads();
-            if (tid == 0) __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (tid == 0) __hip_atomic_store(glb(&st->rec_flag), step + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
         if (role == ROLE_TAIL) {
@@ -2296,7 +2336,7 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
             if (tid == 0) st->field_epoch = epoch + 1u;
             return;
         }
-        births_deposit<BIG_TILE>(dd, fs.bp, keys, step, R, a0, b0, hb, a0, b0);
+        births_deposit<BIG_TILE>(fs.bc, fs.bp, keys, step, R, a0, b0, hb, a0, b0);
         __syncthreads();
     } else if (tid == 0 && !writer) {
         // done with the epoch: the writer advances it once every tile has read it
@@ -2305,7 +2345,8 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
 
     // The tile's aggregates with one barrier: per wave, the inclusive prefix
     // a of the charge and the exclusive prefix c of a over the interior nodes;
-    // then each thread combines the totals of the waves before its own.  With
+    // then the first wave combines the waves' totals, one lane per wave, and
+    // keeps each wave's offsets in LDS for after the look-back.  With
     // P_w the charge of the earlier waves and Q_w their sum of S1 over
     // interior nodes (sum over each earlier wave of C + n P), the in-tile
     // prefix of the charge at j is s1l = P_w + a and the in-tile exclusive
@@ -2332,29 +2373,33 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
         }
     }
     __syncthreads();
-    long long Pw = 0, A = 0;
-    I128 Qw = i128(0), B = i128(0);
-#pragma unroll
-    for (int q = 0; q < TW; ++q) {
-        if (q == wv) {
-            Pw = A;
-            Qw = B;
-        }
-        B = add(B, add(w_C[q], mul_small(i128(A), (unsigned)w_n[q])));
-        A += w_A[q];
-    }
-    const I128 tl = add(add(Qw, mul_small(i128(Pw), (unsigned)cw)), c);
     const int nint = max(0, min(b0, N) - max(a0, 1));   // interior nodes of the tile
-    if (tid == 0) {
-        FieldAgg g;
-        g.A = A;
-        g.B_lo = B.lo;
-        g.B_hi = B.hi;
-        g.n = nint;
-        g.pad = 0;
-        dd.agg[t] = g;
-        // the release store orders the aggregate before the flag
-        __hip_atomic_store(glb(&dd.agg_flag[t]), epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid < 64) {
+        // one lane per wave of the tile: P_w, Q_w as exclusive scans over the
+        // waves (Q_w adds each earlier wave's C + n P), the tile's A and B as
+        // the last wave's inclusive ones, published at once
+        const long long aw = lane < TW ? w_A[lane] : 0;
+        const I128 cl = lane < TW ? w_C[lane] : i128(0);
+        const int nl = lane < TW ? w_n[lane] : 0;
+        const long long ai = wave_incl_scan_i64(aw);
+        const I128 term = add(cl, mul_small(i128(ai - aw), (unsigned)nl));
+        const I128 bi = wave_incl_scan_i128(term);
+        if (lane < TW) {
+            s_Pw[lane] = ai - aw;
+            s_Qw[lane] = add(bi, neg(term));
+        }
+        if (lane == TW - 1) {
+            s_B = bi;
+            FieldAgg g;
+            g.A = ai;
+            g.B_lo = bi.lo;
+            g.B_hi = bi.hi;
+            g.n = nint;
+            g.pad = 0;
+            dd.agg[t] = g;
+            // the release store orders the aggregate before the flag
+            __hip_atomic_store(glb(&dd.agg_flag[t]), epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     if (tid < 64) {
         // the tiles before this one, one lane each: P_u = sum_{v<u} A_v, the
@@ -2386,7 +2431,8 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     }
     __syncthreads();
     const long long P = s_P;
-    const I128 Q = s_Q;
+    const I128 Q = s_Q, B = s_B;
+    const I128 tl = wv < TW ? add(add(s_Qw[wv], mul_small(i128(s_Pw[wv]), (unsigned)cw)), c) : i128(0);
     // exact T_j = Q + (interior nodes of the tile before j) P + tl
     if (j < b0) {
         const int cnt = max(0, min(j, N) - max(a0, 1));
