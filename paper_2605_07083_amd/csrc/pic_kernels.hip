@@ -1802,27 +1802,31 @@ __device__ __forceinline__ void births_deposit(const BirthConsts &bc, const Birt
                                                uint32_t step, long long *R, int r0, int r1,
                                                unsigned long long (*hb)[HB], int a0, int b0)
 {
-    const int q = bp.q, ne = bp.ne, total = q + ne + bp.R;
-    for (int x = threadIdx.x; x < total; x += FT) {
-        if (x < q) {
-            const double z = bc.izq[iz_index(bp, keys, x)].z;
-            if (x < bp.okP) fused_deposit<HB>(bc, R, r0, r1, hb, a0, b0, SP_P, z);
-            if (x < bp.okI) fused_deposit<HB>(bc, R, r0, r1, hb, a0, b0, SP_I, z);
-        } else if (x < q + ne) {
-            const int i = x - q;
-            if (i >= bp.okE) continue;
+    // one kind of newborn per wave (thermionic electrons on the first,
+    // replenished pairs on the second, ionisation products on the others): a
+    // wave holding several kinds would run their branches one after another
+    const int q = bp.q, ne = bp.ne, w = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    if (w == 0) {
+        for (int i = lane; i < bp.okE; i += 64) {
             const uint32_t idn = bp.id0 + 2u * q + i;
             const uint4 b0w = philox(step, EV_BIRTH, 0u, 0u, idn, bc.kseed);
             const float vz = (float)(bc.sig_c * sqrt(-2.0 * log(u53(b0w.z, b0w.w))));
             const double z = (double)vz * bc.dt;
             if (z < bc.L) fused_deposit<HB>(bc, R, r0, r1, hb, a0, b0, SP_E, z);
-        } else {
-            const int r = x - q - ne;
+        }
+    } else if (w == 1) {
+        for (int r = lane; r < bp.R; r += 64) {
             const uint32_t ide = bp.id0 + 2u * q + ne + 2u * r;
             const uint4 e1 = philox(step, EV_BIRTH, 1u, 0u, ide, bc.kseed);
             const double z = bc.L * u53(e1.x, e1.y);
             if (q + r < bp.okP) fused_deposit<HB>(bc, R, r0, r1, hb, a0, b0, SP_P, z);
             if (q + r < bp.okI) fused_deposit<HB>(bc, R, r0, r1, hb, a0, b0, SP_I, z);
+        }
+    } else {
+        for (int x = (int)threadIdx.x - 128; x < q; x += FT - 128) {
+            const double z = bc.izq[iz_index(bp, keys, x)].z;
+            if (x < bp.okP) fused_deposit<HB>(bc, R, r0, r1, hb, a0, b0, SP_P, z);
+            if (x < bp.okI) fused_deposit<HB>(bc, R, r0, r1, hb, a0, b0, SP_I, z);
         }
     }
 }
@@ -1946,7 +1950,7 @@ __device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, Fiel
     DiodeState *st = dd.st;
     const int tid = threadIdx.x;
     const bool records = role == ROLE_RECORDS;
-    if (role == ROLE_TAIL) {
+    if (__builtin_expect(role == ROLE_TAIL, 0)) {
         fold_tally_copies(copy, &fs.rt);      // the step's totals, applied by the tail block
     } else if (tid < 64) {
         int v = copy.ion_lost;                // the others need the ions lost only
@@ -1954,7 +1958,7 @@ __device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, Fiel
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
         if (tid == 0) fs.rt.ion_lost = v;
     }
-    if (fs.s_st.rare_n[SP_P] | fs.s_st.rare_n[SP_E] | fs.s_st.rare_n[SP_I]) {
+    if (__builtin_expect((fs.s_st.rare_n[SP_P] | fs.s_st.rare_n[SP_E] | fs.s_st.rare_n[SP_I]) != 0, 0)) {
         // items the particle kernel's queues could not hold: the record
         // block collides them (they may queue ionisations and lose ions),
         // then raises the flag the other blocks wait for
@@ -2008,7 +2012,7 @@ __device__ void field_step_plan(const Diode &dd, int parity, uint32_t step, Fiel
         fs.bp = p;
     }
     __syncthreads();
-    if (fs.bp.sorted) {
+    if (__builtin_expect(fs.bp.sorted, 0)) {
         const int q = fs.bp.q;
         int np2 = 1;
         while (np2 < q) np2 <<= 1;
@@ -2190,7 +2194,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     const int avg = uni(s_avg);
     if (mode == 0) {
         field_step_plan(dd, parity, step, role, copy, fs, keys);
-        if (records) {
+        if (__builtin_expect(records, 0)) {
             // the newborns' records and tallies; the flag releases the
             // tallies to the tail block, which waits for them only when the
             // step takes a snapshot
@@ -2199,7 +2203,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
             if (tid == 0) __hip_atomic_store(glb(&st->rec_flag), step + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
-        if (role == ROLE_TAIL) {
+        if (__builtin_expect(role == ROLE_TAIL, 0)) {
             // the tiles and the record block: the step's tallies, counters and snapshot
             field_step_tail(dd, fs, step, avg, T + 1);
             return;
@@ -2320,7 +2324,7 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     const int avg = uni(s_avg);
     if (mode == 0) {
         field_step_plan(dd, parity, step, role, copy, fs, keys);
-        if (records) {
+        if (__builtin_expect(records, 0)) {
             // the newborns' records and tallies; the flag releases the
             // tallies to the tail block, which waits for them only when the
             // step takes a snapshot
@@ -2329,7 +2333,7 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
             if (tid == 0) __hip_atomic_store(glb(&st->rec_flag), step + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
-        if (role == ROLE_TAIL) {
+        if (__builtin_expect(role == ROLE_TAIL, 0)) {
             // once every tile has read the counters, the copies and the
             // epoch: the step's tallies, counters and snapshot, the next epoch
             field_step_tail(dd, fs, step, avg, T + 1);
@@ -2456,7 +2460,7 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
         st->e_shift = -slope / dd.dz;
         if (avg) st->phi_slope_sum += slope;
     }
-    if (mode != 0 && tid == 0) {
+    if (__builtin_expect(mode != 0, 0) && tid == 0) {
         // mode 1 has no record block: the writer advances the epoch once
         // every other tile has read it
         while (__hip_atomic_load(glb(&st->arrive), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < T - 1)
