@@ -1725,7 +1725,7 @@ constexpr int FUSED_MAX_NODES = 2049;
 // nodes per tile block of k_field_tiles (one per thread of its first half:
 // the per-node work of a tile runs on one CU, so smaller tiles spread it)
 constexpr int BIG_TILE = FIELD_BIG_TILE;
-static_assert(BIG_TILE <= FT && BIG_TILE % 64 == 0, "one thread per node of a tile, whole waves");
+static_assert(2 * BIG_TILE <= FT && BIG_TILE % 64 == 0, "one thread per node of a tile, whole waves, and as many waves again for the node bookkeeping");
 constexpr int MAX_TILES = 32768 / BIG_TILE;    // N <= 32767: the earlier tiles fit one wave
 static_assert(MAX_TILES <= 64, "one lane per earlier tile");
 
@@ -2116,34 +2116,46 @@ __device__ __forceinline__ void tile_consts(const Diode &dd, TileConsts &fc)
     fc.err = &dd.st->err;
 }
 
-// A tile's node bookkeeping and field: E from phi on the tile and its halo
-// (ph[k] = phi at node a0 - 1 + k), the step's deposits of the tile (hb) into
-// the last-step and summed histograms, H cleared, phi (and its sum).
+// A node's bookkeeping (node j, index i in the tile): the step's deposits
+// (hb) into the last-step and summed histograms, and H cleared when `clear`
+// (by whichever block may: every reader of the node's H has read it).
 template <int HB>
-__device__ __forceinline__ void field_tile_out(const TileConsts &fc, const double *ph, unsigned long long (*hb)[HB],
-                                               int a0, int b0, int avg)
+__device__ __forceinline__ void field_node_hist(const TileConsts &fc, unsigned long long (*hb)[HB], int i, int j,
+                                                int avg, bool clear)
 {
-    const int N = fc.N, tid = threadIdx.x;
-    const int j = a0 + tid;
-    if (tid < HB && j < b0) {
-        const int k = tid + 1;
-        const double pc = ph[k];
-        const double dz = fc.dz;
-        double E;
-        if (j == 0) E = (pc - ph[k + 1]) / dz;
-        else if (j == N) E = (ph[k - 1] - pc) / dz;
-        else E = (ph[k - 1] - ph[k + 1]) * (1.0 / (2.0 * dz));
-        glb(fc.phi)[j] = pc;
-        glb(fc.E)[j] = E;
 #pragma unroll
-        for (int s = 0; s < NSP; ++s) {
-            const unsigned long long hu = hb[s][tid];
-            if (hu >= DEPOSIT_LIMIT) atomicOr(fc.err, ERR_RANGE);
-            glb(fc.Hlast[s])[j] = (long long)hu;
-            glb(fc.H[s])[j] = 0ull;
-            if (avg) glb(fc.Hsum[s])[j] += (long long)hu;
-        }
-        if (avg) glb(fc.phi_sum)[j] += pc;
+    for (int s = 0; s < NSP; ++s) {
+        const unsigned long long hu = hb[s][i];
+        if (hu >= DEPOSIT_LIMIT) atomicOr(fc.err, ERR_RANGE);
+        glb(fc.Hlast[s])[j] = (long long)hu;
+        if (clear) glb(fc.H[s])[j] = 0ull;
+        if (avg) glb(fc.Hsum[s])[j] += (long long)hu;
+    }
+}
+
+// A node's field: E from phi on the tile and its halo (ph[k] = phi at node
+// a0 - 1 + k, k = i + 1), phi (and its sum).
+__device__ __forceinline__ void field_node_phi(const TileConsts &fc, const double *ph, int k, int j, int avg)
+{
+    const int N = fc.N;
+    const double pc = ph[k];
+    const double dz = fc.dz;
+    double E;
+    if (j == 0) E = (pc - ph[k + 1]) / dz;
+    else if (j == N) E = (ph[k - 1] - pc) / dz;
+    else E = (ph[k - 1] - ph[k + 1]) * (1.0 / (2.0 * dz));
+    glb(fc.phi)[j] = pc;
+    glb(fc.E)[j] = E;
+    if (avg) glb(fc.phi_sum)[j] += pc;
+}
+
+// Every node's H of the diode cleared by one block.
+__device__ __forceinline__ void clear_node_hist(const TileConsts &fc)
+{
+    const int nn = fc.N + 1;
+    for (int x = threadIdx.x; x < NSP * nn; x += FT) {
+        const int s = x / nn;
+        glb(fc.H[s])[x - s * nn] = 0ull;
     }
 }
 
@@ -2158,7 +2170,7 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
     __shared__ I128 tT[TILE + 2];                     // T_j on the own tile and its halo
     __shared__ FieldShared fs;
     __shared__ TileConsts fc;
-    __shared__ int s_avg;
+    __shared__ int s_avg, s_last;
     const Diode &dd = D[blockIdx.y];
     DiodeState *st = dd.st;
     const int N = dd.N, nn = N + 1;
@@ -2204,12 +2216,25 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
             return;
         }
         if (__builtin_expect(role == ROLE_TAIL, 0)) {
-            // the tiles and the record block: the step's tallies, counters and snapshot
+            // the tiles and the record block: the step's tallies, counters and
+            // snapshot; every tile block reads every node's H before it
+            // arrives, so the grid's H is cleared here, after the arrivals
             field_step_tail(dd, fs, step, avg, T + 1);
+            clear_node_hist(fc);
             return;
         }
         births_deposit<TILE>(fs.bc, fs.bp, keys, step, R, 0, nn, hb, a0, b0);
         __syncthreads();
+    } else {
+        // refield (no tail block): the last tile block to arrive, once every
+        // tile block has read every node's H, clears it
+        if (tid == 0)
+            s_last = __hip_atomic_fetch_add(glb(&st->arrive), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == T - 1;
+        __syncthreads();
+        if (s_last) {
+            clear_node_hist(fc);
+            if (tid == 0) __hip_atomic_store(glb(&st->arrive), 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 
     // phi_j = V j / N + alpha (j T_N - N T_j) / N with the exact sums
@@ -2257,8 +2282,15 @@ __global__ __launch_bounds__(FT) void k_field_step(const Diode *__restrict__ D, 
         ph[k] = v;
     }
     __syncthreads();
-    // the own tile: field, potential, deposits of the step and their sums
-    field_tile_out<TILE>(fc, ph, hb, a0, b0, avg);
+    // the own tile's field and potential on the first waves, its node
+    // bookkeeping on the last ones
+    static_assert(FT >= 2 * TILE, "separate waves for the field and the bookkeeping");
+    if (tid < TILE) {
+        if (a0 + tid < b0) field_node_phi(fc, ph, tid + 1, a0 + tid, avg);
+    } else if (tid >= FT - TILE) {
+        const int i = tid - (FT - TILE);
+        if (a0 + i < b0) field_node_hist<TILE>(fc, hb, i, a0 + i, avg, false);
+    }
 }
 
 // phi' at node j (see k_field_tiles) from the exact T_j.
@@ -2404,6 +2436,11 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
             // the release store orders the aggregate before the flag
             __hip_atomic_store(glb(&dd.agg_flag[t]), epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
+    } else if (tid >= FT - BIG_TILE) {
+        // the tile's node bookkeeping on waves idle until the look-back ends;
+        // only this block reads the tile's H, so it clears it
+        const int i = tid - (FT - BIG_TILE);
+        if (a0 + i < b0) field_node_hist<BIG_TILE>(fc, hb, i, a0 + i, avg, true);
     }
     if (tid < 64) {
         // the tiles before this one, one lane each: P_u = sum_{v<u} A_v, the
@@ -2450,7 +2487,7 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     }
     if (tid == 128 && b0 <= N) ph[b0 - a0 + 1] = phi_prime(fc, b0, add(add(Q, mul_small(i128(P), (unsigned)nint)), B));
     __syncthreads();
-    field_tile_out<BIG_TILE>(fc, ph, hb, a0, b0, avg);
+    if (j < b0) field_node_phi(fc, ph, tid + 1, j, avg);
     if (!writer) return;
     // the writer's tile ends at node N: T_N = Q + n P + B, slope = alpha T_N / N
     if (tid == 0) {
