@@ -2436,11 +2436,6 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
             // the release store orders the aggregate before the flag
             __hip_atomic_store(glb(&dd.agg_flag[t]), epoch + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
-    } else if (tid >= FT - BIG_TILE) {
-        // the tile's node bookkeeping on waves idle until the look-back ends;
-        // only this block reads the tile's H, so it clears it
-        const int i = tid - (FT - BIG_TILE);
-        if (a0 + i < b0) field_node_hist<BIG_TILE>(fc, hb, i, a0 + i, avg, true);
     }
     if (tid < 64) {
         // the tiles before this one, one lane each: P_u = sum_{v<u} A_v, the
@@ -2487,7 +2482,16 @@ __global__ __launch_bounds__(FT) void k_field_tiles(const Diode *__restrict__ D,
     }
     if (tid == 128 && b0 <= N) ph[b0 - a0 + 1] = phi_prime(fc, b0, add(add(Q, mul_small(i128(P), (unsigned)nint)), B));
     __syncthreads();
-    if (j < b0) field_node_phi(fc, ph, tid + 1, j, avg);
+    // the tile's field and potential on its waves, its node bookkeeping on as
+    // many others (after every tile's release, whose L2 write-back would
+    // otherwise take these stores too); only this block reads the tile's H,
+    // so it clears it
+    if (j < b0) {
+        field_node_phi(fc, ph, tid + 1, j, avg);
+    } else if (tid >= FT - BIG_TILE) {
+        const int i = tid - (FT - BIG_TILE);
+        if (a0 + i < b0) field_node_hist<BIG_TILE>(fc, hb, i, a0 + i, avg, true);
+    }
     if (!writer) return;
     // the writer's tile ends at node N: T_N = Q + n P + B, slope = alpha T_N / N
     if (tid == 0) {
