@@ -1832,14 +1832,21 @@ __device__ __forceinline__ void births_deposit(const BirthConsts &bc, const Birt
 }
 
 // The newborn records (positions as births_deposit, velocities, ids and
-// first free flights), one thread per newborn (pair).
+// first free flights), one thread per newborn (pair), each kind on waves of
+// its own.
 __device__ __forceinline__ void births_records(const Diode &dd, const BirthPlan &bp, const unsigned long long *keys,
                                                uint32_t step, int parity, const int *flip)
 {
-    const int q = bp.q, ne = bp.ne, total = q + ne + bp.R;
+    const int q = bp.q, ne = bp.ne, w = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
     const GBuf bP = gbuf(dd.buf[parity ^ flip[SP_P]][SP_P]), bE = gbuf(dd.buf[parity ^ flip[SP_E]][SP_E]),
                bI = gbuf(dd.buf[parity ^ flip[SP_I]][SP_I]);
-    for (int x = threadIdx.x; x < total; x += FT) {
+    // one kind of newborn per wave, as in births_deposit: thermionic
+    // electrons on the first, replenished pairs on the second, ionisation
+    // products on the others
+    const int first = w == 0 ? q : w == 1 ? q + ne : 0;
+    const int end = w == 0 ? q + ne : w == 1 ? q + ne + bp.R : q;
+    const int stride = w < 2 ? 64 : FT - 128;
+    for (int x = first + (w < 2 ? lane : (int)threadIdx.x - 128); x < end; x += stride) {
         if (x < q) {
             const int r = x;
             const IzEvent ev = dd.izq[iz_index(bp, keys, r)];
