@@ -441,8 +441,9 @@ int get_graph(pic_handle *h, int p, bool sorted, int64_t r, bool timed, GraphEnt
         h->graphs.erase(lru);
     }
     if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    // timing placeholders of the captured event nodes (see pic_step_timed)
     for (auto &e : h->tev)
-        if (!e) HIP_TRY(hipEventCreate(&e));
+        if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     hipGraph_t g;
     HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
     int rc = sorted ? enqueue_sort(h, h->cap_stream, p) : PIC_OK;
@@ -1047,8 +1048,12 @@ int pic_step_timed(pic_handle *h, int64_t nsteps, double *particle_kernel_ms, do
     const int64_t every = nsteps <= want ? 1 : ((nsteps + want - 1) / want) | 1;
     auto pair = [&](int64_t k, hipEvent_t &a, hipEvent_t &b) -> int {
         while ((int64_t)h->evpool.size() < 2 * (k + 1)) {
+            // timing only: their timestamps are read once the run's end
+            // event (with the default fence) has synchronised; without a
+            // system-scope fence the record does not write back and
+            // invalidate the caches around the kernel it brackets
             hipEvent_t e;
-            HIP_TRY(hipEventCreate(&e));
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
             h->evpool.push_back(e);
         }
         a = h->evpool[2 * k];
