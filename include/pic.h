@@ -307,8 +307,9 @@ int pic_get_tuning(pic_handle *h, int *ppt, int *grid, int *sort_period, int *us
 
 /* Choose the launch schedule by timing candidates on the handle's own
  * diodes: every combination of particles per thread {1, 2, 4}, re-sort period
- * {16, 32, 64, 128} and grid {2048, 4096, 8192, 16384, and the grid that gives
- * each block eight chunks of the current particles}; the best four timed twice
+ * {16, 32, 64, 128} and grid {2048, 3072, 4096, 6144, 8192, 12288, 16384, and
+ * the grid that gives each block eight chunks of the current particles (a
+ * multiple of 8 in 256..65536)}; the best four timed twice
  * more; then graph replay on or off for the best one.  Each candidate runs
  * whole re-sort periods of at least trial_steps real steps, so the diodes
  * advance.  Leaves the best schedule set and returns it with its time per
