@@ -9,6 +9,8 @@ reach, and the library's error reporting, through the C ABI.
   neutral targets at 300 K and 1740 K, 40 V, 4096 cells -- the tiled field
   kernel, nine tiles, the last of one node) and two of its sensitivity cases (Table 3: charge exchange off; the
   electron-side neutral target at 1740 K), at 20 particles per cell.
+* Thermionic newborns placed beyond the anode (a gap shorter than one
+  step): every step's snapshot holds the record block's tallies of them.
 * The largest batch (256 diodes, one on the tiled field grid), through
   re-sorts with graph replay, then restart parity on three of them.
 * The 32-diode emission sweep (100k-600k particles per species per diode):
@@ -26,6 +28,7 @@ reach, and the library's error reporting, through the C ABI.
 import numpy as np
 import pytest
 
+from _helpers import empty, quiet_cfg
 from gpu_compare import by_id, gpu_state, oracle_from_gpu, restart_step_check
 from paper_2605_07083_amd import presets
 
@@ -146,6 +149,41 @@ def test_maximum_batch_of_diodes(pic, O):
         # each check steps the whole handle on from the state it finds
         probs = restart_step_check(O, cfgs[d], h, 2, d=d)
         assert probs == [], "diode %d:\n%s" % (d, "\n".join(probs[:20]))
+
+
+def test_snapshots_hold_newborns_beyond_the_anode(pic, O):
+    """On a gap far shorter than one step of the slowest emitted electron,
+    every thermionic newborn crosses at birth: the record block tallies it,
+    absorbed at the anode with its birth energy, and releases those tallies
+    to the tail block, which waits for them on a step that takes a snapshot.
+    With a snapshot every step, each step's snapshot equals the oracle's
+    tallies after that step (counts exactly, the energy within 1e-5)."""
+    Tc = 2000.0 * presets.KB_OVER_E
+    cfg = quiet_cfg(n_load=1, Tc=Tc, L=1e-11, N=2, tally_period=1)
+    cfg["gamma_emit"] = 500.5 * O.derive(cfg)["w0"] / cfg["dt"]
+    _say("case: every newborn beyond the anode, a snapshot every step")
+    h = pic.Handle(cfg)
+    s = O.Sim(cfg)
+    s.load()
+    none = {"z": np.zeros(0), "vx": np.zeros(0), "vy": np.zeros(0), "vz": np.zeros(0),
+            "id": np.zeros(0, np.uint32), "tc": np.zeros(0, np.uint32)}
+    for sp in range(3):
+        h.set_particles(0, sp, none)
+        empty(s, sp)
+    h.set_counters(0, 0, 10)
+    s.set_counters(0, 10)
+    h.refield()
+    s.refield()
+    for k in range(1, 7):
+        h.step(1)
+        s.step()
+        snap, ot = h.snapshot(0, k), s.tally()
+        # 500.5 newborns per step: 500 or 501 each
+        assert snap["n_emit"] == ot["n_emit"] and 500 * k <= ot["n_emit"] <= 501 * k, k
+        assert snap["abs_count"][1][1] == ot["abs_count"][1][1] == ot["n_emit"], k
+        assert snap["abs_count"].sum() == ot["n_emit"], k
+        # velocities are FP32 on the device: energies agree to the parity tests' 1e-5
+        assert np.isclose(snap["abs_energy"][1][1], ot["abs_energy"][1][1], rtol=1e-5, atol=0.0), k
 
 
 def test_graph_runs_equal_plain_stream(pic):
