@@ -1942,10 +1942,10 @@ __device__ __forceinline__ RareTally field_step_reads(const Diode &dd, FieldShar
 
 // After field_step_reads and a barrier: the tail block folds every tally
 // copy into fs.rt, the others only the ions lost; the spilled rare items are
-// worked off (record block) or waited for; once a tile block is done with the
-// counters it bumps st->arrive, then every block works out the plan of the
-// step's births and, when the plan needs it, the ionisation events in
-// parent-id order in keys.
+// worked off (record block) or waited for; once a tile block or the record
+// block is done with the counters it bumps st->arrive, then every block works
+// out the plan of the step's births and, when the plan needs it, the
+// ionisation events in parent-id order in keys.
 // The roles of a field step's blocks (mode 0): block 0 writes the newborn
 // records, blocks 1..T take the node tiles, block T + 1 (dispatched last)
 // applies the step's tallies and advances the counters.
