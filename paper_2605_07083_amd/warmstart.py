@@ -354,6 +354,7 @@ def main(argv=None):
     t.add_argument("--epochs", type=int, default=4000)
     t.add_argument("--batch", type=int, default=32)
     t.add_argument("--lr", type=float, default=2e-3)
+    t.add_argument("--seed", type=int, default=7, help="initial weights and sample order")
     t.add_argument("--report")
     e = sub.add_parser("evaluate")
     e.add_argument("--data", required=True)
@@ -372,7 +373,7 @@ def main(argv=None):
         generate(a.n, int(a.seed, 0) if seed is None else seed, a.out, first=a.first, count=a.count,
                  max_steps=a.max_steps, block_steps=a.block_steps, tol_rel=a.tol_rel, avg_blocks=a.avg_blocks)
     elif a.cmd == "train":
-        rep = train(a.data, a.out, epochs=a.epochs, batch=a.batch, lr=a.lr, heldout=a.heldout)
+        rep = train(a.data, a.out, epochs=a.epochs, batch=a.batch, lr=a.lr, seed=a.seed, heldout=a.heldout)
         if a.report:
             json.dump(rep, open(a.report, "w"), indent=1)
     else:
